@@ -1,0 +1,199 @@
+/*
+ * zkvc.h - Groth16 prover for the matrix-multiplication statement Y = X W on
+ * BN254, for AMD MI355X (gfx950).
+ *
+ * The statement follows the paper's use case (Section I and Figure 1): a
+ * client holds X, a server holds the weights W, returns Y = X W and proves
+ * that Y is correct without revealing W.  X and Y are public inputs; W is
+ * private.  Gen, Prove and Verify are the three algorithms of a zk-SNARK
+ * (Section II); the backend is Groth16 (Section IV, zkVC-G).  Two circuits
+ * are provided: the per-product R1CS and the paper's constraint-reduced
+ * polynomial circuit with prefix-sum queries (Section III-A, III-B), plus the
+ * remaining rows of the ablation in Table II.
+ *
+ * Conventions for every entry point:
+ *   - All integers are little-endian.  Field elements at this interface are
+ *     canonical integers (value < modulus) unless a flag selects the
+ *     library's internal layout (ZKVC_LAYOUT_MONT: 8 words holding
+ *     x * 2^261 mod modulus).
+ *   - A G1 point is (x, y); a G2 point is (x0, x1, y0, y1) with x = x0 + x1 i
+ *     over Fq2 = Fq[i]/(i^2 + 1).  The all-zero encoding is the point at
+ *     infinity.
+ *   - Ownership: the caller owns every buffer it passes (host or device) and
+ *     keeps it alive for the duration of the call.  The library owns proving
+ *     keys until zkvc_pk_free and its own scratch memory.
+ *   - Streams: hip_stream is a hipStream_t (NULL = the default stream).  Every
+ *     call is synchronous with respect to its outputs: when it returns, host
+ *     outputs are written and device outputs are complete.  Calls on
+ *     different streams may run concurrently, except that two calls using
+ *     the same proving key must not overlap.
+ *   - Errors: negative return codes; no exception crosses this interface and
+ *     nothing aborts.  zkvc_strerror gives the last error message of the
+ *     calling thread.
+ */
+#ifndef ZKVC_H
+#define ZKVC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ZKVC_OK 0
+#define ZKVC_EINVAL (-1)  /* null pointer, empty or oversized shape, bad flag, value out of range */
+#define ZKVC_ENOMEM (-2)  /* device allocation failed or exceeded ZKVC_MEMORY_BUDGET_MB */
+#define ZKVC_EDEVICE (-3) /* a HIP runtime error */
+#define ZKVC_EFORMAT (-4) /* malformed verification-key blob */
+
+typedef struct { uint32_t l[8]; } zkvc_fr;
+typedef struct { uint32_t x[8], y[8]; } zkvc_g1;
+typedef struct { uint32_t x0[8], x1[8], y0[8], y1[8]; } zkvc_g2;
+typedef struct { zkvc_g1 A; zkvc_g2 B; zkvc_g1 C; } zkvc_proof; /* 256 bytes */
+
+/* Constraint systems (Section III and Table II). */
+enum {
+  ZKVC_PLAIN = 0,     /* one constraint per product x_ik w_kj; the output sum is folded
+                         into the last product's constraint: a*b*n constraints */
+  ZKVC_CRPC_PSQ = 1,  /* CRPC with prefix sums: n constraints X_k(z) W_k(z) = s_k - s_(k-1) */
+  ZKVC_PLAIN_ADD = 2, /* per-product plus one long-addition constraint per output */
+  ZKVC_PLAIN_PSQ = 3, /* per-product with prefix sums in place of products */
+  ZKVC_CRPC = 4       /* CRPC with products and one final addition: n + 1 constraints */
+};
+
+typedef struct {
+  uint32_t a, n, b; /* X is a x n, W is n x b, Y is a x b */
+  uint32_t kind;    /* one of the ZKVC_* circuit kinds above */
+} zkvc_shape;
+
+typedef struct zkvc_pk zkvc_pk; /* opaque proving key, resident in device memory */
+
+/* Flags for zkvc_ntt_fr, zkvc_msm_g1, zkvc_msm_g2, zkvc_fixed_base_*. */
+#define ZKVC_NTT_INVERSE 1u  /* inverse transform, including the 1/N factor */
+#define ZKVC_NTT_COSET 2u    /* forward: input j scaled by g^j first; inverse: output j scaled by g^-j; g = 5 */
+#define ZKVC_LAYOUT_MONT 4u  /* operands in the library's internal Montgomery layout */
+
+/*
+ * Gen (Section II; Groth16 key generation for the circuit of `shape`).
+ * toxic = {tau, alpha, beta, gamma, delta}: nonzero elements of Fr, canonical;
+ * tau must lie outside the evaluation domain (tau^N != 1).  z is the public
+ * CRPC evaluation point (Section III-A's variable Z), required nonzero for the
+ * CRPC kinds and ignored otherwise.  On success *pk_out receives a proving
+ * key in device memory.  The verification key is serialized into vk; if vk
+ * is NULL only the required size is written to *vk_len.  On input *vk_len
+ * is the capacity of vk.  Errors: ZKVC_EINVAL (bad shape/kind/toxic/z, or vk
+ * too small), ZKVC_ENOMEM, ZKVC_EDEVICE.
+ */
+int zkvc_setup(const zkvc_shape* shape, const zkvc_fr toxic[5], const zkvc_fr* z, zkvc_pk** pk_out,
+               uint8_t* vk, size_t* vk_len, void* hip_stream);
+
+/* Releases a proving key and its device memory.  NULL is accepted. */
+int zkvc_pk_free(zkvc_pk* pk);
+
+/*
+ * Prove (Section II; Groth16 proof that Y = X W).
+ * X: host int8 a x n row-major; W: host int8 n x b row-major (private);
+ * r, s: the prover's blinding scalars, canonical Fr (the caller draws them).
+ * Writes Y = X W (host int32 a x b row-major) and the 256-byte proof.
+ * Errors: ZKVC_EINVAL (null pointer, r or s >= r), ZKVC_ENOMEM, ZKVC_EDEVICE.
+ */
+int zkvc_prove(const zkvc_pk* pk, const int8_t* X, const int8_t* W, const zkvc_fr* r, const zkvc_fr* s,
+               int32_t* Y_out, zkvc_proof* proof_out, void* hip_stream);
+
+/*
+ * Verify (Section II; the Groth16 pairing-product equation), on the host.
+ * vk: blob written by zkvc_setup; X: int8 a x n; Y: int32 a x b (the shape is
+ * read from vk).  Returns 1 if the proof is valid for (X, Y), 0 if not
+ * (including points off the curve, at infinity, or B outside the order-r
+ * subgroup), ZKVC_EFORMAT for a malformed blob, ZKVC_EINVAL for null pointers.
+ */
+int zkvc_verify(const uint8_t* vk, size_t vk_len, const int8_t* X, const int32_t* Y,
+                const zkvc_proof* proof);
+
+/*
+ * In-place number-theoretic transform over Fr of N = 2^log_n elements on the
+ * device (d_data: N elements of 8 words), natural order in and out:
+ *   forward: X_k = sum_j x_j omega^(jk), omega = 5^((r-1)/N)
+ *   inverse: x_j = N^-1 sum_k X_k omega^(-jk)
+ * plus the coset scalings of ZKVC_NTT_COSET.  This is the transform the QAP
+ * quotient uses (Section II: the QAP comes from the R1CS by interpolation).
+ * 0 <= log_n <= 28.  Elements must be < r.  Errors: ZKVC_EINVAL, ZKVC_ENOMEM,
+ * ZKVC_EDEVICE.
+ */
+int zkvc_ntt_fr(void* d_data, uint32_t log_n, uint32_t flags, void* hip_stream);
+
+/*
+ * Multi-scalar multiplication sum_i s_i P_i over G1 (Groth16's A, B1, L and H
+ * queries).  d_points: n affine points (16 words each); d_scalars: n Fr
+ * elements (8 words each); both in device memory.  Points must lie on the
+ * curve (the all-zero encoding, infinity, is allowed); scalars must be < r.
+ * The result is written to *out (host).  n = 0 gives infinity.
+ * Errors: ZKVC_EINVAL, ZKVC_ENOMEM, ZKVC_EDEVICE.
+ */
+int zkvc_msm_g1(const void* d_points, const void* d_scalars, size_t n, uint32_t flags, zkvc_g1* out,
+                void* hip_stream);
+
+/* As zkvc_msm_g1 over G2 (Groth16's B query); points are 32 words each and
+ * must lie in the order-r subgroup of the twist. */
+int zkvc_msm_g2(const void* d_points, const void* d_scalars, size_t n, uint32_t flags, zkvc_g2* out,
+                void* hip_stream);
+
+/* Message for the last error on the calling thread (or for the code if none). */
+const char* zkvc_strerror(int err);
+
+/* ---------------------------------------------------------------- support calls */
+
+/*
+ * Fixed-base batch multiplication (Groth16 key generation): out_i = [k_i] G
+ * for the standard generator G of G1 (resp. G2), written as affine points.
+ * d_scalars: n Fr elements (device); d_points_out: n points (device, 16 or
+ * 32 words each).  ZKVC_LAYOUT_MONT selects the internal layout for both.
+ */
+int zkvc_fixed_base_g1(const void* d_scalars, size_t n, void* d_points_out, uint32_t flags, void* hip_stream);
+int zkvc_fixed_base_g2(const void* d_scalars, size_t n, void* d_points_out, uint32_t flags, void* hip_stream);
+
+/* Sizes of a proving key's queries (number of points). */
+typedef struct {
+  uint32_t a, n, b, kind;
+  uint32_t log_n;       /* QAP domain size N = 2^log_n */
+  uint64_t num_vars;    /* full assignment length */
+  uint64_t num_public;  /* l: public inputs excluding the constant */
+  uint64_t a_query, b_query, l_query, h_query;
+  uint64_t device_bytes; /* proving key plus its proving workspace */
+} zkvc_pk_info_t;
+int zkvc_pk_info(const zkvc_pk* pk, zkvc_pk_info_t* info);
+
+/* Query identifiers for zkvc_pk_export. */
+enum { ZKVC_Q_A = 0, ZKVC_Q_B1 = 1, ZKVC_Q_B2 = 2, ZKVC_Q_L = 3, ZKVC_Q_H = 4, ZKVC_Q_CONST = 5 };
+/*
+ * Copies entries [start, start + count) of a proving-key query to host memory
+ * as canonical affine points (zkvc_g1, or zkvc_g2 for ZKVC_Q_B2).  For
+ * ZKVC_Q_CONST the entries are alpha1, beta1, delta1 (zkvc_g1) followed by
+ * beta2, delta2 (zkvc_g2), and start/count are ignored.  The A and B queries
+ * cover the variables listed by zkvc_pk_query_vars.  Used to spot-check keys.
+ */
+int zkvc_pk_export(const zkvc_pk* pk, uint32_t query, uint64_t start, uint64_t count, void* host_out);
+
+/* Per-stage device times (milliseconds, from HIP events) of the last
+ * zkvc_prove with this key, and its host-side assembly time. */
+typedef struct {
+  float witness_ms, ntt_ms, msm_g1_ms, msm_g2_ms, host_ms, total_ms;
+} zkvc_prove_stats;
+int zkvc_pk_last_stats(const zkvc_pk* pk, zkvc_prove_stats* out);
+
+/*
+ * Elementwise field operations on device arrays, for arithmetic parity
+ * tests.  field: 0 = Fq, 1 = Fr.  op: 0 add, 1 sub, 2 mul, 3 sqr, 4 inv
+ * (of nonzero), 5 to-internal (canonical -> Montgomery), 6 from-internal.
+ * Inputs and output are n elements of 8 words in device memory; a, b and
+ * out are canonical integers except for ops 5 and 6.
+ */
+int zkvc_field_op(uint32_t field, uint32_t op, const void* d_a, const void* d_b, void* d_out, size_t n,
+                  void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ZKVC_H */

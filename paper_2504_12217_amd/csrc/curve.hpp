@@ -1,0 +1,178 @@
+// Device group law for BN254 G1 (over Fq) and G2 (over Fq2, on the twist).
+//
+// Accumulators use XYZZ coordinates (X, Y, ZZ, ZZZ) with x = X/ZZ, y = Y/ZZZ
+// and ZZ^3 = ZZZ^2; ZZ = 0 marks the point at infinity.  The addition and
+// doubling formulas are the "add-2008-s", "madd-2008-s" and "dbl-2008-s-1"
+// entries of Bernstein and Lange's Explicit-Formulas Database for a = 0:
+// a mixed addition costs 8M + 2S and needs no inversion, which suits the
+// bucket accumulation of Pippenger's method.
+//
+// Affine points in memory are stored x then y (each coordinate 8 x 32-bit
+// words in the device Montgomery form); the pair (0, 0) encodes infinity.
+#pragma once
+#include "field.hpp"
+
+namespace zkvc {
+
+template <class F>
+struct Affine {
+  F x, y;
+};
+
+template <class F>
+struct Xyzz {
+  F X, Y, ZZ, ZZZ;
+
+  static ZK_DEV Xyzz inf() { return {F::one(), F::one(), F::zero(), F::zero()}; }
+  static ZK_DEV bool is_inf(const Xyzz& p) { return F::is_zero(p.ZZ); }
+  static ZK_DEV Xyzz from_affine(const Affine<F>& q) { return {q.x, q.y, F::one(), F::one()}; }
+
+  // 2 * (x, y) for an affine input (mdbl-2008-s-1 with ZZ = ZZZ = 1)
+  static ZK_DEV Xyzz dbl_affine(const Affine<F>& q) {
+    const F U = F::dbl(q.y);
+    const F V = F::sqr(U);
+    const F W = F::mul(U, V);
+    const F S = F::mul(q.x, V);
+    const F xx = F::sqr(q.x);
+    const F M = F::add(F::dbl(xx), xx);
+    const F X3 = F::sub(F::sqr(M), F::dbl(S));
+    const F Y3 = F::sub(F::mul(M, F::sub(S, X3)), F::mul(W, q.y));
+    return {X3, Y3, V, W};
+  }
+
+  // 2P (dbl-2008-s-1)
+  static ZK_DEV Xyzz dbl(const Xyzz& p) {
+    const F U = F::dbl(p.Y);
+    const F V = F::sqr(U);
+    const F W = F::mul(U, V);
+    const F S = F::mul(p.X, V);
+    const F xx = F::sqr(p.X);
+    const F M = F::add(F::dbl(xx), xx);
+    const F X3 = F::sub(F::sqr(M), F::dbl(S));
+    const F Y3 = F::sub(F::mul(M, F::sub(S, X3)), F::mul(W, p.Y));
+    return {X3, Y3, F::mul(V, p.ZZ), F::mul(W, p.ZZZ)};
+  }
+
+  // P + Q with Q affine (madd-2008-s), Q not infinity
+  static ZK_DEV Xyzz madd(const Xyzz& p, const Affine<F>& q) {
+    if (is_inf(p)) return from_affine(q);
+    const F U2 = F::mul(q.x, p.ZZ);
+    const F S2 = F::mul(q.y, p.ZZZ);
+    const F P = F::sub(U2, p.X);
+    const F R = F::sub(S2, p.Y);
+    if (F::is_zero(P)) {
+      if (F::is_zero(R)) return dbl_affine(q);
+      return inf();
+    }
+    const F PP = F::sqr(P);
+    const F PPP = F::mul(P, PP);
+    const F Q = F::mul(p.X, PP);
+    const F X3 = F::sub(F::sub(F::sqr(R), PPP), F::dbl(Q));
+    const F Y3 = F::sub(F::mul(R, F::sub(Q, X3)), F::mul(p.Y, PPP));
+    return {X3, Y3, F::mul(p.ZZ, PP), F::mul(p.ZZZ, PPP)};
+  }
+
+  // P + Q (add-2008-s)
+  static ZK_DEV Xyzz add(const Xyzz& p, const Xyzz& q) {
+    if (is_inf(p)) return q;
+    if (is_inf(q)) return p;
+    const F U1 = F::mul(p.X, q.ZZ);
+    const F U2 = F::mul(q.X, p.ZZ);
+    const F S1 = F::mul(p.Y, q.ZZZ);
+    const F S2 = F::mul(q.Y, p.ZZZ);
+    const F P = F::sub(U2, U1);
+    const F R = F::sub(S2, S1);
+    if (F::is_zero(P)) {
+      if (F::is_zero(R)) return dbl(p);
+      return inf();
+    }
+    const F PP = F::sqr(P);
+    const F PPP = F::mul(P, PP);
+    const F Q = F::mul(U1, PP);
+    const F X3 = F::sub(F::sub(F::sqr(R), PPP), F::dbl(Q));
+    const F Y3 = F::sub(F::mul(R, F::sub(Q, X3)), F::mul(S1, PPP));
+    return {X3, Y3, F::mul(F::mul(p.ZZ, q.ZZ), PP), F::mul(F::mul(p.ZZZ, q.ZZZ), PPP)};
+  }
+
+  static ZK_DEV Xyzz neg(const Xyzz& p) { return {p.X, F::neg(p.Y), p.ZZ, p.ZZZ}; }
+
+  // [k]P for a small non-negative k (double-and-add, most significant bit first)
+  static ZK_DEV Xyzz mul_small(const Xyzz& p, uint32_t k) {
+    Xyzz acc = inf();
+    if (k == 0u) return acc;
+    const int top = 31 - __builtin_clz(k);
+    acc = p;
+    for (int b = top - 1; b >= 0; b--) {
+      acc = dbl(acc);
+      if ((k >> b) & 1u) acc = add(acc, p);
+    }
+    return acc;
+  }
+};
+
+// Memory helpers: a G1 affine point is 16 words, a G2 affine point 32 words,
+// an XYZZ accumulator 4 coordinates of the same widths.
+template <class F>
+struct PointIO;
+
+template <>
+struct PointIO<Fq> {
+  static constexpr int AFF_WORDS = 16;
+  static constexpr int XYZZ_WORDS = 32;
+  static ZK_DEV Affine<Fq> load_affine(const uint32_t* p) { return {Fq::load(p), Fq::load(p + 8)}; }
+  static ZK_DEV void store_affine(uint32_t* p, const Affine<Fq>& a) {
+    a.x.store(p);
+    a.y.store(p + 8);
+  }
+  static ZK_DEV bool affine_is_zero(const uint32_t* p) {
+    const uint4* q = reinterpret_cast<const uint4*>(p);
+    uint32_t t = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const uint4 v = q[k];
+      t |= v.x | v.y | v.z | v.w;
+    }
+    return t == 0u;
+  }
+  static ZK_DEV Xyzz<Fq> load_xyzz(const uint32_t* p) {
+    return {Fq::load(p), Fq::load(p + 8), Fq::load(p + 16), Fq::load(p + 24)};
+  }
+  static ZK_DEV void store_xyzz(uint32_t* p, const Xyzz<Fq>& a) {
+    a.X.store(p);
+    a.Y.store(p + 8);
+    a.ZZ.store(p + 16);
+    a.ZZZ.store(p + 24);
+  }
+};
+
+template <>
+struct PointIO<Fq2> {
+  static constexpr int AFF_WORDS = 32;
+  static constexpr int XYZZ_WORDS = 64;
+  static ZK_DEV Affine<Fq2> load_affine(const uint32_t* p) { return {Fq2::load(p), Fq2::load(p + 16)}; }
+  static ZK_DEV void store_affine(uint32_t* p, const Affine<Fq2>& a) {
+    a.x.store(p);
+    a.y.store(p + 16);
+  }
+  static ZK_DEV bool affine_is_zero(const uint32_t* p) {
+    const uint4* q = reinterpret_cast<const uint4*>(p);
+    uint32_t t = 0;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      const uint4 v = q[k];
+      t |= v.x | v.y | v.z | v.w;
+    }
+    return t == 0u;
+  }
+  static ZK_DEV Xyzz<Fq2> load_xyzz(const uint32_t* p) {
+    return {Fq2::load(p), Fq2::load(p + 16), Fq2::load(p + 32), Fq2::load(p + 48)};
+  }
+  static ZK_DEV void store_xyzz(uint32_t* p, const Xyzz<Fq2>& a) {
+    a.X.store(p);
+    a.Y.store(p + 16);
+    a.ZZ.store(p + 32);
+    a.ZZZ.store(p + 48);
+  }
+};
+
+}  // namespace zkvc

@@ -1,0 +1,298 @@
+// Device arithmetic for the BN254 base field Fq and scalar field Fr.
+//
+// Representation.  A field element is held in registers as 9 limbs of 29 bits
+// (261 bits) in Montgomery form with R = 2^261.  In memory it is stored packed
+// as 8 little-endian 32-bit words (32 bytes), so arrays stay 32-byte aligned
+// and an element moves with two 16-byte loads.
+//
+// Why 29-bit limbs on gfx950: v_mad_u64_u32 issues at full rate, as do 32-bit
+// adds, so cost is the total VALU instruction count.  With 29-bit limbs every
+// partial product is below 2^58 and a whole column (at most 18 products plus
+// the incoming carry) fits a 64-bit accumulator.  Each partial product is then
+// a single v_mad_u64_u32 into the accumulator with no per-product carry
+// handling; carries are resolved once per column (Montgomery's reduction,
+// 1985, in the column-interleaved "product scanning" order).
+//
+// Invariant: every Fp value returned by these functions is fully reduced,
+// i.e. in [0, m) with each limb below 2^29.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "constants.hpp"
+
+#define ZK_DEV __device__ __forceinline__
+
+namespace zkvc {
+
+constexpr int NL = 9;
+constexpr int LB = 29;
+constexpr uint32_t LMASK = (1u << LB) - 1u;
+
+template <class M>
+struct Fp {
+  uint32_t v[NL];
+
+  static ZK_DEV Fp zero() {
+    Fp r;
+#pragma unroll
+    for (int k = 0; k < NL; k++) r.v[k] = 0u;
+    return r;
+  }
+  static ZK_DEV Fp one() {  // R mod m: the Montgomery form of 1
+    Fp r;
+#pragma unroll
+    for (int k = 0; k < NL; k++) r.v[k] = M::ONE[k];
+    return r;
+  }
+  static ZK_DEV Fp raw_one() {  // the integer 1 (Montgomery form of R^-1)
+    Fp r = zero();
+    r.v[0] = 1u;
+    return r;
+  }
+
+  // ---- packing between 8 x 32-bit words and 9 x 29-bit limbs ----
+  static ZK_DEV Fp unpack(const uint32_t w[8]) {
+    Fp r;
+#pragma unroll
+    for (int k = 0; k < NL; k++) {
+      const int o = LB * k, q = o >> 5, sh = o & 31;
+      const uint32_t lo = w[q];
+      const uint32_t hi = (q + 1 < 8) ? w[q + 1] : 0u;
+      r.v[k] = __builtin_amdgcn_alignbit(hi, lo, sh) & LMASK;
+    }
+    return r;
+  }
+  ZK_DEV void pack(uint32_t w[8]) const {
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      const int o = 32 * j, k = o / LB, sh = o % LB;
+      uint64_t acc = (uint64_t)(v[k] >> sh);
+      if (k + 1 < NL) acc |= (uint64_t)v[k + 1] << (LB - sh);
+      if (k + 2 < NL && 2 * LB - sh < 32) acc |= (uint64_t)v[k + 2] << (2 * LB - sh);
+      w[j] = (uint32_t)acc;
+    }
+  }
+  static ZK_DEV Fp load(const uint32_t* p) {
+    const uint4 a = reinterpret_cast<const uint4*>(p)[0];
+    const uint4 b = reinterpret_cast<const uint4*>(p)[1];
+    const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    return unpack(w);
+  }
+  ZK_DEV void store(uint32_t* p) const {
+    uint32_t w[8];
+    pack(w);
+    reinterpret_cast<uint4*>(p)[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    reinterpret_cast<uint4*>(p)[1] = make_uint4(w[4], w[5], w[6], w[7]);
+  }
+
+  // ---- reduction helpers ----
+  // r in [0, 2m) with r[8] possibly above 29 bits only by the value range -> [0, m)
+  static ZK_DEV Fp reduce_once(const uint32_t r[NL]) {
+    uint32_t d[NL];
+    int32_t borrow = 0;
+#pragma unroll
+    for (int k = 0; k < NL; k++) {
+      const int32_t t = (int32_t)r[k] - (int32_t)M::P[k] + borrow;
+      d[k] = (uint32_t)t & LMASK;
+      borrow = t >> LB;
+    }
+    Fp out;
+    const bool keep = borrow < 0;
+#pragma unroll
+    for (int k = 0; k < NL; k++) out.v[k] = keep ? r[k] : d[k];
+    return out;
+  }
+
+  // ---- ring operations ----
+  static ZK_DEV Fp add(const Fp& a, const Fp& b) {
+    uint32_t s[NL];
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < NL; k++) {
+      const uint32_t t = a.v[k] + b.v[k] + c;
+      s[k] = t & LMASK;
+      c = t >> LB;
+    }
+    s[NL - 1] += c << LB;  // value < 2m < 2^255: the top limb absorbs the carry
+    return reduce_once(s);
+  }
+  static ZK_DEV Fp sub(const Fp& a, const Fp& b) {
+    uint32_t d[NL];
+    int32_t borrow = 0;
+#pragma unroll
+    for (int k = 0; k < NL; k++) {
+      const int32_t t = (int32_t)a.v[k] - (int32_t)b.v[k] + borrow;
+      d[k] = (uint32_t)t & LMASK;
+      borrow = t >> LB;
+    }
+    // if negative, add m back
+    Fp out;
+    uint32_t c = 0;
+    const uint32_t mask = borrow < 0 ? 0xffffffffu : 0u;
+#pragma unroll
+    for (int k = 0; k < NL; k++) {
+      const uint32_t t = d[k] + (M::P[k] & mask) + c;
+      out.v[k] = t & LMASK;
+      c = t >> LB;
+    }
+    return out;
+  }
+  static ZK_DEV Fp neg(const Fp& a) { return sub(zero(), a); }
+  static ZK_DEV Fp dbl(const Fp& a) { return add(a, a); }
+
+  // Montgomery product a*b*2^-261 mod m (column-interleaved reduction).
+  static ZK_DEV Fp mul(const Fp& a, const Fp& b) {
+    uint64_t acc = 0;
+    uint32_t m[NL];
+    uint32_t r[NL];
+#pragma unroll
+    for (int k = 0; k < NL; k++) {
+#pragma unroll
+      for (int i = 0; i <= k; i++) acc += (uint64_t)a.v[i] * b.v[k - i];
+#pragma unroll
+      for (int i = 0; i < k; i++) acc += (uint64_t)m[i] * M::P[k - i];
+      m[k] = ((uint32_t)acc * M::PINV) & LMASK;
+      acc += (uint64_t)m[k] * M::P[0];
+      acc >>= LB;
+    }
+#pragma unroll
+    for (int k = NL; k < 2 * NL - 1; k++) {
+#pragma unroll
+      for (int i = k - NL + 1; i < NL; i++) acc += (uint64_t)a.v[i] * b.v[k - i];
+#pragma unroll
+      for (int i = k - NL + 1; i < NL; i++) acc += (uint64_t)m[i] * M::P[k - i];
+      r[k - NL] = (uint32_t)acc & LMASK;
+      acc >>= LB;
+    }
+    r[NL - 1] = (uint32_t)acc;
+    return reduce_once(r);
+  }
+
+  // Squaring: off-diagonal products computed once against a doubled operand.
+  static ZK_DEV Fp sqr(const Fp& a) {
+    uint32_t a2[NL];
+#pragma unroll
+    for (int k = 0; k < NL; k++) a2[k] = a.v[k] << 1;  // < 2^30, products stay < 2^59
+    uint64_t acc = 0;
+    uint32_t m[NL];
+    uint32_t r[NL];
+#pragma unroll
+    for (int k = 0; k < 2 * NL - 1; k++) {
+      const int lo = k < NL ? 0 : k - NL + 1;
+      const int hi = k < NL ? k : NL - 1;
+#pragma unroll
+      for (int i = lo; i <= hi; i++) {
+        const int j = k - i;
+        if (i < j) acc += (uint64_t)a2[i] * a.v[j];
+        else if (i == j) acc += (uint64_t)a.v[i] * a.v[i];
+      }
+      if (k < NL) {
+#pragma unroll
+        for (int i = 0; i < k; i++) acc += (uint64_t)m[i] * M::P[k - i];
+        m[k] = ((uint32_t)acc * M::PINV) & LMASK;
+        acc += (uint64_t)m[k] * M::P[0];
+      } else {
+#pragma unroll
+        for (int i = k - NL + 1; i < NL; i++) acc += (uint64_t)m[i] * M::P[k - i];
+        r[k - NL] = (uint32_t)acc & LMASK;
+      }
+      acc >>= LB;
+    }
+    r[NL - 1] = (uint32_t)acc;
+    return reduce_once(r);
+  }
+
+  static ZK_DEV bool is_zero(const Fp& a) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int k = 0; k < NL; k++) t |= a.v[k];
+    return t == 0u;
+  }
+  static ZK_DEV bool eq(const Fp& a, const Fp& b) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int k = 0; k < NL; k++) t |= a.v[k] ^ b.v[k];
+    return t == 0u;
+  }
+  static ZK_DEV Fp select(bool c, const Fp& a, const Fp& b) {  // c ? a : b
+    Fp r;
+#pragma unroll
+    for (int k = 0; k < NL; k++) r.v[k] = c ? a.v[k] : b.v[k];
+    return r;
+  }
+
+  // canonical integer -> Montgomery form, and back
+  static ZK_DEV Fp to_mont(const Fp& a) {
+    Fp r2;
+#pragma unroll
+    for (int k = 0; k < NL; k++) r2.v[k] = M::R2[k];
+    return mul(a, r2);
+  }
+  static ZK_DEV Fp from_mont(const Fp& a) { return mul(a, raw_one()); }
+
+  // a^e for a small exponent held in 32-bit words, most significant first
+  static ZK_DEV Fp pow_words(const Fp& a, const uint32_t* e, int nwords) {
+    Fp r = one();
+    for (int w = nwords - 1; w >= 0; w--) {
+      for (int b = 31; b >= 0; b--) {
+        r = sqr(r);
+        if ((e[w] >> b) & 1u) r = mul(r, a);
+      }
+    }
+    return r;
+  }
+  // inverse by Fermat's little theorem: a^(m-2); a must be nonzero
+  static ZK_DEV Fp inv(const Fp& a) {
+    uint32_t e[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) e[k] = M::P32[k];
+    e[0] -= 2u;  // m is odd and > 2, no borrow
+    return pow_words(a, e, 8);
+  }
+};
+
+using Fq = Fp<FqParams>;
+using Fr = Fp<FrParams>;
+
+// Fq2 = Fq[i]/(i^2 + 1)
+struct Fq2 {
+  Fq c0, c1;
+  static ZK_DEV Fq2 zero() { return {Fq::zero(), Fq::zero()}; }
+  static ZK_DEV Fq2 one() { return {Fq::one(), Fq::zero()}; }
+  static ZK_DEV Fq2 add(const Fq2& a, const Fq2& b) { return {Fq::add(a.c0, b.c0), Fq::add(a.c1, b.c1)}; }
+  static ZK_DEV Fq2 sub(const Fq2& a, const Fq2& b) { return {Fq::sub(a.c0, b.c0), Fq::sub(a.c1, b.c1)}; }
+  static ZK_DEV Fq2 dbl(const Fq2& a) { return {Fq::dbl(a.c0), Fq::dbl(a.c1)}; }
+  static ZK_DEV Fq2 neg(const Fq2& a) { return {Fq::neg(a.c0), Fq::neg(a.c1)}; }
+  // Karatsuba: 3 base multiplications
+  static ZK_DEV Fq2 mul(const Fq2& a, const Fq2& b) {
+    const Fq v0 = Fq::mul(a.c0, b.c0);
+    const Fq v1 = Fq::mul(a.c1, b.c1);
+    const Fq s = Fq::mul(Fq::add(a.c0, a.c1), Fq::add(b.c0, b.c1));
+    return {Fq::sub(v0, v1), Fq::sub(Fq::sub(s, v0), v1)};
+  }
+  // (a0 + a1 i)^2 = (a0 + a1)(a0 - a1) + 2 a0 a1 i
+  static ZK_DEV Fq2 sqr(const Fq2& a) {
+    const Fq t = Fq::mul(a.c0, a.c1);
+    return {Fq::mul(Fq::add(a.c0, a.c1), Fq::sub(a.c0, a.c1)), Fq::dbl(t)};
+  }
+  static ZK_DEV bool is_zero(const Fq2& a) { return Fq::is_zero(a.c0) && Fq::is_zero(a.c1); }
+  static ZK_DEV bool eq(const Fq2& a, const Fq2& b) { return Fq::eq(a.c0, b.c0) && Fq::eq(a.c1, b.c1); }
+  static ZK_DEV Fq2 select(bool c, const Fq2& a, const Fq2& b) {
+    return {Fq::select(c, a.c0, b.c0), Fq::select(c, a.c1, b.c1)};
+  }
+  // 1/(a0 + a1 i) = (a0 - a1 i) / (a0^2 + a1^2)
+  static ZK_DEV Fq2 inv(const Fq2& a) {
+    const Fq d = Fq::inv(Fq::add(Fq::sqr(a.c0), Fq::sqr(a.c1)));
+    return {Fq::mul(a.c0, d), Fq::neg(Fq::mul(a.c1, d))};
+  }
+  static ZK_DEV Fq2 load(const uint32_t* p) { return {Fq::load(p), Fq::load(p + 8)}; }
+  ZK_DEV void store(uint32_t* p) const {
+    c0.store(p);
+    c1.store(p + 8);
+  }
+  static ZK_DEV Fq2 to_mont(const Fq2& a) { return {Fq::to_mont(a.c0), Fq::to_mont(a.c1)}; }
+  static ZK_DEV Fq2 from_mont(const Fq2& a) { return {Fq::from_mont(a.c0), Fq::from_mont(a.c1)}; }
+};
+
+}  // namespace zkvc

@@ -1,0 +1,295 @@
+// Host-side BN254 arithmetic: Fq, Fr (4 x 64-bit limbs, Montgomery R = 2^256),
+// the tower Fq2 = Fq[i]/(i^2+1), Fq6 = Fq2[v]/(v^3 - xi), Fq12 = Fq6[w]/(w^2 - v)
+// with xi = 9 + i, and Jacobian G1/G2 group operations.
+//
+// The host does the serial tails of the prover (Pippenger's window
+// combination, the blinding terms of the proof, affine conversion) and the
+// verifier's pairing.  These are chains of a few thousand dependent field
+// operations: one CPU core runs them far faster than one GPU wavefront.
+#pragma once
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "constants.hpp"
+
+namespace zkvc {
+namespace host {
+
+typedef unsigned __int128 u128;
+
+template <class M>
+struct HF {
+  uint64_t l[4];  // Montgomery form, fully reduced
+
+  static HF zero() { return HF{{0, 0, 0, 0}}; }
+  static HF one() { return HF{{M::ONE64[0], M::ONE64[1], M::ONE64[2], M::ONE64[3]}}; }
+
+  static bool geq_mod(const uint64_t a[4]) {
+    for (int k = 3; k >= 0; k--) {
+      if (a[k] != M::P64[k]) return a[k] > M::P64[k];
+    }
+    return true;
+  }
+  static void sub_mod_inplace(uint64_t a[4]) {
+    u128 borrow = 0;
+    for (int k = 0; k < 4; k++) {
+      u128 t = (u128)a[k] - M::P64[k] - borrow;
+      a[k] = (uint64_t)t;
+      borrow = (t >> 64) & 1;
+    }
+  }
+  static HF add(const HF& a, const HF& b) {
+    HF r;
+    u128 c = 0;
+    for (int k = 0; k < 4; k++) {
+      c += (u128)a.l[k] + b.l[k];
+      r.l[k] = (uint64_t)c;
+      c >>= 64;
+    }
+    if (c || geq_mod(r.l)) sub_mod_inplace(r.l);
+    return r;
+  }
+  static HF sub(const HF& a, const HF& b) {
+    HF r;
+    u128 borrow = 0;
+    for (int k = 0; k < 4; k++) {
+      u128 t = (u128)a.l[k] - b.l[k] - borrow;
+      r.l[k] = (uint64_t)t;
+      borrow = (t >> 64) & 1;
+    }
+    if (borrow) {
+      u128 c = 0;
+      for (int k = 0; k < 4; k++) {
+        c += (u128)r.l[k] + M::P64[k];
+        r.l[k] = (uint64_t)c;
+        c >>= 64;
+      }
+    }
+    return r;
+  }
+  static HF neg(const HF& a) { return sub(zero(), a); }
+  static HF dbl(const HF& a) { return add(a, a); }
+  // CIOS Montgomery multiplication (Koc, Acar, Kaliski 1996)
+  static HF mul(const HF& a, const HF& b) {
+    uint64_t t[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = 0; i < 4; i++) {
+      u128 c = 0;
+      for (int j = 0; j < 4; j++) {
+        c += (u128)a.l[j] * b.l[i] + t[j];
+        t[j] = (uint64_t)c;
+        c >>= 64;
+      }
+      c += t[4];
+      t[4] = (uint64_t)c;
+      t[5] = (uint64_t)(c >> 64);
+      const uint64_t m = t[0] * M::PINV64;
+      c = (u128)m * M::P64[0] + t[0];
+      c >>= 64;
+      for (int j = 1; j < 4; j++) {
+        c += (u128)m * M::P64[j] + t[j];
+        t[j - 1] = (uint64_t)c;
+        c >>= 64;
+      }
+      c += t[4];
+      t[3] = (uint64_t)c;
+      t[4] = t[5] + (uint64_t)(c >> 64);
+    }
+    HF r{{t[0], t[1], t[2], t[3]}};
+    if (t[4] || geq_mod(r.l)) sub_mod_inplace(r.l);
+    return r;
+  }
+  static HF sqr(const HF& a) { return mul(a, a); }
+  bool is_zero() const { return (l[0] | l[1] | l[2] | l[3]) == 0; }
+  bool operator==(const HF& o) const { return std::memcmp(l, o.l, sizeof(l)) == 0; }
+  bool operator!=(const HF& o) const { return !(*this == o); }
+
+  // canonical little-endian words (value < m) <-> Montgomery
+  static HF from_u64(const uint64_t c[4]) {
+    HF a{{c[0], c[1], c[2], c[3]}};
+    HF r2{{M::R2_64[0], M::R2_64[1], M::R2_64[2], M::R2_64[3]}};
+    return mul(a, r2);
+  }
+  static HF from_u32(const uint32_t w[8]) {
+    uint64_t c[4];
+    for (int k = 0; k < 4; k++) c[k] = (uint64_t)w[2 * k] | ((uint64_t)w[2 * k + 1] << 32);
+    return from_u64(c);
+  }
+  static HF from_uint(uint64_t v) {
+    uint64_t c[4] = {v, 0, 0, 0};
+    return from_u64(c);
+  }
+  void to_u64(uint64_t c[4]) const {
+    HF one_raw{{1, 0, 0, 0}};
+    HF r = mul(*this, one_raw);
+    for (int k = 0; k < 4; k++) c[k] = r.l[k];
+  }
+  void to_u32(uint32_t w[8]) const {
+    uint64_t c[4];
+    to_u64(c);
+    for (int k = 0; k < 4; k++) {
+      w[2 * k] = (uint32_t)c[k];
+      w[2 * k + 1] = (uint32_t)(c[k] >> 32);
+    }
+  }
+  static bool canonical_ok(const uint32_t w[8]) {  // value < m
+    uint64_t c[4];
+    for (int k = 0; k < 4; k++) c[k] = (uint64_t)w[2 * k] | ((uint64_t)w[2 * k + 1] << 32);
+    return !geq_mod(c);
+  }
+  // a^e, e as 4 little-endian 64-bit words
+  static HF pow(const HF& a, const uint64_t e[4]) {
+    HF r = one();
+    for (int k = 3; k >= 0; k--)
+      for (int b = 63; b >= 0; b--) {
+        r = sqr(r);
+        if ((e[k] >> b) & 1) r = mul(r, a);
+      }
+    return r;
+  }
+  static HF inv(const HF& a) {  // a^(m-2)
+    uint64_t e[4] = {M::P64[0] - 2, M::P64[1], M::P64[2], M::P64[3]};
+    return pow(a, e);
+  }
+
+  // Device representation: 8 words of x * 2^261 mod m.
+  static const HF& dev_r() {  // Montgomery form of 2^261 mod m
+    static const HF v = from_u64(M::DEVR_64);
+    return v;
+  }
+  static const HF& dev_r_inv() {
+    static const HF v = inv(dev_r());
+    return v;
+  }
+  static HF from_dev(const uint32_t w[8]) { return mul(from_u32(w), dev_r_inv()); }
+  void to_dev(uint32_t w[8]) const { mul(*this, dev_r()).to_u32(w); }
+};
+
+using HFq = HF<FqParams>;
+using HFr = HF<FrParams>;
+
+// ---------------------------------------------------------------- Fq2
+struct HFq2 {
+  HFq c0, c1;
+  static HFq2 zero() { return {HFq::zero(), HFq::zero()}; }
+  static HFq2 one() { return {HFq::one(), HFq::zero()}; }
+  static HFq2 add(const HFq2& a, const HFq2& b) { return {HFq::add(a.c0, b.c0), HFq::add(a.c1, b.c1)}; }
+  static HFq2 sub(const HFq2& a, const HFq2& b) { return {HFq::sub(a.c0, b.c0), HFq::sub(a.c1, b.c1)}; }
+  static HFq2 neg(const HFq2& a) { return {HFq::neg(a.c0), HFq::neg(a.c1)}; }
+  static HFq2 dbl(const HFq2& a) { return add(a, a); }
+  static HFq2 mul(const HFq2& a, const HFq2& b) {
+    HFq v0 = HFq::mul(a.c0, b.c0), v1 = HFq::mul(a.c1, b.c1);
+    HFq s = HFq::mul(HFq::add(a.c0, a.c1), HFq::add(b.c0, b.c1));
+    return {HFq::sub(v0, v1), HFq::sub(HFq::sub(s, v0), v1)};
+  }
+  static HFq2 sqr(const HFq2& a) { return mul(a, a); }
+  static HFq2 scale(const HFq2& a, const HFq& k) { return {HFq::mul(a.c0, k), HFq::mul(a.c1, k)}; }
+  static HFq2 conj(const HFq2& a) { return {a.c0, HFq::neg(a.c1)}; }
+  static HFq2 inv(const HFq2& a) {
+    HFq d = HFq::inv(HFq::add(HFq::sqr(a.c0), HFq::sqr(a.c1)));
+    return {HFq::mul(a.c0, d), HFq::neg(HFq::mul(a.c1, d))};
+  }
+  // multiply by xi = 9 + i
+  static HFq2 mul_xi(const HFq2& a) {
+    HFq nine = HFq::from_uint(9);
+    return {HFq::sub(HFq::mul(a.c0, nine), a.c1), HFq::add(HFq::mul(a.c1, nine), a.c0)};
+  }
+  bool is_zero() const { return c0.is_zero() && c1.is_zero(); }
+  bool operator==(const HFq2& o) const { return c0 == o.c0 && c1 == o.c1; }
+  bool operator!=(const HFq2& o) const { return !(*this == o); }
+  static HFq2 pow(const HFq2& a, const uint64_t* e, int nwords) {
+    HFq2 r = one();
+    for (int k = nwords - 1; k >= 0; k--)
+      for (int b = 63; b >= 0; b--) {
+        r = sqr(r);
+        if ((e[k] >> b) & 1) r = mul(r, a);
+      }
+    return r;
+  }
+};
+
+// ---------------------------------------------------------------- Jacobian points
+// Generic over the coordinate field (HFq for G1, HFq2 for G2); a = 0.
+template <class F>
+struct Jac {
+  F X, Y, Z;  // x = X/Z^2, y = Y/Z^3; Z = 0 is infinity
+  static Jac inf() { return {F::one(), F::one(), F::zero()}; }
+  bool is_inf() const { return Z.is_zero(); }
+  static Jac from_affine(const F& x, const F& y) { return {x, y, F::one()}; }
+
+  static Jac dbl(const Jac& p) {
+    if (p.is_inf() || p.Y.is_zero()) return inf();
+    F YY = F::sqr(p.Y);
+    F S = F::dbl(F::dbl(F::mul(p.X, YY)));
+    F XX = F::sqr(p.X);
+    F M = F::add(F::dbl(XX), XX);
+    F X3 = F::sub(F::sqr(M), F::dbl(S));
+    F YYYY8 = F::dbl(F::dbl(F::dbl(F::sqr(YY))));
+    F Y3 = F::sub(F::mul(M, F::sub(S, X3)), YYYY8);
+    F Z3 = F::dbl(F::mul(p.Y, p.Z));
+    return {X3, Y3, Z3};
+  }
+  static Jac add(const Jac& p, const Jac& q) {
+    if (p.is_inf()) return q;
+    if (q.is_inf()) return p;
+    F Z1Z1 = F::sqr(p.Z), Z2Z2 = F::sqr(q.Z);
+    F U1 = F::mul(p.X, Z2Z2), U2 = F::mul(q.X, Z1Z1);
+    F S1 = F::mul(F::mul(p.Y, q.Z), Z2Z2), S2 = F::mul(F::mul(q.Y, p.Z), Z1Z1);
+    if (U1 == U2) {
+      if (S1 == S2) return dbl(p);
+      return inf();
+    }
+    F H = F::sub(U2, U1), Rr = F::sub(S2, S1);
+    F HH = F::sqr(H), HHH = F::mul(H, HH);
+    F V = F::mul(U1, HH);
+    F X3 = F::sub(F::sub(F::sqr(Rr), HHH), F::dbl(V));
+    F Y3 = F::sub(F::mul(Rr, F::sub(V, X3)), F::mul(S1, HHH));
+    F Z3 = F::mul(F::mul(p.Z, q.Z), H);
+    return {X3, Y3, Z3};
+  }
+  static Jac neg(const Jac& p) { return {p.X, F::neg(p.Y), p.Z}; }
+  // scalar given as little-endian 64-bit words (4-bit fixed window)
+  static Jac mul(const Jac& p, const uint64_t k[4]) {
+    Jac table[16];
+    table[0] = inf();
+    for (int i = 1; i < 16; i++) table[i] = add(table[i - 1], p);
+    Jac acc = inf();
+    for (int w = 63; w >= 0; w--) {
+      for (int d = 0; d < 4; d++) acc = dbl(acc);
+      const int nib = (int)((k[w / 16] >> (4 * (w % 16))) & 15);
+      if (nib) acc = add(acc, table[nib]);
+    }
+    return acc;
+  }
+  void to_affine(F& x, F& y) const {  // requires !is_inf()
+    F zi = F::inv(Z);
+    F zi2 = F::sqr(zi);
+    x = F::mul(X, zi2);
+    y = F::mul(Y, F::mul(zi2, zi));
+  }
+  bool eq(const Jac& q) const {
+    if (is_inf() || q.is_inf()) return is_inf() && q.is_inf();
+    F Z1Z1 = F::sqr(Z), Z2Z2 = F::sqr(q.Z);
+    if (F::mul(X, Z2Z2) != F::mul(q.X, Z1Z1)) return false;
+    return F::mul(F::mul(Y, q.Z), Z2Z2) == F::mul(F::mul(q.Y, Z), Z1Z1);
+  }
+};
+
+using G1J = Jac<HFq>;
+using G2J = Jac<HFq2>;
+
+// XYZZ (x = X/ZZ, y = Y/ZZZ, ZZ^3 = ZZZ^2) -> Jacobian without an inversion.
+template <class F>
+inline Jac<F> xyzz_to_jac(const F& X, const F& Y, const F& ZZ, const F& ZZZ) {
+  if (ZZ.is_zero()) return Jac<F>::inf();
+  // Let Z = ZZ * ZZZ.  Then Z^2 = ZZ^2 ZZZ^2 and x = X/ZZ = (X ZZ ZZZ^2)/Z^2;
+  // Z^3 = ZZ^3 ZZZ^3 = ZZZ^2 ZZZ^3 (since ZZ^3 = ZZZ^2), so y = Y/ZZZ = (Y ZZZ^4)/Z^3.
+  F Z = F::mul(ZZ, ZZZ);
+  F ZZZ2 = F::sqr(ZZZ);
+  F Xj = F::mul(F::mul(X, ZZ), ZZZ2);
+  F Yj = F::mul(Y, F::sqr(ZZZ2));
+  return {Xj, Yj, Z};
+}
+
+}  // namespace host
+}  // namespace zkvc

@@ -1,0 +1,50 @@
+// Pippenger multi-scalar multiplication over G1 and G2.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "host_field.hpp"
+#include "util.hpp"
+
+namespace zkvc {
+
+struct MsmInput {
+  const uint32_t* points = nullptr;   // affine, device Montgomery layout, (0,0) = infinity
+  size_t npoints = 0;                 // number of valid points
+  const uint32_t* scalars = nullptr;  // Fr elements, 8 words each
+  size_t nscalars = 0;
+  bool scalars_mont = false;          // scalars in device Montgomery form
+  int point_index_bitrev = 0;         // if > 0: scalar j pairs with point bitrev_{bits}(j)
+  int max_bits = 254;                 // bound on |scalar| after sign folding (signed view)
+};
+
+struct MsmTiming {
+  float device_ms = 0.f;
+};
+
+// Returns sum_j s_j P_idx(j) as a host Jacobian point.  The bulk work (digit
+// recoding, counting sort by bucket, bucket accumulation, bucket reduction per
+// window) runs on the device; the host combines the per-window sums.
+host::G1J msm_g1(const MsmInput& in, Workspace& ws, hipStream_t st);
+host::G2J msm_g2(const MsmInput& in, Workspace& ws, hipStream_t st);
+
+// Pick the window width c and the number of signed windows for n terms with
+// scalars of at most `bits` bits (after folding s > (r-1)/2 to -(r - s)).
+void msm_choose_window(size_t n, int bits, int* c, int* nw);
+
+// Fixed-base batch multiplication by the standard generator: out_j = [k_j] G,
+// written affine (device Montgomery layout unless out_canonical).
+void fixed_base_g1(const uint32_t* scalars, bool scalars_mont, size_t n, uint32_t* out, bool out_canonical,
+                   Workspace& ws, hipStream_t st);
+void fixed_base_g2(const uint32_t* scalars, bool scalars_mont, size_t n, uint32_t* out, bool out_canonical,
+                   Workspace& ws, hipStream_t st);
+
+// Canonical <-> internal layout conversion of affine point arrays.
+void points_to_mont_g1(const uint32_t* in, uint32_t* out, size_t n, hipStream_t st);
+void points_to_mont_g2(const uint32_t* in, uint32_t* out, size_t n, hipStream_t st);
+
+// Host helpers: internal device words <-> host field elements.
+host::HFq2 hfq2_from_dev(const uint32_t* w);
+void hfq2_to_dev(const host::HFq2& a, uint32_t* w);
+
+}  // namespace zkvc

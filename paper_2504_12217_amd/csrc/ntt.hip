@@ -1,0 +1,361 @@
+// Fr number-theoretic transforms for the QAP quotient (iNTT, coset NTT, coset iNTT).
+//
+// A transform of N = 2^L points runs as a sequence of in-place passes (the
+// four-step decomposition of Bailey applied recursively).  Pass j owns a
+// contiguous bit range of the element address: for every setting of the other
+// bits ("group") it performs a 2^k-point radix-2 transform in LDS over that
+// bit range, then multiplies by the inter-pass twiddles.  With address
+//   a = hi * M + t * 2^B + g     (M = 2^(B+k), t < 2^k, g < 2^B)
+// a decimation-in-frequency (DIF) pass leaves position t holding frequency
+// bitrev_k(t) of its group and then multiplies it by omega_M^(g * bitrev_k(t)).
+// Running DIF passes from the top bit range down yields the full transform in
+// bit-reversed order.  The decimation-in-time (DIT) transform is the exact
+// transpose: passes from the bottom bit range up, twiddle first, then DIT
+// butterflies, mapping bit-reversed input to natural-order output.
+//
+// Memory: elements are 32 bytes (8 words).  A workgroup stages 1024 elements
+// (its groups, chosen so that global loads and stores come in runs of
+// consecutive addresses) in LDS as 29-bit limbs, 36 bytes each.
+#include "ntt.hpp"
+
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "field.hpp"
+#include "host_field.hpp"
+#include "util.hpp"
+
+namespace zkvc {
+
+constexpr int NTT_MAX_K = 10;
+constexpr int NTT_E = 1 << NTT_MAX_K;  // elements per workgroup
+constexpr int NTT_THREADS = NTT_E / 2;
+constexpr int POW_BITS = 14;           // two-level tables: 2^14 + 2^14 entries
+constexpr int MAX_LOG = 28;
+
+struct PassParams {
+  uint32_t* data;
+  int log_n, log_m, k, log_g;
+  int dit, inverse, twiddle;
+  int first, last;
+  int pre_mont, pre_coset, pre_bitrev;
+  int post_canon, post_coset, post_bitrev;
+  const uint32_t* pre_const;
+  const uint32_t* post_const;
+};
+
+__device__ __forceinline__ Fr pow_lookup(const PowTable& t, uint32_t x) {
+  const Fr a = Fr::load(t.lo + 8u * (x & ((1u << POW_BITS) - 1u)));
+  const Fr b = Fr::load(t.hi + 8u * (x >> POW_BITS));
+  return Fr::mul(a, b);
+}
+
+__device__ __forceinline__ uint32_t bitrev_bits(uint32_t a, int bits) {
+  return bits == 0 ? 0u : (__builtin_bitreverse32(a) >> (32 - bits));
+}
+
+__device__ __forceinline__ void lds_put(uint32_t* lds, uint32_t slot, const Fr& x) {
+#pragma unroll
+  for (int q = 0; q < NL; q++) lds[slot * NL + q] = x.v[q];
+}
+__device__ __forceinline__ Fr lds_get(const uint32_t* lds, uint32_t slot) {
+  Fr x;
+#pragma unroll
+  for (int q = 0; q < NL; q++) x.v[q] = lds[slot * NL + q];
+  return x;
+}
+
+__global__ void __launch_bounds__(NTT_THREADS) k_ntt_pass(PassParams p, NttTables T) {
+  extern __shared__ uint32_t lds[];
+  const int k = p.k;
+  const uint32_t K = 1u << k;
+  const uint32_t G = 1u << p.log_g;
+  const uint32_t E = K * G;
+  const int B = p.log_m - k;
+  const uint32_t gmask = (1u << B) - 1u;
+  const uint32_t gamma0 = blockIdx.x * G;
+  const int tw_shift = MAX_LOG - p.log_m;
+
+  // ---- load (global -> registers -> LDS), with first-pass fusions and DIT twiddles
+  for (uint32_t e = threadIdx.x; e < E; e += blockDim.x) {
+    uint32_t gl, t;
+    if (B == 0) {
+      gl = e >> k;
+      t = e & (K - 1u);
+    } else {
+      gl = e & (G - 1u);
+      t = e >> p.log_g;
+    }
+    const uint32_t gamma = gamma0 + gl;
+    const uint32_t g = gamma & gmask;
+    const uint32_t addr = ((gamma >> B) << p.log_m) | (t << B) | g;
+    Fr x = Fr::load(p.data + 8ull * addr);
+    if (p.first) {
+      if (p.pre_mont) x = Fr::to_mont(x);
+      if (p.pre_coset) {
+        const uint32_t idx = p.pre_bitrev ? bitrev_bits(addr, p.log_n) : addr;
+        x = Fr::mul(x, pow_lookup(T.g[p.pre_coset < 0 ? 1 : 0], idx));
+      }
+      if (p.pre_const) x = Fr::mul(x, Fr::load(p.pre_const));
+    }
+    if (p.dit && p.twiddle) {
+      const uint32_t ex = g * bitrev_bits(t, k);
+      if (ex) x = Fr::mul(x, pow_lookup(T.w[p.inverse], ex << tw_shift));
+    }
+    lds_put(lds, gl * K + t, x);
+  }
+  __syncthreads();
+
+  // ---- radix-2 stages in LDS
+  const uint32_t half = K >> 1;
+  const uint32_t* local = k > 0 ? T.local[p.inverse] + 8u * (half - 1u) : T.local[p.inverse];
+  for (int st = 0; st < k; st++) {
+    const int s = p.dit ? st : (k - 1 - st);
+    const uint32_t smask = (1u << s) - 1u;
+    for (uint32_t bi = threadIdx.x; bi < E / 2; bi += blockDim.x) {
+      const uint32_t gl = bi >> (k - 1);
+      const uint32_t j = bi & (half - 1u);
+      const uint32_t t0 = ((j >> s) << (s + 1)) | (j & smask);
+      const uint32_t t1 = t0 | (1u << s);
+      const uint32_t widx = (j & smask) << (k - 1 - s);
+      Fr a = lds_get(lds, gl * K + t0);
+      Fr b = lds_get(lds, gl * K + t1);
+      if (p.dit) {
+        if (widx) b = Fr::mul(b, Fr::load(local + 8u * widx));
+        const Fr u = Fr::add(a, b);
+        const Fr v = Fr::sub(a, b);
+        a = u;
+        b = v;
+      } else {
+        const Fr u = Fr::add(a, b);
+        Fr v = Fr::sub(a, b);
+        if (widx) v = Fr::mul(v, Fr::load(local + 8u * widx));
+        a = u;
+        b = v;
+      }
+      lds_put(lds, gl * K + t0, a);
+      lds_put(lds, gl * K + t1, b);
+    }
+    __syncthreads();
+  }
+
+  // ---- store, with DIF twiddles and last-pass fusions
+  for (uint32_t e = threadIdx.x; e < E; e += blockDim.x) {
+    uint32_t gl, t;
+    if (B == 0) {
+      gl = e >> k;
+      t = e & (K - 1u);
+    } else {
+      gl = e & (G - 1u);
+      t = e >> p.log_g;
+    }
+    const uint32_t gamma = gamma0 + gl;
+    const uint32_t g = gamma & gmask;
+    const uint32_t addr = ((gamma >> B) << p.log_m) | (t << B) | g;
+    Fr x = lds_get(lds, gl * K + t);
+    if (!p.dit && p.twiddle) {
+      const uint32_t ex = g * bitrev_bits(t, k);
+      if (ex) x = Fr::mul(x, pow_lookup(T.w[p.inverse], ex << tw_shift));
+    }
+    if (p.last) {
+      if (p.post_coset) {
+        const uint32_t idx = p.post_bitrev ? bitrev_bits(addr, p.log_n) : addr;
+        x = Fr::mul(x, pow_lookup(T.g[p.post_coset < 0 ? 1 : 0], idx));
+      }
+      if (p.post_const) x = Fr::mul(x, Fr::load(p.post_const));
+      if (p.post_canon) x = Fr::from_mont(x);
+    }
+    x.store(p.data + 8ull * addr);
+  }
+}
+
+__global__ void k_bitrev(uint32_t* data, int log_n, uint32_t n) {
+  const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  const uint32_t b = bitrev_bits(a, log_n);
+  if (a < b) {
+    uint4* pa = reinterpret_cast<uint4*>(data + 8ull * a);
+    uint4* pb = reinterpret_cast<uint4*>(data + 8ull * b);
+    const uint4 a0 = pa[0], a1 = pa[1], b0 = pb[0], b1 = pb[1];
+    pa[0] = b0;
+    pa[1] = b1;
+    pb[0] = a0;
+    pb[1] = a1;
+  }
+}
+
+// ------------------------------------------------------------------ host side
+namespace {
+
+struct DeviceTables {
+  DevBuf buf;
+  NttTables t;
+};
+
+void pow_table_host(const host::HFr& base, std::vector<uint32_t>& lo, std::vector<uint32_t>& hi) {
+  const int n = 1 << POW_BITS;
+  lo.resize(8 * n);
+  hi.resize(8 * n);
+  host::HFr x = host::HFr::one();
+  for (int i = 0; i < n; i++) {
+    x.to_dev(&lo[8 * i]);
+    x = host::HFr::mul(x, base);
+  }
+  // x = base^(2^14)
+  const host::HFr step = x;
+  host::HFr y = host::HFr::one();
+  for (int i = 0; i < n; i++) {
+    y.to_dev(&hi[8 * i]);
+    y = host::HFr::mul(y, step);
+  }
+}
+
+DeviceTables* build_tables() {
+  using host::HFr;
+  // omega_{2^28} = 5^((r-1)/2^28)
+  uint64_t e[4];
+  {
+    // (r - 1) >> 28
+    uint64_t rm1[4] = {FrParams::P64[0] - 1, FrParams::P64[1], FrParams::P64[2], FrParams::P64[3]};
+    for (int k = 0; k < 4; k++) e[k] = (rm1[k] >> 28) | (k < 3 ? (rm1[k + 1] << 36) : 0);
+  }
+  const HFr five = HFr::from_uint(5);
+  const HFr w = HFr::pow(five, e);
+  const HFr wi = HFr::inv(w);
+  const HFr gi = HFr::inv(five);
+  std::vector<uint32_t> tabs[8];
+  pow_table_host(w, tabs[0], tabs[1]);
+  pow_table_host(wi, tabs[2], tabs[3]);
+  pow_table_host(five, tabs[4], tabs[5]);
+  pow_table_host(gi, tabs[6], tabs[7]);
+  // local tables: omega_{2^k}^j for k = 1..10, j < 2^(k-1), at offset 2^(k-1) - 1
+  std::vector<uint32_t> loc[2];
+  for (int dir = 0; dir < 2; dir++) {
+    loc[dir].assign(8 * ((1 << NTT_MAX_K) - 1), 0);
+    for (int k = 1; k <= NTT_MAX_K; k++) {
+      HFr wk = dir == 0 ? w : wi;
+      for (int q = k; q < MAX_LOG; q++) wk = HFr::sqr(wk);  // omega_{2^k}
+      HFr x = HFr::one();
+      const int off = (1 << (k - 1)) - 1;
+      for (int j = 0; j < (1 << (k - 1)); j++) {
+        x.to_dev(&loc[dir][8 * (off + j)]);
+        x = HFr::mul(x, wk);
+      }
+    }
+  }
+  // 2^-L and (g^(2^L) - 1)^-1 for every L
+  std::vector<uint32_t> ninv(8 * (MAX_LOG + 1)), zinv(8 * (MAX_LOG + 1));
+  {
+    const HFr two_inv = HFr::inv(HFr::from_uint(2));
+    HFr x = HFr::one();
+    HFr gpow = five;  // g^(2^L)
+    for (int L = 0; L <= MAX_LOG; L++) {
+      x.to_dev(&ninv[8 * L]);
+      x = HFr::mul(x, two_inv);
+      HFr::inv(HFr::sub(gpow, HFr::one())).to_dev(&zinv[8 * L]);
+      gpow = HFr::sqr(gpow);
+    }
+  }
+  size_t total = 0;
+  for (auto& v : tabs) total += v.size();
+  total += loc[0].size() + loc[1].size() + ninv.size() + zinv.size();
+  auto* dt = new DeviceTables();
+  dt->buf.alloc(total * 4);
+  uint32_t* base = dt->buf.get();
+  size_t off = 0;
+  const uint32_t* ptrs[10];
+  for (int i = 0; i < 8; i++) {
+    ZK_HIP(hipMemcpy(base + off, tabs[i].data(), tabs[i].size() * 4, hipMemcpyHostToDevice));
+    ptrs[i] = base + off;
+    off += tabs[i].size();
+  }
+  for (int dir = 0; dir < 2; dir++) {
+    ZK_HIP(hipMemcpy(base + off, loc[dir].data(), loc[dir].size() * 4, hipMemcpyHostToDevice));
+    ptrs[8 + dir] = base + off;
+    off += loc[dir].size();
+  }
+  dt->t.w[0] = {ptrs[0], ptrs[1]};
+  dt->t.w[1] = {ptrs[2], ptrs[3]};
+  dt->t.g[0] = {ptrs[4], ptrs[5]};
+  dt->t.g[1] = {ptrs[6], ptrs[7]};
+  dt->t.local[0] = ptrs[8];
+  dt->t.local[1] = ptrs[9];
+  ZK_HIP(hipMemcpy(base + off, ninv.data(), ninv.size() * 4, hipMemcpyHostToDevice));
+  dt->t.ninv = base + off;
+  off += ninv.size();
+  ZK_HIP(hipMemcpy(base + off, zinv.data(), zinv.size() * 4, hipMemcpyHostToDevice));
+  dt->t.coset_zinv = base + off;
+  off += zinv.size();
+  return dt;
+}
+
+}  // namespace
+
+const NttTables& ntt_tables(int device) {
+  static std::mutex mu;
+  static std::map<int, DeviceTables*> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(device);
+  if (it != cache.end()) return it->second->t;
+  DeviceTables* dt = build_tables();
+  cache[device] = dt;
+  return dt->t;
+}
+
+void ntt_launch(uint32_t* data, int log_n, bool dit, bool inverse, const NttFuse& fuse, hipStream_t st) {
+  ZK_REQUIRE(log_n >= 0 && log_n <= MAX_LOG, "log_n out of range");
+  const NttTables& T = ntt_tables(current_device());
+  const int L = log_n;
+  const int npass = L == 0 ? 1 : (L + NTT_MAX_K - 1) / NTT_MAX_K;
+  std::vector<int> ks(npass);
+  for (int j = 0; j < npass; j++) ks[j] = L / npass + (j < L % npass ? 1 : 0);
+  // DIF order: top bit range first.  log_m of pass j = L - sum_{i<j} k_i.
+  std::vector<int> log_ms(npass);
+  int lm = L;
+  for (int j = 0; j < npass; j++) {
+    log_ms[j] = lm;
+    lm -= ks[j];
+  }
+  for (int step = 0; step < npass; step++) {
+    const int j = dit ? (npass - 1 - step) : step;
+    const int k = ks[j];
+    const int B = log_ms[j] - k;
+    PassParams p{};
+    p.data = data;
+    p.log_n = L;
+    p.log_m = log_ms[j];
+    p.k = k;
+    const int max_log_g = NTT_MAX_K - k;
+    const int log_groups_total = L - k;
+    p.log_g = max_log_g < log_groups_total ? max_log_g : log_groups_total;
+    p.dit = dit;
+    p.inverse = inverse ? 1 : 0;
+    p.twiddle = B > 0;
+    p.first = step == 0;
+    p.last = step == npass - 1;
+    p.pre_mont = fuse.in_canonical;
+    p.pre_coset = fuse.pre_coset;
+    p.pre_bitrev = fuse.pre_bitrev;
+    p.pre_const = fuse.pre_const;
+    p.post_canon = fuse.out_canonical;
+    p.post_coset = fuse.post_coset;
+    p.post_bitrev = fuse.post_bitrev;
+    p.post_const = fuse.post_const;
+    const unsigned grid = 1u << (log_groups_total - p.log_g);
+    const size_t lds = (size_t)(1u << (k + p.log_g)) * NL * 4;
+    unsigned threads = (1u << (k + p.log_g)) / 2;
+    if (threads < 64) threads = 64;
+    hipLaunchKernelGGL(k_ntt_pass, dim3(grid), dim3(threads), lds, st, p, T);
+    ZK_HIP(hipGetLastError());
+  }
+}
+
+void bitrev_launch(uint32_t* data, int log_n, hipStream_t st) {
+  if (log_n < 2) return;
+  const uint32_t n = 1u << log_n;
+  hipLaunchKernelGGL(k_bitrev, dim3(cdiv(n, 256)), dim3(256), 0, st, data, log_n, n);
+  ZK_HIP(hipGetLastError());
+}
+
+}  // namespace zkvc

@@ -1,0 +1,48 @@
+// Number-theoretic transforms over Fr (the QAP's domain of 2^L points).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace zkvc {
+
+// Two-level power tables for a fixed base b: b^x = lo[x & 0x3fff] * hi[x >> 14]
+// for x < 2^28, elements in device Montgomery form (8 words each).
+struct PowTable {
+  const uint32_t* lo;
+  const uint32_t* hi;
+};
+
+// Device-resident constants for every transform size up to 2^28.
+struct NttTables {
+  PowTable w[2];      // powers of omega_{2^28} (index 0) and of its inverse (index 1)
+  PowTable g[2];      // powers of the coset shift g = 5 and of g^-1
+  const uint32_t* local[2];  // omega_{2^k}^j for k = 1..10, j < 2^(k-1), at offset 2^(k-1) - 1
+  const uint32_t* ninv;      // 2^-L for L = 0..28 (8 words each)
+  const uint32_t* coset_zinv; // (g^(2^L) - 1)^-1 for L = 0..28: 1/t on the coset g H
+};
+
+// Options fused into the first and last pass.
+struct NttFuse {
+  bool in_canonical = false;   // input elements are canonical integers (convert to Montgomery)
+  bool out_canonical = false;  // write canonical integers
+  int pre_coset = 0;           // multiply input element of index i by g^(+1 / -1 * i) before
+  bool pre_bitrev = false;     //   ... where i = bitrev(address) if set, else the address
+  const uint32_t* pre_const = nullptr;  // optional extra factor on the input (8 words, Montgomery)
+  int post_coset = 0;          // multiply output element of index i by g^(+-i) after
+  bool post_bitrev = false;    //   ... where i = bitrev(address) if set
+  const uint32_t* post_const = nullptr; // optional extra factor on the output
+};
+
+const NttTables& ntt_tables(int device);
+
+// In-place transform of n = 2^log_n Fr elements (8 words each, device Montgomery
+// form unless fused conversions say otherwise).
+//   dit = false: decimation in frequency, natural-order input -> bit-reversed output
+//   dit = true : decimation in time, bit-reversed input -> natural-order output
+//   inverse    : use omega^-1 (no 1/N scaling here; pass it as pre/post_const)
+void ntt_launch(uint32_t* data, int log_n, bool dit, bool inverse, const NttFuse& fuse, hipStream_t st);
+
+// In-place bit-reversal permutation of 2^log_n elements.
+void bitrev_launch(uint32_t* data, int log_n, hipStream_t st);
+
+}  // namespace zkvc

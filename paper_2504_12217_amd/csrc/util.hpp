@@ -1,0 +1,97 @@
+// Error plumbing, device buffers and scratch workspaces for the library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "zkvc.h"
+
+namespace zkvc {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define ZK_HIP(expr)                                                                          \
+  do {                                                                                        \
+    hipError_t _e = (expr);                                                                   \
+    if (_e != hipSuccess)                                                                     \
+      throw ::zkvc::Error(ZKVC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));   \
+  } while (0)
+
+#define ZK_REQUIRE(cond, msg)                                   \
+  do {                                                          \
+    if (!(cond)) throw ::zkvc::Error(ZKVC_EINVAL, (msg));       \
+  } while (0)
+
+void set_last_error(const std::string& m);
+size_t memory_budget_bytes();  // optional cap from ZKVC_MEMORY_BUDGET_MB (0 = none)
+
+// Owning device allocation.
+class DevBuf {
+ public:
+  DevBuf() = default;
+  explicit DevBuf(size_t bytes) { alloc(bytes); }
+  ~DevBuf() { release(); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p_(o.p_), n_(o.n_) { o.p_ = nullptr; o.n_ = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p_ = o.p_; n_ = o.n_; o.p_ = nullptr; o.n_ = 0; }
+    return *this;
+  }
+  void alloc(size_t bytes);
+  void release();
+  void ensure(size_t bytes) { if (bytes > n_) { release(); alloc(bytes); } }
+  template <class T = uint32_t>
+  T* get() const { return reinterpret_cast<T*>(p_); }
+  size_t size() const { return n_; }
+
+ private:
+  void* p_ = nullptr;
+  size_t n_ = 0;
+};
+
+// Grow-only named scratch buffers.  Not thread-safe by itself: each owner
+// (a proving key, or one stream of the standalone calls) has its own.
+class Workspace {
+ public:
+  template <class T = uint32_t>
+  T* get(int slot, size_t bytes) {
+    auto& b = bufs_[slot];
+    b.ensure(bytes < 256 ? 256 : bytes);
+    return b.get<T>();
+  }
+  size_t bytes() const {
+    size_t s = 0;
+    for (auto& kv : bufs_) s += kv.second.size();
+    return s;
+  }
+  void clear() { bufs_.clear(); }
+
+ private:
+  std::map<int, DevBuf> bufs_;
+};
+
+// One workspace per (device, stream) for the standalone entry points.
+struct StreamWorkspace {
+  std::mutex mu;
+  Workspace ws;
+};
+StreamWorkspace& stream_workspace(hipStream_t st);
+
+int current_device();
+
+inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
+
+// Fill a u32 device array with a value (a kernel, so it is safe inside captured graphs).
+void fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
+
+}  // namespace zkvc
