@@ -128,29 +128,54 @@ def verify(vk, X, Y, proof):
     ])
 
 
-def trapdoor_scalars(s, kind, toxic, X, W, r, s_rand, z=None):
+_SHARED = {}
+
+
+def _row_sums(job):
+    """Sums over rows c0 <= c < c1 of L_c(tau) <A_c,a>, ..., and of the witness-only parts."""
+    s, kind, zp, tau, n_dom, c0, c1 = job
+    a = _SHARED["a"]
+    first = r1cs.first_witness(s)
+    L = qap.lagrange_basis_range(n_dom, tau, c0, c1)
+    sums = [0, 0, 0, 0, 0, 0]
+    for c in range(c0, c1):
+        lc = L[c - c0]
+        for q, row in enumerate(r1cs.row(s, kind, c, zp)):
+            full = wit = 0
+            for v, coef in row.items():
+                term = coef * a[v]
+                full += term
+                if v >= first:
+                    wit += term
+            sums[q] += lc * full
+            sums[3 + q] += lc * wit
+    return [x % R for x in sums]
+
+
+def trapdoor_scalars(s, kind, toxic, X, W, r, s_rand, z=None, workers=1):
     """Discrete logarithms (base the generators) of every proof component.
 
     With L_c(tau) the Lagrange basis at tau:
       A(tau) = sum_c <A_c,a> L_c(tau), and likewise B(tau), C(tau);
       the witness-only parts use the assignment with a_0..a_l set to zero;
       h(tau) t(tau) = A(tau) B(tau) - C(tau) for a satisfying assignment.
+    The row sums may be split over `workers` processes (same sums, any order).
     """
     n_dom = r1cs.domain_size(s, kind)
-    L = qap.lagrange_basis_at(n_dom, toxic.tau)
     a, Y = r1cs.assignment(s, kind, X, W, z)
-    ell = r1cs.num_public(s)
-    a_wit = [0] * (ell + 1) + a[ell + 1:]
-    At = Bt = Ct = Aw = Bw = Cw = 0
-    for c, (Ar, Br, Cr) in enumerate(r1cs.rows(s, kind, z)):
-        lc = L[c]
-        At += lc * r1cs.dot(Ar, a)
-        Bt += lc * r1cs.dot(Br, a)
-        Ct += lc * r1cs.dot(Cr, a)
-        Aw += lc * r1cs.dot(Ar, a_wit)
-        Bw += lc * r1cs.dot(Br, a_wit)
-        Cw += lc * r1cs.dot(Cr, a_wit)
-    At, Bt, Ct, Aw, Bw, Cw = (x % R for x in (At, Bt, Ct, Aw, Bw, Cw))
+    zp = r1cs.z_powers(s, z) if kind in r1cs.CRPC_KINDS else None
+    nrows = r1cs.num_constraints(s, kind) + r1cs.num_public(s) + 1
+    _SHARED["a"] = a
+    if workers <= 1:
+        parts = [_row_sums((s, kind, zp, toxic.tau, n_dom, 0, nrows))]
+    else:
+        import multiprocessing as mp
+        step = -(-nrows // (workers * 4))
+        jobs = [(s, kind, zp, toxic.tau, n_dom, c, min(c + step, nrows)) for c in range(0, nrows, step)]
+        with mp.get_context("fork").Pool(workers) as pool:
+            parts = pool.map(_row_sums, jobs)
+    _SHARED.clear()
+    At, Bt, Ct, Aw, Bw, Cw = (sum(p[q] for p in parts) % R for q in range(6))
     d_inv = _inv(toxic.delta)
     msm_l = (toxic.beta * Aw + toxic.alpha * Bw + Cw) * d_inv % R
     msm_h = (At * Bt - Ct) * d_inv % R
@@ -161,6 +186,6 @@ def trapdoor_scalars(s, kind, toxic, X, W, r, s_rand, z=None):
             "msm_H": msm_h, "Y": Y}
 
 
-def expected_proof_trapdoor(s, kind, toxic, X, W, r, s_rand, z=None):
-    t = trapdoor_scalars(s, kind, toxic, X, W, r, s_rand, z)
+def expected_proof_trapdoor(s, kind, toxic, X, W, r, s_rand, z=None, workers=1):
+    t = trapdoor_scalars(s, kind, toxic, X, W, r, s_rand, z, workers)
     return Proof(g1_mul(G1_GEN, t["A"]), g2_mul(G2_GEN, t["B"]), g1_mul(G1_GEN, t["C"])), t["Y"]

@@ -44,6 +44,21 @@ def lagrange_basis_at(n, tau):
     return out
 
 
+def lagrange_basis_range(n, tau, c0, c1):
+    """[L_c(tau) for c0 <= c < c1] by the same closed form as lagrange_basis_at."""
+    omega = ntt.root_of_unity(n)
+    tn1 = (pow(tau, n, R) - 1) % R
+    if tn1 == 0:
+        raise ValueError("tau lies in the evaluation domain")
+    k = tn1 * pow(n, -1, R) % R
+    out = []
+    wc = pow(omega, c0, R)
+    for _ in range(c0, c1):
+        out.append(wc * k % R * pow((tau - wc) % R, -1, R) % R)
+        wc = wc * omega % R
+    return out
+
+
 def lagrange_basis_at_product_form(n, tau):
     """L_c(tau) = prod_{k != c} (tau - omega^k) / (omega^c - omega^k); O(n^2), for pins."""
     omega = ntt.root_of_unity(n)
@@ -73,6 +88,49 @@ def var_polys_at(s, kind, tau, z=None):
         for i, coef in C.items():
             w[i] = (w[i] + coef * L[c]) % R
     return u, v, w
+
+
+_SHARED = {}
+
+
+def _var_poly_part(job):
+    s, kind, zp, tau, n_dom, c0, c1 = job
+    want = _SHARED["vars"]
+    L = lagrange_basis_range(n_dom, tau, c0, c1)
+    acc = {}
+    for c in range(c0, c1):
+        for q, row in enumerate(r1cs.row(s, kind, c, zp)):
+            for i, coef in row.items():
+                if i in want:
+                    key = (q, i)
+                    acc[key] = (acc.get(key, 0) + coef * L[c - c0]) % R
+    return acc
+
+
+def var_polys_sampled(s, kind, tau, variables, z=None, workers=1):
+    """{i: (u_i(tau), v_i(tau), w_i(tau))} for the listed variables only.
+
+    The same row sums as var_polys_at, restricted to a sample of variables and
+    optionally split over processes by row range.
+    """
+    n_dom = r1cs.domain_size(s, kind)
+    zp = r1cs.z_powers(s, z) if kind in r1cs.CRPC_KINDS else None
+    nrows = r1cs.num_constraints(s, kind) + r1cs.num_public(s) + 1
+    _SHARED["vars"] = set(variables)
+    if workers <= 1:
+        parts = [_var_poly_part((s, kind, zp, tau, n_dom, 0, nrows))]
+    else:
+        import multiprocessing as mp
+        step = -(-nrows // (workers * 4))
+        jobs = [(s, kind, zp, tau, n_dom, c, min(c + step, nrows)) for c in range(0, nrows, step)]
+        with mp.get_context("fork").Pool(workers) as pool:
+            parts = pool.map(_var_poly_part, jobs)
+    _SHARED.clear()
+    out = {i: [0, 0, 0] for i in variables}
+    for part in parts:
+        for (q, i), v in part.items():
+            out[i][q] = (out[i][q] + v) % R
+    return {i: tuple(v) for i, v in out.items()}
 
 
 def poly_mul(a, b):

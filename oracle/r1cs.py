@@ -124,73 +124,83 @@ def first_witness(s):
     return 1 + num_public(s)
 
 
-def rows(s, kind, z=None):
-    """Yield (A, B, C) for every nonzero row, each a {variable: coefficient} dict.
+def z_powers(s, z):
+    """[z^e for e < a*b]: the weights of the CRPC polynomials (Section III-A)."""
+    if z is None or z % R == 0:
+        raise ValueError("the CRPC kinds need a nonzero public z")
+    return [pow(z, e, R) for e in range(s.a * s.b)]
 
-    Rows come in domain order: multiplication rows 0..m-1, then the l+1
-    input-consistency rows.
+
+def row(s, kind, c, zp=None):
+    """(A, B, C) of row c as {variable: coefficient} dicts (rows past the last are empty).
+
+    zp: z_powers(s, z) for the CRPC kinds.
     """
+    m = num_constraints(s, kind)
     ell = num_public(s)
-    if kind == PLAIN:
-        for i in range(s.a):
-            for j in range(s.b):
-                base = (i * s.b + j) * (s.n - 1)
-                for k in range(s.n):
-                    A = {var_x(s, i, k): 1}
-                    B = {var_w(s, k, j): 1}
-                    if k < s.n - 1:
-                        C = {var_aux(s, base + k): 1}
-                    else:
-                        C = {var_y(s, i, j): 1}
-                        for kk in range(s.n - 1):
-                            C[var_aux(s, base + kk)] = R - 1
-                    yield A, B, C
-    elif kind == CRPC_PSQ:
-        if z is None or z % R == 0:
-            raise ValueError("CRPC_PSQ needs a nonzero public z")
-        zp = [pow(z, e, R) for e in range(s.a * s.b)]
-        for k in range(s.n):
-            A = {var_x(s, i, k): zp[i * s.b] for i in range(s.a)}
-            B = {var_w(s, k, j): zp[j] for j in range(s.b)}
+    if c >= m:
+        t = c - m
+        return ({t: 1}, {}, {}) if t <= ell else ({}, {}, {})
+    if kind in (PLAIN, PLAIN_PSQ):
+        ij, k = divmod(c, s.n)
+        i, j = divmod(ij, s.b)
+        base = ij * (s.n - 1)
+        A = {var_x(s, i, k): 1}
+        B = {var_w(s, k, j): 1}
+        if kind == PLAIN:
             if k < s.n - 1:
-                C = {var_aux(s, k): 1}
-                if k >= 1:
-                    C[var_aux(s, k - 1)] = R - 1
+                C = {var_aux(s, base + k): 1}
             else:
-                C = {var_y(s, i, j): zp[i * s.b + j] for i in range(s.a) for j in range(s.b)}
-                if s.n >= 2:
-                    C[var_aux(s, s.n - 2)] = R - 1
-            yield A, B, C
-    elif kind == PLAIN_ADD:
-        for i in range(s.a):
-            for j in range(s.b):
-                base = (i * s.b + j) * s.n
-                for k in range(s.n):
-                    yield {var_x(s, i, k): 1}, {var_w(s, k, j): 1}, {var_aux(s, base + k): 1}
-                yield ({var_aux(s, base + k): 1 for k in range(s.n)}, {0: 1}, {var_y(s, i, j): 1})
-    elif kind == PLAIN_PSQ:
-        for i in range(s.a):
-            for j in range(s.b):
-                base = (i * s.b + j) * (s.n - 1)
-                for k in range(s.n):
-                    C = {var_aux(s, base + k): 1} if k < s.n - 1 else {var_y(s, i, j): 1}
-                    if k >= 1:
-                        C[var_aux(s, base + k - 1)] = R - 1
-                    yield {var_x(s, i, k): 1}, {var_w(s, k, j): 1}, C
-    elif kind == CRPC:
-        if z is None or z % R == 0:
-            raise ValueError("CRPC needs a nonzero public z")
-        zp = [pow(z, e, R) for e in range(s.a * s.b)]
-        for k in range(s.n):
-            yield ({var_x(s, i, k): zp[i * s.b] for i in range(s.a)},
-                   {var_w(s, k, j): zp[j] for j in range(s.b)},
-                   {var_aux(s, k): 1})
-        yield ({var_aux(s, k): 1 for k in range(s.n)}, {0: 1},
-               {var_y(s, i, j): zp[i * s.b + j] for i in range(s.a) for j in range(s.b)})
-    else:
+                C = {var_y(s, i, j): 1}
+                for kk in range(s.n - 1):
+                    C[var_aux(s, base + kk)] = R - 1
+        else:
+            C = {var_aux(s, base + k): 1} if k < s.n - 1 else {var_y(s, i, j): 1}
+            if k >= 1:
+                C[var_aux(s, base + k - 1)] = R - 1
+        return A, B, C
+    if kind == PLAIN_ADD:
+        ij, k = divmod(c, s.n + 1)
+        i, j = divmod(ij, s.b)
+        base = ij * s.n
+        if k < s.n:
+            return {var_x(s, i, k): 1}, {var_w(s, k, j): 1}, {var_aux(s, base + k): 1}
+        return {var_aux(s, base + kk): 1 for kk in range(s.n)}, {0: 1}, {var_y(s, i, j): 1}
+    if kind == CRPC_PSQ:
+        k = c
+        A = {var_x(s, i, k): zp[i * s.b] for i in range(s.a)}
+        B = {var_w(s, k, j): zp[j] for j in range(s.b)}
+        if k < s.n - 1:
+            C = {var_aux(s, k): 1}
+            if k >= 1:
+                C[var_aux(s, k - 1)] = R - 1
+        else:
+            C = {var_y(s, i, j): zp[i * s.b + j] for i in range(s.a) for j in range(s.b)}
+            if s.n >= 2:
+                C[var_aux(s, s.n - 2)] = R - 1
+        return A, B, C
+    if kind == CRPC:
+        if c < s.n:
+            k = c
+            return ({var_x(s, i, k): zp[i * s.b] for i in range(s.a)},
+                    {var_w(s, k, j): zp[j] for j in range(s.b)},
+                    {var_aux(s, k): 1})
+        return ({var_aux(s, k): 1 for k in range(s.n)}, {0: 1},
+                {var_y(s, i, j): zp[i * s.b + j] for i in range(s.a) for j in range(s.b)})
+    raise ValueError("unknown kind")
+
+
+def rows(s, kind, z=None):
+    """Yield (A, B, C) for every nonzero row in domain order.
+
+    Rows 0..m-1 are the multiplication constraints, then come the l+1
+    input-consistency rows (row m + t has A = variable t, B = C = 0).
+    """
+    if kind not in KIND_NAMES:
         raise ValueError("unknown kind")
-    for t in range(ell + 1):
-        yield {t: 1}, {}, {}
+    zp = z_powers(s, z) if kind in CRPC_KINDS else None
+    for c in range(num_constraints(s, kind) + num_public(s) + 1):
+        yield row(s, kind, c, zp)
 
 
 def matmul(X, W):

@@ -31,8 +31,8 @@ namespace zkvc {
 constexpr int NTT_MAX_K = 10;
 constexpr int NTT_E = 1 << NTT_MAX_K;  // elements per workgroup
 constexpr int NTT_THREADS = NTT_E / 2;
-constexpr int POW_BITS = 14;           // two-level tables: 2^14 + 2^14 entries
-constexpr int MAX_LOG = 28;
+constexpr int POW_BITS = NTT_POW_BITS;
+constexpr int MAX_LOG = NTT_MAX_LOG;
 
 struct PassParams {
   uint32_t* data;
@@ -44,16 +44,6 @@ struct PassParams {
   const uint32_t* pre_const;
   const uint32_t* post_const;
 };
-
-__device__ __forceinline__ Fr pow_lookup(const PowTable& t, uint32_t x) {
-  const Fr a = Fr::load(t.lo + 8u * (x & ((1u << POW_BITS) - 1u)));
-  const Fr b = Fr::load(t.hi + 8u * (x >> POW_BITS));
-  return Fr::mul(a, b);
-}
-
-__device__ __forceinline__ uint32_t bitrev_bits(uint32_t a, int bits) {
-  return bits == 0 ? 0u : (__builtin_bitreverse32(a) >> (32 - bits));
-}
 
 __device__ __forceinline__ void lds_put(uint32_t* lds, uint32_t slot, const Fr& x) {
 #pragma unroll

@@ -3,7 +3,12 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "field.hpp"
+
 namespace zkvc {
+
+constexpr int NTT_POW_BITS = 14;  // two-level power tables: 2^14 + 2^14 entries
+constexpr int NTT_MAX_LOG = 28;
 
 // Two-level power tables for a fixed base b: b^x = lo[x & 0x3fff] * hi[x >> 14]
 // for x < 2^28, elements in device Montgomery form (8 words each).
@@ -34,6 +39,17 @@ struct NttFuse {
 };
 
 const NttTables& ntt_tables(int device);
+
+// base^x for x < 2^28 from a two-level table (one multiplication)
+__device__ __forceinline__ Fr pow_lookup(const PowTable& t, uint32_t x) {
+  const Fr a = Fr::load(t.lo + 8u * (x & ((1u << NTT_POW_BITS) - 1u)));
+  const Fr b = Fr::load(t.hi + 8u * (x >> NTT_POW_BITS));
+  return Fr::mul(a, b);
+}
+
+__device__ __forceinline__ uint32_t bitrev_bits(uint32_t a, int bits) {
+  return bits == 0 ? 0u : (__builtin_bitreverse32(a) >> (32 - bits));
+}
 
 // In-place transform of n = 2^log_n Fr elements (8 words each, device Montgomery
 // form unless fused conversions say otherwise).

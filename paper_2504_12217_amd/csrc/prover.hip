@@ -1,0 +1,842 @@
+// Groth16 setup and prove for Y = X W (Section II: Gen and Prove; Section III:
+// the circuits).  The constraint systems are never materialized: every
+// quantity the protocol needs is a closed-form function of the shape, the
+// circuit kind and the inputs.
+//
+// Domain and rows.  Row c of the constraint system sits at omega^c of the
+// domain H of size N = 2^L >= m + l + 1: the m multiplication rows, then one
+// input-consistency row per public variable t <= l (A = variable t, B = C = 0),
+// then zero rows.  L_c is the Lagrange basis of H.
+//
+// Variables.  0 = constant 1; x_ik at 1 + i n + k; y_ij at 1 + a n + i b + j;
+// w_kj at l + 1 + k b + j; then the auxiliary variables of each kind:
+//   PLAIN      p_ijk = x_ik w_kj (k < n-1); row (i b + j) n + k:
+//              x_ik * w_kj = p_ijk, last row = y_ij - sum_k p_ijk
+//   PLAIN_ADD  p_ijk for every k; rows (i b + j)(n+1) + k: x_ik * w_kj = p_ijk,
+//              then (sum_k p_ijk) * 1 = y_ij
+//   PLAIN_PSQ  prefix sums s_ijk (k < n-1); row (i b + j) n + k:
+//              x_ik * w_kj = s_ijk - s_ij(k-1), last row = y_ij - s_ij(n-2)
+//   CRPC_PSQ   prefix sums s_k of X_k(z) W_k(z) (k < n-1); row k:
+//              X_k(z) * W_k(z) = s_k - s_(k-1), last row = Y(z) - s_(n-2)
+//   CRPC       products P_k = X_k(z) W_k(z); rows k < n, then (sum_k P_k) * 1 = Y(z)
+// with X_k(z) = sum_i z^(i b) x_ik, W_k(z) = sum_j z^j w_kj,
+// Y(z) = sum_ij z^(i b + j) y_ij (Section III-A's identity at Z = z).
+#include "prover.hpp"
+
+#include <chrono>
+#include <cstring>
+
+#include "api_common.hpp"
+#include "curve.hpp"
+#include "field.hpp"
+#include "msm.hpp"
+#include "ntt.hpp"
+
+namespace zkvc {
+
+static int bitlen(uint64_t v) {
+  int b = 0;
+  while (v) {
+    b++;
+    v >>= 1;
+  }
+  return b;
+}
+
+bool kind_uses_z(uint32_t kind) { return kind == ZKVC_CRPC_PSQ || kind == ZKVC_CRPC; }
+
+Layout r1cs_layout(uint32_t a, uint32_t n, uint32_t b, uint32_t kind) {
+  Layout L;
+  ZK_REQUIRE(a >= 1 && n >= 1 && b >= 1, "shape dimensions must be positive");
+  ZK_REQUIRE(kind <= ZKVC_CRPC, "unknown circuit kind");
+  ZK_REQUIRE((uint64_t)a * n * b <= (1ull << 28) && (uint64_t)n * 16384ull < (1ull << 40), "shape too large");
+  L.a = a;
+  L.n = n;
+  L.b = b;
+  L.kind = kind;
+  L.ell = (uint64_t)a * n + (uint64_t)a * b;
+  const uint64_t ab = (uint64_t)a * b;
+  switch (kind) {
+    case ZKVC_PLAIN: L.m = ab * n; L.naux = ab * (n - 1); L.aux_bits = 15; break;
+    case ZKVC_PLAIN_ADD: L.m = ab * (n + 1); L.naux = ab * n; L.aux_bits = 15; break;
+    case ZKVC_PLAIN_PSQ: L.m = ab * n; L.naux = ab * (n - 1); L.aux_bits = bitlen((uint64_t)(n > 1 ? n - 1 : 1) * 16384); break;
+    case ZKVC_CRPC_PSQ: L.m = n; L.naux = n - 1; L.aux_bits = 253; break;
+    default: L.m = n + 1; L.naux = n; L.aux_bits = 253; break;
+  }
+  L.y_bits = bitlen((uint64_t)n * 16384);
+  L.w_start = L.ell + 1;
+  L.aux_start = L.w_start + (uint64_t)n * b;
+  L.nv = L.aux_start + L.naux;
+  const uint64_t rows = L.m + L.ell + 1;
+  L.log_n = 0;
+  while ((1ull << L.log_n) < rows) L.log_n++;
+  ZK_REQUIRE(L.log_n <= 28, "circuit needs a domain above 2^28");
+  ZK_REQUIRE(L.nv < (1ull << 31), "too many variables");
+  L.N = 1ull << L.log_n;
+  const bool aux_in_a = kind == ZKVC_PLAIN_ADD || kind == ZKVC_CRPC;
+  auto push = [](std::vector<Seg>& v, uint64_t start, uint64_t count, int bits) {
+    if (!count) return;
+    Seg s;
+    s.var_start = start;
+    s.count = count;
+    s.bits = bits;
+    s.point_offset = v.empty() ? 0 : v.back().point_offset + v.back().count;
+    v.push_back(s);
+  };
+  push(L.segA, 0, L.ell + 1, L.y_bits);
+  if (aux_in_a) push(L.segA, L.aux_start, L.naux, L.aux_bits);
+  push(L.segB, L.w_start, (uint64_t)n * b, 8);
+  if (aux_in_a) push(L.segB, 0, 1, 1);
+  push(L.segL, L.w_start, (uint64_t)n * b, 8);
+  push(L.segL, L.aux_start, L.naux, L.aux_bits);
+  return L;
+}
+
+static uint64_t seg_total(const std::vector<Seg>& v) { return v.empty() ? 0 : v.back().point_offset + v.back().count; }
+
+// ------------------------------------------------------------------ device helpers
+// Canonical words of a small signed integer: v >= 0 -> v, v < 0 -> r - |v|.
+__device__ __forceinline__ void encode_int(int64_t v, uint32_t w[8]) {
+  if (v >= 0) {
+    w[0] = (uint32_t)v;
+    w[1] = (uint32_t)((uint64_t)v >> 32);
+#pragma unroll
+    for (int k = 2; k < 8; k++) w[k] = 0u;
+    return;
+  }
+  const uint64_t mag = (uint64_t)(-v);
+  uint64_t borrow = 0;
+#pragma unroll
+  for (int k = 0; k < 8; k++) {
+    const uint64_t sub = k == 0 ? (mag & 0xffffffffull) : (k == 1 ? (mag >> 32) : 0ull);
+    const uint64_t t = (uint64_t)FrParams::P32[k] - sub - borrow;
+    w[k] = (uint32_t)t;
+    borrow = (t >> 32) & 1u;
+  }
+}
+
+__device__ __forceinline__ void store_words(uint32_t* p, const uint32_t w[8]) {
+  reinterpret_cast<uint4*>(p)[0] = make_uint4(w[0], w[1], w[2], w[3]);
+  reinterpret_cast<uint4*>(p)[1] = make_uint4(w[4], w[5], w[6], w[7]);
+}
+__device__ __forceinline__ void store_int(uint32_t* p, int64_t v) {
+  uint32_t w[8];
+  encode_int(v, w);
+  store_words(p, w);
+}
+__device__ __forceinline__ Fr fr_of_int(int64_t v) {
+  uint32_t w[8];
+  encode_int(v, w);
+  return Fr::to_mont(Fr::unpack(w));
+}
+__device__ __forceinline__ void store_canonical(uint32_t* p, const Fr& x) { Fr::from_mont(x).store(p); }
+
+// ------------------------------------------------------------------ setup kernels
+constexpr int LG_CHUNK = 16;
+
+// L_c(tau) = omega^c (tau^N - 1) / (N (tau - omega^c)), with Montgomery's
+// simultaneous inversion over chunks of LG_CHUNK rows per thread.
+__global__ void __launch_bounds__(128) k_lagrange(uint32_t N, int log_n, const uint32_t* consts, NttTables T,
+                                                  uint32_t* Lc, uint32_t* prefix) {
+  const uint32_t c0 = (blockIdx.x * blockDim.x + threadIdx.x) * LG_CHUNK;
+  if (c0 >= N) return;
+  const uint32_t c1 = c0 + LG_CHUNK < N ? c0 + LG_CHUNK : N;
+  const Fr tau = Fr::load(consts);
+  const Fr K = Fr::load(consts + 8);  // (tau^N - 1) / N
+  const int sh = NTT_MAX_LOG - log_n;
+  Fr acc = Fr::one();
+  for (uint32_t c = c0; c < c1; c++) {
+    const Fr d = Fr::sub(tau, pow_lookup(T.w[0], c << sh));
+    acc.store(prefix + 8ull * c);
+    d.store(Lc + 8ull * c);
+    acc = Fr::mul(acc, d);
+  }
+  Fr inv = Fr::inv(acc);
+  for (uint32_t cc = c1; cc > c0; cc--) {
+    const uint32_t c = cc - 1;
+    const Fr d = Fr::load(Lc + 8ull * c);
+    const Fr dinv = Fr::mul(inv, Fr::load(prefix + 8ull * c));
+    inv = Fr::mul(inv, d);
+    Fr::mul(Fr::mul(pow_lookup(T.w[0], c << sh), K), dinv).store(Lc + 8ull * c);
+  }
+}
+
+__global__ void k_zpow(const uint32_t* z, uint32_t count, uint32_t* out) {
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const Fr base = Fr::load(z);
+  Fr r = Fr::one();
+  for (int bit = 31; bit >= 0; bit--) {
+    r = Fr::sqr(r);
+    if ((e >> bit) & 1u) r = Fr::mul(r, base);
+  }
+  r.store(out + 8ull * e);
+}
+
+struct VarParams {
+  uint32_t kind, a, n, b;
+  uint64_t ell, m, nv, w_start, aux_start;
+  const uint32_t* L;
+  const uint32_t* zpow;
+  uint32_t *u, *v, *w;
+};
+
+// u_i(tau), v_i(tau), w_i(tau) for every variable: sums of L_c over the rows in
+// which the variable appears, weighted by its coefficient there.
+__global__ void __launch_bounds__(128) k_var_polys(VarParams p) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.nv) return;
+  auto Lc = [&](uint64_t c) { return Fr::load(p.L + 8ull * c); };
+  auto zp = [&](uint64_t e) { return Fr::load(p.zpow + 8ull * e); };
+  const uint32_t a = p.a, n = p.n, b = p.b, kind = p.kind;
+  const bool crpc = kind == ZKVC_CRPC_PSQ || kind == ZKVC_CRPC;
+  const uint64_t stride = kind == ZKVC_PLAIN_ADD ? n + 1 : n;  // rows per output in the plain family
+  Fr U = Fr::zero(), V = Fr::zero(), W = Fr::zero();
+  if (i <= p.ell) U = Lc(p.m + i);  // input-consistency row
+  if (i == 0) {
+    if (kind == ZKVC_PLAIN_ADD) {
+      for (uint64_t ij = 0; ij < (uint64_t)a * b; ij++) V = Fr::add(V, Lc(ij * stride + n));
+    } else if (kind == ZKVC_CRPC) {
+      V = Lc(n);
+    }
+  } else if (i <= (uint64_t)a * n) {  // x_ik
+    const uint64_t t = i - 1, ii = t / n, k = t % n;
+    if (crpc) {
+      U = Fr::add(U, Fr::mul(zp(ii * b), Lc(k)));
+    } else {
+      for (uint64_t j = 0; j < b; j++) U = Fr::add(U, Lc((ii * b + j) * stride + k));
+    }
+  } else if (i <= p.ell) {  // y_ij
+    const uint64_t t = i - 1 - (uint64_t)a * n, ii = t / b, j = t % b;
+    switch (kind) {
+      case ZKVC_PLAIN: case ZKVC_PLAIN_PSQ: W = Lc((ii * b + j) * n + n - 1); break;
+      case ZKVC_PLAIN_ADD: W = Lc((ii * b + j) * stride + n); break;
+      case ZKVC_CRPC_PSQ: W = Fr::mul(zp(ii * b + j), Lc(n - 1)); break;
+      default: W = Fr::mul(zp(ii * b + j), Lc(n)); break;
+    }
+  } else if (i < p.aux_start) {  // w_kj
+    const uint64_t t = i - p.w_start, k = t / b, j = t % b;
+    if (crpc) {
+      V = Fr::mul(zp(j), Lc(k));
+    } else {
+      for (uint64_t ii = 0; ii < a; ii++) V = Fr::add(V, Lc((ii * b + j) * stride + k));
+    }
+  } else {  // auxiliary
+    const uint64_t t = i - p.aux_start;
+    switch (kind) {
+      case ZKVC_PLAIN: {
+        const uint64_t ij = t / (n - 1), k = t % (n - 1), base = ij * n;
+        W = Fr::sub(Lc(base + k), Lc(base + n - 1));
+        break;
+      }
+      case ZKVC_PLAIN_ADD: {
+        const uint64_t ij = t / n, k = t % n, base = ij * stride;
+        U = Lc(base + n);
+        W = Lc(base + k);
+        break;
+      }
+      case ZKVC_PLAIN_PSQ: {
+        const uint64_t ij = t / (n - 1), k = t % (n - 1), base = ij * n;
+        W = Fr::sub(Lc(base + k), Lc(base + k + 1));
+        break;
+      }
+      case ZKVC_CRPC_PSQ: W = Fr::sub(Lc(t), Lc(t + 1)); break;
+      default: U = Lc(n); W = Lc(t); break;
+    }
+  }
+  U.store(p.u + 8ull * i);
+  V.store(p.v + 8ull * i);
+  W.store(p.w + 8ull * i);
+}
+
+// out_j = (beta u_i + alpha v_i + w_i) * f for i = start + j  (f = 1/delta or 1/gamma)
+__global__ void k_lin(const uint32_t* u, const uint32_t* v, const uint32_t* w, uint64_t start, uint32_t count,
+                      const uint32_t* consts, uint32_t* out) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= count) return;
+  const Fr alpha = Fr::load(consts), beta = Fr::load(consts + 8), f = Fr::load(consts + 16);
+  const uint64_t i = start + j;
+  Fr s = Fr::add(Fr::add(Fr::mul(beta, Fr::load(u + 8ull * i)), Fr::mul(alpha, Fr::load(v + 8ull * i))),
+                 Fr::load(w + 8ull * i));
+  Fr::mul(s, f).store(out + 8ull * j);
+}
+
+constexpr int H_CHUNK = 32;
+
+// H_j scalars tau^j (tau^N - 1) / delta for j < count
+__global__ void k_h_scalars(uint32_t count, const uint32_t* consts, uint32_t* out) {
+  const uint32_t j0 = (blockIdx.x * blockDim.x + threadIdx.x) * H_CHUNK;
+  if (j0 >= count) return;
+  const Fr tau = Fr::load(consts), c = Fr::load(consts + 8);
+  Fr x = Fr::one();
+  for (int bit = 31; bit >= 0; bit--) {
+    x = Fr::sqr(x);
+    if ((j0 >> bit) & 1u) x = Fr::mul(x, tau);
+  }
+  x = Fr::mul(x, c);
+  const uint32_t j1 = j0 + H_CHUNK < count ? j0 + H_CHUNK : count;
+  for (uint32_t j = j0; j < j1; j++) {
+    x.store(out + 8ull * j);
+    x = Fr::mul(x, tau);
+  }
+}
+
+// ------------------------------------------------------------------ prove kernels
+__global__ void k_matmul(const int8_t* X, const int8_t* W, uint32_t a, uint32_t n, uint32_t b, int32_t* Y) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a * b) return;
+  const uint32_t i = t / b, j = t % b;
+  int32_t acc = 0;
+  for (uint32_t k = 0; k < n; k++) acc += (int32_t)X[(size_t)i * n + k] * (int32_t)W[(size_t)k * b + j];
+  Y[t] = acc;
+}
+
+// assignment (canonical words) of the constant, x, y and w variables
+__global__ void k_assign_public(const int8_t* X, const int8_t* W, const int32_t* Y, uint32_t a, uint32_t n,
+                                uint32_t b, uint32_t* assign) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t an = (uint64_t)a * n, ab = (uint64_t)a * b, nb = (uint64_t)n * b;
+  if (i >= 1 + an + ab + nb) return;
+  int64_t v;
+  if (i == 0) v = 1;
+  else if (i <= an) v = X[i - 1];
+  else if (i <= an + ab) v = Y[i - 1 - an];
+  else v = W[i - 1 - an - ab];
+  store_int(assign + 8ull * i, v);
+}
+
+struct PlainRowParams {
+  uint32_t kind, a, n, b;
+  uint64_t m, aux_start;
+  const int8_t* X;
+  const int8_t* W;
+  const int32_t* Y;
+  uint32_t *assign, *aev, *bev, *cev;
+};
+
+// Multiplication rows of the plain family, and their auxiliary variables.
+__global__ void k_rows_plain(PlainRowParams p) {
+  const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= p.m) return;
+  const uint32_t n = p.n, b = p.b;
+  const uint64_t stride = p.kind == ZKVC_PLAIN_ADD ? n + 1 : n;
+  const uint64_t ij = c / stride, k = c % stride;
+  const uint64_t i = ij / b, j = ij % b;
+  auto x = [&](uint64_t kk) { return (int64_t)p.X[i * n + kk]; };
+  auto w = [&](uint64_t kk) { return (int64_t)p.W[kk * b + j]; };
+  if (p.kind == ZKVC_PLAIN_ADD && k == n) {  // (sum_k p_ijk) * 1 = y_ij
+    int64_t sum = 0;
+    for (uint64_t kk = 0; kk < n; kk++) sum += x(kk) * w(kk);
+    store_int(p.aev + 8ull * c, sum);
+    store_int(p.bev + 8ull * c, 1);
+    store_int(p.cev + 8ull * c, p.Y[ij]);
+    return;
+  }
+  const int64_t prod = x(k) * w(k);
+  store_int(p.aev + 8ull * c, x(k));
+  store_int(p.bev + 8ull * c, w(k));
+  int64_t cval;
+  switch (p.kind) {
+    case ZKVC_PLAIN:
+      if (k < n - 1) {
+        cval = prod;
+        store_int(p.assign + 8ull * (p.aux_start + ij * (n - 1) + k), prod);
+      } else {  // y_ij - sum_{k' < n-1} p_ijk'
+        int64_t s = 0;
+        for (uint64_t kk = 0; kk + 1 < n; kk++) s += x(kk) * w(kk);
+        cval = (int64_t)p.Y[ij] - s;
+      }
+      break;
+    case ZKVC_PLAIN_ADD:
+      cval = prod;
+      store_int(p.assign + 8ull * (p.aux_start + ij * n + k), prod);
+      break;
+    default: {  // PLAIN_PSQ: s_k - s_(k-1), last row y - s_(n-2)
+      int64_t before = 0;
+      for (uint64_t kk = 0; kk < k; kk++) before += x(kk) * w(kk);
+      if (k < n - 1) {
+        store_int(p.assign + 8ull * (p.aux_start + ij * (n - 1) + k), before + prod);
+        cval = (before + prod) - before;
+      } else {
+        cval = (int64_t)p.Y[ij] - before;
+      }
+      break;
+    }
+  }
+  store_int(p.cev + 8ull * c, cval);
+}
+
+// Input-consistency rows m .. m + l (A = variable t) and the zero rows after them.
+__global__ void k_rows_tail(uint64_t m, uint64_t ell, uint64_t N, const uint32_t* assign, uint32_t* aev,
+                            uint32_t* bev, uint32_t* cev) {
+  const uint64_t c = m + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
+  if (c - m <= ell) {
+    const uint4* s = reinterpret_cast<const uint4*>(assign + 8ull * (c - m));
+    reinterpret_cast<uint4*>(aev + 8ull * c)[0] = s[0];
+    reinterpret_cast<uint4*>(aev + 8ull * c)[1] = s[1];
+  } else {
+    reinterpret_cast<uint4*>(aev + 8ull * c)[0] = z4;
+    reinterpret_cast<uint4*>(aev + 8ull * c)[1] = z4;
+  }
+  reinterpret_cast<uint4*>(bev + 8ull * c)[0] = z4;
+  reinterpret_cast<uint4*>(bev + 8ull * c)[1] = z4;
+  reinterpret_cast<uint4*>(cev + 8ull * c)[0] = z4;
+  reinterpret_cast<uint4*>(cev + 8ull * c)[1] = z4;
+}
+
+constexpr int RED_THREADS = 256;
+
+__device__ Fr block_sum(Fr x, uint32_t* sh) {
+  for (int o = RED_THREADS / 2; o >= 1; o >>= 1) {
+#pragma unroll
+    for (int q = 0; q < NL; q++) sh[threadIdx.x * NL + q] = x.v[q];
+    __syncthreads();
+    if ((int)threadIdx.x < o) {
+      Fr y;
+#pragma unroll
+      for (int q = 0; q < NL; q++) y.v[q] = sh[(threadIdx.x + o) * NL + q];
+      x = Fr::add(x, y);
+    }
+    __syncthreads();
+  }
+  return x;
+}
+
+// Block k: X_k(z) = sum_i z^(i b) x_ik, W_k(z) = sum_j z^j w_kj and their product.
+__global__ void __launch_bounds__(RED_THREADS) k_crpc_xw(const int8_t* X, const int8_t* W, uint32_t a, uint32_t n,
+                                                         uint32_t b, const uint32_t* zpow, uint32_t* xk,
+                                                         uint32_t* wk, uint32_t* pk) {
+  __shared__ uint32_t sh[RED_THREADS * NL];
+  const uint32_t k = blockIdx.x;
+  Fr sx = Fr::zero(), sw = Fr::zero();
+  for (uint32_t i = threadIdx.x; i < a; i += RED_THREADS)
+    sx = Fr::add(sx, Fr::mul(Fr::load(zpow + 8ull * ((uint64_t)i * b)), fr_of_int(X[(size_t)i * n + k])));
+  for (uint32_t j = threadIdx.x; j < b; j += RED_THREADS)
+    sw = Fr::add(sw, Fr::mul(Fr::load(zpow + 8ull * j), fr_of_int(W[(size_t)k * b + j])));
+  sx = block_sum(sx, sh);
+  sw = block_sum(sw, sh);
+  if (threadIdx.x == 0) {
+    sx.store(xk + 8ull * k);
+    sw.store(wk + 8ull * k);
+    Fr::mul(sx, sw).store(pk + 8ull * k);
+  }
+}
+
+// Y(z) = sum_ij z^(i b + j) y_ij with one block.
+__global__ void __launch_bounds__(RED_THREADS) k_crpc_yz(const int32_t* Y, uint32_t ab, const uint32_t* zpow,
+                                                         uint32_t* out) {
+  __shared__ uint32_t sh[RED_THREADS * NL];
+  Fr s = Fr::zero();
+  for (uint32_t e = threadIdx.x; e < ab; e += RED_THREADS)
+    s = Fr::add(s, Fr::mul(Fr::load(zpow + 8ull * e), fr_of_int(Y[e])));
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) s.store(out);
+}
+
+// Rows 0 .. m-1 and auxiliary variables of the CRPC kinds (serial over k <= n).
+__global__ void k_crpc_rows(uint32_t kind, uint32_t n, uint64_t aux_start, const uint32_t* xk, const uint32_t* wk,
+                            const uint32_t* pk, const uint32_t* yz, uint32_t* assign, uint32_t* aev, uint32_t* bev,
+                            uint32_t* cev) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  Fr s = Fr::zero();  // running prefix sum
+  for (uint32_t k = 0; k < n; k++) {
+    const Fr X = Fr::load(xk + 8ull * k), W = Fr::load(wk + 8ull * k), P = Fr::load(pk + 8ull * k);
+    store_canonical(aev + 8ull * k, X);
+    store_canonical(bev + 8ull * k, W);
+    if (kind == ZKVC_CRPC) {
+      store_canonical(cev + 8ull * k, P);
+      store_canonical(assign + 8ull * (aux_start + k), P);
+      s = Fr::add(s, P);
+    } else {
+      const Fr prev = s;
+      s = Fr::add(s, P);
+      if (k + 1 < n) {
+        store_canonical(assign + 8ull * (aux_start + k), s);
+        store_canonical(cev + 8ull * k, Fr::sub(s, prev));
+      } else {
+        store_canonical(cev + 8ull * k, Fr::sub(Fr::load(yz), prev));
+      }
+    }
+  }
+  if (kind == ZKVC_CRPC) {  // (sum_k P_k) * 1 = Y(z)
+    store_canonical(aev + 8ull * n, s);
+    store_canonical(bev + 8ull * n, Fr::one());
+    store_canonical(cev + 8ull * n, Fr::load(yz));
+  }
+}
+
+// q = (A B - C) / (g^N - 1) on the coset, written over A.
+__global__ void k_qap_pointwise(uint32_t* A, const uint32_t* B, const uint32_t* C, uint64_t N, const uint32_t* zinv) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const Fr a = Fr::load(A + 8ull * i), b = Fr::load(B + 8ull * i), c = Fr::load(C + 8ull * i);
+  Fr::mul(Fr::sub(Fr::mul(a, b), c), Fr::load(zinv)).store(A + 8ull * i);
+}
+
+// ------------------------------------------------------------------ host: setup
+namespace {
+
+void put_g1(std::vector<uint8_t>& out, const host::G1J& p) {
+  zkvc_g1 g;
+  g1_to_abi(p, &g);
+  const uint8_t* b = reinterpret_cast<const uint8_t*>(&g);
+  out.insert(out.end(), b, b + sizeof(g));
+}
+void put_g2(std::vector<uint8_t>& out, const host::G2J& p) {
+  zkvc_g2 g;
+  g2_to_abi(p, &g);
+  const uint8_t* b = reinterpret_cast<const uint8_t*>(&g);
+  out.insert(out.end(), b, b + sizeof(g));
+}
+template <class T>
+void put_raw(std::vector<uint8_t>& out, const T& v) {
+  const uint8_t* b = reinterpret_cast<const uint8_t*>(&v);
+  out.insert(out.end(), b, b + sizeof(T));
+}
+
+host::G1J g1_gen() {
+  const uint64_t x[4] = {1, 0, 0, 0}, y[4] = {2, 0, 0, 0};
+  return host::G1J::from_affine(host::HFq::from_u64(x), host::HFq::from_u64(y));
+}
+host::G2J g2_gen() {
+  host::HFq2 x{host::HFq::from_u64(G2Gen::X0), host::HFq::from_u64(G2Gen::X1)};
+  host::HFq2 y{host::HFq::from_u64(G2Gen::Y0), host::HFq::from_u64(G2Gen::Y1)};
+  return host::G2J::from_affine(x, y);
+}
+void scalar_words(const host::HFr& s, uint64_t w[4]) { s.to_u64(w); }
+
+void upload_words(uint32_t* dst, const std::vector<uint32_t>& src, hipStream_t st) {
+  ZK_HIP(hipMemcpyAsync(dst, src.data(), src.size() * 4, hipMemcpyHostToDevice, st));
+  ZK_HIP(hipStreamSynchronize(st));
+}
+
+}  // namespace
+
+zkvc_pk* groth16_setup(const Layout& L, const host::HFr toxic[5], const host::HFr* z, std::vector<uint8_t>& vk,
+                       hipStream_t st) {
+  using host::HFr;
+  const HFr &tau = toxic[0], &alpha = toxic[1], &beta = toxic[2], &gamma = toxic[3], &delta = toxic[4];
+  for (int k = 0; k < 5; k++) ZK_REQUIRE(!toxic[k].is_zero(), "toxic waste elements must be nonzero");
+  const uint64_t Nexp[4] = {L.N, 0, 0, 0};
+  const HFr tN = HFr::pow(tau, Nexp);
+  ZK_REQUIRE(tN != HFr::one(), "tau lies in the evaluation domain");
+  const bool use_z = kind_uses_z(L.kind);
+  if (use_z) ZK_REQUIRE(z != nullptr && !z->is_zero(), "this circuit kind needs a nonzero z");
+
+  std::unique_ptr<zkvc_pk> pk(new zkvc_pk());
+  pk->L = L;
+  pk->device = current_device();
+  pk->has_z = use_z;
+  if (use_z) pk->z = *z;
+  const NttTables& T = ntt_tables(pk->device);
+  Workspace& ws = pk->ws;
+  const uint64_t N = L.N, nv = L.nv;
+
+  // constants (device Montgomery words)
+  std::vector<uint32_t> consts(8 * 8, 0u);
+  auto put = [&](int slot, const HFr& x) { x.to_dev(&consts[8 * slot]); };
+  const HFr Ninv = HFr::inv(HFr::from_uint(L.N));
+  put(0, tau);
+  put(1, HFr::mul(HFr::sub(tN, HFr::one()), Ninv));
+  uint32_t* dconsts = ws.get(1, consts.size() * 4);
+  upload_words(dconsts, consts, st);
+
+  uint32_t* Lc = ws.get(2, N * 32);
+  uint32_t* prefix = ws.get(3, N * 32);
+  {
+    const size_t threads = cdiv(N, LG_CHUNK);
+    hipLaunchKernelGGL(k_lagrange, dim3(cdiv(threads, 128)), dim3(128), 0, st, (uint32_t)N, L.log_n, dconsts, T, Lc,
+                       prefix);
+    ZK_HIP(hipGetLastError());
+  }
+  if (use_z) {
+    const uint32_t cnt = L.a * L.b;
+    pk->zpow.alloc((size_t)cnt * 32);
+    std::vector<uint32_t> zw(8);
+    z->to_dev(zw.data());
+    uint32_t* dz = ws.get(4, 32);
+    upload_words(dz, zw, st);
+    hipLaunchKernelGGL(k_zpow, dim3(cdiv(cnt, 128)), dim3(128), 0, st, dz, cnt, pk->zpow.get());
+    ZK_HIP(hipGetLastError());
+  }
+  uint32_t* u = ws.get(5, nv * 32);
+  uint32_t* v = ws.get(6, nv * 32);
+  uint32_t* w = ws.get(7, nv * 32);
+  {
+    VarParams vp{L.kind, L.a, L.n, L.b, L.ell, L.m, nv, L.w_start, L.aux_start, Lc,
+                 use_z ? pk->zpow.get() : nullptr, u, v, w};
+    hipLaunchKernelGGL(k_var_polys, dim3(cdiv(nv, 128)), dim3(128), 0, st, vp);
+    ZK_HIP(hipGetLastError());
+  }
+
+  // A, B1, B2 queries straight from u and v
+  const uint64_t nA = seg_total(L.segA), nB = seg_total(L.segB), nL = seg_total(L.segL);
+  pk->qA.alloc(std::max<uint64_t>(nA, 1) * 64);
+  pk->qB1.alloc(std::max<uint64_t>(nB, 1) * 64);
+  pk->qB2.alloc(std::max<uint64_t>(nB, 1) * 128);
+  pk->qL.alloc(std::max<uint64_t>(nL, 1) * 64);
+  pk->qH.alloc((N - 1 ? N - 1 : 1) * 64);
+  for (const Seg& s : L.segA)
+    fixed_base_g1(u + 8 * s.var_start, true, s.count, pk->qA.get() + 16 * s.point_offset, false, ws, st);
+  for (const Seg& s : L.segB) {
+    fixed_base_g1(v + 8 * s.var_start, true, s.count, pk->qB1.get() + 16 * s.point_offset, false, ws, st);
+    fixed_base_g2(v + 8 * s.var_start, true, s.count, pk->qB2.get() + 32 * s.point_offset, false, ws, st);
+  }
+  // L query: (beta u + alpha v + w) / delta over the witness variables
+  std::vector<uint32_t> lc(8 * 3);
+  alpha.to_dev(&lc[0]);
+  beta.to_dev(&lc[8]);
+  HFr::inv(delta).to_dev(&lc[16]);
+  uint32_t* dlc = ws.get(8, lc.size() * 4);
+  upload_words(dlc, lc, st);
+  uint64_t maxseg = L.ell + 1;
+  for (const Seg& s : L.segL) maxseg = std::max(maxseg, s.count);
+  maxseg = std::max(maxseg, N);
+  uint32_t* sc = ws.get(9, maxseg * 32);
+  for (const Seg& s : L.segL) {
+    hipLaunchKernelGGL(k_lin, dim3(cdiv(s.count, 128)), dim3(128), 0, st, u, v, w, s.var_start, (uint32_t)s.count,
+                       dlc, sc);
+    ZK_HIP(hipGetLastError());
+    fixed_base_g1(sc, true, s.count, pk->qL.get() + 16 * s.point_offset, false, ws, st);
+  }
+  // H query: tau^j (tau^N - 1) / delta, j < N - 1
+  if (N > 1) {
+    std::vector<uint32_t> hc(16);
+    tau.to_dev(&hc[0]);
+    HFr::mul(HFr::sub(tN, HFr::one()), HFr::inv(delta)).to_dev(&hc[8]);
+    uint32_t* dhc = ws.get(10, hc.size() * 4);
+    upload_words(dhc, hc, st);
+    const uint32_t cnt = (uint32_t)(N - 1);
+    hipLaunchKernelGGL(k_h_scalars, dim3(cdiv(cdiv(cnt, H_CHUNK), 128)), dim3(128), 0, st, cnt, dhc, sc);
+    ZK_HIP(hipGetLastError());
+    fixed_base_g1(sc, true, cnt, pk->qH.get(), false, ws, st);
+  }
+  // IC for the verification key: (beta u + alpha v + w) / gamma over 0..l
+  HFr::inv(gamma).to_dev(&lc[16]);
+  upload_words(dlc, lc, st);
+  const uint64_t nic = L.ell + 1;
+  hipLaunchKernelGGL(k_lin, dim3(cdiv(nic, 128)), dim3(128), 0, st, u, v, w, (uint64_t)0, (uint32_t)nic, dlc, sc);
+  ZK_HIP(hipGetLastError());
+  uint32_t* ic = ws.get(11, nic * 64);
+  fixed_base_g1(sc, true, nic, ic, true, ws, st);
+  std::vector<uint8_t> ic_host(nic * 64);
+  ZK_HIP(hipMemcpyAsync(ic_host.data(), ic, ic_host.size(), hipMemcpyDeviceToHost, st));
+  ZK_HIP(hipStreamSynchronize(st));
+
+  // group constants on the host
+  uint64_t e[4];
+  const host::G1J g1 = g1_gen();
+  const host::G2J g2 = g2_gen();
+  scalar_words(alpha, e);
+  pk->alpha1 = host::G1J::mul(g1, e);
+  scalar_words(beta, e);
+  pk->beta1 = host::G1J::mul(g1, e);
+  pk->beta2 = host::G2J::mul(g2, e);
+  scalar_words(delta, e);
+  pk->delta1 = host::G1J::mul(g1, e);
+  pk->delta2 = host::G2J::mul(g2, e);
+  scalar_words(gamma, e);
+  const host::G2J gamma2 = host::G2J::mul(g2, e);
+
+  // verification key blob
+  vk.clear();
+  const char magic[8] = {'Z', 'K', 'V', 'C', '-', 'V', 'K', '1'};
+  vk.insert(vk.end(), magic, magic + 8);
+  const uint32_t hdr[6] = {1u, L.a, L.n, L.b, L.kind, (uint32_t)L.log_n};
+  for (uint32_t h : hdr) put_raw(vk, h);
+  uint32_t zw[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (use_z) z->to_u32(zw);
+  for (uint32_t x : zw) put_raw(vk, x);
+  put_g1(vk, pk->alpha1);
+  put_g2(vk, pk->beta2);
+  put_g2(vk, gamma2);
+  put_g2(vk, pk->delta2);
+  put_raw(vk, (uint64_t)nic);
+  vk.insert(vk.end(), ic_host.begin(), ic_host.end());
+
+  pk->key_bytes = pk->qA.size() + pk->qB1.size() + pk->qB2.size() + pk->qL.size() + pk->qH.size() + pk->zpow.size();
+  pk->ws.clear();  // setup scratch is not needed for proving
+  return pk.release();
+}
+
+// ------------------------------------------------------------------ host: prove
+namespace {
+enum ProveSlot { P_X = 20, P_W, P_Y, P_ASSIGN, P_AEV, P_BEV, P_CEV, P_XK, P_WK, P_PK, P_YZ };
+
+struct Events {
+  hipEvent_t e[6];
+  Events() {
+    for (auto& x : e) ZK_HIP(hipEventCreate(&x));
+  }
+  ~Events() {
+    for (auto& x : e) (void)hipEventDestroy(x);
+  }
+  float ms(int a, int b) const {
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, e[a], e[b]);
+    return t;
+  }
+};
+
+host::G1J run_g1(const std::vector<Seg>& segs, const uint32_t* points, const uint32_t* assign, Workspace& ws,
+                 hipStream_t st) {
+  host::G1J acc = host::G1J::inf();
+  for (const Seg& s : segs) {
+    MsmInput in;
+    in.points = points + 16 * s.point_offset;
+    in.npoints = s.count;
+    in.scalars = assign + 8 * s.var_start;
+    in.nscalars = s.count;
+    in.max_bits = s.bits;
+    acc = host::G1J::add(acc, msm_g1(in, ws, st));
+  }
+  return acc;
+}
+
+host::G2J run_g2(const std::vector<Seg>& segs, const uint32_t* points, const uint32_t* assign, Workspace& ws,
+                 hipStream_t st) {
+  host::G2J acc = host::G2J::inf();
+  for (const Seg& s : segs) {
+    MsmInput in;
+    in.points = points + 32 * s.point_offset;
+    in.npoints = s.count;
+    in.scalars = assign + 8 * s.var_start;
+    in.nscalars = s.count;
+    in.max_bits = s.bits;
+    acc = host::G2J::add(acc, msm_g2(in, ws, st));
+  }
+  return acc;
+}
+
+}  // namespace
+
+void groth16_prove(zkvc_pk* pk, const int8_t* X, const int8_t* W, const host::HFr& r, const host::HFr& s, int32_t* Y,
+                   zkvc_proof* out, hipStream_t st) {
+  const Layout& L = pk->L;
+  Workspace& ws = pk->ws;
+  const uint64_t N = L.N;
+  const uint32_t a = L.a, n = L.n, b = L.b;
+  const NttTables& T = ntt_tables(pk->device);
+  Events ev;
+  const auto host_t0 = std::chrono::steady_clock::now();
+  ZK_HIP(hipEventRecord(ev.e[0], st));
+
+  int8_t* dX = ws.get<int8_t>(P_X, (size_t)a * n);
+  int8_t* dW = ws.get<int8_t>(P_W, (size_t)n * b);
+  int32_t* dY = ws.get<int32_t>(P_Y, (size_t)a * b * 4);
+  uint32_t* assign = ws.get(P_ASSIGN, L.nv * 32);
+  uint32_t* aev = ws.get(P_AEV, N * 32);
+  uint32_t* bev = ws.get(P_BEV, N * 32);
+  uint32_t* cev = ws.get(P_CEV, N * 32);
+  ZK_HIP(hipMemcpyAsync(dX, X, (size_t)a * n, hipMemcpyHostToDevice, st));
+  ZK_HIP(hipMemcpyAsync(dW, W, (size_t)n * b, hipMemcpyHostToDevice, st));
+
+  // ---- witness and evaluation vectors
+  hipLaunchKernelGGL(k_matmul, dim3(cdiv((size_t)a * b, 128)), dim3(128), 0, st, dX, dW, a, n, b, dY);
+  ZK_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_assign_public, dim3(cdiv(L.aux_start, 256)), dim3(256), 0, st, dX, dW, dY, a, n, b, assign);
+  ZK_HIP(hipGetLastError());
+  if (kind_uses_z(L.kind)) {
+    uint32_t* xk = ws.get(P_XK, (size_t)n * 32);
+    uint32_t* wk = ws.get(P_WK, (size_t)n * 32);
+    uint32_t* pkk = ws.get(P_PK, (size_t)n * 32);
+    uint32_t* yz = ws.get(P_YZ, 32);
+    hipLaunchKernelGGL(k_crpc_xw, dim3(n), dim3(RED_THREADS), 0, st, dX, dW, a, n, b, pk->zpow.get(), xk, wk, pkk);
+    ZK_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_crpc_yz, dim3(1), dim3(RED_THREADS), 0, st, dY, a * b, pk->zpow.get(), yz);
+    ZK_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_crpc_rows, dim3(1), dim3(1), 0, st, L.kind, n, L.aux_start, xk, wk, pkk, yz, assign, aev,
+                       bev, cev);
+    ZK_HIP(hipGetLastError());
+  } else {
+    PlainRowParams rp{L.kind, a, n, b, L.m, L.aux_start, dX, dW, dY, assign, aev, bev, cev};
+    hipLaunchKernelGGL(k_rows_plain, dim3(cdiv(L.m, 256)), dim3(256), 0, st, rp);
+    ZK_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_rows_tail, dim3(cdiv(N - L.m, 256)), dim3(256), 0, st, L.m, L.ell, N, assign, aev, bev, cev);
+  ZK_HIP(hipGetLastError());
+  ZK_HIP(hipMemcpyAsync(Y, dY, (size_t)a * b * 4, hipMemcpyDeviceToHost, st));
+  ZK_HIP(hipEventRecord(ev.e[1], st));
+
+  // ---- QAP quotient h: iNTT (DIF, natural -> bit-reversed coefficients),
+  // coset NTT (DIT, bit-reversed -> natural evaluations on g H), pointwise
+  // (A B - C)/(g^N - 1), inverse coset NTT (DIF: h in bit-reversed order).
+  const int Lg = L.log_n;
+  for (uint32_t* vec : {aev, bev, cev}) {
+    NttFuse f1;
+    f1.in_canonical = true;
+    ntt_launch(vec, Lg, false, true, f1, st);
+    NttFuse f2;
+    f2.pre_coset = 1;
+    f2.pre_bitrev = true;
+    f2.pre_const = T.ninv + 8 * Lg;
+    ntt_launch(vec, Lg, true, false, f2, st);
+  }
+  hipLaunchKernelGGL(k_qap_pointwise, dim3(cdiv(N, 256)), dim3(256), 0, st, aev, bev, cev, N,
+                     T.coset_zinv + 8 * Lg);
+  ZK_HIP(hipGetLastError());
+  {
+    NttFuse f;
+    f.post_const = T.ninv + 8 * Lg;
+    f.post_coset = -1;
+    f.post_bitrev = true;
+    ntt_launch(aev, Lg, false, true, f, st);
+  }
+  // h_{N-1} sits at the last position (bitrev of N-1 is N-1); it must be zero
+  uint32_t top[8];
+  ZK_HIP(hipMemcpyAsync(top, aev + 8 * (N - 1), 32, hipMemcpyDeviceToHost, st));
+  ZK_HIP(hipEventRecord(ev.e[2], st));
+  ZK_HIP(hipStreamSynchronize(st));
+  for (uint32_t t : top)
+    if (t) throw Error(ZKVC_EDEVICE, "internal error: the witness does not satisfy the circuit");
+
+  // ---- MSMs over G1, then G2
+  const host::G1J msmA = run_g1(L.segA, pk->qA.get(), assign, ws, st);
+  const host::G1J msmB1 = run_g1(L.segB, pk->qB1.get(), assign, ws, st);
+  const host::G1J msmL = run_g1(L.segL, pk->qL.get(), assign, ws, st);
+  host::G1J msmH = host::G1J::inf();
+  if (N > 1) {
+    MsmInput in;
+    in.points = pk->qH.get();
+    in.npoints = N - 1;
+    in.scalars = aev;
+    in.nscalars = N;
+    in.scalars_mont = true;
+    in.point_index_bitrev = Lg;
+    in.max_bits = 253;
+    msmH = msm_g1(in, ws, st);
+  }
+  ZK_HIP(hipEventRecord(ev.e[3], st));
+  const host::G2J msmB2 = run_g2(L.segB, pk->qB2.get(), assign, ws, st);
+  ZK_HIP(hipEventRecord(ev.e[4], st));
+  ZK_HIP(hipStreamSynchronize(st));
+
+  // ---- assembly on the host
+  const auto asm_t0 = std::chrono::steady_clock::now();
+  uint64_t rw[4], sw[4], rsw[4];
+  r.to_u64(rw);
+  s.to_u64(sw);
+  host::HFr::mul(r, s).to_u64(rsw);
+  const host::G1J A = host::G1J::add(host::G1J::add(pk->alpha1, msmA), host::G1J::mul(pk->delta1, rw));
+  const host::G2J B = host::G2J::add(host::G2J::add(pk->beta2, msmB2), host::G2J::mul(pk->delta2, sw));
+  const host::G1J B1 = host::G1J::add(host::G1J::add(pk->beta1, msmB1), host::G1J::mul(pk->delta1, sw));
+  host::G1J C = host::G1J::add(msmL, msmH);
+  C = host::G1J::add(C, host::G1J::mul(A, sw));
+  C = host::G1J::add(C, host::G1J::mul(B1, rw));
+  C = host::G1J::add(C, host::G1J::neg(host::G1J::mul(pk->delta1, rsw)));
+  g1_to_abi(A, &out->A);
+  g2_to_abi(B, &out->B);
+  g1_to_abi(C, &out->C);
+  const auto host_t1 = std::chrono::steady_clock::now();
+
+  pk->last.witness_ms = ev.ms(0, 1);
+  pk->last.ntt_ms = ev.ms(1, 2);
+  pk->last.msm_g1_ms = ev.ms(2, 3);
+  pk->last.msm_g2_ms = ev.ms(3, 4);
+  pk->last.host_ms = std::chrono::duration<float, std::milli>(host_t1 - asm_t0).count();
+  pk->last.total_ms = std::chrono::duration<float, std::milli>(host_t1 - host_t0).count();
+}
+
+}  // namespace zkvc

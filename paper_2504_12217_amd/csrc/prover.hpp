@@ -1,0 +1,75 @@
+// Groth16 for the matrix-multiplication circuits: proving key layout and the
+// setup / prove drivers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <mutex>
+#include <vector>
+
+#include "host_field.hpp"
+#include "util.hpp"
+#include "zkvc.h"
+
+namespace zkvc {
+
+// A contiguous range of variables that one proving-key query covers, with a
+// bound on the bit length of their values (after folding to a signed view),
+// which sets the MSM window.
+struct Seg {
+  uint64_t var_start = 0;
+  uint64_t count = 0;
+  int bits = 253;
+  uint64_t point_offset = 0;  // first point of this range inside the query array
+};
+
+// Sizes and variable layout of one circuit (see r1cs_layout()).
+struct Layout {
+  uint32_t a = 0, n = 0, b = 0, kind = 0;
+  uint64_t ell = 0;       // public inputs: a*n + a*b
+  uint64_t m = 0;         // multiplication constraints
+  uint64_t naux = 0;      // auxiliary witness variables
+  uint64_t nv = 0;        // 1 + ell + n*b + naux
+  int log_n = 0;          // domain 2^log_n >= m + ell + 1
+  uint64_t N = 0;
+  uint64_t w_start = 0;   // first W variable (= first witness variable) = ell + 1
+  uint64_t aux_start = 0; // first auxiliary variable
+  int y_bits = 0, aux_bits = 253;
+  std::vector<Seg> segA, segB, segL;  // query coverage
+};
+
+Layout r1cs_layout(uint32_t a, uint32_t n, uint32_t b, uint32_t kind);
+bool kind_uses_z(uint32_t kind);
+
+}  // namespace zkvc
+
+// The opaque proving key of the C ABI.
+struct zkvc_pk {
+  zkvc::Layout L;
+  int device = 0;
+  bool has_z = false;
+  zkvc::host::HFr z;
+  // Queries in the internal layout (affine, Montgomery); segments concatenated.
+  zkvc::DevBuf qA, qB1, qB2, qL, qH;
+  zkvc::DevBuf zpow;  // z^e for e < a*b (CRPC kinds), internal Fr layout
+  zkvc::host::G1J alpha1, beta1, delta1;
+  zkvc::host::G2J beta2, delta2;
+  zkvc::Workspace ws;
+  std::mutex mu;
+  zkvc_prove_stats last{};
+  size_t key_bytes = 0;
+};
+
+namespace zkvc {
+
+// Builds the proving key and the verification-key blob.
+zkvc_pk* groth16_setup(const Layout& L, const host::HFr toxic[5], const host::HFr* z, std::vector<uint8_t>& vk,
+                       hipStream_t st);
+
+// Proves Y = X W.  X, W, Y are host arrays.
+void groth16_prove(zkvc_pk* pk, const int8_t* X, const int8_t* W, const host::HFr& r, const host::HFr& s,
+                   int32_t* Y, zkvc_proof* out, hipStream_t st);
+
+// Host verifier (pairing product) over a parsed key.
+int groth16_verify(const uint8_t* vk, size_t vk_len, const int8_t* X, const int32_t* Y, const zkvc_proof* proof);
+
+}  // namespace zkvc

@@ -1,0 +1,187 @@
+"""GPU Groth16 (zkvc_setup / zkvc_prove / zkvc_verify) against the CPU oracle.
+
+Bar: bit-exact.  For fixed toxic waste, z and (r, s) the proving key, the
+verification key and the proof are unique, so the GPU values must equal the
+oracle's honest setup/prove exactly (small shapes) or the oracle's closed-form
+trapdoor proof (shapes too large for double-and-add).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import bn254 as bn
+from oracle import encoding, groth16, qap, r1cs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+KINDS = (r1cs.PLAIN, r1cs.CRPC_PSQ, r1cs.PLAIN_ADD, r1cs.PLAIN_PSQ, r1cs.CRPC)
+
+
+@pytest.fixture(scope="module")
+def zk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_12217_amd import zkvc
+    zkvc.lib()
+    return zkvc
+
+
+def _job(seed, a, n, b, kind):
+    X, W = synth.matmul_inputs(seed, a, n, b)
+    tox = groth16.Toxic(*synth.toxic_waste(seed))
+    z = synth.crpc_point(seed) if kind in r1cs.CRPC_KINDS else None
+    r, s = synth.prover_randomness(seed)
+    return X, W, tox, z, r, s
+
+
+def _oracle_query_layout(s, kind):
+    """Variables covered by each pk query (the library's documented order)."""
+    ell = r1cs.num_public(s)
+    w0 = r1cs.first_witness(s)
+    aux0 = r1cs.var_aux(s, 0)
+    naux = r1cs.num_aux(s, kind)
+    aux_in_a = kind in (r1cs.PLAIN_ADD, r1cs.CRPC)
+    A = list(range(ell + 1)) + (list(range(aux0, aux0 + naux)) if aux_in_a else [])
+    B = list(range(w0, w0 + s.n * s.b)) + ([0] if aux_in_a else [])
+    L = list(range(w0, aux0 + naux))
+    return A, B, L
+
+
+def _check_honest(zk, seed, a, n, b, kind):
+    s = r1cs.Shape(a, n, b)
+    X, W, tox, z, r, sr = _job(seed, a, n, b, kind)
+    pk = zk.setup(a, n, b, kind, tuple(tox), z)
+    Y, proof = zk.prove(pk, X, W, r, sr)
+    Xl, Wl = X.astype(int).tolist(), W.astype(int).tolist()
+    assert Y.tolist() == r1cs.matmul(Xl, Wl)
+    opk, ovk = groth16.setup(s, kind, tox, z)
+    # verification key blob identical
+    assert pk.vk == encoding.vk_blob(ovk)
+    # every proving-key entry identical
+    info = pk.info()
+    A, B, L = _oracle_query_layout(s, kind)
+    assert (info.a_query, info.b_query, info.l_query, info.h_query) == (len(A), len(B), len(L), len(opk["H"]))
+    assert pk.export(zk.Q_A, 0, len(A)) == [opk["A"][i] for i in A]
+    assert pk.export(zk.Q_B1, 0, len(B)) == [opk["B1"][i] for i in B]
+    assert pk.export(zk.Q_B2, 0, len(B)) == [opk["B2"][i] for i in B]
+    w0 = r1cs.first_witness(s)
+    assert pk.export(zk.Q_L, 0, len(L)) == [opk["L"][i - w0] for i in L]
+    assert pk.export(zk.Q_H, 0, len(opk["H"])) == opk["H"]
+    assert pk.export(zk.Q_CONST, 0, 0) == [opk["alpha1"], opk["beta1"], opk["delta1"], opk["beta2"],
+                                           opk["delta2"]]
+    # the proof equals the oracle's honest proof
+    oproof, _ = groth16.prove(opk, Xl, Wl, r, sr)
+    assert zk.proof_to_tuple(proof) == tuple(oproof)
+    # cross verification in both directions
+    assert groth16.verify(ovk, Xl, Y.tolist(), zk.proof_to_tuple(proof))
+    assert zk.verify(pk.vk, X, Y, zk.proof_from_bytes(encoding.proof_bytes(oproof))) == 1
+    pk.close()
+
+
+def test_config1_plain_honest(zk):
+    """4x8 by 8x4 int8, one constraint per product (128 constraints, N = 2^8)."""
+    _check_honest(zk, 0, 4, 8, 4, r1cs.PLAIN)
+
+
+def test_config1_crpc_psq_honest(zk):
+    _check_honest(zk, 0, 4, 8, 4, r1cs.CRPC_PSQ)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_every_kind_small_honest(zk, kind):
+    _check_honest(zk, 11 + kind, 2, 3, 2, kind)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 1, 2), (1, 5, 1), (2, 2, 3)])
+@pytest.mark.parametrize("kind", [r1cs.PLAIN, r1cs.CRPC_PSQ])
+def test_degenerate_shapes_honest(zk, shape, kind):
+    _check_honest(zk, sum(shape), *shape, kind)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_multi_pass_domain_trapdoor(zk, kind):
+    """A shape whose domain needs several NTT passes (N >= 2^11), checked in closed form."""
+    a, n, b = (5, 24, 9) if kind not in r1cs.CRPC_KINDS else (23, 40, 31)
+    s = r1cs.Shape(a, n, b)
+    X, W, tox, z, r, sr = _job(77 + kind, a, n, b, kind)
+    pk = zk.setup(a, n, b, kind, tuple(tox), z)
+    assert pk.info().log_n >= 11
+    Y, proof = zk.prove(pk, X, W, r, sr)
+    Xl, Wl = X.astype(int).tolist(), W.astype(int).tolist()
+    want, Yo = groth16.expected_proof_trapdoor(s, kind, tox, Xl, Wl, r, sr, z)
+    assert Y.tolist() == Yo
+    assert zk.proof_to_tuple(proof) == tuple(want)
+    assert zk.verify(pk.vk, X, Y, proof) == 1
+    pk.close()
+
+
+def test_verify_rejects_tampering(zk):
+    a, n, b = 3, 4, 2
+    X, W, tox, z, r, sr = _job(5, a, n, b, r1cs.CRPC_PSQ)
+    pk = zk.setup(a, n, b, r1cs.CRPC_PSQ, tuple(tox), z)
+    Y, proof = zk.prove(pk, X, W, r, sr)
+    assert zk.verify(pk.vk, X, Y, proof) == 1
+    Yb = Y.copy()
+    Yb[1, 1] += 1
+    assert zk.verify(pk.vk, X, Yb, proof) == 0
+    Xb = X.copy()
+    Xb[0, 0] ^= 1
+    assert zk.verify(pk.vk, Xb, Y, proof) == 0
+    raw = bytearray(zk.proof_bytes(proof))
+    t = encoding.proof_from(bytes(raw))
+    bad_a = encoding.proof_bytes((bn.g1_add(t[0], bn.G1_GEN), t[1], t[2]))
+    assert zk.verify(pk.vk, X, Y, zk.proof_from_bytes(bad_a)) == 0
+    bad_c = encoding.proof_bytes((t[0], t[1], bn.g1_neg(t[2])))
+    assert zk.verify(pk.vk, X, Y, zk.proof_from_bytes(bad_c)) == 0
+    bad_b = encoding.proof_bytes((t[0], bn.g2_add(t[1], bn.G2_GEN), t[2]))
+    assert zk.verify(pk.vk, X, Y, zk.proof_from_bytes(bad_b)) == 0
+    off_curve = encoding.proof_bytes(((1, 3), t[1], t[2]))
+    assert zk.verify(pk.vk, X, Y, zk.proof_from_bytes(off_curve)) == 0
+    assert zk.verify(pk.vk, X, Y, zk.proof_from_bytes(bytes(256))) == 0
+    with pytest.raises(zk.ZkvcError) as e:
+        zk.verify(pk.vk[:-1], X, Y, proof)
+    assert e.value.code == zk.EFORMAT
+    with pytest.raises(zk.ZkvcError):
+        zk.verify(b"NOTAKEY!" + pk.vk[8:], X, Y, proof)
+    pk.close()
+
+
+def test_setup_and_prove_argument_errors(zk):
+    with pytest.raises(zk.ZkvcError) as e:
+        zk.setup(0, 2, 2, r1cs.PLAIN, synth.toxic_waste(1))
+    assert e.value.code == zk.EINVAL
+    with pytest.raises(zk.ZkvcError):
+        zk.setup(2, 2, 2, r1cs.CRPC_PSQ, synth.toxic_waste(1), None)  # CRPC needs z
+    with pytest.raises(zk.ZkvcError):
+        zk.setup(2, 2, 2, 9, synth.toxic_waste(1))
+    tox = list(synth.toxic_waste(1))
+    tox[2] = 0
+    with pytest.raises(zk.ZkvcError):
+        zk.setup(2, 2, 2, r1cs.PLAIN, tox)
+    tox = list(synth.toxic_waste(1))
+    tox[0] = 1  # tau = 1 lies in the domain
+    with pytest.raises(zk.ZkvcError):
+        zk.setup(2, 2, 2, r1cs.PLAIN, tox)
+    pk = zk.setup(2, 2, 2, r1cs.PLAIN, synth.toxic_waste(1))
+    X, W = synth.matmul_inputs(1, 2, 2, 2)
+    with pytest.raises(zk.ZkvcError):
+        zk.prove(pk, X, W, bn.R, 5)  # r not below the group order
+    pk.close()
+
+
+def test_prove_is_deterministic_and_reusable(zk):
+    a, n, b = 4, 8, 4
+    X, W, tox, z, r, sr = _job(9, a, n, b, r1cs.CRPC_PSQ)
+    pk = zk.setup(a, n, b, r1cs.CRPC_PSQ, tuple(tox), z)
+    Y1, p1 = zk.prove(pk, X, W, r, sr)
+    X2, W2 = synth.matmul_inputs(10, a, n, b)
+    Y2, p2 = zk.prove(pk, X2, W2, r, sr)
+    Y3, p3 = zk.prove(pk, X, W, r, sr)
+    assert bytes(p1) == bytes(p3) and np.array_equal(Y1, Y3)
+    assert bytes(p1) != bytes(p2)
+    assert zk.verify(pk.vk, X2, Y2, p2) == 1
+    st = pk.last_stats()
+    assert st.total_ms > 0
+    pk.close()

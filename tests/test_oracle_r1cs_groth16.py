@@ -265,3 +265,21 @@ def test_trapdoor_localizes_msms():
     assert t["A"] == (tox.alpha + t["msm_A"] + r * tox.delta) % R
     assert t["B"] == (tox.beta + t["msm_B"] + sr * tox.delta) % R
     assert t["C"] == (t["msm_L"] + t["msm_H"] + sr * t["A"] + r * t["B"] - r * sr * tox.delta) % R
+
+
+def test_parallel_and_sampled_sums_match_serial():
+    """The process-split trapdoor and the sampled u/v/w agree with the serial definitions."""
+    s = r1cs.Shape(3, 5, 4)
+    tox = groth16.Toxic(*synth.toxic_waste(21))
+    z = synth.crpc_point(21)
+    X, W = _inputs(21, 3, 5, 4)
+    r, sr = synth.prover_randomness(21)
+    for kind in ALL_KINDS:
+        zz = z if kind in r1cs.CRPC_KINDS else None
+        t1 = groth16.trapdoor_scalars(s, kind, tox, X, W, r, sr, zz, workers=1)
+        t2 = groth16.trapdoor_scalars(s, kind, tox, X, W, r, sr, zz, workers=3)
+        assert t1 == t2
+        u, v, w = qap.var_polys_at(s, kind, tox.tau, zz)
+        sample = [0, 1, 7, r1cs.num_vars(s, kind) - 1]
+        got = qap.var_polys_sampled(s, kind, tox.tau, sample, zz, workers=2)
+        assert got == {i: (u[i], v[i], w[i]) for i in sample}
