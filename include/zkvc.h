@@ -170,8 +170,13 @@ enum { ZKVC_Q_A = 0, ZKVC_Q_B1 = 1, ZKVC_Q_B2 = 2, ZKVC_Q_L = 3, ZKVC_Q_H = 4, Z
  * Copies entries [start, start + count) of a proving-key query to host memory
  * as canonical affine points (zkvc_g1, or zkvc_g2 for ZKVC_Q_B2).  For
  * ZKVC_Q_CONST the entries are alpha1, beta1, delta1 (zkvc_g1) followed by
- * beta2, delta2 (zkvc_g2), and start/count are ignored.  The A and B queries
- * cover the variables listed by zkvc_pk_query_vars.  Used to spot-check keys.
+ * beta2, delta2 (zkvc_g2), and start/count are ignored.  Query order, with
+ * variables numbered 0 = constant, then x (a*n), y (a*b), w (n*b), auxiliary:
+ *   A:      [u_i(tau)]1 for i = 0 .. l, then (PLAIN_ADD, CRPC) the auxiliary variables
+ *   B1, B2: [v_i(tau)]1,2 for the w variables, then (PLAIN_ADD, CRPC) the constant
+ *   L:      [(beta u_i + alpha v_i + w_i)(tau)/delta]1 for the w, then auxiliary variables
+ *   H:      [tau^j (tau^N - 1)/delta]1 for j = 0 .. N-2
+ * Used to spot-check keys.  Errors: ZKVC_EINVAL (unknown query or range).
  */
 int zkvc_pk_export(const zkvc_pk* pk, uint32_t query, uint64_t start, uint64_t count, void* host_out);
 
@@ -191,6 +196,24 @@ int zkvc_pk_last_stats(const zkvc_pk* pk, zkvc_prove_stats* out);
  */
 int zkvc_field_op(uint32_t field, uint32_t op, const void* d_a, const void* d_b, void* d_out, size_t n,
                   void* hip_stream);
+
+/*
+ * Kernel profiling with HIP events on the launching stream.  zkvc_profile_begin
+ * clears earlier records and turns recording on; every instrumented launch
+ * then records a start and stop event and its algorithmic work units (bucket
+ * additions for MSM accumulation, butterflies for NTT passes, elements for
+ * the others).  zkvc_profile_read turns recording off, waits for the events
+ * and writes one aggregate per kernel name (up to `capacity`; *count receives
+ * the number of kernels seen).  Recording adds two event records per launch.
+ */
+typedef struct {
+  char name[48];
+  uint64_t launches;
+  double total_ms;
+  double work;
+} zkvc_kernel_stat;
+int zkvc_profile_begin(void);
+int zkvc_profile_read(zkvc_kernel_stat* out, int capacity, int* count);
 
 #ifdef __cplusplus
 }

@@ -31,6 +31,7 @@
 
 #include "curve.hpp"
 #include "field.hpp"
+#include "profile.hpp"
 #include "scan.hpp"
 
 namespace zkvc {
@@ -290,8 +291,11 @@ typename HostOf<F>::Pt msm_run(const MsmInput& in, Workspace& ws, hipStream_t st
 
   DigitParams dp{in.scalars, n, in.points, (uint32_t)in.npoints, in.scalars_mont ? 1 : 0,
                  in.point_index_bitrev, c, nw, nb, digits, counts};
-  hipLaunchKernelGGL(k_msm_digits<F>, dim3(cdiv(n, 256)), dim3(256), 0, st, dp);
-  ZK_HIP(hipGetLastError());
+  {
+    ProfScope ps(PointIO<F>::AFF_WORDS == 16 ? "msm_digits_g1" : "msm_digits_g2", st, (double)n);
+    hipLaunchKernelGGL(k_msm_digits<F>, dim3(cdiv(n, 256)), dim3(256), 0, st, dp);
+    ZK_HIP(hipGetLastError());
+  }
   scan_exclusive(counts, offsets, nbt, 0, meta + 0, meta + 1, ws, S_SCRATCH, st);
   ZK_HIP(hipMemcpyAsync(cursor, offsets, (size_t)nbt * 4, hipMemcpyDeviceToDevice, st));
   uint32_t hm[2];
@@ -300,9 +304,12 @@ typename HostOf<F>::Pt msm_run(const MsmInput& in, Workspace& ws, hipStream_t st
   const uint32_t total = hm[0];
   if (total == 0) return HP::inf();
   uint32_t* sorted = ws.get(S_SORTED, (size_t)total * 4);
-  hipLaunchKernelGGL(k_msm_scatter, dim3(cdiv(n, 256)), dim3(256), 0, st, digits, n, nw, nb, cursor, sorted,
-                     in.point_index_bitrev);
-  ZK_HIP(hipGetLastError());
+  {
+    ProfScope ps("msm_scatter", st, (double)total);
+    hipLaunchKernelGGL(k_msm_scatter, dim3(cdiv(n, 256)), dim3(256), 0, st, digits, n, nw, nb, cursor, sorted,
+                       in.point_index_bitrev);
+    ZK_HIP(hipGetLastError());
+  }
 
   // Accumulation levels.  Level 0 sums points; later levels sum the partial
   // sums of buckets that were split into several tasks.
@@ -310,6 +317,7 @@ typename HostOf<F>::Pt msm_run(const MsmInput& in, Workspace& ws, hipStream_t st
   const uint32_t* cur_cnt = counts;
   const uint32_t* cur_off = offsets;
   const uint32_t* in_part = nullptr;
+  uint32_t level_entries = total;  // entries summed at the current level
   for (int level = 0;; level++) {
     uint32_t* task_off = offb[level & 1];
     uint32_t* next_cnt = cntb[level & 1];
@@ -324,13 +332,21 @@ typename HostOf<F>::Pt msm_run(const MsmInput& in, Workspace& ws, hipStream_t st
     ZK_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_div_ceil, dim3(cdiv(nbt, 256)), dim3(256), 0, st, cur_cnt, next_cnt, nbt, K);
     ZK_HIP(hipGetLastError());
-    if (level == 0)
-      hipLaunchKernelGGL(k_msm_acc_points<F>, dim3(cdiv(ntasks, 64)), dim3(64), 0, st, tasks, meta + 2, sorted,
-                         in.points, out_part);
-    else
-      hipLaunchKernelGGL(k_msm_acc_partials<F>, dim3(cdiv(ntasks, 64)), dim3(64), 0, st, tasks, meta + 2, in_part,
-                         out_part);
-    ZK_HIP(hipGetLastError());
+    {
+      const bool g1 = PointIO<F>::AFF_WORDS == 16;
+      // work: one addition per entry summed (level 0: points; later: partials)
+      ProfScope ps(level == 0 ? (g1 ? "msm_acc_points_g1" : "msm_acc_points_g2")
+                              : (g1 ? "msm_acc_partials_g1" : "msm_acc_partials_g2"),
+                   st, level == 0 ? (double)total : (double)level_entries);
+      if (level == 0)
+        hipLaunchKernelGGL(k_msm_acc_points<F>, dim3(cdiv(ntasks, 64)), dim3(64), 0, st, tasks, meta + 2, sorted,
+                           in.points, out_part);
+      else
+        hipLaunchKernelGGL(k_msm_acc_partials<F>, dim3(cdiv(ntasks, 64)), dim3(64), 0, st, tasks, meta + 2,
+                           in_part, out_part);
+      ZK_HIP(hipGetLastError());
+    }
+    level_entries = ntasks;
     cur_cnt = next_cnt;
     cur_off = task_off;
     in_part = out_part;
@@ -343,12 +359,19 @@ typename HostOf<F>::Pt msm_run(const MsmInput& in, Workspace& ws, hipStream_t st
   while ((size_t)nbt / L > 32768 && L < nb) L <<= 1;
   const uint32_t G = nb / L;
   uint32_t* seg = ws.get(S_SEG, (size_t)nw * G * XW * 4);
-  hipLaunchKernelGGL(k_msm_segments<F>, dim3(cdiv((size_t)nw * G, 64)), dim3(64), 0, st, cur_cnt, cur_off, in_part,
-                     nw, nb, L, seg);
-  ZK_HIP(hipGetLastError());
+  {
+    ProfScope ps(PointIO<F>::AFF_WORDS == 16 ? "msm_segments_g1" : "msm_segments_g2", st, (double)nbt);
+    hipLaunchKernelGGL(k_msm_segments<F>, dim3(cdiv((size_t)nw * G, 64)), dim3(64), 0, st, cur_cnt, cur_off,
+                       in_part, nw, nb, L, seg);
+    ZK_HIP(hipGetLastError());
+  }
   uint32_t* win = ws.get(S_WIN, (size_t)nw * XW * 4);
-  hipLaunchKernelGGL(k_msm_window_reduce<F>, dim3(nw), dim3(WR_THREADS), 0, st, seg, G, win);
-  ZK_HIP(hipGetLastError());
+  {
+    ProfScope ps(PointIO<F>::AFF_WORDS == 16 ? "msm_window_reduce_g1" : "msm_window_reduce_g2", st,
+                 (double)nw * G);
+    hipLaunchKernelGGL(k_msm_window_reduce<F>, dim3(nw), dim3(WR_THREADS), 0, st, seg, G, win);
+    ZK_HIP(hipGetLastError());
+  }
   std::vector<uint32_t> hw((size_t)nw * XW);
   ZK_HIP(hipMemcpyAsync(hw.data(), win, hw.size() * 4, hipMemcpyDeviceToHost, st));
   ZK_HIP(hipStreamSynchronize(st));

@@ -24,6 +24,7 @@
 
 #include "field.hpp"
 #include "host_field.hpp"
+#include "profile.hpp"
 #include "util.hpp"
 
 namespace zkvc {
@@ -336,6 +337,7 @@ void ntt_launch(uint32_t* data, int log_n, bool dit, bool inverse, const NttFuse
     const size_t lds = (size_t)(1u << (k + p.log_g)) * NL * 4;
     unsigned threads = (1u << (k + p.log_g)) / 2;
     if (threads < 64) threads = 64;
+    ProfScope ps("ntt_pass", st, (double)(1ull << L) * k / 2.0);  // radix-2 butterflies
     hipLaunchKernelGGL(k_ntt_pass, dim3(grid), dim3(threads), lds, st, p, T);
     ZK_HIP(hipGetLastError());
   }

@@ -1,0 +1,25 @@
+// Opt-in per-kernel timing with HIP events on the launching stream.
+//
+// When enabled (zkvc_profile_begin), each instrumented launch records a start
+// and a stop event around itself and the algorithmic work it performs (for
+// example the number of point additions of a bucket-accumulation launch).
+// zkvc_profile_read waits for the events and aggregates by kernel name.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace zkvc {
+
+bool profiling_enabled();
+
+class ProfScope {
+ public:
+  ProfScope(const char* name, hipStream_t st, double work);
+  ~ProfScope();
+  void stop();
+
+ private:
+  int slot_ = -1;
+  hipStream_t st_;
+};
+
+}  // namespace zkvc
