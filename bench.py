@@ -49,21 +49,6 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_stats(zk):
-    import ctypes
-
-    class Stat(ctypes.Structure):
-        _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double),
-                    ("work", ctypes.c_double)]
-
-    lib = zk.lib()
-    lib.zkvc_profile_read.argtypes = [ctypes.POINTER(Stat), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
-    buf = (Stat * 64)()
-    cnt = ctypes.c_int(0)
-    zk._check(lib.zkvc_profile_read(buf, 64, ctypes.byref(cnt)))
-    return {buf[k].name.decode(): (buf[k].launches, buf[k].total_ms, buf[k].work) for k in range(min(cnt.value, 64))}
-
-
 def roofline(stats):
     """Roofline entry for the kernel with the most device time."""
     name, (launches, total_ms, work) = max(stats.items(), key=lambda kv: kv[1][1])
@@ -87,7 +72,7 @@ def time_proofs(zk, pk, X, W, r, s, steps, warmup, profile):
     torch.cuda.synchronize()
     lat = []
     if profile:
-        zk._check(zk.lib().zkvc_profile_begin())
+        zk.profile_begin()
     t0 = time.perf_counter()
     for _ in range(steps):
         t = time.perf_counter()
@@ -95,7 +80,7 @@ def time_proofs(zk, pk, X, W, r, s, steps, warmup, profile):
         lat.append(time.perf_counter() - t)
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
-    stats = kernel_stats(zk) if profile else None
+    stats = zk.profile_read() if profile else None
     return total, lat, stats
 
 
@@ -206,8 +191,9 @@ def main():
     Y, proof = zkvc.prove(pk, X, W, r, s)
     ok = zkvc.verify(pk.vk, X, Y, proof) == 1
     st = pk.last_stats()
-    stage_ms = {"witness": round(st.witness_ms, 3), "ntt": round(st.ntt_ms, 3), "msm_g1": round(st.msm_g1_ms, 3),
-                "msm_g2": round(st.msm_g2_ms, 3), "host_assembly": round(st.host_ms, 3)}
+    stage_ms = {"witness": round(st.witness_ms, 3), "qap_ntt": round(st.ntt_ms, 3),
+                "msm_all_concurrent": round(st.msm_ms, 3), "host_windows_and_assembly": round(st.host_ms, 3),
+                "total_wall": round(st.total_ms, 3)}
     pk.close()
     dom_name, roof = roofline(stats)
     lat_ms = sorted(x * 1e3 for x in lat)

@@ -180,10 +180,13 @@ enum { ZKVC_Q_A = 0, ZKVC_Q_B1 = 1, ZKVC_Q_B2 = 2, ZKVC_Q_L = 3, ZKVC_Q_H = 4, Z
  */
 int zkvc_pk_export(const zkvc_pk* pk, uint32_t query, uint64_t start, uint64_t count, void* host_out);
 
-/* Per-stage device times (milliseconds, from HIP events) of the last
- * zkvc_prove with this key, and its host-side assembly time. */
+/* Per-stage device times (milliseconds, from HIP events on the calling
+ * stream) of the last zkvc_prove with this key: witness and evaluation
+ * vectors, the QAP quotient, all multi-scalar multiplications (they run
+ * concurrently on the key's own streams), then the host-side window
+ * combination and assembly, and the wall time of the whole call. */
 typedef struct {
-  float witness_ms, ntt_ms, msm_g1_ms, msm_g2_ms, host_ms, total_ms;
+  float witness_ms, ntt_ms, msm_ms, host_ms, total_ms;
 } zkvc_prove_stats;
 int zkvc_pk_last_stats(const zkvc_pk* pk, zkvc_prove_stats* out);
 

@@ -10,6 +10,7 @@
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "constants.hpp"
 
@@ -248,6 +249,40 @@ struct Jac {
     return {X3, Y3, Z3};
   }
   static Jac neg(const Jac& p) { return {p.X, F::neg(p.Y), p.Z}; }
+  // P + (x, y) with an affine second operand (Z2 = 1)
+  static Jac add_affine(const Jac& p, const F& x2, const F& y2) {
+    if (p.is_inf()) return from_affine(x2, y2);
+    F Z1Z1 = F::sqr(p.Z);
+    F U2 = F::mul(x2, Z1Z1);
+    F S2 = F::mul(F::mul(y2, p.Z), Z1Z1);
+    if (p.X == U2) {
+      if (p.Y == S2) return dbl(p);
+      return inf();
+    }
+    F H = F::sub(U2, p.X), Rr = F::sub(S2, p.Y);
+    F HH = F::sqr(H), HHH = F::mul(H, HH);
+    F V = F::mul(p.X, HH);
+    F X3 = F::sub(F::sub(F::sqr(Rr), HHH), F::dbl(V));
+    F Y3 = F::sub(F::mul(Rr, F::sub(V, X3)), F::mul(p.Y, HHH));
+    return {X3, Y3, F::mul(p.Z, H)};
+  }
+  // a P + b Q sharing one doubling chain (Straus), 4-bit windows
+  static Jac mul2(const Jac& p, const uint64_t a[4], const Jac& q, const uint64_t b[4]) {
+    Jac tp[16], tq[16];
+    tp[0] = tq[0] = inf();
+    for (int i = 1; i < 16; i++) {
+      tp[i] = add(tp[i - 1], p);
+      tq[i] = add(tq[i - 1], q);
+    }
+    Jac acc = inf();
+    for (int w = 63; w >= 0; w--) {
+      for (int d = 0; d < 4; d++) acc = dbl(acc);
+      const int na = (int)((a[w / 16] >> (4 * (w % 16))) & 15), nb = (int)((b[w / 16] >> (4 * (w % 16))) & 15);
+      if (na) acc = add(acc, tp[na]);
+      if (nb) acc = add(acc, tq[nb]);
+    }
+    return acc;
+  }
   // scalar given as little-endian 64-bit words (4-bit fixed window)
   static Jac mul(const Jac& p, const uint64_t k[4]) {
     Jac table[16];
@@ -279,6 +314,51 @@ using G1J = Jac<HFq>;
 using G2J = Jac<HFq2>;
 
 // XYZZ (x = X/ZZ, y = Y/ZZZ, ZZ^3 = ZZZ^2) -> Jacobian without an inversion.
+// Fixed-base table: entry [w][d] = d 2^(8w) P in affine form, for w < 32, d < 256;
+// k P is then at most 32 mixed additions.
+template <class F>
+struct FixedBaseTable {
+  std::vector<F> x, y;  // 32 * 256 entries; entry d = 0 unused
+  void build(const Jac<F>& P) {
+    const int total = 32 * 256;
+    std::vector<Jac<F>> pts(total);
+    Jac<F> base = P;
+    for (int w = 0; w < 32; w++) {
+      pts[w * 256] = Jac<F>::inf();
+      for (int d = 1; d < 256; d++) pts[w * 256 + d] = Jac<F>::add(pts[w * 256 + d - 1], base);
+      for (int k = 0; k < 8; k++) base = Jac<F>::dbl(base);
+    }
+    // simultaneous inversion of the Z coordinates
+    std::vector<F> pre(total), zs(total);
+    F acc = F::one();
+    for (int i = 0; i < total; i++) {
+      zs[i] = pts[i].is_inf() ? F::one() : pts[i].Z;
+      pre[i] = acc;
+      acc = F::mul(acc, zs[i]);
+    }
+    F inv = F::inv(acc);
+    x.assign(total, F::zero());
+    y.assign(total, F::zero());
+    for (int i = total; i-- > 0;) {
+      const F zi = F::mul(inv, pre[i]);
+      inv = F::mul(inv, zs[i]);
+      if (pts[i].is_inf()) continue;
+      const F zi2 = F::sqr(zi);
+      x[i] = F::mul(pts[i].X, zi2);
+      y[i] = F::mul(pts[i].Y, F::mul(zi2, zi));
+    }
+  }
+  bool empty() const { return x.empty(); }
+  Jac<F> mul(const uint64_t k[4]) const {
+    Jac<F> acc = Jac<F>::inf();
+    for (int w = 0; w < 32; w++) {
+      const int d = (int)((k[w / 8] >> (8 * (w % 8))) & 255);
+      if (d) acc = Jac<F>::add_affine(acc, x[w * 256 + d], y[w * 256 + d]);
+    }
+    return acc;
+  }
+};
+
 template <class F>
 inline Jac<F> xyzz_to_jac(const F& X, const F& Y, const F& ZZ, const F& ZZZ) {
   if (ZZ.is_zero()) return Jac<F>::inf();

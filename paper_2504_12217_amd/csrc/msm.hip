@@ -25,6 +25,7 @@
 #include "msm.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -37,10 +38,11 @@
 namespace zkvc {
 
 constexpr uint32_t EMPTY = 0xffffffffu;
+constexpr uint32_t WG_TASK_ENTRIES = 256;  // entries per large-bucket (wavefront) task
 constexpr uint32_t SIGN = 0x80000000u;
 enum MsmSlot {
   S_DIGITS = 100, S_COUNTS, S_OFFSETS, S_CURSOR, S_SORTED, S_TASKS, S_CNT_A, S_CNT_B, S_OFF_A, S_OFF_B,
-  S_PART0, S_PART1, S_SCRATCH, S_SCRATCH2, S_SEG, S_WIN, S_META, S_FB_XYZZ, S_FB_PREFIX
+  S_PART0, S_PART1, S_SCRATCH, S_SCRATCH2, S_SEG, S_WIN, S_META, S_FB_XYZZ, S_FB_PREFIX, S_UNUSED
 };
 
 __device__ __forceinline__ uint32_t bitrev_n(uint32_t a, int bits) {
@@ -143,85 +145,126 @@ __global__ void k_msm_scatter(const uint32_t* digits, uint32_t nscalars, int nw,
 }
 
 // ---------------------------------------------------------------- 3. tasks and accumulation
-__global__ void k_msm_tasks(const uint32_t* cnt, const uint32_t* off, const uint32_t* task_off, uint32_t nbt,
-                            uint32_t K, uint2* tasks) {
+// Buckets are split into tasks by their actual size: a bucket with fewer than
+// `large` entries becomes thread tasks of at most K entries (one thread sums a
+// task serially); a larger one becomes wavefront tasks of WG_TASK_ENTRIES
+// entries reduced by an LDS tree.  nt[f] is the number of partial sums of
+// bucket f; a bucket's partial sums are contiguous.
+__global__ void k_msm_task_counts(const uint32_t* cnt, uint32_t nbt, uint32_t K, uint32_t large, uint32_t* nt) {
+  const uint32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nbt) return;
+  const uint32_t c = cnt[f];
+  const uint32_t sz = c >= large ? WG_TASK_ENTRIES : K;
+  nt[f] = (c + sz - 1) / sz;
+}
+
+// Task records (first entry, length, output partial slot); the two task lists
+// are filled through atomic counters (their order does not matter).
+__global__ void k_msm_make_tasks(const uint32_t* cnt, const uint32_t* off, const uint32_t* part_off, uint32_t nbt,
+                                 uint32_t K, uint32_t large, uint32_t* counters, uint4* th_tasks, uint4* wg_tasks) {
   const uint32_t f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= nbt) return;
   const uint32_t c = cnt[f];
   if (c == 0) return;
-  const uint32_t o = off[f], t0 = task_off[f];
-  for (uint32_t q = 0; q * K < c; q++) {
-    const uint32_t len = c - q * K < K ? c - q * K : K;
-    tasks[t0 + q] = make_uint2(o + q * K, len);
+  const uint32_t o = off[f], p = part_off[f];
+  const bool big = c >= large;
+  const uint32_t sz = big ? WG_TASK_ENTRIES : K;
+  const uint32_t nt = (c + sz - 1) / sz;
+  const uint32_t base = atomicAdd(&counters[big ? 1 : 0], nt);
+  uint4* dst = big ? wg_tasks : th_tasks;
+  for (uint32_t q = 0; q < nt; q++) {
+    const uint32_t len = c - q * sz < sz ? c - q * sz : sz;
+    dst[base + q] = make_uint4(o + q * sz, len, p + q, 0u);
   }
 }
 
 template <class F>
-__global__ void __launch_bounds__(64) k_msm_acc_points(const uint2* tasks, const uint32_t* d_ntasks, const uint32_t* sorted,
+__global__ void __launch_bounds__(64) k_msm_acc_points(const uint4* tasks, const uint32_t* d_ntasks, const uint32_t* sorted,
                                  const uint32_t* points, uint32_t* partials) {
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= *d_ntasks) return;
-  const uint2 task = tasks[t];
+  const uint32_t ntasks = *d_ntasks;
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntasks; t += gridDim.x * blockDim.x) {
+    const uint4 task = tasks[t];
+    Xyzz<F> acc = Xyzz<F>::inf();
+    for (uint32_t e = task.x; e < task.x + task.y; e++) {
+      const uint32_t ref = sorted[e];
+      Affine<F> pt = PointIO<F>::load_affine(points + (size_t)(ref & ~SIGN) * PointIO<F>::AFF_WORDS);
+      if (ref & SIGN) pt.y = F::neg(pt.y);
+      acc = Xyzz<F>::madd(acc, pt);
+    }
+    PointIO<F>::store_xyzz(partials + (size_t)task.z * PointIO<F>::XYZZ_WORDS, acc);
+  }
+}
+
+constexpr int WG_THREADS = 64;   // one wavefront per large-bucket task (at most 4 entries per thread)
+constexpr int BP_THREADS = 256;  // bit-plane reduction block
+
+// One wavefront per task of up to WG_TASK_ENTRIES entries of one large
+// bucket: each lane sums its entries, then an LDS tree reduces the task.
+template <class F>
+__global__ void __launch_bounds__(WG_THREADS) k_msm_acc_points_wg(const uint4* tasks, const uint32_t* d_ntasks,
+                                                                  const uint32_t* sorted, const uint32_t* points,
+                                                                  uint32_t* partials) {
+  constexpr int XW = PointIO<F>::XYZZ_WORDS;
+  __shared__ uint32_t sh[WG_THREADS / 2 * XW];
+  const uint32_t ntasks = *d_ntasks;  // uniform: every block runs the same loop count
+  for (uint32_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
+    const uint4 task = tasks[t];
+    Xyzz<F> acc = Xyzz<F>::inf();
+    for (uint32_t e = threadIdx.x; e < task.y; e += WG_THREADS) {
+      const uint32_t ref = sorted[task.x + e];
+      Affine<F> pt = PointIO<F>::load_affine(points + (size_t)(ref & ~SIGN) * PointIO<F>::AFF_WORDS);
+      if (ref & SIGN) pt.y = F::neg(pt.y);
+      acc = Xyzz<F>::madd(acc, pt);
+    }
+    for (int o = WG_THREADS / 2; o >= 1; o >>= 1) {
+      if ((int)threadIdx.x >= o && (int)threadIdx.x < 2 * o) PointIO<F>::store_xyzz(sh + (threadIdx.x - o) * XW, acc);
+      __syncthreads();
+      if ((int)threadIdx.x < o) acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(sh + threadIdx.x * XW));
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) PointIO<F>::store_xyzz(partials + (size_t)task.z * XW, acc);
+  }
+}
+
+// Bucket sums: the remaining partials of each bucket, summed in order.
+template <class F>
+__global__ void __launch_bounds__(64) k_msm_finalize(const uint32_t* cnt, const uint32_t* off, const uint32_t* partials,
+                                                     uint32_t nbt, uint32_t* buckets) {
+  constexpr int XW = PointIO<F>::XYZZ_WORDS;
+  const uint32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nbt) return;
+  const uint32_t c = cnt[f], o = off[f];
   Xyzz<F> acc = Xyzz<F>::inf();
-  for (uint32_t e = task.x; e < task.x + task.y; e++) {
-    const uint32_t ref = sorted[e];
-    Affine<F> pt = PointIO<F>::load_affine(points + (size_t)(ref & ~SIGN) * PointIO<F>::AFF_WORDS);
-    if (ref & SIGN) pt.y = F::neg(pt.y);
-    acc = Xyzz<F>::madd(acc, pt);
-  }
-  PointIO<F>::store_xyzz(partials + (size_t)t * PointIO<F>::XYZZ_WORDS, acc);
+  for (uint32_t e = 0; e < c; e++) acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(partials + (size_t)(o + e) * XW));
+  PointIO<F>::store_xyzz(buckets + (size_t)f * XW, acc);
 }
 
+// Bit planes of the bucket reduction: for window w and bit j,
+//   S[w c + j] = sum of B_b over the buckets whose digit value b + 1 has bit j set,
+// so that window w contributes sum_j 2^j S[w c + j] = sum_b (b + 1) B_b.
+// One block per (w, j); each thread sums a strided share, then an LDS tree.
 template <class F>
-__global__ void __launch_bounds__(64) k_msm_acc_partials(const uint2* tasks, const uint32_t* d_ntasks, const uint32_t* in,
-                                   uint32_t* out) {
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= *d_ntasks) return;
-  const uint2 task = tasks[t];
+__global__ void __launch_bounds__(BP_THREADS) k_msm_bitplanes(const uint32_t* buckets, uint32_t nb, int c,
+                                                              uint32_t* S) {
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
-  Xyzz<F> acc = PointIO<F>::load_xyzz(in + (size_t)task.x * XW);
-  for (uint32_t e = task.x + 1; e < task.x + task.y; e++)
-    acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(in + (size_t)e * XW));
-  PointIO<F>::store_xyzz(out + (size_t)t * XW, acc);
-}
-
-// ---------------------------------------------------------------- 4. bucket reduction
-template <class F>
-__global__ void __launch_bounds__(64) k_msm_segments(const uint32_t* cnt, const uint32_t* off, const uint32_t* partials, int nw,
-                               uint32_t nb, uint32_t L, uint32_t* seg_out) {
-  const uint32_t G = nb / L;
-  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= (uint32_t)nw * G) return;
-  const uint32_t w = tid / G, g = tid % G;
-  constexpr int XW = PointIO<F>::XYZZ_WORDS;
-  Xyzz<F> acc = Xyzz<F>::inf(), sum = Xyzz<F>::inf();
-  for (int q = (int)L - 1; q >= 0; q--) {
-    const size_t f = (size_t)w * nb + g * L + (uint32_t)q;
-    if (cnt[f]) acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(partials + (size_t)off[f] * XW));
-    sum = Xyzz<F>::add(sum, acc);
-  }
-  // buckets g*L .. g*L+L-1 hold digit values g*L+1 .. g*L+L: add (g*L) * total
-  if (g) sum = Xyzz<F>::add(sum, Xyzz<F>::mul_small(acc, g * L));
-  PointIO<F>::store_xyzz(seg_out + (size_t)tid * XW, sum);
-}
-
-constexpr int WR_THREADS = 64;
-
-template <class F>
-__global__ void __launch_bounds__(WR_THREADS) k_msm_window_reduce(const uint32_t* seg, uint32_t G, uint32_t* win) {
-  constexpr int XW = PointIO<F>::XYZZ_WORDS;
-  __shared__ uint32_t sh[WR_THREADS * XW];
-  const uint32_t w = blockIdx.x;
+  __shared__ uint32_t sh[BP_THREADS / 2 * XW];
+  const uint32_t w = blockIdx.x / c, j = blockIdx.x % c;
+  // digit values v in [1, nb] with bit j set: v = ((t >> j) << (j + 1)) | 2^j | (t & (2^j - 1))
+  const uint32_t jmask = (1u << j) - 1u;
+  const uint32_t count = (j + 1 < (uint32_t)c) ? nb / 2 : 1u;  // bit c-1 is set only in v = nb
   Xyzz<F> acc = Xyzz<F>::inf();
-  for (uint32_t g = threadIdx.x; g < G; g += WR_THREADS)
-    acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(seg + ((size_t)w * G + g) * XW));
-  for (int o = WR_THREADS / 2; o >= 1; o >>= 1) {
-    PointIO<F>::store_xyzz(sh + threadIdx.x * XW, acc);
+  for (uint32_t t = threadIdx.x; t < count; t += BP_THREADS) {
+    const uint32_t v = ((t >> j) << (j + 1)) | (1u << j) | (t & jmask);
+    if (v > nb) continue;
+    acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(buckets + ((size_t)w * nb + v - 1) * XW));
+  }
+  for (int o = BP_THREADS / 2; o >= 1; o >>= 1) {
+    if ((int)threadIdx.x >= o && (int)threadIdx.x < 2 * o) PointIO<F>::store_xyzz(sh + (threadIdx.x - o) * XW, acc);
     __syncthreads();
-    if ((int)threadIdx.x < o) acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(sh + (threadIdx.x + o) * XW));
+    if ((int)threadIdx.x < o) acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(sh + threadIdx.x * XW));
     __syncthreads();
   }
-  if (threadIdx.x == 0) PointIO<F>::store_xyzz(win + (size_t)w * XW, acc);
+  if (threadIdx.x == 0) PointIO<F>::store_xyzz(S + (size_t)blockIdx.x * XW, acc);
 }
 
 // ---------------------------------------------------------------- host driver
@@ -262,132 +305,165 @@ void hfq2_to_dev(const host::HFq2& a, uint32_t* w) {
   a.c1.to_dev(w + 8);
 }
 
-__global__ void k_div_ceil(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t K) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = (in[i] + K - 1u) / K;
+// Sizes of one MSM, all known on the host before any launch, so the device
+// pipeline needs no host synchronization until the window sums come back.
+struct MsmPlan {
+  uint32_t n = 0;
+  int c = 0, nw = 0;
+  uint32_t nb = 0, nbt = 0;
+  uint64_t max_entries = 0;
+  uint32_t K = 0;      // entries per thread task
+  uint32_t large = 0;  // buckets with at least this many entries get wavefront tasks
+  uint64_t max_th_tasks = 0, max_wg_tasks = 0, max_partials = 0;
+};
+
+static MsmPlan msm_plan(const MsmInput& in) {
+  MsmPlan p;
+  p.n = (uint32_t)in.nscalars;
+  msm_choose_window(p.n, in.max_bits, &p.c, &p.nw);
+  p.nb = 1u << (p.c - 1);
+  p.nbt = (uint32_t)p.nw * p.nb;
+  p.max_entries = (uint64_t)p.n * p.nw;
+  // thread tasks: enough of them to fill the device, long enough to amortize
+  p.K = (uint32_t)std::max<uint64_t>(4, std::min<uint64_t>(p.max_entries / 65536, 64));
+  p.large = std::max<uint32_t>(64, 8 * p.K);
+  p.max_th_tasks = p.max_entries / p.K + p.nbt;
+  // a large bucket of c entries makes ceil(c / WG_TASK_ENTRIES) tasks, and at
+  // most max_entries / large buckets are large
+  p.max_wg_tasks = p.max_entries / WG_TASK_ENTRIES + p.max_entries / p.large + 1;
+  p.max_partials = p.max_th_tasks + p.max_wg_tasks;
+  return p;
+}
+
+template <class F>
+void msm_enqueue(const MsmInput& in, Workspace& ws, hipStream_t st, MsmPending& pend) {
+  constexpr int XW = PointIO<F>::XYZZ_WORDS;
+  ZK_REQUIRE(in.nscalars < (1ull << 31) && in.npoints < (1ull << 31), "MSM too large");
+  pend = MsmPending();
+  pend.xyzz_words = XW;
+  if (in.nscalars == 0) return;
+  const MsmPlan p = msm_plan(in);
+  ZK_REQUIRE(p.max_entries < (1ull << 32), "MSM too large for 32-bit bucket offsets");
+  pend.empty = false;
+  pend.c = p.c;
+  pend.nw = p.nw;
+  const uint32_t n = p.n, nbt = p.nbt;
+  const bool g1 = PointIO<F>::AFF_WORDS == 16;
+
+  // all buffers first (growing a buffer synchronizes the device)
+  uint32_t* digits = ws.get(S_DIGITS, (size_t)p.nw * n * 4);
+  uint32_t* counts = ws.get(S_COUNTS, (size_t)nbt * 4);
+  uint32_t* offsets = ws.get(S_OFFSETS, (size_t)nbt * 4);
+  uint32_t* cursor = ws.get(S_CURSOR, (size_t)nbt * 4);
+  uint32_t* nt = ws.get(S_CNT_A, (size_t)nbt * 4);
+  uint32_t* part_off = ws.get(S_OFF_A, (size_t)nbt * 4);
+  uint32_t* sorted = ws.get(S_SORTED, p.max_entries * 4);
+  uint4* th_tasks = ws.get<uint4>(S_TASKS, p.max_th_tasks * 16);
+  uint4* wg_tasks = ws.get<uint4>(S_PART1, p.max_wg_tasks * 16);
+  uint32_t* part = ws.get(S_PART0, p.max_partials * XW * 4);
+  uint32_t* buckets = ws.get(S_SEG, (size_t)nbt * XW * 4);
+  const size_t nplanes = (size_t)p.nw * p.c;
+  uint32_t* win = ws.get(S_WIN, nplanes * XW * 4);
+  uint32_t* meta = ws.get(S_META, 64 * 4);  // [0] entries [2] partials [8] thread tasks [9] wavefront tasks
+  uint32_t* win_host = ws.host<uint32_t>(S_WIN, nplanes * XW * 4);
+  ws.get(S_SCRATCH, (size_t)cdiv(nbt, 2048) * 4 + 64);
+  pend.win_host = win_host;
+
+  fill_u32(counts, 0u, nbt, st);
+  fill_u32(meta + 8, 0u, 2, st);
+  DigitParams dp{in.scalars, n, in.points, (uint32_t)in.npoints, in.scalars_mont ? 1 : 0,
+                 in.point_index_bitrev, p.c, p.nw, p.nb, digits, counts};
+  {
+    ProfScope ps(g1 ? "msm_digits_g1" : "msm_digits_g2", st, (double)n);
+    hipLaunchKernelGGL(k_msm_digits<F>, dim3(cdiv(n, 256)), dim3(256), 0, st, dp);
+    ZK_HIP(hipGetLastError());
+  }
+  scan_exclusive(counts, offsets, nbt, 0, meta + 0, nullptr, ws, S_SCRATCH, st);
+  ZK_HIP(hipMemcpyAsync(cursor, offsets, (size_t)nbt * 4, hipMemcpyDeviceToDevice, st));
+  {
+    ProfScope ps("msm_scatter", st, (double)n * p.nw);
+    hipLaunchKernelGGL(k_msm_scatter, dim3(cdiv(n, 256)), dim3(256), 0, st, digits, n, p.nw, p.nb, cursor, sorted,
+                       in.point_index_bitrev);
+    ZK_HIP(hipGetLastError());
+  }
+  // tasks by actual bucket size
+  hipLaunchKernelGGL(k_msm_task_counts, dim3(cdiv(nbt, 256)), dim3(256), 0, st, counts, nbt, p.K, p.large, nt);
+  ZK_HIP(hipGetLastError());
+  scan_exclusive(nt, part_off, nbt, 0, meta + 2, nullptr, ws, S_SCRATCH, st);
+  hipLaunchKernelGGL(k_msm_make_tasks, dim3(cdiv(nbt, 256)), dim3(256), 0, st, counts, offsets, part_off, nbt, p.K,
+                     p.large, meta + 8, th_tasks, wg_tasks);
+  ZK_HIP(hipGetLastError());
+  {
+    ProfScope ps(g1 ? "msm_acc_points_g1" : "msm_acc_points_g2", st, -1.0);
+    // capped grids with stride loops: the task counts are only known on the device
+    const unsigned th_grid = (unsigned)std::min<uint64_t>(cdiv(p.max_th_tasks, 64), 65536);
+    const unsigned wg_grid = (unsigned)std::min<uint64_t>(p.max_wg_tasks, 8192);
+    hipLaunchKernelGGL(k_msm_acc_points<F>, dim3(th_grid), dim3(64), 0, st, th_tasks, meta + 8, sorted, in.points,
+                       part);
+    ZK_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_msm_acc_points_wg<F>, dim3(wg_grid), dim3(WG_THREADS), 0, st, wg_tasks, meta + 9, sorted,
+                       in.points, part);
+    ZK_HIP(hipGetLastError());
+    ps.set_work_from_device(meta + 0);
+  }
+  const uint32_t* cur_cnt = nt;
+  const uint32_t* cur_off = part_off;
+  const uint32_t* cur_part = part;
+  {
+    ProfScope ps(g1 ? "msm_finalize_g1" : "msm_finalize_g2", st, (double)nbt);
+    hipLaunchKernelGGL(k_msm_finalize<F>, dim3(cdiv(nbt, 64)), dim3(64), 0, st, cur_cnt, cur_off, cur_part, nbt,
+                       buckets);
+    ZK_HIP(hipGetLastError());
+  }
+  {
+    ProfScope ps(g1 ? "msm_bitplanes_g1" : "msm_bitplanes_g2", st, (double)nplanes * p.nb / 2);
+    hipLaunchKernelGGL(k_msm_bitplanes<F>, dim3((unsigned)nplanes), dim3(BP_THREADS), 0, st, buckets, p.nb, p.c, win);
+    ZK_HIP(hipGetLastError());
+  }
+  ZK_HIP(hipMemcpyAsync(win_host, win, nplanes * XW * 4, hipMemcpyDeviceToHost, st));
+}
+
+// Horner over the windows on the host; call after the MSM's stream has completed.
+template <class F>
+typename HostOf<F>::Pt msm_finish(const MsmPending& pend) {
+  using HP = typename HostOf<F>::Pt;
+  constexpr int XW = PointIO<F>::XYZZ_WORDS;
+  constexpr int CW = XW / 4;
+  HP acc = HP::inf();
+  if (pend.empty) return acc;
+  // the plane sum of bit position q = c w + j carries weight 2^q
+  const int nplanes = pend.nw * pend.c;
+  bool started = false;
+  for (int q = nplanes - 1; q >= 0; q--) {
+    if (started) acc = HP::dbl(acc);
+    const uint32_t* e = pend.win_host + (size_t)q * XW;
+    bool zero = true;
+    for (int k = 2 * CW; k < 3 * CW; k++) zero = zero && e[k] == 0u;  // ZZ = 0: infinity
+    if (zero) continue;
+    auto X = HostOf<F>::coord(e), Y = HostOf<F>::coord(e + CW), ZZ = HostOf<F>::coord(e + 2 * CW),
+         ZZZ = HostOf<F>::coord(e + 3 * CW);
+    acc = HP::add(acc, host::xyzz_to_jac(X, Y, ZZ, ZZZ));
+    started = true;
+  }
+  return acc;
 }
 
 template <class F>
 typename HostOf<F>::Pt msm_run(const MsmInput& in, Workspace& ws, hipStream_t st) {
-  using HP = typename HostOf<F>::Pt;
-  constexpr int XW = PointIO<F>::XYZZ_WORDS;
-  constexpr int CW = XW / 4;  // words per coordinate
-  ZK_REQUIRE(in.nscalars < (1ull << 31) && in.npoints < (1ull << 31), "MSM too large");
-  const uint32_t n = (uint32_t)in.nscalars;
-  if (n == 0) return HP::inf();
-  int c, nw;
-  msm_choose_window(n, in.max_bits, &c, &nw);
-  const uint32_t nb = 1u << (c - 1);
-  const uint32_t nbt = (uint32_t)nw * nb;
-
-  uint32_t* digits = ws.get(S_DIGITS, (size_t)nw * n * 4);
-  uint32_t* counts = ws.get(S_COUNTS, (size_t)nbt * 4);
-  uint32_t* offsets = ws.get(S_OFFSETS, (size_t)nbt * 4);
-  uint32_t* cursor = ws.get(S_CURSOR, (size_t)nbt * 4);
-  uint32_t* meta = ws.get(S_META, 64 * 4);  // [0] entries, [1] max bucket, [2] tasks, [3] max tasks/bucket
-  uint32_t* cntb[2] = {ws.get(S_CNT_A, (size_t)nbt * 4), ws.get(S_CNT_B, (size_t)nbt * 4)};
-  uint32_t* offb[2] = {ws.get(S_OFF_A, (size_t)nbt * 4), ws.get(S_OFF_B, (size_t)nbt * 4)};
-  fill_u32(counts, 0u, nbt, st);
-
-  DigitParams dp{in.scalars, n, in.points, (uint32_t)in.npoints, in.scalars_mont ? 1 : 0,
-                 in.point_index_bitrev, c, nw, nb, digits, counts};
-  {
-    ProfScope ps(PointIO<F>::AFF_WORDS == 16 ? "msm_digits_g1" : "msm_digits_g2", st, (double)n);
-    hipLaunchKernelGGL(k_msm_digits<F>, dim3(cdiv(n, 256)), dim3(256), 0, st, dp);
-    ZK_HIP(hipGetLastError());
-  }
-  scan_exclusive(counts, offsets, nbt, 0, meta + 0, meta + 1, ws, S_SCRATCH, st);
-  ZK_HIP(hipMemcpyAsync(cursor, offsets, (size_t)nbt * 4, hipMemcpyDeviceToDevice, st));
-  uint32_t hm[2];
-  ZK_HIP(hipMemcpyAsync(hm, meta, 8, hipMemcpyDeviceToHost, st));
+  MsmPending pend;
+  msm_enqueue<F>(in, ws, st, pend);
   ZK_HIP(hipStreamSynchronize(st));
-  const uint32_t total = hm[0];
-  if (total == 0) return HP::inf();
-  uint32_t* sorted = ws.get(S_SORTED, (size_t)total * 4);
-  {
-    ProfScope ps("msm_scatter", st, (double)total);
-    hipLaunchKernelGGL(k_msm_scatter, dim3(cdiv(n, 256)), dim3(256), 0, st, digits, n, nw, nb, cursor, sorted,
-                       in.point_index_bitrev);
-    ZK_HIP(hipGetLastError());
-  }
-
-  // Accumulation levels.  Level 0 sums points; later levels sum the partial
-  // sums of buckets that were split into several tasks.
-  uint32_t K = std::max(4u, std::min(total / 65536u, 64u));
-  const uint32_t* cur_cnt = counts;
-  const uint32_t* cur_off = offsets;
-  const uint32_t* in_part = nullptr;
-  uint32_t level_entries = total;  // entries summed at the current level
-  for (int level = 0;; level++) {
-    uint32_t* task_off = offb[level & 1];
-    uint32_t* next_cnt = cntb[level & 1];
-    scan_exclusive(cur_cnt, task_off, nbt, K, meta + 2, meta + 3, ws, S_SCRATCH, st);
-    ZK_HIP(hipMemcpyAsync(hm, meta + 2, 8, hipMemcpyDeviceToHost, st));
-    ZK_HIP(hipStreamSynchronize(st));
-    const uint32_t ntasks = hm[0], maxt = hm[1];
-    uint2* tasks = ws.get<uint2>(S_TASKS, (size_t)ntasks * 8);
-    uint32_t* out_part = ws.get(level & 1 ? S_PART1 : S_PART0, (size_t)ntasks * XW * 4);
-    hipLaunchKernelGGL(k_msm_tasks, dim3(cdiv(nbt, 256)), dim3(256), 0, st, cur_cnt, cur_off, task_off, nbt, K,
-                       tasks);
-    ZK_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_div_ceil, dim3(cdiv(nbt, 256)), dim3(256), 0, st, cur_cnt, next_cnt, nbt, K);
-    ZK_HIP(hipGetLastError());
-    {
-      const bool g1 = PointIO<F>::AFF_WORDS == 16;
-      // work: one addition per entry summed (level 0: points; later: partials)
-      ProfScope ps(level == 0 ? (g1 ? "msm_acc_points_g1" : "msm_acc_points_g2")
-                              : (g1 ? "msm_acc_partials_g1" : "msm_acc_partials_g2"),
-                   st, level == 0 ? (double)total : (double)level_entries);
-      if (level == 0)
-        hipLaunchKernelGGL(k_msm_acc_points<F>, dim3(cdiv(ntasks, 64)), dim3(64), 0, st, tasks, meta + 2, sorted,
-                           in.points, out_part);
-      else
-        hipLaunchKernelGGL(k_msm_acc_partials<F>, dim3(cdiv(ntasks, 64)), dim3(64), 0, st, tasks, meta + 2,
-                           in_part, out_part);
-      ZK_HIP(hipGetLastError());
-    }
-    level_entries = ntasks;
-    cur_cnt = next_cnt;
-    cur_off = task_off;
-    in_part = out_part;
-    if (maxt <= 1) break;
-    K = 8;
-  }
-
-  // Bucket reduction: segments of L buckets, about 32k segments in all.
-  uint32_t L = 1;
-  while ((size_t)nbt / L > 32768 && L < nb) L <<= 1;
-  const uint32_t G = nb / L;
-  uint32_t* seg = ws.get(S_SEG, (size_t)nw * G * XW * 4);
-  {
-    ProfScope ps(PointIO<F>::AFF_WORDS == 16 ? "msm_segments_g1" : "msm_segments_g2", st, (double)nbt);
-    hipLaunchKernelGGL(k_msm_segments<F>, dim3(cdiv((size_t)nw * G, 64)), dim3(64), 0, st, cur_cnt, cur_off,
-                       in_part, nw, nb, L, seg);
-    ZK_HIP(hipGetLastError());
-  }
-  uint32_t* win = ws.get(S_WIN, (size_t)nw * XW * 4);
-  {
-    ProfScope ps(PointIO<F>::AFF_WORDS == 16 ? "msm_window_reduce_g1" : "msm_window_reduce_g2", st,
-                 (double)nw * G);
-    hipLaunchKernelGGL(k_msm_window_reduce<F>, dim3(nw), dim3(WR_THREADS), 0, st, seg, G, win);
-    ZK_HIP(hipGetLastError());
-  }
-  std::vector<uint32_t> hw((size_t)nw * XW);
-  ZK_HIP(hipMemcpyAsync(hw.data(), win, hw.size() * 4, hipMemcpyDeviceToHost, st));
-  ZK_HIP(hipStreamSynchronize(st));
-
-  // Horner over windows on the host
-  HP acc = HP::inf();
-  for (int w = nw - 1; w >= 0; w--) {
-    if (w != nw - 1)
-      for (int d = 0; d < c; d++) acc = HP::dbl(acc);
-    const uint32_t* p = hw.data() + (size_t)w * XW;
-    auto X = HostOf<F>::coord(p), Y = HostOf<F>::coord(p + CW), ZZ = HostOf<F>::coord(p + 2 * CW),
-         ZZZ = HostOf<F>::coord(p + 3 * CW);
-    acc = HP::add(acc, host::xyzz_to_jac(X, Y, ZZ, ZZZ));
-  }
-  return acc;
+  return msm_finish<F>(pend);
 }
+
+void msm_enqueue_g1(const MsmInput& in, Workspace& ws, hipStream_t st, MsmPending& pend) {
+  msm_enqueue<Fq>(in, ws, st, pend);
+}
+void msm_enqueue_g2(const MsmInput& in, Workspace& ws, hipStream_t st, MsmPending& pend) {
+  msm_enqueue<Fq2>(in, ws, st, pend);
+}
+host::G1J msm_finish_g1(const MsmPending& pend) { return msm_finish<Fq>(pend); }
+host::G2J msm_finish_g2(const MsmPending& pend) { return msm_finish<Fq2>(pend); }
 
 host::G1J msm_g1(const MsmInput& in, Workspace& ws, hipStream_t st) { return msm_run<Fq>(in, ws, st); }
 host::G2J msm_g2(const MsmInput& in, Workspace& ws, hipStream_t st) { return msm_run<Fq2>(in, ws, st); }

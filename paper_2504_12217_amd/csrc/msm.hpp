@@ -18,11 +18,23 @@ struct MsmInput {
   int max_bits = 254;                 // bound on |scalar| after sign folding (signed view)
 };
 
-struct MsmTiming {
-  float device_ms = 0.f;
+// An MSM enqueued on a stream; its window sums land in pinned host memory.
+struct MsmPending {
+  bool empty = true;
+  int c = 0, nw = 0;
+  int xyzz_words = 0;
+  const uint32_t* win_host = nullptr;
 };
 
-// Returns sum_j s_j P_idx(j) as a host Jacobian point.  The bulk work (digit
+// Enqueue the device pipeline of one MSM with no host synchronization; the
+// workspace must not be used by anything else until the stream completes.
+void msm_enqueue_g1(const MsmInput& in, Workspace& ws, hipStream_t st, MsmPending& pend);
+void msm_enqueue_g2(const MsmInput& in, Workspace& ws, hipStream_t st, MsmPending& pend);
+// After the stream has completed: combine the windows (host).
+host::G1J msm_finish_g1(const MsmPending& pend);
+host::G2J msm_finish_g2(const MsmPending& pend);
+
+// Returns sum_j s_j P_idx(j) as a host Jacobian point (enqueue, wait, finish).  The bulk work (digit
 // recoding, counting sort by bucket, bucket accumulation, bucket reduction per
 // window) runs on the device; the host combines the per-window sums.
 host::G1J msm_g1(const MsmInput& in, Workspace& ws, hipStream_t st);

@@ -16,6 +16,8 @@ class ProfScope {
   ProfScope(const char* name, hipStream_t st, double work);
   ~ProfScope();
   void stop();
+  // work units = the device word at p when the profile is read (copied on the stream now)
+  void set_work_from_device(const uint32_t* p);
 
  private:
   int slot_ = -1;

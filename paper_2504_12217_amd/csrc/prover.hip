@@ -24,6 +24,7 @@
 #include "prover.hpp"
 
 #include <chrono>
+#include <future>
 #include <cstring>
 
 #include "api_common.hpp"
@@ -282,13 +283,24 @@ __global__ void k_h_scalars(uint32_t count, const uint32_t* consts, uint32_t* ou
 }
 
 // ------------------------------------------------------------------ prove kernels
-__global__ void k_matmul(const int8_t* X, const int8_t* W, uint32_t a, uint32_t n, uint32_t b, int32_t* Y) {
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a * b) return;
-  const uint32_t i = t / b, j = t % b;
-  int32_t acc = 0;
-  for (uint32_t k = 0; k < n; k++) acc += (int32_t)X[(size_t)i * n + k] * (int32_t)W[(size_t)k * b + j];
-  Y[t] = acc;
+// Y = X W in int32; block (i, j-tile): X row i is shared by the block.
+__global__ void __launch_bounds__(256) k_matmul(const int8_t* X, const int8_t* W, uint32_t a, uint32_t n, uint32_t b,
+                                               int32_t* Y) {
+  const uint32_t i = blockIdx.y;
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= b) return;
+  const int8_t* x = X + (size_t)i * n;
+  int32_t acc0 = 0, acc1 = 0;
+  uint32_t k = 0;
+  for (; k + 8 <= n; k += 8) {
+#pragma unroll
+    for (int q = 0; q < 8; q += 2) {
+      acc0 += (int32_t)x[k + q] * (int32_t)W[(size_t)(k + q) * b + j];
+      acc1 += (int32_t)x[k + q + 1] * (int32_t)W[(size_t)(k + q + 1) * b + j];
+    }
+  }
+  for (; k < n; k++) acc0 += (int32_t)x[k] * (int32_t)W[(size_t)k * b + j];
+  Y[(size_t)i * b + j] = acc0 + acc1;
 }
 
 // assignment (canonical words) of the constant, x, y and w variables
@@ -424,46 +436,87 @@ __global__ void __launch_bounds__(RED_THREADS) k_crpc_xw(const int8_t* X, const 
   }
 }
 
-// Y(z) = sum_ij z^(i b + j) y_ij with one block.
+constexpr int YZ_BLOCKS = 64;
+
+// Partial sums of Y(z) = sum_ij z^(i b + j) y_ij, one per block (YZ_BLOCKS blocks).
 __global__ void __launch_bounds__(RED_THREADS) k_crpc_yz(const int32_t* Y, uint32_t ab, const uint32_t* zpow,
-                                                         uint32_t* out) {
+                                                         uint32_t* partial) {
   __shared__ uint32_t sh[RED_THREADS * NL];
   Fr s = Fr::zero();
-  for (uint32_t e = threadIdx.x; e < ab; e += RED_THREADS)
+  for (uint32_t e = blockIdx.x * RED_THREADS + threadIdx.x; e < ab; e += gridDim.x * RED_THREADS)
     s = Fr::add(s, Fr::mul(Fr::load(zpow + 8ull * e), fr_of_int(Y[e])));
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) s.store(out);
+  if (threadIdx.x == 0) s.store(partial + 8ull * blockIdx.x);
 }
 
-// Rows 0 .. m-1 and auxiliary variables of the CRPC kinds (serial over k <= n).
-__global__ void k_crpc_rows(uint32_t kind, uint32_t n, uint64_t aux_start, const uint32_t* xk, const uint32_t* wk,
-                            const uint32_t* pk, const uint32_t* yz, uint32_t* assign, uint32_t* aev, uint32_t* bev,
-                            uint32_t* cev) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  Fr s = Fr::zero();  // running prefix sum
-  for (uint32_t k = 0; k < n; k++) {
-    const Fr X = Fr::load(xk + 8ull * k), W = Fr::load(wk + 8ull * k), P = Fr::load(pk + 8ull * k);
-    store_canonical(aev + 8ull * k, X);
-    store_canonical(bev + 8ull * k, W);
-    if (kind == ZKVC_CRPC) {
-      store_canonical(cev + 8ull * k, P);
-      store_canonical(assign + 8ull * (aux_start + k), P);
-      s = Fr::add(s, P);
-    } else {
-      const Fr prev = s;
-      s = Fr::add(s, P);
-      if (k + 1 < n) {
+// Rows 0 .. m-1 and auxiliary variables of the CRPC kinds, one block: the
+// prefix sums s_k = sum_{k' <= k} P_k' come from a block-wide inclusive scan
+// over chunks of RED_THREADS rows with a running carry.
+__global__ void __launch_bounds__(RED_THREADS) k_crpc_rows(uint32_t kind, uint32_t n, uint64_t aux_start,
+                                                           const uint32_t* xk, const uint32_t* wk,
+                                                           const uint32_t* pk, const uint32_t* yz_partial,
+                                                           uint32_t* assign, uint32_t* aev, uint32_t* bev,
+                                                           uint32_t* cev) {
+  __shared__ uint32_t sh[RED_THREADS * NL];
+  __shared__ uint32_t carry_sh[NL];
+  // Y(z) from the per-block partial sums
+  Fr yz = threadIdx.x < YZ_BLOCKS ? Fr::load(yz_partial + 8ull * threadIdx.x) : Fr::zero();
+  yz = block_sum(yz, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NL; q++) carry_sh[q] = yz.v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NL; q++) yz.v[q] = carry_sh[q];
+  __syncthreads();
+  Fr carry = Fr::zero();
+  for (uint32_t k0 = 0; k0 < n; k0 += RED_THREADS) {
+    const uint32_t k = k0 + threadIdx.x;
+    const Fr P = k < n ? Fr::load(pk + 8ull * k) : Fr::zero();
+    // Hillis-Steele inclusive scan of P over the chunk
+    Fr x = P;
+    for (int o = 1; o < RED_THREADS; o <<= 1) {
+#pragma unroll
+      for (int q = 0; q < NL; q++) sh[threadIdx.x * NL + q] = x.v[q];
+      __syncthreads();
+      if ((int)threadIdx.x >= o) {
+        Fr y;
+#pragma unroll
+        for (int q = 0; q < NL; q++) y.v[q] = sh[(threadIdx.x - o) * NL + q];
+        x = Fr::add(x, y);
+      }
+      __syncthreads();
+    }
+    const Fr s = Fr::add(x, carry);  // s_k
+    const Fr prev = Fr::sub(s, P);   // s_(k-1)
+    if (k < n) {
+      store_canonical(aev + 8ull * k, Fr::load(xk + 8ull * k));
+      store_canonical(bev + 8ull * k, Fr::load(wk + 8ull * k));
+      if (kind == ZKVC_CRPC) {
+        store_canonical(cev + 8ull * k, P);
+        store_canonical(assign + 8ull * (aux_start + k), P);
+      } else if (k + 1 < n) {
         store_canonical(assign + 8ull * (aux_start + k), s);
         store_canonical(cev + 8ull * k, Fr::sub(s, prev));
       } else {
-        store_canonical(cev + 8ull * k, Fr::sub(Fr::load(yz), prev));
+        store_canonical(cev + 8ull * k, Fr::sub(yz, prev));
+      }
+      if (kind == ZKVC_CRPC && k == n - 1) {  // (sum_k P_k) * 1 = Y(z)
+        store_canonical(aev + 8ull * n, s);
+        store_canonical(bev + 8ull * n, Fr::one());
+        store_canonical(cev + 8ull * n, yz);
       }
     }
-  }
-  if (kind == ZKVC_CRPC) {  // (sum_k P_k) * 1 = Y(z)
-    store_canonical(aev + 8ull * n, s);
-    store_canonical(bev + 8ull * n, Fr::one());
-    store_canonical(cev + 8ull * n, Fr::load(yz));
+    // carry for the next chunk: the last thread's inclusive sum
+    if (threadIdx.x == RED_THREADS - 1) {
+#pragma unroll
+      for (int q = 0; q < NL; q++) carry_sh[q] = s.v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NL; q++) carry.v[q] = carry_sh[q];
+    __syncthreads();
   }
 }
 
@@ -637,6 +690,8 @@ zkvc_pk* groth16_setup(const Layout& L, const host::HFr toxic[5], const host::HF
   scalar_words(delta, e);
   pk->delta1 = host::G1J::mul(g1, e);
   pk->delta2 = host::G2J::mul(g2, e);
+  pk->delta1_table.build(pk->delta1);
+  pk->delta2_table.build(pk->delta2);
   scalar_words(gamma, e);
   const host::G2J gamma2 = host::G2J::mul(g2, e);
 
@@ -656,6 +711,11 @@ zkvc_pk* groth16_setup(const Layout& L, const host::HFr toxic[5], const host::HF
   put_raw(vk, (uint64_t)nic);
   vk.insert(vk.end(), ic_host.begin(), ic_host.end());
 
+  for (int lane = 0; lane < zkvc_pk::LANES; lane++) {
+    ZK_HIP(hipStreamCreateWithFlags(&pk->lanes[lane], hipStreamNonBlocking));
+    ZK_HIP(hipEventCreateWithFlags(&pk->join_ev[lane], hipEventDisableTiming));
+  }
+  ZK_HIP(hipEventCreateWithFlags(&pk->fork_ev, hipEventDisableTiming));
   pk->key_bytes = pk->qA.size() + pk->qB1.size() + pk->qB2.size() + pk->qL.size() + pk->qH.size() + pk->zpow.size();
   pk->ws.clear();  // setup scratch is not needed for proving
   return pk.release();
@@ -663,7 +723,7 @@ zkvc_pk* groth16_setup(const Layout& L, const host::HFr toxic[5], const host::HF
 
 // ------------------------------------------------------------------ host: prove
 namespace {
-enum ProveSlot { P_X = 20, P_W, P_Y, P_ASSIGN, P_AEV, P_BEV, P_CEV, P_XK, P_WK, P_PK, P_YZ };
+enum ProveSlot { P_X = 20, P_W, P_Y, P_ASSIGN, P_AEV, P_BEV, P_CEV, P_XK, P_WK, P_PK, P_YZ, P_TOP, P_XH, P_WH };
 
 struct Events {
   hipEvent_t e[6];
@@ -680,34 +740,46 @@ struct Events {
   }
 };
 
-host::G1J run_g1(const std::vector<Seg>& segs, const uint32_t* points, const uint32_t* assign, Workspace& ws,
-                 hipStream_t st) {
-  host::G1J acc = host::G1J::inf();
-  for (const Seg& s : segs) {
-    MsmInput in;
-    in.points = points + 16 * s.point_offset;
-    in.npoints = s.count;
-    in.scalars = assign + 8 * s.var_start;
-    in.nscalars = s.count;
-    in.max_bits = s.bits;
-    acc = host::G1J::add(acc, msm_g1(in, ws, st));
-  }
-  return acc;
-}
+// One MSM of the proof: a query segment (or the H query) and its scalars.
+struct MsmJob {
+  int group;  // 1 = G1, 2 = G2
+  int query;  // ZKVC_Q_*
+  MsmInput in;
+  MsmPending pend;
+};
 
-host::G2J run_g2(const std::vector<Seg>& segs, const uint32_t* points, const uint32_t* assign, Workspace& ws,
-                 hipStream_t st) {
-  host::G2J acc = host::G2J::inf();
-  for (const Seg& s : segs) {
-    MsmInput in;
-    in.points = points + 32 * s.point_offset;
-    in.npoints = s.count;
-    in.scalars = assign + 8 * s.var_start;
-    in.nscalars = s.count;
-    in.max_bits = s.bits;
-    acc = host::G2J::add(acc, msm_g2(in, ws, st));
+std::vector<MsmJob> msm_jobs(const zkvc_pk* pk, const uint32_t* assign, const uint32_t* h_bitrev) {
+  const Layout& L = pk->L;
+  std::vector<MsmJob> jobs;
+  auto add = [&](int group, int query, const uint32_t* points, const Seg& s) {
+    MsmJob j;
+    j.group = group;
+    j.query = query;
+    j.in.points = points + (group == 1 ? 16 : 32) * s.point_offset;
+    j.in.npoints = s.count;
+    j.in.scalars = assign + 8 * s.var_start;
+    j.in.nscalars = s.count;
+    j.in.max_bits = s.bits;
+    jobs.push_back(j);
+  };
+  if (L.N > 1) {  // H first: the largest
+    MsmJob j;
+    j.group = 1;
+    j.query = ZKVC_Q_H;
+    j.in.points = pk->qH.get();
+    j.in.npoints = L.N - 1;
+    j.in.scalars = h_bitrev;
+    j.in.nscalars = L.N;
+    j.in.scalars_mont = true;
+    j.in.point_index_bitrev = L.log_n;
+    j.in.max_bits = 253;
+    jobs.push_back(j);
   }
-  return acc;
+  for (const Seg& s : L.segL) add(1, ZKVC_Q_L, pk->qL.get(), s);
+  for (const Seg& s : L.segB) add(2, ZKVC_Q_B2, pk->qB2.get(), s);
+  for (const Seg& s : L.segB) add(1, ZKVC_Q_B1, pk->qB1.get(), s);
+  for (const Seg& s : L.segA) add(1, ZKVC_Q_A, pk->qA.get(), s);
+  return jobs;
 }
 
 }  // namespace
@@ -734,7 +806,7 @@ void groth16_prove(zkvc_pk* pk, const int8_t* X, const int8_t* W, const host::HF
   ZK_HIP(hipMemcpyAsync(dW, W, (size_t)n * b, hipMemcpyHostToDevice, st));
 
   // ---- witness and evaluation vectors
-  hipLaunchKernelGGL(k_matmul, dim3(cdiv((size_t)a * b, 128)), dim3(128), 0, st, dX, dW, a, n, b, dY);
+  hipLaunchKernelGGL(k_matmul, dim3(cdiv(b, 256), a), dim3(256), 0, st, dX, dW, a, n, b, dY);
   ZK_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_assign_public, dim3(cdiv(L.aux_start, 256)), dim3(256), 0, st, dX, dW, dY, a, n, b, assign);
   ZK_HIP(hipGetLastError());
@@ -742,13 +814,13 @@ void groth16_prove(zkvc_pk* pk, const int8_t* X, const int8_t* W, const host::HF
     uint32_t* xk = ws.get(P_XK, (size_t)n * 32);
     uint32_t* wk = ws.get(P_WK, (size_t)n * 32);
     uint32_t* pkk = ws.get(P_PK, (size_t)n * 32);
-    uint32_t* yz = ws.get(P_YZ, 32);
+    uint32_t* yz = ws.get(P_YZ, 32 * YZ_BLOCKS);
     hipLaunchKernelGGL(k_crpc_xw, dim3(n), dim3(RED_THREADS), 0, st, dX, dW, a, n, b, pk->zpow.get(), xk, wk, pkk);
     ZK_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_crpc_yz, dim3(1), dim3(RED_THREADS), 0, st, dY, a * b, pk->zpow.get(), yz);
+    hipLaunchKernelGGL(k_crpc_yz, dim3(YZ_BLOCKS), dim3(RED_THREADS), 0, st, dY, a * b, pk->zpow.get(), yz);
     ZK_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_crpc_rows, dim3(1), dim3(1), 0, st, L.kind, n, L.aux_start, xk, wk, pkk, yz, assign, aev,
-                       bev, cev);
+    hipLaunchKernelGGL(k_crpc_rows, dim3(1), dim3(RED_THREADS), 0, st, L.kind, n, L.aux_start, xk, wk, pkk, yz,
+                       assign, aev, bev, cev);
     ZK_HIP(hipGetLastError());
   } else {
     PlainRowParams rp{L.kind, a, n, b, L.m, L.aux_start, dX, dW, dY, assign, aev, bev, cev};
@@ -785,47 +857,86 @@ void groth16_prove(zkvc_pk* pk, const int8_t* X, const int8_t* W, const host::HF
     ntt_launch(aev, Lg, false, true, f, st);
   }
   // h_{N-1} sits at the last position (bitrev of N-1 is N-1); it must be zero
-  uint32_t top[8];
+  uint32_t* top = ws.host<uint32_t>(P_TOP, 32);
   ZK_HIP(hipMemcpyAsync(top, aev + 8 * (N - 1), 32, hipMemcpyDeviceToHost, st));
   ZK_HIP(hipEventRecord(ev.e[2], st));
-  ZK_HIP(hipStreamSynchronize(st));
-  for (uint32_t t : top)
-    if (t) throw Error(ZKVC_EDEVICE, "internal error: the witness does not satisfy the circuit");
 
-  // ---- MSMs over G1, then G2
-  const host::G1J msmA = run_g1(L.segA, pk->qA.get(), assign, ws, st);
-  const host::G1J msmB1 = run_g1(L.segB, pk->qB1.get(), assign, ws, st);
-  const host::G1J msmL = run_g1(L.segL, pk->qL.get(), assign, ws, st);
-  host::G1J msmH = host::G1J::inf();
-  if (N > 1) {
-    MsmInput in;
-    in.points = pk->qH.get();
-    in.npoints = N - 1;
-    in.scalars = aev;
-    in.nscalars = N;
-    in.scalars_mont = true;
-    in.point_index_bitrev = Lg;
-    in.max_bits = 253;
-    msmH = msm_g1(in, ws, st);
+  // ---- MSMs: every query segment on its own lane stream, concurrently.
+  // Each job's window sums are combined on a host thread as soon as that job
+  // completes, overlapping the jobs still running on the device.
+  std::vector<MsmJob> jobs = msm_jobs(pk, assign, aev);
+  while (pk->msm_ws.size() < jobs.size()) pk->msm_ws.emplace_back(new Workspace());
+  while (pk->job_ev.size() < jobs.size()) {
+    hipEvent_t e;
+    ZK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    pk->job_ev.push_back(e);
+  }
+  ZK_HIP(hipEventRecord(pk->fork_ev, st));
+  bool used[zkvc_pk::LANES] = {};
+  for (size_t q = 0; q < jobs.size(); q++) {
+    const int lane = (int)(q % zkvc_pk::LANES);
+    if (!used[lane]) ZK_HIP(hipStreamWaitEvent(pk->lanes[lane], pk->fork_ev, 0));
+    used[lane] = true;
+    if (jobs[q].group == 1)
+      msm_enqueue_g1(jobs[q].in, *pk->msm_ws[q], pk->lanes[lane], jobs[q].pend);
+    else
+      msm_enqueue_g2(jobs[q].in, *pk->msm_ws[q], pk->lanes[lane], jobs[q].pend);
+    ZK_HIP(hipEventRecord(pk->job_ev[q], pk->lanes[lane]));
+  }
+  for (int lane = 0; lane < zkvc_pk::LANES; lane++) {
+    if (!used[lane]) continue;
+    ZK_HIP(hipEventRecord(pk->join_ev[lane], pk->lanes[lane]));
+    ZK_HIP(hipStreamWaitEvent(st, pk->join_ev[lane], 0));
   }
   ZK_HIP(hipEventRecord(ev.e[3], st));
-  const host::G2J msmB2 = run_g2(L.segB, pk->qB2.get(), assign, ws, st);
-  ZK_HIP(hipEventRecord(ev.e[4], st));
+  std::vector<std::future<host::G1J>> f1(jobs.size());
+  std::vector<std::future<host::G2J>> f2(jobs.size());
+  for (size_t q = 0; q < jobs.size(); q++) {
+    hipEvent_t done = pk->job_ev[q];
+    const MsmPending pend = jobs[q].pend;
+    if (jobs[q].group == 1)
+      f1[q] = std::async(std::launch::async, [done, pend] {
+        ZK_HIP(hipEventSynchronize(done));
+        return msm_finish_g1(pend);
+      });
+    else
+      f2[q] = std::async(std::launch::async, [done, pend] {
+        ZK_HIP(hipEventSynchronize(done));
+        return msm_finish_g2(pend);
+      });
+  }
   ZK_HIP(hipStreamSynchronize(st));
-
-  // ---- assembly on the host
+  for (int q = 0; q < 8; q++)
+    if (top[q]) throw Error(ZKVC_EDEVICE, "internal error: the witness does not satisfy the circuit");
   const auto asm_t0 = std::chrono::steady_clock::now();
+  host::G1J msmA = host::G1J::inf(), msmB1 = host::G1J::inf(), msmL = host::G1J::inf(), msmH = host::G1J::inf();
+  host::G2J msmB2 = host::G2J::inf();
+  for (size_t q = 0; q < jobs.size(); q++) {
+    if (jobs[q].group == 2) {
+      msmB2 = host::G2J::add(msmB2, f2[q].get());
+      continue;
+    }
+    const host::G1J v = f1[q].get();
+    switch (jobs[q].query) {
+      case ZKVC_Q_A: msmA = host::G1J::add(msmA, v); break;
+      case ZKVC_Q_B1: msmB1 = host::G1J::add(msmB1, v); break;
+      case ZKVC_Q_L: msmL = host::G1J::add(msmL, v); break;
+      default: msmH = host::G1J::add(msmH, v); break;
+    }
+  }
+
+  // ---- assembly on the host: blinding multiples of delta from fixed-base
+  // tables, s A + r B1 with one shared doubling chain
   uint64_t rw[4], sw[4], rsw[4];
   r.to_u64(rw);
   s.to_u64(sw);
   host::HFr::mul(r, s).to_u64(rsw);
-  const host::G1J A = host::G1J::add(host::G1J::add(pk->alpha1, msmA), host::G1J::mul(pk->delta1, rw));
-  const host::G2J B = host::G2J::add(host::G2J::add(pk->beta2, msmB2), host::G2J::mul(pk->delta2, sw));
-  const host::G1J B1 = host::G1J::add(host::G1J::add(pk->beta1, msmB1), host::G1J::mul(pk->delta1, sw));
+  const host::G1J A = host::G1J::add(host::G1J::add(pk->alpha1, msmA), pk->delta1_table.mul(rw));
+  const host::G2J B = host::G2J::add(host::G2J::add(pk->beta2, msmB2), pk->delta2_table.mul(sw));
+  const host::G1J B1 = host::G1J::add(host::G1J::add(pk->beta1, msmB1), pk->delta1_table.mul(sw));
   host::G1J C = host::G1J::add(msmL, msmH);
-  C = host::G1J::add(C, host::G1J::mul(A, sw));
-  C = host::G1J::add(C, host::G1J::mul(B1, rw));
-  C = host::G1J::add(C, host::G1J::neg(host::G1J::mul(pk->delta1, rsw)));
+  C = host::G1J::add(C, host::G1J::mul2(A, sw, B1, rw));
+  C = host::G1J::add(C, host::G1J::neg(pk->delta1_table.mul(rsw)));
   g1_to_abi(A, &out->A);
   g2_to_abi(B, &out->B);
   g1_to_abi(C, &out->C);
@@ -833,10 +944,22 @@ void groth16_prove(zkvc_pk* pk, const int8_t* X, const int8_t* W, const host::HF
 
   pk->last.witness_ms = ev.ms(0, 1);
   pk->last.ntt_ms = ev.ms(1, 2);
-  pk->last.msm_g1_ms = ev.ms(2, 3);
-  pk->last.msm_g2_ms = ev.ms(3, 4);
+  pk->last.msm_ms = ev.ms(2, 3);
   pk->last.host_ms = std::chrono::duration<float, std::milli>(host_t1 - asm_t0).count();
   pk->last.total_ms = std::chrono::duration<float, std::milli>(host_t1 - host_t0).count();
 }
 
 }  // namespace zkvc
+
+zkvc_pk::~zkvc_pk() {
+  // wait for anything still queued on this key's streams, then release them
+  for (int lane = 0; lane < LANES; lane++) {
+    if (lanes[lane]) {
+      (void)hipStreamSynchronize(lanes[lane]);
+      (void)hipStreamDestroy(lanes[lane]);
+    }
+    if (join_ev[lane]) (void)hipEventDestroy(join_ev[lane]);
+  }
+  if (fork_ev) (void)hipEventDestroy(fork_ev);
+  for (hipEvent_t e : job_ev) (void)hipEventDestroy(e);
+}

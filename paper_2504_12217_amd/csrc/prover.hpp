@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <memory>
 #include <mutex>
 #include <vector>
 
@@ -44,6 +45,8 @@ bool kind_uses_z(uint32_t kind);
 
 // The opaque proving key of the C ABI.
 struct zkvc_pk {
+  static constexpr int LANES = 6;  // concurrent MSM streams
+  ~zkvc_pk();
   zkvc::Layout L;
   int device = 0;
   bool has_z = false;
@@ -53,7 +56,14 @@ struct zkvc_pk {
   zkvc::DevBuf zpow;  // z^e for e < a*b (CRPC kinds), internal Fr layout
   zkvc::host::G1J alpha1, beta1, delta1;
   zkvc::host::G2J beta2, delta2;
-  zkvc::Workspace ws;
+  zkvc::host::FixedBaseTable<zkvc::host::HFq> delta1_table;
+  zkvc::host::FixedBaseTable<zkvc::host::HFq2> delta2_table;
+  std::vector<hipEvent_t> job_ev;  // completion of each MSM job
+  zkvc::Workspace ws;                  // witness, evaluation vectors, quotient
+  std::vector<std::unique_ptr<zkvc::Workspace>> msm_ws;  // one per MSM job
+  hipStream_t lanes[LANES] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[LANES] = {};
   std::mutex mu;
   zkvc_prove_stats last{};
   size_t key_bytes = 0;

@@ -50,6 +50,25 @@ void DevBuf::release() {
   n_ = 0;
 }
 
+void HostBuf::ensure(size_t bytes) {
+  if (bytes <= n_) return;
+  release();
+  void* p = nullptr;
+  hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(ZKVC_ENOMEM, "hipHostMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
+  }
+  p_ = p;
+  n_ = bytes;
+}
+
+void HostBuf::release() {
+  if (p_) (void)hipHostFree(p_);
+  p_ = nullptr;
+  n_ = 0;
+}
+
 int current_device() {
   int d = 0;
   ZK_HIP(hipGetDevice(&d));

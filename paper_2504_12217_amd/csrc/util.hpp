@@ -59,8 +59,25 @@ class DevBuf {
   size_t n_ = 0;
 };
 
+// Owning pinned host allocation (hipHostMalloc), for asynchronous copies.
+class HostBuf {
+ public:
+  HostBuf() = default;
+  ~HostBuf() { release(); }
+  HostBuf(const HostBuf&) = delete;
+  HostBuf& operator=(const HostBuf&) = delete;
+  void ensure(size_t bytes);
+  void release();
+  template <class T = uint32_t>
+  T* get() const { return reinterpret_cast<T*>(p_); }
+
+ private:
+  void* p_ = nullptr;
+  size_t n_ = 0;
+};
+
 // Grow-only named scratch buffers.  Not thread-safe by itself: each owner
-// (a proving key, or one stream of the standalone calls) has its own.
+// (a proving key's MSM lane, or one stream of the standalone calls) has its own.
 class Workspace {
  public:
   template <class T = uint32_t>
@@ -69,15 +86,25 @@ class Workspace {
     b.ensure(bytes < 256 ? 256 : bytes);
     return b.get<T>();
   }
+  template <class T = uint32_t>
+  T* host(int slot, size_t bytes) {
+    auto& b = host_[slot];
+    b.ensure(bytes < 256 ? 256 : bytes);
+    return b.get<T>();
+  }
   size_t bytes() const {
     size_t s = 0;
     for (auto& kv : bufs_) s += kv.second.size();
     return s;
   }
-  void clear() { bufs_.clear(); }
+  void clear() {
+    bufs_.clear();
+    host_.clear();
+  }
 
  private:
   std::map<int, DevBuf> bufs_;
+  std::map<int, HostBuf> host_;
 };
 
 // One workspace per (device, stream) for the standalone entry points.

@@ -59,9 +59,14 @@ class PkInfo(ctypes.Structure):
                 ("device_bytes", ctypes.c_uint64)]
 
 
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double),
+                ("work", ctypes.c_double)]
+
+
 class ProveStats(ctypes.Structure):
-    _fields_ = [("witness_ms", ctypes.c_float), ("ntt_ms", ctypes.c_float), ("msm_g1_ms", ctypes.c_float),
-                ("msm_g2_ms", ctypes.c_float), ("host_ms", ctypes.c_float), ("total_ms", ctypes.c_float)]
+    _fields_ = [("witness_ms", ctypes.c_float), ("ntt_ms", ctypes.c_float), ("msm_ms", ctypes.c_float),
+                ("host_ms", ctypes.c_float), ("total_ms", ctypes.c_float)]
 
 
 _lib = None
@@ -84,6 +89,8 @@ _SIGS = {
     "zkvc_pk_export": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, _VP]),
     "zkvc_pk_last_stats": (ctypes.c_int, [_VP, ctypes.POINTER(ProveStats)]),
     "zkvc_field_op": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
+    "zkvc_profile_begin": (ctypes.c_int, []),
+    "zkvc_profile_read": (ctypes.c_int, [ctypes.POINTER(KernelStat), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
 }
 
 EXPORTS = tuple(_SIGS)
@@ -189,6 +196,19 @@ def fixed_base_g2(scalars, n, points_out, flags=0, stream=None):
 
 def field_op(field, op, a, b, out, n, stream=None):
     _check(lib().zkvc_field_op(field, op, _ptr(a), _ptr(b), _ptr(out), n, _stream(stream)))
+
+
+def profile_begin():
+    """Start recording HIP events around the library's instrumented launches."""
+    _check(lib().zkvc_profile_begin())
+
+
+def profile_read():
+    """Stop recording; {kernel: (launches, total_ms, work_units)}."""
+    buf = (KernelStat * 128)()
+    cnt = ctypes.c_int(0)
+    _check(lib().zkvc_profile_read(buf, 128, ctypes.byref(cnt)))
+    return {buf[k].name.decode(): (buf[k].launches, buf[k].total_ms, buf[k].work) for k in range(min(cnt.value, 128))}
 
 
 # -------------------------------------------------------------------- Groth16
