@@ -2,25 +2,25 @@
 // A, B, L and H queries), plus fixed-base batch multiplication for key
 // generation.
 //
-// Device pipeline for one MSM with window width c and nw signed windows:
+// Device pipeline for a batch of MSMs, each with its own window width c and
+// nw signed windows (all steps cover every MSM of the batch):
 //   1. digits:  each scalar is folded to |s| <= (r-1)/2 with a sign (s > (r-1)/2
 //               becomes -(r - s)) and recoded into signed digits in
 //               (-2^(c-1), 2^(c-1)]; digit d != 0 of window w names bucket
-//               |d| - 1 of that window and carries the sign.  A histogram of
-//               bucket sizes is built with atomics.
-//   2. sort:    an exclusive scan of the histogram gives each bucket's range;
-//               a scatter places (point index | sign) into it (counting sort;
-//               the order inside a bucket is irrelevant to the sum).
-//   3. accumulate: every bucket is cut into tasks of at most K entries, one
-//               thread per task, so work stays balanced whatever the bucket
-//               sizes (small-integer scalars pile into few buckets).  Each
-//               task sums its points with mixed XYZZ additions.  The partial
-//               sums of a bucket are contiguous, so the same cut-and-sum step
-//               repeats on them until every bucket holds one point.
-//   4. reduce:  per window, sum_b (b+1) B_b by running sums over segments of
-//               buckets plus a small multiple of each segment total, then a
-//               tree sum over segments.
-//   5. host:    sum_w 2^(c w) W_w by Horner's rule (a serial chain of about 254
+//               |d| - 1 of that window and carries the sign.
+//   2. sort:    per (window, chunk of scalars) an LDS histogram of buckets;
+//               an exclusive scan over (bucket, chunk) gives every chunk its
+//               slots inside each bucket, and a scatter with LDS cursors
+//               places (point index | sign) there (a counting sort with no
+//               global atomics, so skewed digits cost nothing extra).
+//   3. accumulate: every bucket is cut into tasks by its size (thread tasks
+//               of K entries, wavefront tasks for heavy buckets), so work
+//               stays balanced whatever the bucket sizes (small-integer
+//               scalars pile into few buckets); a task sums its points with
+//               mixed XYZZ additions, and a pass per bucket adds its task sums.
+//   4. reduce:  bit planes: S[w c + j] = sum of the buckets whose digit value
+//               has bit j set, so sum_j 2^j S[w c + j] = sum_b (b + 1) B_b.
+//   5. host:    sum_q 2^q S[q] by Horner's rule (a serial chain of about 254
 //               doublings, which one CPU core does far faster than one wave).
 #include "msm.hpp"
 
@@ -41,7 +41,7 @@ constexpr uint32_t EMPTY = 0xffffffffu;
 constexpr uint32_t WG_TASK_ENTRIES = 256;  // entries per large-bucket (wavefront) task
 constexpr uint32_t SIGN = 0x80000000u;
 enum MsmSlot {
-  S_DIGITS = 100, S_COUNTS, S_OFFSETS, S_CURSOR, S_SORTED, S_TASKS, S_CNT_A, S_CNT_B, S_OFF_A, S_OFF_B,
+  S_DIGITS = 100, S_COUNTS, S_OFFSETS, S_HEAVY, S_SORTED, S_TASKS, S_CNT_A, S_CNT_B, S_OFF_A, S_OFF_B,
   S_PART0, S_PART1, S_SCRATCH, S_SCRATCH2, S_SEG, S_WIN, S_META, S_FB_XYZZ, S_FB_PREFIX, S_UNUSED
 };
 
@@ -49,32 +49,62 @@ __device__ __forceinline__ uint32_t bitrev_n(uint32_t a, int bits) {
   return bits == 0 ? 0u : (__builtin_bitreverse32(a) >> (32 - bits));
 }
 
-// ---------------------------------------------------------------- 1. digits
-struct DigitParams {
-  const uint32_t* scalars;
-  uint32_t nscalars;
-  const uint32_t* points;
-  uint32_t npoints;
+// ---------------------------------------------------------------- batch description
+// Several MSMs over the same group run as one device pipeline: every kernel
+// below covers all of them, so a batch of small MSMs still fills the device.
+// Each job has its own window width and its own ranges in the shared arrays.
+struct JobDev {
+  const uint32_t* points;   // affine points, device layout
+  const uint32_t* scalars;  // Fr elements, 8 words each
+  uint32_t n, npoints;
   int mont, bitrev_bits, c, nw;
-  uint32_t nb;
-  uint32_t* digits;
-  uint32_t* counts;
+  uint32_t nb;              // buckets per window: 2^(c-1)
+  uint32_t chunk, nch;      // scalars per histogram chunk, number of chunks
+  uint32_t digit_base;      // first digit word (nw * n words, window-major)
+  uint32_t bucket_base;     // first bucket (nw * nb buckets, window-major)
+  uint32_t hist_base;       // first histogram word (nw * nb * nch words)
+  uint32_t plane_base;      // first bit plane (nw * c planes) = first block of the plane grid
+  uint32_t blk_digits;      // first block of the digit grid
+  uint32_t blk_hs;          // first block of the histogram / scatter grid (nw * nch blocks)
+};
+struct BatchDev {
+  int njobs;
+  JobDev job[MSM_MAX_JOBS];
 };
 
+// The job owning a block, bucket or plane: the last job whose first index is
+// <= v (the tables are ascending).  Unrolled so the index stays a constant.
+#define ZK_JOB_OF(B, field, v)                                                   \
+  ([&]() {                                                                       \
+    int k_ = 0;                                                                  \
+    _Pragma("unroll") for (int q_ = 1; q_ < MSM_MAX_JOBS; q_++) if (q_ < (B).njobs && (v) >= (B).job[q_].field) k_ = q_; \
+    return k_;                                                                   \
+  }())
+
+constexpr int MAX_C = 15;         // the LDS histogram holds 2^(c-1) u32 counters (<= 64 KiB)
+constexpr int HS_THREADS = 512;   // histogram / scatter blocks
+constexpr int WG_THREADS = 64;    // one wavefront per large-bucket task (at most 4 entries per lane)
+constexpr int BP_THREADS = 256;   // bit-plane reduction block
+
+// ---------------------------------------------------------------- 1. digits
+// One thread per scalar: fold, recode into signed digits, write one word per
+// window (bucket | sign, or EMPTY for a zero digit or a point at infinity).
 template <class F>
-__global__ void k_msm_digits(DigitParams p) {
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= p.nscalars) return;
-  const uint32_t idx = p.bitrev_bits ? bitrev_n(j, p.bitrev_bits) : j;
-  bool skip = idx >= p.npoints;
-  if (!skip) skip = PointIO<F>::affine_is_zero(p.points + (size_t)idx * PointIO<F>::AFF_WORDS);
+__global__ void __launch_bounds__(256) k_msm_digits(BatchDev B, uint32_t* digits) {
+  const int k = ZK_JOB_OF(B, blk_digits, blockIdx.x);
+  const JobDev& J = B.job[k];
+  const uint32_t j = (blockIdx.x - J.blk_digits) * 256 + threadIdx.x;
+  if (j >= J.n) return;
+  const uint32_t idx = J.bitrev_bits ? bitrev_n(j, J.bitrev_bits) : j;
+  bool skip = idx >= J.npoints;
+  if (!skip) skip = PointIO<F>::affine_is_zero(J.points + (size_t)idx * PointIO<F>::AFF_WORDS);
   uint32_t s[8];
   {
-    const uint4 a = reinterpret_cast<const uint4*>(p.scalars + 8ull * j)[0];
-    const uint4 b = reinterpret_cast<const uint4*>(p.scalars + 8ull * j)[1];
+    const uint4 a = reinterpret_cast<const uint4*>(J.scalars + 8ull * j)[0];
+    const uint4 b = reinterpret_cast<const uint4*>(J.scalars + 8ull * j)[1];
     s[0] = a.x; s[1] = a.y; s[2] = a.z; s[3] = a.w; s[4] = b.x; s[5] = b.y; s[6] = b.z; s[7] = b.w;
   }
-  if (p.mont) {
+  if (J.mont) {
     Fr x = Fr::unpack(s);
     x = Fr::from_mont(x);
     x.pack(s);
@@ -82,9 +112,9 @@ __global__ void k_msm_digits(DigitParams p) {
   // fold: s > (r-1)/2  ->  r - s with the sign flipped
   bool gt = false, decided = false;
 #pragma unroll
-  for (int k = 7; k >= 0; k--) {
-    if (!decided && s[k] != FrParams::HALF32[k]) {
-      gt = s[k] > FrParams::HALF32[k];
+  for (int q = 7; q >= 0; q--) {
+    if (!decided && s[q] != FrParams::HALF32[q]) {
+      gt = s[q] > FrParams::HALF32[q];
       decided = true;
     }
   }
@@ -92,17 +122,19 @@ __global__ void k_msm_digits(DigitParams p) {
   if (gt) {
     uint64_t borrow = 0;
 #pragma unroll
-    for (int k = 0; k < 8; k++) {
-      const uint64_t t = (uint64_t)FrParams::P32[k] - s[k] - borrow;
-      s[k] = (uint32_t)t;
+    for (int q = 0; q < 8; q++) {
+      const uint64_t t = (uint64_t)FrParams::P32[q] - s[q] - borrow;
+      s[q] = (uint32_t)t;
       borrow = (t >> 32) & 1u;
     }
   }
-  const uint32_t half = 1u << (p.c - 1);
-  const uint32_t cmask = (1u << p.c) - 1u;
+  const int c = J.c;
+  const uint32_t half = 1u << (c - 1);
+  const uint32_t cmask = (1u << c) - 1u;
   uint32_t carry = 0;
-  for (int w = 0; w < p.nw; w++) {
-    const int pos = p.c * w;
+  uint32_t* out = digits + J.digit_base + j;
+  for (int w = 0; w < J.nw; w++) {
+    const int pos = c * w;
     const int q = pos >> 5, sh = pos & 31;
     uint32_t raw = 0;
     if (q < 8) {
@@ -113,34 +145,61 @@ __global__ void k_msm_digits(DigitParams p) {
     uint32_t d = raw + carry;
     uint32_t sgn = 0;
     if (d > half) {
-      d = (1u << p.c) - d;
+      d = (1u << c) - d;
       sgn = 1;
       carry = 1;
     } else {
       carry = 0;
     }
-    uint32_t out = EMPTY;
-    if (!skip && d != 0u) {
-      const uint32_t bucket = d - 1u;
-      out = bucket | ((neg ^ sgn) << 31);
-      atomicAdd(&p.counts[(size_t)w * p.nb + bucket], 1u);
-    }
-    p.digits[(size_t)w * p.nscalars + j] = out;
+    out[(size_t)w * J.n] = (!skip && d != 0u) ? ((d - 1u) | ((neg ^ sgn) << 31)) : EMPTY;
   }
 }
 
-// ---------------------------------------------------------------- 2. scatter
-__global__ void k_msm_scatter(const uint32_t* digits, uint32_t nscalars, int nw, uint32_t nb, uint32_t* cursor,
-                              uint32_t* sorted, int bitrev_bits) {
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nscalars) return;
-  const uint32_t idx = bitrev_bits ? bitrev_n(j, bitrev_bits) : j;
-  for (int w = 0; w < nw; w++) {
-    const uint32_t d = digits[(size_t)w * nscalars + j];
-    if (d == EMPTY) continue;
-    const uint32_t b = d & ~SIGN;
-    const uint32_t pos = atomicAdd(&cursor[(size_t)w * nb + b], 1u);
-    sorted[pos] = idx | (d & SIGN);
+// ---------------------------------------------------------------- 2. counting sort
+// Block (window w, chunk ch) counts its digits per bucket in LDS and writes
+// the counts to hist[(w nb + b) nch + ch].  An exclusive scan of hist then
+// gives every (bucket, chunk) pair its first slot in bucket order, with no
+// global atomics however skewed the digits are.
+__global__ void __launch_bounds__(HS_THREADS) k_msm_hist(BatchDev B, const uint32_t* digits, uint32_t* hist) {
+  extern __shared__ uint32_t cnt[];
+  const int k = ZK_JOB_OF(B, blk_hs, blockIdx.x);
+  const JobDev& J = B.job[k];
+  const uint32_t local = blockIdx.x - J.blk_hs;
+  const uint32_t w = local / J.nch, ch = local % J.nch;
+  for (uint32_t b = threadIdx.x; b < J.nb; b += HS_THREADS) cnt[b] = 0u;
+  __syncthreads();
+  const uint32_t* d = digits + J.digit_base + (size_t)w * J.n;
+  const uint32_t lo = ch * J.chunk, hi = min(J.n, lo + J.chunk);
+  for (uint32_t i = lo + threadIdx.x; i < hi; i += HS_THREADS) {
+    const uint32_t v = d[i];
+    if (v != EMPTY) atomicAdd(&cnt[v & ~SIGN], 1u);
+  }
+  __syncthreads();
+  uint32_t* h = hist + J.hist_base + (size_t)w * J.nb * J.nch + ch;
+  for (uint32_t b = threadIdx.x; b < J.nb; b += HS_THREADS) h[(size_t)b * J.nch] = cnt[b];
+}
+
+// Same blocks as k_msm_hist: LDS cursors start at the scanned offsets and
+// every digit takes the next slot of its bucket (order inside a bucket does
+// not matter to the sum).  Entries are (point index | sign).
+__global__ void __launch_bounds__(HS_THREADS) k_msm_scatter(BatchDev B, const uint32_t* digits, const uint32_t* offs,
+                                                            uint32_t* sorted) {
+  extern __shared__ uint32_t cur[];
+  const int k = ZK_JOB_OF(B, blk_hs, blockIdx.x);
+  const JobDev& J = B.job[k];
+  const uint32_t local = blockIdx.x - J.blk_hs;
+  const uint32_t w = local / J.nch, ch = local % J.nch;
+  const uint32_t* o = offs + J.hist_base + (size_t)w * J.nb * J.nch + ch;
+  for (uint32_t b = threadIdx.x; b < J.nb; b += HS_THREADS) cur[b] = o[(size_t)b * J.nch];
+  __syncthreads();
+  const uint32_t* d = digits + J.digit_base + (size_t)w * J.n;
+  const uint32_t lo = ch * J.chunk, hi = min(J.n, lo + J.chunk);
+  for (uint32_t i = lo + threadIdx.x; i < hi; i += HS_THREADS) {
+    const uint32_t v = d[i];
+    if (v == EMPTY) continue;
+    const uint32_t pos = atomicAdd(&cur[v & ~SIGN], 1u);
+    const uint32_t idx = J.bitrev_bits ? bitrev_n(i, J.bitrev_bits) : i;
+    sorted[pos] = idx | (v & SIGN);
   }
 }
 
@@ -150,69 +209,113 @@ __global__ void k_msm_scatter(const uint32_t* digits, uint32_t nscalars, int nw,
 // task serially); a larger one becomes wavefront tasks of WG_TASK_ENTRIES
 // entries reduced by an LDS tree.  nt[f] is the number of partial sums of
 // bucket f; a bucket's partial sums are contiguous.
-__global__ void k_msm_task_counts(const uint32_t* cnt, uint32_t nbt, uint32_t K, uint32_t large, uint32_t* nt) {
+__global__ void k_msm_task_counts(BatchDev B, const uint32_t* offs, uint32_t nbt, uint32_t K, uint32_t large,
+                                  uint32_t* cnt, uint32_t* off, uint32_t* nt, uint32_t* counters) {
   const uint32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f == 0) {
+    counters[0] = 0u;
+    counters[1] = 0u;
+    counters[2] = 0u;
+  }
   if (f >= nbt) return;
-  const uint32_t c = cnt[f];
+  const int k = ZK_JOB_OF(B, bucket_base, f);
+  const JobDev& J = B.job[k];
+  const size_t lf = f - J.bucket_base;
+  // the bucket after the job's last one starts the next job's range (or the total)
+  const uint32_t s = offs[J.hist_base + lf * J.nch];
+  const uint32_t e = offs[J.hist_base + (lf + 1) * J.nch];
+  const uint32_t c = e - s;
+  cnt[f] = c;
+  off[f] = s;
   const uint32_t sz = c >= large ? WG_TASK_ENTRIES : K;
   nt[f] = (c + sz - 1) / sz;
 }
 
-// Task records (first entry, length, output partial slot); the two task lists
-// are filled through atomic counters (their order does not matter).
-__global__ void k_msm_make_tasks(const uint32_t* cnt, const uint32_t* off, const uint32_t* part_off, uint32_t nbt,
-                                 uint32_t K, uint32_t large, uint32_t* counters, uint4* th_tasks, uint4* wg_tasks) {
+// Task records (first entry, length, output partial slot, bucket).  Slots in
+// the two task lists are claimed with one atomic per wavefront and list.
+// Buckets that end up with more than FIN_THREAD_MAX partial sums are listed
+// for a wavefront each in the finalize step.
+constexpr uint32_t FIN_THREAD_MAX = 8;
+
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v, uint32_t lane) {
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t a = __shfl_up(v, o, 64);
+    if ((int)lane >= o) v += a;
+  }
+  return v;
+}
+
+__global__ void __launch_bounds__(256) k_msm_make_tasks(const uint32_t* cnt, const uint32_t* off, const uint32_t* part_off,
+                                                        uint32_t nbt, uint32_t K, uint32_t large, uint32_t* counters,
+                                                        uint4* th_tasks, uint4* wg_tasks, uint32_t* heavy) {
   const uint32_t f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= nbt) return;
-  const uint32_t c = cnt[f];
-  if (c == 0) return;
-  const uint32_t o = off[f], p = part_off[f];
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t c = f < nbt ? cnt[f] : 0u;
   const bool big = c >= large;
   const uint32_t sz = big ? WG_TASK_ENTRIES : K;
   const uint32_t nt = (c + sz - 1) / sz;
-  const uint32_t base = atomicAdd(&counters[big ? 1 : 0], nt);
+  const uint32_t hv = nt > FIN_THREAD_MAX ? 1u : 0u;
+  // inclusive wavefront scans of the three claims
+  const uint32_t sth = wave_inclusive_sum(big ? 0u : nt, lane);
+  const uint32_t swg = wave_inclusive_sum(big ? nt : 0u, lane);
+  const uint32_t shv = wave_inclusive_sum(hv, lane);
+  uint32_t bth = 0, bwg = 0, bhv = 0;
+  if (lane == 63u) {
+    if (sth) bth = atomicAdd(&counters[0], sth);
+    if (swg) bwg = atomicAdd(&counters[1], swg);
+    if (shv) bhv = atomicAdd(&counters[2], shv);
+  }
+  bth = __shfl(bth, 63, 64);
+  bwg = __shfl(bwg, 63, 64);
+  bhv = __shfl(bhv, 63, 64);
+  if (c == 0) return;
+  if (hv) heavy[bhv + shv - 1u] = f;
+  const uint32_t base = big ? bwg + swg - nt : bth + sth - nt;
   uint4* dst = big ? wg_tasks : th_tasks;
+  const uint32_t o = off[f], p = part_off[f];
   for (uint32_t q = 0; q < nt; q++) {
     const uint32_t len = c - q * sz < sz ? c - q * sz : sz;
-    dst[base + q] = make_uint4(o + q * sz, len, p + q, 0u);
+    dst[base + q] = make_uint4(o + q * sz, len, p + q, f);
   }
 }
 
+// Bucket accumulation, one launch for both task lists: blocks below
+// th_blocks run thread tasks (each thread sums its entries serially), the
+// others run wavefront tasks (each lane sums a strided share of the task's
+// entries, then an LDS tree).  Task counts are read on the device; every
+// loop is bounded by them.
 template <class F>
-__global__ void __launch_bounds__(64) k_msm_acc_points(const uint4* tasks, const uint32_t* d_ntasks, const uint32_t* sorted,
-                                 const uint32_t* points, uint32_t* partials) {
-  const uint32_t ntasks = *d_ntasks;
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntasks; t += gridDim.x * blockDim.x) {
-    const uint4 task = tasks[t];
-    Xyzz<F> acc = Xyzz<F>::inf();
-    for (uint32_t e = task.x; e < task.x + task.y; e++) {
-      const uint32_t ref = sorted[e];
-      Affine<F> pt = PointIO<F>::load_affine(points + (size_t)(ref & ~SIGN) * PointIO<F>::AFF_WORDS);
-      if (ref & SIGN) pt.y = F::neg(pt.y);
-      acc = Xyzz<F>::madd(acc, pt);
-    }
-    PointIO<F>::store_xyzz(partials + (size_t)task.z * PointIO<F>::XYZZ_WORDS, acc);
-  }
-}
-
-constexpr int WG_THREADS = 64;   // one wavefront per large-bucket task (at most 4 entries per thread)
-constexpr int BP_THREADS = 256;  // bit-plane reduction block
-
-// One wavefront per task of up to WG_TASK_ENTRIES entries of one large
-// bucket: each lane sums its entries, then an LDS tree reduces the task.
-template <class F>
-__global__ void __launch_bounds__(WG_THREADS) k_msm_acc_points_wg(const uint4* tasks, const uint32_t* d_ntasks,
-                                                                  const uint32_t* sorted, const uint32_t* points,
-                                                                  uint32_t* partials) {
+__global__ void __launch_bounds__(64) k_msm_acc(BatchDev B, const uint4* th_tasks, const uint4* wg_tasks,
+                                                const uint32_t* counters, uint32_t th_blocks, const uint32_t* sorted,
+                                                uint32_t* partials) {
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
+  constexpr int AW = PointIO<F>::AFF_WORDS;
   __shared__ uint32_t sh[WG_THREADS / 2 * XW];
-  const uint32_t ntasks = *d_ntasks;  // uniform: every block runs the same loop count
-  for (uint32_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
-    const uint4 task = tasks[t];
+  if (blockIdx.x < th_blocks) {
+    const uint32_t ntasks = counters[0];
+    for (uint32_t t = blockIdx.x * 64 + threadIdx.x; t < ntasks; t += th_blocks * 64) {
+      const uint4 task = th_tasks[t];
+      const uint32_t* points = B.job[ZK_JOB_OF(B, bucket_base, task.w)].points;
+      Xyzz<F> acc = Xyzz<F>::inf();
+      for (uint32_t e = task.x; e < task.x + task.y; e++) {
+        const uint32_t ref = sorted[e];
+        Affine<F> pt = PointIO<F>::load_affine(points + (size_t)(ref & ~SIGN) * AW);
+        if (ref & SIGN) pt.y = F::neg(pt.y);
+        acc = Xyzz<F>::madd(acc, pt);
+      }
+      PointIO<F>::store_xyzz(partials + (size_t)task.z * XW, acc);
+    }
+    return;
+  }
+  const uint32_t ntasks = counters[1];  // uniform: every lane of the block runs the same loop count
+  const uint32_t wg_blocks = gridDim.x - th_blocks;
+  for (uint32_t t = blockIdx.x - th_blocks; t < ntasks; t += wg_blocks) {
+    const uint4 task = wg_tasks[t];
+    const uint32_t* points = B.job[ZK_JOB_OF(B, bucket_base, task.w)].points;
     Xyzz<F> acc = Xyzz<F>::inf();
     for (uint32_t e = threadIdx.x; e < task.y; e += WG_THREADS) {
       const uint32_t ref = sorted[task.x + e];
-      Affine<F> pt = PointIO<F>::load_affine(points + (size_t)(ref & ~SIGN) * PointIO<F>::AFF_WORDS);
+      Affine<F> pt = PointIO<F>::load_affine(points + (size_t)(ref & ~SIGN) * AW);
       if (ref & SIGN) pt.y = F::neg(pt.y);
       acc = Xyzz<F>::madd(acc, pt);
     }
@@ -226,37 +329,68 @@ __global__ void __launch_bounds__(WG_THREADS) k_msm_acc_points_wg(const uint4* t
   }
 }
 
-// Bucket sums: the remaining partials of each bucket, summed in order.
+// Bucket sums from the partial sums, one launch: blocks below light_blocks
+// give each bucket with at most FIN_THREAD_MAX partials a thread (serial
+// sum); the others give each listed heavy bucket a wavefront (strided sums,
+// then an LDS tree), so one crowded bucket (e.g. the top window's few digit
+// values under uniform scalars) does not serialize the step.
 template <class F>
-__global__ void __launch_bounds__(64) k_msm_finalize(const uint32_t* cnt, const uint32_t* off, const uint32_t* partials,
-                                                     uint32_t nbt, uint32_t* buckets) {
+__global__ void __launch_bounds__(64) k_msm_finalize(const uint32_t* nt, const uint32_t* part_off,
+                                                     const uint32_t* partials, uint32_t nbt, const uint32_t* counters,
+                                                     const uint32_t* heavy, uint32_t light_blocks, uint32_t* buckets) {
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
-  const uint32_t f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= nbt) return;
-  const uint32_t c = cnt[f], o = off[f];
-  Xyzz<F> acc = Xyzz<F>::inf();
-  for (uint32_t e = 0; e < c; e++) acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(partials + (size_t)(o + e) * XW));
-  PointIO<F>::store_xyzz(buckets + (size_t)f * XW, acc);
+  __shared__ uint32_t sh[WG_THREADS / 2 * XW];
+  if (blockIdx.x < light_blocks) {
+    const uint32_t f = blockIdx.x * 64 + threadIdx.x;
+    if (f >= nbt) return;
+    const uint32_t c = nt[f], o = part_off[f];
+    if (c > FIN_THREAD_MAX) return;
+    Xyzz<F> acc = Xyzz<F>::inf();
+    for (uint32_t e = 0; e < c; e++) acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(partials + (size_t)(o + e) * XW));
+    PointIO<F>::store_xyzz(buckets + (size_t)f * XW, acc);
+    return;
+  }
+  const uint32_t nheavy = counters[2];
+  const uint32_t hblocks = gridDim.x - light_blocks;
+  for (uint32_t h = blockIdx.x - light_blocks; h < nheavy; h += hblocks) {
+    const uint32_t f = heavy[h];
+    const uint32_t c = nt[f], o = part_off[f];
+    Xyzz<F> acc = Xyzz<F>::inf();
+    for (uint32_t e = threadIdx.x; e < c; e += WG_THREADS)
+      acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(partials + (size_t)(o + e) * XW));
+    for (int q = WG_THREADS / 2; q >= 1; q >>= 1) {
+      if ((int)threadIdx.x >= q && (int)threadIdx.x < 2 * q) PointIO<F>::store_xyzz(sh + (threadIdx.x - q) * XW, acc);
+      __syncthreads();
+      if ((int)threadIdx.x < q) acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(sh + threadIdx.x * XW));
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) PointIO<F>::store_xyzz(buckets + (size_t)f * XW, acc);
+  }
 }
 
-// Bit planes of the bucket reduction: for window w and bit j,
+// ---------------------------------------------------------------- 4. bucket reduction by bit planes
+// For window w and bit j,
 //   S[w c + j] = sum of B_b over the buckets whose digit value b + 1 has bit j set,
 // so that window w contributes sum_j 2^j S[w c + j] = sum_b (b + 1) B_b.
-// One block per (w, j); each thread sums a strided share, then an LDS tree.
+// One block per plane; each thread sums a strided share, then an LDS tree.
 template <class F>
-__global__ void __launch_bounds__(BP_THREADS) k_msm_bitplanes(const uint32_t* buckets, uint32_t nb, int c,
-                                                              uint32_t* S) {
+__global__ void __launch_bounds__(BP_THREADS) k_msm_bitplanes(BatchDev B, const uint32_t* buckets, uint32_t* S) {
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
   __shared__ uint32_t sh[BP_THREADS / 2 * XW];
-  const uint32_t w = blockIdx.x / c, j = blockIdx.x % c;
+  const int k = ZK_JOB_OF(B, plane_base, blockIdx.x);
+  const JobDev& J = B.job[k];
+  const uint32_t q = blockIdx.x - J.plane_base;
+  const uint32_t c = (uint32_t)J.c, nb = J.nb;
+  const uint32_t w = q / c, j = q % c;
+  const uint32_t* bw = buckets + ((size_t)J.bucket_base + (size_t)w * nb) * XW;
   // digit values v in [1, nb] with bit j set: v = ((t >> j) << (j + 1)) | 2^j | (t & (2^j - 1))
   const uint32_t jmask = (1u << j) - 1u;
-  const uint32_t count = (j + 1 < (uint32_t)c) ? nb / 2 : 1u;  // bit c-1 is set only in v = nb
+  const uint32_t count = (j + 1 < c) ? nb / 2 : 1u;  // bit c-1 is set only in v = nb
   Xyzz<F> acc = Xyzz<F>::inf();
   for (uint32_t t = threadIdx.x; t < count; t += BP_THREADS) {
     const uint32_t v = ((t >> j) << (j + 1)) | (1u << j) | (t & jmask);
     if (v > nb) continue;
-    acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(buckets + ((size_t)w * nb + v - 1) * XW));
+    acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(bw + (size_t)(v - 1) * XW));
   }
   for (int o = BP_THREADS / 2; o >= 1; o >>= 1) {
     if ((int)threadIdx.x >= o && (int)threadIdx.x < 2 * o) PointIO<F>::store_xyzz(sh + (threadIdx.x - o) * XW, acc);
@@ -271,11 +405,13 @@ __global__ void __launch_bounds__(BP_THREADS) k_msm_bitplanes(const uint32_t* bu
 void msm_choose_window(size_t n, int bits, int* c_out, int* nw_out) {
   if (bits < 1) bits = 1;
   double best = 1e300;
-  int bc = 1, bnw = bits + 1;
-  for (int c = 2; c <= 18; c++) {
+  int bc = 2, bnw = (bits + 2) / 2;
+  for (int c = 2; c <= MAX_C; c++) {
     const int nw = (bits + 1 + c - 1) / c;
-    // entries + about three group additions per bucket for the reduction
-    const double cost = (double)n * nw + 3.0 * nw * (double)(1u << (c - 1));
+    const double nb = (double)(1u << (c - 1));
+    // mixed additions for the entries, a pass over every bucket, and the
+    // bit-plane reduction (c nb / 2 full additions per window, ~1.4 mixed each)
+    const double cost = (double)n * nw + 0.5 * nw * nb + 1.4 * nw * c * nb / 2;
     if (cost < best) {
       best = cost;
       bc = c;
@@ -305,125 +441,161 @@ void hfq2_to_dev(const host::HFq2& a, uint32_t* w) {
   a.c1.to_dev(w + 8);
 }
 
-// Sizes of one MSM, all known on the host before any launch, so the device
+// Sizes of one batch, all known on the host before any launch, so the device
 // pipeline needs no host synchronization until the window sums come back.
-struct MsmPlan {
-  uint32_t n = 0;
-  int c = 0, nw = 0;
-  uint32_t nb = 0, nbt = 0;
-  uint64_t max_entries = 0;
+struct BatchPlan {
+  BatchDev dev{};
+  int map[MSM_MAX_JOBS] = {};  // device job -> caller's job
+  uint64_t ndigits = 0, nbt = 0, nh = 0, nplanes = 0, digit_blocks = 0, hs_blocks = 0;
+  uint32_t max_nb = 0;
   uint32_t K = 0;      // entries per thread task
   uint32_t large = 0;  // buckets with at least this many entries get wavefront tasks
   uint64_t max_th_tasks = 0, max_wg_tasks = 0, max_partials = 0;
 };
 
-static MsmPlan msm_plan(const MsmInput& in) {
-  MsmPlan p;
-  p.n = (uint32_t)in.nscalars;
-  msm_choose_window(p.n, in.max_bits, &p.c, &p.nw);
-  p.nb = 1u << (p.c - 1);
-  p.nbt = (uint32_t)p.nw * p.nb;
-  p.max_entries = (uint64_t)p.n * p.nw;
+static BatchPlan batch_plan(const MsmInput* in, int njobs) {
+  BatchPlan p;
+  for (int q = 0; q < njobs; q++) {
+    ZK_REQUIRE(in[q].nscalars < (1ull << 31) && in[q].npoints < (1ull << 31), "MSM too large");
+    if (in[q].nscalars == 0) continue;
+    JobDev& J = p.dev.job[p.dev.njobs];
+    J.points = in[q].points;
+    J.scalars = in[q].scalars;
+    J.n = (uint32_t)in[q].nscalars;
+    J.npoints = (uint32_t)in[q].npoints;
+    J.mont = in[q].scalars_mont ? 1 : 0;
+    J.bitrev_bits = in[q].point_index_bitrev;
+    msm_choose_window(J.n, in[q].max_bits, &J.c, &J.nw);
+    J.nb = 1u << (J.c - 1);
+    // chunks of >= 4096 scalars, at most 2^22 histogram words per job
+    const uint64_t wb = (uint64_t)J.nw * J.nb;
+    uint64_t nch = std::max<uint64_t>(1, std::min<uint64_t>((J.n + 4095) / 4096, (1ull << 22) / wb));
+    const uint64_t chunk = ((J.n + nch - 1) / nch + 255) / 256 * 256;
+    J.chunk = (uint32_t)chunk;
+    J.nch = (uint32_t)((J.n + chunk - 1) / chunk);
+    J.digit_base = (uint32_t)p.ndigits;
+    J.bucket_base = (uint32_t)p.nbt;
+    J.hist_base = (uint32_t)p.nh;
+    J.plane_base = (uint32_t)p.nplanes;
+    J.blk_digits = (uint32_t)p.digit_blocks;
+    J.blk_hs = (uint32_t)p.hs_blocks;
+    p.ndigits += (uint64_t)J.nw * J.n;
+    p.nbt += wb;
+    p.nh += wb * J.nch;
+    p.nplanes += (uint64_t)J.nw * J.c;
+    p.digit_blocks += cdiv(J.n, 256);
+    p.hs_blocks += (uint64_t)J.nw * J.nch;
+    p.max_nb = std::max(p.max_nb, J.nb);
+    p.map[p.dev.njobs] = q;
+    p.dev.njobs++;
+    ZK_REQUIRE(p.ndigits < (1ull << 32) && p.nh < (1ull << 32) - 1 && p.nbt < (1ull << 31),
+               "MSM batch too large for 32-bit offsets");
+  }
+  const uint64_t E = p.ndigits;  // bound on the bucket entries
   // thread tasks: enough of them to fill the device, long enough to amortize
-  p.K = (uint32_t)std::max<uint64_t>(4, std::min<uint64_t>(p.max_entries / 65536, 64));
-  p.large = std::max<uint32_t>(64, 8 * p.K);
-  p.max_th_tasks = p.max_entries / p.K + p.nbt;
+  p.K = (uint32_t)std::max<uint64_t>(4, std::min<uint64_t>(E / 65536, 64));
+  // wavefront tasks only for buckets far above the typical size (a window's
+  // few possible top digits, or small-integer scalars piling into few buckets)
+  p.large = std::max<uint32_t>(128, 32 * p.K);
+  p.max_th_tasks = E / p.K + p.nbt;
   // a large bucket of c entries makes ceil(c / WG_TASK_ENTRIES) tasks, and at
-  // most max_entries / large buckets are large
-  p.max_wg_tasks = p.max_entries / WG_TASK_ENTRIES + p.max_entries / p.large + 1;
+  // most E / large buckets are large
+  p.max_wg_tasks = E / WG_TASK_ENTRIES + E / p.large + 1;
   p.max_partials = p.max_th_tasks + p.max_wg_tasks;
   return p;
 }
 
 template <class F>
-void msm_enqueue(const MsmInput& in, Workspace& ws, hipStream_t st, MsmPending& pend) {
+void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t st, MsmPending* pend) {
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
-  ZK_REQUIRE(in.nscalars < (1ull << 31) && in.npoints < (1ull << 31), "MSM too large");
-  pend = MsmPending();
-  pend.xyzz_words = XW;
-  if (in.nscalars == 0) return;
-  const MsmPlan p = msm_plan(in);
-  ZK_REQUIRE(p.max_entries < (1ull << 32), "MSM too large for 32-bit bucket offsets");
-  pend.empty = false;
-  pend.c = p.c;
-  pend.nw = p.nw;
-  const uint32_t n = p.n, nbt = p.nbt;
+  ZK_REQUIRE(njobs >= 0 && njobs <= MSM_MAX_JOBS, "too many MSMs in one batch");
+  for (int q = 0; q < njobs; q++) {
+    pend[q] = MsmPending();
+    pend[q].xyzz_words = XW;
+  }
+  const BatchPlan p = batch_plan(in, njobs);
+  if (p.dev.njobs == 0) return;
+  const uint32_t nbt = (uint32_t)p.nbt;
   const bool g1 = PointIO<F>::AFF_WORDS == 16;
 
   // all buffers first (growing a buffer synchronizes the device)
-  uint32_t* digits = ws.get(S_DIGITS, (size_t)p.nw * n * 4);
-  uint32_t* counts = ws.get(S_COUNTS, (size_t)nbt * 4);
-  uint32_t* offsets = ws.get(S_OFFSETS, (size_t)nbt * 4);
-  uint32_t* cursor = ws.get(S_CURSOR, (size_t)nbt * 4);
-  uint32_t* nt = ws.get(S_CNT_A, (size_t)nbt * 4);
-  uint32_t* part_off = ws.get(S_OFF_A, (size_t)nbt * 4);
-  uint32_t* sorted = ws.get(S_SORTED, p.max_entries * 4);
+  uint32_t* digits = ws.get(S_DIGITS, p.ndigits * 4);
+  uint32_t* hist = ws.get(S_COUNTS, p.nh * 4);
+  uint32_t* offs = ws.get(S_OFFSETS, (p.nh + 1) * 4);
+  uint32_t* cnt = ws.get(S_CNT_A, p.nbt * 4);
+  uint32_t* off = ws.get(S_OFF_A, p.nbt * 4);
+  uint32_t* nt = ws.get(S_CNT_B, p.nbt * 4);
+  uint32_t* part_off = ws.get(S_OFF_B, p.nbt * 4);
+  uint32_t* sorted = ws.get(S_SORTED, p.ndigits * 4);
   uint4* th_tasks = ws.get<uint4>(S_TASKS, p.max_th_tasks * 16);
   uint4* wg_tasks = ws.get<uint4>(S_PART1, p.max_wg_tasks * 16);
   uint32_t* part = ws.get(S_PART0, p.max_partials * XW * 4);
-  uint32_t* buckets = ws.get(S_SEG, (size_t)nbt * XW * 4);
-  const size_t nplanes = (size_t)p.nw * p.c;
-  uint32_t* win = ws.get(S_WIN, nplanes * XW * 4);
-  uint32_t* meta = ws.get(S_META, 64 * 4);  // [0] entries [2] partials [8] thread tasks [9] wavefront tasks
-  uint32_t* win_host = ws.host<uint32_t>(S_WIN, nplanes * XW * 4);
-  ws.get(S_SCRATCH, (size_t)cdiv(nbt, 2048) * 4 + 64);
-  pend.win_host = win_host;
-
-  fill_u32(counts, 0u, nbt, st);
-  fill_u32(meta + 8, 0u, 2, st);
-  DigitParams dp{in.scalars, n, in.points, (uint32_t)in.npoints, in.scalars_mont ? 1 : 0,
-                 in.point_index_bitrev, p.c, p.nw, p.nb, digits, counts};
+  uint32_t* buckets = ws.get(S_SEG, p.nbt * XW * 4);
+  uint32_t* win = ws.get(S_WIN, p.nplanes * XW * 4);
+  uint32_t* heavy = ws.get(S_HEAVY, p.nbt * 4);
+  uint32_t* meta = ws.get(S_META, 64 * 4);  // [2] partials [8..10] thread tasks, wavefront tasks, heavy buckets
+  uint32_t* win_host = ws.host<uint32_t>(S_WIN, p.nplanes * XW * 4);
+  ws.get(S_SCRATCH, (size_t)cdiv(std::max(p.nh, p.nbt), 2048) * 4 + 64);
+  for (int k = 0; k < p.dev.njobs; k++) {
+    MsmPending& pd = pend[p.map[k]];
+    pd.empty = false;
+    pd.c = p.dev.job[k].c;
+    pd.nw = p.dev.job[k].nw;
+    pd.win_host = win_host + (size_t)p.dev.job[k].plane_base * XW;
+  }
+  const size_t lds = (size_t)p.max_nb * 4;
   {
-    ProfScope ps(g1 ? "msm_digits_g1" : "msm_digits_g2", st, (double)n);
-    hipLaunchKernelGGL(k_msm_digits<F>, dim3(cdiv(n, 256)), dim3(256), 0, st, dp);
+    ProfScope ps(g1 ? "msm_digits_g1" : "msm_digits_g2", st, (double)p.ndigits);
+    hipLaunchKernelGGL(k_msm_digits<F>, dim3((unsigned)p.digit_blocks), dim3(256), 0, st, p.dev, digits);
     ZK_HIP(hipGetLastError());
   }
-  scan_exclusive(counts, offsets, nbt, 0, meta + 0, nullptr, ws, S_SCRATCH, st);
-  ZK_HIP(hipMemcpyAsync(cursor, offsets, (size_t)nbt * 4, hipMemcpyDeviceToDevice, st));
   {
-    ProfScope ps("msm_scatter", st, (double)n * p.nw);
-    hipLaunchKernelGGL(k_msm_scatter, dim3(cdiv(n, 256)), dim3(256), 0, st, digits, n, p.nw, p.nb, cursor, sorted,
-                       in.point_index_bitrev);
+    ProfScope ps("msm_sort", st, (double)p.ndigits);
+    hipLaunchKernelGGL(k_msm_hist, dim3((unsigned)p.hs_blocks), dim3(HS_THREADS), lds, st, p.dev, digits, hist);
+    ZK_HIP(hipGetLastError());
+    // offs[nh] receives the total number of entries
+    scan_exclusive(hist, offs, (uint32_t)p.nh, 0, offs + p.nh, nullptr, ws, S_SCRATCH, st);
+    hipLaunchKernelGGL(k_msm_scatter, dim3((unsigned)p.hs_blocks), dim3(HS_THREADS), lds, st, p.dev, digits, offs,
+                       sorted);
     ZK_HIP(hipGetLastError());
   }
   // tasks by actual bucket size
-  hipLaunchKernelGGL(k_msm_task_counts, dim3(cdiv(nbt, 256)), dim3(256), 0, st, counts, nbt, p.K, p.large, nt);
+  hipLaunchKernelGGL(k_msm_task_counts, dim3(cdiv(nbt, 256)), dim3(256), 0, st, p.dev, offs, nbt, p.K, p.large, cnt,
+                     off, nt, meta + 8);
   ZK_HIP(hipGetLastError());
   scan_exclusive(nt, part_off, nbt, 0, meta + 2, nullptr, ws, S_SCRATCH, st);
-  hipLaunchKernelGGL(k_msm_make_tasks, dim3(cdiv(nbt, 256)), dim3(256), 0, st, counts, offsets, part_off, nbt, p.K,
-                     p.large, meta + 8, th_tasks, wg_tasks);
+  hipLaunchKernelGGL(k_msm_make_tasks, dim3(cdiv(nbt, 256)), dim3(256), 0, st, cnt, off, part_off, nbt, p.K, p.large,
+                     meta + 8, th_tasks, wg_tasks, heavy);
   ZK_HIP(hipGetLastError());
   {
     ProfScope ps(g1 ? "msm_acc_points_g1" : "msm_acc_points_g2", st, -1.0);
     // capped grids with stride loops: the task counts are only known on the device
-    const unsigned th_grid = (unsigned)std::min<uint64_t>(cdiv(p.max_th_tasks, 64), 65536);
-    const unsigned wg_grid = (unsigned)std::min<uint64_t>(p.max_wg_tasks, 8192);
-    hipLaunchKernelGGL(k_msm_acc_points<F>, dim3(th_grid), dim3(64), 0, st, th_tasks, meta + 8, sorted, in.points,
-                       part);
+    const unsigned th_blocks = (unsigned)std::min<uint64_t>(cdiv(p.max_th_tasks, 64), 65536);
+    const unsigned wg_blocks = (unsigned)std::min<uint64_t>(p.max_wg_tasks, 4096);
+    hipLaunchKernelGGL(k_msm_acc<F>, dim3(th_blocks + wg_blocks), dim3(64), 0, st, p.dev, th_tasks, wg_tasks,
+                       meta + 8, th_blocks, sorted, part);
     ZK_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_msm_acc_points_wg<F>, dim3(wg_grid), dim3(WG_THREADS), 0, st, wg_tasks, meta + 9, sorted,
-                       in.points, part);
-    ZK_HIP(hipGetLastError());
-    ps.set_work_from_device(meta + 0);
+    ps.set_work_from_device(offs + p.nh);
   }
-  const uint32_t* cur_cnt = nt;
-  const uint32_t* cur_off = part_off;
-  const uint32_t* cur_part = part;
   {
     ProfScope ps(g1 ? "msm_finalize_g1" : "msm_finalize_g2", st, (double)nbt);
-    hipLaunchKernelGGL(k_msm_finalize<F>, dim3(cdiv(nbt, 64)), dim3(64), 0, st, cur_cnt, cur_off, cur_part, nbt,
-                       buckets);
+    const unsigned light_blocks = cdiv(nbt, 64);
+    const unsigned heavy_blocks = (unsigned)std::min<uint64_t>(nbt, 1024);
+    hipLaunchKernelGGL(k_msm_finalize<F>, dim3(light_blocks + heavy_blocks), dim3(64), 0, st, nt, part_off, part, nbt,
+                       meta + 8, heavy, light_blocks, buckets);
     ZK_HIP(hipGetLastError());
   }
   {
-    ProfScope ps(g1 ? "msm_bitplanes_g1" : "msm_bitplanes_g2", st, (double)nplanes * p.nb / 2);
-    hipLaunchKernelGGL(k_msm_bitplanes<F>, dim3((unsigned)nplanes), dim3(BP_THREADS), 0, st, buckets, p.nb, p.c, win);
+    double adds = 0;
+    for (int k = 0; k < p.dev.njobs; k++) adds += (double)p.dev.job[k].nw * p.dev.job[k].c * p.dev.job[k].nb / 2;
+    ProfScope ps(g1 ? "msm_bitplanes_g1" : "msm_bitplanes_g2", st, adds);
+    hipLaunchKernelGGL(k_msm_bitplanes<F>, dim3((unsigned)p.nplanes), dim3(BP_THREADS), 0, st, p.dev, buckets, win);
     ZK_HIP(hipGetLastError());
   }
-  ZK_HIP(hipMemcpyAsync(win_host, win, nplanes * XW * 4, hipMemcpyDeviceToHost, st));
+  ZK_HIP(hipMemcpyAsync(win_host, win, p.nplanes * XW * 4, hipMemcpyDeviceToHost, st));
 }
 
-// Horner over the windows on the host; call after the MSM's stream has completed.
+// Horner over the bit planes on the host; call after the MSM's stream has completed.
 template <class F>
 typename HostOf<F>::Pt msm_finish(const MsmPending& pend) {
   using HP = typename HostOf<F>::Pt;
@@ -451,16 +623,16 @@ typename HostOf<F>::Pt msm_finish(const MsmPending& pend) {
 template <class F>
 typename HostOf<F>::Pt msm_run(const MsmInput& in, Workspace& ws, hipStream_t st) {
   MsmPending pend;
-  msm_enqueue<F>(in, ws, st, pend);
+  msm_enqueue_batch<F>(&in, 1, ws, st, &pend);
   ZK_HIP(hipStreamSynchronize(st));
   return msm_finish<F>(pend);
 }
 
-void msm_enqueue_g1(const MsmInput& in, Workspace& ws, hipStream_t st, MsmPending& pend) {
-  msm_enqueue<Fq>(in, ws, st, pend);
+void msm_enqueue_batch_g1(const MsmInput* in, int njobs, Workspace& ws, hipStream_t st, MsmPending* pend) {
+  msm_enqueue_batch<Fq>(in, njobs, ws, st, pend);
 }
-void msm_enqueue_g2(const MsmInput& in, Workspace& ws, hipStream_t st, MsmPending& pend) {
-  msm_enqueue<Fq2>(in, ws, st, pend);
+void msm_enqueue_batch_g2(const MsmInput* in, int njobs, Workspace& ws, hipStream_t st, MsmPending* pend) {
+  msm_enqueue_batch<Fq2>(in, njobs, ws, st, pend);
 }
 host::G1J msm_finish_g1(const MsmPending& pend) { return msm_finish<Fq>(pend); }
 host::G2J msm_finish_g2(const MsmPending& pend) { return msm_finish<Fq2>(pend); }

@@ -18,7 +18,10 @@ struct MsmInput {
   int max_bits = 254;                 // bound on |scalar| after sign folding (signed view)
 };
 
-// An MSM enqueued on a stream; its window sums land in pinned host memory.
+// At most this many MSMs share one device pipeline (a batch).
+constexpr int MSM_MAX_JOBS = 8;
+
+// An MSM enqueued on a stream; its bit-plane sums land in pinned host memory.
 struct MsmPending {
   bool empty = true;
   int c = 0, nw = 0;
@@ -26,17 +29,18 @@ struct MsmPending {
   const uint32_t* win_host = nullptr;
 };
 
-// Enqueue the device pipeline of one MSM with no host synchronization; the
-// workspace must not be used by anything else until the stream completes.
-void msm_enqueue_g1(const MsmInput& in, Workspace& ws, hipStream_t st, MsmPending& pend);
-void msm_enqueue_g2(const MsmInput& in, Workspace& ws, hipStream_t st, MsmPending& pend);
-// After the stream has completed: combine the windows (host).
+// Enqueue one device pipeline for njobs MSMs over the same group, with no
+// host synchronization; the workspace must not be used by anything else until
+// the stream completes.  pend[q] receives job q's pending result.
+void msm_enqueue_batch_g1(const MsmInput* in, int njobs, Workspace& ws, hipStream_t st, MsmPending* pend);
+void msm_enqueue_batch_g2(const MsmInput* in, int njobs, Workspace& ws, hipStream_t st, MsmPending* pend);
+// After the stream has completed: combine one job's bit planes (host).
 host::G1J msm_finish_g1(const MsmPending& pend);
 host::G2J msm_finish_g2(const MsmPending& pend);
 
 // Returns sum_j s_j P_idx(j) as a host Jacobian point (enqueue, wait, finish).  The bulk work (digit
-// recoding, counting sort by bucket, bucket accumulation, bucket reduction per
-// window) runs on the device; the host combines the per-window sums.
+// recoding, counting sort by bucket, bucket accumulation, bit-plane reduction)
+// runs on the device; the host combines the plane sums.
 host::G1J msm_g1(const MsmInput& in, Workspace& ws, hipStream_t st);
 host::G2J msm_g2(const MsmInput& in, Workspace& ws, hipStream_t st);
 

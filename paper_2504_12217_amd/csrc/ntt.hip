@@ -36,7 +36,7 @@ constexpr int POW_BITS = NTT_POW_BITS;
 constexpr int MAX_LOG = NTT_MAX_LOG;
 
 struct PassParams {
-  uint32_t* data;
+  uint32_t* data[NTT_MAX_BATCH];  // one vector per blockIdx.y
   int log_n, log_m, k, log_g;
   int dit, inverse, twiddle;
   int first, last;
@@ -67,6 +67,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_pass(PassParams p, NttTable
   const uint32_t gmask = (1u << B) - 1u;
   const uint32_t gamma0 = blockIdx.x * G;
   const int tw_shift = MAX_LOG - p.log_m;
+  uint32_t* const data = p.data[blockIdx.y];
 
   // ---- load (global -> registers -> LDS), with first-pass fusions and DIT twiddles
   for (uint32_t e = threadIdx.x; e < E; e += blockDim.x) {
@@ -81,7 +82,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_pass(PassParams p, NttTable
     const uint32_t gamma = gamma0 + gl;
     const uint32_t g = gamma & gmask;
     const uint32_t addr = ((gamma >> B) << p.log_m) | (t << B) | g;
-    Fr x = Fr::load(p.data + 8ull * addr);
+    Fr x = Fr::load(data + 8ull * addr);
     if (p.first) {
       if (p.pre_mont) x = Fr::to_mont(x);
       if (p.pre_coset) {
@@ -157,7 +158,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_pass(PassParams p, NttTable
       if (p.post_const) x = Fr::mul(x, Fr::load(p.post_const));
       if (p.post_canon) x = Fr::from_mont(x);
     }
-    x.store(p.data + 8ull * addr);
+    x.store(data + 8ull * addr);
   }
 }
 
@@ -294,11 +295,16 @@ const NttTables& ntt_tables(int device) {
   return dt->t;
 }
 
-void ntt_launch(uint32_t* data, int log_n, bool dit, bool inverse, const NttFuse& fuse, hipStream_t st) {
+void ntt_launch_batch(uint32_t* const* data, int nvec, int log_n, bool dit, bool inverse, const NttFuse& fuse,
+                      hipStream_t st) {
   ZK_REQUIRE(log_n >= 0 && log_n <= MAX_LOG, "log_n out of range");
+  ZK_REQUIRE(nvec >= 1 && nvec <= NTT_MAX_BATCH, "NTT batch size out of range");
   const NttTables& T = ntt_tables(current_device());
   const int L = log_n;
-  const int npass = L == 0 ? 1 : (L + NTT_MAX_K - 1) / NTT_MAX_K;
+  // small transforms use 256-element workgroups so that a pass still spreads
+  // over the device; large ones use 1024 (fewer passes over HBM)
+  const int kmax = L <= 18 ? 8 : NTT_MAX_K;
+  const int npass = L == 0 ? 1 : (L + kmax - 1) / kmax;
   std::vector<int> ks(npass);
   for (int j = 0; j < npass; j++) ks[j] = L / npass + (j < L % npass ? 1 : 0);
   // DIF order: top bit range first.  log_m of pass j = L - sum_{i<j} k_i.
@@ -313,11 +319,11 @@ void ntt_launch(uint32_t* data, int log_n, bool dit, bool inverse, const NttFuse
     const int k = ks[j];
     const int B = log_ms[j] - k;
     PassParams p{};
-    p.data = data;
+    for (int v = 0; v < nvec; v++) p.data[v] = data[v];
     p.log_n = L;
     p.log_m = log_ms[j];
     p.k = k;
-    const int max_log_g = NTT_MAX_K - k;
+    const int max_log_g = kmax - k;
     const int log_groups_total = L - k;
     p.log_g = max_log_g < log_groups_total ? max_log_g : log_groups_total;
     p.dit = dit;
@@ -337,10 +343,14 @@ void ntt_launch(uint32_t* data, int log_n, bool dit, bool inverse, const NttFuse
     const size_t lds = (size_t)(1u << (k + p.log_g)) * NL * 4;
     unsigned threads = (1u << (k + p.log_g)) / 2;
     if (threads < 64) threads = 64;
-    ProfScope ps("ntt_pass", st, (double)(1ull << L) * k / 2.0);  // radix-2 butterflies
-    hipLaunchKernelGGL(k_ntt_pass, dim3(grid), dim3(threads), lds, st, p, T);
+    ProfScope ps("ntt_pass", st, (double)nvec * (double)(1ull << L) * k / 2.0);  // radix-2 butterflies
+    hipLaunchKernelGGL(k_ntt_pass, dim3(grid, nvec), dim3(threads), lds, st, p, T);
     ZK_HIP(hipGetLastError());
   }
+}
+
+void ntt_launch(uint32_t* data, int log_n, bool dit, bool inverse, const NttFuse& fuse, hipStream_t st) {
+  ntt_launch_batch(&data, 1, log_n, dit, inverse, fuse, st);
 }
 
 void bitrev_launch(uint32_t* data, int log_n, hipStream_t st) {

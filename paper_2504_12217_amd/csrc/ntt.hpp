@@ -9,6 +9,7 @@ namespace zkvc {
 
 constexpr int NTT_POW_BITS = 14;  // two-level power tables: 2^14 + 2^14 entries
 constexpr int NTT_MAX_LOG = 28;
+constexpr int NTT_MAX_BATCH = 3;  // vectors transformed together by one launch
 
 // Two-level power tables for a fixed base b: b^x = lo[x & 0x3fff] * hi[x >> 14]
 // for x < 2^28, elements in device Montgomery form (8 words each).
@@ -57,6 +58,10 @@ __device__ __forceinline__ uint32_t bitrev_bits(uint32_t a, int bits) {
 //   dit = true : decimation in time, bit-reversed input -> natural-order output
 //   inverse    : use omega^-1 (no 1/N scaling here; pass it as pre/post_const)
 void ntt_launch(uint32_t* data, int log_n, bool dit, bool inverse, const NttFuse& fuse, hipStream_t st);
+// The same transform applied to nvec <= NTT_MAX_BATCH vectors of the same size
+// in one set of launches (more workgroups in flight per pass).
+void ntt_launch_batch(uint32_t* const* data, int nvec, int log_n, bool dit, bool inverse, const NttFuse& fuse,
+                      hipStream_t st);
 
 // In-place bit-reversal permutation of 2^log_n elements.
 void bitrev_launch(uint32_t* data, int log_n, hipStream_t st);

@@ -713,9 +713,10 @@ zkvc_pk* groth16_setup(const Layout& L, const host::HFr toxic[5], const host::HF
 
   for (int lane = 0; lane < zkvc_pk::LANES; lane++) {
     ZK_HIP(hipStreamCreateWithFlags(&pk->lanes[lane], hipStreamNonBlocking));
-    ZK_HIP(hipEventCreateWithFlags(&pk->join_ev[lane], hipEventDisableTiming));
+    ZK_HIP(hipEventCreateWithFlags(&pk->done_ev[lane], hipEventDisableTiming));
   }
-  ZK_HIP(hipEventCreateWithFlags(&pk->fork_ev, hipEventDisableTiming));
+  ZK_HIP(hipEventCreateWithFlags(&pk->witness_ev, hipEventDisableTiming));
+  ZK_HIP(hipEventCreateWithFlags(&pk->quotient_ev, hipEventDisableTiming));
   pk->key_bytes = pk->qA.size() + pk->qB1.size() + pk->qB2.size() + pk->qL.size() + pk->qH.size() + pk->zpow.size();
   pk->ws.clear();  // setup scratch is not needed for proving
   return pk.release();
@@ -745,7 +746,6 @@ struct MsmJob {
   int group;  // 1 = G1, 2 = G2
   int query;  // ZKVC_Q_*
   MsmInput in;
-  MsmPending pend;
 };
 
 std::vector<MsmJob> msm_jobs(const zkvc_pk* pk, const uint32_t* assign, const uint32_t* h_bitrev) {
@@ -832,19 +832,40 @@ void groth16_prove(zkvc_pk* pk, const int8_t* X, const int8_t* W, const host::HF
   ZK_HIP(hipMemcpyAsync(Y, dY, (size_t)a * b * 4, hipMemcpyDeviceToHost, st));
   ZK_HIP(hipEventRecord(ev.e[1], st));
 
+  // ---- MSM jobs.  Those that need only the assignment run on their own
+  // lanes from the end of the witness on, overlapping the quotient: one
+  // batched pipeline for the G1 queries (A, B1, L) and one for B2 in G2.  The
+  // quotient and the H MSM form the critical path and are enqueued first.
+  std::vector<MsmJob> jobs = msm_jobs(pk, assign, aev);
+  std::vector<MsmInput> in_g1, in_g2, in_h;
+  std::vector<int> query_g1;
+  for (const MsmJob& j : jobs) {
+    if (j.query == ZKVC_Q_H) {
+      in_h.push_back(j.in);
+    } else if (j.group == 2) {
+      in_g2.push_back(j.in);
+    } else {
+      in_g1.push_back(j.in);
+      query_g1.push_back(j.query);
+    }
+  }
+  ZK_REQUIRE(in_g1.size() <= (size_t)MSM_MAX_JOBS && in_g2.size() <= (size_t)MSM_MAX_JOBS, "too many query segments");
+  MsmPending pend_g1[MSM_MAX_JOBS], pend_g2[MSM_MAX_JOBS], pend_h[1];
+  ZK_HIP(hipEventRecord(pk->witness_ev, st));
   // ---- QAP quotient h: iNTT (DIF, natural -> bit-reversed coefficients),
   // coset NTT (DIT, bit-reversed -> natural evaluations on g H), pointwise
   // (A B - C)/(g^N - 1), inverse coset NTT (DIF: h in bit-reversed order).
   const int Lg = L.log_n;
-  for (uint32_t* vec : {aev, bev, cev}) {
+  {
+    uint32_t* const vecs[3] = {aev, bev, cev};
     NttFuse f1;
     f1.in_canonical = true;
-    ntt_launch(vec, Lg, false, true, f1, st);
+    ntt_launch_batch(vecs, 3, Lg, false, true, f1, st);
     NttFuse f2;
     f2.pre_coset = 1;
     f2.pre_bitrev = true;
     f2.pre_const = T.ninv + 8 * Lg;
-    ntt_launch(vec, Lg, true, false, f2, st);
+    ntt_launch_batch(vecs, 3, Lg, true, false, f2, st);
   }
   hipLaunchKernelGGL(k_qap_pointwise, dim3(cdiv(N, 256)), dim3(256), 0, st, aev, bev, cev, N,
                      T.coset_zinv + 8 * Lg);
@@ -861,69 +882,54 @@ void groth16_prove(zkvc_pk* pk, const int8_t* X, const int8_t* W, const host::HF
   ZK_HIP(hipMemcpyAsync(top, aev + 8 * (N - 1), 32, hipMemcpyDeviceToHost, st));
   ZK_HIP(hipEventRecord(ev.e[2], st));
 
-  // ---- MSMs: every query segment on its own lane stream, concurrently.
-  // Each job's window sums are combined on a host thread as soon as that job
-  // completes, overlapping the jobs still running on the device.
-  std::vector<MsmJob> jobs = msm_jobs(pk, assign, aev);
-  while (pk->msm_ws.size() < jobs.size()) pk->msm_ws.emplace_back(new Workspace());
-  while (pk->job_ev.size() < jobs.size()) {
-    hipEvent_t e;
-    ZK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    pk->job_ev.push_back(e);
-  }
-  ZK_HIP(hipEventRecord(pk->fork_ev, st));
-  bool used[zkvc_pk::LANES] = {};
-  for (size_t q = 0; q < jobs.size(); q++) {
-    const int lane = (int)(q % zkvc_pk::LANES);
-    if (!used[lane]) ZK_HIP(hipStreamWaitEvent(pk->lanes[lane], pk->fork_ev, 0));
-    used[lane] = true;
-    if (jobs[q].group == 1)
-      msm_enqueue_g1(jobs[q].in, *pk->msm_ws[q], pk->lanes[lane], jobs[q].pend);
-    else
-      msm_enqueue_g2(jobs[q].in, *pk->msm_ws[q], pk->lanes[lane], jobs[q].pend);
-    ZK_HIP(hipEventRecord(pk->job_ev[q], pk->lanes[lane]));
-  }
-  for (int lane = 0; lane < zkvc_pk::LANES; lane++) {
-    if (!used[lane]) continue;
-    ZK_HIP(hipEventRecord(pk->join_ev[lane], pk->lanes[lane]));
-    ZK_HIP(hipStreamWaitEvent(st, pk->join_ev[lane], 0));
-  }
+  // ---- the H MSM follows the quotient on its own lane; then the other
+  // lanes.  Each lane's plane sums are combined on a host thread as soon as
+  // that lane completes, overlapping the lanes still running on the device.
+  ZK_HIP(hipEventRecord(pk->quotient_ev, st));
+  ZK_HIP(hipStreamWaitEvent(pk->lanes[zkvc_pk::LANE_H], pk->quotient_ev, 0));
+  msm_enqueue_batch_g1(in_h.data(), (int)in_h.size(), pk->msm_ws[zkvc_pk::LANE_H], pk->lanes[zkvc_pk::LANE_H], pend_h);
+  ZK_HIP(hipEventRecord(pk->done_ev[zkvc_pk::LANE_H], pk->lanes[zkvc_pk::LANE_H]));
+  for (int lane : {zkvc_pk::LANE_G1, zkvc_pk::LANE_G2}) ZK_HIP(hipStreamWaitEvent(pk->lanes[lane], pk->witness_ev, 0));
+  msm_enqueue_batch_g1(in_g1.data(), (int)in_g1.size(), pk->msm_ws[zkvc_pk::LANE_G1], pk->lanes[zkvc_pk::LANE_G1],
+                       pend_g1);
+  ZK_HIP(hipEventRecord(pk->done_ev[zkvc_pk::LANE_G1], pk->lanes[zkvc_pk::LANE_G1]));
+  msm_enqueue_batch_g2(in_g2.data(), (int)in_g2.size(), pk->msm_ws[zkvc_pk::LANE_G2], pk->lanes[zkvc_pk::LANE_G2],
+                       pend_g2);
+  ZK_HIP(hipEventRecord(pk->done_ev[zkvc_pk::LANE_G2], pk->lanes[zkvc_pk::LANE_G2]));
+
+  for (int lane = 0; lane < zkvc_pk::LANES; lane++) ZK_HIP(hipStreamWaitEvent(st, pk->done_ev[lane], 0));
   ZK_HIP(hipEventRecord(ev.e[3], st));
-  std::vector<std::future<host::G1J>> f1(jobs.size());
-  std::vector<std::future<host::G2J>> f2(jobs.size());
-  for (size_t q = 0; q < jobs.size(); q++) {
-    hipEvent_t done = pk->job_ev[q];
-    const MsmPending pend = jobs[q].pend;
-    if (jobs[q].group == 1)
-      f1[q] = std::async(std::launch::async, [done, pend] {
-        ZK_HIP(hipEventSynchronize(done));
-        return msm_finish_g1(pend);
-      });
-    else
-      f2[q] = std::async(std::launch::async, [done, pend] {
-        ZK_HIP(hipEventSynchronize(done));
-        return msm_finish_g2(pend);
-      });
-  }
+
+  const size_t ng1 = in_g1.size(), ng2 = in_g2.size(), nh = in_h.size();
+  auto finish_g1 = [](hipEvent_t done, const MsmPending* pend, size_t n) {
+    ZK_HIP(hipEventSynchronize(done));
+    std::vector<host::G1J> out(n);
+    for (size_t q = 0; q < n; q++) out[q] = msm_finish_g1(pend[q]);
+    return out;
+  };
+  auto f_g1 = std::async(std::launch::async, finish_g1, pk->done_ev[zkvc_pk::LANE_G1], pend_g1, ng1);
+  auto f_h = std::async(std::launch::async, finish_g1, pk->done_ev[zkvc_pk::LANE_H], pend_h, nh);
+  auto f_g2 = std::async(std::launch::async, [&] {
+    ZK_HIP(hipEventSynchronize(pk->done_ev[zkvc_pk::LANE_G2]));
+    host::G2J acc = host::G2J::inf();
+    for (size_t q = 0; q < ng2; q++) acc = host::G2J::add(acc, msm_finish_g2(pend_g2[q]));
+    return acc;
+  });
   ZK_HIP(hipStreamSynchronize(st));
   for (int q = 0; q < 8; q++)
     if (top[q]) throw Error(ZKVC_EDEVICE, "internal error: the witness does not satisfy the circuit");
   const auto asm_t0 = std::chrono::steady_clock::now();
   host::G1J msmA = host::G1J::inf(), msmB1 = host::G1J::inf(), msmL = host::G1J::inf(), msmH = host::G1J::inf();
-  host::G2J msmB2 = host::G2J::inf();
-  for (size_t q = 0; q < jobs.size(); q++) {
-    if (jobs[q].group == 2) {
-      msmB2 = host::G2J::add(msmB2, f2[q].get());
-      continue;
-    }
-    const host::G1J v = f1[q].get();
-    switch (jobs[q].query) {
-      case ZKVC_Q_A: msmA = host::G1J::add(msmA, v); break;
-      case ZKVC_Q_B1: msmB1 = host::G1J::add(msmB1, v); break;
-      case ZKVC_Q_L: msmL = host::G1J::add(msmL, v); break;
-      default: msmH = host::G1J::add(msmH, v); break;
+  const std::vector<host::G1J> r_g1 = f_g1.get(), r_h = f_h.get();
+  const host::G2J msmB2 = f_g2.get();
+  for (size_t q = 0; q < ng1; q++) {
+    switch (query_g1[q]) {
+      case ZKVC_Q_A: msmA = host::G1J::add(msmA, r_g1[q]); break;
+      case ZKVC_Q_B1: msmB1 = host::G1J::add(msmB1, r_g1[q]); break;
+      default: msmL = host::G1J::add(msmL, r_g1[q]); break;
     }
   }
+  for (size_t q = 0; q < nh; q++) msmH = host::G1J::add(msmH, r_h[q]);
 
   // ---- assembly on the host: blinding multiples of delta from fixed-base
   // tables, s A + r B1 with one shared doubling chain
@@ -958,8 +964,8 @@ zkvc_pk::~zkvc_pk() {
       (void)hipStreamSynchronize(lanes[lane]);
       (void)hipStreamDestroy(lanes[lane]);
     }
-    if (join_ev[lane]) (void)hipEventDestroy(join_ev[lane]);
+    if (done_ev[lane]) (void)hipEventDestroy(done_ev[lane]);
   }
-  if (fork_ev) (void)hipEventDestroy(fork_ev);
-  for (hipEvent_t e : job_ev) (void)hipEventDestroy(e);
+  if (witness_ev) (void)hipEventDestroy(witness_ev);
+  if (quotient_ev) (void)hipEventDestroy(quotient_ev);
 }

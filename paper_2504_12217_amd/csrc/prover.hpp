@@ -45,7 +45,10 @@ bool kind_uses_z(uint32_t kind);
 
 // The opaque proving key of the C ABI.
 struct zkvc_pk {
-  static constexpr int LANES = 6;  // concurrent MSM streams
+  // MSM lanes: the H query (after the quotient), the other G1 queries and the
+  // G2 query (both right after the witness) run concurrently.
+  static constexpr int LANES = 3;
+  enum Lane { LANE_H = 0, LANE_G1 = 1, LANE_G2 = 2 };
   ~zkvc_pk();
   zkvc::Layout L;
   int device = 0;
@@ -58,12 +61,12 @@ struct zkvc_pk {
   zkvc::host::G2J beta2, delta2;
   zkvc::host::FixedBaseTable<zkvc::host::HFq> delta1_table;
   zkvc::host::FixedBaseTable<zkvc::host::HFq2> delta2_table;
-  std::vector<hipEvent_t> job_ev;  // completion of each MSM job
   zkvc::Workspace ws;                  // witness, evaluation vectors, quotient
-  std::vector<std::unique_ptr<zkvc::Workspace>> msm_ws;  // one per MSM job
+  zkvc::Workspace msm_ws[LANES];       // one per lane
   hipStream_t lanes[LANES] = {};
-  hipEvent_t fork_ev = nullptr;
-  hipEvent_t join_ev[LANES] = {};
+  hipEvent_t witness_ev = nullptr;     // assignment complete
+  hipEvent_t quotient_ev = nullptr;    // h complete
+  hipEvent_t done_ev[LANES] = {};      // lane's batch complete
   std::mutex mu;
   zkvc_prove_stats last{};
   size_t key_bytes = 0;
