@@ -39,8 +39,8 @@ MAD_PER_FMUL = 136                   # 8-limb Montgomery product: 64 product + 7
 FMUL_PER_UNIT = {                    # algorithmic Fq/Fr multiplications per counted unit
     "msm_acc_points_g1": 10,         # G1 mixed addition (8M + 2S)
     "msm_acc_points_g2": 30,         # G2 mixed addition over Fq2
-    "msm_acc_partials_g1": 14,       # G1 general addition (12M + 2S)
-    "msm_acc_partials_g2": 42,
+    "msm_bitplanes_g1": 14,          # G1 general addition (12M + 2S)
+    "msm_bitplanes_g2": 42,
     "ntt_pass": 1,                   # radix-2 butterfly
 }
 

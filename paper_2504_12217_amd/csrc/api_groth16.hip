@@ -1,4 +1,5 @@
 // C-ABI entry points for Groth16: setup, prove, verify and proving-key access.
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -78,7 +79,7 @@ int zkvc_pk_info(const zkvc_pk* pk, zkvc_pk_info_t* info) {
   return guarded([&] {
     ZK_REQUIRE(pk && info, "null argument");
     const Layout& L = pk->L;
-    auto total = [](const std::vector<Seg>& v) { return v.empty() ? 0ull : (unsigned long long)(v.back().point_offset + v.back().count); };
+    auto total = [](const std::vector<Seg>& v) { return v.empty() ? 0ull : (unsigned long long)(v.back().index + v.back().count); };
     info->a = L.a;
     info->n = L.n;
     info->b = L.b;
@@ -108,21 +109,27 @@ int zkvc_pk_export(const zkvc_pk* pk, uint32_t query, uint64_t start, uint64_t c
       return;
     }
     const Layout& L = pk->L;
-    auto total = [](const std::vector<Seg>& v) { return v.empty() ? 0ull : (unsigned long long)(v.back().point_offset + v.back().count); };
     const DevBuf* buf = nullptr;
-    uint64_t size = 0;
+    std::vector<Seg> segs;
     switch (query) {
-      case ZKVC_Q_A: buf = &pk->qA; size = total(L.segA); break;
-      case ZKVC_Q_B1: buf = &pk->qB1; size = total(L.segB); break;
-      case ZKVC_Q_B2: buf = &pk->qB2; size = total(L.segB); break;
-      case ZKVC_Q_L: buf = &pk->qL; size = total(L.segL); break;
-      case ZKVC_Q_H: buf = &pk->qH; size = L.N - 1; break;
+      case ZKVC_Q_A: buf = &pk->qA; segs = L.segA; break;
+      case ZKVC_Q_B1: buf = &pk->qB1; segs = L.segB; break;
+      case ZKVC_Q_B2: buf = &pk->qB2; segs = L.segB; break;
+      case ZKVC_Q_L: buf = &pk->qL; segs = L.segL; break;
+      case ZKVC_Q_H: buf = &pk->qH; if (L.segH.count) segs.push_back(L.segH); break;
       default: throw Error(ZKVC_EINVAL, "unknown query");
     }
+    const uint64_t size = segs.empty() ? 0 : segs.back().index + segs.back().count;
     ZK_REQUIRE(start <= size && count <= size - start, "range outside the query");
     const int words = query == ZKVC_Q_B2 ? 32 : 16;
     std::vector<uint32_t> raw(count * words);
-    if (count) ZK_HIP(hipMemcpy(raw.data(), buf->get() + start * words, raw.size() * 4, hipMemcpyDeviceToHost));
+    // query index -> stored point: the first copy of the range holding it
+    for (const Seg& sg : segs) {
+      const uint64_t lo = std::max<uint64_t>(start, sg.index), hi = std::min<uint64_t>(start + count, sg.index + sg.count);
+      if (lo >= hi) continue;
+      ZK_HIP(hipMemcpy(raw.data() + (lo - start) * words, buf->get() + (sg.point_offset + (lo - sg.index)) * words,
+                       (hi - lo) * words * 4, hipMemcpyDeviceToHost));
+    }
     for (uint64_t k = 0; k < count; k++) {
       const uint32_t* p = raw.data() + k * words;
       bool zero = true;

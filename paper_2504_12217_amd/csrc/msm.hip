@@ -42,7 +42,7 @@ constexpr uint32_t WG_TASK_ENTRIES = 256;  // entries per large-bucket (wavefron
 constexpr uint32_t SIGN = 0x80000000u;
 enum MsmSlot {
   S_DIGITS = 100, S_COUNTS, S_OFFSETS, S_HEAVY, S_SORTED, S_TASKS, S_CNT_A, S_CNT_B, S_OFF_A, S_OFF_B,
-  S_PART0, S_PART1, S_SCRATCH, S_SCRATCH2, S_SEG, S_WIN, S_META, S_FB_XYZZ, S_FB_PREFIX, S_UNUSED
+  S_PART0, S_PART1, S_SCRATCH, S_SCRATCH2, S_SEG, S_WIN, S_META, S_FB_XYZZ, S_FB_PREFIX, S_BP_PART
 };
 
 __device__ __forceinline__ uint32_t bitrev_n(uint32_t a, int bits) {
@@ -58,12 +58,17 @@ struct JobDev {
   const uint32_t* scalars;  // Fr elements, 8 words each
   uint32_t n, npoints;
   int mont, bitrev_bits, c, nw;
+  int pre;                  // precomputed windows: window w's digits index the points of copy w
   uint32_t nb;              // buckets per window: 2^(c-1)
+  uint32_t nwb;             // bucket sets: nw, or 1 with precomputed windows
   uint32_t chunk, nch;      // scalars per histogram chunk, number of chunks
+  uint32_t nchw;            // histogram columns per bucket: nch, or nw * nch with precomputed windows
   uint32_t digit_base;      // first digit word (nw * n words, window-major)
-  uint32_t bucket_base;     // first bucket (nw * nb buckets, window-major)
-  uint32_t hist_base;       // first histogram word (nw * nb * nch words)
-  uint32_t plane_base;      // first bit plane (nw * c planes) = first block of the plane grid
+  uint32_t bucket_base;     // first bucket (nwb * nb buckets, window-major)
+  uint32_t hist_base;       // first histogram word (nwb * nb * nchw words)
+  uint32_t plane_base;      // first bit plane (nwb * c planes)
+  uint32_t bpb;             // blocks per bit plane (a power of two)
+  uint32_t blk_bp;          // first block of the bit-plane grid (nwb * c * bpb blocks)
   uint32_t blk_digits;      // first block of the digit grid
   uint32_t blk_hs;          // first block of the histogram / scatter grid (nw * nch blocks)
 };
@@ -157,9 +162,14 @@ __global__ void __launch_bounds__(256) k_msm_digits(BatchDev B, uint32_t* digits
 
 // ---------------------------------------------------------------- 2. counting sort
 // Block (window w, chunk ch) counts its digits per bucket in LDS and writes
-// the counts to hist[(w nb + b) nch + ch].  An exclusive scan of hist then
-// gives every (bucket, chunk) pair its first slot in bucket order, with no
-// global atomics however skewed the digits are.
+// the counts to hist[(w nb + b) nch + ch] (with precomputed windows, all
+// windows share one bucket set: hist[b (nw nch) + w nch + ch]).  An exclusive
+// scan of hist then gives every (bucket, column) pair its first slot in
+// bucket order, with no global atomics however skewed the digits are.
+__device__ __forceinline__ size_t hist_column(const JobDev& J, uint32_t w, uint32_t ch) {
+  return J.pre ? (size_t)J.hist_base + (size_t)w * J.nch + ch
+               : (size_t)J.hist_base + (size_t)w * J.nb * J.nchw + ch;
+}
 __global__ void __launch_bounds__(HS_THREADS) k_msm_hist(BatchDev B, const uint32_t* digits, uint32_t* hist) {
   extern __shared__ uint32_t cnt[];
   const int k = ZK_JOB_OF(B, blk_hs, blockIdx.x);
@@ -175,8 +185,8 @@ __global__ void __launch_bounds__(HS_THREADS) k_msm_hist(BatchDev B, const uint3
     if (v != EMPTY) atomicAdd(&cnt[v & ~SIGN], 1u);
   }
   __syncthreads();
-  uint32_t* h = hist + J.hist_base + (size_t)w * J.nb * J.nch + ch;
-  for (uint32_t b = threadIdx.x; b < J.nb; b += HS_THREADS) h[(size_t)b * J.nch] = cnt[b];
+  uint32_t* h = hist + hist_column(J, w, ch);
+  for (uint32_t b = threadIdx.x; b < J.nb; b += HS_THREADS) h[(size_t)b * J.nchw] = cnt[b];
 }
 
 // Same blocks as k_msm_hist: LDS cursors start at the scanned offsets and
@@ -189,8 +199,9 @@ __global__ void __launch_bounds__(HS_THREADS) k_msm_scatter(BatchDev B, const ui
   const JobDev& J = B.job[k];
   const uint32_t local = blockIdx.x - J.blk_hs;
   const uint32_t w = local / J.nch, ch = local % J.nch;
-  const uint32_t* o = offs + J.hist_base + (size_t)w * J.nb * J.nch + ch;
-  for (uint32_t b = threadIdx.x; b < J.nb; b += HS_THREADS) cur[b] = o[(size_t)b * J.nch];
+  const uint32_t* o = offs + hist_column(J, w, ch);
+  for (uint32_t b = threadIdx.x; b < J.nb; b += HS_THREADS) cur[b] = o[(size_t)b * J.nchw];
+  const uint32_t pbase = J.pre ? w * J.npoints : 0u;
   __syncthreads();
   const uint32_t* d = digits + J.digit_base + (size_t)w * J.n;
   const uint32_t lo = ch * J.chunk, hi = min(J.n, lo + J.chunk);
@@ -199,7 +210,7 @@ __global__ void __launch_bounds__(HS_THREADS) k_msm_scatter(BatchDev B, const ui
     if (v == EMPTY) continue;
     const uint32_t pos = atomicAdd(&cur[v & ~SIGN], 1u);
     const uint32_t idx = J.bitrev_bits ? bitrev_n(i, J.bitrev_bits) : i;
-    sorted[pos] = idx | (v & SIGN);
+    sorted[pos] = (pbase + idx) | (v & SIGN);
   }
 }
 
@@ -222,8 +233,8 @@ __global__ void k_msm_task_counts(BatchDev B, const uint32_t* offs, uint32_t nbt
   const JobDev& J = B.job[k];
   const size_t lf = f - J.bucket_base;
   // the bucket after the job's last one starts the next job's range (or the total)
-  const uint32_t s = offs[J.hist_base + lf * J.nch];
-  const uint32_t e = offs[J.hist_base + (lf + 1) * J.nch];
+  const uint32_t s = offs[J.hist_base + lf * J.nchw];
+  const uint32_t e = offs[J.hist_base + (lf + 1) * J.nchw];
   const uint32_t c = e - s;
   cnt[f] = c;
   off[f] = s;
@@ -297,11 +308,19 @@ __global__ void __launch_bounds__(64) k_msm_acc(BatchDev B, const uint4* th_task
       const uint4 task = th_tasks[t];
       const uint32_t* points = B.job[ZK_JOB_OF(B, bucket_base, task.w)].points;
       Xyzz<F> acc = Xyzz<F>::inf();
-      for (uint32_t e = task.x; e < task.x + task.y; e++) {
-        const uint32_t ref = sorted[e];
-        Affine<F> pt = PointIO<F>::load_affine(points + (size_t)(ref & ~SIGN) * AW);
-        if (ref & SIGN) pt.y = F::neg(pt.y);
-        acc = Xyzz<F>::madd(acc, pt);
+      // the next entry's point is loaded while the current one is added
+      const uint32_t end = task.x + task.y;
+      uint32_t ref = sorted[task.x];
+      Affine<F> pt = PointIO<F>::load_affine(points + (size_t)(ref & ~SIGN) * AW);
+      for (uint32_t e = task.x; e < end; e++) {
+        Affine<F> cur = pt;
+        const uint32_t cref = ref;
+        if (e + 1 < end) {
+          ref = sorted[e + 1];
+          pt = PointIO<F>::load_affine(points + (size_t)(ref & ~SIGN) * AW);
+        }
+        if (cref & SIGN) cur.y = F::neg(cur.y);
+        acc = Xyzz<F>::madd(acc, cur);
       }
       PointIO<F>::store_xyzz(partials + (size_t)task.z * XW, acc);
     }
@@ -372,32 +391,59 @@ __global__ void __launch_bounds__(64) k_msm_finalize(const uint32_t* nt, const u
 // For window w and bit j,
 //   S[w c + j] = sum of B_b over the buckets whose digit value b + 1 has bit j set,
 // so that window w contributes sum_j 2^j S[w c + j] = sum_b (b + 1) B_b.
-// One block per plane; each thread sums a strided share, then an LDS tree.
+// A plane is split over bpb blocks; each thread sums a strided share of its
+// block's slice, an LDS tree sums the block, and k_msm_plane_sums adds the
+// bpb block sums of each plane.
 template <class F>
-__global__ void __launch_bounds__(BP_THREADS) k_msm_bitplanes(BatchDev B, const uint32_t* buckets, uint32_t* S) {
+__device__ __forceinline__ Xyzz<F> block_tree_sum(Xyzz<F> acc, uint32_t* sh, int nthreads) {
+  constexpr int XW = PointIO<F>::XYZZ_WORDS;
+  for (int o = nthreads / 2; o >= 1; o >>= 1) {
+    if ((int)threadIdx.x >= o && (int)threadIdx.x < 2 * o) PointIO<F>::store_xyzz(sh + (threadIdx.x - o) * XW, acc);
+    __syncthreads();
+    if ((int)threadIdx.x < o) acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(sh + threadIdx.x * XW));
+    __syncthreads();
+  }
+  return acc;
+}
+
+template <class F>
+__global__ void __launch_bounds__(BP_THREADS) k_msm_bitplanes(BatchDev B, const uint32_t* buckets, uint32_t* part) {
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
   __shared__ uint32_t sh[BP_THREADS / 2 * XW];
-  const int k = ZK_JOB_OF(B, plane_base, blockIdx.x);
+  const int k = ZK_JOB_OF(B, blk_bp, blockIdx.x);
   const JobDev& J = B.job[k];
-  const uint32_t q = blockIdx.x - J.plane_base;
+  const uint32_t local = blockIdx.x - J.blk_bp;
+  const uint32_t q = local / J.bpb, slice = local % J.bpb;
   const uint32_t c = (uint32_t)J.c, nb = J.nb;
   const uint32_t w = q / c, j = q % c;
   const uint32_t* bw = buckets + ((size_t)J.bucket_base + (size_t)w * nb) * XW;
   // digit values v in [1, nb] with bit j set: v = ((t >> j) << (j + 1)) | 2^j | (t & (2^j - 1))
   const uint32_t jmask = (1u << j) - 1u;
   const uint32_t count = (j + 1 < c) ? nb / 2 : 1u;  // bit c-1 is set only in v = nb
+  const uint32_t per = (count + J.bpb - 1) / J.bpb;
+  const uint32_t t0 = slice * per, t1 = min(count, t0 + per);
   Xyzz<F> acc = Xyzz<F>::inf();
-  for (uint32_t t = threadIdx.x; t < count; t += BP_THREADS) {
+  for (uint32_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
     const uint32_t v = ((t >> j) << (j + 1)) | (1u << j) | (t & jmask);
     if (v > nb) continue;
     acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(bw + (size_t)(v - 1) * XW));
   }
-  for (int o = BP_THREADS / 2; o >= 1; o >>= 1) {
-    if ((int)threadIdx.x >= o && (int)threadIdx.x < 2 * o) PointIO<F>::store_xyzz(sh + (threadIdx.x - o) * XW, acc);
-    __syncthreads();
-    if ((int)threadIdx.x < o) acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(sh + threadIdx.x * XW));
-    __syncthreads();
-  }
+  acc = block_tree_sum<F>(acc, sh, (int)blockDim.x);
+  if (threadIdx.x == 0) PointIO<F>::store_xyzz(part + (size_t)blockIdx.x * XW, acc);
+}
+
+// One wavefront per plane: the sum of the plane's bpb block sums.
+template <class F>
+__global__ void __launch_bounds__(64) k_msm_plane_sums(BatchDev B, const uint32_t* part, uint32_t* S) {
+  constexpr int XW = PointIO<F>::XYZZ_WORDS;
+  __shared__ uint32_t sh[32 * XW];
+  const int k = ZK_JOB_OF(B, plane_base, blockIdx.x);
+  const JobDev& J = B.job[k];
+  const uint32_t q = blockIdx.x - J.plane_base;
+  const uint32_t* pp = part + ((size_t)J.blk_bp + (size_t)q * J.bpb) * XW;
+  Xyzz<F> acc = Xyzz<F>::inf();
+  for (uint32_t t = threadIdx.x; t < J.bpb; t += 64) acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(pp + (size_t)t * XW));
+  acc = block_tree_sum<F>(acc, sh, 64);
   if (threadIdx.x == 0) PointIO<F>::store_xyzz(S + (size_t)blockIdx.x * XW, acc);
 }
 
@@ -412,6 +458,33 @@ void msm_choose_window(size_t n, int bits, int* c_out, int* nw_out) {
     // mixed additions for the entries, a pass over every bucket, and the
     // bit-plane reduction (c nb / 2 full additions per window, ~1.4 mixed each)
     const double cost = (double)n * nw + 0.5 * nw * nb + 1.4 * nw * c * nb / 2;
+    if (cost < best) {
+      best = cost;
+      bc = c;
+      bnw = nw;
+    }
+  }
+  *c_out = bc;
+  *nw_out = bnw;
+}
+
+void msm_choose_precomputed(size_t n, int bits, int max_copies, int* c_out, int* nw_out) {
+  if (bits < 1) bits = 1;
+  int c0, nw0;
+  msm_choose_window(n, bits, &c0, &nw0);
+  double best = (double)n * nw0 + 0.5 * nw0 * (double)(1u << (c0 - 1)) + 1.4 * nw0 * c0 * (double)(1u << (c0 - 1)) / 2;
+  int bc = c0, bnw = 1;
+  if (nw0 == 1) {
+    *c_out = c0;
+    *nw_out = 1;
+    return;
+  }
+  for (int c = 2; c <= MAX_C; c++) {
+    const int nw = (bits + 1 + c - 1) / c;
+    if (nw > max_copies) continue;
+    const double nb = (double)(1u << (c - 1));
+    // one bucket set: entries, a pass over the buckets, one bit-plane reduction
+    const double cost = (double)n * nw + 0.5 * nb + 1.4 * c * nb / 2;
     if (cost < best) {
       best = cost;
       bc = c;
@@ -446,7 +519,7 @@ void hfq2_to_dev(const host::HFq2& a, uint32_t* w) {
 struct BatchPlan {
   BatchDev dev{};
   int map[MSM_MAX_JOBS] = {};  // device job -> caller's job
-  uint64_t ndigits = 0, nbt = 0, nh = 0, nplanes = 0, digit_blocks = 0, hs_blocks = 0;
+  uint64_t ndigits = 0, nbt = 0, nh = 0, nplanes = 0, digit_blocks = 0, hs_blocks = 0, bp_blocks = 0;
   uint32_t max_nb = 0;
   uint32_t K = 0;      // entries per thread task
   uint32_t large = 0;  // buckets with at least this many entries get wavefront tasks
@@ -465,24 +538,41 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs) {
     J.npoints = (uint32_t)in[q].npoints;
     J.mont = in[q].scalars_mont ? 1 : 0;
     J.bitrev_bits = in[q].point_index_bitrev;
-    msm_choose_window(J.n, in[q].max_bits, &J.c, &J.nw);
+    if (in[q].pre_c > 0) {
+      ZK_REQUIRE(in[q].pre_c >= 2 && in[q].pre_c <= MAX_C && in[q].pre_nw >= 1 &&
+                     in[q].pre_c * in[q].pre_nw >= in[q].max_bits + 1 &&
+                     (uint64_t)in[q].npoints * in[q].pre_nw < (1ull << 31),
+                 "invalid precomputed MSM windows");
+      J.c = in[q].pre_c;
+      J.nw = in[q].pre_nw;
+      J.pre = 1;
+    } else {
+      msm_choose_window(J.n, in[q].max_bits, &J.c, &J.nw);
+      J.pre = 0;
+    }
     J.nb = 1u << (J.c - 1);
+    J.nwb = J.pre ? 1u : (uint32_t)J.nw;
     // chunks of >= 4096 scalars, at most 2^22 histogram words per job
     const uint64_t wb = (uint64_t)J.nw * J.nb;
     uint64_t nch = std::max<uint64_t>(1, std::min<uint64_t>((J.n + 4095) / 4096, (1ull << 22) / wb));
     const uint64_t chunk = ((J.n + nch - 1) / nch + 255) / 256 * 256;
     J.chunk = (uint32_t)chunk;
     J.nch = (uint32_t)((J.n + chunk - 1) / chunk);
+    J.nchw = J.pre ? J.nch * (uint32_t)J.nw : J.nch;
     J.digit_base = (uint32_t)p.ndigits;
     J.bucket_base = (uint32_t)p.nbt;
     J.hist_base = (uint32_t)p.nh;
     J.plane_base = (uint32_t)p.nplanes;
+    // about two bucket additions per thread before each block's tree
+    J.bpb = std::max<uint32_t>(1, J.nb / 2 / (2 * BP_THREADS));
+    J.blk_bp = (uint32_t)p.bp_blocks;
     J.blk_digits = (uint32_t)p.digit_blocks;
     J.blk_hs = (uint32_t)p.hs_blocks;
     p.ndigits += (uint64_t)J.nw * J.n;
-    p.nbt += wb;
+    p.nbt += (uint64_t)J.nwb * J.nb;
     p.nh += wb * J.nch;
-    p.nplanes += (uint64_t)J.nw * J.c;
+    p.nplanes += (uint64_t)J.nwb * J.c;
+    p.bp_blocks += (uint64_t)J.nwb * J.c * J.bpb;
     p.digit_blocks += cdiv(J.n, 256);
     p.hs_blocks += (uint64_t)J.nw * J.nch;
     p.max_nb = std::max(p.max_nb, J.nb);
@@ -532,6 +622,7 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
   uint32_t* part = ws.get(S_PART0, p.max_partials * XW * 4);
   uint32_t* buckets = ws.get(S_SEG, p.nbt * XW * 4);
   uint32_t* win = ws.get(S_WIN, p.nplanes * XW * 4);
+  uint32_t* bp_part = ws.get(S_BP_PART, p.bp_blocks * XW * 4);
   uint32_t* heavy = ws.get(S_HEAVY, p.nbt * 4);
   uint32_t* meta = ws.get(S_META, 64 * 4);  // [2] partials [8..10] thread tasks, wavefront tasks, heavy buckets
   uint32_t* win_host = ws.host<uint32_t>(S_WIN, p.nplanes * XW * 4);
@@ -540,7 +631,7 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
     MsmPending& pd = pend[p.map[k]];
     pd.empty = false;
     pd.c = p.dev.job[k].c;
-    pd.nw = p.dev.job[k].nw;
+    pd.nw = (int)p.dev.job[k].nwb;
     pd.win_host = win_host + (size_t)p.dev.job[k].plane_base * XW;
   }
   const size_t lds = (size_t)p.max_nb * 4;
@@ -587,9 +678,18 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
   }
   {
     double adds = 0;
-    for (int k = 0; k < p.dev.njobs; k++) adds += (double)p.dev.job[k].nw * p.dev.job[k].c * p.dev.job[k].nb / 2;
+    for (int k = 0; k < p.dev.njobs; k++) adds += (double)p.dev.job[k].nwb * p.dev.job[k].c * p.dev.job[k].nb / 2;
     ProfScope ps(g1 ? "msm_bitplanes_g1" : "msm_bitplanes_g2", st, adds);
-    hipLaunchKernelGGL(k_msm_bitplanes<F>, dim3((unsigned)p.nplanes), dim3(BP_THREADS), 0, st, p.dev, buckets, win);
+    // block size: about two bucket additions per thread (64 to BP_THREADS threads)
+    uint32_t per_block = 1;
+    for (int k = 0; k < p.dev.njobs; k++)
+      per_block = std::max(per_block, (p.dev.job[k].nb / 2 + p.dev.job[k].bpb - 1) / p.dev.job[k].bpb);
+    unsigned bp_threads = 64;
+    while (bp_threads < (unsigned)BP_THREADS && bp_threads * 2 < per_block) bp_threads *= 2;
+    hipLaunchKernelGGL(k_msm_bitplanes<F>, dim3((unsigned)p.bp_blocks), dim3(bp_threads), 0, st, p.dev, buckets,
+                       bp_part);
+    ZK_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_msm_plane_sums<F>, dim3((unsigned)p.nplanes), dim3(64), 0, st, p.dev, bp_part, win);
     ZK_HIP(hipGetLastError());
   }
   ZK_HIP(hipMemcpyAsync(win_host, win, p.nplanes * XW * 4, hipMemcpyDeviceToHost, st));

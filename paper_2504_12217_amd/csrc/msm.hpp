@@ -15,7 +15,12 @@ struct MsmInput {
   size_t nscalars = 0;
   bool scalars_mont = false;          // scalars in device Montgomery form
   int point_index_bitrev = 0;         // if > 0: scalar j pairs with point bitrev_{bits}(j)
-  int max_bits = 254;                 // bound on |scalar| after sign folding (signed view)
+  int max_bits = 254;                 // |s| <= 2^max_bits after sign folding (s > (r-1)/2 -> s - r)
+  // Precomputed windows: if pre_c > 0, points holds pre_nw arrays of npoints
+  // points each (window-major), window w holding 2^(pre_c w) P_i; the MSM then
+  // uses that window width and one set of buckets for all windows.
+  int pre_c = 0;
+  int pre_nw = 0;
 };
 
 // At most this many MSMs share one device pipeline (a batch).
@@ -47,6 +52,9 @@ host::G2J msm_g2(const MsmInput& in, Workspace& ws, hipStream_t st);
 // Pick the window width c and the number of signed windows for n terms with
 // scalars of at most `bits` bits (after folding s > (r-1)/2 to -(r - s)).
 void msm_choose_window(size_t n, int bits, int* c, int* nw);
+// The same for fixed points with precomputed windows (nw copies of the
+// points, at most max_copies); returns nw = 1 when precomputation does not pay.
+void msm_choose_precomputed(size_t n, int bits, int max_copies, int* c, int* nw);
 
 // Fixed-base batch multiplication by the standard generator: out_j = [k_j] G,
 // written affine (device Montgomery layout unless out_canonical).

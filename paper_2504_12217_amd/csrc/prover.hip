@@ -23,6 +23,7 @@
 // Y(z) = sum_ij z^(i b + j) y_ij (Section III-A's identity at Z = z).
 #include "prover.hpp"
 
+#include <array>
 #include <chrono>
 #include <future>
 #include <cstring>
@@ -58,8 +59,8 @@ Layout r1cs_layout(uint32_t a, uint32_t n, uint32_t b, uint32_t kind) {
   L.ell = (uint64_t)a * n + (uint64_t)a * b;
   const uint64_t ab = (uint64_t)a * b;
   switch (kind) {
-    case ZKVC_PLAIN: L.m = ab * n; L.naux = ab * (n - 1); L.aux_bits = 15; break;
-    case ZKVC_PLAIN_ADD: L.m = ab * (n + 1); L.naux = ab * n; L.aux_bits = 15; break;
+    case ZKVC_PLAIN: L.m = ab * n; L.naux = ab * (n - 1); L.aux_bits = 14; break;     // |x w| <= 2^14
+    case ZKVC_PLAIN_ADD: L.m = ab * (n + 1); L.naux = ab * n; L.aux_bits = 14; break;
     case ZKVC_PLAIN_PSQ: L.m = ab * n; L.naux = ab * (n - 1); L.aux_bits = bitlen((uint64_t)(n > 1 ? n - 1 : 1) * 16384); break;
     case ZKVC_CRPC_PSQ: L.m = n; L.naux = n - 1; L.aux_bits = 253; break;
     default: L.m = n + 1; L.naux = n; L.aux_bits = 253; break;
@@ -75,25 +76,45 @@ Layout r1cs_layout(uint32_t a, uint32_t n, uint32_t b, uint32_t kind) {
   ZK_REQUIRE(L.nv < (1ull << 31), "too many variables");
   L.N = 1ull << L.log_n;
   const bool aux_in_a = kind == ZKVC_PLAIN_ADD || kind == ZKVC_CRPC;
-  auto push = [](std::vector<Seg>& v, uint64_t start, uint64_t count, int bits) {
+  // G1 ranges with wide scalars store precomputed windows while all copies
+  // stay within 256 MiB (the gathers then stay cache-friendly; larger tables
+  // turn the random point reads into HBM and TLB misses)
+  auto precompute = [](Seg& s) {
+    const int max_copies = (int)std::min<uint64_t>(32, (256ull << 20) / (64ull * std::max<uint64_t>(s.count, 1)));
+    int c = 0, nw = 1;
+    if (max_copies >= 2) msm_choose_precomputed(s.count, s.bits, max_copies, &c, &nw);
+    if (nw > 1) {
+      s.pre_c = c;
+      s.pre_nw = nw;
+    }
+  };
+  auto push = [&](std::vector<Seg>& v, uint64_t start, uint64_t count, int bits, bool pre) {
     if (!count) return;
     Seg s;
     s.var_start = start;
     s.count = count;
     s.bits = bits;
-    s.point_offset = v.empty() ? 0 : v.back().point_offset + v.back().count;
+    s.index = v.empty() ? 0 : v.back().index + v.back().count;
+    s.point_offset = v.empty() ? 0 : v.back().point_offset + v.back().count * v.back().pre_nw;
+    if (pre) precompute(s);
     v.push_back(s);
   };
-  push(L.segA, 0, L.ell + 1, L.y_bits);
-  if (aux_in_a) push(L.segA, L.aux_start, L.naux, L.aux_bits);
-  push(L.segB, L.w_start, (uint64_t)n * b, 8);
-  if (aux_in_a) push(L.segB, 0, 1, 1);
-  push(L.segL, L.w_start, (uint64_t)n * b, 8);
-  push(L.segL, L.aux_start, L.naux, L.aux_bits);
+  push(L.segA, 0, L.ell + 1, L.y_bits, true);
+  if (aux_in_a) push(L.segA, L.aux_start, L.naux, L.aux_bits, true);
+  push(L.segB, L.w_start, (uint64_t)n * b, 7, false);  // |w| <= 2^7
+  if (aux_in_a) push(L.segB, 0, 1, 1, false);
+  push(L.segL, L.w_start, (uint64_t)n * b, 7, true);
+  push(L.segL, L.aux_start, L.naux, L.aux_bits, true);
+  L.segH.count = L.N - 1;
+  L.segH.bits = 253;
+  if (L.segH.count) precompute(L.segH);
   return L;
 }
 
-static uint64_t seg_total(const std::vector<Seg>& v) { return v.empty() ? 0 : v.back().point_offset + v.back().count; }
+// stored points of a query (every precomputed copy included)
+static uint64_t seg_total(const std::vector<Seg>& v) {
+  return v.empty() ? 0 : v.back().point_offset + v.back().count * v.back().pre_nw;
+}
 
 // ------------------------------------------------------------------ device helpers
 // Canonical words of a small signed integer: v >= 0 -> v, v < 0 -> r - |v|.
@@ -260,6 +281,13 @@ __global__ void k_lin(const uint32_t* u, const uint32_t* v, const uint32_t* w, u
   Fr s = Fr::add(Fr::add(Fr::mul(beta, Fr::load(u + 8ull * i)), Fr::mul(alpha, Fr::load(v + 8ull * i))),
                  Fr::load(w + 8ull * i));
   Fr::mul(s, f).store(out + 8ull * j);
+}
+
+// out_j = in_j * f (Montgomery form): the scalars of a precomputed window copy.
+__global__ void k_scale_fr(const uint32_t* in, uint32_t n, const uint32_t* f, uint32_t* out) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  Fr::mul(Fr::load(in + 8ull * j), Fr::load(f)).store(out + 8ull * j);
 }
 
 constexpr int H_CHUNK = 32;
@@ -630,9 +658,33 @@ zkvc_pk* groth16_setup(const Layout& L, const host::HFr toxic[5], const host::HF
   pk->qB1.alloc(std::max<uint64_t>(nB, 1) * 64);
   pk->qB2.alloc(std::max<uint64_t>(nB, 1) * 128);
   pk->qL.alloc(std::max<uint64_t>(nL, 1) * 64);
-  pk->qH.alloc((N - 1 ? N - 1 : 1) * 64);
-  for (const Seg& s : L.segA)
-    fixed_base_g1(u + 8 * s.var_start, true, s.count, pk->qA.get() + 16 * s.point_offset, false, ws, st);
+  pk->qH.alloc(std::max<uint64_t>(L.segH.count * L.segH.pre_nw, 1) * 64);
+  uint64_t maxseg = L.ell + 1;
+  for (const Seg& s : L.segL) maxseg = std::max(maxseg, s.count);
+  maxseg = std::max(maxseg, N);
+  uint32_t* sc = ws.get(9, maxseg * 32);
+  uint32_t* scaled = ws.get(12, maxseg * 32);
+  // a G1 range and its precomputed copies: copy w from the scalars times 2^(c w)
+  auto emit_g1 = [&](const uint32_t* sc_mont, const Seg& s, uint32_t* qbase) {
+    fixed_base_g1(sc_mont, true, s.count, qbase + 16 * s.point_offset, false, ws, st);
+    if (s.pre_nw <= 1) return;
+    std::vector<uint32_t> fw(8 * s.pre_nw);
+    const HFr step = HFr::pow(HFr::from_uint(2), std::array<uint64_t, 4>{(uint64_t)s.pre_c, 0, 0, 0}.data());
+    HFr f = HFr::one();
+    for (int w = 0; w < s.pre_nw; w++) {
+      f.to_dev(&fw[8 * w]);
+      f = HFr::mul(f, step);
+    }
+    uint32_t* dfw = ws.get(13, fw.size() * 4);
+    upload_words(dfw, fw, st);
+    for (int w = 1; w < s.pre_nw; w++) {
+      hipLaunchKernelGGL(k_scale_fr, dim3(cdiv(s.count, 256)), dim3(256), 0, st, sc_mont, (uint32_t)s.count,
+                         dfw + 8 * w, scaled);
+      ZK_HIP(hipGetLastError());
+      fixed_base_g1(scaled, true, s.count, qbase + 16 * (s.point_offset + (uint64_t)w * s.count), false, ws, st);
+    }
+  };
+  for (const Seg& s : L.segA) emit_g1(u + 8 * s.var_start, s, pk->qA.get());
   for (const Seg& s : L.segB) {
     fixed_base_g1(v + 8 * s.var_start, true, s.count, pk->qB1.get() + 16 * s.point_offset, false, ws, st);
     fixed_base_g2(v + 8 * s.var_start, true, s.count, pk->qB2.get() + 32 * s.point_offset, false, ws, st);
@@ -644,15 +696,11 @@ zkvc_pk* groth16_setup(const Layout& L, const host::HFr toxic[5], const host::HF
   HFr::inv(delta).to_dev(&lc[16]);
   uint32_t* dlc = ws.get(8, lc.size() * 4);
   upload_words(dlc, lc, st);
-  uint64_t maxseg = L.ell + 1;
-  for (const Seg& s : L.segL) maxseg = std::max(maxseg, s.count);
-  maxseg = std::max(maxseg, N);
-  uint32_t* sc = ws.get(9, maxseg * 32);
   for (const Seg& s : L.segL) {
     hipLaunchKernelGGL(k_lin, dim3(cdiv(s.count, 128)), dim3(128), 0, st, u, v, w, s.var_start, (uint32_t)s.count,
                        dlc, sc);
     ZK_HIP(hipGetLastError());
-    fixed_base_g1(sc, true, s.count, pk->qL.get() + 16 * s.point_offset, false, ws, st);
+    emit_g1(sc, s, pk->qL.get());
   }
   // H query: tau^j (tau^N - 1) / delta, j < N - 1
   if (N > 1) {
@@ -664,7 +712,7 @@ zkvc_pk* groth16_setup(const Layout& L, const host::HFr toxic[5], const host::HF
     const uint32_t cnt = (uint32_t)(N - 1);
     hipLaunchKernelGGL(k_h_scalars, dim3(cdiv(cdiv(cnt, H_CHUNK), 128)), dim3(128), 0, st, cnt, dhc, sc);
     ZK_HIP(hipGetLastError());
-    fixed_base_g1(sc, true, cnt, pk->qH.get(), false, ws, st);
+    emit_g1(sc, L.segH, pk->qH.get());
   }
   // IC for the verification key: (beta u + alpha v + w) / gamma over 0..l
   HFr::inv(gamma).to_dev(&lc[16]);
@@ -760,6 +808,10 @@ std::vector<MsmJob> msm_jobs(const zkvc_pk* pk, const uint32_t* assign, const ui
     j.in.scalars = assign + 8 * s.var_start;
     j.in.nscalars = s.count;
     j.in.max_bits = s.bits;
+    if (s.pre_nw > 1) {
+      j.in.pre_c = s.pre_c;
+      j.in.pre_nw = s.pre_nw;
+    }
     jobs.push_back(j);
   };
   if (L.N > 1) {  // H first: the largest
@@ -772,7 +824,11 @@ std::vector<MsmJob> msm_jobs(const zkvc_pk* pk, const uint32_t* assign, const ui
     j.in.nscalars = L.N;
     j.in.scalars_mont = true;
     j.in.point_index_bitrev = L.log_n;
-    j.in.max_bits = 253;
+    j.in.max_bits = L.segH.bits;
+    if (L.segH.pre_nw > 1) {
+      j.in.pre_c = L.segH.pre_c;
+      j.in.pre_nw = L.segH.pre_nw;
+    }
     jobs.push_back(j);
   }
   for (const Seg& s : L.segL) add(1, ZKVC_Q_L, pk->qL.get(), s);
@@ -834,8 +890,8 @@ void groth16_prove(zkvc_pk* pk, const int8_t* X, const int8_t* W, const host::HF
 
   // ---- MSM jobs.  Those that need only the assignment run on their own
   // lanes from the end of the witness on, overlapping the quotient: one
-  // batched pipeline for the G1 queries (A, B1, L) and one for B2 in G2.  The
-  // quotient and the H MSM form the critical path and are enqueued first.
+  // batched pipeline for the G1 queries (A, B1, L) and one for B2 in G2.  B2,
+  // then the quotient and the H MSM (the critical path) are enqueued first.
   std::vector<MsmJob> jobs = msm_jobs(pk, assign, aev);
   std::vector<MsmInput> in_g1, in_g2, in_h;
   std::vector<int> query_g1;
@@ -852,6 +908,12 @@ void groth16_prove(zkvc_pk* pk, const int8_t* X, const int8_t* W, const host::HF
   ZK_REQUIRE(in_g1.size() <= (size_t)MSM_MAX_JOBS && in_g2.size() <= (size_t)MSM_MAX_JOBS, "too many query segments");
   MsmPending pend_g1[MSM_MAX_JOBS], pend_g2[MSM_MAX_JOBS], pend_h[1];
   ZK_HIP(hipEventRecord(pk->witness_ev, st));
+  // B2 (G2, the longest chain of dependent group operations) goes first
+  ZK_HIP(hipStreamWaitEvent(pk->lanes[zkvc_pk::LANE_G2], pk->witness_ev, 0));
+  msm_enqueue_batch_g2(in_g2.data(), (int)in_g2.size(), pk->msm_ws[zkvc_pk::LANE_G2], pk->lanes[zkvc_pk::LANE_G2],
+                       pend_g2);
+  ZK_HIP(hipEventRecord(pk->done_ev[zkvc_pk::LANE_G2], pk->lanes[zkvc_pk::LANE_G2]));
+
   // ---- QAP quotient h: iNTT (DIF, natural -> bit-reversed coefficients),
   // coset NTT (DIT, bit-reversed -> natural evaluations on g H), pointwise
   // (A B - C)/(g^N - 1), inverse coset NTT (DIF: h in bit-reversed order).
@@ -889,61 +951,66 @@ void groth16_prove(zkvc_pk* pk, const int8_t* X, const int8_t* W, const host::HF
   ZK_HIP(hipStreamWaitEvent(pk->lanes[zkvc_pk::LANE_H], pk->quotient_ev, 0));
   msm_enqueue_batch_g1(in_h.data(), (int)in_h.size(), pk->msm_ws[zkvc_pk::LANE_H], pk->lanes[zkvc_pk::LANE_H], pend_h);
   ZK_HIP(hipEventRecord(pk->done_ev[zkvc_pk::LANE_H], pk->lanes[zkvc_pk::LANE_H]));
-  for (int lane : {zkvc_pk::LANE_G1, zkvc_pk::LANE_G2}) ZK_HIP(hipStreamWaitEvent(pk->lanes[lane], pk->witness_ev, 0));
+  ZK_HIP(hipStreamWaitEvent(pk->lanes[zkvc_pk::LANE_G1], pk->witness_ev, 0));
   msm_enqueue_batch_g1(in_g1.data(), (int)in_g1.size(), pk->msm_ws[zkvc_pk::LANE_G1], pk->lanes[zkvc_pk::LANE_G1],
                        pend_g1);
   ZK_HIP(hipEventRecord(pk->done_ev[zkvc_pk::LANE_G1], pk->lanes[zkvc_pk::LANE_G1]));
-  msm_enqueue_batch_g2(in_g2.data(), (int)in_g2.size(), pk->msm_ws[zkvc_pk::LANE_G2], pk->lanes[zkvc_pk::LANE_G2],
-                       pend_g2);
-  ZK_HIP(hipEventRecord(pk->done_ev[zkvc_pk::LANE_G2], pk->lanes[zkvc_pk::LANE_G2]));
 
   for (int lane = 0; lane < zkvc_pk::LANES; lane++) ZK_HIP(hipStreamWaitEvent(st, pk->done_ev[lane], 0));
   ZK_HIP(hipEventRecord(ev.e[3], st));
 
+  // ---- host side, one thread per lane as each lane completes: the plane
+  // sums by Horner's rule, then everything that lane's results allow.  The G1
+  // lane yields A, B1 and s A + r B1 - r s delta (one shared doubling chain,
+  // off the critical path); the G2 lane yields B; the H lane only its sum.
+  uint64_t rw[4], sw[4], rsw[4];
+  r.to_u64(rw);
+  s.to_u64(sw);
+  host::HFr::mul(r, s).to_u64(rsw);
   const size_t ng1 = in_g1.size(), ng2 = in_g2.size(), nh = in_h.size();
-  auto finish_g1 = [](hipEvent_t done, const MsmPending* pend, size_t n) {
-    ZK_HIP(hipEventSynchronize(done));
-    std::vector<host::G1J> out(n);
-    for (size_t q = 0; q < n; q++) out[q] = msm_finish_g1(pend[q]);
-    return out;
+  struct G1Part {
+    host::G1J A, L, sA_rB1;
   };
-  auto f_g1 = std::async(std::launch::async, finish_g1, pk->done_ev[zkvc_pk::LANE_G1], pend_g1, ng1);
-  auto f_h = std::async(std::launch::async, finish_g1, pk->done_ev[zkvc_pk::LANE_H], pend_h, nh);
+  auto f_g1 = std::async(std::launch::async, [&] {
+    ZK_HIP(hipEventSynchronize(pk->done_ev[zkvc_pk::LANE_G1]));
+    host::G1J msmA = host::G1J::inf(), msmB1 = host::G1J::inf(), msmL = host::G1J::inf();
+    for (size_t q = 0; q < ng1; q++) {
+      const host::G1J v = msm_finish_g1(pend_g1[q]);
+      switch (query_g1[q]) {
+        case ZKVC_Q_A: msmA = host::G1J::add(msmA, v); break;
+        case ZKVC_Q_B1: msmB1 = host::G1J::add(msmB1, v); break;
+        default: msmL = host::G1J::add(msmL, v); break;
+      }
+    }
+    G1Part o;
+    o.A = host::G1J::add(host::G1J::add(pk->alpha1, msmA), pk->delta1_table.mul(rw));
+    const host::G1J B1 = host::G1J::add(host::G1J::add(pk->beta1, msmB1), pk->delta1_table.mul(sw));
+    o.sA_rB1 = host::G1J::add(host::G1J::mul2(o.A, sw, B1, rw), host::G1J::neg(pk->delta1_table.mul(rsw)));
+    o.L = msmL;
+    return o;
+  });
   auto f_g2 = std::async(std::launch::async, [&] {
     ZK_HIP(hipEventSynchronize(pk->done_ev[zkvc_pk::LANE_G2]));
-    host::G2J acc = host::G2J::inf();
-    for (size_t q = 0; q < ng2; q++) acc = host::G2J::add(acc, msm_finish_g2(pend_g2[q]));
-    return acc;
+    host::G2J msmB2 = host::G2J::inf();
+    for (size_t q = 0; q < ng2; q++) msmB2 = host::G2J::add(msmB2, msm_finish_g2(pend_g2[q]));
+    return host::G2J::add(host::G2J::add(pk->beta2, msmB2), pk->delta2_table.mul(sw));
+  });
+  auto f_h = std::async(std::launch::async, [&] {
+    ZK_HIP(hipEventSynchronize(pk->done_ev[zkvc_pk::LANE_H]));
+    host::G1J msmH = host::G1J::inf();
+    for (size_t q = 0; q < nh; q++) msmH = host::G1J::add(msmH, msm_finish_g1(pend_h[q]));
+    return msmH;
   });
   ZK_HIP(hipStreamSynchronize(st));
   for (int q = 0; q < 8; q++)
     if (top[q]) throw Error(ZKVC_EDEVICE, "internal error: the witness does not satisfy the circuit");
   const auto asm_t0 = std::chrono::steady_clock::now();
-  host::G1J msmA = host::G1J::inf(), msmB1 = host::G1J::inf(), msmL = host::G1J::inf(), msmH = host::G1J::inf();
-  const std::vector<host::G1J> r_g1 = f_g1.get(), r_h = f_h.get();
-  const host::G2J msmB2 = f_g2.get();
-  for (size_t q = 0; q < ng1; q++) {
-    switch (query_g1[q]) {
-      case ZKVC_Q_A: msmA = host::G1J::add(msmA, r_g1[q]); break;
-      case ZKVC_Q_B1: msmB1 = host::G1J::add(msmB1, r_g1[q]); break;
-      default: msmL = host::G1J::add(msmL, r_g1[q]); break;
-    }
-  }
-  for (size_t q = 0; q < nh; q++) msmH = host::G1J::add(msmH, r_h[q]);
-
-  // ---- assembly on the host: blinding multiples of delta from fixed-base
-  // tables, s A + r B1 with one shared doubling chain
-  uint64_t rw[4], sw[4], rsw[4];
-  r.to_u64(rw);
-  s.to_u64(sw);
-  host::HFr::mul(r, s).to_u64(rsw);
-  const host::G1J A = host::G1J::add(host::G1J::add(pk->alpha1, msmA), pk->delta1_table.mul(rw));
-  const host::G2J B = host::G2J::add(host::G2J::add(pk->beta2, msmB2), pk->delta2_table.mul(sw));
-  const host::G1J B1 = host::G1J::add(host::G1J::add(pk->beta1, msmB1), pk->delta1_table.mul(sw));
-  host::G1J C = host::G1J::add(msmL, msmH);
-  C = host::G1J::add(C, host::G1J::mul2(A, sw, B1, rw));
-  C = host::G1J::add(C, host::G1J::neg(pk->delta1_table.mul(rsw)));
-  g1_to_abi(A, &out->A);
+  const G1Part g1 = f_g1.get();
+  const host::G2J B = f_g2.get();
+  const host::G1J msmH = f_h.get();
+  // C = sum_aux a_i L_i + h(tau) t(tau)/delta + s A + r B1 - r s delta
+  const host::G1J C = host::G1J::add(host::G1J::add(g1.L, msmH), g1.sA_rB1);
+  g1_to_abi(g1.A, &out->A);
   g2_to_abi(B, &out->B);
   g1_to_abi(C, &out->C);
   const auto host_t1 = std::chrono::steady_clock::now();

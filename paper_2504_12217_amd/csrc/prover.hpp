@@ -19,8 +19,13 @@ namespace zkvc {
 struct Seg {
   uint64_t var_start = 0;
   uint64_t count = 0;
-  int bits = 253;
-  uint64_t point_offset = 0;  // first point of this range inside the query array
+  int bits = 253;             // |value| <= 2^bits after sign folding
+  uint64_t index = 0;         // first query index of this range (segments are consecutive)
+  uint64_t point_offset = 0;  // first stored point of this range inside the query array
+  // Precomputed windows: the range is stored pre_nw times, copy w holding
+  // 2^(pre_c w) times each point (pre_nw = 1: stored once, no precomputation).
+  int pre_c = 0;
+  int pre_nw = 1;
 };
 
 // Sizes and variable layout of one circuit (see r1cs_layout()).
@@ -36,6 +41,7 @@ struct Layout {
   uint64_t aux_start = 0; // first auxiliary variable
   int y_bits = 0, aux_bits = 253;
   std::vector<Seg> segA, segB, segL;  // query coverage
+  Seg segH;                            // the H query (j < N - 1)
 };
 
 Layout r1cs_layout(uint32_t a, uint32_t n, uint32_t b, uint32_t kind);
