@@ -84,25 +84,122 @@ def time_proofs(zk, pk, X, W, r, s, steps, warmup, profile):
     return total, lat, stats
 
 
-def msm_rate(zk, log_n, seed=0):
+FR_ORDER = 21888242871839275222246405745257275088548364400416034343698204186575808495617
+
+
+def int8_scalar_limbs(seed, n):
+    """[n, 8] uint32 limbs of int8 values (uniform in [-128, 127], negatives as r - |v|)."""
+    v = synth.int8_matrix(seed, synth.STREAM_MSM_SCALARS, 1, n).reshape(-1).astype(np.int64)
+    return synth.ints_to_limbs([int(x) % FR_ORDER for x in v])
+
+
+def msm_rate(zk, n, seed=0, group=1, int8=False, reps=3):
+    """Points per second of the standalone MSM: bases [k_i]G from the fixed-base kernel."""
     import torch
-    n = (1 << log_n)
     ks = synth.fr_limbs(seed, synth.STREAM_MSM_BASES, n)
-    sc = synth.fr_limbs(seed, synth.STREAM_MSM_SCALARS, n)
+    sc = int8_scalar_limbs(seed, n) if int8 else synth.fr_limbs(seed, synth.STREAM_MSM_SCALARS, n)
     dk = torch.from_numpy(ks.view(np.int32).copy()).cuda()
     ds = torch.from_numpy(sc.view(np.int32).copy()).cuda()
-    pts = torch.zeros((n * 16,), dtype=torch.int32, device="cuda")
-    zk.fixed_base_g1(dk, n, pts)
+    pts = torch.zeros((n * (16 if group == 1 else 32),), dtype=torch.int32, device="cuda")
+    (zk.fixed_base_g1 if group == 1 else zk.fixed_base_g2)(dk, n, pts)
     del dk
-    zk.msm_g1(pts, ds, n)  # warm-up (workspace growth)
+    run = zk.msm_g1 if group == 1 else zk.msm_g2
+    run(pts, ds, n)  # warm-up (workspace growth)
     torch.cuda.synchronize()
-    reps = 3
     t0 = time.perf_counter()
     for _ in range(reps):
-        zk.msm_g1(pts, ds, n)
+        run(pts, ds, n)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
+    del pts, ds
+    torch.cuda.empty_cache()
     return n / dt / 1e6, dt * 1e3
+
+
+def ntt_rate(zk, log_n, seed=0, reps=5):
+    """Forward Fr NTT of 2^log_n elements in the internal layout (natural order in and out)."""
+    import torch
+    n = 1 << log_n
+    x = synth.fr_limbs(seed, synth.STREAM_NTT, n)
+    d = torch.from_numpy(x.view(np.int32).copy()).cuda()
+    zk.ntt_fr(d, log_n, zk.LAYOUT_MONT)
+    torch.cuda.synchronize()
+    zk.profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        zk.ntt_fr(d, log_n, zk.LAYOUT_MONT)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    st = zk.profile_read()
+    del d
+    torch.cuda.empty_cache()
+    out = {"melem_per_s": round(n / dt / 1e6, 2), "ms": round(dt * 1e3, 4)}
+    if "ntt_pass" in st:
+        launches, total_ms, work = st["ntt_pass"]
+        passes = launches // reps
+        # each pass reads and writes every element once: 64 B per element
+        gbs = passes * n * 64 / (total_ms / reps * 1e-3) / 1e9
+        mad = work / reps * MAD_PER_FMUL / (total_ms / reps * 1e-3) / 1e12
+        out.update({"passes": passes, "pass_ms_avg": round(total_ms / launches, 4),
+                    "hbm": {"achieved_gb_s": round(gbs, 1), "peak_gb_s": 8000, "frac": round(gbs / 8000, 4)},
+                    "alu": {"achieved_t_mad_s": round(mad, 3), "peak": round(PEAK_MAD / 1e12, 3),
+                            "frac": round(mad * 1e12 / PEAK_MAD, 4)}})
+    return out
+
+
+BATCH_N = (64, 128, 320)
+BATCH_B = (64, 256, 512)
+
+
+def batch_jobs(seed, count):
+    """(n, b) per job from stream 10 over the 9 classes; X, W of job j from seed 1000*seed + j + 1."""
+    raw = synth.rng(seed, synth.STREAM_SHAPES).bit_generator.random_raw(count)
+    shapes = [(49, BATCH_N[int(w % 9) // 3], BATCH_B[int(w % 9) % 3]) for w in raw]
+    jobs = []
+    for j, (a, n, b) in enumerate(shapes):
+        X, W = synth.matmul_inputs(1000 * seed + j + 1, a, n, b)
+        r, s = synth.prover_randomness(seed, job=j)
+        jobs.append(((a, n, b), X, W, r, s))
+    return jobs
+
+
+def batch_section(zk, seed, count=64, reps=3):
+    """Throughput of batched CRPC+PSQ proving over mixed shapes (one key per shape class)."""
+    import torch
+    jobs = batch_jobs(seed, count)
+    tox = synth.toxic_waste(seed)
+    z = synth.crpc_point(seed)
+    keys = {}
+    t0 = time.perf_counter()
+    for shape, *_ in jobs:
+        if shape not in keys:
+            keys[shape] = zk.setup(*shape, zk.CRPC_PSQ, tox, z)
+    setup_s = time.perf_counter() - t0
+    batch = [(keys[sh], X, W, r, s) for sh, X, W, r, s in jobs]
+    outs = zk.prove_batch(batch)  # warm-up (workspace growth)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        t = time.perf_counter()
+        outs = zk.prove_batch(batch)
+        lat.append(time.perf_counter() - t)
+    dt = time.perf_counter() - t0
+    ok = all(zk.verify(keys[sh].vk, X, Y, p) == 1 for (sh, X, W, r, s), (Y, p) in zip(jobs[:4], outs[:4]))
+    # the same jobs one by one, for comparison
+    t0 = time.perf_counter()
+    for pk, X, W, r, s in batch:
+        zk.prove(pk, X, W, r, s)
+    single_s = time.perf_counter() - t0
+    for pk in keys.values():
+        pk.close()
+    classes = sorted(set(sh for sh, *_ in jobs))
+    return {"workload": f"{count} CRPC+PSQ proofs, a=49, (n, b) drawn per proof from {{64,128,320}}x{{64,256,512}} "
+                        f"({len(classes)} shape classes, QAP domains 2^13..2^16), one zkvc_prove_batch call",
+            "proofs_per_s": round(count * reps / dt, 2), "ms_per_batch": round(dt / reps * 1e3, 3),
+            "batch_latency_ms_max": round(max(lat) * 1e3, 3),
+            "same_jobs_one_by_one_proofs_per_s": round(count / single_s, 2),
+            "setup_s_all_keys": round(setup_s, 3), "verified_sample": ok}
 
 
 def cpu_baseline(X, W, tox, z, r, s, budget_frac=256):
@@ -163,6 +260,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-msm", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build proves on a single MI355X "
@@ -242,11 +340,31 @@ def main():
                         "crpc_psq_speedup": round((tp / steps_p) / (total / args.steps), 2)}
     if not args.no_msm:
         msm = {}
-        for lg in (16, 20, 23):
+        for lg in (16, 20, 23, 24):
             log(f"G1 MSM 2^{lg}")
-            rate, ms = msm_rate(zkvc, lg, seed)
+            rate, ms = msm_rate(zkvc, 1 << lg, seed)
             msm[f"2^{lg}"] = {"mpts_per_s": round(rate, 2), "ms": round(ms, 3)}
         out["msm_g1_uniform_scalars"] = msm
+        msm2 = {}
+        for lg in (16, 20):
+            log(f"G2 MSM 2^{lg}")
+            rate, ms = msm_rate(zkvc, 1 << lg, seed, group=2)
+            msm2[f"2^{lg}"] = {"mpts_per_s": round(rate, 2), "ms": round(ms, 3)}
+        out["msm_g2_uniform_scalars"] = msm2
+        nb = SHAPE[1] * SHAPE[2]
+        log(f"int8-scalar MSMs of {nb} terms (the B query)")
+        r1, m1 = msm_rate(zkvc, nb, seed, group=1, int8=True)
+        r2, m2 = msm_rate(zkvc, nb, seed, group=2, int8=True)
+        out["msm_int8_scalars_163840"] = {"g1": {"mpts_per_s": round(r1, 2), "ms": round(m1, 3)},
+                                          "g2": {"mpts_per_s": round(r2, 2), "ms": round(m2, 3)}}
+        ntt = {}
+        for lg in (16, 20, 24):
+            log(f"NTT 2^{lg}")
+            ntt[f"2^{lg}"] = ntt_rate(zkvc, lg, seed)
+        out["ntt_fr_forward"] = ntt
+    if not args.no_batch:
+        log("batched proving: 64 mixed-shape CRPC+PSQ proofs")
+        out["batched_crpc_psq_64"] = batch_section(zkvc, seed)
     out["paper_context"] = {"note": "the paper's CPU figures, other hardware (16-core Threadripper PRO 3955WX)",
                             "plain_prove_s_49x320x512": 180, "crpc_psq_prove_s_49x64x128_table2": 0.73}
     if not args.no_cpu_baseline:

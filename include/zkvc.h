@@ -101,6 +101,31 @@ int zkvc_pk_free(zkvc_pk* pk);
 int zkvc_prove(const zkvc_pk* pk, const int8_t* X, const int8_t* W, const zkvc_fr* r, const zkvc_fr* s,
                int32_t* Y_out, zkvc_proof* proof_out, void* hip_stream);
 
+/* One proof of a batch (zkvc_prove_batch): the arguments of zkvc_prove. */
+typedef struct {
+  const zkvc_pk* pk;      /* proving key of this proof's shape and circuit kind */
+  const int8_t* X;        /* host int8 a x n row-major (public) */
+  const int8_t* W;        /* host int8 n x b row-major (private) */
+  zkvc_fr r, s;           /* blinding scalars, canonical Fr */
+  int32_t* Y_out;         /* host int32 a x b row-major, written */
+  zkvc_proof* proof_out;  /* host, written */
+} zkvc_prove_job;
+
+/*
+ * Batched proving (the same statement as zkvc_prove, many at once).  The
+ * proofs may use keys of different shapes and kinds, and a key may repeat.
+ * All stages run once for the whole batch: the witnesses, the quotient
+ * transforms of all proofs of one domain size in shared launches, and every
+ * multi-scalar multiplication of the batch in three shared pipelines (G1
+ * queries, the G2 query, the H query).  Every proof and Y equal, bit for bit,
+ * what zkvc_prove returns for the same job.  Synchronous; the library keeps
+ * one batch context per (device, stream), so calls on one stream serialize
+ * and calls on different streams run concurrently.  Keys are only read.
+ * Errors: ZKVC_EINVAL (no jobs, null pointer, r or s >= r, a key on another
+ * device), ZKVC_ENOMEM, ZKVC_EDEVICE.
+ */
+int zkvc_prove_batch(const zkvc_prove_job* jobs, size_t njobs, void* hip_stream);
+
 /*
  * Verify (Section II; the Groth16 pairing-product equation), on the host.
  * vk: blob written by zkvc_setup; X: int8 a x n; Y: int32 a x b (the shape is
@@ -182,9 +207,11 @@ int zkvc_pk_export(const zkvc_pk* pk, uint32_t query, uint64_t start, uint64_t c
 
 /* Per-stage device times (milliseconds, from HIP events on the calling
  * stream) of the last zkvc_prove with this key: witness and evaluation
- * vectors, the QAP quotient, all multi-scalar multiplications (they run
- * concurrently on the key's own streams), then the host-side window
- * combination and assembly, and the wall time of the whole call. */
+ * vectors, the QAP quotient, then from the end of the quotient to the end of
+ * the last multi-scalar multiplication (the G1 and G2 queries other than H
+ * start right after the witness, on the key's own streams, overlapping the
+ * quotient), then the host-side plane combination and assembly left after
+ * the device work, and the wall time of the whole call. */
 typedef struct {
   float witness_ms, ntt_ms, msm_ms, host_ms, total_ms;
 } zkvc_prove_stats;

@@ -1,6 +1,9 @@
 // C-ABI entry points for Groth16: setup, prove, verify and proving-key access.
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <vector>
 
 #include "api_common.hpp"
@@ -66,6 +69,46 @@ int zkvc_prove(const zkvc_pk* pk, const int8_t* X, const int8_t* W, const zkvc_f
   });
 }
 
+namespace {
+// One batch context per (device, stream), created on first use.
+struct BatchCtxEntry {
+  std::mutex mu;
+  std::unique_ptr<ProveCtx> ctx;
+};
+BatchCtxEntry& batch_ctx(int dev, hipStream_t st) {
+  static std::mutex mu;
+  static std::map<std::pair<int, hipStream_t>, std::unique_ptr<BatchCtxEntry>> table;
+  std::lock_guard<std::mutex> lock(mu);
+  auto& e = table[{dev, st}];
+  if (!e) e.reset(new BatchCtxEntry());
+  return *e;
+}
+}  // namespace
+
+int zkvc_prove_batch(const zkvc_prove_job* jobs, size_t njobs, void* hip_stream) {
+  return guarded([&] {
+    ZK_REQUIRE(jobs && njobs > 0, "no proof jobs");
+    const int dev = current_device();
+    std::vector<ProveJob> pj(njobs);
+    for (size_t j = 0; j < njobs; j++) {
+      const zkvc_prove_job& in = jobs[j];
+      ZK_REQUIRE(in.pk && in.X && in.W && in.Y_out && in.proof_out, "null argument in a proof job");
+      ZK_REQUIRE(in.pk->device == dev, "a proving key lives on another device");
+      pj[j].pk = in.pk;
+      pj[j].X = in.X;
+      pj[j].W = in.W;
+      pj[j].r = fr_in(in.r, "r");
+      pj[j].s = fr_in(in.s, "s");
+      pj[j].Y = in.Y_out;
+      pj[j].out = in.proof_out;
+    }
+    BatchCtxEntry& e = batch_ctx(dev, (hipStream_t)hip_stream);
+    std::lock_guard<std::mutex> lock(e.mu);
+    if (!e.ctx) e.ctx.reset(new ProveCtx());
+    groth16_prove_batch(*e.ctx, pj.data(), njobs, (hipStream_t)hip_stream);
+  });
+}
+
 int zkvc_verify(const uint8_t* vk, size_t vk_len, const int8_t* X, const int32_t* Y, const zkvc_proof* proof) {
   int result = 0;
   const int rc = guarded([&] {
@@ -91,7 +134,13 @@ int zkvc_pk_info(const zkvc_pk* pk, zkvc_pk_info_t* info) {
     info->b_query = total(L.segB);
     info->l_query = total(L.segL);
     info->h_query = L.N - 1;
-    info->device_bytes = pk->key_bytes + pk->ws.bytes();
+    size_t ctx_bytes = 0;
+    if (pk->ctx) {
+      for (const Workspace& w : pk->ctx->lane_ws) ctx_bytes += w.bytes();
+      for (const auto& w : pk->ctx->slot_ws) ctx_bytes += w->bytes();
+      ctx_bytes += pk->ctx->shared.bytes();
+    }
+    info->device_bytes = pk->key_bytes + pk->ws.bytes() + ctx_bytes;
   });
 }
 

@@ -5,7 +5,9 @@
 // doubling formulas are the "add-2008-s", "madd-2008-s" and "dbl-2008-s-1"
 // entries of Bernstein and Lange's Explicit-Formulas Database for a = 0:
 // a mixed addition costs 8M + 2S and needs no inversion, which suits the
-// bucket accumulation of Pippenger's method.
+// bucket accumulation of Pippenger's method.  Products are F::cmul / F::csqr:
+// inlined over Fq, out-of-line over Fq2 (keeping G2 kernels inside the
+// instruction cache).
 //
 // Affine points in memory are stored x then y (each coordinate 8 x 32-bit
 // words in the device Montgomery form); the pair (0, 0) encodes infinity.
@@ -30,68 +32,68 @@ struct Xyzz {
   // 2 * (x, y) for an affine input (mdbl-2008-s-1 with ZZ = ZZZ = 1)
   static ZK_DEV Xyzz dbl_affine(const Affine<F>& q) {
     const F U = F::dbl(q.y);
-    const F V = F::sqr(U);
-    const F W = F::mul(U, V);
-    const F S = F::mul(q.x, V);
-    const F xx = F::sqr(q.x);
+    const F V = F::csqr(U);
+    const F W = F::cmul(U, V);
+    const F S = F::cmul(q.x, V);
+    const F xx = F::csqr(q.x);
     const F M = F::add(F::dbl(xx), xx);
-    const F X3 = F::sub(F::sqr(M), F::dbl(S));
-    const F Y3 = F::sub(F::mul(M, F::sub(S, X3)), F::mul(W, q.y));
+    const F X3 = F::sub(F::csqr(M), F::dbl(S));
+    const F Y3 = F::sub(F::cmul(M, F::sub(S, X3)), F::cmul(W, q.y));
     return {X3, Y3, V, W};
   }
 
   // 2P (dbl-2008-s-1)
   static ZK_DEV Xyzz dbl(const Xyzz& p) {
     const F U = F::dbl(p.Y);
-    const F V = F::sqr(U);
-    const F W = F::mul(U, V);
-    const F S = F::mul(p.X, V);
-    const F xx = F::sqr(p.X);
+    const F V = F::csqr(U);
+    const F W = F::cmul(U, V);
+    const F S = F::cmul(p.X, V);
+    const F xx = F::csqr(p.X);
     const F M = F::add(F::dbl(xx), xx);
-    const F X3 = F::sub(F::sqr(M), F::dbl(S));
-    const F Y3 = F::sub(F::mul(M, F::sub(S, X3)), F::mul(W, p.Y));
-    return {X3, Y3, F::mul(V, p.ZZ), F::mul(W, p.ZZZ)};
+    const F X3 = F::sub(F::csqr(M), F::dbl(S));
+    const F Y3 = F::sub(F::cmul(M, F::sub(S, X3)), F::cmul(W, p.Y));
+    return {X3, Y3, F::cmul(V, p.ZZ), F::cmul(W, p.ZZZ)};
   }
 
   // P + Q with Q affine (madd-2008-s), Q not infinity
   static ZK_DEV Xyzz madd(const Xyzz& p, const Affine<F>& q) {
     if (is_inf(p)) return from_affine(q);
-    const F U2 = F::mul(q.x, p.ZZ);
-    const F S2 = F::mul(q.y, p.ZZZ);
+    const F U2 = F::cmul(q.x, p.ZZ);
+    const F S2 = F::cmul(q.y, p.ZZZ);
     const F P = F::sub(U2, p.X);
     const F R = F::sub(S2, p.Y);
     if (F::is_zero(P)) {
       if (F::is_zero(R)) return dbl_affine(q);
       return inf();
     }
-    const F PP = F::sqr(P);
-    const F PPP = F::mul(P, PP);
-    const F Q = F::mul(p.X, PP);
-    const F X3 = F::sub(F::sub(F::sqr(R), PPP), F::dbl(Q));
-    const F Y3 = F::sub(F::mul(R, F::sub(Q, X3)), F::mul(p.Y, PPP));
-    return {X3, Y3, F::mul(p.ZZ, PP), F::mul(p.ZZZ, PPP)};
+    const F PP = F::csqr(P);
+    const F PPP = F::cmul(P, PP);
+    const F Q = F::cmul(p.X, PP);
+    const F X3 = F::sub(F::sub(F::csqr(R), PPP), F::dbl(Q));
+    const F Y3 = F::sub(F::cmul(R, F::sub(Q, X3)), F::cmul(p.Y, PPP));
+    return {X3, Y3, F::cmul(p.ZZ, PP), F::cmul(p.ZZZ, PPP)};
   }
 
   // P + Q (add-2008-s)
   static ZK_DEV Xyzz add(const Xyzz& p, const Xyzz& q) {
     if (is_inf(p)) return q;
     if (is_inf(q)) return p;
-    const F U1 = F::mul(p.X, q.ZZ);
-    const F U2 = F::mul(q.X, p.ZZ);
-    const F S1 = F::mul(p.Y, q.ZZZ);
-    const F S2 = F::mul(q.Y, p.ZZZ);
+    const F U1 = F::cmul(p.X, q.ZZ);
+    const F U2 = F::cmul(q.X, p.ZZ);
+    const F S1 = F::cmul(p.Y, q.ZZZ);
+    const F S2 = F::cmul(q.Y, p.ZZZ);
     const F P = F::sub(U2, U1);
     const F R = F::sub(S2, S1);
     if (F::is_zero(P)) {
       if (F::is_zero(R)) return dbl(p);
       return inf();
     }
-    const F PP = F::sqr(P);
-    const F PPP = F::mul(P, PP);
-    const F Q = F::mul(U1, PP);
-    const F X3 = F::sub(F::sub(F::sqr(R), PPP), F::dbl(Q));
-    const F Y3 = F::sub(F::mul(R, F::sub(Q, X3)), F::mul(S1, PPP));
-    return {X3, Y3, F::mul(F::mul(p.ZZ, q.ZZ), PP), F::mul(F::mul(p.ZZZ, q.ZZZ), PPP)};
+    const F PP = F::csqr(P);
+    const F PPP = F::cmul(P, PP);
+    const F Q = F::cmul(U1, PP);
+    const F X3 = F::sub(F::sub(F::csqr(R), PPP), F::dbl(Q));
+    const F Y3 = F::sub(F::cmul(R, F::sub(Q, X3)), F::cmul(S1, PPP));
+    return {X3, Y3, F::cmul(F::cmul(p.ZZ, q.ZZ), PP), F::cmul(F::cmul(p.ZZZ, q.ZZZ), PPP)};
   }
 
   static ZK_DEV Xyzz neg(const Xyzz& p) { return {p.X, F::neg(p.Y), p.ZZ, p.ZZZ}; }

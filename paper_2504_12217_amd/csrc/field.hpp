@@ -30,6 +30,24 @@ constexpr int LB = 29;
 constexpr uint32_t LMASK = (1u << LB) - 1u;
 
 template <class M>
+struct Fp;
+
+// Out-of-line Montgomery product and square.  The G2 group law calls these
+// instead of inlining ~230 instructions per product: an inlined G2 addition
+// alone exceeds the instruction cache shared by two CUs (G1 additions fit, and
+// run faster inlined).  The limbs travel as scalar arguments, so both
+// operands and the result stay in VGPRs (an aggregate argument beyond the
+// first would be passed through scratch).
+template <class M>
+__device__ __noinline__ Fp<M> fp_mul_call(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3, uint32_t a4,
+                                          uint32_t a5, uint32_t a6, uint32_t a7, uint32_t a8, uint32_t b0,
+                                          uint32_t b1, uint32_t b2, uint32_t b3, uint32_t b4, uint32_t b5,
+                                          uint32_t b6, uint32_t b7, uint32_t b8);
+template <class M>
+__device__ __noinline__ Fp<M> fp_sqr_call(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3, uint32_t a4,
+                                          uint32_t a5, uint32_t a6, uint32_t a7, uint32_t a8);
+
+template <class M>
 struct Fp {
   uint32_t v[NL];
 
@@ -203,6 +221,18 @@ struct Fp {
     return reduce_once(r);
   }
 
+  // the same products through the out-of-line functions
+  static ZK_DEV Fp mul_oop(const Fp& a, const Fp& b) {
+    return fp_mul_call<M>(a.v[0], a.v[1], a.v[2], a.v[3], a.v[4], a.v[5], a.v[6], a.v[7], a.v[8], b.v[0], b.v[1],
+                          b.v[2], b.v[3], b.v[4], b.v[5], b.v[6], b.v[7], b.v[8]);
+  }
+  static ZK_DEV Fp sqr_oop(const Fp& a) {
+    return fp_sqr_call<M>(a.v[0], a.v[1], a.v[2], a.v[3], a.v[4], a.v[5], a.v[6], a.v[7], a.v[8]);
+  }
+  // the products of the group law (curve.hpp): inlined over the base field
+  static ZK_DEV Fp cmul(const Fp& a, const Fp& b) { return mul(a, b); }
+  static ZK_DEV Fp csqr(const Fp& a) { return sqr(a); }
+
   static ZK_DEV bool is_zero(const Fp& a) {
     uint32_t t = 0;
 #pragma unroll
@@ -252,6 +282,22 @@ struct Fp {
   }
 };
 
+template <class M>
+__device__ __noinline__ Fp<M> fp_mul_call(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3, uint32_t a4,
+                                          uint32_t a5, uint32_t a6, uint32_t a7, uint32_t a8, uint32_t b0,
+                                          uint32_t b1, uint32_t b2, uint32_t b3, uint32_t b4, uint32_t b5,
+                                          uint32_t b6, uint32_t b7, uint32_t b8) {
+  const Fp<M> a{{a0, a1, a2, a3, a4, a5, a6, a7, a8}};
+  const Fp<M> b{{b0, b1, b2, b3, b4, b5, b6, b7, b8}};
+  return Fp<M>::mul(a, b);
+}
+template <class M>
+__device__ __noinline__ Fp<M> fp_sqr_call(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3, uint32_t a4,
+                                          uint32_t a5, uint32_t a6, uint32_t a7, uint32_t a8) {
+  const Fp<M> a{{a0, a1, a2, a3, a4, a5, a6, a7, a8}};
+  return Fp<M>::sqr(a);
+}
+
 using Fq = Fp<FqParams>;
 using Fr = Fp<FrParams>;
 
@@ -275,6 +321,17 @@ struct Fq2 {
   static ZK_DEV Fq2 sqr(const Fq2& a) {
     const Fq t = Fq::mul(a.c0, a.c1);
     return {Fq::mul(Fq::add(a.c0, a.c1), Fq::sub(a.c0, a.c1)), Fq::dbl(t)};
+  }
+  // the products of the group law: through the out-of-line base-field products
+  static ZK_DEV Fq2 cmul(const Fq2& a, const Fq2& b) {
+    const Fq v0 = Fq::mul_oop(a.c0, b.c0);
+    const Fq v1 = Fq::mul_oop(a.c1, b.c1);
+    const Fq s = Fq::mul_oop(Fq::add(a.c0, a.c1), Fq::add(b.c0, b.c1));
+    return {Fq::sub(v0, v1), Fq::sub(Fq::sub(s, v0), v1)};
+  }
+  static ZK_DEV Fq2 csqr(const Fq2& a) {
+    const Fq t = Fq::mul_oop(a.c0, a.c1);
+    return {Fq::mul_oop(Fq::add(a.c0, a.c1), Fq::sub(a.c0, a.c1)), Fq::dbl(t)};
   }
   static ZK_DEV bool is_zero(const Fq2& a) { return Fq::is_zero(a.c0) && Fq::is_zero(a.c1); }
   static ZK_DEV bool eq(const Fq2& a, const Fq2& b) { return Fq::eq(a.c0, b.c0) && Fq::eq(a.c1, b.c1); }

@@ -42,7 +42,7 @@ constexpr uint32_t WG_TASK_ENTRIES = 256;  // entries per large-bucket (wavefron
 constexpr uint32_t SIGN = 0x80000000u;
 enum MsmSlot {
   S_DIGITS = 100, S_COUNTS, S_OFFSETS, S_HEAVY, S_SORTED, S_TASKS, S_CNT_A, S_CNT_B, S_OFF_A, S_OFF_B,
-  S_PART0, S_PART1, S_SCRATCH, S_SCRATCH2, S_SEG, S_WIN, S_META, S_FB_XYZZ, S_FB_PREFIX, S_BP_PART
+  S_PART0, S_PART1, S_SCRATCH, S_SCRATCH2, S_SEG, S_WIN, S_META, S_FB_XYZZ, S_FB_PREFIX, S_BP_PART, S_JOBS
 };
 
 __device__ __forceinline__ uint32_t bitrev_n(uint32_t a, int bits) {
@@ -72,19 +72,27 @@ struct JobDev {
   uint32_t blk_digits;      // first block of the digit grid
   uint32_t blk_hs;          // first block of the histogram / scatter grid (nw * nch blocks)
 };
+// The jobs of a batch live in a device table (uploaded with the batch), so a
+// batch may hold any number of MSMs: every proof of a proving batch at once.
 struct BatchDev {
   int njobs;
-  JobDev job[MSM_MAX_JOBS];
+  const JobDev* jobs;
 };
 
-// The job owning a block, bucket or plane: the last job whose first index is
-// <= v (the tables are ascending).  Unrolled so the index stays a constant.
-#define ZK_JOB_OF(B, field, v)                                                   \
-  ([&]() {                                                                       \
-    int k_ = 0;                                                                  \
-    _Pragma("unroll") for (int q_ = 1; q_ < MSM_MAX_JOBS; q_++) if (q_ < (B).njobs && (v) >= (B).job[q_].field) k_ = q_; \
-    return k_;                                                                   \
-  }())
+// The job owning index v of a per-job range whose first index is the field F
+// (ascending over the jobs): a binary search of the table.
+template <uint32_t JobDev::*F>
+__device__ __forceinline__ int job_of(const BatchDev& B, uint32_t v) {
+  int lo = 0, hi = B.njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (B.jobs[mid].*F <= v)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
 
 constexpr int MAX_C = 15;         // the LDS histogram holds 2^(c-1) u32 counters (<= 64 KiB)
 constexpr int HS_THREADS = 512;   // histogram / scatter blocks
@@ -96,8 +104,8 @@ constexpr int BP_THREADS = 256;   // bit-plane reduction block
 // window (bucket | sign, or EMPTY for a zero digit or a point at infinity).
 template <class F>
 __global__ void __launch_bounds__(256) k_msm_digits(BatchDev B, uint32_t* digits) {
-  const int k = ZK_JOB_OF(B, blk_digits, blockIdx.x);
-  const JobDev& J = B.job[k];
+  const int k = job_of<&JobDev::blk_digits>(B, blockIdx.x);
+  const JobDev& J = B.jobs[k];
   const uint32_t j = (blockIdx.x - J.blk_digits) * 256 + threadIdx.x;
   if (j >= J.n) return;
   const uint32_t idx = J.bitrev_bits ? bitrev_n(j, J.bitrev_bits) : j;
@@ -172,8 +180,8 @@ __device__ __forceinline__ size_t hist_column(const JobDev& J, uint32_t w, uint3
 }
 __global__ void __launch_bounds__(HS_THREADS) k_msm_hist(BatchDev B, const uint32_t* digits, uint32_t* hist) {
   extern __shared__ uint32_t cnt[];
-  const int k = ZK_JOB_OF(B, blk_hs, blockIdx.x);
-  const JobDev& J = B.job[k];
+  const int k = job_of<&JobDev::blk_hs>(B, blockIdx.x);
+  const JobDev& J = B.jobs[k];
   const uint32_t local = blockIdx.x - J.blk_hs;
   const uint32_t w = local / J.nch, ch = local % J.nch;
   for (uint32_t b = threadIdx.x; b < J.nb; b += HS_THREADS) cnt[b] = 0u;
@@ -195,8 +203,8 @@ __global__ void __launch_bounds__(HS_THREADS) k_msm_hist(BatchDev B, const uint3
 __global__ void __launch_bounds__(HS_THREADS) k_msm_scatter(BatchDev B, const uint32_t* digits, const uint32_t* offs,
                                                             uint32_t* sorted) {
   extern __shared__ uint32_t cur[];
-  const int k = ZK_JOB_OF(B, blk_hs, blockIdx.x);
-  const JobDev& J = B.job[k];
+  const int k = job_of<&JobDev::blk_hs>(B, blockIdx.x);
+  const JobDev& J = B.jobs[k];
   const uint32_t local = blockIdx.x - J.blk_hs;
   const uint32_t w = local / J.nch, ch = local % J.nch;
   const uint32_t* o = offs + hist_column(J, w, ch);
@@ -229,8 +237,8 @@ __global__ void k_msm_task_counts(BatchDev B, const uint32_t* offs, uint32_t nbt
     counters[2] = 0u;
   }
   if (f >= nbt) return;
-  const int k = ZK_JOB_OF(B, bucket_base, f);
-  const JobDev& J = B.job[k];
+  const int k = job_of<&JobDev::bucket_base>(B, f);
+  const JobDev& J = B.jobs[k];
   const size_t lf = f - J.bucket_base;
   // the bucket after the job's last one starts the next job's range (or the total)
   const uint32_t s = offs[J.hist_base + lf * J.nchw];
@@ -242,7 +250,7 @@ __global__ void k_msm_task_counts(BatchDev B, const uint32_t* offs, uint32_t nbt
   nt[f] = (c + sz - 1) / sz;
 }
 
-// Task records (first entry, length, output partial slot, bucket).  Slots in
+// Task records (first entry, length, output partial slot, job).  Slots in
 // the two task lists are claimed with one atomic per wavefront and list.
 // Buckets that end up with more than FIN_THREAD_MAX partial sums are listed
 // for a wavefront each in the finalize step.
@@ -256,9 +264,10 @@ __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v, uint32_t lane
   return v;
 }
 
-__global__ void __launch_bounds__(256) k_msm_make_tasks(const uint32_t* cnt, const uint32_t* off, const uint32_t* part_off,
-                                                        uint32_t nbt, uint32_t K, uint32_t large, uint32_t* counters,
-                                                        uint4* th_tasks, uint4* wg_tasks, uint32_t* heavy) {
+__global__ void __launch_bounds__(256) k_msm_make_tasks(BatchDev B, const uint32_t* cnt, const uint32_t* off,
+                                                        const uint32_t* part_off, uint32_t nbt, uint32_t K,
+                                                        uint32_t large, uint32_t* counters, uint4* th_tasks,
+                                                        uint4* wg_tasks, uint32_t* heavy) {
   const uint32_t f = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t c = f < nbt ? cnt[f] : 0u;
@@ -284,9 +293,10 @@ __global__ void __launch_bounds__(256) k_msm_make_tasks(const uint32_t* cnt, con
   const uint32_t base = big ? bwg + swg - nt : bth + sth - nt;
   uint4* dst = big ? wg_tasks : th_tasks;
   const uint32_t o = off[f], p = part_off[f];
+  const uint32_t job = (uint32_t)job_of<&JobDev::bucket_base>(B, f);
   for (uint32_t q = 0; q < nt; q++) {
     const uint32_t len = c - q * sz < sz ? c - q * sz : sz;
-    dst[base + q] = make_uint4(o + q * sz, len, p + q, f);
+    dst[base + q] = make_uint4(o + q * sz, len, p + q, job);
   }
 }
 
@@ -306,7 +316,7 @@ __global__ void __launch_bounds__(64) k_msm_acc(BatchDev B, const uint4* th_task
     const uint32_t ntasks = counters[0];
     for (uint32_t t = blockIdx.x * 64 + threadIdx.x; t < ntasks; t += th_blocks * 64) {
       const uint4 task = th_tasks[t];
-      const uint32_t* points = B.job[ZK_JOB_OF(B, bucket_base, task.w)].points;
+      const uint32_t* points = B.jobs[task.w].points;
       Xyzz<F> acc = Xyzz<F>::inf();
       // the next entry's point is loaded while the current one is added
       const uint32_t end = task.x + task.y;
@@ -330,7 +340,7 @@ __global__ void __launch_bounds__(64) k_msm_acc(BatchDev B, const uint4* th_task
   const uint32_t wg_blocks = gridDim.x - th_blocks;
   for (uint32_t t = blockIdx.x - th_blocks; t < ntasks; t += wg_blocks) {
     const uint4 task = wg_tasks[t];
-    const uint32_t* points = B.job[ZK_JOB_OF(B, bucket_base, task.w)].points;
+    const uint32_t* points = B.jobs[task.w].points;
     Xyzz<F> acc = Xyzz<F>::inf();
     for (uint32_t e = threadIdx.x; e < task.y; e += WG_THREADS) {
       const uint32_t ref = sorted[task.x + e];
@@ -410,8 +420,8 @@ template <class F>
 __global__ void __launch_bounds__(BP_THREADS) k_msm_bitplanes(BatchDev B, const uint32_t* buckets, uint32_t* part) {
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
   __shared__ uint32_t sh[BP_THREADS / 2 * XW];
-  const int k = ZK_JOB_OF(B, blk_bp, blockIdx.x);
-  const JobDev& J = B.job[k];
+  const int k = job_of<&JobDev::blk_bp>(B, blockIdx.x);
+  const JobDev& J = B.jobs[k];
   const uint32_t local = blockIdx.x - J.blk_bp;
   const uint32_t q = local / J.bpb, slice = local % J.bpb;
   const uint32_t c = (uint32_t)J.c, nb = J.nb;
@@ -437,8 +447,8 @@ template <class F>
 __global__ void __launch_bounds__(64) k_msm_plane_sums(BatchDev B, const uint32_t* part, uint32_t* S) {
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
   __shared__ uint32_t sh[32 * XW];
-  const int k = ZK_JOB_OF(B, plane_base, blockIdx.x);
-  const JobDev& J = B.job[k];
+  const int k = job_of<&JobDev::plane_base>(B, blockIdx.x);
+  const JobDev& J = B.jobs[k];
   const uint32_t q = blockIdx.x - J.plane_base;
   const uint32_t* pp = part + ((size_t)J.blk_bp + (size_t)q * J.bpb) * XW;
   Xyzz<F> acc = Xyzz<F>::inf();
@@ -517,8 +527,8 @@ void hfq2_to_dev(const host::HFq2& a, uint32_t* w) {
 // Sizes of one batch, all known on the host before any launch, so the device
 // pipeline needs no host synchronization until the window sums come back.
 struct BatchPlan {
-  BatchDev dev{};
-  int map[MSM_MAX_JOBS] = {};  // device job -> caller's job
+  std::vector<JobDev> jobs;   // the device table's contents
+  std::vector<int> map;       // table entry -> caller's job
   uint64_t ndigits = 0, nbt = 0, nh = 0, nplanes = 0, digit_blocks = 0, hs_blocks = 0, bp_blocks = 0;
   uint32_t max_nb = 0;
   uint32_t K = 0;      // entries per thread task
@@ -531,7 +541,8 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs) {
   for (int q = 0; q < njobs; q++) {
     ZK_REQUIRE(in[q].nscalars < (1ull << 31) && in[q].npoints < (1ull << 31), "MSM too large");
     if (in[q].nscalars == 0) continue;
-    JobDev& J = p.dev.job[p.dev.njobs];
+    p.jobs.emplace_back();
+    JobDev& J = p.jobs.back();
     J.points = in[q].points;
     J.scalars = in[q].scalars;
     J.n = (uint32_t)in[q].nscalars;
@@ -576,8 +587,7 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs) {
     p.digit_blocks += cdiv(J.n, 256);
     p.hs_blocks += (uint64_t)J.nw * J.nch;
     p.max_nb = std::max(p.max_nb, J.nb);
-    p.map[p.dev.njobs] = q;
-    p.dev.njobs++;
+    p.map.push_back(q);
     ZK_REQUIRE(p.ndigits < (1ull << 32) && p.nh < (1ull << 32) - 1 && p.nbt < (1ull << 31),
                "MSM batch too large for 32-bit offsets");
   }
@@ -598,13 +608,14 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs) {
 template <class F>
 void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t st, MsmPending* pend) {
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
-  ZK_REQUIRE(njobs >= 0 && njobs <= MSM_MAX_JOBS, "too many MSMs in one batch");
+  ZK_REQUIRE(njobs >= 0, "negative MSM count");
   for (int q = 0; q < njobs; q++) {
     pend[q] = MsmPending();
     pend[q].xyzz_words = XW;
   }
   const BatchPlan p = batch_plan(in, njobs);
-  if (p.dev.njobs == 0) return;
+  const int nj = (int)p.jobs.size();
+  if (nj == 0) return;
   const uint32_t nbt = (uint32_t)p.nbt;
   const bool g1 = PointIO<F>::AFF_WORDS == 16;
 
@@ -627,43 +638,50 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
   uint32_t* meta = ws.get(S_META, 64 * 4);  // [2] partials [8..10] thread tasks, wavefront tasks, heavy buckets
   uint32_t* win_host = ws.host<uint32_t>(S_WIN, p.nplanes * XW * 4);
   ws.get(S_SCRATCH, (size_t)cdiv(std::max(p.nh, p.nbt), 2048) * 4 + 64);
-  for (int k = 0; k < p.dev.njobs; k++) {
+  // the job table, through pinned memory (the workspace is not reused before
+  // this stream has completed)
+  JobDev* jt_host = ws.host<JobDev>(S_JOBS, nj * sizeof(JobDev));
+  JobDev* jt_dev = ws.get<JobDev>(S_JOBS, nj * sizeof(JobDev));
+  std::memcpy(jt_host, p.jobs.data(), nj * sizeof(JobDev));
+  ZK_HIP(hipMemcpyAsync(jt_dev, jt_host, nj * sizeof(JobDev), hipMemcpyHostToDevice, st));
+  const BatchDev dev{nj, jt_dev};
+  for (int k = 0; k < nj; k++) {
     MsmPending& pd = pend[p.map[k]];
     pd.empty = false;
-    pd.c = p.dev.job[k].c;
-    pd.nw = (int)p.dev.job[k].nwb;
-    pd.win_host = win_host + (size_t)p.dev.job[k].plane_base * XW;
+    pd.c = p.jobs[k].c;
+    pd.nw = (int)p.jobs[k].nwb;
+    pd.win_host = win_host + (size_t)p.jobs[k].plane_base * XW;
   }
   const size_t lds = (size_t)p.max_nb * 4;
   {
     ProfScope ps(g1 ? "msm_digits_g1" : "msm_digits_g2", st, (double)p.ndigits);
-    hipLaunchKernelGGL(k_msm_digits<F>, dim3((unsigned)p.digit_blocks), dim3(256), 0, st, p.dev, digits);
+    hipLaunchKernelGGL(k_msm_digits<F>, dim3((unsigned)p.digit_blocks), dim3(256), 0, st, dev, digits);
     ZK_HIP(hipGetLastError());
   }
   {
     ProfScope ps("msm_sort", st, (double)p.ndigits);
-    hipLaunchKernelGGL(k_msm_hist, dim3((unsigned)p.hs_blocks), dim3(HS_THREADS), lds, st, p.dev, digits, hist);
+    hipLaunchKernelGGL(k_msm_hist, dim3((unsigned)p.hs_blocks), dim3(HS_THREADS), lds, st, dev, digits, hist);
     ZK_HIP(hipGetLastError());
     // offs[nh] receives the total number of entries
     scan_exclusive(hist, offs, (uint32_t)p.nh, 0, offs + p.nh, nullptr, ws, S_SCRATCH, st);
-    hipLaunchKernelGGL(k_msm_scatter, dim3((unsigned)p.hs_blocks), dim3(HS_THREADS), lds, st, p.dev, digits, offs,
+    hipLaunchKernelGGL(k_msm_scatter, dim3((unsigned)p.hs_blocks), dim3(HS_THREADS), lds, st, dev, digits, offs,
                        sorted);
     ZK_HIP(hipGetLastError());
   }
   // tasks by actual bucket size
-  hipLaunchKernelGGL(k_msm_task_counts, dim3(cdiv(nbt, 256)), dim3(256), 0, st, p.dev, offs, nbt, p.K, p.large, cnt,
+  hipLaunchKernelGGL(k_msm_task_counts, dim3(cdiv(nbt, 256)), dim3(256), 0, st, dev, offs, nbt, p.K, p.large, cnt,
                      off, nt, meta + 8);
   ZK_HIP(hipGetLastError());
   scan_exclusive(nt, part_off, nbt, 0, meta + 2, nullptr, ws, S_SCRATCH, st);
-  hipLaunchKernelGGL(k_msm_make_tasks, dim3(cdiv(nbt, 256)), dim3(256), 0, st, cnt, off, part_off, nbt, p.K, p.large,
-                     meta + 8, th_tasks, wg_tasks, heavy);
+  hipLaunchKernelGGL(k_msm_make_tasks, dim3(cdiv(nbt, 256)), dim3(256), 0, st, dev, cnt, off, part_off, nbt, p.K,
+                     p.large, meta + 8, th_tasks, wg_tasks, heavy);
   ZK_HIP(hipGetLastError());
   {
     ProfScope ps(g1 ? "msm_acc_points_g1" : "msm_acc_points_g2", st, -1.0);
     // capped grids with stride loops: the task counts are only known on the device
     const unsigned th_blocks = (unsigned)std::min<uint64_t>(cdiv(p.max_th_tasks, 64), 65536);
     const unsigned wg_blocks = (unsigned)std::min<uint64_t>(p.max_wg_tasks, 4096);
-    hipLaunchKernelGGL(k_msm_acc<F>, dim3(th_blocks + wg_blocks), dim3(64), 0, st, p.dev, th_tasks, wg_tasks,
+    hipLaunchKernelGGL(k_msm_acc<F>, dim3(th_blocks + wg_blocks), dim3(64), 0, st, dev, th_tasks, wg_tasks,
                        meta + 8, th_blocks, sorted, part);
     ZK_HIP(hipGetLastError());
     ps.set_work_from_device(offs + p.nh);
@@ -678,18 +696,18 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
   }
   {
     double adds = 0;
-    for (int k = 0; k < p.dev.njobs; k++) adds += (double)p.dev.job[k].nwb * p.dev.job[k].c * p.dev.job[k].nb / 2;
+    for (int k = 0; k < nj; k++) adds += (double)p.jobs[k].nwb * p.jobs[k].c * p.jobs[k].nb / 2;
     ProfScope ps(g1 ? "msm_bitplanes_g1" : "msm_bitplanes_g2", st, adds);
     // block size: about two bucket additions per thread (64 to BP_THREADS threads)
     uint32_t per_block = 1;
-    for (int k = 0; k < p.dev.njobs; k++)
-      per_block = std::max(per_block, (p.dev.job[k].nb / 2 + p.dev.job[k].bpb - 1) / p.dev.job[k].bpb);
+    for (int k = 0; k < nj; k++)
+      per_block = std::max(per_block, (p.jobs[k].nb / 2 + p.jobs[k].bpb - 1) / p.jobs[k].bpb);
     unsigned bp_threads = 64;
     while (bp_threads < (unsigned)BP_THREADS && bp_threads * 2 < per_block) bp_threads *= 2;
-    hipLaunchKernelGGL(k_msm_bitplanes<F>, dim3((unsigned)p.bp_blocks), dim3(bp_threads), 0, st, p.dev, buckets,
+    hipLaunchKernelGGL(k_msm_bitplanes<F>, dim3((unsigned)p.bp_blocks), dim3(bp_threads), 0, st, dev, buckets,
                        bp_part);
     ZK_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_msm_plane_sums<F>, dim3((unsigned)p.nplanes), dim3(64), 0, st, p.dev, bp_part, win);
+    hipLaunchKernelGGL(k_msm_plane_sums<F>, dim3((unsigned)p.nplanes), dim3(64), 0, st, dev, bp_part, win);
     ZK_HIP(hipGetLastError());
   }
   ZK_HIP(hipMemcpyAsync(win_host, win, p.nplanes * XW * 4, hipMemcpyDeviceToHost, st));

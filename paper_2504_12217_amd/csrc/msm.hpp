@@ -23,9 +23,6 @@ struct MsmInput {
   int pre_nw = 0;
 };
 
-// At most this many MSMs share one device pipeline (a batch).
-constexpr int MSM_MAX_JOBS = 8;
-
 // An MSM enqueued on a stream; its bit-plane sums land in pinned host memory.
 struct MsmPending {
   bool empty = true;
@@ -34,9 +31,10 @@ struct MsmPending {
   const uint32_t* win_host = nullptr;
 };
 
-// Enqueue one device pipeline for njobs MSMs over the same group, with no
-// host synchronization; the workspace must not be used by anything else until
-// the stream completes.  pend[q] receives job q's pending result.
+// Enqueue one device pipeline for njobs MSMs (any number) over the same
+// group, with no host synchronization; the workspace must not be used by
+// anything else until the stream completes.  pend[q] receives job q's
+// pending result.
 void msm_enqueue_batch_g1(const MsmInput* in, int njobs, Workspace& ws, hipStream_t st, MsmPending* pend);
 void msm_enqueue_batch_g2(const MsmInput* in, int njobs, Workspace& ws, hipStream_t st, MsmPending* pend);
 // After the stream has completed: combine one job's bit planes (host).

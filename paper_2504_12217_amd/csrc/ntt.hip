@@ -36,7 +36,8 @@ constexpr int POW_BITS = NTT_POW_BITS;
 constexpr int MAX_LOG = NTT_MAX_LOG;
 
 struct PassParams {
-  uint32_t* data[NTT_MAX_BATCH];  // one vector per blockIdx.y
+  uint32_t* data[NTT_MAX_BATCH];  // one vector per blockIdx.y ...
+  uint32_t* const* table;         // ... or, if set, a device table of vectors
   int log_n, log_m, k, log_g;
   int dit, inverse, twiddle;
   int first, last;
@@ -67,7 +68,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_pass(PassParams p, NttTable
   const uint32_t gmask = (1u << B) - 1u;
   const uint32_t gamma0 = blockIdx.x * G;
   const int tw_shift = MAX_LOG - p.log_m;
-  uint32_t* const data = p.data[blockIdx.y];
+  uint32_t* const data = p.table ? p.table[blockIdx.y] : p.data[blockIdx.y];
 
   // ---- load (global -> registers -> LDS), with first-pass fusions and DIT twiddles
   for (uint32_t e = threadIdx.x; e < E; e += blockDim.x) {
@@ -295,10 +296,12 @@ const NttTables& ntt_tables(int device) {
   return dt->t;
 }
 
-void ntt_launch_batch(uint32_t* const* data, int nvec, int log_n, bool dit, bool inverse, const NttFuse& fuse,
-                      hipStream_t st) {
+namespace {
+
+void ntt_launch_impl(uint32_t* const* data, uint32_t* const* dev_table, int nvec, int log_n, bool dit, bool inverse,
+                     const NttFuse& fuse, hipStream_t st) {
   ZK_REQUIRE(log_n >= 0 && log_n <= MAX_LOG, "log_n out of range");
-  ZK_REQUIRE(nvec >= 1 && nvec <= NTT_MAX_BATCH, "NTT batch size out of range");
+  ZK_REQUIRE(nvec >= 1 && nvec <= (dev_table ? 65535 : NTT_MAX_BATCH), "NTT batch size out of range");
   const NttTables& T = ntt_tables(current_device());
   const int L = log_n;
   // small transforms use 256-element workgroups so that a pass still spreads
@@ -319,7 +322,10 @@ void ntt_launch_batch(uint32_t* const* data, int nvec, int log_n, bool dit, bool
     const int k = ks[j];
     const int B = log_ms[j] - k;
     PassParams p{};
-    for (int v = 0; v < nvec; v++) p.data[v] = data[v];
+    if (dev_table)
+      p.table = dev_table;
+    else
+      for (int v = 0; v < nvec; v++) p.data[v] = data[v];
     p.log_n = L;
     p.log_m = log_ms[j];
     p.k = k;
@@ -347,6 +353,18 @@ void ntt_launch_batch(uint32_t* const* data, int nvec, int log_n, bool dit, bool
     hipLaunchKernelGGL(k_ntt_pass, dim3(grid, nvec), dim3(threads), lds, st, p, T);
     ZK_HIP(hipGetLastError());
   }
+}
+
+}  // namespace
+
+void ntt_launch_batch(uint32_t* const* data, int nvec, int log_n, bool dit, bool inverse, const NttFuse& fuse,
+                      hipStream_t st) {
+  ntt_launch_impl(data, nullptr, nvec, log_n, dit, inverse, fuse, st);
+}
+
+void ntt_launch_table(uint32_t* const* dev_table, int nvec, int log_n, bool dit, bool inverse, const NttFuse& fuse,
+                      hipStream_t st) {
+  ntt_launch_impl(nullptr, dev_table, nvec, log_n, dit, inverse, fuse, st);
 }
 
 void ntt_launch(uint32_t* data, int log_n, bool dit, bool inverse, const NttFuse& fuse, hipStream_t st) {

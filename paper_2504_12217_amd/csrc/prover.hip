@@ -25,6 +25,9 @@
 
 #include <array>
 #include <chrono>
+#include <algorithm>
+#include <thread>
+#include <map>
 #include <future>
 #include <cstring>
 
@@ -759,37 +762,43 @@ zkvc_pk* groth16_setup(const Layout& L, const host::HFr toxic[5], const host::HF
   put_raw(vk, (uint64_t)nic);
   vk.insert(vk.end(), ic_host.begin(), ic_host.end());
 
-  for (int lane = 0; lane < zkvc_pk::LANES; lane++) {
-    ZK_HIP(hipStreamCreateWithFlags(&pk->lanes[lane], hipStreamNonBlocking));
-    ZK_HIP(hipEventCreateWithFlags(&pk->done_ev[lane], hipEventDisableTiming));
-  }
-  ZK_HIP(hipEventCreateWithFlags(&pk->witness_ev, hipEventDisableTiming));
-  ZK_HIP(hipEventCreateWithFlags(&pk->quotient_ev, hipEventDisableTiming));
   pk->key_bytes = pk->qA.size() + pk->qB1.size() + pk->qB2.size() + pk->qL.size() + pk->qH.size() + pk->zpow.size();
   pk->ws.clear();  // setup scratch is not needed for proving
   return pk.release();
 }
 
 // ------------------------------------------------------------------ host: prove
+// q = (A B - C) / (g^N - 1) on the coset for a batch of proofs of one domain
+// size; tab lists (A, B, C) per proof; the result overwrites A.
+__global__ void k_qap_pointwise_batch(uint32_t* const* tab, uint64_t N, const uint32_t* zinv) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  uint32_t* A = tab[3 * blockIdx.y];
+  const uint32_t* B = tab[3 * blockIdx.y + 1];
+  const uint32_t* C = tab[3 * blockIdx.y + 2];
+  const Fr a = Fr::load(A + 8ull * i), b = Fr::load(B + 8ull * i), c = Fr::load(C + 8ull * i);
+  Fr::mul(Fr::sub(Fr::mul(a, b), c), Fr::load(zinv)).store(A + 8ull * i);
+}
+
+// flag |= 1 if some proof's h_{N-1} (the last element of its quotient, which
+// bit reversal leaves in place) is nonzero: the quotient of a satisfied
+// system has degree < N - 1.  The vectors come from a table (count of them)
+// or, without a table, `one` alone.
+__global__ void k_check_top(uint32_t* const* tab, const uint32_t* one, uint32_t count, uint64_t N, uint32_t* flag) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= count) return;
+  const uint32_t* h = (tab ? tab[j] : one) + 8ull * (N - 1);
+  uint32_t t = 0;
+#pragma unroll
+  for (int q = 0; q < 8; q++) t |= h[q];
+  if (t) atomicOr(flag, 1u);
+}
+
 namespace {
-enum ProveSlot { P_X = 20, P_W, P_Y, P_ASSIGN, P_AEV, P_BEV, P_CEV, P_XK, P_WK, P_PK, P_YZ, P_TOP, P_XH, P_WH };
+enum ProveSlot { P_X = 20, P_W, P_Y, P_ASSIGN, P_AEV, P_BEV, P_CEV, P_XK, P_WK, P_PK, P_YZ, P_XH, P_WH, P_YH };
+enum SharedSlot { C_TABLE = 60, C_FLAG };
 
-struct Events {
-  hipEvent_t e[6];
-  Events() {
-    for (auto& x : e) ZK_HIP(hipEventCreate(&x));
-  }
-  ~Events() {
-    for (auto& x : e) (void)hipEventDestroy(x);
-  }
-  float ms(int a, int b) const {
-    float t = 0.f;
-    (void)hipEventElapsedTime(&t, e[a], e[b]);
-    return t;
-  }
-};
-
-// One MSM of the proof: a query segment (or the H query) and its scalars.
+// One MSM of a proof: a query segment (or the H query) and its scalars.
 struct MsmJob {
   int group;  // 1 = G1, 2 = G2
   int query;  // ZKVC_Q_*
@@ -814,7 +823,7 @@ std::vector<MsmJob> msm_jobs(const zkvc_pk* pk, const uint32_t* assign, const ui
     }
     jobs.push_back(j);
   };
-  if (L.N > 1) {  // H first: the largest
+  if (L.N > 1) {
     MsmJob j;
     j.group = 1;
     j.query = ZKVC_Q_H;
@@ -838,33 +847,37 @@ std::vector<MsmJob> msm_jobs(const zkvc_pk* pk, const uint32_t* assign, const ui
   return jobs;
 }
 
-}  // namespace
+// Device buffers of one proof in flight.
+struct Slot {
+  uint32_t *assign, *aev, *bev, *cev;
+  int32_t* yh;  // pinned copy of Y
+};
 
-void groth16_prove(zkvc_pk* pk, const int8_t* X, const int8_t* W, const host::HFr& r, const host::HFr& s, int32_t* Y,
-                   zkvc_proof* out, hipStream_t st) {
+// Witness and evaluation vectors of one proof (X, W through pinned staging,
+// Y back to pinned memory: no host wait inside the enqueue).
+Slot enqueue_witness(const ProveJob& J, Workspace& ws, hipStream_t st) {
+  const zkvc_pk* pk = J.pk;
   const Layout& L = pk->L;
-  Workspace& ws = pk->ws;
   const uint64_t N = L.N;
   const uint32_t a = L.a, n = L.n, b = L.b;
-  const NttTables& T = ntt_tables(pk->device);
-  Events ev;
-  const auto host_t0 = std::chrono::steady_clock::now();
-  ZK_HIP(hipEventRecord(ev.e[0], st));
-
+  Slot S;
   int8_t* dX = ws.get<int8_t>(P_X, (size_t)a * n);
   int8_t* dW = ws.get<int8_t>(P_W, (size_t)n * b);
   int32_t* dY = ws.get<int32_t>(P_Y, (size_t)a * b * 4);
-  uint32_t* assign = ws.get(P_ASSIGN, L.nv * 32);
-  uint32_t* aev = ws.get(P_AEV, N * 32);
-  uint32_t* bev = ws.get(P_BEV, N * 32);
-  uint32_t* cev = ws.get(P_CEV, N * 32);
-  ZK_HIP(hipMemcpyAsync(dX, X, (size_t)a * n, hipMemcpyHostToDevice, st));
-  ZK_HIP(hipMemcpyAsync(dW, W, (size_t)n * b, hipMemcpyHostToDevice, st));
-
-  // ---- witness and evaluation vectors
+  S.assign = ws.get(P_ASSIGN, L.nv * 32);
+  S.aev = ws.get(P_AEV, N * 32);
+  S.bev = ws.get(P_BEV, N * 32);
+  S.cev = ws.get(P_CEV, N * 32);
+  int8_t* xh = ws.host<int8_t>(P_XH, (size_t)a * n);
+  int8_t* wh = ws.host<int8_t>(P_WH, (size_t)n * b);
+  S.yh = ws.host<int32_t>(P_YH, (size_t)a * b * 4);
+  std::memcpy(xh, J.X, (size_t)a * n);
+  std::memcpy(wh, J.W, (size_t)n * b);
+  ZK_HIP(hipMemcpyAsync(dX, xh, (size_t)a * n, hipMemcpyHostToDevice, st));
+  ZK_HIP(hipMemcpyAsync(dW, wh, (size_t)n * b, hipMemcpyHostToDevice, st));
   hipLaunchKernelGGL(k_matmul, dim3(cdiv(b, 256), a), dim3(256), 0, st, dX, dW, a, n, b, dY);
   ZK_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_assign_public, dim3(cdiv(L.aux_start, 256)), dim3(256), 0, st, dX, dW, dY, a, n, b, assign);
+  hipLaunchKernelGGL(k_assign_public, dim3(cdiv(L.aux_start, 256)), dim3(256), 0, st, dX, dW, dY, a, n, b, S.assign);
   ZK_HIP(hipGetLastError());
   if (kind_uses_z(L.kind)) {
     uint32_t* xk = ws.get(P_XK, (size_t)n * 32);
@@ -876,156 +889,56 @@ void groth16_prove(zkvc_pk* pk, const int8_t* X, const int8_t* W, const host::HF
     hipLaunchKernelGGL(k_crpc_yz, dim3(YZ_BLOCKS), dim3(RED_THREADS), 0, st, dY, a * b, pk->zpow.get(), yz);
     ZK_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_crpc_rows, dim3(1), dim3(RED_THREADS), 0, st, L.kind, n, L.aux_start, xk, wk, pkk, yz,
-                       assign, aev, bev, cev);
+                       S.assign, S.aev, S.bev, S.cev);
     ZK_HIP(hipGetLastError());
   } else {
-    PlainRowParams rp{L.kind, a, n, b, L.m, L.aux_start, dX, dW, dY, assign, aev, bev, cev};
+    PlainRowParams rp{L.kind, a, n, b, L.m, L.aux_start, dX, dW, dY, S.assign, S.aev, S.bev, S.cev};
     hipLaunchKernelGGL(k_rows_plain, dim3(cdiv(L.m, 256)), dim3(256), 0, st, rp);
     ZK_HIP(hipGetLastError());
   }
-  hipLaunchKernelGGL(k_rows_tail, dim3(cdiv(N - L.m, 256)), dim3(256), 0, st, L.m, L.ell, N, assign, aev, bev, cev);
+  hipLaunchKernelGGL(k_rows_tail, dim3(cdiv(N - L.m, 256)), dim3(256), 0, st, L.m, L.ell, N, S.assign, S.aev, S.bev,
+                     S.cev);
   ZK_HIP(hipGetLastError());
-  ZK_HIP(hipMemcpyAsync(Y, dY, (size_t)a * b * 4, hipMemcpyDeviceToHost, st));
-  ZK_HIP(hipEventRecord(ev.e[1], st));
-
-  // ---- MSM jobs.  Those that need only the assignment run on their own
-  // lanes from the end of the witness on, overlapping the quotient: one
-  // batched pipeline for the G1 queries (A, B1, L) and one for B2 in G2.  B2,
-  // then the quotient and the H MSM (the critical path) are enqueued first.
-  std::vector<MsmJob> jobs = msm_jobs(pk, assign, aev);
-  std::vector<MsmInput> in_g1, in_g2, in_h;
-  std::vector<int> query_g1;
-  for (const MsmJob& j : jobs) {
-    if (j.query == ZKVC_Q_H) {
-      in_h.push_back(j.in);
-    } else if (j.group == 2) {
-      in_g2.push_back(j.in);
-    } else {
-      in_g1.push_back(j.in);
-      query_g1.push_back(j.query);
-    }
-  }
-  ZK_REQUIRE(in_g1.size() <= (size_t)MSM_MAX_JOBS && in_g2.size() <= (size_t)MSM_MAX_JOBS, "too many query segments");
-  MsmPending pend_g1[MSM_MAX_JOBS], pend_g2[MSM_MAX_JOBS], pend_h[1];
-  ZK_HIP(hipEventRecord(pk->witness_ev, st));
-  // B2 (G2, the longest chain of dependent group operations) goes first
-  ZK_HIP(hipStreamWaitEvent(pk->lanes[zkvc_pk::LANE_G2], pk->witness_ev, 0));
-  msm_enqueue_batch_g2(in_g2.data(), (int)in_g2.size(), pk->msm_ws[zkvc_pk::LANE_G2], pk->lanes[zkvc_pk::LANE_G2],
-                       pend_g2);
-  ZK_HIP(hipEventRecord(pk->done_ev[zkvc_pk::LANE_G2], pk->lanes[zkvc_pk::LANE_G2]));
-
-  // ---- QAP quotient h: iNTT (DIF, natural -> bit-reversed coefficients),
-  // coset NTT (DIT, bit-reversed -> natural evaluations on g H), pointwise
-  // (A B - C)/(g^N - 1), inverse coset NTT (DIF: h in bit-reversed order).
-  const int Lg = L.log_n;
-  {
-    uint32_t* const vecs[3] = {aev, bev, cev};
-    NttFuse f1;
-    f1.in_canonical = true;
-    ntt_launch_batch(vecs, 3, Lg, false, true, f1, st);
-    NttFuse f2;
-    f2.pre_coset = 1;
-    f2.pre_bitrev = true;
-    f2.pre_const = T.ninv + 8 * Lg;
-    ntt_launch_batch(vecs, 3, Lg, true, false, f2, st);
-  }
-  hipLaunchKernelGGL(k_qap_pointwise, dim3(cdiv(N, 256)), dim3(256), 0, st, aev, bev, cev, N,
-                     T.coset_zinv + 8 * Lg);
-  ZK_HIP(hipGetLastError());
-  {
-    NttFuse f;
-    f.post_const = T.ninv + 8 * Lg;
-    f.post_coset = -1;
-    f.post_bitrev = true;
-    ntt_launch(aev, Lg, false, true, f, st);
-  }
-  // h_{N-1} sits at the last position (bitrev of N-1 is N-1); it must be zero
-  uint32_t* top = ws.host<uint32_t>(P_TOP, 32);
-  ZK_HIP(hipMemcpyAsync(top, aev + 8 * (N - 1), 32, hipMemcpyDeviceToHost, st));
-  ZK_HIP(hipEventRecord(ev.e[2], st));
-
-  // ---- the H MSM follows the quotient on its own lane; then the other
-  // lanes.  Each lane's plane sums are combined on a host thread as soon as
-  // that lane completes, overlapping the lanes still running on the device.
-  ZK_HIP(hipEventRecord(pk->quotient_ev, st));
-  ZK_HIP(hipStreamWaitEvent(pk->lanes[zkvc_pk::LANE_H], pk->quotient_ev, 0));
-  msm_enqueue_batch_g1(in_h.data(), (int)in_h.size(), pk->msm_ws[zkvc_pk::LANE_H], pk->lanes[zkvc_pk::LANE_H], pend_h);
-  ZK_HIP(hipEventRecord(pk->done_ev[zkvc_pk::LANE_H], pk->lanes[zkvc_pk::LANE_H]));
-  ZK_HIP(hipStreamWaitEvent(pk->lanes[zkvc_pk::LANE_G1], pk->witness_ev, 0));
-  msm_enqueue_batch_g1(in_g1.data(), (int)in_g1.size(), pk->msm_ws[zkvc_pk::LANE_G1], pk->lanes[zkvc_pk::LANE_G1],
-                       pend_g1);
-  ZK_HIP(hipEventRecord(pk->done_ev[zkvc_pk::LANE_G1], pk->lanes[zkvc_pk::LANE_G1]));
-
-  for (int lane = 0; lane < zkvc_pk::LANES; lane++) ZK_HIP(hipStreamWaitEvent(st, pk->done_ev[lane], 0));
-  ZK_HIP(hipEventRecord(ev.e[3], st));
-
-  // ---- host side, one thread per lane as each lane completes: the plane
-  // sums by Horner's rule, then everything that lane's results allow.  The G1
-  // lane yields A, B1 and s A + r B1 - r s delta (one shared doubling chain,
-  // off the critical path); the G2 lane yields B; the H lane only its sum.
-  uint64_t rw[4], sw[4], rsw[4];
-  r.to_u64(rw);
-  s.to_u64(sw);
-  host::HFr::mul(r, s).to_u64(rsw);
-  const size_t ng1 = in_g1.size(), ng2 = in_g2.size(), nh = in_h.size();
-  struct G1Part {
-    host::G1J A, L, sA_rB1;
-  };
-  auto f_g1 = std::async(std::launch::async, [&] {
-    ZK_HIP(hipEventSynchronize(pk->done_ev[zkvc_pk::LANE_G1]));
-    host::G1J msmA = host::G1J::inf(), msmB1 = host::G1J::inf(), msmL = host::G1J::inf();
-    for (size_t q = 0; q < ng1; q++) {
-      const host::G1J v = msm_finish_g1(pend_g1[q]);
-      switch (query_g1[q]) {
-        case ZKVC_Q_A: msmA = host::G1J::add(msmA, v); break;
-        case ZKVC_Q_B1: msmB1 = host::G1J::add(msmB1, v); break;
-        default: msmL = host::G1J::add(msmL, v); break;
-      }
-    }
-    G1Part o;
-    o.A = host::G1J::add(host::G1J::add(pk->alpha1, msmA), pk->delta1_table.mul(rw));
-    const host::G1J B1 = host::G1J::add(host::G1J::add(pk->beta1, msmB1), pk->delta1_table.mul(sw));
-    o.sA_rB1 = host::G1J::add(host::G1J::mul2(o.A, sw, B1, rw), host::G1J::neg(pk->delta1_table.mul(rsw)));
-    o.L = msmL;
-    return o;
-  });
-  auto f_g2 = std::async(std::launch::async, [&] {
-    ZK_HIP(hipEventSynchronize(pk->done_ev[zkvc_pk::LANE_G2]));
-    host::G2J msmB2 = host::G2J::inf();
-    for (size_t q = 0; q < ng2; q++) msmB2 = host::G2J::add(msmB2, msm_finish_g2(pend_g2[q]));
-    return host::G2J::add(host::G2J::add(pk->beta2, msmB2), pk->delta2_table.mul(sw));
-  });
-  auto f_h = std::async(std::launch::async, [&] {
-    ZK_HIP(hipEventSynchronize(pk->done_ev[zkvc_pk::LANE_H]));
-    host::G1J msmH = host::G1J::inf();
-    for (size_t q = 0; q < nh; q++) msmH = host::G1J::add(msmH, msm_finish_g1(pend_h[q]));
-    return msmH;
-  });
-  ZK_HIP(hipStreamSynchronize(st));
-  for (int q = 0; q < 8; q++)
-    if (top[q]) throw Error(ZKVC_EDEVICE, "internal error: the witness does not satisfy the circuit");
-  const auto asm_t0 = std::chrono::steady_clock::now();
-  const G1Part g1 = f_g1.get();
-  const host::G2J B = f_g2.get();
-  const host::G1J msmH = f_h.get();
-  // C = sum_aux a_i L_i + h(tau) t(tau)/delta + s A + r B1 - r s delta
-  const host::G1J C = host::G1J::add(host::G1J::add(g1.L, msmH), g1.sA_rB1);
-  g1_to_abi(g1.A, &out->A);
-  g2_to_abi(B, &out->B);
-  g1_to_abi(C, &out->C);
-  const auto host_t1 = std::chrono::steady_clock::now();
-
-  pk->last.witness_ms = ev.ms(0, 1);
-  pk->last.ntt_ms = ev.ms(1, 2);
-  pk->last.msm_ms = ev.ms(2, 3);
-  pk->last.host_ms = std::chrono::duration<float, std::milli>(host_t1 - asm_t0).count();
-  pk->last.total_ms = std::chrono::duration<float, std::milli>(host_t1 - host_t0).count();
+  ZK_HIP(hipMemcpyAsync(S.yh, dY, (size_t)a * b * 4, hipMemcpyDeviceToHost, st));
+  return S;
 }
 
-}  // namespace zkvc
+// Runs fn(i) for i < n on up to `threads` host threads.
+template <class Fn>
+void parallel_for(size_t n, size_t threads, Fn&& fn) {
+  threads = std::max<size_t>(1, std::min(threads, n));
+  if (threads == 1) {
+    for (size_t i = 0; i < n; i++) fn(i);
+    return;
+  }
+  std::vector<std::future<void>> fs;
+  for (size_t t = 0; t < threads; t++)
+    fs.push_back(std::async(std::launch::async, [&, t] {
+      for (size_t i = t; i < n; i += threads) fn(i);
+    }));
+  for (auto& f : fs) f.get();
+}
 
-zkvc_pk::~zkvc_pk() {
-  // wait for anything still queued on this key's streams, then release them
+size_t host_threads() {
+  const unsigned hc = std::thread::hardware_concurrency();
+  return hc ? std::min<size_t>(16, std::max<size_t>(1, hc / 2)) : 4;
+}
+
+}  // namespace
+
+ProveCtx::ProveCtx() {
+  device = current_device();
+  for (int lane = 0; lane < LANES; lane++) {
+    ZK_HIP(hipStreamCreateWithFlags(&lanes[lane], hipStreamNonBlocking));
+    ZK_HIP(hipEventCreateWithFlags(&done_ev[lane], hipEventDisableTiming));
+  }
+  ZK_HIP(hipEventCreateWithFlags(&witness_ev, hipEventDisableTiming));
+  ZK_HIP(hipEventCreateWithFlags(&quotient_ev, hipEventDisableTiming));
+  for (auto& e : ev) ZK_HIP(hipEventCreate(&e));
+}
+
+ProveCtx::~ProveCtx() {
+  // wait for anything still queued on the lanes, then release them
   for (int lane = 0; lane < LANES; lane++) {
     if (lanes[lane]) {
       (void)hipStreamSynchronize(lanes[lane]);
@@ -1035,4 +948,237 @@ zkvc_pk::~zkvc_pk() {
   }
   if (witness_ev) (void)hipEventDestroy(witness_ev);
   if (quotient_ev) (void)hipEventDestroy(quotient_ev);
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
 }
+
+void groth16_prove_batch(ProveCtx& ctx, const ProveJob* jobs, size_t nj, hipStream_t st) {
+  ZK_REQUIRE(nj >= 1, "empty proof batch");
+  ZK_REQUIRE(current_device() == ctx.device, "proof context of another device");
+  for (size_t j = 0; j < nj; j++)
+    ZK_REQUIRE(jobs[j].pk && jobs[j].pk->device == ctx.device, "a proving key lives on another device");
+  const auto host_t0 = std::chrono::steady_clock::now();
+  const NttTables& T = ntt_tables(ctx.device);
+  while (ctx.slot_ws.size() < nj) ctx.slot_ws.emplace_back(new Workspace());
+  ZK_HIP(hipEventRecord(ctx.ev[0], st));
+
+  // ---- witnesses and evaluation vectors
+  std::vector<Slot> slots(nj);
+  for (size_t j = 0; j < nj; j++) slots[j] = enqueue_witness(jobs[j], *ctx.slot_ws[j], st);
+  ZK_HIP(hipEventRecord(ctx.ev[1], st));
+  ZK_HIP(hipEventRecord(ctx.witness_ev, st));
+
+  // ---- MSM jobs of every proof, by lane.  Those that need only the
+  // assignment run from the end of the witness on, overlapping the quotient:
+  // one pipeline for all G1 queries A, B1, L and one for B2 in G2; the H MSMs
+  // follow the quotient on the third lane.  B2 (the longest chain of
+  // dependent group operations), then the quotient and H (the critical path)
+  // are enqueued first.
+  std::vector<MsmInput> in_g1, in_g2, in_h;
+  std::vector<int> own_g1, query_g1, own_g2, own_h;
+  for (size_t j = 0; j < nj; j++) {
+    for (const MsmJob& m : msm_jobs(jobs[j].pk, slots[j].assign, slots[j].aev)) {
+      if (m.query == ZKVC_Q_H) {
+        in_h.push_back(m.in);
+        own_h.push_back((int)j);
+      } else if (m.group == 2) {
+        in_g2.push_back(m.in);
+        own_g2.push_back((int)j);
+      } else {
+        in_g1.push_back(m.in);
+        own_g1.push_back((int)j);
+        query_g1.push_back(m.query);
+      }
+    }
+  }
+  std::vector<MsmPending> pend_g1(in_g1.size()), pend_g2(in_g2.size()), pend_h(in_h.size());
+  hipStream_t lane_h = ctx.lanes[ProveCtx::LANE_H], lane_g1 = ctx.lanes[ProveCtx::LANE_G1],
+              lane_g2 = ctx.lanes[ProveCtx::LANE_G2];
+  ZK_HIP(hipStreamWaitEvent(lane_g2, ctx.witness_ev, 0));
+  msm_enqueue_batch_g2(in_g2.data(), (int)in_g2.size(), ctx.lane_ws[ProveCtx::LANE_G2], lane_g2, pend_g2.data());
+  ZK_HIP(hipEventRecord(ctx.done_ev[ProveCtx::LANE_G2], lane_g2));
+
+  // ---- QAP quotients: iNTT (DIF, natural -> bit-reversed coefficients),
+  // coset NTT (DIT, bit-reversed -> natural evaluations on g H), pointwise
+  // (A B - C)/(g^N - 1), inverse coset NTT (DIF: h in bit-reversed order).
+  // Proofs of one domain size share every launch.
+  std::map<int, std::vector<size_t>> by_size;
+  for (size_t j = 0; j < nj; j++) by_size[jobs[j].pk->L.log_n].push_back(j);
+  uint32_t* flag = ctx.shared.get(C_FLAG, 4);
+  uint32_t* flag_host = ctx.shared.host<uint32_t>(C_FLAG, 4);
+  fill_u32(flag, 0u, 1, st);
+  // device tables for groups of several proofs: (A, B, C) triples, then the A's
+  std::vector<uint32_t*> tab_v;
+  std::vector<size_t> tab_off;
+  for (auto& kv : by_size) {
+    tab_off.push_back(tab_v.size());
+    if (kv.second.size() < 2) continue;
+    for (size_t j : kv.second) {
+      tab_v.push_back(slots[j].aev);
+      tab_v.push_back(slots[j].bev);
+      tab_v.push_back(slots[j].cev);
+    }
+    for (size_t j : kv.second) tab_v.push_back(slots[j].aev);
+  }
+  uint32_t** tab_dev = nullptr;
+  if (!tab_v.empty()) {
+    const size_t bytes = tab_v.size() * sizeof(uint32_t*);
+    uint32_t** tab_host = ctx.shared.host<uint32_t*>(C_TABLE, bytes);
+    tab_dev = ctx.shared.get<uint32_t*>(C_TABLE, bytes);
+    std::memcpy(tab_host, tab_v.data(), bytes);
+    ZK_HIP(hipMemcpyAsync(tab_dev, tab_host, bytes, hipMemcpyHostToDevice, st));
+  }
+  size_t gi = 0;
+  for (auto& kv : by_size) {
+    const int Lg = kv.first;
+    const uint64_t N = 1ull << Lg;
+    const size_t k = kv.second.size();
+    NttFuse f1;
+    f1.in_canonical = true;
+    NttFuse f2;
+    f2.pre_coset = 1;
+    f2.pre_bitrev = true;
+    f2.pre_const = T.ninv + 8 * Lg;
+    NttFuse f3;
+    f3.post_const = T.ninv + 8 * Lg;
+    f3.post_coset = -1;
+    f3.post_bitrev = true;
+    const uint32_t* zinv = T.coset_zinv + 8 * Lg;
+    if (k == 1) {
+      const Slot& S = slots[kv.second[0]];
+      uint32_t* const vecs[3] = {S.aev, S.bev, S.cev};
+      ntt_launch_batch(vecs, 3, Lg, false, true, f1, st);
+      ntt_launch_batch(vecs, 3, Lg, true, false, f2, st);
+      hipLaunchKernelGGL(k_qap_pointwise, dim3(cdiv(N, 256)), dim3(256), 0, st, S.aev, S.bev, S.cev, N, zinv);
+      ZK_HIP(hipGetLastError());
+      ntt_launch(S.aev, Lg, false, true, f3, st);
+      hipLaunchKernelGGL(k_check_top, dim3(1), dim3(64), 0, st, (uint32_t* const*)nullptr, S.aev, 1u, N, flag);
+      ZK_HIP(hipGetLastError());
+    } else {
+      uint32_t** tg = tab_dev + tab_off[gi];
+      uint32_t** ta = tg + 3 * k;
+      ntt_launch_table(tg, (int)(3 * k), Lg, false, true, f1, st);
+      ntt_launch_table(tg, (int)(3 * k), Lg, true, false, f2, st);
+      hipLaunchKernelGGL(k_qap_pointwise_batch, dim3(cdiv(N, 256), (unsigned)k), dim3(256), 0, st, tg, N, zinv);
+      ZK_HIP(hipGetLastError());
+      ntt_launch_table(ta, (int)k, Lg, false, true, f3, st);
+      hipLaunchKernelGGL(k_check_top, dim3(cdiv(k, 64)), dim3(64), 0, st, ta, (const uint32_t*)nullptr, (uint32_t)k,
+                         N, flag);
+      ZK_HIP(hipGetLastError());
+    }
+    gi++;
+  }
+  ZK_HIP(hipMemcpyAsync(flag_host, flag, 4, hipMemcpyDeviceToHost, st));
+  ZK_HIP(hipEventRecord(ctx.ev[2], st));
+  ZK_HIP(hipEventRecord(ctx.quotient_ev, st));
+
+  // ---- the H lane after the quotients, then the G1 lane
+  ZK_HIP(hipStreamWaitEvent(lane_h, ctx.quotient_ev, 0));
+  msm_enqueue_batch_g1(in_h.data(), (int)in_h.size(), ctx.lane_ws[ProveCtx::LANE_H], lane_h, pend_h.data());
+  ZK_HIP(hipEventRecord(ctx.done_ev[ProveCtx::LANE_H], lane_h));
+  ZK_HIP(hipStreamWaitEvent(lane_g1, ctx.witness_ev, 0));
+  msm_enqueue_batch_g1(in_g1.data(), (int)in_g1.size(), ctx.lane_ws[ProveCtx::LANE_G1], lane_g1, pend_g1.data());
+  ZK_HIP(hipEventRecord(ctx.done_ev[ProveCtx::LANE_G1], lane_g1));
+  for (int lane = 0; lane < ProveCtx::LANES; lane++) ZK_HIP(hipStreamWaitEvent(st, ctx.done_ev[lane], 0));
+  ZK_HIP(hipEventRecord(ctx.ev[3], st));
+
+  // ---- host side, per lane as each lane completes: the plane sums by
+  // Horner's rule, then everything that lane's results allow.  The G1 lane
+  // yields A, B1 and s A + r B1 - r s delta (one shared doubling chain, off the
+  // critical path); the G2 lane yields B; the H lane only its sums.
+  const size_t nthr = host_threads();
+  struct G1Part {
+    host::G1J A, L, sA_rB1;
+  };
+  std::vector<G1Part> g1p(nj);
+  std::vector<host::G2J> Bp(nj);
+  std::vector<host::G1J> Hp(nj, host::G1J::inf());
+  // each proof's MSM results, indexed by lane entry
+  std::vector<std::vector<size_t>> g1_of(nj), g2_of(nj);
+  for (size_t q = 0; q < own_g1.size(); q++) g1_of[own_g1[q]].push_back(q);
+  for (size_t q = 0; q < own_g2.size(); q++) g2_of[own_g2[q]].push_back(q);
+  auto f_g1 = std::async(std::launch::async, [&] {
+    ZK_HIP(hipEventSynchronize(ctx.done_ev[ProveCtx::LANE_G1]));
+    parallel_for(nj, nthr, [&](size_t j) {
+      const ProveJob& J = jobs[j];
+      const zkvc_pk* pk = J.pk;
+      uint64_t rw[4], sw[4], rsw[4];
+      J.r.to_u64(rw);
+      J.s.to_u64(sw);
+      host::HFr::mul(J.r, J.s).to_u64(rsw);
+      host::G1J msmA = host::G1J::inf(), msmB1 = host::G1J::inf(), msmL = host::G1J::inf();
+      for (size_t q : g1_of[j]) {
+        const host::G1J v = msm_finish_g1(pend_g1[q]);
+        switch (query_g1[q]) {
+          case ZKVC_Q_A: msmA = host::G1J::add(msmA, v); break;
+          case ZKVC_Q_B1: msmB1 = host::G1J::add(msmB1, v); break;
+          default: msmL = host::G1J::add(msmL, v); break;
+        }
+      }
+      G1Part& o = g1p[j];
+      o.A = host::G1J::add(host::G1J::add(pk->alpha1, msmA), pk->delta1_table.mul(rw));
+      const host::G1J B1 = host::G1J::add(host::G1J::add(pk->beta1, msmB1), pk->delta1_table.mul(sw));
+      o.sA_rB1 = host::G1J::add(host::G1J::mul2(o.A, sw, B1, rw), host::G1J::neg(pk->delta1_table.mul(rsw)));
+      o.L = msmL;
+    });
+  });
+  auto f_g2 = std::async(std::launch::async, [&] {
+    ZK_HIP(hipEventSynchronize(ctx.done_ev[ProveCtx::LANE_G2]));
+    parallel_for(nj, nthr / 2 + 1, [&](size_t j) {
+      uint64_t sw[4];
+      jobs[j].s.to_u64(sw);
+      host::G2J msmB2 = host::G2J::inf();
+      for (size_t q : g2_of[j]) msmB2 = host::G2J::add(msmB2, msm_finish_g2(pend_g2[q]));
+      Bp[j] = host::G2J::add(host::G2J::add(jobs[j].pk->beta2, msmB2), jobs[j].pk->delta2_table.mul(sw));
+    });
+  });
+  auto f_h = std::async(std::launch::async, [&] {
+    ZK_HIP(hipEventSynchronize(ctx.done_ev[ProveCtx::LANE_H]));
+    parallel_for(own_h.size(), nthr / 2 + 1, [&](size_t q) { Hp[own_h[q]] = msm_finish_g1(pend_h[q]); });
+  });
+  ZK_HIP(hipStreamSynchronize(st));
+  if (*flag_host) throw Error(ZKVC_EDEVICE, "internal error: a witness does not satisfy its circuit");
+  const auto asm_t0 = std::chrono::steady_clock::now();
+  f_g1.get();
+  f_g2.get();
+  f_h.get();
+  for (size_t j = 0; j < nj; j++) {
+    const Layout& L = jobs[j].pk->L;
+    // C = sum_aux a_i L_i + h(tau) t(tau)/delta + s A + r B1 - r s delta
+    const host::G1J C = host::G1J::add(host::G1J::add(g1p[j].L, Hp[j]), g1p[j].sA_rB1);
+    g1_to_abi(g1p[j].A, &jobs[j].out->A);
+    g2_to_abi(Bp[j], &jobs[j].out->B);
+    g1_to_abi(C, &jobs[j].out->C);
+    std::memcpy(jobs[j].Y, slots[j].yh, (size_t)L.a * L.b * 4);
+  }
+  const auto host_t1 = std::chrono::steady_clock::now();
+  auto ms = [&](int a, int b) {
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, ctx.ev[a], ctx.ev[b]);
+    return t;
+  };
+  ctx.last.witness_ms = ms(0, 1);
+  ctx.last.ntt_ms = ms(1, 2);
+  ctx.last.msm_ms = ms(2, 3);
+  ctx.last.host_ms = std::chrono::duration<float, std::milli>(host_t1 - asm_t0).count();
+  ctx.last.total_ms = std::chrono::duration<float, std::milli>(host_t1 - host_t0).count();
+}
+
+void groth16_prove(zkvc_pk* pk, const int8_t* X, const int8_t* W, const host::HFr& r, const host::HFr& s, int32_t* Y,
+                   zkvc_proof* out, hipStream_t st) {
+  if (!pk->ctx) pk->ctx.reset(new ProveCtx());
+  ProveJob j;
+  j.pk = pk;
+  j.X = X;
+  j.W = W;
+  j.r = r;
+  j.s = s;
+  j.Y = Y;
+  j.out = out;
+  groth16_prove_batch(*pk->ctx, &j, 1, st);
+  pk->last = pk->ctx->last;
+}
+
+}  // namespace zkvc
+
+zkvc_pk::~zkvc_pk() = default;

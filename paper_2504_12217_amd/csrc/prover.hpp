@@ -49,12 +49,36 @@ bool kind_uses_z(uint32_t kind);
 
 }  // namespace zkvc
 
-// The opaque proving key of the C ABI.
-struct zkvc_pk {
-  // MSM lanes: the H query (after the quotient), the other G1 queries and the
-  // G2 query (both right after the witness) run concurrently.
+namespace zkvc {
+
+// Device and host state for proofs in flight: the three MSM lanes (streams),
+// their events, one workspace per lane, and one workspace per proof of a
+// batch (witness, evaluation vectors, quotient, pinned staging).  A proving
+// key owns one for its single proofs; the batch entry point keeps one per
+// (device, stream).  Not thread-safe: callers serialize its use.
+struct ProveCtx {
   static constexpr int LANES = 3;
   enum Lane { LANE_H = 0, LANE_G1 = 1, LANE_G2 = 2 };
+  ProveCtx();
+  ~ProveCtx();
+  ProveCtx(const ProveCtx&) = delete;
+  ProveCtx& operator=(const ProveCtx&) = delete;
+  int device = 0;
+  hipStream_t lanes[LANES] = {};
+  hipEvent_t witness_ev = nullptr;   // assignments complete
+  hipEvent_t quotient_ev = nullptr;  // every h complete
+  hipEvent_t done_ev[LANES] = {};    // lane's batch complete
+  hipEvent_t ev[4] = {};             // stage timing
+  Workspace lane_ws[LANES];
+  Workspace shared;                  // batch-level tables and flags
+  std::vector<std::unique_ptr<Workspace>> slot_ws;
+  zkvc_prove_stats last{};
+};
+
+}  // namespace zkvc
+
+// The opaque proving key of the C ABI.
+struct zkvc_pk {
   ~zkvc_pk();
   zkvc::Layout L;
   int device = 0;
@@ -67,12 +91,8 @@ struct zkvc_pk {
   zkvc::host::G2J beta2, delta2;
   zkvc::host::FixedBaseTable<zkvc::host::HFq> delta1_table;
   zkvc::host::FixedBaseTable<zkvc::host::HFq2> delta2_table;
-  zkvc::Workspace ws;                  // witness, evaluation vectors, quotient
-  zkvc::Workspace msm_ws[LANES];       // one per lane
-  hipStream_t lanes[LANES] = {};
-  hipEvent_t witness_ev = nullptr;     // assignment complete
-  hipEvent_t quotient_ev = nullptr;    // h complete
-  hipEvent_t done_ev[LANES] = {};      // lane's batch complete
+  zkvc::Workspace ws;                     // setup scratch
+  std::unique_ptr<zkvc::ProveCtx> ctx;    // single proofs (created on first use)
   std::mutex mu;
   zkvc_prove_stats last{};
   size_t key_bytes = 0;
@@ -84,7 +104,23 @@ namespace zkvc {
 zkvc_pk* groth16_setup(const Layout& L, const host::HFr toxic[5], const host::HFr* z, std::vector<uint8_t>& vk,
                        hipStream_t st);
 
-// Proves Y = X W.  X, W, Y are host arrays.
+// One proof of a batch: Y = X W for the key's shape; X, W, Y are host arrays.
+struct ProveJob {
+  const zkvc_pk* pk = nullptr;
+  const int8_t* X = nullptr;
+  const int8_t* W = nullptr;
+  host::HFr r, s;
+  int32_t* Y = nullptr;
+  zkvc_proof* out = nullptr;
+};
+
+// Proves every job (keys of any shapes and kinds, repeats allowed) with one
+// set of launches per stage: batched quotient transforms per domain size and
+// three MSM pipelines shared by all proofs.  Each proof equals its single
+// proof bit for bit.
+void groth16_prove_batch(ProveCtx& ctx, const ProveJob* jobs, size_t njobs, hipStream_t st);
+
+// Proves Y = X W (a batch of one on the key's own context).
 void groth16_prove(zkvc_pk* pk, const int8_t* X, const int8_t* W, const host::HFr& r, const host::HFr& s,
                    int32_t* Y, zkvc_proof* out, hipStream_t st);
 

@@ -64,6 +64,11 @@ class KernelStat(ctypes.Structure):
                 ("work", ctypes.c_double)]
 
 
+class ProveJob(ctypes.Structure):
+    _fields_ = [("pk", ctypes.c_void_p), ("X", ctypes.c_void_p), ("W", ctypes.c_void_p), ("r", Fr), ("s", Fr),
+                ("Y_out", ctypes.c_void_p), ("proof_out", ctypes.POINTER(Proof))]
+
+
 class ProveStats(ctypes.Structure):
     _fields_ = [("witness_ms", ctypes.c_float), ("ntt_ms", ctypes.c_float), ("msm_ms", ctypes.c_float),
                 ("host_ms", ctypes.c_float), ("total_ms", ctypes.c_float)]
@@ -78,6 +83,7 @@ _SIGS = {
     "zkvc_pk_free": (ctypes.c_int, [_VP]),
     "zkvc_prove": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(Fr), ctypes.POINTER(Fr), _VP,
                                   ctypes.POINTER(Proof), _VP]),
+    "zkvc_prove_batch": (ctypes.c_int, [ctypes.POINTER(ProveJob), ctypes.c_size_t, _VP]),
     "zkvc_verify": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, _VP, _VP, ctypes.POINTER(Proof)]),
     "zkvc_ntt_fr": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint32, _VP]),
     "zkvc_msm_g1": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, ctypes.c_uint32, ctypes.POINTER(G1), _VP]),
@@ -287,6 +293,32 @@ def prove(pk, X, W, r, s, stream=None):
     _check(lib().zkvc_prove(pk.handle, X.ctypes.data, W.ctypes.data, ctypes.byref(rr), ctypes.byref(ss),
                             Y.ctypes.data, ctypes.byref(out), _stream(stream)))
     return Y, out
+
+
+def prove_batch(jobs, stream=None):
+    """jobs: sequence of (pk, X, W, r, s); returns [(Y, Proof)] in the same order."""
+    keep = []
+    arr = (ProveJob * len(jobs))()
+    outs = []
+    for k, (pk, X, W, r, s) in enumerate(jobs):
+        info = pk.info()
+        X = np.ascontiguousarray(X, dtype=np.int8)
+        W = np.ascontiguousarray(W, dtype=np.int8)
+        if X.shape != (info.a, info.n) or W.shape != (info.n, info.b):
+            raise ValueError(f"job {k}: X or W does not match its proving key's shape")
+        Y = np.zeros((info.a, info.b), dtype=np.int32)
+        out = Proof()
+        keep += [X, W]
+        outs.append((Y, out))
+        arr[k].pk = pk.handle
+        arr[k].X = X.ctypes.data
+        arr[k].W = W.ctypes.data
+        arr[k].r = fr(r)
+        arr[k].s = fr(s)
+        arr[k].Y_out = Y.ctypes.data
+        arr[k].proof_out = ctypes.pointer(out)
+    _check(lib().zkvc_prove_batch(arr, len(jobs), _stream(stream)))
+    return outs
 
 
 def verify(vk, X, Y, proof):

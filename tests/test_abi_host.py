@@ -40,6 +40,7 @@ def test_struct_layouts_match_header(zk):
     assert ctypes.sizeof(zk.G2) == 128
     assert ctypes.sizeof(zk.Proof) == 256
     assert ctypes.sizeof(zk.Shape) == 16
+    assert ctypes.sizeof(zk.ProveJob) == 104  # 3 pointers, 2 zkvc_fr, 2 pointers
     text = open(HEADER).read()
     for name in ("ZKVC_PLAIN = 0", "ZKVC_CRPC_PSQ = 1", "ZKVC_PLAIN_ADD = 2", "ZKVC_PLAIN_PSQ = 3", "ZKVC_CRPC = 4"):
         assert name in text
@@ -53,6 +54,10 @@ def test_marshalling_round_trip(zk):
     assert zk.proof_from_bytes(bytes(256)).A.x[0] == 0
     assert zk.vk_header(b"ZKVC-VK1" + bytes([1, 0, 0, 0, 4, 0, 0, 0, 8, 0, 0, 0, 4, 0, 0, 0, 0, 0, 0, 0, 8, 0, 0, 0])) \
         == (4, 8, 4, 0, 8)
+
+
+def test_prove_batch_rejects_empty_batch_before_device_work(zk):
+    assert zk.lib().zkvc_prove_batch(None, 0, None) == zk.EINVAL
 
 
 def test_strerror_without_gpu(zk):
