@@ -202,6 +202,60 @@ def batch_section(zk, seed, count=64, reps=3):
             "setup_s_all_keys": round(setup_s, 3), "verified_sample": ok}
 
 
+SERVE_RATES = (5, 20, 50, 100, 200, 2000)  # the last one overloads a one-at-a-time prover
+
+
+def serve_section(zk, seed, rates=SERVE_RATES, max_batch=64):
+    """Poisson arrivals of CRPC+PSQ jobs over 10 shape classes (the batch mix plus the paper shape),
+    proved by the library's server; latency = submission to results written."""
+    import torch
+    classes = [(49, n, b) for n in BATCH_N for b in BATCH_B] + [(49, 320, 512)]
+    tox = synth.toxic_waste(seed)
+    z = synth.crpc_point(seed)
+    keys = {sh: zk.setup(*sh, zk.CRPC_PSQ, tox, z) for sh in classes}
+    # warm the server's workspaces with one batch of every class
+    srv = zk.Server(max_batch=max_batch)
+    for t in [srv.submit(keys[sh], *synth.matmul_inputs(seed, *sh), 3, 5) for sh in classes]:
+        srv.wait(t)
+    out = {}
+    for lam in rates:
+        count = int(min(400, max(40, 4 * lam)))
+        gaps = synth.exponential_gaps(seed + lam, lam, count)
+        pick = synth.rng(seed + lam, synth.STREAM_SHAPES).bit_generator.random_raw(count)
+        jobs = []
+        for j in range(count):
+            sh = classes[int(pick[j] % len(classes))]
+            X, W = synth.matmul_inputs(10000 * seed + 1000 * lam + j + 1, *sh)
+            r, s = synth.prover_randomness(seed + lam, job=j)
+            jobs.append((keys[sh], X, W, r, s))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        due = t0
+        tickets = []
+        for j, job in enumerate(jobs):
+            due += gaps[j]
+            pause = due - time.perf_counter()
+            if pause > 0:
+                time.sleep(pause)
+            tickets.append(srv.submit(*job))
+        res = [srv.wait(t)[2] for t in tickets]
+        span = time.perf_counter() - t0
+        lat = sorted(r.latency_ms for r in res)
+        out[f"{lam}_req_s"] = {"jobs": count, "proofs_per_s": round(count / span, 2),
+                               "p50_ms": round(lat[len(lat) // 2], 3),
+                               "p99_ms": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 3),
+                               "mean_batch": round(sum(r.batch_size for r in res) / count, 2),
+                               "max_batch": max(r.batch_size for r in res)}
+        log(f"served {lam} req/s: p50 {out[f'{lam}_req_s']['p50_ms']} ms, p99 {out[f'{lam}_req_s']['p99_ms']} ms")
+    srv.close()
+    for pk in keys.values():
+        pk.close()
+    return {"workload": "Poisson arrivals of CRPC+PSQ proof jobs, shapes uniform over 10 classes: a=49, (n, b) in "
+                        "{64,128,320}x{64,256,512} and (320, 512); keys resident in HBM; one server, continuous "
+                        f"batching (max {max_batch} per batch); latency = submission to proof on the host",
+            "rates": out}
+
+
 def cpu_baseline(X, W, tox, z, r, s, budget_frac=256):
     """The oracle prover's cost for one CRPC + PSQ proof of the paper shape.
 
@@ -261,6 +315,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-msm", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build proves on a single MI355X "
@@ -365,6 +420,9 @@ def main():
     if not args.no_batch:
         log("batched proving: 64 mixed-shape CRPC+PSQ proofs")
         out["batched_crpc_psq_64"] = batch_section(zkvc, seed)
+    if not args.no_serve:
+        log("served proving: Poisson arrivals")
+        out["served_crpc_psq"] = serve_section(zkvc, seed)
     out["paper_context"] = {"note": "the paper's CPU figures, other hardware (16-core Threadripper PRO 3955WX)",
                             "plain_prove_s_49x320x512": 180, "crpc_psq_prove_s_49x64x128_table2": 0.73}
     if not args.no_cpu_baseline:

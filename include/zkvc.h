@@ -127,6 +127,41 @@ typedef struct {
 int zkvc_prove_batch(const zkvc_prove_job* jobs, size_t njobs, void* hip_stream);
 
 /*
+ * Proving server (continuous batching).  One worker thread proves submitted
+ * jobs in batches: each batch takes every queued job that fits max_batch and
+ * memory_budget (bytes of estimated device workspace admitted at once; 0 = no
+ * limit; a single job is always admitted), and is enqueued while the
+ * previous batch is still on the device, so jobs that arrive during a batch
+ * overlap it.  Every result equals zkvc_prove's for the same job, bit for bit.
+ * The server is created on the current device and owns its own streams.
+ */
+typedef struct zkvc_server zkvc_server;
+typedef struct {
+  uint32_t max_batch;      /* most proofs per batch, >= 1 */
+  uint64_t memory_budget;  /* bytes of estimated workspace per batch, 0 = unlimited */
+} zkvc_server_config;
+typedef struct {
+  int32_t status;          /* ZKVC_OK, or the error code of the job's batch */
+  uint32_t batch_size;     /* proofs in the batch that carried the job */
+  double queue_ms;         /* submission to the start of its batch */
+  double latency_ms;       /* submission to Y and the proof written */
+} zkvc_server_result;
+/* Errors: ZKVC_EINVAL (null pointer, max_batch 0). */
+int zkvc_server_create(const zkvc_server_config* config, zkvc_server** server_out);
+/* Queues one job and returns its ticket.  X and W are copied before return;
+ * Y_out and proof_out must stay valid until zkvc_server_wait returns for the
+ * ticket.  Errors: ZKVC_EINVAL (null pointer, r or s >= r, key on another
+ * device, server stopping). */
+int zkvc_server_submit(zkvc_server* server, const zkvc_prove_job* job, uint64_t* ticket);
+/* Blocks until the job is done (results written), then reports it; each
+ * ticket is reported once.  Errors: ZKVC_EINVAL (unknown ticket),
+ * ZKVC_EDEVICE (the worker could not start). */
+int zkvc_server_wait(zkvc_server* server, uint64_t ticket, zkvc_server_result* result);
+/* Proves every job still queued, stops the worker and frees the server.
+ * NULL is accepted. */
+int zkvc_server_destroy(zkvc_server* server);
+
+/*
  * Verify (Section II; the Groth16 pairing-product equation), on the host.
  * vk: blob written by zkvc_setup; X: int8 a x n; Y: int32 a x b (the shape is
  * read from vk).  Returns 1 if the proof is valid for (X, Y), 0 if not

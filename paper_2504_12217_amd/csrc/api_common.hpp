@@ -40,6 +40,12 @@ int guarded(Fn&& fn) {
 // responsible for passing buffers of the documented size.)
 void require_device_range(const void* p, size_t bytes, const char* name);
 
+// A canonical Fr argument of the ABI (rejects values >= r with ZKVC_EINVAL).
+inline host::HFr fr_in(const zkvc_fr& v, const char* name) {
+  ZK_REQUIRE(host::HFr::canonical_ok(v.l), std::string(name) + " must be below the group order r");
+  return host::HFr::from_u32(v.l);
+}
+
 void g1_to_abi(const host::G1J& p, zkvc_g1* out);
 void g2_to_abi(const host::G2J& p, zkvc_g2* out);
 

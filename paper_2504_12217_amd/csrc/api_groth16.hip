@@ -13,11 +13,6 @@ using namespace zkvc;
 
 namespace {
 
-host::HFr fr_in(const zkvc_fr& v, const char* name) {
-  ZK_REQUIRE(host::HFr::canonical_ok(v.l), std::string(name) + " must be below the group order r");
-  return host::HFr::from_u32(v.l);
-}
-
 size_t vk_size(const Layout& L) { return 8 + 24 + 32 + 64 + 3 * 128 + 8 + 64 * (L.ell + 1); }
 
 }  // namespace
@@ -135,11 +130,12 @@ int zkvc_pk_info(const zkvc_pk* pk, zkvc_pk_info_t* info) {
     info->l_query = total(L.segL);
     info->h_query = L.N - 1;
     size_t ctx_bytes = 0;
-    if (pk->ctx) {
-      for (const Workspace& w : pk->ctx->lane_ws) ctx_bytes += w.bytes();
-      for (const auto& w : pk->ctx->slot_ws) ctx_bytes += w->bytes();
-      ctx_bytes += pk->ctx->shared.bytes();
-    }
+    if (pk->ctx)
+      for (const ProveGen& g : pk->ctx->gen) {
+        for (const Workspace& w : g.lane_ws) ctx_bytes += w.bytes();
+        for (const auto& w : g.slot_ws) ctx_bytes += w->bytes();
+        ctx_bytes += g.shared.bytes();
+      }
     info->device_bytes = pk->key_bytes + pk->ws.bytes() + ctx_bytes;
   });
 }

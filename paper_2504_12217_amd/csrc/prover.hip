@@ -928,13 +928,16 @@ size_t host_threads() {
 
 ProveCtx::ProveCtx() {
   device = current_device();
-  for (int lane = 0; lane < LANES; lane++) {
-    ZK_HIP(hipStreamCreateWithFlags(&lanes[lane], hipStreamNonBlocking));
-    ZK_HIP(hipEventCreateWithFlags(&done_ev[lane], hipEventDisableTiming));
+  for (int lane = 0; lane < LANES; lane++) ZK_HIP(hipStreamCreateWithFlags(&lanes[lane], hipStreamNonBlocking));
+  for (ProveGen& g : gen) {
+    ZK_HIP(hipEventCreateWithFlags(&g.witness_ev, hipEventDisableTiming));
+    ZK_HIP(hipEventCreateWithFlags(&g.quotient_ev, hipEventDisableTiming));
+    for (int lane = 0; lane < LANES; lane++) {
+      ZK_HIP(hipEventCreateWithFlags(&g.done_ev[lane], hipEventDisableTiming));
+      ZK_HIP(hipEventCreate(&g.lane_t[lane]));
+    }
+    for (auto& e : g.ev) ZK_HIP(hipEventCreate(&e));
   }
-  ZK_HIP(hipEventCreateWithFlags(&witness_ev, hipEventDisableTiming));
-  ZK_HIP(hipEventCreateWithFlags(&quotient_ev, hipEventDisableTiming));
-  for (auto& e : ev) ZK_HIP(hipEventCreate(&e));
 }
 
 ProveCtx::~ProveCtx() {
@@ -944,38 +947,67 @@ ProveCtx::~ProveCtx() {
       (void)hipStreamSynchronize(lanes[lane]);
       (void)hipStreamDestroy(lanes[lane]);
     }
-    if (done_ev[lane]) (void)hipEventDestroy(done_ev[lane]);
   }
-  if (witness_ev) (void)hipEventDestroy(witness_ev);
-  if (quotient_ev) (void)hipEventDestroy(quotient_ev);
-  for (auto& e : ev)
-    if (e) (void)hipEventDestroy(e);
+  for (ProveGen& g : gen) {
+    if (g.witness_ev) (void)hipEventSynchronize(g.witness_ev), (void)hipEventDestroy(g.witness_ev);
+    if (g.quotient_ev) (void)hipEventSynchronize(g.quotient_ev), (void)hipEventDestroy(g.quotient_ev);
+    for (int lane = 0; lane < LANES; lane++) {
+      if (g.done_ev[lane]) (void)hipEventDestroy(g.done_ev[lane]);
+      if (g.lane_t[lane]) (void)hipEventDestroy(g.lane_t[lane]);
+    }
+    for (auto& e : g.ev)
+      if (e) (void)hipEventDestroy(e);
+  }
 }
 
-void groth16_prove_batch(ProveCtx& ctx, const ProveJob* jobs, size_t nj, hipStream_t st) {
+// Everything a begun batch needs to be finished.
+struct BatchRun {
+  ProveCtx* ctx = nullptr;
+  int g = 0;
+  bool finished = false;
+  std::vector<ProveJob> jobs;
+  std::vector<Slot> slots;
+  std::vector<MsmInput> in_g1, in_g2, in_h;
+  std::vector<int> own_g1, query_g1, own_g2, own_h;
+  std::vector<MsmPending> pend_g1, pend_g2, pend_h;
+  const uint32_t* flag_host = nullptr;
+  std::chrono::steady_clock::time_point host_t0;
+};
+
+void BatchRunDeleter::operator()(BatchRun* r) const { delete r; }
+
+BatchRunPtr prove_batch_begin(ProveCtx& ctx, int g, const ProveJob* jobs_in, size_t nj, hipStream_t st) {
   ZK_REQUIRE(nj >= 1, "empty proof batch");
+  ZK_REQUIRE(g >= 0 && g < ProveCtx::GENS, "bad context generation");
   ZK_REQUIRE(current_device() == ctx.device, "proof context of another device");
   for (size_t j = 0; j < nj; j++)
-    ZK_REQUIRE(jobs[j].pk && jobs[j].pk->device == ctx.device, "a proving key lives on another device");
-  const auto host_t0 = std::chrono::steady_clock::now();
+    ZK_REQUIRE(jobs_in[j].pk && jobs_in[j].pk->device == ctx.device, "a proving key lives on another device");
+  BatchRunPtr run(new BatchRun());
+  BatchRun& R = *run;
+  R.ctx = &ctx;
+  R.g = g;
+  R.jobs.assign(jobs_in, jobs_in + nj);
+  R.host_t0 = std::chrono::steady_clock::now();
+  const ProveJob* jobs = R.jobs.data();
+  ProveGen& G = ctx.gen[g];
   const NttTables& T = ntt_tables(ctx.device);
-  while (ctx.slot_ws.size() < nj) ctx.slot_ws.emplace_back(new Workspace());
-  ZK_HIP(hipEventRecord(ctx.ev[0], st));
+  while (G.slot_ws.size() < nj) G.slot_ws.emplace_back(new Workspace());
+  ZK_HIP(hipEventRecord(G.ev[0], st));
 
   // ---- witnesses and evaluation vectors
-  std::vector<Slot> slots(nj);
-  for (size_t j = 0; j < nj; j++) slots[j] = enqueue_witness(jobs[j], *ctx.slot_ws[j], st);
-  ZK_HIP(hipEventRecord(ctx.ev[1], st));
-  ZK_HIP(hipEventRecord(ctx.witness_ev, st));
-
+  R.slots.resize(nj);
+  std::vector<Slot>& slots = R.slots;
+  for (size_t j = 0; j < nj; j++) slots[j] = enqueue_witness(jobs[j], *G.slot_ws[j], st);
+  ZK_HIP(hipEventRecord(G.ev[1], st));
+  ZK_HIP(hipEventRecord(G.witness_ev, st));
   // ---- MSM jobs of every proof, by lane.  Those that need only the
   // assignment run from the end of the witness on, overlapping the quotient:
   // one pipeline for all G1 queries A, B1, L and one for B2 in G2; the H MSMs
   // follow the quotient on the third lane.  B2 (the longest chain of
   // dependent group operations), then the quotient and H (the critical path)
   // are enqueued first.
-  std::vector<MsmInput> in_g1, in_g2, in_h;
-  std::vector<int> own_g1, query_g1, own_g2, own_h;
+  std::vector<MsmInput> &in_g1 = R.in_g1, &in_g2 = R.in_g2, &in_h = R.in_h;
+  std::vector<int> &own_g1 = R.own_g1, &query_g1 = R.query_g1, &own_g2 = R.own_g2, &own_h = R.own_h;
   for (size_t j = 0; j < nj; j++) {
     for (const MsmJob& m : msm_jobs(jobs[j].pk, slots[j].assign, slots[j].aev)) {
       if (m.query == ZKVC_Q_H) {
@@ -991,12 +1023,15 @@ void groth16_prove_batch(ProveCtx& ctx, const ProveJob* jobs, size_t nj, hipStre
       }
     }
   }
-  std::vector<MsmPending> pend_g1(in_g1.size()), pend_g2(in_g2.size()), pend_h(in_h.size());
+  R.pend_g1.resize(in_g1.size());
+  R.pend_g2.resize(in_g2.size());
+  R.pend_h.resize(in_h.size());
   hipStream_t lane_h = ctx.lanes[ProveCtx::LANE_H], lane_g1 = ctx.lanes[ProveCtx::LANE_G1],
               lane_g2 = ctx.lanes[ProveCtx::LANE_G2];
-  ZK_HIP(hipStreamWaitEvent(lane_g2, ctx.witness_ev, 0));
-  msm_enqueue_batch_g2(in_g2.data(), (int)in_g2.size(), ctx.lane_ws[ProveCtx::LANE_G2], lane_g2, pend_g2.data());
-  ZK_HIP(hipEventRecord(ctx.done_ev[ProveCtx::LANE_G2], lane_g2));
+  ZK_HIP(hipStreamWaitEvent(lane_g2, G.witness_ev, 0));
+  msm_enqueue_batch_g2(in_g2.data(), (int)in_g2.size(), G.lane_ws[ProveCtx::LANE_G2], lane_g2, R.pend_g2.data());
+  ZK_HIP(hipEventRecord(G.done_ev[ProveCtx::LANE_G2], lane_g2));
+  ZK_HIP(hipEventRecord(G.lane_t[ProveCtx::LANE_G2], lane_g2));
 
   // ---- QAP quotients: iNTT (DIF, natural -> bit-reversed coefficients),
   // coset NTT (DIT, bit-reversed -> natural evaluations on g H), pointwise
@@ -1004,8 +1039,8 @@ void groth16_prove_batch(ProveCtx& ctx, const ProveJob* jobs, size_t nj, hipStre
   // Proofs of one domain size share every launch.
   std::map<int, std::vector<size_t>> by_size;
   for (size_t j = 0; j < nj; j++) by_size[jobs[j].pk->L.log_n].push_back(j);
-  uint32_t* flag = ctx.shared.get(C_FLAG, 4);
-  uint32_t* flag_host = ctx.shared.host<uint32_t>(C_FLAG, 4);
+  uint32_t* flag = G.shared.get(C_FLAG, 4);
+  uint32_t* flag_host = G.shared.host<uint32_t>(C_FLAG, 4);
   fill_u32(flag, 0u, 1, st);
   // device tables for groups of several proofs: (A, B, C) triples, then the A's
   std::vector<uint32_t*> tab_v;
@@ -1023,8 +1058,8 @@ void groth16_prove_batch(ProveCtx& ctx, const ProveJob* jobs, size_t nj, hipStre
   uint32_t** tab_dev = nullptr;
   if (!tab_v.empty()) {
     const size_t bytes = tab_v.size() * sizeof(uint32_t*);
-    uint32_t** tab_host = ctx.shared.host<uint32_t*>(C_TABLE, bytes);
-    tab_dev = ctx.shared.get<uint32_t*>(C_TABLE, bytes);
+    uint32_t** tab_host = G.shared.host<uint32_t*>(C_TABLE, bytes);
+    tab_dev = G.shared.get<uint32_t*>(C_TABLE, bytes);
     std::memcpy(tab_host, tab_v.data(), bytes);
     ZK_HIP(hipMemcpyAsync(tab_dev, tab_host, bytes, hipMemcpyHostToDevice, st));
   }
@@ -1069,19 +1104,32 @@ void groth16_prove_batch(ProveCtx& ctx, const ProveJob* jobs, size_t nj, hipStre
     gi++;
   }
   ZK_HIP(hipMemcpyAsync(flag_host, flag, 4, hipMemcpyDeviceToHost, st));
-  ZK_HIP(hipEventRecord(ctx.ev[2], st));
-  ZK_HIP(hipEventRecord(ctx.quotient_ev, st));
+  R.flag_host = flag_host;
+  ZK_HIP(hipEventRecord(G.ev[2], st));
+  ZK_HIP(hipEventRecord(G.quotient_ev, st));
 
   // ---- the H lane after the quotients, then the G1 lane
-  ZK_HIP(hipStreamWaitEvent(lane_h, ctx.quotient_ev, 0));
-  msm_enqueue_batch_g1(in_h.data(), (int)in_h.size(), ctx.lane_ws[ProveCtx::LANE_H], lane_h, pend_h.data());
-  ZK_HIP(hipEventRecord(ctx.done_ev[ProveCtx::LANE_H], lane_h));
-  ZK_HIP(hipStreamWaitEvent(lane_g1, ctx.witness_ev, 0));
-  msm_enqueue_batch_g1(in_g1.data(), (int)in_g1.size(), ctx.lane_ws[ProveCtx::LANE_G1], lane_g1, pend_g1.data());
-  ZK_HIP(hipEventRecord(ctx.done_ev[ProveCtx::LANE_G1], lane_g1));
-  for (int lane = 0; lane < ProveCtx::LANES; lane++) ZK_HIP(hipStreamWaitEvent(st, ctx.done_ev[lane], 0));
-  ZK_HIP(hipEventRecord(ctx.ev[3], st));
+  ZK_HIP(hipStreamWaitEvent(lane_h, G.quotient_ev, 0));
+  msm_enqueue_batch_g1(in_h.data(), (int)in_h.size(), G.lane_ws[ProveCtx::LANE_H], lane_h, R.pend_h.data());
+  ZK_HIP(hipEventRecord(G.done_ev[ProveCtx::LANE_H], lane_h));
+  ZK_HIP(hipEventRecord(G.lane_t[ProveCtx::LANE_H], lane_h));
+  ZK_HIP(hipStreamWaitEvent(lane_g1, G.witness_ev, 0));
+  msm_enqueue_batch_g1(in_g1.data(), (int)in_g1.size(), G.lane_ws[ProveCtx::LANE_G1], lane_g1, R.pend_g1.data());
+  ZK_HIP(hipEventRecord(G.done_ev[ProveCtx::LANE_G1], lane_g1));
+  ZK_HIP(hipEventRecord(G.lane_t[ProveCtx::LANE_G1], lane_g1));
+  return run;
+}
 
+
+void prove_batch_finish(ProveCtx& ctx, BatchRun& R) {
+  ZK_REQUIRE(!R.finished && R.ctx == &ctx, "batch already finished or of another context");
+  R.finished = true;
+  ProveGen& G = ctx.gen[R.g];
+  const ProveJob* jobs = R.jobs.data();
+  const size_t nj = R.jobs.size();
+  const std::vector<Slot>& slots = R.slots;
+  const std::vector<int> &own_g1 = R.own_g1, &query_g1 = R.query_g1, &own_g2 = R.own_g2, &own_h = R.own_h;
+  const std::vector<MsmPending> &pend_g1 = R.pend_g1, &pend_g2 = R.pend_g2, &pend_h = R.pend_h;
   // ---- host side, per lane as each lane completes: the plane sums by
   // Horner's rule, then everything that lane's results allow.  The G1 lane
   // yields A, B1 and s A + r B1 - r s delta (one shared doubling chain, off the
@@ -1098,7 +1146,7 @@ void groth16_prove_batch(ProveCtx& ctx, const ProveJob* jobs, size_t nj, hipStre
   for (size_t q = 0; q < own_g1.size(); q++) g1_of[own_g1[q]].push_back(q);
   for (size_t q = 0; q < own_g2.size(); q++) g2_of[own_g2[q]].push_back(q);
   auto f_g1 = std::async(std::launch::async, [&] {
-    ZK_HIP(hipEventSynchronize(ctx.done_ev[ProveCtx::LANE_G1]));
+    ZK_HIP(hipEventSynchronize(G.done_ev[ProveCtx::LANE_G1]));
     parallel_for(nj, nthr, [&](size_t j) {
       const ProveJob& J = jobs[j];
       const zkvc_pk* pk = J.pk;
@@ -1123,7 +1171,7 @@ void groth16_prove_batch(ProveCtx& ctx, const ProveJob* jobs, size_t nj, hipStre
     });
   });
   auto f_g2 = std::async(std::launch::async, [&] {
-    ZK_HIP(hipEventSynchronize(ctx.done_ev[ProveCtx::LANE_G2]));
+    ZK_HIP(hipEventSynchronize(G.done_ev[ProveCtx::LANE_G2]));
     parallel_for(nj, nthr / 2 + 1, [&](size_t j) {
       uint64_t sw[4];
       jobs[j].s.to_u64(sw);
@@ -1133,11 +1181,12 @@ void groth16_prove_batch(ProveCtx& ctx, const ProveJob* jobs, size_t nj, hipStre
     });
   });
   auto f_h = std::async(std::launch::async, [&] {
-    ZK_HIP(hipEventSynchronize(ctx.done_ev[ProveCtx::LANE_H]));
+    ZK_HIP(hipEventSynchronize(G.done_ev[ProveCtx::LANE_H]));
     parallel_for(own_h.size(), nthr / 2 + 1, [&](size_t q) { Hp[own_h[q]] = msm_finish_g1(pend_h[q]); });
   });
-  ZK_HIP(hipStreamSynchronize(st));
-  if (*flag_host) throw Error(ZKVC_EDEVICE, "internal error: a witness does not satisfy its circuit");
+  ZK_HIP(hipEventSynchronize(G.quotient_ev));
+  if (*R.flag_host) throw Error(ZKVC_EDEVICE, "internal error: a witness does not satisfy its circuit");
+  for (int lane = 0; lane < ProveCtx::LANES; lane++) ZK_HIP(hipEventSynchronize(G.done_ev[lane]));
   const auto asm_t0 = std::chrono::steady_clock::now();
   f_g1.get();
   f_g2.get();
@@ -1152,17 +1201,41 @@ void groth16_prove_batch(ProveCtx& ctx, const ProveJob* jobs, size_t nj, hipStre
     std::memcpy(jobs[j].Y, slots[j].yh, (size_t)L.a * L.b * 4);
   }
   const auto host_t1 = std::chrono::steady_clock::now();
-  auto ms = [&](int a, int b) {
+  auto ms = [&](hipEvent_t a, hipEvent_t b) {
     float t = 0.f;
-    (void)hipEventElapsedTime(&t, ctx.ev[a], ctx.ev[b]);
+    (void)hipEventElapsedTime(&t, a, b);
     return t;
   };
-  ctx.last.witness_ms = ms(0, 1);
-  ctx.last.ntt_ms = ms(1, 2);
-  ctx.last.msm_ms = ms(2, 3);
+  ctx.last.witness_ms = ms(G.ev[0], G.ev[1]);
+  ctx.last.ntt_ms = ms(G.ev[1], G.ev[2]);
+  float msm = 0.f;
+  for (int lane = 0; lane < ProveCtx::LANES; lane++) msm = std::max(msm, ms(G.ev[2], G.lane_t[lane]));
+  ctx.last.msm_ms = msm;
   ctx.last.host_ms = std::chrono::duration<float, std::milli>(host_t1 - asm_t0).count();
-  ctx.last.total_ms = std::chrono::duration<float, std::milli>(host_t1 - host_t0).count();
+  ctx.last.total_ms = std::chrono::duration<float, std::milli>(host_t1 - R.host_t0).count();
 }
+
+void prove_batch_abandon(BatchRunPtr& run) {
+  if (!run) return;
+  if (!run->finished) {
+    ProveGen& G = run->ctx->gen[run->g];
+    (void)hipEventSynchronize(G.quotient_ev);
+    for (int lane = 0; lane < ProveCtx::LANES; lane++) (void)hipEventSynchronize(G.done_ev[lane]);
+  }
+  run.reset();
+}
+
+void groth16_prove_batch(ProveCtx& ctx, const ProveJob* jobs, size_t nj, hipStream_t st) {
+  BatchRunPtr run = prove_batch_begin(ctx, 0, jobs, nj, st);
+  try {
+    prove_batch_finish(ctx, *run);
+  } catch (...) {
+    prove_batch_abandon(run);
+    throw;
+  }
+}
+
+
 
 void groth16_prove(zkvc_pk* pk, const int8_t* X, const int8_t* W, const host::HFr& r, const host::HFr& s, int32_t* Y,
                    zkvc_proof* out, hipStream_t st) {

@@ -51,13 +51,29 @@ bool kind_uses_z(uint32_t kind);
 
 namespace zkvc {
 
-// Device and host state for proofs in flight: the three MSM lanes (streams),
-// their events, one workspace per lane, and one workspace per proof of a
-// batch (witness, evaluation vectors, quotient, pinned staging).  A proving
+// The resources of one batch in flight: events, one workspace per MSM lane,
+// batch-level tables, and one workspace per proof (witness, evaluation
+// vectors, quotient, pinned staging).
+struct ProveGen {
+  hipEvent_t witness_ev = nullptr;   // assignments complete
+  hipEvent_t quotient_ev = nullptr;  // every h complete (and the tail flag copied)
+  hipEvent_t done_ev[3] = {};        // each lane's batch complete
+  hipEvent_t lane_t[3] = {};         // the same, with timing
+  hipEvent_t ev[3] = {};             // stage timing on the calling stream
+  Workspace lane_ws[3];
+  Workspace shared;
+  std::vector<std::unique_ptr<Workspace>> slot_ws;
+};
+
+// Device and host state for proving: the three MSM lanes (streams) and two
+// generations of per-batch resources, so that a batch can be enqueued while
+// the previous one is still on the device (continuous batching).  A proving
 // key owns one for its single proofs; the batch entry point keeps one per
-// (device, stream).  Not thread-safe: callers serialize its use.
+// (device, stream); each server has its own.  Not thread-safe: callers
+// serialize its use.
 struct ProveCtx {
   static constexpr int LANES = 3;
+  static constexpr int GENS = 2;
   enum Lane { LANE_H = 0, LANE_G1 = 1, LANE_G2 = 2 };
   ProveCtx();
   ~ProveCtx();
@@ -65,13 +81,7 @@ struct ProveCtx {
   ProveCtx& operator=(const ProveCtx&) = delete;
   int device = 0;
   hipStream_t lanes[LANES] = {};
-  hipEvent_t witness_ev = nullptr;   // assignments complete
-  hipEvent_t quotient_ev = nullptr;  // every h complete
-  hipEvent_t done_ev[LANES] = {};    // lane's batch complete
-  hipEvent_t ev[4] = {};             // stage timing
-  Workspace lane_ws[LANES];
-  Workspace shared;                  // batch-level tables and flags
-  std::vector<std::unique_ptr<Workspace>> slot_ws;
+  ProveGen gen[GENS];
   zkvc_prove_stats last{};
 };
 
@@ -119,6 +129,20 @@ struct ProveJob {
 // three MSM pipelines shared by all proofs.  Each proof equals its single
 // proof bit for bit.
 void groth16_prove_batch(ProveCtx& ctx, const ProveJob* jobs, size_t njobs, hipStream_t st);
+
+// The same in two halves: begin enqueues all device work of the batch on
+// generation g of the context (no host wait); finish waits for it, combines
+// and assembles on the host, and writes the outputs.  A generation must be
+// finished before it is begun again; the other one may be in flight.
+struct BatchRun;
+struct BatchRunDeleter {
+  void operator()(BatchRun* r) const;
+};
+using BatchRunPtr = std::unique_ptr<BatchRun, BatchRunDeleter>;
+BatchRunPtr prove_batch_begin(ProveCtx& ctx, int g, const ProveJob* jobs, size_t njobs, hipStream_t st);
+void prove_batch_finish(ProveCtx& ctx, BatchRun& run);
+// Releases a run; one begun but not finished first waits for its device work.
+void prove_batch_abandon(BatchRunPtr& run);
 
 // Proves Y = X W (a batch of one on the key's own context).
 void groth16_prove(zkvc_pk* pk, const int8_t* X, const int8_t* W, const host::HFr& r, const host::HFr& s,

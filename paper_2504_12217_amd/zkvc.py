@@ -69,6 +69,15 @@ class ProveJob(ctypes.Structure):
                 ("Y_out", ctypes.c_void_p), ("proof_out", ctypes.POINTER(Proof))]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_uint32), ("memory_budget", ctypes.c_uint64)]
+
+
+class ServerResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("batch_size", ctypes.c_uint32), ("queue_ms", ctypes.c_double),
+                ("latency_ms", ctypes.c_double)]
+
+
 class ProveStats(ctypes.Structure):
     _fields_ = [("witness_ms", ctypes.c_float), ("ntt_ms", ctypes.c_float), ("msm_ms", ctypes.c_float),
                 ("host_ms", ctypes.c_float), ("total_ms", ctypes.c_float)]
@@ -84,6 +93,10 @@ _SIGS = {
     "zkvc_prove": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(Fr), ctypes.POINTER(Fr), _VP,
                                   ctypes.POINTER(Proof), _VP]),
     "zkvc_prove_batch": (ctypes.c_int, [ctypes.POINTER(ProveJob), ctypes.c_size_t, _VP]),
+    "zkvc_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(_VP)]),
+    "zkvc_server_submit": (ctypes.c_int, [_VP, ctypes.POINTER(ProveJob), ctypes.POINTER(ctypes.c_uint64)]),
+    "zkvc_server_wait": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(ServerResult)]),
+    "zkvc_server_destroy": (ctypes.c_int, [_VP]),
     "zkvc_verify": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, _VP, _VP, ctypes.POINTER(Proof)]),
     "zkvc_ntt_fr": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint32, _VP]),
     "zkvc_msm_g1": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, ctypes.c_uint32, ctypes.POINTER(G1), _VP]),
@@ -319,6 +332,57 @@ def prove_batch(jobs, stream=None):
         arr[k].proof_out = ctypes.pointer(out)
     _check(lib().zkvc_prove_batch(arr, len(jobs), _stream(stream)))
     return outs
+
+
+class Server:
+    """The library's proving server: submit jobs as they arrive, wait for each ticket."""
+
+    def __init__(self, max_batch=64, memory_budget=0):
+        cfg = ServerConfig(max_batch, memory_budget)
+        h = _VP()
+        _check(lib().zkvc_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h.value
+        self._pending = {}  # ticket -> (Y, Proof, inputs kept alive)
+
+    def submit(self, pk, X, W, r, s):
+        info = pk.info()
+        X = np.ascontiguousarray(X, dtype=np.int8)
+        W = np.ascontiguousarray(W, dtype=np.int8)
+        if X.shape != (info.a, info.n) or W.shape != (info.n, info.b):
+            raise ValueError("X or W does not match the proving key's shape")
+        Y = np.zeros((info.a, info.b), dtype=np.int32)
+        out = Proof()
+        job = ProveJob()
+        job.pk = pk.handle
+        job.X = X.ctypes.data
+        job.W = W.ctypes.data
+        job.r = fr(r)
+        job.s = fr(s)
+        job.Y_out = Y.ctypes.data
+        job.proof_out = ctypes.pointer(out)
+        t = ctypes.c_uint64(0)
+        _check(lib().zkvc_server_submit(self.handle, ctypes.byref(job), ctypes.byref(t)))
+        self._pending[t.value] = (Y, out)
+        return t.value
+
+    def wait(self, ticket):
+        """(Y, Proof, ServerResult) of a ticket; raises ZkvcError if its batch failed."""
+        res = ServerResult()
+        _check(lib().zkvc_server_wait(self.handle, ticket, ctypes.byref(res)))
+        Y, out = self._pending.pop(ticket)
+        _check(res.status)
+        return Y, out, res
+
+    def close(self):
+        if self.handle:
+            _check(lib().zkvc_server_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def verify(vk, X, Y, proof):

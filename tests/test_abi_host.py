@@ -41,6 +41,8 @@ def test_struct_layouts_match_header(zk):
     assert ctypes.sizeof(zk.Proof) == 256
     assert ctypes.sizeof(zk.Shape) == 16
     assert ctypes.sizeof(zk.ProveJob) == 104  # 3 pointers, 2 zkvc_fr, 2 pointers
+    assert ctypes.sizeof(zk.ServerConfig) == 16
+    assert ctypes.sizeof(zk.ServerResult) == 24
     text = open(HEADER).read()
     for name in ("ZKVC_PLAIN = 0", "ZKVC_CRPC_PSQ = 1", "ZKVC_PLAIN_ADD = 2", "ZKVC_PLAIN_PSQ = 3", "ZKVC_CRPC = 4"):
         assert name in text
@@ -58,6 +60,17 @@ def test_marshalling_round_trip(zk):
 
 def test_prove_batch_rejects_empty_batch_before_device_work(zk):
     assert zk.lib().zkvc_prove_batch(None, 0, None) == zk.EINVAL
+
+
+def test_server_argument_errors_before_device_work(zk):
+    lib = zk.lib()
+    assert lib.zkvc_server_create(None, None) == zk.EINVAL
+    cfg = zk.ServerConfig(0, 0)
+    h = ctypes.c_void_p()
+    assert lib.zkvc_server_create(ctypes.byref(cfg), ctypes.byref(h)) == zk.EINVAL
+    assert lib.zkvc_server_submit(None, None, None) == zk.EINVAL
+    assert lib.zkvc_server_wait(None, 1, None) == zk.EINVAL
+    assert lib.zkvc_server_destroy(None) == zk.OK
 
 
 def test_strerror_without_gpu(zk):

@@ -1,0 +1,101 @@
+"""Served proving (zkvc_server_*): continuous batching gives every job the
+same result as proving it alone.
+
+Bar: bit-exact.  Jobs of mixed shapes and kinds are submitted faster than
+they are proved, so the worker forms batches of several jobs and enqueues a
+batch while the previous one is on the device; every Y and proof must equal
+the single proof of the same job and the oracle's closed-form proof.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import bn254, groth16, r1cs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def zk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_12217_amd import zkvc
+    zkvc.lib()
+    return zkvc
+
+
+@pytest.fixture(scope="module")
+def keys(zk):
+    specs = [((4, 8, 4), r1cs.CRPC_PSQ, 11), ((3, 5, 6), r1cs.CRPC_PSQ, 12), ((4, 8, 4), r1cs.PLAIN, 13),
+             ((2, 9, 5), r1cs.CRPC, 14)]
+    out = []
+    for shape, kind, seed in specs:
+        tox = groth16.Toxic(*synth.toxic_waste(seed))
+        z = synth.crpc_point(seed) if kind in r1cs.CRPC_KINDS else None
+        out.append((shape, kind, tox, z, zk.setup(*shape, kind, tuple(tox), z)))
+    yield out
+    for *_, pk in out:
+        pk.close()
+
+
+def _jobs(keys, count, seed):
+    order = [int(w % len(keys)) for w in synth.rng(seed, synth.STREAM_SHAPES).bit_generator.random_raw(count)]
+    jobs = []
+    for q, ki in enumerate(order):
+        (a, n, b), *_ = keys[ki]
+        X, W = synth.matmul_inputs(seed * 100 + q, a, n, b)
+        r, s = synth.prover_randomness(seed, job=q)
+        jobs.append((ki, X, W, r, s))
+    return jobs
+
+
+def _serve_and_check(zk, keys, jobs, **cfg):
+    srv = zk.Server(**cfg)
+    try:
+        tickets = [srv.submit(keys[ki][4], X, W, r, s) for ki, X, W, r, s in jobs]
+        results = [srv.wait(t) for t in tickets]
+    finally:
+        srv.close()
+    sizes = []
+    for (ki, X, W, r, s), (Y, proof, res) in zip(jobs, results):
+        (a, n, b), kind, tox, z, pk = keys[ki]
+        assert res.status == zk.OK and res.latency_ms >= res.queue_ms >= 0
+        sizes.append(res.batch_size)
+        Y1, p1 = zk.prove(pk, X, W, r, s)
+        assert np.array_equal(Y, Y1) and zk.proof_bytes(proof) == zk.proof_bytes(p1)
+        want, Yo = groth16.expected_proof_trapdoor(r1cs.Shape(a, n, b), kind, tox, X.astype(int).tolist(),
+                                                    W.astype(int).tolist(), r, s, z)
+        assert Y.tolist() == Yo and zk.proof_to_tuple(proof) == tuple(want)
+    return sizes
+
+
+def test_served_results_equal_single_proofs(zk, keys):
+    sizes = _serve_and_check(zk, keys, _jobs(keys, 24, 1), max_batch=8)
+    assert max(sizes) > 1  # the jobs really were batched
+
+
+def test_memory_budget_admits_one_job_at_a_time(zk, keys):
+    # a budget below any job's footprint still admits a single job per batch
+    sizes = _serve_and_check(zk, keys, _jobs(keys, 6, 2), max_batch=8, memory_budget=1)
+    assert max(sizes) == 1
+
+
+def test_server_argument_errors(zk, keys):
+    pk = keys[0][4]
+    X, W = synth.matmul_inputs(3, 4, 8, 4)
+    srv = zk.Server(max_batch=4)
+    try:
+        with pytest.raises(zk.ZkvcError) as e:
+            srv.submit(pk, X, W, bn254.R, 1)
+        assert e.value.code == zk.EINVAL
+        with pytest.raises(zk.ZkvcError) as e:
+            srv.wait(12345)
+        assert e.value.code == zk.EINVAL
+        t = srv.submit(pk, X, W, 5, 7)
+        Y, proof, res = srv.wait(t)
+        assert res.status == zk.OK and res.batch_size == 1
+        assert zk.verify(pk.vk, X, Y, proof) == 1
+    finally:
+        srv.close()
