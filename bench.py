@@ -45,11 +45,46 @@ FMUL_PER_UNIT = {                    # algorithmic Fq/Fr multiplications per cou
 }
 
 
+# Measured HBM traffic per launch of a kernel (from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs,
+# scaled by the same counters on a device copy of known size) is recorded in profiles/ with a fingerprint
+# of the sources the kernel is built from; it is reported only while the sources still match.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_per_launch.md")
+KERNEL_SOURCES = ["paper_2504_12217_amd/csrc/msm.hip", "paper_2504_12217_amd/csrc/curve.hpp",
+                  "paper_2504_12217_amd/csrc/field.hpp", "paper_2504_12217_amd/csrc/ntt.hip"]
+
+
+def source_fingerprint():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel, workload):
+    """Bytes per launch recorded for (kernel, workload), or None if absent or the sources changed."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    fp = source_fingerprint()
+    for ln in lines:
+        # | kernel | workload | fingerprint | fetch bytes/launch | write bytes/launch | total |
+        cells = [c.strip().strip("`") for c in ln.strip().strip("|").split("|")]
+        if len(cells) >= 6 and cells[0] == kernel and cells[1] == workload and cells[2] == fp:
+            try:
+                return float(cells[5])
+            except ValueError:
+                return None
+    return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def roofline(stats):
+def roofline(stats, workload=None):
     """Roofline entry for the kernel with the most device time."""
     name, (launches, total_ms, work) = max(stats.items(), key=lambda kv: kv[1][1])
     avg_ms = total_ms / max(launches, 1)
@@ -59,8 +94,10 @@ def roofline(stats):
     mad_per_launch = work / launches * per_unit * MAD_PER_FMUL
     achieved = mad_per_launch / (avg_ms * 1e-3) / 1e12
     peak = PEAK_MAD / 1e12
+    traffic = recorded_traffic(name, workload) if workload else None
     return name, {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
-                  "unit": "T u32-MAD/s", "frac": round(achieved / peak, 4), "traffic": None,
+                  "unit": "T u32-MAD/s", "frac": round(achieved / peak, 4),
+                  "traffic": None if traffic is None else round(traffic),
                   "kernel": name, "launches": launches, "avg_launch_ms": round(avg_ms, 4),
                   "work_units_per_launch": work / launches}
 
@@ -176,15 +213,24 @@ def batch_section(zk, seed, count=64, reps=3):
             keys[shape] = zk.setup(*shape, zk.CRPC_PSQ, tox, z)
     setup_s = time.perf_counter() - t0
     batch = [(keys[sh], X, W, r, s) for sh, X, W, r, s in jobs]
-    outs = zk.prove_batch(batch)  # warm-up (workspace growth)
-    torch.cuda.synchronize()
-    lat = []
+
+    def timed():
+        zk.prove_batch(batch)  # warm-up (workspace growth)
+        torch.cuda.synchronize()
+        lat = []
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            t = time.perf_counter()
+            res = zk.prove_batch(batch)
+            lat.append(time.perf_counter() - t)
+        return time.perf_counter() - t0, lat, res
+
+    dt0, _, _ = timed()
+    # then with the autotuner's picks for these sizes (MSM window and task size, NTT pass size)
     t0 = time.perf_counter()
-    for _ in range(reps):
-        t = time.perf_counter()
-        outs = zk.prove_batch(batch)
-        lat.append(time.perf_counter() - t)
-    dt = time.perf_counter() - t0
+    nset = zk.autotune(zk.TUNE_MSM_G1 | zk.TUNE_MSM_G2 | zk.TUNE_NTT, 12, 16)
+    tune_s = time.perf_counter() - t0
+    dt, lat, outs = timed()
     ok = all(zk.verify(keys[sh].vk, X, Y, p) == 1 for (sh, X, W, r, s), (Y, p) in zip(jobs[:4], outs[:4]))
     # the same jobs one by one, for comparison
     t0 = time.perf_counter()
@@ -197,6 +243,8 @@ def batch_section(zk, seed, count=64, reps=3):
     return {"workload": f"{count} CRPC+PSQ proofs, a=49, (n, b) drawn per proof from {{64,128,320}}x{{64,256,512}} "
                         f"({len(classes)} shape classes, QAP domains 2^13..2^16), one zkvc_prove_batch call",
             "proofs_per_s": round(count * reps / dt, 2), "ms_per_batch": round(dt / reps * 1e3, 3),
+            "proofs_per_s_builtin_rules": round(count * reps / dt0, 2),
+            "autotune": {"seconds": round(tune_s, 2), "settings": nset, "table": zk.tune_export().split("\n")[:-1]},
             "batch_latency_ms_max": round(max(lat) * 1e3, 3),
             "same_jobs_one_by_one_proofs_per_s": round(count / single_s, 2),
             "setup_s_all_keys": round(setup_s, 3), "verified_sample": ok}
@@ -316,6 +364,8 @@ def main():
     ap.add_argument("--no-msm", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="first copy this many MiB device to device (a known-size kernel for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build proves on a single MI355X "
@@ -327,6 +377,14 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     zkvc.lib()
+    if args.calib_copy_mb:
+        nb = args.calib_copy_mb << 20
+        src = torch.ones(nb // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.calib_copy_mb} MiB done")
+        del src, dst
     a, n, b = SHAPE
     seed = args.seed
     X, W = synth.matmul_inputs(seed, a, n, b)
@@ -348,7 +406,7 @@ def main():
                 "msm_all_concurrent": round(st.msm_ms, 3), "host_windows_and_assembly": round(st.host_ms, 3),
                 "total_wall": round(st.total_ms, 3)}
     pk.close()
-    dom_name, roof = roofline(stats)
+    dom_name, roof = roofline(stats, "crpc_psq_49x320x512" if main_kind == zkvc.CRPC_PSQ else "plain_49x320x512")
     lat_ms = sorted(x * 1e3 for x in lat)
     ms_per_step = total / args.steps * 1e3
     out = {
@@ -388,7 +446,7 @@ def main():
         Yp, pp = zkvc.prove(pkp, X, W, r, s)
         okp = zkvc.verify(pkp.vk, X, Yp, pp) == 1
         pkp.close()
-        name_p, roof_p = roofline(statsp)
+        name_p, roof_p = roofline(statsp, "plain_49x320x512")
         out["plain"] = {"workload": "same matmul, per-product circuit: 8,028,160 constraints, QAP domain 2^23",
                         "proofs_per_s": round(steps_p / tp, 3), "ms_per_proof": round(tp / steps_p * 1e3, 3),
                         "setup_s": round(setup_plain, 3), "verified": okp, "roofline": roof_p,

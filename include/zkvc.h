@@ -253,6 +253,30 @@ typedef struct {
 int zkvc_pk_last_stats(const zkvc_pk* pk, zkvc_prove_stats* out);
 
 /*
+ * Autotuner.  Times candidate settings on synthetic inputs on the device
+ * (hip_stream) and keeps the fastest for the rest of the process: the MSM
+ * window width for wide scalars and the thread-task size per power-of-two
+ * size 2^min_log..2^max_log (G2 up to 2^18), and the largest sub-transform per
+ * NTT pass per domain size.  Proving keys built later use the tuned values
+ * too; results never depend on them (bit-exact either way), only speed.
+ * Returns the number of settings chosen (>= 0) or an error: ZKVC_EINVAL
+ * (unknown target, sizes outside 4 <= min_log <= max_log <= 22),
+ * ZKVC_ENOMEM, ZKVC_EDEVICE.
+ */
+#define ZKVC_TUNE_MSM_G1 1u
+#define ZKVC_TUNE_MSM_G2 2u
+#define ZKVC_TUNE_NTT 4u
+int zkvc_autotune(uint32_t what, uint32_t min_log, uint32_t max_log, void* hip_stream);
+/* The tuned settings as text, one "<key> <log2 size> <value>" line each
+ * (keys msm_g1, msm_g2, msm_kdiv, ntt); with buf NULL only the size
+ * (including the terminating zero) is written to *len.  Host only. */
+int zkvc_tune_export(char* buf, size_t* len);
+/* Loads settings in the export format (value 0 restores the built-in rule).
+ * All lines are checked before any is applied.  ZKVC_EINVAL on a malformed
+ * line or a value out of range.  Host only. */
+int zkvc_tune_import(const char* text);
+
+/*
  * Elementwise field operations on device arrays, for arithmetic parity
  * tests.  field: 0 = Fq, 1 = Fr.  op: 0 add, 1 sub, 2 mul, 3 sqr, 4 inv
  * (of nonzero), 5 to-internal (canonical -> Montgomery), 6 from-internal.

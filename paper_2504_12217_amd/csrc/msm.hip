@@ -34,6 +34,7 @@
 #include "field.hpp"
 #include "profile.hpp"
 #include "scan.hpp"
+#include "tune.hpp"
 
 namespace zkvc {
 
@@ -252,9 +253,10 @@ __global__ void k_msm_task_counts(BatchDev B, const uint32_t* offs, uint32_t nbt
 
 // Task records (first entry, length, output partial slot, job).  Slots in
 // the two task lists are claimed with one atomic per wavefront and list.
-// Buckets that end up with more than FIN_THREAD_MAX partial sums are listed
-// for a wavefront each in the finalize step.
-constexpr uint32_t FIN_THREAD_MAX = 8;
+// Buckets that end up with more than `fin_max` partial sums (several times
+// the batch's average, at least FIN_THREAD_MIN) are listed for a wavefront
+// each in the finalize step; the others are summed by one thread each.
+constexpr uint32_t FIN_THREAD_MIN = 8;
 
 __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v, uint32_t lane) {
   for (int o = 1; o < 64; o <<= 1) {
@@ -266,15 +268,15 @@ __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v, uint32_t lane
 
 __global__ void __launch_bounds__(256) k_msm_make_tasks(BatchDev B, const uint32_t* cnt, const uint32_t* off,
                                                         const uint32_t* part_off, uint32_t nbt, uint32_t K,
-                                                        uint32_t large, uint32_t* counters, uint4* th_tasks,
-                                                        uint4* wg_tasks, uint32_t* heavy) {
+                                                        uint32_t large, uint32_t fin_max, uint32_t* counters,
+                                                        uint4* th_tasks, uint4* wg_tasks, uint32_t* heavy) {
   const uint32_t f = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t c = f < nbt ? cnt[f] : 0u;
   const bool big = c >= large;
   const uint32_t sz = big ? WG_TASK_ENTRIES : K;
   const uint32_t nt = (c + sz - 1) / sz;
-  const uint32_t hv = nt > FIN_THREAD_MAX ? 1u : 0u;
+  const uint32_t hv = nt > fin_max ? 1u : 0u;
   // inclusive wavefront scans of the three claims
   const uint32_t sth = wave_inclusive_sum(big ? 0u : nt, lane);
   const uint32_t swg = wave_inclusive_sum(big ? nt : 0u, lane);
@@ -359,21 +361,22 @@ __global__ void __launch_bounds__(64) k_msm_acc(BatchDev B, const uint4* th_task
 }
 
 // Bucket sums from the partial sums, one launch: blocks below light_blocks
-// give each bucket with at most FIN_THREAD_MAX partials a thread (serial
+// give each bucket with at most fin_max partials a thread (serial
 // sum); the others give each listed heavy bucket a wavefront (strided sums,
 // then an LDS tree), so one crowded bucket (e.g. the top window's few digit
 // values under uniform scalars) does not serialize the step.
 template <class F>
 __global__ void __launch_bounds__(64) k_msm_finalize(const uint32_t* nt, const uint32_t* part_off,
                                                      const uint32_t* partials, uint32_t nbt, const uint32_t* counters,
-                                                     const uint32_t* heavy, uint32_t light_blocks, uint32_t* buckets) {
+                                                     const uint32_t* heavy, uint32_t light_blocks, uint32_t fin_max,
+                                                     uint32_t* buckets) {
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
   __shared__ uint32_t sh[WG_THREADS / 2 * XW];
   if (blockIdx.x < light_blocks) {
     const uint32_t f = blockIdx.x * 64 + threadIdx.x;
     if (f >= nbt) return;
     const uint32_t c = nt[f], o = part_off[f];
-    if (c > FIN_THREAD_MAX) return;
+    if (c > fin_max) return;
     Xyzz<F> acc = Xyzz<F>::inf();
     for (uint32_t e = 0; e < c; e++) acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(partials + (size_t)(o + e) * XW));
     PointIO<F>::store_xyzz(buckets + (size_t)f * XW, acc);
@@ -534,9 +537,10 @@ struct BatchPlan {
   uint32_t K = 0;      // entries per thread task
   uint32_t large = 0;  // buckets with at least this many entries get wavefront tasks
   uint64_t max_th_tasks = 0, max_wg_tasks = 0, max_partials = 0;
+  uint32_t fin_max = 0;  // partial sums above which a bucket gets a wavefront in the finalize step
 };
 
-static BatchPlan batch_plan(const MsmInput* in, int njobs) {
+static BatchPlan batch_plan(const MsmInput* in, int njobs, int group) {
   BatchPlan p;
   for (int q = 0; q < njobs; q++) {
     ZK_REQUIRE(in[q].nscalars < (1ull << 31) && in[q].npoints < (1ull << 31), "MSM too large");
@@ -559,6 +563,12 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs) {
       J.pre = 1;
     } else {
       msm_choose_window(J.n, in[q].max_bits, &J.c, &J.nw);
+      // a tuned width for wide scalars of this size, if the autotuner picked one
+      const int tc = in[q].max_bits > 64 ? tuning().msm_c[group][std::min(32, ceil_log2(J.n))].load() : 0;
+      if (tc >= 2 && tc <= MAX_C) {
+        J.c = tc;
+        J.nw = (in[q].max_bits + 1 + tc - 1) / tc;
+      }
       J.pre = 0;
     }
     J.nb = 1u << (J.c - 1);
@@ -593,7 +603,8 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs) {
   }
   const uint64_t E = p.ndigits;  // bound on the bucket entries
   // thread tasks: enough of them to fill the device, long enough to amortize
-  p.K = (uint32_t)std::max<uint64_t>(4, std::min<uint64_t>(E / 65536, 64));
+  const int kd = E ? tuning().msm_kdiv_log[std::min(33, floor_log2(E))].load() : 0;
+  p.K = (uint32_t)std::max<uint64_t>(4, std::min<uint64_t>(E >> (kd > 0 ? kd : 16), 64));
   // wavefront tasks only for buckets far above the typical size (a window's
   // few possible top digits, or small-integer scalars piling into few buckets)
   p.large = std::max<uint32_t>(128, 32 * p.K);
@@ -602,6 +613,11 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs) {
   // most E / large buckets are large
   p.max_wg_tasks = E / WG_TASK_ENTRIES + E / p.large + 1;
   p.max_partials = p.max_th_tasks + p.max_wg_tasks;
+  // a thread per bucket unless a bucket holds several times the average
+  // number of partial sums (a tree over a wavefront costs ~7 dependent
+  // additions, so only far-above-average buckets gain from it)
+  const uint64_t avg = p.nbt ? (E / p.K + p.nbt - 1) / p.nbt : 1;
+  p.fin_max = (uint32_t)std::max<uint64_t>(FIN_THREAD_MIN, 4 * avg);
   return p;
 }
 
@@ -613,7 +629,7 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
     pend[q] = MsmPending();
     pend[q].xyzz_words = XW;
   }
-  const BatchPlan p = batch_plan(in, njobs);
+  const BatchPlan p = batch_plan(in, njobs, PointIO<F>::AFF_WORDS == 16 ? 0 : 1);
   const int nj = (int)p.jobs.size();
   if (nj == 0) return;
   const uint32_t nbt = (uint32_t)p.nbt;
@@ -674,7 +690,7 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
   ZK_HIP(hipGetLastError());
   scan_exclusive(nt, part_off, nbt, 0, meta + 2, nullptr, ws, S_SCRATCH, st);
   hipLaunchKernelGGL(k_msm_make_tasks, dim3(cdiv(nbt, 256)), dim3(256), 0, st, dev, cnt, off, part_off, nbt, p.K,
-                     p.large, meta + 8, th_tasks, wg_tasks, heavy);
+                     p.large, p.fin_max, meta + 8, th_tasks, wg_tasks, heavy);
   ZK_HIP(hipGetLastError());
   {
     ProfScope ps(g1 ? "msm_acc_points_g1" : "msm_acc_points_g2", st, -1.0);
@@ -691,7 +707,7 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
     const unsigned light_blocks = cdiv(nbt, 64);
     const unsigned heavy_blocks = (unsigned)std::min<uint64_t>(nbt, 1024);
     hipLaunchKernelGGL(k_msm_finalize<F>, dim3(light_blocks + heavy_blocks), dim3(64), 0, st, nt, part_off, part, nbt,
-                       meta + 8, heavy, light_blocks, buckets);
+                       meta + 8, heavy, light_blocks, p.fin_max, buckets);
     ZK_HIP(hipGetLastError());
   }
   {

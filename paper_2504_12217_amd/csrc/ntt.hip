@@ -25,6 +25,7 @@
 #include "field.hpp"
 #include "host_field.hpp"
 #include "profile.hpp"
+#include "tune.hpp"
 #include "util.hpp"
 
 namespace zkvc {
@@ -306,7 +307,8 @@ void ntt_launch_impl(uint32_t* const* data, uint32_t* const* dev_table, int nvec
   const int L = log_n;
   // small transforms use 256-element workgroups so that a pass still spreads
   // over the device; large ones use 1024 (fewer passes over HBM)
-  const int kmax = L <= 18 ? 8 : NTT_MAX_K;
+  const int tk = tuning().ntt_kmax[L].load();
+  const int kmax = (tk >= 1 && tk <= NTT_MAX_K) ? tk : (L <= 18 ? 8 : NTT_MAX_K);
   const int npass = L == 0 ? 1 : (L + kmax - 1) / kmax;
   std::vector<int> ks(npass);
   for (int j = 0; j < npass; j++) ks[j] = L / npass + (j < L % npass ? 1 : 0);

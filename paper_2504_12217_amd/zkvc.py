@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libzkvc.so")
 OK, EINVAL, ENOMEM, EDEVICE, EFORMAT = 0, -1, -2, -3, -4
 PLAIN, CRPC_PSQ, PLAIN_ADD, PLAIN_PSQ, CRPC = 0, 1, 2, 3, 4
 NTT_INVERSE, NTT_COSET, LAYOUT_MONT = 1, 2, 4
+TUNE_MSM_G1, TUNE_MSM_G2, TUNE_NTT = 1, 2, 4
 Q_A, Q_B1, Q_B2, Q_L, Q_H, Q_CONST = 0, 1, 2, 3, 4, 5
 FQ, FR = 0, 1
 OP_ADD, OP_SUB, OP_MUL, OP_SQR, OP_INV, OP_TO_MONT, OP_FROM_MONT = range(7)
@@ -97,6 +98,9 @@ _SIGS = {
     "zkvc_server_submit": (ctypes.c_int, [_VP, ctypes.POINTER(ProveJob), ctypes.POINTER(ctypes.c_uint64)]),
     "zkvc_server_wait": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(ServerResult)]),
     "zkvc_server_destroy": (ctypes.c_int, [_VP]),
+    "zkvc_autotune": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _VP]),
+    "zkvc_tune_export": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "zkvc_tune_import": (ctypes.c_int, [ctypes.c_char_p]),
     "zkvc_verify": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, _VP, _VP, ctypes.POINTER(Proof)]),
     "zkvc_ntt_fr": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint32, _VP]),
     "zkvc_msm_g1": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, ctypes.c_uint32, ctypes.POINTER(G1), _VP]),
@@ -215,6 +219,23 @@ def fixed_base_g2(scalars, n, points_out, flags=0, stream=None):
 
 def field_op(field, op, a, b, out, n, stream=None):
     _check(lib().zkvc_field_op(field, op, _ptr(a), _ptr(b), _ptr(out), n, _stream(stream)))
+
+
+def autotune(what=TUNE_MSM_G1 | TUNE_MSM_G2 | TUNE_NTT, min_log=10, max_log=16, stream=None):
+    """Tune on the device; returns the number of settings chosen."""
+    return _check(lib().zkvc_autotune(what, min_log, max_log, _stream(stream)))
+
+
+def tune_export():
+    n = ctypes.c_size_t(0)
+    _check(lib().zkvc_tune_export(None, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value)
+    _check(lib().zkvc_tune_export(buf, ctypes.byref(n)))
+    return buf.value.decode()
+
+
+def tune_import(text):
+    _check(lib().zkvc_tune_import(text.encode()))
 
 
 def profile_begin():

@@ -73,6 +73,25 @@ def test_server_argument_errors_before_device_work(zk):
     assert lib.zkvc_server_destroy(None) == zk.OK
 
 
+def test_tuning_table_import_export_round_trip(zk):
+    before = zk.tune_export()
+    try:
+        zk.tune_import("msm_g1 16 11\nmsm_kdiv 20 15\nntt 16 8\n")
+        got = set(zk.tune_export().splitlines())
+        assert {"msm_g1 16 11", "msm_kdiv 20 15", "ntt 16 8"} <= got
+        for bad in ("msm_g1 16 40", "ntt 30 8", "bogus 1 2", "msm_g1 16"):
+            with pytest.raises(zk.ZkvcError) as e:
+                zk.tune_import(bad)
+            assert e.value.code == zk.EINVAL
+        # a rejected text changes nothing
+        assert {"msm_g1 16 11", "msm_kdiv 20 15", "ntt 16 8"} <= set(zk.tune_export().splitlines())
+    finally:
+        zk.tune_import("msm_g1 16 0\nmsm_kdiv 20 0\nntt 16 0\n")
+        zk.tune_import(before)
+    assert zk.lib().zkvc_autotune(8, 10, 12, None) == zk.EINVAL  # unknown target, before device work
+    assert zk.lib().zkvc_autotune(1, 12, 10, None) == zk.EINVAL
+
+
 def test_strerror_without_gpu(zk):
     # strerror only formats text; no device work
     assert zk.lib().zkvc_strerror(zk.EINVAL)
