@@ -5,9 +5,11 @@
 // doubling formulas are the "add-2008-s", "madd-2008-s" and "dbl-2008-s-1"
 // entries of Bernstein and Lange's Explicit-Formulas Database for a = 0:
 // a mixed addition costs 8M + 2S and needs no inversion, which suits the
-// bucket accumulation of Pippenger's method.  Products are F::cmul / F::csqr:
-// inlined over Fq, out-of-line over Fq2 (keeping G2 kernels inside the
-// instruction cache).
+// bucket accumulation of Pippenger's method.  The coordinates are kept in
+// the lazy range [0, 2m) (F::c* operations: no final subtraction after a
+// product); products are inlined over Fq and out-of-line over Fq2 (keeping G2
+// kernels inside the instruction cache).  Equality tests use the canonical
+// representative; coordinates leave for the host through canonical stores.
 //
 // Affine points in memory are stored x then y (each coordinate 8 x 32-bit
 // words in the device Montgomery form); the pair (0, 0) encodes infinity.
@@ -26,32 +28,32 @@ struct Xyzz {
   F X, Y, ZZ, ZZZ;
 
   static ZK_DEV Xyzz inf() { return {F::one(), F::one(), F::zero(), F::zero()}; }
-  static ZK_DEV bool is_inf(const Xyzz& p) { return F::is_zero(p.ZZ); }
+  static ZK_DEV bool is_inf(const Xyzz& p) { return F::cis_zero(p.ZZ); }
   static ZK_DEV Xyzz from_affine(const Affine<F>& q) { return {q.x, q.y, F::one(), F::one()}; }
 
   // 2 * (x, y) for an affine input (mdbl-2008-s-1 with ZZ = ZZZ = 1)
   static ZK_DEV Xyzz dbl_affine(const Affine<F>& q) {
-    const F U = F::dbl(q.y);
+    const F U = F::cdbl(q.y);
     const F V = F::csqr(U);
     const F W = F::cmul(U, V);
     const F S = F::cmul(q.x, V);
     const F xx = F::csqr(q.x);
-    const F M = F::add(F::dbl(xx), xx);
-    const F X3 = F::sub(F::csqr(M), F::dbl(S));
-    const F Y3 = F::sub(F::cmul(M, F::sub(S, X3)), F::cmul(W, q.y));
+    const F M = F::cadd(F::cdbl(xx), xx);
+    const F X3 = F::csub(F::csqr(M), F::cdbl(S));
+    const F Y3 = F::csub(F::cmul(M, F::csub(S, X3)), F::cmul(W, q.y));
     return {X3, Y3, V, W};
   }
 
   // 2P (dbl-2008-s-1)
   static ZK_DEV Xyzz dbl(const Xyzz& p) {
-    const F U = F::dbl(p.Y);
+    const F U = F::cdbl(p.Y);
     const F V = F::csqr(U);
     const F W = F::cmul(U, V);
     const F S = F::cmul(p.X, V);
     const F xx = F::csqr(p.X);
-    const F M = F::add(F::dbl(xx), xx);
-    const F X3 = F::sub(F::csqr(M), F::dbl(S));
-    const F Y3 = F::sub(F::cmul(M, F::sub(S, X3)), F::cmul(W, p.Y));
+    const F M = F::cadd(F::cdbl(xx), xx);
+    const F X3 = F::csub(F::csqr(M), F::cdbl(S));
+    const F Y3 = F::csub(F::cmul(M, F::csub(S, X3)), F::cmul(W, p.Y));
     return {X3, Y3, F::cmul(V, p.ZZ), F::cmul(W, p.ZZZ)};
   }
 
@@ -60,17 +62,17 @@ struct Xyzz {
     if (is_inf(p)) return from_affine(q);
     const F U2 = F::cmul(q.x, p.ZZ);
     const F S2 = F::cmul(q.y, p.ZZZ);
-    const F P = F::sub(U2, p.X);
-    const F R = F::sub(S2, p.Y);
-    if (F::is_zero(P)) {
-      if (F::is_zero(R)) return dbl_affine(q);
+    const F P = F::csub(U2, p.X);
+    const F R = F::csub(S2, p.Y);
+    if (F::cis_zero(P)) {
+      if (F::cis_zero(R)) return dbl_affine(q);
       return inf();
     }
     const F PP = F::csqr(P);
     const F PPP = F::cmul(P, PP);
     const F Q = F::cmul(p.X, PP);
-    const F X3 = F::sub(F::sub(F::csqr(R), PPP), F::dbl(Q));
-    const F Y3 = F::sub(F::cmul(R, F::sub(Q, X3)), F::cmul(p.Y, PPP));
+    const F X3 = F::csub(F::csub(F::csqr(R), PPP), F::cdbl(Q));
+    const F Y3 = F::csub(F::cmul(R, F::csub(Q, X3)), F::cmul(p.Y, PPP));
     return {X3, Y3, F::cmul(p.ZZ, PP), F::cmul(p.ZZZ, PPP)};
   }
 
@@ -82,21 +84,24 @@ struct Xyzz {
     const F U2 = F::cmul(q.X, p.ZZ);
     const F S1 = F::cmul(p.Y, q.ZZZ);
     const F S2 = F::cmul(q.Y, p.ZZZ);
-    const F P = F::sub(U2, U1);
-    const F R = F::sub(S2, S1);
-    if (F::is_zero(P)) {
-      if (F::is_zero(R)) return dbl(p);
+    const F P = F::csub(U2, U1);
+    const F R = F::csub(S2, S1);
+    if (F::cis_zero(P)) {
+      if (F::cis_zero(R)) return dbl(p);
       return inf();
     }
     const F PP = F::csqr(P);
     const F PPP = F::cmul(P, PP);
     const F Q = F::cmul(U1, PP);
-    const F X3 = F::sub(F::sub(F::csqr(R), PPP), F::dbl(Q));
-    const F Y3 = F::sub(F::cmul(R, F::sub(Q, X3)), F::cmul(S1, PPP));
+    const F X3 = F::csub(F::csub(F::csqr(R), PPP), F::cdbl(Q));
+    const F Y3 = F::csub(F::cmul(R, F::csub(Q, X3)), F::cmul(S1, PPP));
     return {X3, Y3, F::cmul(F::cmul(p.ZZ, q.ZZ), PP), F::cmul(F::cmul(p.ZZZ, q.ZZZ), PPP)};
   }
 
-  static ZK_DEV Xyzz neg(const Xyzz& p) { return {p.X, F::neg(p.Y), p.ZZ, p.ZZZ}; }
+  // the canonical representative of every coordinate (for values the host reads)
+  static ZK_DEV Xyzz canon(const Xyzz& p) { return {F::canon(p.X), F::canon(p.Y), F::canon(p.ZZ), F::canon(p.ZZZ)}; }
+
+  static ZK_DEV Xyzz neg(const Xyzz& p) { return {p.X, F::cneg(p.Y), p.ZZ, p.ZZZ}; }
 
   // [k]P for a small non-negative k (double-and-add, most significant bit first)
   static ZK_DEV Xyzz mul_small(const Xyzz& p, uint32_t k) {

@@ -32,7 +32,8 @@ constexpr uint32_t LMASK = (1u << LB) - 1u;
 template <class M>
 struct Fp;
 
-// Out-of-line Montgomery product and square.  The G2 group law calls these
+// Out-of-line lazy Montgomery product and square (inputs and results in
+// [0, 2m), see Fp::mul_core).  The G2 group law calls these
 // instead of inlining ~230 instructions per product: an inlined G2 addition
 // alone exceeds the instruction cache shared by two CUs (G1 additions fit, and
 // run faster inlined).  The limbs travel as scalar arguments, so both
@@ -161,9 +162,22 @@ struct Fp {
 
   // Montgomery product a*b*2^-261 mod m (column-interleaved reduction).
   static ZK_DEV Fp mul(const Fp& a, const Fp& b) {
+    uint32_t r[NL];
+    mul_core(a, b, r);
+    return reduce_once(r);
+  }
+  // Squaring: off-diagonal products computed once against a doubled operand.
+  static ZK_DEV Fp sqr(const Fp& a) {
+    uint32_t r[NL];
+    sqr_core(a, r);
+    return reduce_once(r);
+  }
+
+  // The products before the final conditional subtraction: for inputs below
+  // 2m the result is below m + 4m^2/2^261 < 2m (m < 2^254).
+  static ZK_DEV void mul_core(const Fp& a, const Fp& b, uint32_t r[NL]) {
     uint64_t acc = 0;
     uint32_t m[NL];
-    uint32_t r[NL];
 #pragma unroll
     for (int k = 0; k < NL; k++) {
 #pragma unroll
@@ -184,17 +198,14 @@ struct Fp {
       acc >>= LB;
     }
     r[NL - 1] = (uint32_t)acc;
-    return reduce_once(r);
   }
 
-  // Squaring: off-diagonal products computed once against a doubled operand.
-  static ZK_DEV Fp sqr(const Fp& a) {
+  static ZK_DEV void sqr_core(const Fp& a, uint32_t r[NL]) {
     uint32_t a2[NL];
 #pragma unroll
     for (int k = 0; k < NL; k++) a2[k] = a.v[k] << 1;  // < 2^30, products stay < 2^59
     uint64_t acc = 0;
     uint32_t m[NL];
-    uint32_t r[NL];
 #pragma unroll
     for (int k = 0; k < 2 * NL - 1; k++) {
       const int lo = k < NL ? 0 : k - NL + 1;
@@ -218,10 +229,72 @@ struct Fp {
       acc >>= LB;
     }
     r[NL - 1] = (uint32_t)acc;
-    return reduce_once(r);
   }
 
-  // the same products through the out-of-line functions
+  // ---- lazy forms for the group law: values kept in [0, 2m) ----
+  // Products skip the final subtraction (see mul_core); sums and differences
+  // fold back into [0, 2m) with 2m.  canon() returns the [0, m) representative.
+  static ZK_DEV Fp reduce_2m(const uint32_t r[NL]) {  // [0, 4m) -> [0, 2m)
+    uint32_t d[NL];
+    int32_t borrow = 0;
+#pragma unroll
+    for (int k = 0; k < NL; k++) {
+      const int32_t t = (int32_t)r[k] - (int32_t)M::P2[k] + borrow;
+      d[k] = (uint32_t)t & LMASK;
+      borrow = t >> LB;
+    }
+    Fp out;
+    const bool keep = borrow < 0;
+#pragma unroll
+    for (int k = 0; k < NL; k++) out.v[k] = keep ? r[k] : d[k];
+    return out;
+  }
+  static ZK_DEV Fp mul_lz(const Fp& a, const Fp& b) {
+    Fp r;
+    mul_core(a, b, r.v);
+    return r;
+  }
+  static ZK_DEV Fp sqr_lz(const Fp& a) {
+    Fp r;
+    sqr_core(a, r.v);
+    return r;
+  }
+  static ZK_DEV Fp add_lz(const Fp& a, const Fp& b) {
+    uint32_t s[NL];
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < NL; k++) {
+      const uint32_t t = a.v[k] + b.v[k] + c;
+      s[k] = t & LMASK;
+      c = t >> LB;
+    }
+    s[NL - 1] += c << LB;  // value < 4m < 2^256: the top limb absorbs the carry
+    return reduce_2m(s);
+  }
+  static ZK_DEV Fp sub_lz(const Fp& a, const Fp& b) {
+    uint32_t d[NL];
+    int32_t borrow = 0;
+#pragma unroll
+    for (int k = 0; k < NL; k++) {
+      const int32_t t = (int32_t)a.v[k] - (int32_t)b.v[k] + borrow;
+      d[k] = (uint32_t)t & LMASK;
+      borrow = t >> LB;
+    }
+    // if negative, add 2m back
+    Fp out;
+    uint32_t c = 0;
+    const uint32_t mask = borrow < 0 ? 0xffffffffu : 0u;
+#pragma unroll
+    for (int k = 0; k < NL; k++) {
+      const uint32_t t = d[k] + (M::P2[k] & mask) + c;
+      out.v[k] = t & LMASK;
+      c = t >> LB;
+    }
+    return out;
+  }
+  static ZK_DEV Fp canon(const Fp& a) { return reduce_once(a.v); }
+
+  // lazy products through the out-of-line functions
   static ZK_DEV Fp mul_oop(const Fp& a, const Fp& b) {
     return fp_mul_call<M>(a.v[0], a.v[1], a.v[2], a.v[3], a.v[4], a.v[5], a.v[6], a.v[7], a.v[8], b.v[0], b.v[1],
                           b.v[2], b.v[3], b.v[4], b.v[5], b.v[6], b.v[7], b.v[8]);
@@ -229,9 +302,14 @@ struct Fp {
   static ZK_DEV Fp sqr_oop(const Fp& a) {
     return fp_sqr_call<M>(a.v[0], a.v[1], a.v[2], a.v[3], a.v[4], a.v[5], a.v[6], a.v[7], a.v[8]);
   }
-  // the products of the group law (curve.hpp): inlined over the base field
-  static ZK_DEV Fp cmul(const Fp& a, const Fp& b) { return mul(a, b); }
-  static ZK_DEV Fp csqr(const Fp& a) { return sqr(a); }
+  // the operations of the group law (curve.hpp): lazy, products inlined
+  static ZK_DEV Fp cmul(const Fp& a, const Fp& b) { return mul_lz(a, b); }
+  static ZK_DEV Fp csqr(const Fp& a) { return sqr_lz(a); }
+  static ZK_DEV Fp cadd(const Fp& a, const Fp& b) { return add_lz(a, b); }
+  static ZK_DEV Fp csub(const Fp& a, const Fp& b) { return sub_lz(a, b); }
+  static ZK_DEV Fp cdbl(const Fp& a) { return add_lz(a, a); }
+  static ZK_DEV Fp cneg(const Fp& a) { return sub_lz(zero(), a); }
+  static ZK_DEV bool cis_zero(const Fp& a) { return is_zero(canon(a)); }
 
   static ZK_DEV bool is_zero(const Fp& a) {
     uint32_t t = 0;
@@ -289,13 +367,13 @@ __device__ __noinline__ Fp<M> fp_mul_call(uint32_t a0, uint32_t a1, uint32_t a2,
                                           uint32_t b6, uint32_t b7, uint32_t b8) {
   const Fp<M> a{{a0, a1, a2, a3, a4, a5, a6, a7, a8}};
   const Fp<M> b{{b0, b1, b2, b3, b4, b5, b6, b7, b8}};
-  return Fp<M>::mul(a, b);
+  return Fp<M>::mul_lz(a, b);
 }
 template <class M>
 __device__ __noinline__ Fp<M> fp_sqr_call(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3, uint32_t a4,
                                           uint32_t a5, uint32_t a6, uint32_t a7, uint32_t a8) {
   const Fp<M> a{{a0, a1, a2, a3, a4, a5, a6, a7, a8}};
-  return Fp<M>::sqr(a);
+  return Fp<M>::sqr_lz(a);
 }
 
 using Fq = Fp<FqParams>;
@@ -322,17 +400,23 @@ struct Fq2 {
     const Fq t = Fq::mul(a.c0, a.c1);
     return {Fq::mul(Fq::add(a.c0, a.c1), Fq::sub(a.c0, a.c1)), Fq::dbl(t)};
   }
-  // the products of the group law: through the out-of-line base-field products
+  // the operations of the group law: lazy, through the out-of-line base-field products
   static ZK_DEV Fq2 cmul(const Fq2& a, const Fq2& b) {
     const Fq v0 = Fq::mul_oop(a.c0, b.c0);
     const Fq v1 = Fq::mul_oop(a.c1, b.c1);
-    const Fq s = Fq::mul_oop(Fq::add(a.c0, a.c1), Fq::add(b.c0, b.c1));
-    return {Fq::sub(v0, v1), Fq::sub(Fq::sub(s, v0), v1)};
+    const Fq s = Fq::mul_oop(Fq::add_lz(a.c0, a.c1), Fq::add_lz(b.c0, b.c1));
+    return {Fq::sub_lz(v0, v1), Fq::sub_lz(Fq::sub_lz(s, v0), v1)};
   }
   static ZK_DEV Fq2 csqr(const Fq2& a) {
     const Fq t = Fq::mul_oop(a.c0, a.c1);
-    return {Fq::mul_oop(Fq::add(a.c0, a.c1), Fq::sub(a.c0, a.c1)), Fq::dbl(t)};
+    return {Fq::mul_oop(Fq::add_lz(a.c0, a.c1), Fq::sub_lz(a.c0, a.c1)), Fq::add_lz(t, t)};
   }
+  static ZK_DEV Fq2 cadd(const Fq2& a, const Fq2& b) { return {Fq::add_lz(a.c0, b.c0), Fq::add_lz(a.c1, b.c1)}; }
+  static ZK_DEV Fq2 csub(const Fq2& a, const Fq2& b) { return {Fq::sub_lz(a.c0, b.c0), Fq::sub_lz(a.c1, b.c1)}; }
+  static ZK_DEV Fq2 cdbl(const Fq2& a) { return cadd(a, a); }
+  static ZK_DEV Fq2 cneg(const Fq2& a) { return csub(zero(), a); }
+  static ZK_DEV bool cis_zero(const Fq2& a) { return Fq::cis_zero(a.c0) && Fq::cis_zero(a.c1); }
+  static ZK_DEV Fq2 canon(const Fq2& a) { return {Fq::canon(a.c0), Fq::canon(a.c1)}; }
   static ZK_DEV bool is_zero(const Fq2& a) { return Fq::is_zero(a.c0) && Fq::is_zero(a.c1); }
   static ZK_DEV bool eq(const Fq2& a, const Fq2& b) { return Fq::eq(a.c0, b.c0) && Fq::eq(a.c1, b.c1); }
   static ZK_DEV Fq2 select(bool c, const Fq2& a, const Fq2& b) {

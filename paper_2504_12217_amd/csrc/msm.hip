@@ -457,7 +457,7 @@ __global__ void __launch_bounds__(64) k_msm_plane_sums(BatchDev B, const uint32_
   Xyzz<F> acc = Xyzz<F>::inf();
   for (uint32_t t = threadIdx.x; t < J.bpb; t += 64) acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(pp + (size_t)t * XW));
   acc = block_tree_sum<F>(acc, sh, 64);
-  if (threadIdx.x == 0) PointIO<F>::store_xyzz(S + (size_t)blockIdx.x * XW, acc);
+  if (threadIdx.x == 0) PointIO<F>::store_xyzz(S + (size_t)blockIdx.x * XW, Xyzz<F>::canon(acc));
 }
 
 // ---------------------------------------------------------------- host driver
@@ -845,7 +845,7 @@ __global__ void __launch_bounds__(64) k_batch_affine(const uint32_t* xyzz, uint3
   for (uint32_t j = j0; j < j1; j++) {
     acc.store(prefix + (size_t)j * CW);  // product of the nonzero ZZZ before j
     const F z = F::load(xyzz + (size_t)j * XW + 3 * CW);
-    if (!F::is_zero(z)) acc = F::mul(acc, z);
+    if (!F::cis_zero(z)) acc = F::mul(acc, z);
   }
   F inv = F::inv(acc);
   for (uint32_t jj = j1; jj > j0; jj--) {
@@ -853,7 +853,7 @@ __global__ void __launch_bounds__(64) k_batch_affine(const uint32_t* xyzz, uint3
     const uint32_t* p = xyzz + (size_t)j * XW;
     const F z = F::load(p + 3 * CW);
     Affine<F> a;
-    if (F::is_zero(z)) {
+    if (F::cis_zero(z)) {
       a.x = F::zero();
       a.y = F::zero();
     } else {
