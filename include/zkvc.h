@@ -76,6 +76,7 @@ typedef struct zkvc_pk zkvc_pk; /* opaque proving key, resident in device memory
 
 /*
  * Gen (Section II; Groth16 key generation for the circuit of `shape`).
+ * Shapes: a, n, b >= 1, a <= 65535, a n b <= 2^28, QAP domain <= 2^28.
  * toxic = {tau, alpha, beta, gamma, delta}: nonzero elements of Fr, canonical;
  * tau must lie outside the evaluation domain (tau^N != 1).  z is the public
  * CRPC evaluation point (Section III-A's variable Z), required nonzero for the

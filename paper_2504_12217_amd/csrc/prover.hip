@@ -53,6 +53,7 @@ bool kind_uses_z(uint32_t kind) { return kind == ZKVC_CRPC_PSQ || kind == ZKVC_C
 Layout r1cs_layout(uint32_t a, uint32_t n, uint32_t b, uint32_t kind) {
   Layout L;
   ZK_REQUIRE(a >= 1 && n >= 1 && b >= 1, "shape dimensions must be positive");
+  ZK_REQUIRE(a <= 65535, "at most 65535 rows in X");  // the product kernel's grid rows
   ZK_REQUIRE(kind <= ZKVC_CRPC, "unknown circuit kind");
   ZK_REQUIRE((uint64_t)a * n * b <= (1ull << 28) && (uint64_t)n * 16384ull < (1ull << 40), "shape too large");
   L.a = a;
@@ -139,6 +140,8 @@ __device__ __forceinline__ void encode_int(int64_t v, uint32_t w[8]) {
     borrow = (t >> 32) & 1u;
   }
 }
+
+__device__ __forceinline__ bool kind_uses_z_dev(uint32_t kind) { return kind == ZKVC_CRPC_PSQ || kind == ZKVC_CRPC; }
 
 __device__ __forceinline__ void store_words(uint32_t* p, const uint32_t w[8]) {
   reinterpret_cast<uint4*>(p)[0] = make_uint4(w[0], w[1], w[2], w[3]);
@@ -315,12 +318,32 @@ __global__ void k_h_scalars(uint32_t count, const uint32_t* consts, uint32_t* ou
 
 // ------------------------------------------------------------------ prove kernels
 // Y = X W in int32; block (i, j-tile): X row i is shared by the block.
-__global__ void __launch_bounds__(256) k_matmul(const int8_t* X, const int8_t* W, uint32_t a, uint32_t n, uint32_t b,
-                                               int32_t* Y) {
+// ---- witness kernels.  Each takes the proofs of a batch from a job table
+// (blockIdx.z or blockIdx.y = proof); a single proof's job travels by value.
+struct WitJob {
+  uint32_t kind, a, n, b;
+  uint64_t m, ell, aux_start, N;
+  const int8_t* X;
+  const int8_t* W;
+  int32_t* Y;
+  const uint32_t* zpow;
+  uint32_t *assign, *aev, *bev, *cev;
+  uint32_t *xk, *wk, *pkk, *yz;  // CRPC kinds: per-k sums and Y(z) partial sums
+};
+struct WitTable {
+  const WitJob* jobs;  // device table, or null: use `one`
+  WitJob one;
+  __device__ __forceinline__ const WitJob& get(uint32_t q) const { return jobs ? jobs[q] : one; }
+};
+
+__global__ void __launch_bounds__(256) k_matmul(WitTable T) {
+  const WitJob& J = T.get(blockIdx.z);
   const uint32_t i = blockIdx.y;
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= b) return;
-  const int8_t* x = X + (size_t)i * n;
+  const uint32_t n = J.n, b = J.b;
+  if (i >= J.a || j >= b) return;
+  const int8_t* x = J.X + (size_t)i * n;
+  const int8_t* W = J.W;
   int32_t acc0 = 0, acc1 = 0;
   uint32_t k = 0;
   for (; k + 8 <= n; k += 8) {
@@ -331,102 +354,94 @@ __global__ void __launch_bounds__(256) k_matmul(const int8_t* X, const int8_t* W
     }
   }
   for (; k < n; k++) acc0 += (int32_t)x[k] * (int32_t)W[(size_t)k * b + j];
-  Y[(size_t)i * b + j] = acc0 + acc1;
+  J.Y[(size_t)i * b + j] = acc0 + acc1;
 }
 
 // assignment (canonical words) of the constant, x, y and w variables
-__global__ void k_assign_public(const int8_t* X, const int8_t* W, const int32_t* Y, uint32_t a, uint32_t n,
-                                uint32_t b, uint32_t* assign) {
+__global__ void k_assign_public(WitTable T) {
+  const WitJob& J = T.get(blockIdx.y);
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t an = (uint64_t)a * n, ab = (uint64_t)a * b, nb = (uint64_t)n * b;
+  const uint64_t an = (uint64_t)J.a * J.n, ab = (uint64_t)J.a * J.b, nb = (uint64_t)J.n * J.b;
   if (i >= 1 + an + ab + nb) return;
   int64_t v;
   if (i == 0) v = 1;
-  else if (i <= an) v = X[i - 1];
-  else if (i <= an + ab) v = Y[i - 1 - an];
-  else v = W[i - 1 - an - ab];
-  store_int(assign + 8ull * i, v);
+  else if (i <= an) v = J.X[i - 1];
+  else if (i <= an + ab) v = J.Y[i - 1 - an];
+  else v = J.W[i - 1 - an - ab];
+  store_int(J.assign + 8ull * i, v);
 }
 
-struct PlainRowParams {
-  uint32_t kind, a, n, b;
-  uint64_t m, aux_start;
-  const int8_t* X;
-  const int8_t* W;
-  const int32_t* Y;
-  uint32_t *assign, *aev, *bev, *cev;
-};
-
 // Multiplication rows of the plain family, and their auxiliary variables.
-__global__ void k_rows_plain(PlainRowParams p) {
+__global__ void k_rows_plain(WitTable T) {
+  const WitJob& J = T.get(blockIdx.y);
   const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= p.m) return;
-  const uint32_t n = p.n, b = p.b;
-  const uint64_t stride = p.kind == ZKVC_PLAIN_ADD ? n + 1 : n;
+  if (kind_uses_z_dev(J.kind) || c >= J.m) return;
+  const uint32_t n = J.n, b = J.b;
+  const uint64_t stride = J.kind == ZKVC_PLAIN_ADD ? n + 1 : n;
   const uint64_t ij = c / stride, k = c % stride;
   const uint64_t i = ij / b, j = ij % b;
-  auto x = [&](uint64_t kk) { return (int64_t)p.X[i * n + kk]; };
-  auto w = [&](uint64_t kk) { return (int64_t)p.W[kk * b + j]; };
-  if (p.kind == ZKVC_PLAIN_ADD && k == n) {  // (sum_k p_ijk) * 1 = y_ij
+  auto x = [&](uint64_t kk) { return (int64_t)J.X[i * n + kk]; };
+  auto w = [&](uint64_t kk) { return (int64_t)J.W[kk * b + j]; };
+  if (J.kind == ZKVC_PLAIN_ADD && k == n) {  // (sum_k p_ijk) * 1 = y_ij
     int64_t sum = 0;
     for (uint64_t kk = 0; kk < n; kk++) sum += x(kk) * w(kk);
-    store_int(p.aev + 8ull * c, sum);
-    store_int(p.bev + 8ull * c, 1);
-    store_int(p.cev + 8ull * c, p.Y[ij]);
+    store_int(J.aev + 8ull * c, sum);
+    store_int(J.bev + 8ull * c, 1);
+    store_int(J.cev + 8ull * c, J.Y[ij]);
     return;
   }
   const int64_t prod = x(k) * w(k);
-  store_int(p.aev + 8ull * c, x(k));
-  store_int(p.bev + 8ull * c, w(k));
+  store_int(J.aev + 8ull * c, x(k));
+  store_int(J.bev + 8ull * c, w(k));
   int64_t cval;
-  switch (p.kind) {
+  switch (J.kind) {
     case ZKVC_PLAIN:
       if (k < n - 1) {
         cval = prod;
-        store_int(p.assign + 8ull * (p.aux_start + ij * (n - 1) + k), prod);
+        store_int(J.assign + 8ull * (J.aux_start + ij * (n - 1) + k), prod);
       } else {  // y_ij - sum_{k' < n-1} p_ijk'
         int64_t s = 0;
         for (uint64_t kk = 0; kk + 1 < n; kk++) s += x(kk) * w(kk);
-        cval = (int64_t)p.Y[ij] - s;
+        cval = (int64_t)J.Y[ij] - s;
       }
       break;
     case ZKVC_PLAIN_ADD:
       cval = prod;
-      store_int(p.assign + 8ull * (p.aux_start + ij * n + k), prod);
+      store_int(J.assign + 8ull * (J.aux_start + ij * n + k), prod);
       break;
     default: {  // PLAIN_PSQ: s_k - s_(k-1), last row y - s_(n-2)
       int64_t before = 0;
       for (uint64_t kk = 0; kk < k; kk++) before += x(kk) * w(kk);
       if (k < n - 1) {
-        store_int(p.assign + 8ull * (p.aux_start + ij * (n - 1) + k), before + prod);
+        store_int(J.assign + 8ull * (J.aux_start + ij * (n - 1) + k), before + prod);
         cval = (before + prod) - before;
       } else {
-        cval = (int64_t)p.Y[ij] - before;
+        cval = (int64_t)J.Y[ij] - before;
       }
       break;
     }
   }
-  store_int(p.cev + 8ull * c, cval);
+  store_int(J.cev + 8ull * c, cval);
 }
 
 // Input-consistency rows m .. m + l (A = variable t) and the zero rows after them.
-__global__ void k_rows_tail(uint64_t m, uint64_t ell, uint64_t N, const uint32_t* assign, uint32_t* aev,
-                            uint32_t* bev, uint32_t* cev) {
-  const uint64_t c = m + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= N) return;
+__global__ void k_rows_tail(WitTable T) {
+  const WitJob& J = T.get(blockIdx.y);
+  const uint64_t c = J.m + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= J.N) return;
   const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
-  if (c - m <= ell) {
-    const uint4* s = reinterpret_cast<const uint4*>(assign + 8ull * (c - m));
-    reinterpret_cast<uint4*>(aev + 8ull * c)[0] = s[0];
-    reinterpret_cast<uint4*>(aev + 8ull * c)[1] = s[1];
+  if (c - J.m <= J.ell) {
+    const uint4* s = reinterpret_cast<const uint4*>(J.assign + 8ull * (c - J.m));
+    reinterpret_cast<uint4*>(J.aev + 8ull * c)[0] = s[0];
+    reinterpret_cast<uint4*>(J.aev + 8ull * c)[1] = s[1];
   } else {
-    reinterpret_cast<uint4*>(aev + 8ull * c)[0] = z4;
-    reinterpret_cast<uint4*>(aev + 8ull * c)[1] = z4;
+    reinterpret_cast<uint4*>(J.aev + 8ull * c)[0] = z4;
+    reinterpret_cast<uint4*>(J.aev + 8ull * c)[1] = z4;
   }
-  reinterpret_cast<uint4*>(bev + 8ull * c)[0] = z4;
-  reinterpret_cast<uint4*>(bev + 8ull * c)[1] = z4;
-  reinterpret_cast<uint4*>(cev + 8ull * c)[0] = z4;
-  reinterpret_cast<uint4*>(cev + 8ull * c)[1] = z4;
+  reinterpret_cast<uint4*>(J.bev + 8ull * c)[0] = z4;
+  reinterpret_cast<uint4*>(J.bev + 8ull * c)[1] = z4;
+  reinterpret_cast<uint4*>(J.cev + 8ull * c)[0] = z4;
+  reinterpret_cast<uint4*>(J.cev + 8ull * c)[1] = z4;
 }
 
 constexpr int RED_THREADS = 256;
@@ -448,50 +463,55 @@ __device__ Fr block_sum(Fr x, uint32_t* sh) {
 }
 
 // Block k: X_k(z) = sum_i z^(i b) x_ik, W_k(z) = sum_j z^j w_kj and their product.
-__global__ void __launch_bounds__(RED_THREADS) k_crpc_xw(const int8_t* X, const int8_t* W, uint32_t a, uint32_t n,
-                                                         uint32_t b, const uint32_t* zpow, uint32_t* xk,
-                                                         uint32_t* wk, uint32_t* pk) {
+__global__ void __launch_bounds__(RED_THREADS) k_crpc_xw(WitTable T) {
   __shared__ uint32_t sh[RED_THREADS * NL];
+  const WitJob& J = T.get(blockIdx.y);
   const uint32_t k = blockIdx.x;
+  if (!kind_uses_z_dev(J.kind) || k >= J.n) return;  // uniform per block
+  const uint32_t a = J.a, n = J.n, b = J.b;
   Fr sx = Fr::zero(), sw = Fr::zero();
   for (uint32_t i = threadIdx.x; i < a; i += RED_THREADS)
-    sx = Fr::add(sx, Fr::mul(Fr::load(zpow + 8ull * ((uint64_t)i * b)), fr_of_int(X[(size_t)i * n + k])));
+    sx = Fr::add(sx, Fr::mul(Fr::load(J.zpow + 8ull * ((uint64_t)i * b)), fr_of_int(J.X[(size_t)i * n + k])));
   for (uint32_t j = threadIdx.x; j < b; j += RED_THREADS)
-    sw = Fr::add(sw, Fr::mul(Fr::load(zpow + 8ull * j), fr_of_int(W[(size_t)k * b + j])));
+    sw = Fr::add(sw, Fr::mul(Fr::load(J.zpow + 8ull * j), fr_of_int(J.W[(size_t)k * b + j])));
   sx = block_sum(sx, sh);
   sw = block_sum(sw, sh);
   if (threadIdx.x == 0) {
-    sx.store(xk + 8ull * k);
-    sw.store(wk + 8ull * k);
-    Fr::mul(sx, sw).store(pk + 8ull * k);
+    sx.store(J.xk + 8ull * k);
+    sw.store(J.wk + 8ull * k);
+    Fr::mul(sx, sw).store(J.pkk + 8ull * k);
   }
 }
 
 constexpr int YZ_BLOCKS = 64;
 
-// Partial sums of Y(z) = sum_ij z^(i b + j) y_ij, one per block (YZ_BLOCKS blocks).
-__global__ void __launch_bounds__(RED_THREADS) k_crpc_yz(const int32_t* Y, uint32_t ab, const uint32_t* zpow,
-                                                         uint32_t* partial) {
+// Partial sums of Y(z) = sum_ij z^(i b + j) y_ij, one per block (YZ_BLOCKS blocks per proof).
+__global__ void __launch_bounds__(RED_THREADS) k_crpc_yz(WitTable T) {
   __shared__ uint32_t sh[RED_THREADS * NL];
+  const WitJob& J = T.get(blockIdx.y);
+  if (!kind_uses_z_dev(J.kind)) return;  // uniform per block
+  const uint32_t ab = J.a * J.b;
   Fr s = Fr::zero();
   for (uint32_t e = blockIdx.x * RED_THREADS + threadIdx.x; e < ab; e += gridDim.x * RED_THREADS)
-    s = Fr::add(s, Fr::mul(Fr::load(zpow + 8ull * e), fr_of_int(Y[e])));
+    s = Fr::add(s, Fr::mul(Fr::load(J.zpow + 8ull * e), fr_of_int(J.Y[e])));
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) s.store(partial + 8ull * blockIdx.x);
+  if (threadIdx.x == 0) s.store(J.yz + 8ull * blockIdx.x);
 }
 
-// Rows 0 .. m-1 and auxiliary variables of the CRPC kinds, one block: the
-// prefix sums s_k = sum_{k' <= k} P_k' come from a block-wide inclusive scan
-// over chunks of RED_THREADS rows with a running carry.
-__global__ void __launch_bounds__(RED_THREADS) k_crpc_rows(uint32_t kind, uint32_t n, uint64_t aux_start,
-                                                           const uint32_t* xk, const uint32_t* wk,
-                                                           const uint32_t* pk, const uint32_t* yz_partial,
-                                                           uint32_t* assign, uint32_t* aev, uint32_t* bev,
-                                                           uint32_t* cev) {
+// Rows 0 .. m-1 and auxiliary variables of the CRPC kinds, one block per
+// proof: the prefix sums s_k = sum_{k' <= k} P_k' come from a block-wide
+// inclusive scan over chunks of RED_THREADS rows with a running carry.
+__global__ void __launch_bounds__(RED_THREADS) k_crpc_rows(WitTable T) {
   __shared__ uint32_t sh[RED_THREADS * NL];
   __shared__ uint32_t carry_sh[NL];
+  const WitJob& J = T.get(blockIdx.x);
+  if (!kind_uses_z_dev(J.kind)) return;  // uniform per block
+  const uint32_t kind = J.kind, n = J.n;
+  const uint64_t aux_start = J.aux_start;
+  const uint32_t *xk = J.xk, *wk = J.wk, *pk = J.pkk;
+  uint32_t *assign = J.assign, *aev = J.aev, *bev = J.bev, *cev = J.cev;
   // Y(z) from the per-block partial sums
-  Fr yz = threadIdx.x < YZ_BLOCKS ? Fr::load(yz_partial + 8ull * threadIdx.x) : Fr::zero();
+  Fr yz = threadIdx.x < YZ_BLOCKS ? Fr::load(J.yz + 8ull * threadIdx.x) : Fr::zero();
   yz = block_sum(yz, sh);
   if (threadIdx.x == 0) {
 #pragma unroll
@@ -795,8 +815,8 @@ __global__ void k_check_top(uint32_t* const* tab, const uint32_t* one, uint32_t 
 }
 
 namespace {
-enum ProveSlot { P_X = 20, P_W, P_Y, P_ASSIGN, P_AEV, P_BEV, P_CEV, P_XK, P_WK, P_PK, P_YZ, P_XH, P_WH, P_YH };
-enum SharedSlot { C_TABLE = 60, C_FLAG };
+enum ProveSlot { P_ASSIGN = 20, P_AEV, P_BEV, P_CEV, P_XK, P_WK, P_PK, P_YZ };
+enum SharedSlot { C_TABLE = 60, C_FLAG, C_XW, C_Y, C_WTAB };
 
 // One MSM of a proof: a query segment (or the H query) and its scalars.
 struct MsmJob {
@@ -853,54 +873,111 @@ struct Slot {
   int32_t* yh;  // pinned copy of Y
 };
 
-// Witness and evaluation vectors of one proof (X, W through pinned staging,
-// Y back to pinned memory: no host wait inside the enqueue).
-Slot enqueue_witness(const ProveJob& J, Workspace& ws, hipStream_t st) {
-  const zkvc_pk* pk = J.pk;
-  const Layout& L = pk->L;
-  const uint64_t N = L.N;
-  const uint32_t a = L.a, n = L.n, b = L.b;
-  Slot S;
-  int8_t* dX = ws.get<int8_t>(P_X, (size_t)a * n);
-  int8_t* dW = ws.get<int8_t>(P_W, (size_t)n * b);
-  int32_t* dY = ws.get<int32_t>(P_Y, (size_t)a * b * 4);
-  S.assign = ws.get(P_ASSIGN, L.nv * 32);
-  S.aev = ws.get(P_AEV, N * 32);
-  S.bev = ws.get(P_BEV, N * 32);
-  S.cev = ws.get(P_CEV, N * 32);
-  int8_t* xh = ws.host<int8_t>(P_XH, (size_t)a * n);
-  int8_t* wh = ws.host<int8_t>(P_WH, (size_t)n * b);
-  S.yh = ws.host<int32_t>(P_YH, (size_t)a * b * 4);
-  std::memcpy(xh, J.X, (size_t)a * n);
-  std::memcpy(wh, J.W, (size_t)n * b);
-  ZK_HIP(hipMemcpyAsync(dX, xh, (size_t)a * n, hipMemcpyHostToDevice, st));
-  ZK_HIP(hipMemcpyAsync(dW, wh, (size_t)n * b, hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(k_matmul, dim3(cdiv(b, 256), a), dim3(256), 0, st, dX, dW, a, n, b, dY);
-  ZK_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_assign_public, dim3(cdiv(L.aux_start, 256)), dim3(256), 0, st, dX, dW, dY, a, n, b, S.assign);
-  ZK_HIP(hipGetLastError());
-  if (kind_uses_z(L.kind)) {
-    uint32_t* xk = ws.get(P_XK, (size_t)n * 32);
-    uint32_t* wk = ws.get(P_WK, (size_t)n * 32);
-    uint32_t* pkk = ws.get(P_PK, (size_t)n * 32);
-    uint32_t* yz = ws.get(P_YZ, 32 * YZ_BLOCKS);
-    hipLaunchKernelGGL(k_crpc_xw, dim3(n), dim3(RED_THREADS), 0, st, dX, dW, a, n, b, pk->zpow.get(), xk, wk, pkk);
-    ZK_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_crpc_yz, dim3(YZ_BLOCKS), dim3(RED_THREADS), 0, st, dY, a * b, pk->zpow.get(), yz);
-    ZK_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_crpc_rows, dim3(1), dim3(RED_THREADS), 0, st, L.kind, n, L.aux_start, xk, wk, pkk, yz,
-                       S.assign, S.aev, S.bev, S.cev);
-    ZK_HIP(hipGetLastError());
+// Witness and evaluation vectors of every proof of a batch, one launch per
+// kernel for all proofs.  X and W of all proofs cross PCIe in one copy from
+// pinned staging, Y of all proofs comes back in one copy to pinned memory:
+// no host wait inside the enqueue.
+std::vector<Slot> enqueue_witness_batch(const ProveJob* jobs, size_t nj, ProveGen& G, hipStream_t st) {
+  ZK_REQUIRE(nj <= 65535, "at most 65535 proofs per batch");
+  auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  std::vector<size_t> xo(nj), wo(nj), yo(nj);
+  size_t xw_bytes = 0, y_bytes = 0;
+  for (size_t j = 0; j < nj; j++) {
+    const Layout& L = jobs[j].pk->L;
+    xo[j] = xw_bytes;
+    xw_bytes += align((size_t)L.a * L.n);
+    wo[j] = xw_bytes;
+    xw_bytes += align((size_t)L.n * L.b);
+    yo[j] = y_bytes;
+    y_bytes += align((size_t)L.a * L.b * 4);
+  }
+  int8_t* xw_host = G.shared.host<int8_t>(C_XW, xw_bytes);
+  int8_t* xw_dev = G.shared.get<int8_t>(C_XW, xw_bytes);
+  int8_t* y_host = G.shared.host<int8_t>(C_Y, y_bytes);
+  int8_t* y_dev = G.shared.get<int8_t>(C_Y, y_bytes);
+  std::vector<Slot> slots(nj);
+  std::vector<WitJob> wj(nj);
+  uint32_t max_a = 0, max_b = 0, max_n_crpc = 0;
+  uint64_t max_pub = 0, max_m_plain = 0, max_tail = 0;
+  bool any_crpc = false, any_plain = false;
+  for (size_t j = 0; j < nj; j++) {
+    const zkvc_pk* pk = jobs[j].pk;
+    const Layout& L = pk->L;
+    Workspace& ws = *G.slot_ws[j];
+    Slot& S = slots[j];
+    S.assign = ws.get(P_ASSIGN, L.nv * 32);
+    S.aev = ws.get(P_AEV, L.N * 32);
+    S.bev = ws.get(P_BEV, L.N * 32);
+    S.cev = ws.get(P_CEV, L.N * 32);
+    S.yh = reinterpret_cast<int32_t*>(y_host + yo[j]);
+    std::memcpy(xw_host + xo[j], jobs[j].X, (size_t)L.a * L.n);
+    std::memcpy(xw_host + wo[j], jobs[j].W, (size_t)L.n * L.b);
+    WitJob& J = wj[j];
+    J.kind = L.kind;
+    J.a = L.a;
+    J.n = L.n;
+    J.b = L.b;
+    J.m = L.m;
+    J.ell = L.ell;
+    J.aux_start = L.aux_start;
+    J.N = L.N;
+    J.X = xw_dev + xo[j];
+    J.W = xw_dev + wo[j];
+    J.Y = reinterpret_cast<int32_t*>(y_dev + yo[j]);
+    J.zpow = pk->zpow.get();
+    J.assign = S.assign;
+    J.aev = S.aev;
+    J.bev = S.bev;
+    J.cev = S.cev;
+    if (kind_uses_z(L.kind)) {
+      J.xk = ws.get(P_XK, (size_t)L.n * 32);
+      J.wk = ws.get(P_WK, (size_t)L.n * 32);
+      J.pkk = ws.get(P_PK, (size_t)L.n * 32);
+      J.yz = ws.get(P_YZ, 32 * YZ_BLOCKS);
+      any_crpc = true;
+      max_n_crpc = std::max(max_n_crpc, L.n);
+    } else {
+      J.xk = J.wk = J.pkk = J.yz = nullptr;
+      any_plain = true;
+      max_m_plain = std::max(max_m_plain, L.m);
+    }
+    max_a = std::max(max_a, L.a);
+    max_b = std::max(max_b, L.b);
+    max_pub = std::max<uint64_t>(max_pub, L.aux_start);
+    max_tail = std::max<uint64_t>(max_tail, L.N - L.m);
+  }
+  ZK_HIP(hipMemcpyAsync(xw_dev, xw_host, xw_bytes, hipMemcpyHostToDevice, st));
+  WitTable T{};
+  if (nj == 1) {
+    T.one = wj[0];
   } else {
-    PlainRowParams rp{L.kind, a, n, b, L.m, L.aux_start, dX, dW, dY, S.assign, S.aev, S.bev, S.cev};
-    hipLaunchKernelGGL(k_rows_plain, dim3(cdiv(L.m, 256)), dim3(256), 0, st, rp);
+    WitJob* th = G.shared.host<WitJob>(C_WTAB, nj * sizeof(WitJob));
+    WitJob* td = G.shared.get<WitJob>(C_WTAB, nj * sizeof(WitJob));
+    std::memcpy(th, wj.data(), nj * sizeof(WitJob));
+    ZK_HIP(hipMemcpyAsync(td, th, nj * sizeof(WitJob), hipMemcpyHostToDevice, st));
+    T.jobs = td;
+  }
+  const unsigned J = (unsigned)nj;
+  hipLaunchKernelGGL(k_matmul, dim3(cdiv(max_b, 256), max_a, J), dim3(256), 0, st, T);
+  ZK_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_assign_public, dim3(cdiv(max_pub, 256), J), dim3(256), 0, st, T);
+  ZK_HIP(hipGetLastError());
+  if (any_crpc) {
+    hipLaunchKernelGGL(k_crpc_xw, dim3(max_n_crpc, J), dim3(RED_THREADS), 0, st, T);
+    ZK_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_crpc_yz, dim3(YZ_BLOCKS, J), dim3(RED_THREADS), 0, st, T);
+    ZK_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_crpc_rows, dim3(J), dim3(RED_THREADS), 0, st, T);
     ZK_HIP(hipGetLastError());
   }
-  hipLaunchKernelGGL(k_rows_tail, dim3(cdiv(N - L.m, 256)), dim3(256), 0, st, L.m, L.ell, N, S.assign, S.aev, S.bev,
-                     S.cev);
+  if (any_plain) {
+    hipLaunchKernelGGL(k_rows_plain, dim3(cdiv(max_m_plain, 256), J), dim3(256), 0, st, T);
+    ZK_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_rows_tail, dim3(cdiv(max_tail, 256), J), dim3(256), 0, st, T);
   ZK_HIP(hipGetLastError());
-  ZK_HIP(hipMemcpyAsync(S.yh, dY, (size_t)a * b * 4, hipMemcpyDeviceToHost, st));
-  return S;
+  ZK_HIP(hipMemcpyAsync(y_host, y_dev, y_bytes, hipMemcpyDeviceToHost, st));
+  return slots;
 }
 
 // Runs fn(i) for i < n on up to `threads` host threads.
@@ -995,9 +1072,8 @@ BatchRunPtr prove_batch_begin(ProveCtx& ctx, int g, const ProveJob* jobs_in, siz
   ZK_HIP(hipEventRecord(G.ev[0], st));
 
   // ---- witnesses and evaluation vectors
-  R.slots.resize(nj);
+  R.slots = enqueue_witness_batch(jobs, nj, G, st);
   std::vector<Slot>& slots = R.slots;
-  for (size_t j = 0; j < nj; j++) slots[j] = enqueue_witness(jobs[j], *G.slot_ws[j], st);
   ZK_HIP(hipEventRecord(G.ev[1], st));
   ZK_HIP(hipEventRecord(G.witness_ev, st));
   // ---- MSM jobs of every proof, by lane.  Those that need only the
