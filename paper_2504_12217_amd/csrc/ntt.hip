@@ -35,6 +35,7 @@ constexpr int NTT_E = 1 << NTT_MAX_K;  // elements per workgroup
 constexpr int NTT_THREADS = NTT_E / 2;
 constexpr int POW_BITS = NTT_POW_BITS;
 constexpr int MAX_LOG = NTT_MAX_LOG;
+constexpr int TOP_MAX_K = 9;  // fused top pass: 3 regions of at most 2^9 elements
 
 struct PassParams {
   uint32_t* data[NTT_MAX_BATCH];  // one vector per blockIdx.y ...
@@ -57,6 +58,64 @@ __device__ __forceinline__ Fr lds_get(const uint32_t* lds, uint32_t slot) {
 #pragma unroll
   for (int q = 0; q < NL; q++) x.v[q] = lds[slot * NL + q];
   return x;
+}
+
+// The k radix-2 stages of a pass on `nreg` consecutive LDS regions of E
+// elements (E / 2^k groups of 2^k each); every thread of the block must call.
+__device__ __forceinline__ void lds_stages(uint32_t* lds, int k, uint32_t E, int nreg, bool dit, const uint32_t* local_tab) {
+  const uint32_t K = 1u << k;
+  const uint32_t half = K >> 1;
+  const uint32_t* local = k > 0 ? local_tab + 8u * (half - 1u) : local_tab;
+  const uint32_t nb = (E / 2) * (uint32_t)nreg;
+  for (int st = 0; st < k; st++) {
+    const int s = dit ? st : (k - 1 - st);
+    const uint32_t smask = (1u << s) - 1u;
+    for (uint32_t bi = threadIdx.x; bi < nb; bi += blockDim.x) {
+      const uint32_t gl = bi >> (k - 1);  // group across all regions (regions are whole groups)
+      const uint32_t j = bi & (half - 1u);
+      const uint32_t t0 = ((j >> s) << (s + 1)) | (j & smask);
+      const uint32_t t1 = t0 | (1u << s);
+      const uint32_t widx = (j & smask) << (k - 1 - s);
+      Fr a = lds_get(lds, gl * K + t0);
+      Fr b = lds_get(lds, gl * K + t1);
+      if (dit) {
+        if (widx) b = Fr::mul(b, Fr::load(local + 8u * widx));
+        const Fr u = Fr::add(a, b);
+        const Fr v = Fr::sub(a, b);
+        a = u;
+        b = v;
+      } else {
+        const Fr u = Fr::add(a, b);
+        Fr v = Fr::sub(a, b);
+        if (widx) v = Fr::mul(v, Fr::load(local + 8u * widx));
+        a = u;
+        b = v;
+      }
+      lds_put(lds, gl * K + t0, a);
+      lds_put(lds, gl * K + t1, b);
+    }
+    __syncthreads();
+  }
+}
+
+// Element e of a block of pass (k, log_g, B = log_m - k): its group slot gl,
+// its position t inside the 2^k-point sub-transform, and its address.
+__device__ __forceinline__ uint32_t pass_addr(uint32_t e, int k, int log_g, int B, int log_m, uint32_t gamma0,
+                                              uint32_t* gl_out, uint32_t* t_out, uint32_t* g_out) {
+  uint32_t gl, t;
+  if (B == 0) {
+    gl = e >> k;
+    t = e & ((1u << k) - 1u);
+  } else {
+    gl = e & ((1u << log_g) - 1u);
+    t = e >> log_g;
+  }
+  const uint32_t gamma = gamma0 + gl;
+  const uint32_t g = gamma & ((1u << B) - 1u);
+  *gl_out = gl;
+  *t_out = t;
+  *g_out = g;
+  return ((gamma >> B) << log_m) | (t << B) | g;
 }
 
 __global__ void __launch_bounds__(NTT_THREADS) k_ntt_pass(PassParams p, NttTables T) {
@@ -102,37 +161,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_pass(PassParams p, NttTable
   __syncthreads();
 
   // ---- radix-2 stages in LDS
-  const uint32_t half = K >> 1;
-  const uint32_t* local = k > 0 ? T.local[p.inverse] + 8u * (half - 1u) : T.local[p.inverse];
-  for (int st = 0; st < k; st++) {
-    const int s = p.dit ? st : (k - 1 - st);
-    const uint32_t smask = (1u << s) - 1u;
-    for (uint32_t bi = threadIdx.x; bi < E / 2; bi += blockDim.x) {
-      const uint32_t gl = bi >> (k - 1);
-      const uint32_t j = bi & (half - 1u);
-      const uint32_t t0 = ((j >> s) << (s + 1)) | (j & smask);
-      const uint32_t t1 = t0 | (1u << s);
-      const uint32_t widx = (j & smask) << (k - 1 - s);
-      Fr a = lds_get(lds, gl * K + t0);
-      Fr b = lds_get(lds, gl * K + t1);
-      if (p.dit) {
-        if (widx) b = Fr::mul(b, Fr::load(local + 8u * widx));
-        const Fr u = Fr::add(a, b);
-        const Fr v = Fr::sub(a, b);
-        a = u;
-        b = v;
-      } else {
-        const Fr u = Fr::add(a, b);
-        Fr v = Fr::sub(a, b);
-        if (widx) v = Fr::mul(v, Fr::load(local + 8u * widx));
-        a = u;
-        b = v;
-      }
-      lds_put(lds, gl * K + t0, a);
-      lds_put(lds, gl * K + t1, b);
-    }
-    __syncthreads();
-  }
+  lds_stages(lds, k, E, 1, p.dit, T.local[p.inverse]);
 
   // ---- store, with DIF twiddles and last-pass fusions
   for (uint32_t e = threadIdx.x; e < E; e += blockDim.x) {
@@ -161,6 +190,88 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_pass(PassParams p, NttTable
       if (p.post_canon) x = Fr::from_mont(x);
     }
     x.store(data + 8ull * addr);
+  }
+}
+
+// ---- fused passes of the QAP quotient chain.  The inverse transform's last
+// pass and the coset transform's first pass cover the same (bottom) bit
+// range, so one block does both with the coset scaling between them; the
+// coset transform's last pass, the pointwise quotient and the inverse coset
+// transform's first pass cover the same (top) bit range, so one block does
+// all three for a proof's A, B and C.
+struct FusedParams {
+  uint32_t* data[3];          // one proof's A, B, C ...
+  uint32_t* const* table;     // ... or a device table, 3 entries per proof
+  int log_n, k, log_g;
+  const uint32_t* ninv;       // N^-1 (bottom: with the coset scaling)
+  const uint32_t* zinv;       // (g^N - 1)^-1 (top: the pointwise quotient)
+};
+
+// Bottom fusion, one vector per blockIdx.y (A, B, C of each proof in turn).
+__global__ void __launch_bounds__(NTT_THREADS) k_ntt_fused_bottom(FusedParams p, NttTables T) {
+  extern __shared__ uint32_t lds[];
+  const int k = p.k;
+  const uint32_t E = 1u << (k + p.log_g);
+  const uint32_t gamma0 = blockIdx.x << p.log_g;
+  uint32_t* const data = p.table ? p.table[blockIdx.y] : p.data[blockIdx.y];
+  uint32_t gl, t, g;
+  for (uint32_t e = threadIdx.x; e < E; e += blockDim.x) {
+    const uint32_t addr = pass_addr(e, k, p.log_g, 0, k, gamma0, &gl, &t, &g);
+    lds_put(lds, gl * (1u << k) + t, Fr::load(data + 8ull * addr));
+  }
+  __syncthreads();
+  lds_stages(lds, k, E, 1, false, T.local[1]);  // inverse DIF, last pass (no twiddle)
+  const Fr ninv = Fr::load(p.ninv);
+  for (uint32_t e = threadIdx.x; e < E; e += blockDim.x) {
+    const uint32_t addr = pass_addr(e, k, p.log_g, 0, k, gamma0, &gl, &t, &g);
+    const uint32_t slot = gl * (1u << k) + t;
+    // coefficient bitrev(addr) of the inverse transform times g^i / N
+    const Fr x = Fr::mul(Fr::mul(lds_get(lds, slot), pow_lookup(T.g[0], bitrev_bits(addr, p.log_n))), ninv);
+    lds_put(lds, slot, x);
+  }
+  __syncthreads();
+  lds_stages(lds, k, E, 1, true, T.local[0]);  // forward DIT, first pass (no twiddle)
+  for (uint32_t e = threadIdx.x; e < E; e += blockDim.x) {
+    const uint32_t addr = pass_addr(e, k, p.log_g, 0, k, gamma0, &gl, &t, &g);
+    lds_get(lds, gl * (1u << k) + t).store(data + 8ull * addr);
+  }
+}
+
+// Top fusion, one proof per blockIdx.y; the quotient overwrites A.
+__global__ void __launch_bounds__(NTT_THREADS) k_ntt_fused_top(FusedParams p, NttTables T) {
+  extern __shared__ uint32_t lds[];
+  const int k = p.k, L = p.log_n, B = L - k;
+  const uint32_t K = 1u << k;
+  const uint32_t E = 1u << (k + p.log_g);
+  const uint32_t gamma0 = blockIdx.x << p.log_g;
+  const int tw_shift = MAX_LOG - L;
+  uint32_t* vec[3];
+#pragma unroll
+  for (int v = 0; v < 3; v++) vec[v] = p.table ? p.table[3 * blockIdx.y + v] : p.data[v];
+  uint32_t gl, t, g;
+  for (uint32_t e = threadIdx.x; e < 3 * E; e += blockDim.x) {
+    const uint32_t v = e / E, el = e - v * E;
+    const uint32_t addr = pass_addr(el, k, p.log_g, B, L, gamma0, &gl, &t, &g);
+    Fr x = Fr::load(vec[v] + 8ull * addr);
+    const uint32_t ex = g * bitrev_bits(t, k);  // forward DIT twiddle first
+    if (ex) x = Fr::mul(x, pow_lookup(T.w[0], ex << tw_shift));
+    lds_put(lds, v * E + gl * K + t, x);
+  }
+  __syncthreads();
+  lds_stages(lds, k, E, 3, true, T.local[0]);  // forward DIT, last pass, on A, B and C
+  const Fr zinv = Fr::load(p.zinv);
+  for (uint32_t e = threadIdx.x; e < E; e += blockDim.x) {
+    const Fr a = lds_get(lds, e), b = lds_get(lds, E + e), c = lds_get(lds, 2 * E + e);
+    lds_put(lds, e, Fr::mul(Fr::sub(Fr::mul(a, b), c), zinv));
+  }
+  __syncthreads();
+  lds_stages(lds, k, E, 1, false, T.local[1]);  // inverse DIF, first pass
+  for (uint32_t e = threadIdx.x; e < E; e += blockDim.x) {
+    const uint32_t addr = pass_addr(e, k, p.log_g, B, L, gamma0, &gl, &t, &g);
+    Fr x = lds_get(lds, gl * K + t);
+    const uint32_t ex = g * bitrev_bits(t, k);  // inverse DIF twiddle last
+    if (ex) x = Fr::mul(x, pow_lookup(T.w[1], ex << tw_shift));
+    x.store(vec[0] + 8ull * addr);
   }
 }
 
@@ -299,61 +410,82 @@ const NttTables& ntt_tables(int device) {
 
 namespace {
 
+// The passes of one transform: pass j covers bits [log_m[j] - k[j], log_m[j])
+// of the address (DIF order: the top bit range first).
+struct PassPlan {
+  int L = 0, kmax = 0, npass = 0;
+  int k[NTT_MAX_LOG + 1] = {};
+  int log_m[NTT_MAX_LOG + 1] = {};
+  int log_g(int j) const {
+    const int a = kmax - k[j], b = L - k[j];
+    return a < b ? a : b;
+  }
+};
+
+PassPlan plan_passes(int L, int min_pass, int max_k) {
+  PassPlan pl;
+  pl.L = L;
+  // small transforms use 256-element workgroups so that a pass still spreads
+  // over the device; large ones use 1024 (fewer passes over HBM)
+  const int tk = tuning().ntt_kmax[L].load();
+  pl.kmax = (tk >= 1 && tk <= NTT_MAX_K) ? tk : (L <= 18 ? 8 : NTT_MAX_K);
+  int np = L == 0 ? 1 : (L + pl.kmax - 1) / pl.kmax;
+  if (np < min_pass) np = min_pass;
+  while ((L + np - 1) / np > max_k) np++;
+  pl.npass = np;
+  int lm = L;
+  for (int j = 0; j < np; j++) {
+    pl.k[j] = L / np + (j < L % np ? 1 : 0);
+    pl.log_m[j] = lm;
+    lm -= pl.k[j];
+  }
+  return pl;
+}
+
+// One pass of a transform over nvec vectors (direct pointers or a device table).
+void launch_pass(uint32_t* const* data, uint32_t* const* dev_table, int nvec, const PassPlan& pl, int j, bool dit,
+                 bool inverse, bool first, bool last, const NttFuse& fuse, const NttTables& T, hipStream_t st) {
+  const int L = pl.L, k = pl.k[j];
+  PassParams p{};
+  if (dev_table)
+    p.table = dev_table;
+  else
+    for (int v = 0; v < nvec; v++) p.data[v] = data[v];
+  p.log_n = L;
+  p.log_m = pl.log_m[j];
+  p.k = k;
+  p.log_g = pl.log_g(j);
+  p.dit = dit;
+  p.inverse = inverse ? 1 : 0;
+  p.twiddle = pl.log_m[j] > k;
+  p.first = first;
+  p.last = last;
+  p.pre_mont = fuse.in_canonical;
+  p.pre_coset = fuse.pre_coset;
+  p.pre_bitrev = fuse.pre_bitrev;
+  p.pre_const = fuse.pre_const;
+  p.post_canon = fuse.out_canonical;
+  p.post_coset = fuse.post_coset;
+  p.post_bitrev = fuse.post_bitrev;
+  p.post_const = fuse.post_const;
+  const unsigned grid = 1u << (L - k - p.log_g);
+  const size_t lds = (size_t)(1u << (k + p.log_g)) * NL * 4;
+  unsigned threads = (1u << (k + p.log_g)) / 2;
+  if (threads < 64) threads = 64;
+  ProfScope ps("ntt_pass", st, (double)nvec * (double)(1ull << L) * k / 2.0);  // radix-2 butterflies
+  hipLaunchKernelGGL(k_ntt_pass, dim3(grid, nvec), dim3(threads), lds, st, p, T);
+  ZK_HIP(hipGetLastError());
+}
+
 void ntt_launch_impl(uint32_t* const* data, uint32_t* const* dev_table, int nvec, int log_n, bool dit, bool inverse,
                      const NttFuse& fuse, hipStream_t st) {
   ZK_REQUIRE(log_n >= 0 && log_n <= MAX_LOG, "log_n out of range");
   ZK_REQUIRE(nvec >= 1 && nvec <= (dev_table ? 65535 : NTT_MAX_BATCH), "NTT batch size out of range");
   const NttTables& T = ntt_tables(current_device());
-  const int L = log_n;
-  // small transforms use 256-element workgroups so that a pass still spreads
-  // over the device; large ones use 1024 (fewer passes over HBM)
-  const int tk = tuning().ntt_kmax[L].load();
-  const int kmax = (tk >= 1 && tk <= NTT_MAX_K) ? tk : (L <= 18 ? 8 : NTT_MAX_K);
-  const int npass = L == 0 ? 1 : (L + kmax - 1) / kmax;
-  std::vector<int> ks(npass);
-  for (int j = 0; j < npass; j++) ks[j] = L / npass + (j < L % npass ? 1 : 0);
-  // DIF order: top bit range first.  log_m of pass j = L - sum_{i<j} k_i.
-  std::vector<int> log_ms(npass);
-  int lm = L;
-  for (int j = 0; j < npass; j++) {
-    log_ms[j] = lm;
-    lm -= ks[j];
-  }
-  for (int step = 0; step < npass; step++) {
-    const int j = dit ? (npass - 1 - step) : step;
-    const int k = ks[j];
-    const int B = log_ms[j] - k;
-    PassParams p{};
-    if (dev_table)
-      p.table = dev_table;
-    else
-      for (int v = 0; v < nvec; v++) p.data[v] = data[v];
-    p.log_n = L;
-    p.log_m = log_ms[j];
-    p.k = k;
-    const int max_log_g = kmax - k;
-    const int log_groups_total = L - k;
-    p.log_g = max_log_g < log_groups_total ? max_log_g : log_groups_total;
-    p.dit = dit;
-    p.inverse = inverse ? 1 : 0;
-    p.twiddle = B > 0;
-    p.first = step == 0;
-    p.last = step == npass - 1;
-    p.pre_mont = fuse.in_canonical;
-    p.pre_coset = fuse.pre_coset;
-    p.pre_bitrev = fuse.pre_bitrev;
-    p.pre_const = fuse.pre_const;
-    p.post_canon = fuse.out_canonical;
-    p.post_coset = fuse.post_coset;
-    p.post_bitrev = fuse.post_bitrev;
-    p.post_const = fuse.post_const;
-    const unsigned grid = 1u << (log_groups_total - p.log_g);
-    const size_t lds = (size_t)(1u << (k + p.log_g)) * NL * 4;
-    unsigned threads = (1u << (k + p.log_g)) / 2;
-    if (threads < 64) threads = 64;
-    ProfScope ps("ntt_pass", st, (double)nvec * (double)(1ull << L) * k / 2.0);  // radix-2 butterflies
-    hipLaunchKernelGGL(k_ntt_pass, dim3(grid, nvec), dim3(threads), lds, st, p, T);
-    ZK_HIP(hipGetLastError());
+  const PassPlan pl = plan_passes(log_n, 1, NTT_MAX_K);
+  for (int step = 0; step < pl.npass; step++) {
+    const int j = dit ? (pl.npass - 1 - step) : step;
+    launch_pass(data, dev_table, nvec, pl, j, dit, inverse, step == 0, step == pl.npass - 1, fuse, T, st);
   }
 }
 
@@ -371,6 +503,64 @@ void ntt_launch_table(uint32_t* const* dev_table, int nvec, int log_n, bool dit,
 
 void ntt_launch(uint32_t* data, int log_n, bool dit, bool inverse, const NttFuse& fuse, hipStream_t st) {
   ntt_launch_batch(&data, 1, log_n, dit, inverse, fuse, st);
+}
+
+void qap_quotient_launch(uint32_t* const* abc, uint32_t* const* dev_table, int nproofs, int log_n, hipStream_t st) {
+  ZK_REQUIRE(log_n >= 2 && log_n <= MAX_LOG, "quotient domain out of range");
+  ZK_REQUIRE(nproofs >= 1 && 3 * nproofs <= 65535 && (dev_table || nproofs == 1), "quotient batch out of range");
+  const NttTables& T = ntt_tables(current_device());
+  const int L = log_n;
+  // at least two passes (the fused kernels need distinct top and bottom bit
+  // ranges); the top pass keeps three 2^k-element regions in 64 KiB of LDS
+  const PassPlan pl = plan_passes(L, 2, TOP_MAX_K);
+  const int P = pl.npass;
+  const int nvec = 3 * nproofs;
+  uint32_t* const* a_tab = dev_table ? dev_table + nvec : nullptr;
+  NttFuse f1;
+  f1.in_canonical = true;
+  NttFuse f3;
+  f3.post_const = T.ninv + 8 * L;
+  f3.post_coset = -1;
+  f3.post_bitrev = true;
+  const NttFuse none;
+  // inverse transform (DIF), all passes but the bottom one
+  for (int j = 0; j < P - 1; j++) launch_pass(abc, dev_table, nvec, pl, j, false, true, j == 0, false, f1, T, st);
+  FusedParams fp{};
+  if (dev_table)
+    fp.table = dev_table;
+  else
+    for (int v = 0; v < 3; v++) fp.data[v] = abc[v];
+  fp.log_n = L;
+  fp.ninv = T.ninv + 8 * L;
+  fp.zinv = T.coset_zinv + 8 * L;
+  {
+    // bottom: inverse DIF pass, coset scaling, forward DIT pass
+    const int j = P - 1;
+    fp.k = pl.k[j];
+    fp.log_g = pl.log_g(j);
+    const uint32_t E = 1u << (fp.k + fp.log_g);
+    ProfScope ps("ntt_fused_bottom", st, (double)nvec * (double)(1ull << L) * fp.k);
+    hipLaunchKernelGGL(k_ntt_fused_bottom, dim3(1u << (L - fp.k - fp.log_g), nvec), dim3(E < 128 ? 64 : E / 2),
+                       (size_t)E * NL * 4, st, fp, T);
+    ZK_HIP(hipGetLastError());
+  }
+  // forward DIT passes between the bottom and the top
+  for (int j = P - 2; j >= 1; j--) launch_pass(abc, dev_table, nvec, pl, j, true, false, false, false, none, T, st);
+  {
+    // top: forward DIT pass, pointwise quotient, inverse DIF pass
+    fp.k = pl.k[0];
+    const int a = TOP_MAX_K - fp.k, b = pl.log_g(0);
+    fp.log_g = a < b ? a : b;
+    const uint32_t E = 1u << (fp.k + fp.log_g);
+    ProfScope ps("ntt_fused_top", st, (double)nproofs * (double)(1ull << L) * (1.5 * fp.k + 1.0));
+    hipLaunchKernelGGL(k_ntt_fused_top, dim3(1u << (L - fp.k - fp.log_g), nproofs), dim3(E < 128 ? 64 : E / 2),
+                       (size_t)3 * E * NL * 4, st, fp, T);
+    ZK_HIP(hipGetLastError());
+  }
+  // inverse coset transform (DIF) on A, the remaining passes
+  uint32_t* const a_only[1] = {abc ? abc[0] : nullptr};
+  for (int j = 1; j < P; j++)
+    launch_pass(dev_table ? nullptr : a_only, a_tab, nproofs, pl, j, false, true, false, j == P - 1, f3, T, st);
 }
 
 void bitrev_launch(uint32_t* data, int log_n, hipStream_t st) {

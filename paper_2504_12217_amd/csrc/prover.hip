@@ -571,14 +571,6 @@ __global__ void __launch_bounds__(RED_THREADS) k_crpc_rows(WitTable T) {
   }
 }
 
-// q = (A B - C) / (g^N - 1) on the coset, written over A.
-__global__ void k_qap_pointwise(uint32_t* A, const uint32_t* B, const uint32_t* C, uint64_t N, const uint32_t* zinv) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const Fr a = Fr::load(A + 8ull * i), b = Fr::load(B + 8ull * i), c = Fr::load(C + 8ull * i);
-  Fr::mul(Fr::sub(Fr::mul(a, b), c), Fr::load(zinv)).store(A + 8ull * i);
-}
-
 // ------------------------------------------------------------------ host: setup
 namespace {
 
@@ -788,18 +780,6 @@ zkvc_pk* groth16_setup(const Layout& L, const host::HFr toxic[5], const host::HF
 }
 
 // ------------------------------------------------------------------ host: prove
-// q = (A B - C) / (g^N - 1) on the coset for a batch of proofs of one domain
-// size; tab lists (A, B, C) per proof; the result overwrites A.
-__global__ void k_qap_pointwise_batch(uint32_t* const* tab, uint64_t N, const uint32_t* zinv) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  uint32_t* A = tab[3 * blockIdx.y];
-  const uint32_t* B = tab[3 * blockIdx.y + 1];
-  const uint32_t* C = tab[3 * blockIdx.y + 2];
-  const Fr a = Fr::load(A + 8ull * i), b = Fr::load(B + 8ull * i), c = Fr::load(C + 8ull * i);
-  Fr::mul(Fr::sub(Fr::mul(a, b), c), Fr::load(zinv)).store(A + 8ull * i);
-}
-
 // flag |= 1 if some proof's h_{N-1} (the last element of its quotient, which
 // bit reversal leaves in place) is nonzero: the quotient of a satisfied
 // system has degree < N - 1.  The vectors come from a table (count of them)
@@ -1067,7 +1047,6 @@ BatchRunPtr prove_batch_begin(ProveCtx& ctx, int g, const ProveJob* jobs_in, siz
   R.host_t0 = std::chrono::steady_clock::now();
   const ProveJob* jobs = R.jobs.data();
   ProveGen& G = ctx.gen[g];
-  const NttTables& T = ntt_tables(ctx.device);
   while (G.slot_ws.size() < nj) G.slot_ws.emplace_back(new Workspace());
   ZK_HIP(hipEventRecord(G.ev[0], st));
 
@@ -1144,37 +1123,17 @@ BatchRunPtr prove_batch_begin(ProveCtx& ctx, int g, const ProveJob* jobs_in, siz
     const int Lg = kv.first;
     const uint64_t N = 1ull << Lg;
     const size_t k = kv.second.size();
-    NttFuse f1;
-    f1.in_canonical = true;
-    NttFuse f2;
-    f2.pre_coset = 1;
-    f2.pre_bitrev = true;
-    f2.pre_const = T.ninv + 8 * Lg;
-    NttFuse f3;
-    f3.post_const = T.ninv + 8 * Lg;
-    f3.post_coset = -1;
-    f3.post_bitrev = true;
-    const uint32_t* zinv = T.coset_zinv + 8 * Lg;
     if (k == 1) {
       const Slot& S = slots[kv.second[0]];
       uint32_t* const vecs[3] = {S.aev, S.bev, S.cev};
-      ntt_launch_batch(vecs, 3, Lg, false, true, f1, st);
-      ntt_launch_batch(vecs, 3, Lg, true, false, f2, st);
-      hipLaunchKernelGGL(k_qap_pointwise, dim3(cdiv(N, 256)), dim3(256), 0, st, S.aev, S.bev, S.cev, N, zinv);
-      ZK_HIP(hipGetLastError());
-      ntt_launch(S.aev, Lg, false, true, f3, st);
+      qap_quotient_launch(vecs, nullptr, 1, Lg, st);
       hipLaunchKernelGGL(k_check_top, dim3(1), dim3(64), 0, st, (uint32_t* const*)nullptr, S.aev, 1u, N, flag);
       ZK_HIP(hipGetLastError());
     } else {
       uint32_t** tg = tab_dev + tab_off[gi];
-      uint32_t** ta = tg + 3 * k;
-      ntt_launch_table(tg, (int)(3 * k), Lg, false, true, f1, st);
-      ntt_launch_table(tg, (int)(3 * k), Lg, true, false, f2, st);
-      hipLaunchKernelGGL(k_qap_pointwise_batch, dim3(cdiv(N, 256), (unsigned)k), dim3(256), 0, st, tg, N, zinv);
-      ZK_HIP(hipGetLastError());
-      ntt_launch_table(ta, (int)k, Lg, false, true, f3, st);
-      hipLaunchKernelGGL(k_check_top, dim3(cdiv(k, 64)), dim3(64), 0, st, ta, (const uint32_t*)nullptr, (uint32_t)k,
-                         N, flag);
+      qap_quotient_launch(nullptr, tg, (int)k, Lg, st);
+      hipLaunchKernelGGL(k_check_top, dim3(cdiv(k, 64)), dim3(64), 0, st, tg + 3 * k, (const uint32_t*)nullptr,
+                         (uint32_t)k, N, flag);
       ZK_HIP(hipGetLastError());
     }
     gi++;
