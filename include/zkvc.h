@@ -128,6 +128,21 @@ typedef struct {
 int zkvc_prove_batch(const zkvc_prove_job* jobs, size_t njobs, void* hip_stream);
 
 /*
+ * Graph replay of repeated proofs (off by default).  When on, zkvc_prove and
+ * zkvc_prove_batch capture the device work of a composition (the sequence of
+ * keys of a call, on one stream) into a HIP graph the second time it runs in
+ * a row on a context, and replay that graph for later calls of the same
+ * composition: one launch instead of one per kernel, with only X and W
+ * restaged.  Results are bit-identical either way.  Off by default because
+ * the eager launches on the context's three streams measured faster (the
+ * graph's nodes are dispatched in capture order, which delays the lanes
+ * captured last).  The proving server always launches eagerly.  enable: 1
+ * on, 0 off (process-wide, affects later calls).  Returns the previous
+ * setting.  Host only; never fails.
+ */
+int zkvc_set_graphs(int enable);
+
+/*
  * Proving server (continuous batching).  One worker thread proves submitted
  * jobs in batches: each batch takes every queued job that fits max_batch and
  * memory_budget (bytes of estimated device workspace admitted at once; 0 = no

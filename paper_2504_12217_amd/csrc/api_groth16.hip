@@ -104,6 +104,8 @@ int zkvc_prove_batch(const zkvc_prove_job* jobs, size_t njobs, void* hip_stream)
   });
 }
 
+int zkvc_set_graphs(int enable) { return set_graphs(enable); }
+
 int zkvc_verify(const uint8_t* vk, size_t vk_len, const int8_t* X, const int32_t* Y, const zkvc_proof* proof) {
   int result = 0;
   const int rc = guarded([&] {

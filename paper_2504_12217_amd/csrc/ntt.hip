@@ -249,8 +249,9 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fused_top(FusedParams p, Nt
 #pragma unroll
   for (int v = 0; v < 3; v++) vec[v] = p.table ? p.table[3 * blockIdx.y + v] : p.data[v];
   uint32_t gl, t, g;
+  const int log_e = k + p.log_g;
   for (uint32_t e = threadIdx.x; e < 3 * E; e += blockDim.x) {
-    const uint32_t v = e / E, el = e - v * E;
+    const uint32_t v = e >> log_e, el = e & (E - 1u);
     const uint32_t addr = pass_addr(el, k, p.log_g, B, L, gamma0, &gl, &t, &g);
     Fr x = Fr::load(vec[v] + 8ull * addr);
     const uint32_t ex = g * bitrev_bits(t, k);  // forward DIT twiddle first
@@ -553,7 +554,9 @@ void qap_quotient_launch(uint32_t* const* abc, uint32_t* const* dev_table, int n
     fp.log_g = a < b ? a : b;
     const uint32_t E = 1u << (fp.k + fp.log_g);
     ProfScope ps("ntt_fused_top", st, (double)nproofs * (double)(1ull << L) * (1.5 * fp.k + 1.0));
-    hipLaunchKernelGGL(k_ntt_fused_top, dim3(1u << (L - fp.k - fp.log_g), nproofs), dim3(E < 128 ? 64 : E / 2),
+    // one butterfly of each of the three regions per thread and stage
+    const uint32_t threads = 3 * E / 2 < 64 ? 64 : (3 * E / 2 > NTT_THREADS ? NTT_THREADS : 3 * E / 2);
+    hipLaunchKernelGGL(k_ntt_fused_top, dim3(1u << (L - fp.k - fp.log_g), nproofs), dim3(threads),
                        (size_t)3 * E * NL * 4, st, fp, T);
     ZK_HIP(hipGetLastError());
   }

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "api_common.hpp"
+#include "util.hpp"
 
 namespace zkvc {
 namespace {
@@ -23,6 +24,8 @@ struct Rec {
   double work = 0;
   bool stopped = false;
   bool work_dev = false;
+  bool fixed = false;  // ms already measured (a graph replay's record)
+  float ms = 0.f;
 };
 
 std::mutex g_mu;
@@ -34,18 +37,90 @@ bool g_ready = false;
 Rec g_recs[POOL];
 hipStream_t g_st[POOL];
 
+// slots for scopes captured into graphs (owned by their graph until released)
+constexpr int GPOOL = 4096;
+hipEvent_t g_gev[2 * GPOOL];
+uint32_t* g_gwords = nullptr;  // pinned, GPOOL words
+Rec g_grecs[GPOOL];
+std::vector<int> g_gfree;
+thread_local std::vector<int>* t_sink = nullptr;
+
+int graph_slot_alloc() {
+  std::lock_guard<std::mutex> lock(g_mu);
+  if (!g_ready || g_gfree.empty()) return -1;
+  const int k = g_gfree.back();
+  g_gfree.pop_back();
+  return k;
+}
+
+bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return cs == hipStreamCaptureStatusActive;
+}
+
 }  // namespace
+
+void set_capture_sink(std::vector<int>* sink) { t_sink = sink; }
+
+void collect_graph_slots(const std::vector<int>& slots) {
+  if (!profiling_enabled()) return;
+  for (int gk : slots) {
+    const Rec& r = g_grecs[gk];
+    if (!r.stopped) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, g_gev[2 * gk], g_gev[2 * gk + 1]) != hipSuccess) {
+      (void)hipGetLastError();
+      continue;
+    }
+    const int k = g_next.fetch_add(1);
+    if (k >= POOL) return;
+    g_recs[k] = r;
+    g_recs[k].work = r.work_dev ? (double)g_gwords[gk] : r.work;
+    g_recs[k].work_dev = false;
+    g_recs[k].fixed = true;
+    g_recs[k].ms = ms;
+  }
+}
+
+void release_graph_slots(std::vector<int>& slots) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  for (int k : slots) g_gfree.push_back(k);
+  slots.clear();
+}
 
 bool profiling_enabled() { return g_on.load(std::memory_order_relaxed); }
 
 ProfScope::ProfScope(const char* name, hipStream_t st, double work) : st_(st) {
   if (!profiling_enabled()) return;
+  if (capturing(st)) {
+    if (!t_sink) return;
+    const int k = graph_slot_alloc();
+    if (k < 0) return;
+    g_grecs[k] = Rec();
+    g_grecs[k].name = name;
+    g_grecs[k].work = work;
+    if (record_event_nothrow(g_gev[2 * k], st) != hipSuccess) {
+      (void)hipGetLastError();
+      std::vector<int> back{k};
+      release_graph_slots(back);
+      return;
+    }
+    t_sink->push_back(k);
+    slot_ = k;
+    graph_ = true;
+    return;
+  }
   const int k = g_next.fetch_add(1);
   if (k >= POOL) return;
   g_recs[k].name = name;
   g_recs[k].work = work;
   g_recs[k].stopped = false;
   g_recs[k].work_dev = false;
+  g_recs[k].fixed = false;
   g_st[k] = st;
   if (hipEventRecord(g_ev[2 * k], st) != hipSuccess) return;
   slot_ = k;
@@ -53,12 +128,21 @@ ProfScope::ProfScope(const char* name, hipStream_t st, double work) : st_(st) {
 
 void ProfScope::set_work_from_device(const uint32_t* p) {
   if (slot_ < 0) return;
+  if (graph_) {
+    if (hipMemcpyAsync(g_gwords + slot_, p, 4, hipMemcpyDeviceToHost, st_) == hipSuccess) g_grecs[slot_].work_dev = true;
+    return;
+  }
   if (hipMemcpyAsync(g_words + slot_, p, 4, hipMemcpyDeviceToHost, st_) == hipSuccess) g_recs[slot_].work_dev = true;
 }
 
 void ProfScope::stop() {
   if (slot_ < 0) return;
-  if (hipEventRecord(g_ev[2 * slot_ + 1], st_) == hipSuccess) g_recs[slot_].stopped = true;
+  if (graph_) {
+    if (record_event_nothrow(g_gev[2 * slot_ + 1], st_) == hipSuccess)
+      g_grecs[slot_].stopped = true;
+  } else if (hipEventRecord(g_ev[2 * slot_ + 1], st_) == hipSuccess) {
+    g_recs[slot_].stopped = true;
+  }
   slot_ = -1;
 }
 
@@ -75,7 +159,10 @@ int zkvc_profile_begin(void) {
     std::lock_guard<std::mutex> lock(g_mu);
     if (!g_ready) {
       for (auto& e : g_ev) ZK_HIP(hipEventCreate(&e));
+      for (auto& e : g_gev) ZK_HIP(hipEventCreate(&e));
       ZK_HIP(hipHostMalloc(reinterpret_cast<void**>(&g_words), POOL * 4, hipHostMallocDefault));
+      ZK_HIP(hipHostMalloc(reinterpret_cast<void**>(&g_gwords), GPOOL * 4, hipHostMallocDefault));
+      for (int k = GPOOL - 1; k >= 0; k--) g_gfree.push_back(k);
       g_ready = true;
     }
     ZK_HIP(hipDeviceSynchronize());
@@ -95,8 +182,8 @@ int zkvc_profile_read(zkvc_kernel_stat* out, int capacity, int* count) {
     for (int k = 0; k < n; k++) {
       const Rec& r = g_recs[k];
       if (!r.stopped) continue;
-      float ms = 0.f;
-      ZK_HIP(hipEventElapsedTime(&ms, g_ev[2 * k], g_ev[2 * k + 1]));
+      float ms = r.ms;
+      if (!r.fixed) ZK_HIP(hipEventElapsedTime(&ms, g_ev[2 * k], g_ev[2 * k + 1]));
       zkvc_kernel_stat& s = agg[r.name];
       std::strncpy(s.name, r.name, sizeof(s.name) - 1);
       s.launches += 1;

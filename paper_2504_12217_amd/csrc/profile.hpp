@@ -7,9 +7,19 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 namespace zkvc {
 
 bool profiling_enabled();
+
+// Inside a stream capture a scope records its two events as event nodes of
+// the graph, in slots of a separate pool listed in the capturing thread's
+// sink; each replay re-records them, and collect_graph_slots adds that
+// replay's records to the open profile once the replay has completed.
+void set_capture_sink(std::vector<int>* sink);
+void collect_graph_slots(const std::vector<int>& slots);
+void release_graph_slots(std::vector<int>& slots);
 
 class ProfScope {
  public:
@@ -21,6 +31,7 @@ class ProfScope {
 
  private:
   int slot_ = -1;
+  bool graph_ = false;
   hipStream_t st_;
 };
 

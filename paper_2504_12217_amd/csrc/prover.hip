@@ -24,6 +24,7 @@
 #include "prover.hpp"
 
 #include <array>
+#include <atomic>
 #include <chrono>
 #include <algorithm>
 #include <thread>
@@ -36,6 +37,8 @@
 #include "field.hpp"
 #include "msm.hpp"
 #include "ntt.hpp"
+#include "profile.hpp"
+#include "tune.hpp"
 
 namespace zkvc {
 
@@ -622,6 +625,8 @@ zkvc_pk* groth16_setup(const Layout& L, const host::HFr toxic[5], const host::HF
   if (use_z) ZK_REQUIRE(z != nullptr && !z->is_zero(), "this circuit kind needs a nonzero z");
 
   std::unique_ptr<zkvc_pk> pk(new zkvc_pk());
+  static std::atomic<uint64_t> serial{0};
+  pk->id = ++serial;
   pk->L = L;
   pk->device = current_device();
   pk->has_z = use_z;
@@ -850,7 +855,8 @@ std::vector<MsmJob> msm_jobs(const zkvc_pk* pk, const uint32_t* assign, const ui
 // Device buffers of one proof in flight.
 struct Slot {
   uint32_t *assign, *aev, *bev, *cev;
-  int32_t* yh;  // pinned copy of Y
+  int32_t* yh;      // pinned copy of Y
+  int8_t *xh, *wh;  // pinned staging of X and W
 };
 
 // Witness and evaluation vectors of every proof of a batch, one launch per
@@ -890,8 +896,10 @@ std::vector<Slot> enqueue_witness_batch(const ProveJob* jobs, size_t nj, ProveGe
     S.bev = ws.get(P_BEV, L.N * 32);
     S.cev = ws.get(P_CEV, L.N * 32);
     S.yh = reinterpret_cast<int32_t*>(y_host + yo[j]);
-    std::memcpy(xw_host + xo[j], jobs[j].X, (size_t)L.a * L.n);
-    std::memcpy(xw_host + wo[j], jobs[j].W, (size_t)L.n * L.b);
+    S.xh = xw_host + xo[j];
+    S.wh = xw_host + wo[j];
+    std::memcpy(S.xh, jobs[j].X, (size_t)L.a * L.n);
+    std::memcpy(S.wh, jobs[j].W, (size_t)L.n * L.b);
     WitJob& J = wj[j];
     J.kind = L.kind;
     J.a = L.a;
@@ -986,11 +994,15 @@ size_t host_threads() {
 ProveCtx::ProveCtx() {
   device = current_device();
   for (int lane = 0; lane < LANES; lane++) ZK_HIP(hipStreamCreateWithFlags(&lanes[lane], hipStreamNonBlocking));
+  ZK_HIP(hipStreamCreateWithFlags(&graph_stream, hipStreamNonBlocking));
   for (ProveGen& g : gen) {
     ZK_HIP(hipEventCreateWithFlags(&g.witness_ev, hipEventDisableTiming));
     ZK_HIP(hipEventCreateWithFlags(&g.quotient_ev, hipEventDisableTiming));
+    ZK_HIP(hipEventCreateWithFlags(&g.fork_ev, hipEventDisableTiming));
+    ZK_HIP(hipEventCreateWithFlags(&g.graph_ev, hipEventDisableTiming));
     for (int lane = 0; lane < LANES; lane++) {
       ZK_HIP(hipEventCreateWithFlags(&g.done_ev[lane], hipEventDisableTiming));
+      ZK_HIP(hipEventCreateWithFlags(&g.join_ev[lane], hipEventDisableTiming));
       ZK_HIP(hipEventCreate(&g.lane_t[lane]));
     }
     for (auto& e : g.ev) ZK_HIP(hipEventCreate(&e));
@@ -1005,11 +1017,20 @@ ProveCtx::~ProveCtx() {
       (void)hipStreamDestroy(lanes[lane]);
     }
   }
+  if (graph_stream) {
+    (void)hipStreamSynchronize(graph_stream);
+    (void)hipStreamDestroy(graph_stream);
+  }
   for (ProveGen& g : gen) {
+    if (g.graph) (void)hipGraphExecDestroy(g.graph);
+    release_graph_slots(g.graph_prof);
+    if (g.fork_ev) (void)hipEventDestroy(g.fork_ev);
+    if (g.graph_ev) (void)hipEventDestroy(g.graph_ev);
     if (g.witness_ev) (void)hipEventSynchronize(g.witness_ev), (void)hipEventDestroy(g.witness_ev);
     if (g.quotient_ev) (void)hipEventSynchronize(g.quotient_ev), (void)hipEventDestroy(g.quotient_ev);
     for (int lane = 0; lane < LANES; lane++) {
       if (g.done_ev[lane]) (void)hipEventDestroy(g.done_ev[lane]);
+      if (g.join_ev[lane]) (void)hipEventDestroy(g.join_ev[lane]);
       if (g.lane_t[lane]) (void)hipEventDestroy(g.lane_t[lane]);
     }
     for (auto& e : g.ev)
@@ -1022,6 +1043,7 @@ struct BatchRun {
   ProveCtx* ctx = nullptr;
   int g = 0;
   bool finished = false;
+  bool graphed = false;  // launched as a graph (records of its profiling scopes come from the graph)
   std::vector<ProveJob> jobs;
   std::vector<Slot> slots;
   std::vector<MsmInput> in_g1, in_g2, in_h;
@@ -1033,27 +1055,143 @@ struct BatchRun {
 
 void BatchRunDeleter::operator()(BatchRun* r) const { delete r; }
 
+namespace {
+
+// off by default: replaying a captured graph measured slower here than the
+// eager multi-stream launches (the runtime dispatches a graph's nodes one by
+// one in capture order, so the later lanes start later)
+std::atomic<int> g_graphs{0};
+
+// Stage and lane-end events: under capture they become event record nodes of
+// the graph that each replay records (the host waits on them and times with them).
+void record_ext(hipEvent_t e, hipStream_t st, bool capture) {
+  if (capture)
+    record_event(e, st);
+  else
+    ZK_HIP(hipEventRecord(e, st));
+}
+
+// Enqueues every device operation of a begun batch (eager, or under capture).
+void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool capture);
+
+}  // namespace
+
+int set_graphs(int enable) { return g_graphs.exchange(enable ? 1 : 0); }
+
 BatchRunPtr prove_batch_begin(ProveCtx& ctx, int g, const ProveJob* jobs_in, size_t nj, hipStream_t st) {
   ZK_REQUIRE(nj >= 1, "empty proof batch");
   ZK_REQUIRE(g >= 0 && g < ProveCtx::GENS, "bad context generation");
   ZK_REQUIRE(current_device() == ctx.device, "proof context of another device");
   for (size_t j = 0; j < nj; j++)
     ZK_REQUIRE(jobs_in[j].pk && jobs_in[j].pk->device == ctx.device, "a proving key lives on another device");
+  ProveGen& G = ctx.gen[g];
+  std::vector<uint64_t> key;
+  key.reserve(nj + 2);
+  key.push_back((uint64_t)(uintptr_t)st);
+  key.push_back(tuning_fingerprint());
+  key.push_back(profiling_enabled() ? 1 : 0);
+  for (size_t j = 0; j < nj; j++) key.push_back(jobs_in[j].pk->id);
+  const bool graphs = ctx.graphs && g_graphs.load();
+  // graphs run on the context's own stream, after everything queued on the
+  // calling stream (which may be the null stream, which cannot be captured)
+  hipStream_t gs = ctx.graph_stream;
+  auto fork = [&] {
+    ZK_HIP(hipEventRecord(G.fork_ev, st));
+    ZK_HIP(hipStreamWaitEvent(gs, G.fork_ev, 0));
+  };
+  auto join = [&] {
+    ZK_HIP(hipEventRecord(G.graph_ev, gs));
+    ZK_HIP(hipStreamWaitEvent(st, G.graph_ev, 0));
+  };
+  if (graphs && G.graph && G.graph_key == key) {
+    // replay: the same buffers, tables and launches; only X and W change
+    BatchRunPtr run(new BatchRun(*G.graph_run));
+    BatchRun& R = *run;
+    R.jobs.assign(jobs_in, jobs_in + nj);
+    R.host_t0 = std::chrono::steady_clock::now();
+    R.graphed = true;
+    for (size_t j = 0; j < nj; j++) {
+      const Layout& L = jobs_in[j].pk->L;
+      std::memcpy(R.slots[j].xh, jobs_in[j].X, (size_t)L.a * L.n);
+      std::memcpy(R.slots[j].wh, jobs_in[j].W, (size_t)L.n * L.b);
+    }
+    fork();
+    ZK_HIP(hipGraphLaunch(G.graph, gs));
+    join();
+    return run;
+  }
+  // a new composition rewrites the generation's tables: the graph is stale
+  const bool capture = graphs && G.seen_key == key;
+  if (G.graph) {
+    ZK_HIP(hipGraphExecDestroy(G.graph));
+    G.graph = nullptr;
+    G.graph_key.clear();
+    G.graph_run.reset();
+    release_graph_slots(G.graph_prof);
+  }
+  G.seen_key = key;
   BatchRunPtr run(new BatchRun());
   BatchRun& R = *run;
   R.ctx = &ctx;
   R.g = g;
   R.jobs.assign(jobs_in, jobs_in + nj);
   R.host_t0 = std::chrono::steady_clock::now();
-  const ProveJob* jobs = R.jobs.data();
-  ProveGen& G = ctx.gen[g];
   while (G.slot_ws.size() < nj) G.slot_ws.emplace_back(new Workspace());
-  ZK_HIP(hipEventRecord(G.ev[0], st));
+  if (!capture) {
+    enqueue_batch(ctx, G, R, st, false);
+    return run;
+  }
+  // the composition ran just before on this generation, so every buffer
+  // already has its size: the capture allocates nothing
+  fork();
+  ZK_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeRelaxed));
+  hipGraph_t graph = nullptr;
+  std::vector<int> prof;
+  set_capture_sink(&prof);
+  try {
+    enqueue_batch(ctx, G, R, gs, true);
+    for (int lane = 0; lane < ProveCtx::LANES; lane++) {
+      ZK_HIP(hipEventRecord(G.join_ev[lane], ctx.lanes[lane]));
+      ZK_HIP(hipStreamWaitEvent(gs, G.join_ev[lane], 0));
+    }
+  } catch (...) {
+    set_capture_sink(nullptr);
+    release_graph_slots(prof);
+    if (hipStreamEndCapture(gs, &graph) == hipSuccess && graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    throw;
+  }
+  set_capture_sink(nullptr);
+  const hipError_t ec = hipStreamEndCapture(gs, &graph);
+  if (ec != hipSuccess) release_graph_slots(prof);
+  ZK_HIP(ec);
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) release_graph_slots(prof);
+  ZK_HIP(e);
+  G.graph = exec;
+  G.graph_key = key;
+  G.graph_prof = std::move(prof);
+  R.graphed = true;
+  G.graph_run.reset(new BatchRun(R));
+  G.graph_run->jobs.clear();
+  ZK_HIP(hipGraphLaunch(exec, gs));
+  join();
+  return run;
+}
+
+namespace {
+
+void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool capture) {
+  const ProveJob* jobs = R.jobs.data();
+  const size_t nj = R.jobs.size();
+  record_ext(G.ev[0], st, capture);
 
   // ---- witnesses and evaluation vectors
   R.slots = enqueue_witness_batch(jobs, nj, G, st);
   std::vector<Slot>& slots = R.slots;
-  ZK_HIP(hipEventRecord(G.ev[1], st));
+  record_ext(G.ev[1], st, capture);
   ZK_HIP(hipEventRecord(G.witness_ev, st));
   // ---- MSM jobs of every proof, by lane.  Those that need only the
   // assignment run from the end of the witness on, overlapping the quotient:
@@ -1085,8 +1223,8 @@ BatchRunPtr prove_batch_begin(ProveCtx& ctx, int g, const ProveJob* jobs_in, siz
               lane_g2 = ctx.lanes[ProveCtx::LANE_G2];
   ZK_HIP(hipStreamWaitEvent(lane_g2, G.witness_ev, 0));
   msm_enqueue_batch_g2(in_g2.data(), (int)in_g2.size(), G.lane_ws[ProveCtx::LANE_G2], lane_g2, R.pend_g2.data());
-  ZK_HIP(hipEventRecord(G.done_ev[ProveCtx::LANE_G2], lane_g2));
-  ZK_HIP(hipEventRecord(G.lane_t[ProveCtx::LANE_G2], lane_g2));
+  record_ext(G.done_ev[ProveCtx::LANE_G2], lane_g2, capture);
+  record_ext(G.lane_t[ProveCtx::LANE_G2], lane_g2, capture);
 
   // ---- QAP quotients: iNTT (DIF, natural -> bit-reversed coefficients),
   // coset NTT (DIT, bit-reversed -> natural evaluations on g H), pointwise
@@ -1140,20 +1278,21 @@ BatchRunPtr prove_batch_begin(ProveCtx& ctx, int g, const ProveJob* jobs_in, siz
   }
   ZK_HIP(hipMemcpyAsync(flag_host, flag, 4, hipMemcpyDeviceToHost, st));
   R.flag_host = flag_host;
-  ZK_HIP(hipEventRecord(G.ev[2], st));
+  record_ext(G.ev[2], st, capture);
   ZK_HIP(hipEventRecord(G.quotient_ev, st));
 
   // ---- the H lane after the quotients, then the G1 lane
   ZK_HIP(hipStreamWaitEvent(lane_h, G.quotient_ev, 0));
   msm_enqueue_batch_g1(in_h.data(), (int)in_h.size(), G.lane_ws[ProveCtx::LANE_H], lane_h, R.pend_h.data());
-  ZK_HIP(hipEventRecord(G.done_ev[ProveCtx::LANE_H], lane_h));
-  ZK_HIP(hipEventRecord(G.lane_t[ProveCtx::LANE_H], lane_h));
+  record_ext(G.done_ev[ProveCtx::LANE_H], lane_h, capture);
+  record_ext(G.lane_t[ProveCtx::LANE_H], lane_h, capture);
   ZK_HIP(hipStreamWaitEvent(lane_g1, G.witness_ev, 0));
   msm_enqueue_batch_g1(in_g1.data(), (int)in_g1.size(), G.lane_ws[ProveCtx::LANE_G1], lane_g1, R.pend_g1.data());
-  ZK_HIP(hipEventRecord(G.done_ev[ProveCtx::LANE_G1], lane_g1));
-  ZK_HIP(hipEventRecord(G.lane_t[ProveCtx::LANE_G1], lane_g1));
-  return run;
+  record_ext(G.done_ev[ProveCtx::LANE_G1], lane_g1, capture);
+  record_ext(G.lane_t[ProveCtx::LANE_G1], lane_g1, capture);
 }
+
+}  // namespace
 
 
 void prove_batch_finish(ProveCtx& ctx, BatchRun& R) {
@@ -1219,7 +1358,7 @@ void prove_batch_finish(ProveCtx& ctx, BatchRun& R) {
     ZK_HIP(hipEventSynchronize(G.done_ev[ProveCtx::LANE_H]));
     parallel_for(own_h.size(), nthr / 2 + 1, [&](size_t q) { Hp[own_h[q]] = msm_finish_g1(pend_h[q]); });
   });
-  ZK_HIP(hipEventSynchronize(G.quotient_ev));
+  ZK_HIP(hipEventSynchronize(G.ev[2]));  // quotients and the tail flag
   if (*R.flag_host) throw Error(ZKVC_EDEVICE, "internal error: a witness does not satisfy its circuit");
   for (int lane = 0; lane < ProveCtx::LANES; lane++) ZK_HIP(hipEventSynchronize(G.done_ev[lane]));
   const auto asm_t0 = std::chrono::steady_clock::now();
@@ -1248,13 +1387,14 @@ void prove_batch_finish(ProveCtx& ctx, BatchRun& R) {
   ctx.last.msm_ms = msm;
   ctx.last.host_ms = std::chrono::duration<float, std::milli>(host_t1 - asm_t0).count();
   ctx.last.total_ms = std::chrono::duration<float, std::milli>(host_t1 - R.host_t0).count();
+  if (R.graphed) collect_graph_slots(G.graph_prof);
 }
 
 void prove_batch_abandon(BatchRunPtr& run) {
   if (!run) return;
   if (!run->finished) {
     ProveGen& G = run->ctx->gen[run->g];
-    (void)hipEventSynchronize(G.quotient_ev);
+    (void)hipEventSynchronize(G.ev[2]);
     for (int lane = 0; lane < ProveCtx::LANES; lane++) (void)hipEventSynchronize(G.done_ev[lane]);
   }
   run.reset();

@@ -51,6 +51,13 @@ bool kind_uses_z(uint32_t kind);
 
 namespace zkvc {
 
+// Host bookkeeping of a begun batch (defined with the prover).
+struct BatchRun;
+struct BatchRunDeleter {
+  void operator()(BatchRun* r) const;
+};
+using BatchRunPtr = std::unique_ptr<BatchRun, BatchRunDeleter>;
+
 // The resources of one batch in flight: events, one workspace per MSM lane,
 // batch-level tables, and one workspace per proof (witness, evaluation
 // vectors, quotient, pinned staging).
@@ -60,9 +67,22 @@ struct ProveGen {
   hipEvent_t done_ev[3] = {};        // each lane's batch complete
   hipEvent_t lane_t[3] = {};         // the same, with timing
   hipEvent_t ev[3] = {};             // stage timing on the calling stream
+  hipEvent_t join_ev[3] = {};        // each lane's end, joined into the graph stream (capture)
+  hipEvent_t fork_ev = nullptr;      // calling stream -> graph stream
+  hipEvent_t graph_ev = nullptr;     // graph stream -> calling stream
   Workspace lane_ws[3];
   Workspace shared;
   std::vector<std::unique_ptr<Workspace>> slot_ws;
+  // Graph replay: a batch with the same composition as the previous one on
+  // this generation (the same keys in the same order, the same stream and
+  // tuning) is captured into a HIP graph; later batches of that composition
+  // replay it after restaging their inputs.  Every buffer the graph touches
+  // belongs to this generation and keeps its address between batches.
+  std::vector<uint64_t> seen_key;    // composition of the last batch begun here
+  std::vector<uint64_t> graph_key;   // composition of the captured graph
+  hipGraphExec_t graph = nullptr;
+  BatchRunPtr graph_run;             // bookkeeping of the captured batch
+  std::vector<int> graph_prof;       // profiling slots recorded by the graph
 };
 
 // Device and host state for proving: the three MSM lanes (streams) and two
@@ -80,7 +100,9 @@ struct ProveCtx {
   ProveCtx(const ProveCtx&) = delete;
   ProveCtx& operator=(const ProveCtx&) = delete;
   int device = 0;
+  bool graphs = true;  // capture and replay repeated compositions
   hipStream_t lanes[LANES] = {};
+  hipStream_t graph_stream = nullptr;  // captures and replays run here, ordered after the calling stream
   ProveGen gen[GENS];
   zkvc_prove_stats last{};
 };
@@ -90,6 +112,7 @@ struct ProveCtx {
 // The opaque proving key of the C ABI.
 struct zkvc_pk {
   ~zkvc_pk();
+  uint64_t id = 0;  // unique per key of the process (never reused)
   zkvc::Layout L;
   int device = 0;
   bool has_z = false;
@@ -134,15 +157,14 @@ void groth16_prove_batch(ProveCtx& ctx, const ProveJob* jobs, size_t njobs, hipS
 // generation g of the context (no host wait); finish waits for it, combines
 // and assembles on the host, and writes the outputs.  A generation must be
 // finished before it is begun again; the other one may be in flight.
-struct BatchRun;
-struct BatchRunDeleter {
-  void operator()(BatchRun* r) const;
-};
-using BatchRunPtr = std::unique_ptr<BatchRun, BatchRunDeleter>;
 BatchRunPtr prove_batch_begin(ProveCtx& ctx, int g, const ProveJob* jobs, size_t njobs, hipStream_t st);
 void prove_batch_finish(ProveCtx& ctx, BatchRun& run);
 // Releases a run; one begun but not finished first waits for its device work.
 void prove_batch_abandon(BatchRunPtr& run);
+
+// Process-wide switch for graph capture and replay (off by default); returns
+// the previous setting.
+int set_graphs(int enable);
 
 // Proves Y = X W (a batch of one on the key's own context).
 void groth16_prove(zkvc_pk* pk, const int8_t* X, const int8_t* W, const host::HFr& r, const host::HFr& s,

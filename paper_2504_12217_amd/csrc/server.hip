@@ -92,6 +92,9 @@ void zkvc_server::run() {
     ZK_HIP(hipSetDevice(device));
     ZK_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     ctx.reset(new ProveCtx());
+    // batches differ from one to the next and two are in flight at once:
+    // eager launches keep the generations overlapping on the device
+    ctx->graphs = false;
   } catch (const std::exception& e) {
     std::lock_guard<std::mutex> lock(mu);
     fatal = e.what();

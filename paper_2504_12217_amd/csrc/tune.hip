@@ -25,6 +25,20 @@ Tuning& tuning() {
   return t;
 }
 
+uint64_t tuning_fingerprint() {
+  const Tuning& t = tuning();
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over every entry
+  auto mix = [&](int v) {
+    h ^= (uint64_t)(uint32_t)v;
+    h *= 1099511628211ull;
+  };
+  for (auto& row : t.msm_c)
+    for (auto& v : row) mix(v.load());
+  for (auto& v : t.msm_kdiv_log) mix(v.load());
+  for (auto& v : t.ntt_kmax) mix(v.load());
+  return h;
+}
+
 namespace {
 
 std::mutex g_tune_mu;  // one tuning run or import at a time

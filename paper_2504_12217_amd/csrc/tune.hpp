@@ -18,6 +18,8 @@ struct Tuning {
 };
 
 Tuning& tuning();
+// A hash of every entry: changes whenever the table does.
+uint64_t tuning_fingerprint();
 
 inline int ceil_log2(uint64_t v) {
   int l = 0;

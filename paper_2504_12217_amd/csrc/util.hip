@@ -75,6 +75,21 @@ int current_device() {
   return d;
 }
 
+hipError_t record_event_nothrow(hipEvent_t e, hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  unsigned long long id = 0;
+  hipGraph_t graph = nullptr;
+  const hipGraphNode_t* deps = nullptr;
+  size_t ndeps = 0;
+  hipError_t r = hipStreamGetCaptureInfo_v2(st, &cs, &id, &graph, &deps, &ndeps);
+  if (r != hipSuccess) return r;
+  if (cs != hipStreamCaptureStatusActive) return hipEventRecord(e, st);
+  hipGraphNode_t node = nullptr;
+  r = hipGraphAddEventRecordNode(&node, graph, deps, ndeps, e);
+  if (r != hipSuccess) return r;
+  return hipStreamUpdateCaptureDependencies(st, &node, 1, hipStreamSetCaptureDependencies);
+}
+
 StreamWorkspace& stream_workspace(hipStream_t st) {
   static std::mutex mu;
   static std::map<std::pair<int, hipStream_t>, StreamWorkspace*> m;

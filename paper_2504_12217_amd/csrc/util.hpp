@@ -116,6 +116,12 @@ StreamWorkspace& stream_workspace(hipStream_t st);
 
 int current_device();
 
+// Records event e on stream st.  While st is capturing a graph, an event
+// record node is added after the stream's captured work instead, so that
+// every replay of the graph records e at that point.
+hipError_t record_event_nothrow(hipEvent_t e, hipStream_t st);
+inline void record_event(hipEvent_t e, hipStream_t st) { ZK_HIP(record_event_nothrow(e, st)); }
+
 inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
 
 // Fill a u32 device array with a value (a kernel, so it is safe inside captured graphs).

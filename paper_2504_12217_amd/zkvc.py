@@ -101,6 +101,7 @@ _SIGS = {
     "zkvc_autotune": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _VP]),
     "zkvc_tune_export": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_size_t)]),
     "zkvc_tune_import": (ctypes.c_int, [ctypes.c_char_p]),
+    "zkvc_set_graphs": (ctypes.c_int, [ctypes.c_int]),
     "zkvc_verify": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, _VP, _VP, ctypes.POINTER(Proof)]),
     "zkvc_ntt_fr": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint32, _VP]),
     "zkvc_msm_g1": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, ctypes.c_uint32, ctypes.POINTER(G1), _VP]),
@@ -236,6 +237,12 @@ def tune_export():
 
 def tune_import(text):
     _check(lib().zkvc_tune_import(text.encode()))
+
+
+def set_graphs(enable):
+    """Turn graph capture and replay of repeated proof compositions on or off
+    (off by default); returns the previous setting."""
+    return lib().zkvc_set_graphs(1 if enable else 0)
 
 
 def profile_begin():
