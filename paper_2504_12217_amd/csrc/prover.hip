@@ -1196,9 +1196,7 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
   // ---- MSM jobs of every proof, by lane.  Those that need only the
   // assignment run from the end of the witness on, overlapping the quotient:
   // one pipeline for all G1 queries A, B1, L and one for B2 in G2; the H MSMs
-  // follow the quotient on the third lane.  B2 (the longest chain of
-  // dependent group operations), then the quotient and H (the critical path)
-  // are enqueued first.
+  // follow the quotient on the third lane.
   std::vector<MsmInput> &in_g1 = R.in_g1, &in_g2 = R.in_g2, &in_h = R.in_h;
   std::vector<int> &own_g1 = R.own_g1, &query_g1 = R.query_g1, &own_g2 = R.own_g2, &own_h = R.own_h;
   for (size_t j = 0; j < nj; j++) {
@@ -1221,75 +1219,104 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
   R.pend_h.resize(in_h.size());
   hipStream_t lane_h = ctx.lanes[ProveCtx::LANE_H], lane_g1 = ctx.lanes[ProveCtx::LANE_G1],
               lane_g2 = ctx.lanes[ProveCtx::LANE_G2];
-  ZK_HIP(hipStreamWaitEvent(lane_g2, G.witness_ev, 0));
-  msm_enqueue_batch_g2(in_g2.data(), (int)in_g2.size(), G.lane_ws[ProveCtx::LANE_G2], lane_g2, R.pend_g2.data());
-  record_ext(G.done_ev[ProveCtx::LANE_G2], lane_g2, capture);
-  record_ext(G.lane_t[ProveCtx::LANE_G2], lane_g2, capture);
-
-  // ---- QAP quotients: iNTT (DIF, natural -> bit-reversed coefficients),
-  // coset NTT (DIT, bit-reversed -> natural evaluations on g H), pointwise
-  // (A B - C)/(g^N - 1), inverse coset NTT (DIF: h in bit-reversed order).
-  // Proofs of one domain size share every launch.
-  std::map<int, std::vector<size_t>> by_size;
-  for (size_t j = 0; j < nj; j++) by_size[jobs[j].pk->L.log_n].push_back(j);
-  uint32_t* flag = G.shared.get(C_FLAG, 4);
-  uint32_t* flag_host = G.shared.host<uint32_t>(C_FLAG, 4);
-  fill_u32(flag, 0u, 1, st);
-  // device tables for groups of several proofs: (A, B, C) triples, then the A's
-  std::vector<uint32_t*> tab_v;
-  std::vector<size_t> tab_off;
-  for (auto& kv : by_size) {
-    tab_off.push_back(tab_v.size());
-    if (kv.second.size() < 2) continue;
-    for (size_t j : kv.second) {
-      tab_v.push_back(slots[j].aev);
-      tab_v.push_back(slots[j].bev);
-      tab_v.push_back(slots[j].cev);
+  auto g2_lane = [&] {
+    ZK_HIP(hipStreamWaitEvent(lane_g2, G.witness_ev, 0));
+    msm_enqueue_batch_g2(in_g2.data(), (int)in_g2.size(), G.lane_ws[ProveCtx::LANE_G2], lane_g2, R.pend_g2.data());
+    record_ext(G.done_ev[ProveCtx::LANE_G2], lane_g2, capture);
+    record_ext(G.lane_t[ProveCtx::LANE_G2], lane_g2, capture);
+  };
+  auto g1_lane = [&] {
+    ZK_HIP(hipStreamWaitEvent(lane_g1, G.witness_ev, 0));
+    msm_enqueue_batch_g1(in_g1.data(), (int)in_g1.size(), G.lane_ws[ProveCtx::LANE_G1], lane_g1, R.pend_g1.data());
+    record_ext(G.done_ev[ProveCtx::LANE_G1], lane_g1, capture);
+    record_ext(G.lane_t[ProveCtx::LANE_G1], lane_g1, capture);
+  };
+  // Every launch costs host time, so one thread enqueueing the lanes one
+  // after the other delays the later ones: the G2 and G1 lanes are enqueued
+  // by helper threads while this thread enqueues the quotient and the H lane
+  // (the critical path).  Under capture everything is enqueued from here.
+  std::future<void> f_g2, f_g1;
+  if (capture) {
+    g2_lane();
+  } else {
+    f_g2 = std::async(std::launch::async, g2_lane);
+    f_g1 = std::async(std::launch::async, g1_lane);
+  }
+  auto join_helpers = [&] {
+    if (f_g2.valid()) f_g2.wait();
+    if (f_g1.valid()) f_g1.wait();
+  };
+  try {
+    // ---- QAP quotients: iNTT (DIF, natural -> bit-reversed coefficients),
+    // coset NTT (DIT, bit-reversed -> natural evaluations on g H), pointwise
+    // (A B - C)/(g^N - 1), inverse coset NTT (DIF: h in bit-reversed order).
+    // Proofs of one domain size share every launch.
+    std::map<int, std::vector<size_t>> by_size;
+    for (size_t j = 0; j < nj; j++) by_size[jobs[j].pk->L.log_n].push_back(j);
+    uint32_t* flag = G.shared.get(C_FLAG, 4);
+    uint32_t* flag_host = G.shared.host<uint32_t>(C_FLAG, 4);
+    fill_u32(flag, 0u, 1, st);
+    // device tables for groups of several proofs: (A, B, C) triples, then the A's
+    std::vector<uint32_t*> tab_v;
+    std::vector<size_t> tab_off;
+    for (auto& kv : by_size) {
+      tab_off.push_back(tab_v.size());
+      if (kv.second.size() < 2) continue;
+      for (size_t j : kv.second) {
+        tab_v.push_back(slots[j].aev);
+        tab_v.push_back(slots[j].bev);
+        tab_v.push_back(slots[j].cev);
+      }
+      for (size_t j : kv.second) tab_v.push_back(slots[j].aev);
     }
-    for (size_t j : kv.second) tab_v.push_back(slots[j].aev);
-  }
-  uint32_t** tab_dev = nullptr;
-  if (!tab_v.empty()) {
-    const size_t bytes = tab_v.size() * sizeof(uint32_t*);
-    uint32_t** tab_host = G.shared.host<uint32_t*>(C_TABLE, bytes);
-    tab_dev = G.shared.get<uint32_t*>(C_TABLE, bytes);
-    std::memcpy(tab_host, tab_v.data(), bytes);
-    ZK_HIP(hipMemcpyAsync(tab_dev, tab_host, bytes, hipMemcpyHostToDevice, st));
-  }
-  size_t gi = 0;
-  for (auto& kv : by_size) {
-    const int Lg = kv.first;
-    const uint64_t N = 1ull << Lg;
-    const size_t k = kv.second.size();
-    if (k == 1) {
-      const Slot& S = slots[kv.second[0]];
-      uint32_t* const vecs[3] = {S.aev, S.bev, S.cev};
-      qap_quotient_launch(vecs, nullptr, 1, Lg, st);
-      hipLaunchKernelGGL(k_check_top, dim3(1), dim3(64), 0, st, (uint32_t* const*)nullptr, S.aev, 1u, N, flag);
-      ZK_HIP(hipGetLastError());
-    } else {
-      uint32_t** tg = tab_dev + tab_off[gi];
-      qap_quotient_launch(nullptr, tg, (int)k, Lg, st);
-      hipLaunchKernelGGL(k_check_top, dim3(cdiv(k, 64)), dim3(64), 0, st, tg + 3 * k, (const uint32_t*)nullptr,
-                         (uint32_t)k, N, flag);
-      ZK_HIP(hipGetLastError());
+    uint32_t** tab_dev = nullptr;
+    if (!tab_v.empty()) {
+      const size_t bytes = tab_v.size() * sizeof(uint32_t*);
+      uint32_t** tab_host = G.shared.host<uint32_t*>(C_TABLE, bytes);
+      tab_dev = G.shared.get<uint32_t*>(C_TABLE, bytes);
+      std::memcpy(tab_host, tab_v.data(), bytes);
+      ZK_HIP(hipMemcpyAsync(tab_dev, tab_host, bytes, hipMemcpyHostToDevice, st));
     }
-    gi++;
-  }
-  ZK_HIP(hipMemcpyAsync(flag_host, flag, 4, hipMemcpyDeviceToHost, st));
-  R.flag_host = flag_host;
-  record_ext(G.ev[2], st, capture);
-  ZK_HIP(hipEventRecord(G.quotient_ev, st));
+    size_t gi = 0;
+    for (auto& kv : by_size) {
+      const int Lg = kv.first;
+      const uint64_t N = 1ull << Lg;
+      const size_t k = kv.second.size();
+      if (k == 1) {
+        const Slot& S = slots[kv.second[0]];
+        uint32_t* const vecs[3] = {S.aev, S.bev, S.cev};
+        qap_quotient_launch(vecs, nullptr, 1, Lg, st);
+        hipLaunchKernelGGL(k_check_top, dim3(1), dim3(64), 0, st, (uint32_t* const*)nullptr, S.aev, 1u, N, flag);
+        ZK_HIP(hipGetLastError());
+      } else {
+        uint32_t** tg = tab_dev + tab_off[gi];
+        qap_quotient_launch(nullptr, tg, (int)k, Lg, st);
+        hipLaunchKernelGGL(k_check_top, dim3(cdiv(k, 64)), dim3(64), 0, st, tg + 3 * k, (const uint32_t*)nullptr,
+                           (uint32_t)k, N, flag);
+        ZK_HIP(hipGetLastError());
+      }
+      gi++;
+    }
+    ZK_HIP(hipMemcpyAsync(flag_host, flag, 4, hipMemcpyDeviceToHost, st));
+    R.flag_host = flag_host;
+    record_ext(G.ev[2], st, capture);
+    ZK_HIP(hipEventRecord(G.quotient_ev, st));
 
-  // ---- the H lane after the quotients, then the G1 lane
-  ZK_HIP(hipStreamWaitEvent(lane_h, G.quotient_ev, 0));
-  msm_enqueue_batch_g1(in_h.data(), (int)in_h.size(), G.lane_ws[ProveCtx::LANE_H], lane_h, R.pend_h.data());
-  record_ext(G.done_ev[ProveCtx::LANE_H], lane_h, capture);
-  record_ext(G.lane_t[ProveCtx::LANE_H], lane_h, capture);
-  ZK_HIP(hipStreamWaitEvent(lane_g1, G.witness_ev, 0));
-  msm_enqueue_batch_g1(in_g1.data(), (int)in_g1.size(), G.lane_ws[ProveCtx::LANE_G1], lane_g1, R.pend_g1.data());
-  record_ext(G.done_ev[ProveCtx::LANE_G1], lane_g1, capture);
-  record_ext(G.lane_t[ProveCtx::LANE_G1], lane_g1, capture);
+    // ---- the H lane after the quotients
+    ZK_HIP(hipStreamWaitEvent(lane_h, G.quotient_ev, 0));
+    msm_enqueue_batch_g1(in_h.data(), (int)in_h.size(), G.lane_ws[ProveCtx::LANE_H], lane_h, R.pend_h.data());
+    record_ext(G.done_ev[ProveCtx::LANE_H], lane_h, capture);
+    record_ext(G.lane_t[ProveCtx::LANE_H], lane_h, capture);
+  } catch (...) {
+    join_helpers();
+    throw;
+  }
+  if (capture) {
+    g1_lane();
+  } else {
+    f_g2.get();
+    f_g1.get();
+  }
 }
 
 }  // namespace
