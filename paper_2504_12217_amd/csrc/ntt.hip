@@ -18,6 +18,7 @@
 // consecutive addresses) in LDS as 29-bit limbs, 36 bytes each.
 #include "ntt.hpp"
 
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -443,6 +444,30 @@ PassPlan plan_passes(int L, int min_pass, int max_k) {
   return pl;
 }
 
+// The passes of the quotient chain: a top pass of at most 2^7 points, so that
+// the fused top kernel holds three regions of 2^9 elements in LDS and still
+// reads runs of at least four consecutive elements (128 bytes) per group, and
+// the other bits split evenly over passes of at most 2^10 points.
+PassPlan plan_quotient(int L) {
+  PassPlan pl = plan_passes(L, 1, NTT_MAX_K);  // the tuned or default tile size
+  const int ktop = std::min(TOP_MAX_K - 2, L / 2);
+  const int rest = L - ktop;
+  const int nrest = (rest + NTT_MAX_K - 1) / NTT_MAX_K;
+  pl.npass = 1 + nrest;
+  pl.k[0] = ktop;
+  pl.log_m[0] = L;
+  int lm = L - ktop;
+  for (int j = 1; j < pl.npass; j++) {
+    pl.k[j] = rest / nrest + (j - 1 < rest % nrest ? 1 : 0);
+    pl.log_m[j] = lm;
+    lm -= pl.k[j];
+  }
+  // every pass has at least one group per block, the top pass four
+  for (int j = 0; j < pl.npass; j++) pl.kmax = std::max(pl.kmax, pl.k[j]);
+  pl.kmax = std::min(NTT_MAX_K, std::max(pl.kmax, ktop + 2));
+  return pl;
+}
+
 // One pass of a transform over nvec vectors (direct pointers or a device table).
 void launch_pass(uint32_t* const* data, uint32_t* const* dev_table, int nvec, const PassPlan& pl, int j, bool dit,
                  bool inverse, bool first, bool last, const NttFuse& fuse, const NttTables& T, hipStream_t st) {
@@ -513,7 +538,7 @@ void qap_quotient_launch(uint32_t* const* abc, uint32_t* const* dev_table, int n
   const int L = log_n;
   // at least two passes (the fused kernels need distinct top and bottom bit
   // ranges); the top pass keeps three 2^k-element regions in 64 KiB of LDS
-  const PassPlan pl = plan_passes(L, 2, TOP_MAX_K);
+  const PassPlan pl = plan_quotient(L);
   const int P = pl.npass;
   const int nvec = 3 * nproofs;
   uint32_t* const* a_tab = dev_table ? dev_table + nvec : nullptr;
