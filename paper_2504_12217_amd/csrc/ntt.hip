@@ -20,7 +20,9 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "field.hpp"
@@ -43,6 +45,7 @@ struct PassParams {
   uint32_t* const* table;         // ... or, if set, a device table of vectors
   int log_n, log_m, k, log_g;
   int dit, inverse, twiddle;
+  const uint32_t* tw;             // this pass's twiddles, entry (t << B) | g, or null: power tables
   int first, last;
   int pre_mont, pre_coset, pre_bitrev;
   int post_canon, post_coset, post_bitrev;
@@ -155,7 +158,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_pass(PassParams p, NttTable
     }
     if (p.dit && p.twiddle) {
       const uint32_t ex = g * bitrev_bits(t, k);
-      if (ex) x = Fr::mul(x, pow_lookup(T.w[p.inverse], ex << tw_shift));
+      if (ex) x = Fr::mul(x, p.tw ? Fr::load(p.tw + 8u * ((t << B) | g)) : pow_lookup(T.w[p.inverse], ex << tw_shift));
     }
     lds_put(lds, gl * K + t, x);
   }
@@ -180,7 +183,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_pass(PassParams p, NttTable
     Fr x = lds_get(lds, gl * K + t);
     if (!p.dit && p.twiddle) {
       const uint32_t ex = g * bitrev_bits(t, k);
-      if (ex) x = Fr::mul(x, pow_lookup(T.w[p.inverse], ex << tw_shift));
+      if (ex) x = Fr::mul(x, p.tw ? Fr::load(p.tw + 8u * ((t << B) | g)) : pow_lookup(T.w[p.inverse], ex << tw_shift));
     }
     if (p.last) {
       if (p.post_coset) {
@@ -206,6 +209,7 @@ struct FusedParams {
   int log_n, k, log_g;
   const uint32_t* ninv;       // N^-1 (bottom: with the coset scaling)
   const uint32_t* zinv;       // (g^N - 1)^-1 (top: the pointwise quotient)
+  const uint32_t* tw[2];      // top: the pass's forward / inverse twiddle tables, or null
 };
 
 // Bottom fusion, one vector per blockIdx.y (A, B, C of each proof in turn).
@@ -256,7 +260,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fused_top(FusedParams p, Nt
     const uint32_t addr = pass_addr(el, k, p.log_g, B, L, gamma0, &gl, &t, &g);
     Fr x = Fr::load(vec[v] + 8ull * addr);
     const uint32_t ex = g * bitrev_bits(t, k);  // forward DIT twiddle first
-    if (ex) x = Fr::mul(x, pow_lookup(T.w[0], ex << tw_shift));
+    if (ex) x = Fr::mul(x, p.tw[0] ? Fr::load(p.tw[0] + 8u * ((t << B) | g)) : pow_lookup(T.w[0], ex << tw_shift));
     lds_put(lds, v * E + gl * K + t, x);
   }
   __syncthreads();
@@ -272,9 +276,20 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fused_top(FusedParams p, Nt
     const uint32_t addr = pass_addr(e, k, p.log_g, B, L, gamma0, &gl, &t, &g);
     Fr x = lds_get(lds, gl * K + t);
     const uint32_t ex = g * bitrev_bits(t, k);  // inverse DIF twiddle last
-    if (ex) x = Fr::mul(x, pow_lookup(T.w[1], ex << tw_shift));
+    if (ex) x = Fr::mul(x, p.tw[1] ? Fr::load(p.tw[1] + 8u * ((t << B) | g)) : pow_lookup(T.w[1], ex << tw_shift));
     x.store(vec[0] + 8ull * addr);
   }
+}
+
+// Twiddles of one pass: entry (t << B) | g = omega_M^(g bitrev_k(t)) (M = 2^(B+k),
+// omega of the direction), read in the same order as the pass reads its data.
+__global__ void k_twiddle_table(uint32_t* out, int log_m, int k, int dir, NttTables T) {
+  const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >> log_m) return;
+  const int B = log_m - k;
+  const uint32_t t = idx >> B, g = idx & ((1u << B) - 1u);
+  const uint32_t ex = g * bitrev_bits(t, k);
+  pow_lookup(T.w[dir], ex << (MAX_LOG - log_m)).store(out + 8ull * idx);
 }
 
 __global__ void k_bitrev(uint32_t* data, int log_n, uint32_t n) {
@@ -412,6 +427,39 @@ const NttTables& ntt_tables(int device) {
 
 namespace {
 
+// Per-pass twiddle tables (32 B per entry, M entries), built on first use for
+// passes of M <= 2^TW_TABLE_MAX_LOG points and kept for the process: one
+// multiplication per twiddled element instead of a power-table product.
+constexpr int TW_TABLE_MAX_LOG = 24;
+
+const uint32_t* twiddle_table(int dir, int log_m, int k, const NttTables& T, hipStream_t st) {
+  if (log_m > TW_TABLE_MAX_LOG || log_m <= k) return nullptr;
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int, int>, DevBuf*> cache;
+  const int dev = current_device();
+  std::lock_guard<std::mutex> lock(mu);
+  const auto key = std::make_tuple(dev, dir, log_m, k);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second->get();
+  // not while the stream is being captured into a graph (the build waits)
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  ZK_HIP(hipStreamIsCapturing(st, &cs));
+  if (cs != hipStreamCaptureStatusNone) return nullptr;
+  auto* buf = new DevBuf();
+  try {
+    buf->alloc((size_t)32 << log_m);
+  } catch (const Error&) {
+    delete buf;
+    return nullptr;  // no room: the power tables serve instead
+  }
+  hipLaunchKernelGGL(k_twiddle_table, dim3(cdiv(1ull << log_m, 256)), dim3(256), 0, st, buf->get(), log_m, k, dir, T);
+  ZK_HIP(hipGetLastError());
+  // complete before any other stream can find it in the cache
+  ZK_HIP(hipStreamSynchronize(st));
+  cache[key] = buf;
+  return buf->get();
+}
+
 // The passes of one transform: pass j covers bits [log_m[j] - k[j], log_m[j])
 // of the address (DIF order: the top bit range first).
 struct PassPlan {
@@ -484,6 +532,7 @@ void launch_pass(uint32_t* const* data, uint32_t* const* dev_table, int nvec, co
   p.dit = dit;
   p.inverse = inverse ? 1 : 0;
   p.twiddle = pl.log_m[j] > k;
+  p.tw = p.twiddle ? twiddle_table(p.inverse, pl.log_m[j], k, T, st) : nullptr;
   p.first = first;
   p.last = last;
   p.pre_mont = fuse.in_canonical;
@@ -575,6 +624,8 @@ void qap_quotient_launch(uint32_t* const* abc, uint32_t* const* dev_table, int n
   {
     // top: forward DIT pass, pointwise quotient, inverse DIF pass
     fp.k = pl.k[0];
+    fp.tw[0] = twiddle_table(0, L, fp.k, T, st);
+    fp.tw[1] = twiddle_table(1, L, fp.k, T, st);
     const int a = TOP_MAX_K - fp.k, b = pl.log_g(0);
     fp.log_g = a < b ? a : b;
     const uint32_t E = 1u << (fp.k + fp.log_g);

@@ -126,6 +126,13 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2504_12217_amd.build`")
+        try:
+            # torch brings its own HIP runtime; loading it first makes the
+            # library bind to that same runtime, so that torch's device
+            # pointers and streams are valid here whatever the import order
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         _lib = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(_lib, name)
