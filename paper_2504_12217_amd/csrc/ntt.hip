@@ -51,6 +51,7 @@ struct PassParams {
   int post_canon, post_coset, post_bitrev;
   const uint32_t* pre_const;
   const uint32_t* post_const;
+  const uint32_t* post_table;     // if set: the last pass's only output factor, entry = address
 };
 
 __device__ __forceinline__ void lds_put(uint32_t* lds, uint32_t slot, const Fr& x) {
@@ -185,7 +186,10 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_pass(PassParams p, NttTable
       const uint32_t ex = g * bitrev_bits(t, k);
       if (ex) x = Fr::mul(x, p.tw ? Fr::load(p.tw + 8u * ((t << B) | g)) : pow_lookup(T.w[p.inverse], ex << tw_shift));
     }
-    if (p.last) {
+    if (p.last && p.post_table) {
+      x = Fr::mul(x, Fr::load(p.post_table + 8ull * addr));
+      if (p.post_canon) x = Fr::from_mont(x);
+    } else if (p.last) {
       if (p.post_coset) {
         const uint32_t idx = p.post_bitrev ? bitrev_bits(addr, p.log_n) : addr;
         x = Fr::mul(x, pow_lookup(T.g[p.post_coset < 0 ? 1 : 0], idx));
@@ -210,6 +214,7 @@ struct FusedParams {
   const uint32_t* ninv;       // N^-1 (bottom: with the coset scaling)
   const uint32_t* zinv;       // (g^N - 1)^-1 (top: the pointwise quotient)
   const uint32_t* tw[2];      // top: the pass's forward / inverse twiddle tables, or null
+  const uint32_t* coset;      // bottom: g^bitrev(i) / N by address i, or null
 };
 
 // Bottom fusion, one vector per blockIdx.y (A, B, C of each proof in turn).
@@ -231,7 +236,8 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fused_bottom(FusedParams p,
     const uint32_t addr = pass_addr(e, k, p.log_g, 0, k, gamma0, &gl, &t, &g);
     const uint32_t slot = gl * (1u << k) + t;
     // coefficient bitrev(addr) of the inverse transform times g^i / N
-    const Fr x = Fr::mul(Fr::mul(lds_get(lds, slot), pow_lookup(T.g[0], bitrev_bits(addr, p.log_n))), ninv);
+    const Fr x = p.coset ? Fr::mul(lds_get(lds, slot), Fr::load(p.coset + 8ull * addr))
+                         : Fr::mul(Fr::mul(lds_get(lds, slot), pow_lookup(T.g[0], bitrev_bits(addr, p.log_n))), ninv);
     lds_put(lds, slot, x);
   }
   __syncthreads();
@@ -290,6 +296,14 @@ __global__ void k_twiddle_table(uint32_t* out, int log_m, int k, int dir, NttTab
   const uint32_t t = idx >> B, g = idx & ((1u << B) - 1u);
   const uint32_t ex = g * bitrev_bits(t, k);
   pow_lookup(T.w[dir], ex << (MAX_LOG - log_m)).store(out + 8ull * idx);
+}
+
+// Coset factors of the quotient by address a: g^(+-bitrev(a)) / N, with the
+// sign of dir (0: +, 1: -) and N = 2^log_n.
+__global__ void k_coset_table(uint32_t* out, int log_n, int dir, NttTables T) {
+  const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >> log_n) return;
+  Fr::mul(pow_lookup(T.g[dir], bitrev_bits(a, log_n)), Fr::load(T.ninv + 8 * log_n)).store(out + 8ull * a);
 }
 
 __global__ void k_bitrev(uint32_t* data, int log_n, uint32_t n) {
@@ -432,13 +446,16 @@ namespace {
 // multiplication per twiddled element instead of a power-table product.
 constexpr int TW_TABLE_MAX_LOG = 24;
 
-const uint32_t* twiddle_table(int dir, int log_m, int k, const NttTables& T, hipStream_t st) {
-  if (log_m > TW_TABLE_MAX_LOG || log_m <= k) return nullptr;
+// A device table of 2^log_n entries made by `build` on first use and kept for
+// the process (null when the stream is being captured, or out of memory: the
+// callers then compute the factors instead).
+template <class Build>
+const uint32_t* cached_table(int kind, int a, int b, int log_n, hipStream_t st, Build&& build) {
   static std::mutex mu;
   static std::map<std::tuple<int, int, int, int>, DevBuf*> cache;
   const int dev = current_device();
   std::lock_guard<std::mutex> lock(mu);
-  const auto key = std::make_tuple(dev, dir, log_m, k);
+  const auto key = std::make_tuple(dev, kind, a, b);
   auto it = cache.find(key);
   if (it != cache.end()) return it->second->get();
   // not while the stream is being captured into a graph (the build waits)
@@ -447,17 +464,32 @@ const uint32_t* twiddle_table(int dir, int log_m, int k, const NttTables& T, hip
   if (cs != hipStreamCaptureStatusNone) return nullptr;
   auto* buf = new DevBuf();
   try {
-    buf->alloc((size_t)32 << log_m);
+    buf->alloc((size_t)32 << log_n);
   } catch (const Error&) {
     delete buf;
-    return nullptr;  // no room: the power tables serve instead
+    return nullptr;
   }
-  hipLaunchKernelGGL(k_twiddle_table, dim3(cdiv(1ull << log_m, 256)), dim3(256), 0, st, buf->get(), log_m, k, dir, T);
+  build(buf->get());
   ZK_HIP(hipGetLastError());
   // complete before any other stream can find it in the cache
   ZK_HIP(hipStreamSynchronize(st));
   cache[key] = buf;
   return buf->get();
+}
+
+const uint32_t* twiddle_table(int dir, int log_m, int k, const NttTables& T, hipStream_t st) {
+  if (log_m > TW_TABLE_MAX_LOG || log_m <= k) return nullptr;
+  return cached_table(0, dir, log_m * 32 + k, log_m, st, [&](uint32_t* out) {
+    hipLaunchKernelGGL(k_twiddle_table, dim3(cdiv(1ull << log_m, 256)), dim3(256), 0, st, out, log_m, k, dir, T);
+  });
+}
+
+// g^(+-bitrev(a)) / N by address a, for the quotient's coset scalings.
+const uint32_t* coset_table(int dir, int log_n, const NttTables& T, hipStream_t st) {
+  if (log_n > TW_TABLE_MAX_LOG) return nullptr;
+  return cached_table(1, dir, log_n, log_n, st, [&](uint32_t* out) {
+    hipLaunchKernelGGL(k_coset_table, dim3(cdiv(1ull << log_n, 256)), dim3(256), 0, st, out, log_n, dir, T);
+  });
 }
 
 // The passes of one transform: pass j covers bits [log_m[j] - k[j], log_m[j])
@@ -543,6 +575,7 @@ void launch_pass(uint32_t* const* data, uint32_t* const* dev_table, int nvec, co
   p.post_coset = fuse.post_coset;
   p.post_bitrev = fuse.post_bitrev;
   p.post_const = fuse.post_const;
+  p.post_table = fuse.post_table;
   const unsigned grid = 1u << (L - k - p.log_g);
   const size_t lds = (size_t)(1u << (k + p.log_g)) * NL * 4;
   unsigned threads = (1u << (k + p.log_g)) / 2;
@@ -597,6 +630,7 @@ void qap_quotient_launch(uint32_t* const* abc, uint32_t* const* dev_table, int n
   f3.post_const = T.ninv + 8 * L;
   f3.post_coset = -1;
   f3.post_bitrev = true;
+  f3.post_table = coset_table(1, L, T, st);  // the same factors, one product
   const NttFuse none;
   // inverse transform (DIF), all passes but the bottom one
   for (int j = 0; j < P - 1; j++) launch_pass(abc, dev_table, nvec, pl, j, false, true, j == 0, false, f1, T, st);
@@ -608,6 +642,7 @@ void qap_quotient_launch(uint32_t* const* abc, uint32_t* const* dev_table, int n
   fp.log_n = L;
   fp.ninv = T.ninv + 8 * L;
   fp.zinv = T.coset_zinv + 8 * L;
+  fp.coset = coset_table(0, L, T, st);
   {
     // bottom: inverse DIF pass, coset scaling, forward DIT pass
     const int j = P - 1;

@@ -37,6 +37,8 @@ struct NttFuse {
   int post_coset = 0;          // multiply output element of index i by g^(+-i) after
   bool post_bitrev = false;    //   ... where i = bitrev(address) if set
   const uint32_t* post_const = nullptr; // optional extra factor on the output
+  const uint32_t* post_table = nullptr; // if set, replaces post_coset and post_const: output element at
+                                        //   address a times entry a (8 words, Montgomery)
 };
 
 const NttTables& ntt_tables(int device);
