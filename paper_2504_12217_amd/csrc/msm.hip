@@ -420,7 +420,8 @@ __device__ __forceinline__ Xyzz<F> block_tree_sum(Xyzz<F> acc, uint32_t* sh, int
 }
 
 template <class F>
-__global__ void __launch_bounds__(BP_THREADS) k_msm_bitplanes(BatchDev B, const uint32_t* buckets, uint32_t* part) {
+__global__ void __launch_bounds__(BP_THREADS) k_msm_bitplanes(BatchDev B, const uint32_t* buckets, uint32_t* part,
+                                                               uint32_t* S) {
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
   __shared__ uint32_t sh[BP_THREADS / 2 * XW];
   const int k = job_of<&JobDev::blk_bp>(B, blockIdx.x);
@@ -442,7 +443,11 @@ __global__ void __launch_bounds__(BP_THREADS) k_msm_bitplanes(BatchDev B, const 
     acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(bw + (size_t)(v - 1) * XW));
   }
   acc = block_tree_sum<F>(acc, sh, (int)blockDim.x);
-  if (threadIdx.x == 0) PointIO<F>::store_xyzz(part + (size_t)blockIdx.x * XW, acc);
+  if (threadIdx.x != 0) return;
+  if (J.bpb == 1)  // the block's sum is the plane
+    PointIO<F>::store_xyzz(S + ((size_t)J.plane_base + q) * XW, Xyzz<F>::canon(acc));
+  else
+    PointIO<F>::store_xyzz(part + (size_t)blockIdx.x * XW, acc);
 }
 
 // One wavefront per plane: the sum of the plane's bpb block sums.
@@ -452,6 +457,7 @@ __global__ void __launch_bounds__(64) k_msm_plane_sums(BatchDev B, const uint32_
   __shared__ uint32_t sh[32 * XW];
   const int k = job_of<&JobDev::plane_base>(B, blockIdx.x);
   const JobDev& J = B.jobs[k];
+  if (J.bpb == 1) return;  // written by k_msm_bitplanes
   const uint32_t q = blockIdx.x - J.plane_base;
   const uint32_t* pp = part + ((size_t)J.blk_bp + (size_t)q * J.bpb) * XW;
   Xyzz<F> acc = Xyzz<F>::inf();
@@ -721,10 +727,15 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
     unsigned bp_threads = 64;
     while (bp_threads < (unsigned)BP_THREADS && bp_threads * 2 < per_block) bp_threads *= 2;
     hipLaunchKernelGGL(k_msm_bitplanes<F>, dim3((unsigned)p.bp_blocks), dim3(bp_threads), 0, st, dev, buckets,
-                       bp_part);
+                       bp_part, win);
     ZK_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_msm_plane_sums<F>, dim3((unsigned)p.nplanes), dim3(64), 0, st, dev, bp_part, win);
-    ZK_HIP(hipGetLastError());
+    // planes of one block each are final already
+    bool split = false;
+    for (int k = 0; k < nj; k++) split = split || p.jobs[k].bpb > 1;
+    if (split) {
+      hipLaunchKernelGGL(k_msm_plane_sums<F>, dim3((unsigned)p.nplanes), dim3(64), 0, st, dev, bp_part, win);
+      ZK_HIP(hipGetLastError());
+    }
   }
   ZK_HIP(hipMemcpyAsync(win_host, win, p.nplanes * XW * 4, hipMemcpyDeviceToHost, st));
 }
