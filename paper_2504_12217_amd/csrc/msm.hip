@@ -99,6 +99,7 @@ constexpr int MAX_C = 15;         // the LDS histogram holds 2^(c-1) u32 counter
 constexpr int HS_THREADS = 512;   // histogram / scatter blocks
 constexpr int WG_THREADS = 64;    // one wavefront per large-bucket task (at most 4 entries per lane)
 constexpr int BP_THREADS = 256;   // bit-plane reduction block
+constexpr uint64_t FEW_BUCKETS = 8192;  // a wavefront per bucket fits the device several times over
 
 // ---------------------------------------------------------------- 1. digits
 // One thread per scalar: fold, recode into signed digits, write one word per
@@ -611,9 +612,15 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs, int group) {
   // thread tasks: enough of them to fill the device, long enough to amortize
   const int kd = E ? tuning().msm_kdiv_log[std::min(33, floor_log2(E))].load() : 0;
   p.K = (uint32_t)std::max<uint64_t>(4, std::min<uint64_t>(E >> (kd > 0 ? kd : 16), 64));
-  // wavefront tasks only for buckets far above the typical size (a window's
-  // few possible top digits, or small-integer scalars piling into few buckets)
-  p.large = std::max<uint32_t>(128, 32 * p.K);
+  // With few buckets in all (a small MSM, or full-width row terms over
+  // precomputed windows) the device has room for a wavefront per bucket, and
+  // a tree's depth beats a thread's chain of dependent additions: buckets of
+  // 32 entries or more become wavefront tasks, and buckets with more than
+  // FIN_THREAD_MIN partial sums are finished by a wavefront tree.
+  const bool few_buckets = p.nbt <= FEW_BUCKETS;
+  // otherwise wavefront tasks only for buckets far above the typical size (a
+  // window's few possible top digits, or small-integer scalars piling into few buckets)
+  p.large = few_buckets ? 32u : std::max<uint32_t>(128, 32 * p.K);
   p.max_th_tasks = E / p.K + p.nbt;
   // a large bucket of c entries makes ceil(c / WG_TASK_ENTRIES) tasks, and at
   // most E / large buckets are large
@@ -623,7 +630,7 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs, int group) {
   // number of partial sums (a tree over a wavefront costs ~7 dependent
   // additions, so only far-above-average buckets gain from it)
   const uint64_t avg = p.nbt ? (E / p.K + p.nbt - 1) / p.nbt : 1;
-  p.fin_max = (uint32_t)std::max<uint64_t>(FIN_THREAD_MIN, 4 * avg);
+  p.fin_max = few_buckets ? (uint32_t)FIN_THREAD_MIN : (uint32_t)std::max<uint64_t>(FIN_THREAD_MIN, 4 * avg);
   return p;
 }
 

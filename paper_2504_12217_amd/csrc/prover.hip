@@ -115,6 +115,21 @@ Layout r1cs_layout(uint32_t a, uint32_t n, uint32_t b, uint32_t kind) {
   L.segH.count = L.N - 1;
   L.segH.bits = 253;
   if (L.segH.count) precompute(L.segH);
+  if (kind_uses_z(kind)) {
+    // full-width row values W_k(z): always precomputed windows, so that the
+    // host combines c plane sums instead of ~254
+    Seg& R = L.segR;
+    R.count = n;
+    R.bits = 253;
+    int c = 0, nw = 1;
+    msm_choose_precomputed(n, R.bits, 32, &c, &nw);
+    if (nw <= 1) {
+      c = 8;
+      nw = 32;
+    }
+    R.pre_c = c;
+    R.pre_nw = nw;
+  }
   return L;
 }
 
@@ -293,6 +308,16 @@ __global__ void k_lin(const uint32_t* u, const uint32_t* v, const uint32_t* w, u
 }
 
 // out_j = in_j * f (Montgomery form): the scalars of a precomputed window copy.
+// out[k] = in[k stride] for k < n (Fr elements).
+__global__ void k_gather_stride(const uint32_t* in, uint32_t stride, uint32_t n, uint32_t* out) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const uint4* src = reinterpret_cast<const uint4*>(in + 8ull * k * stride);
+  uint4* dst = reinterpret_cast<uint4*>(out + 8ull * k);
+  dst[0] = src[0];
+  dst[1] = src[1];
+}
+
 __global__ void k_scale_fr(const uint32_t* in, uint32_t n, const uint32_t* f, uint32_t* out) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
@@ -709,6 +734,40 @@ zkvc_pk* groth16_setup(const Layout& L, const host::HFr toxic[5], const host::HF
     fixed_base_g1(v + 8 * s.var_start, true, s.count, pk->qB1.get() + 16 * s.point_offset, false, ws, st);
     fixed_base_g2(v + 8 * s.var_start, true, s.count, pk->qB2.get() + 32 * s.point_offset, false, ws, st);
   }
+  // a G2 range's precomputed copies, as emit_g1
+  auto emit_g2 = [&](const uint32_t* sc_mont, const Seg& s, uint32_t* qbase) {
+    fixed_base_g2(sc_mont, true, s.count, qbase + 32 * s.point_offset, false, ws, st);
+    std::vector<uint32_t> fw(8 * s.pre_nw);
+    const HFr step = HFr::pow(HFr::from_uint(2), std::array<uint64_t, 4>{(uint64_t)s.pre_c, 0, 0, 0}.data());
+    HFr f = HFr::one();
+    for (int w = 0; w < s.pre_nw; w++) {
+      f.to_dev(&fw[8 * w]);
+      f = HFr::mul(f, step);
+    }
+    uint32_t* dfw = ws.get(13, fw.size() * 4);
+    upload_words(dfw, fw, st);
+    for (int w = 1; w < s.pre_nw; w++) {
+      hipLaunchKernelGGL(k_scale_fr, dim3(cdiv(s.count, 256)), dim3(256), 0, st, sc_mont, (uint32_t)s.count,
+                         dfw + 8 * w, scaled);
+      ZK_HIP(hipGetLastError());
+      fixed_base_g2(scaled, true, s.count, qbase + 32 * (s.point_offset + (uint64_t)w * s.count), false, ws, st);
+    }
+  };
+  // row bases of the CRPC kinds: v_{w_k0}(tau) = L_k(tau) for B1 and B2
+  uint32_t* rsc = nullptr;
+  if (L.segR.count) {
+    const Seg& R = L.segR;
+    const size_t nr = (size_t)R.count * R.pre_nw;
+    pk->qRB1.alloc(nr * 64);
+    pk->qRB2.alloc(nr * 128);
+    pk->qRL.alloc(nr * 64);
+    rsc = ws.get(14, R.count * 32);
+    hipLaunchKernelGGL(k_gather_stride, dim3(cdiv(R.count, 256)), dim3(256), 0, st, v + 8 * L.w_start, (uint32_t)L.b,
+                       (uint32_t)R.count, rsc);
+    ZK_HIP(hipGetLastError());
+    emit_g1(rsc, R, pk->qRB1.get());
+    emit_g2(rsc, R, pk->qRB2.get());
+  }
   // L query: (beta u + alpha v + w) / delta over the witness variables
   std::vector<uint32_t> lc(8 * 3);
   alpha.to_dev(&lc[0]);
@@ -721,6 +780,13 @@ zkvc_pk* groth16_setup(const Layout& L, const host::HFr toxic[5], const host::HF
                        dlc, sc);
     ZK_HIP(hipGetLastError());
     emit_g1(sc, s, pk->qL.get());
+    if (rsc && s.var_start == L.w_start) {
+      // row bases for L: the entries of w_k0, (alpha L_k(tau)) / delta
+      hipLaunchKernelGGL(k_gather_stride, dim3(cdiv(L.segR.count, 256)), dim3(256), 0, st, sc, (uint32_t)L.b,
+                         (uint32_t)L.segR.count, rsc);
+      ZK_HIP(hipGetLastError());
+      emit_g1(rsc, L.segR, pk->qRL.get());
+    }
   }
   // H query: tau^j (tau^N - 1) / delta, j < N - 1
   if (N > 1) {
@@ -779,7 +845,8 @@ zkvc_pk* groth16_setup(const Layout& L, const host::HFr toxic[5], const host::HF
   put_raw(vk, (uint64_t)nic);
   vk.insert(vk.end(), ic_host.begin(), ic_host.end());
 
-  pk->key_bytes = pk->qA.size() + pk->qB1.size() + pk->qB2.size() + pk->qL.size() + pk->qH.size() + pk->zpow.size();
+  pk->key_bytes = pk->qA.size() + pk->qB1.size() + pk->qB2.size() + pk->qL.size() + pk->qH.size() + pk->zpow.size() +
+                  pk->qRB1.size() + pk->qRB2.size() + pk->qRL.size();
   pk->ws.clear();  // setup scratch is not needed for proving
   return pk.release();
 }
@@ -810,9 +877,19 @@ struct MsmJob {
   MsmInput in;
 };
 
-std::vector<MsmJob> msm_jobs(const zkvc_pk* pk, const uint32_t* assign, const uint32_t* h_bitrev) {
+// wk: for the CRPC kinds, W_k(z) = sum_j z^j w_kj for k < n (device Montgomery form).
+std::vector<MsmJob> msm_jobs(const zkvc_pk* pk, const uint32_t* assign, const uint32_t* h_bitrev,
+                             const uint32_t* wk) {
   const Layout& L = pk->L;
   std::vector<MsmJob> jobs;
+  // In the CRPC kinds a variable w_kj enters one row only, the B side of
+  // constraint k with coefficient z^j, so v_{w_kj} = z^j L_k and u, w vanish:
+  // its B1, B2 and L key entries are z^j times those of w_k0 (setup makes
+  // both from the same L_k).  Their n b terms sum to sum_k W_k(z) [entry of
+  // w_k0]: n terms with the row values the witness already holds, over the
+  // row bases stored with precomputed windows (the same group elements, so
+  // the proof does not change).
+  const bool collapse_w = kind_uses_z(L.kind) && wk != nullptr && L.segR.count == L.n;
   auto add = [&](int group, int query, const uint32_t* points, const Seg& s) {
     MsmJob j;
     j.group = group;
@@ -825,6 +902,17 @@ std::vector<MsmJob> msm_jobs(const zkvc_pk* pk, const uint32_t* assign, const ui
     if (s.pre_nw > 1) {
       j.in.pre_c = s.pre_c;
       j.in.pre_nw = s.pre_nw;
+    }
+    if (collapse_w && s.var_start == L.w_start && s.count == (uint64_t)L.n * L.b) {
+      const DevBuf& rb = query == ZKVC_Q_B2 ? pk->qRB2 : (query == ZKVC_Q_B1 ? pk->qRB1 : pk->qRL);
+      j.in.points = rb.get();
+      j.in.npoints = L.n;
+      j.in.scalars = wk;
+      j.in.nscalars = L.n;
+      j.in.scalars_mont = true;
+      j.in.max_bits = L.segR.bits;
+      j.in.pre_c = L.segR.pre_c;
+      j.in.pre_nw = L.segR.pre_nw;
     }
     jobs.push_back(j);
   };
@@ -855,6 +943,7 @@ std::vector<MsmJob> msm_jobs(const zkvc_pk* pk, const uint32_t* assign, const ui
 // Device buffers of one proof in flight.
 struct Slot {
   uint32_t *assign, *aev, *bev, *cev;
+  const uint32_t* wk;  // CRPC kinds: W_k(z) for k < n, else null
   int32_t* yh;      // pinned copy of Y
   int8_t *xh, *wh;  // pinned staging of X and W
 };
@@ -920,12 +1009,14 @@ std::vector<Slot> enqueue_witness_batch(const ProveJob* jobs, size_t nj, ProveGe
     if (kind_uses_z(L.kind)) {
       J.xk = ws.get(P_XK, (size_t)L.n * 32);
       J.wk = ws.get(P_WK, (size_t)L.n * 32);
+      S.wk = J.wk;
       J.pkk = ws.get(P_PK, (size_t)L.n * 32);
       J.yz = ws.get(P_YZ, 32 * YZ_BLOCKS);
       any_crpc = true;
       max_n_crpc = std::max(max_n_crpc, L.n);
     } else {
       J.xk = J.wk = J.pkk = J.yz = nullptr;
+      S.wk = nullptr;
       any_plain = true;
       max_m_plain = std::max(max_m_plain, L.m);
     }
@@ -1200,7 +1291,7 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
   std::vector<MsmInput> &in_g1 = R.in_g1, &in_g2 = R.in_g2, &in_h = R.in_h;
   std::vector<int> &own_g1 = R.own_g1, &query_g1 = R.query_g1, &own_g2 = R.own_g2, &own_h = R.own_h;
   for (size_t j = 0; j < nj; j++) {
-    for (const MsmJob& m : msm_jobs(jobs[j].pk, slots[j].assign, slots[j].aev)) {
+    for (const MsmJob& m : msm_jobs(jobs[j].pk, slots[j].assign, slots[j].aev, slots[j].wk)) {
       if (m.query == ZKVC_Q_H) {
         in_h.push_back(m.in);
         own_h.push_back((int)j);

@@ -42,6 +42,10 @@ struct Layout {
   int y_bits = 0, aux_bits = 253;
   std::vector<Seg> segA, segB, segL;  // query coverage
   Seg segH;                            // the H query (j < N - 1)
+  // CRPC kinds: one base per constraint row k < n (the B1, B2 and L entries
+  // of w_k0), stored with precomputed windows; the prover sums the n b
+  // W terms of those queries as n row terms (see msm_jobs)
+  Seg segR;
 };
 
 Layout r1cs_layout(uint32_t a, uint32_t n, uint32_t b, uint32_t kind);
@@ -119,6 +123,7 @@ struct zkvc_pk {
   zkvc::host::HFr z;
   // Queries in the internal layout (affine, Montgomery); segments concatenated.
   zkvc::DevBuf qA, qB1, qB2, qL, qH;
+  zkvc::DevBuf qRB1, qRB2, qRL;  // row bases (CRPC kinds), Layout::segR copies each
   zkvc::DevBuf zpow;  // z^e for e < a*b (CRPC kinds), internal Fr layout
   zkvc::host::G1J alpha1, beta1, delta1;
   zkvc::host::G2J beta2, delta2;
