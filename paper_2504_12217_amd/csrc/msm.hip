@@ -99,7 +99,7 @@ constexpr int MAX_C = 15;         // the LDS histogram holds 2^(c-1) u32 counter
 constexpr int HS_THREADS = 512;   // histogram / scatter blocks
 constexpr int WG_THREADS = 64;    // one wavefront per large-bucket task (at most 4 entries per lane)
 constexpr int BP_THREADS = 256;   // bit-plane reduction block
-constexpr uint64_t FEW_BUCKETS = 8192;  // a wavefront per bucket fits the device several times over
+constexpr uint64_t FEW_BUCKETS = 4096;  // a wavefront per bucket leaves most of the device free
 
 // ---------------------------------------------------------------- 1. digits
 // One thread per scalar: fold, recode into signed digits, write one word per
