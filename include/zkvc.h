@@ -319,6 +319,12 @@ typedef struct {
 } zkvc_kernel_stat;
 int zkvc_profile_begin(void);
 int zkvc_profile_read(zkvc_kernel_stat* out, int capacity, int* count);
+/* Restricts recording to the instrumented launches named `kernel` (a name as
+ * reported by zkvc_profile_read; NULL or "" records every launch again), so
+ * that timing one kernel costs two event records per launch of that kernel
+ * only.  Takes effect for launches enqueued afterwards.  Host only;
+ * ZKVC_EINVAL if the name is longer than 47 bytes. */
+int zkvc_profile_select(const char* kernel);
 
 #ifdef __cplusplus
 }

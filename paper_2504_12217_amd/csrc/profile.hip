@@ -5,6 +5,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -30,6 +31,9 @@ struct Rec {
 
 std::mutex g_mu;
 std::atomic<bool> g_on{false};
+// the one kernel name recorded, or null: all (names interned for the process)
+std::atomic<const char*> g_select{nullptr};
+std::set<std::string> g_names;
 std::atomic<int> g_next{0};
 hipEvent_t g_ev[2 * POOL];
 uint32_t* g_words = nullptr;  // pinned, POOL words
@@ -96,6 +100,8 @@ bool profiling_enabled() { return g_on.load(std::memory_order_relaxed); }
 
 ProfScope::ProfScope(const char* name, hipStream_t st, double work) : st_(st) {
   if (!profiling_enabled()) return;
+  const char* sel = g_select.load(std::memory_order_acquire);
+  if (sel && std::strcmp(sel, name) != 0) return;
   if (capturing(st)) {
     if (!t_sink) return;
     const int k = graph_slot_alloc();
@@ -168,6 +174,15 @@ int zkvc_profile_begin(void) {
     ZK_HIP(hipDeviceSynchronize());
     g_next = 0;
     g_on = true;
+  });
+}
+
+int zkvc_profile_select(const char* kernel) {
+  return guarded([&] {
+    const size_t len = kernel ? std::strlen(kernel) : 0;
+    ZK_REQUIRE(len < sizeof(zkvc_kernel_stat::name), "kernel name too long");
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_select.store(len ? g_names.insert(std::string(kernel)).first->c_str() : nullptr, std::memory_order_release);
   });
 }
 

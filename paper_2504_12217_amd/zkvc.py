@@ -102,6 +102,7 @@ _SIGS = {
     "zkvc_tune_export": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_size_t)]),
     "zkvc_tune_import": (ctypes.c_int, [ctypes.c_char_p]),
     "zkvc_set_graphs": (ctypes.c_int, [ctypes.c_int]),
+    "zkvc_profile_select": (ctypes.c_int, [ctypes.c_char_p]),
     "zkvc_verify": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, _VP, _VP, ctypes.POINTER(Proof)]),
     "zkvc_ntt_fr": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint32, _VP]),
     "zkvc_msm_g1": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, ctypes.c_uint32, ctypes.POINTER(G1), _VP]),
@@ -255,6 +256,11 @@ def set_graphs(enable):
 def profile_begin():
     """Start recording HIP events around the library's instrumented launches."""
     _check(lib().zkvc_profile_begin())
+
+
+def profile_select(kernel=None):
+    """Record only the launches named `kernel` (None: all of them)."""
+    _check(lib().zkvc_profile_select(kernel.encode() if kernel else None))
 
 
 def profile_read():

@@ -244,3 +244,27 @@ def test_msm_rejects_bad_arguments(zk):
         zk.msm_g2(0, d, 2)
     with pytest.raises(zk.ZkvcError):
         zk.msm_g1(d, d, 2, flags=8)
+
+
+def test_profile_records_launches_and_selects_one_kernel(zk):
+    """The event profiler: every instrumented launch, or only the selected kernel's."""
+    log_n = 12
+    d = dev_words(synth.fr_limbs(3, synth.STREAM_NTT, 1 << log_n))
+    zk.profile_select(None)
+    zk.profile_begin()
+    zk.ntt_fr(d, log_n, zk.LAYOUT_MONT)
+    st = zk.profile_read()
+    assert "ntt_pass" in st and st["ntt_pass"][0] >= 2 and st["ntt_pass"][1] > 0
+    # butterflies: (N/2) log N over all passes
+    assert st["ntt_pass"][2] == (1 << (log_n - 1)) * log_n
+    zk.profile_select("no_such_kernel")
+    zk.profile_begin()
+    zk.ntt_fr(d, log_n, zk.LAYOUT_MONT)
+    assert zk.profile_read() == {}
+    zk.profile_select("ntt_pass")
+    zk.profile_begin()
+    zk.ntt_fr(d, log_n, zk.LAYOUT_MONT)
+    assert set(zk.profile_read()) == {"ntt_pass"}
+    zk.profile_select(None)
+    with pytest.raises(zk.ZkvcError):
+        zk.profile_select("x" * 60)
