@@ -106,6 +106,33 @@ def test_ntt_large_freivalds_and_round_trip(zk, log_n):
     assert np.array_equal(host_words(d).reshape(-1, 8), x)
 
 
+def test_ntt_beyond_twiddle_tables(zk):
+    """2^25 points: the top pass computes its twiddles from the power tables
+    (per-pass twiddle tables stop at 2^24): sampled outputs of a delta input
+    against the root of unity's powers, and plain and coset round trips."""
+    log_n = 25
+    n = 1 << log_n
+    x = np.zeros((n, 8), dtype=np.uint32)
+    x[1, 0] = 1  # X_k = omega^k
+    d = dev_words(x)
+    zk.ntt_fr(d, log_n, 0)
+    out = host_words(d).reshape(-1, 8)
+    w = ontt.root_of_unity(n)
+    rng = random.Random(25)
+    for k in [0, 1, 2, n // 2, n - 1] + [rng.randrange(n) for _ in range(400)]:
+        assert synth.limbs_to_ints(out[k:k + 1])[0] == pow(w, k, bn.R), k
+    del d
+    y = synth.fr_limbs(4, synth.STREAM_NTT, n)
+    d = dev_words(y)
+    zk.ntt_fr(d, log_n, 0)
+    assert not np.array_equal(host_words(d).reshape(-1, 8), y)
+    zk.ntt_fr(d, log_n, zk.NTT_INVERSE)
+    assert np.array_equal(host_words(d).reshape(-1, 8), y)
+    zk.ntt_fr(d, log_n, zk.NTT_COSET)
+    zk.ntt_fr(d, log_n, zk.NTT_COSET | zk.NTT_INVERSE)
+    assert np.array_equal(host_words(d).reshape(-1, 8), y)
+
+
 def test_ntt_internal_layout_consistent(zk):
     log_n = 10
     x = synth.fr_limbs(5, synth.STREAM_NTT, 1 << log_n)
