@@ -86,7 +86,10 @@ def log(msg):
 
 def roofline(stats, workload=None):
     """Roofline entry for the kernel with the most device time."""
-    name, (launches, total_ms, work) = max(stats.items(), key=lambda kv: kv[1][1])
+    modeled = {k: v for k, v in stats.items() if k in FMUL_PER_UNIT} or stats
+    if not modeled:
+        return None, None
+    name, (launches, total_ms, work) = max(modeled.items(), key=lambda kv: kv[1][1])
     avg_ms = total_ms / max(launches, 1)
     per_unit = FMUL_PER_UNIT.get(name)
     if per_unit is None:
@@ -105,8 +108,9 @@ def roofline(stats, workload=None):
 def time_proofs(zk, pk, X, W, r, s, steps, warmup, profile):
     """Times `steps` proofs after `warmup` ones.  With profile set, the warm-up
     proofs time every instrumented launch (the per-kernel table), and the
-    timed proofs record only the launches of the kernel with the most device
-    time there (two HIP events per launch of that kernel, for its roofline).
+    timed proofs record only the launches of the kernels with an algorithmic
+    work model (two HIP events per such launch), among which the roofline
+    takes the one with the most device time over the timed region.
     Returns (seconds, per-proof latencies, timed-region stats, warm-up stats)."""
     import torch
     stats_all = None
@@ -118,8 +122,9 @@ def time_proofs(zk, pk, X, W, r, s, steps, warmup, profile):
     torch.cuda.synchronize()
     if profile:
         stats_all = zk.profile_read()
-        dominant = max(stats_all.items(), key=lambda kv: kv[1][1])[0]
-        zk.profile_select(dominant)
+        # single-kernel scopes with an algorithmic work model (msm_sort, say,
+        # spans several kernels)
+        zk.profile_select(sorted(FMUL_PER_UNIT))
         zk.profile_begin()
     lat = []
     t0 = time.perf_counter()

@@ -319,12 +319,13 @@ typedef struct {
 } zkvc_kernel_stat;
 int zkvc_profile_begin(void);
 int zkvc_profile_read(zkvc_kernel_stat* out, int capacity, int* count);
-/* Restricts recording to the instrumented launches named `kernel` (a name as
- * reported by zkvc_profile_read; NULL or "" records every launch again), so
- * that timing one kernel costs two event records per launch of that kernel
- * only.  Takes effect for launches enqueued afterwards.  Host only;
- * ZKVC_EINVAL if the name is longer than 47 bytes. */
-int zkvc_profile_select(const char* kernel);
+/* Restricts recording to the instrumented launches whose names (as reported
+ * by zkvc_profile_read) are listed in `kernels`, comma separated; NULL or ""
+ * records every launch again.  Timing a few kernels then costs two event
+ * records per launch of those kernels only.  Takes effect for launches
+ * enqueued afterwards.  Host only; ZKVC_EINVAL if the list is 4096 bytes or
+ * longer. */
+int zkvc_profile_select(const char* kernels);
 
 #ifdef __cplusplus
 }

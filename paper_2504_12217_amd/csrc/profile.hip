@@ -31,7 +31,7 @@ struct Rec {
 
 std::mutex g_mu;
 std::atomic<bool> g_on{false};
-// the one kernel name recorded, or null: all (names interned for the process)
+// the kernel names recorded, comma separated, or null: all (interned for the process)
 std::atomic<const char*> g_select{nullptr};
 std::set<std::string> g_names;
 std::atomic<int> g_next{0};
@@ -55,6 +55,19 @@ int graph_slot_alloc() {
   const int k = g_gfree.back();
   g_gfree.pop_back();
   return k;
+}
+
+// name is one of the comma-separated names in sel
+bool selected(const char* sel, const char* name) {
+  const size_t n = std::strlen(name);
+  for (const char* p = sel; *p;) {
+    const char* e = std::strchr(p, ',');
+    const size_t len = e ? (size_t)(e - p) : std::strlen(p);
+    if (len == n && std::strncmp(p, name, n) == 0) return true;
+    if (!e) break;
+    p = e + 1;
+  }
+  return false;
 }
 
 bool capturing(hipStream_t st) {
@@ -101,7 +114,7 @@ bool profiling_enabled() { return g_on.load(std::memory_order_relaxed); }
 ProfScope::ProfScope(const char* name, hipStream_t st, double work) : st_(st) {
   if (!profiling_enabled()) return;
   const char* sel = g_select.load(std::memory_order_acquire);
-  if (sel && std::strcmp(sel, name) != 0) return;
+  if (sel && !selected(sel, name)) return;
   if (capturing(st)) {
     if (!t_sink) return;
     const int k = graph_slot_alloc();
@@ -180,7 +193,7 @@ int zkvc_profile_begin(void) {
 int zkvc_profile_select(const char* kernel) {
   return guarded([&] {
     const size_t len = kernel ? std::strlen(kernel) : 0;
-    ZK_REQUIRE(len < sizeof(zkvc_kernel_stat::name), "kernel name too long");
+    ZK_REQUIRE(len < 4096, "kernel list too long");
     std::lock_guard<std::mutex> lock(g_mu);
     g_select.store(len ? g_names.insert(std::string(kernel)).first->c_str() : nullptr, std::memory_order_release);
   });

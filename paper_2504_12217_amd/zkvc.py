@@ -258,9 +258,11 @@ def profile_begin():
     _check(lib().zkvc_profile_begin())
 
 
-def profile_select(kernel=None):
-    """Record only the launches named `kernel` (None: all of them)."""
-    _check(lib().zkvc_profile_select(kernel.encode() if kernel else None))
+def profile_select(kernels=None):
+    """Record only the launches of the named kernels (a name or a list of names; None: all)."""
+    if isinstance(kernels, (list, tuple, set)):
+        kernels = ",".join(sorted(kernels))
+    _check(lib().zkvc_profile_select(kernels.encode() if kernels else None))
 
 
 def profile_read():

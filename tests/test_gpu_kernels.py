@@ -292,6 +292,10 @@ def test_profile_records_launches_and_selects_one_kernel(zk):
     zk.profile_begin()
     zk.ntt_fr(d, log_n, zk.LAYOUT_MONT)
     assert set(zk.profile_read()) == {"ntt_pass"}
+    zk.profile_select(["msm_acc_points_g1", "ntt_pass"])
+    zk.profile_begin()
+    zk.ntt_fr(d, log_n, zk.LAYOUT_MONT)
+    assert set(zk.profile_read()) == {"ntt_pass"}
     zk.profile_select(None)
     with pytest.raises(zk.ZkvcError):
-        zk.profile_select("x" * 60)
+        zk.profile_select("x" * 5000)
