@@ -370,17 +370,31 @@ template <class F>
 __global__ void __launch_bounds__(64) k_msm_finalize(const uint32_t* nt, const uint32_t* part_off,
                                                      const uint32_t* partials, uint32_t nbt, const uint32_t* counters,
                                                      const uint32_t* heavy, uint32_t light_blocks, uint32_t fin_max,
-                                                     uint32_t* buckets) {
+                                                     uint32_t group, uint32_t* buckets) {
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
-  __shared__ uint32_t sh[WG_THREADS / 2 * XW];
+  __shared__ uint32_t sh[WG_THREADS * XW];
   if (blockIdx.x < light_blocks) {
-    const uint32_t f = blockIdx.x * 64 + threadIdx.x;
-    if (f >= nbt) return;
-    const uint32_t c = nt[f], o = part_off[f];
-    if (c > fin_max) return;
+    // `group` lanes per bucket (a power of two <= 64): each sums a strided
+    // share of the bucket's partials, then a tree over the group
+    const uint32_t f = blockIdx.x * (WG_THREADS / group) + threadIdx.x / group;
+    const uint32_t lane = threadIdx.x & (group - 1u);
+    uint32_t c = 0, o = 0;
+    if (f < nbt) {
+      c = nt[f];
+      o = part_off[f];
+    }
+    const bool mine = f < nbt && c <= fin_max;
     Xyzz<F> acc = Xyzz<F>::inf();
-    for (uint32_t e = 0; e < c; e++) acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(partials + (size_t)(o + e) * XW));
-    PointIO<F>::store_xyzz(buckets + (size_t)f * XW, acc);
+    if (mine)
+      for (uint32_t e = lane; e < c; e += group)
+        acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(partials + (size_t)(o + e) * XW));
+    for (uint32_t q = group / 2; q >= 1; q >>= 1) {  // every thread of the block takes part
+      if (lane >= q && lane < 2 * q) PointIO<F>::store_xyzz(sh + (threadIdx.x - q) * XW, acc);
+      __syncthreads();
+      if (lane < q) acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(sh + threadIdx.x * XW));
+      __syncthreads();
+    }
+    if (mine && lane == 0) PointIO<F>::store_xyzz(buckets + (size_t)f * XW, acc);
     return;
   }
   const uint32_t nheavy = counters[2];
@@ -545,6 +559,7 @@ struct BatchPlan {
   uint32_t large = 0;  // buckets with at least this many entries get wavefront tasks
   uint64_t max_th_tasks = 0, max_wg_tasks = 0, max_partials = 0;
   uint32_t fin_max = 0;  // partial sums above which a bucket gets a wavefront in the finalize step
+  uint32_t fin_group = 1;  // lanes per bucket below that (about four partial sums per lane)
 };
 
 static BatchPlan batch_plan(const MsmInput* in, int njobs, int group) {
@@ -611,7 +626,7 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs, int group) {
   const uint64_t E = p.ndigits;  // bound on the bucket entries
   // thread tasks: enough of them to fill the device, long enough to amortize
   const int kd = E ? tuning().msm_kdiv_log[std::min(33, floor_log2(E))].load() : 0;
-  p.K = (uint32_t)std::max<uint64_t>(4, std::min<uint64_t>(E >> (kd > 0 ? kd : 16), 64));
+  p.K = (uint32_t)std::max<uint64_t>(4, std::min<uint64_t>(E >> (kd > 0 ? kd : 17), 64));
   // With few buckets in all (a small MSM, or full-width row terms over
   // precomputed windows) the device has room for a wavefront per bucket, and
   // a tree's depth beats a thread's chain of dependent additions: buckets of
@@ -631,6 +646,10 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs, int group) {
   // additions, so only far-above-average buckets gain from it)
   const uint64_t avg = p.nbt ? (E / p.K + p.nbt - 1) / p.nbt : 1;
   p.fin_max = few_buckets ? (uint32_t)FIN_THREAD_MIN : (uint32_t)std::max<uint64_t>(FIN_THREAD_MIN, 4 * avg);
+  // short thread tasks leave many partial sums per bucket: a small tree per
+  // bucket keeps the finalize chain short
+  p.fin_group = 1;
+  while (p.fin_group < 64 && 4 * p.fin_group < avg) p.fin_group *= 2;
   return p;
 }
 
@@ -717,10 +736,10 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
   }
   {
     ProfScope ps(g1 ? "msm_finalize_g1" : "msm_finalize_g2", st, (double)nbt);
-    const unsigned light_blocks = cdiv(nbt, 64);
+    const unsigned light_blocks = cdiv(nbt, 64 / p.fin_group);
     const unsigned heavy_blocks = (unsigned)std::min<uint64_t>(nbt, 1024);
     hipLaunchKernelGGL(k_msm_finalize<F>, dim3(light_blocks + heavy_blocks), dim3(64), 0, st, nt, part_off, part, nbt,
-                       meta + 8, heavy, light_blocks, p.fin_max, buckets);
+                       meta + 8, heavy, light_blocks, p.fin_max, p.fin_group, buckets);
     ZK_HIP(hipGetLastError());
   }
   {
