@@ -95,3 +95,19 @@ def test_tuning_table_import_export_round_trip(zk):
 def test_strerror_without_gpu(zk):
     # strerror only formats text; no device work
     assert zk.lib().zkvc_strerror(zk.EINVAL)
+
+
+def test_graph_switch_and_profile_selection_are_host_only(zk):
+    """zkvc_set_graphs returns the previous setting; zkvc_profile_select checks its list length."""
+    prev = zk.set_graphs(1)
+    try:
+        assert zk.set_graphs(0) == 1
+        assert zk.set_graphs(0) == 0
+    finally:
+        zk.set_graphs(prev)
+    zk.profile_select(["msm_acc_points_g1", "ntt_pass"])
+    zk.profile_select("ntt_pass")
+    zk.profile_select(None)
+    with pytest.raises(zk.ZkvcError) as e:
+        zk.profile_select("k" * 5000)
+    assert e.value.code == zk.EINVAL
