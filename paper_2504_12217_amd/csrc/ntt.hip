@@ -585,15 +585,15 @@ void launch_pass(uint32_t* const* data, uint32_t* const* dev_table, int nvec, co
   ZK_HIP(hipGetLastError());
 }
 
-void ntt_launch_impl(uint32_t* const* data, uint32_t* const* dev_table, int nvec, int log_n, bool dit, bool inverse,
-                     const NttFuse& fuse, hipStream_t st) {
+void ntt_launch_impl(uint32_t* const* data, int nvec, int log_n, bool dit, bool inverse, const NttFuse& fuse,
+                     hipStream_t st) {
   ZK_REQUIRE(log_n >= 0 && log_n <= MAX_LOG, "log_n out of range");
-  ZK_REQUIRE(nvec >= 1 && nvec <= (dev_table ? 65535 : NTT_MAX_BATCH), "NTT batch size out of range");
+  ZK_REQUIRE(nvec >= 1 && nvec <= NTT_MAX_BATCH, "NTT batch size out of range");
   const NttTables& T = ntt_tables(current_device());
   const PassPlan pl = plan_passes(log_n, 1, NTT_MAX_K);
   for (int step = 0; step < pl.npass; step++) {
     const int j = dit ? (pl.npass - 1 - step) : step;
-    launch_pass(data, dev_table, nvec, pl, j, dit, inverse, step == 0, step == pl.npass - 1, fuse, T, st);
+    launch_pass(data, nullptr, nvec, pl, j, dit, inverse, step == 0, step == pl.npass - 1, fuse, T, st);
   }
 }
 
@@ -601,12 +601,7 @@ void ntt_launch_impl(uint32_t* const* data, uint32_t* const* dev_table, int nvec
 
 void ntt_launch_batch(uint32_t* const* data, int nvec, int log_n, bool dit, bool inverse, const NttFuse& fuse,
                       hipStream_t st) {
-  ntt_launch_impl(data, nullptr, nvec, log_n, dit, inverse, fuse, st);
-}
-
-void ntt_launch_table(uint32_t* const* dev_table, int nvec, int log_n, bool dit, bool inverse, const NttFuse& fuse,
-                      hipStream_t st) {
-  ntt_launch_impl(nullptr, dev_table, nvec, log_n, dit, inverse, fuse, st);
+  ntt_launch_impl(data, nvec, log_n, dit, inverse, fuse, st);
 }
 
 void ntt_launch(uint32_t* data, int log_n, bool dit, bool inverse, const NttFuse& fuse, hipStream_t st) {

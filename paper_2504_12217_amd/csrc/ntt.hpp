@@ -64,9 +64,6 @@ void ntt_launch(uint32_t* data, int log_n, bool dit, bool inverse, const NttFuse
 // in one set of launches (more workgroups in flight per pass).
 void ntt_launch_batch(uint32_t* const* data, int nvec, int log_n, bool dit, bool inverse, const NttFuse& fuse,
                       hipStream_t st);
-// The same for any number of vectors (up to 65535) listed in a device table.
-void ntt_launch_table(uint32_t* const* dev_table, int nvec, int log_n, bool dit, bool inverse, const NttFuse& fuse,
-                      hipStream_t st);
 
 // The QAP quotient of nproofs proofs of one domain size N = 2^log_n (>= 4):
 // A, B, C hold canonical evaluations on the domain; afterwards A holds the
