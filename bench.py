@@ -281,8 +281,13 @@ def serve_section(zk, seed, rates=SERVE_RATES, max_batch=64):
     tox = synth.toxic_waste(seed)
     z = synth.crpc_point(seed)
     keys = {sh: zk.setup(*sh, zk.CRPC_PSQ, tox, z) for sh in classes}
-    # warm the server's workspaces with one batch of every class
+    # warm the server (a server in steady state): every class alone twice in a
+    # row (both batch generations size their buffers and factor tables for it),
+    # then one batch of all classes together
     srv = zk.Server(max_batch=max_batch)
+    for sh in classes:
+        for _ in range(2):
+            srv.wait(srv.submit(keys[sh], *synth.matmul_inputs(seed, *sh), 3, 5))
     for t in [srv.submit(keys[sh], *synth.matmul_inputs(seed, *sh), 3, 5) for sh in classes]:
         srv.wait(t)
     out = {}
