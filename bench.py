@@ -290,6 +290,12 @@ def serve_section(zk, seed, rates=SERVE_RATES, max_batch=64):
             srv.wait(srv.submit(keys[sh], *synth.matmul_inputs(seed, *sh), 3, 5))
     for t in [srv.submit(keys[sh], *synth.matmul_inputs(seed, *sh), 3, 5) for sh in classes]:
         srv.wait(t)
+    # and bursts of the largest class, so that the first few batch slots of
+    # both generations hold buffers of its size
+    big = max(classes, key=lambda sh: sh[1] * sh[2])
+    for _ in range(2):
+        for t in [srv.submit(keys[big], *synth.matmul_inputs(seed, *big), 3, 5) for _ in range(8)]:
+            srv.wait(t)
     out = {}
     for lam in rates:
         count = int(min(400, max(40, 4 * lam)))

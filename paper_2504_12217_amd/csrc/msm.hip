@@ -667,7 +667,7 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
   const uint32_t nbt = (uint32_t)p.nbt;
   const bool g1 = PointIO<F>::AFF_WORDS == 16;
 
-  // all buffers first (growing a buffer synchronizes the device)
+  // all buffers first (a buffer that grows is replaced by a new one)
   uint32_t* digits = ws.get(S_DIGITS, p.ndigits * 4);
   uint32_t* hist = ws.get(S_COUNTS, p.nh * 4);
   uint32_t* offs = ws.get(S_OFFSETS, (p.nh + 1) * 4);

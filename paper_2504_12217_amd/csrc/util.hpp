@@ -66,6 +66,8 @@ class HostBuf {
   ~HostBuf() { release(); }
   HostBuf(const HostBuf&) = delete;
   HostBuf& operator=(const HostBuf&) = delete;
+  HostBuf(HostBuf&& o) noexcept : p_(o.p_), n_(o.n_) { o.p_ = nullptr; o.n_ = 0; }
+  size_t size() const { return n_; }
   void ensure(size_t bytes);
   void release();
   template <class T = uint32_t>
@@ -80,31 +82,48 @@ class HostBuf {
 // (a proving key's MSM lane, or one stream of the standalone calls) has its own.
 class Workspace {
  public:
+  // A buffer that has to grow is replaced, and the old one is retired (kept
+  // until the workspace goes) rather than freed: work still in flight may
+  // read it, and freeing device memory would wait for the whole device,
+  // stalling every other stream (a latency spike for a server).
   template <class T = uint32_t>
   T* get(int slot, size_t bytes) {
     auto& b = bufs_[slot];
-    b.ensure(bytes < 256 ? 256 : bytes);
+    const size_t need = bytes < 256 ? 256 : bytes;
+    if (need > b.size()) {
+      if (b.size()) retired_.push_back(std::move(b));
+      b.alloc(need);
+    }
     return b.get<T>();
   }
   template <class T = uint32_t>
   T* host(int slot, size_t bytes) {
     auto& b = host_[slot];
-    b.ensure(bytes < 256 ? 256 : bytes);
+    const size_t need = bytes < 256 ? 256 : bytes;
+    if (need > b.size()) {
+      if (b.size()) retired_host_.push_back(std::move(b));
+      b.ensure(need);
+    }
     return b.get<T>();
   }
   size_t bytes() const {
     size_t s = 0;
     for (auto& kv : bufs_) s += kv.second.size();
+    for (auto& b : retired_) s += b.size();
     return s;
   }
   void clear() {
     bufs_.clear();
     host_.clear();
+    retired_.clear();
+    retired_host_.clear();
   }
 
  private:
   std::map<int, DevBuf> bufs_;
   std::map<int, HostBuf> host_;
+  std::vector<DevBuf> retired_;
+  std::vector<HostBuf> retired_host_;
 };
 
 // One workspace per (device, stream) for the standalone entry points.
