@@ -1082,8 +1082,46 @@ size_t host_threads() {
 
 }  // namespace
 
+TaskPool::TaskPool(int nthreads) {
+  for (int t = 0; t < nthreads; t++)
+    threads_.emplace_back([this] {
+      for (;;) {
+        std::packaged_task<void()> task;
+        {
+          std::unique_lock<std::mutex> lock(mu_);
+          cv_.wait(lock, [this] { return stop_ || !queue_.empty(); });
+          if (queue_.empty()) return;  // stopping with nothing left to run
+          task = std::move(queue_.front());
+          queue_.pop_front();
+        }
+        task();
+      }
+    });
+}
+
+TaskPool::~TaskPool() {
+  {
+    std::lock_guard<std::mutex> lock(mu_);
+    stop_ = true;
+  }
+  cv_.notify_all();
+  for (auto& t : threads_) t.join();
+}
+
+std::future<void> TaskPool::run(std::function<void()> fn) {
+  std::packaged_task<void()> task(std::move(fn));
+  std::future<void> f = task.get_future();
+  {
+    std::lock_guard<std::mutex> lock(mu_);
+    queue_.push_back(std::move(task));
+  }
+  cv_.notify_one();
+  return f;
+}
+
 ProveCtx::ProveCtx() {
   device = current_device();
+  pool.reset(new TaskPool(4));
   for (int lane = 0; lane < LANES; lane++) ZK_HIP(hipStreamCreateWithFlags(&lanes[lane], hipStreamNonBlocking));
   ZK_HIP(hipStreamCreateWithFlags(&graph_stream, hipStreamNonBlocking));
   for (ProveGen& g : gen) {
@@ -1330,8 +1368,8 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
   if (capture) {
     g2_lane();
   } else {
-    f_g2 = std::async(std::launch::async, g2_lane);
-    f_g1 = std::async(std::launch::async, g1_lane);
+    f_g2 = ctx.pool->run(g2_lane);
+    f_g1 = ctx.pool->run(g1_lane);
   }
   auto join_helpers = [&] {
     if (f_g2.valid()) f_g2.wait();
@@ -1405,6 +1443,7 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
   if (capture) {
     g1_lane();
   } else {
+    join_helpers();  // both finished before either error is rethrown
     f_g2.get();
     f_g1.get();
   }
@@ -1437,7 +1476,7 @@ void prove_batch_finish(ProveCtx& ctx, BatchRun& R) {
   std::vector<std::vector<size_t>> g1_of(nj), g2_of(nj);
   for (size_t q = 0; q < own_g1.size(); q++) g1_of[own_g1[q]].push_back(q);
   for (size_t q = 0; q < own_g2.size(); q++) g2_of[own_g2[q]].push_back(q);
-  auto f_g1 = std::async(std::launch::async, [&] {
+  auto f_g1 = ctx.pool->run([&] {
     ZK_HIP(hipEventSynchronize(G.done_ev[ProveCtx::LANE_G1]));
     parallel_for(nj, nthr, [&](size_t j) {
       const ProveJob& J = jobs[j];
@@ -1462,7 +1501,7 @@ void prove_batch_finish(ProveCtx& ctx, BatchRun& R) {
       o.L = msmL;
     });
   });
-  auto f_g2 = std::async(std::launch::async, [&] {
+  auto f_g2 = ctx.pool->run([&] {
     ZK_HIP(hipEventSynchronize(G.done_ev[ProveCtx::LANE_G2]));
     parallel_for(nj, nthr / 2 + 1, [&](size_t j) {
       uint64_t sw[4];
@@ -1472,10 +1511,19 @@ void prove_batch_finish(ProveCtx& ctx, BatchRun& R) {
       Bp[j] = host::G2J::add(host::G2J::add(jobs[j].pk->beta2, msmB2), jobs[j].pk->delta2_table.mul(sw));
     });
   });
-  auto f_h = std::async(std::launch::async, [&] {
+  auto f_h = ctx.pool->run([&] {
     ZK_HIP(hipEventSynchronize(G.done_ev[ProveCtx::LANE_H]));
     parallel_for(own_h.size(), nthr / 2 + 1, [&](size_t q) { Hp[own_h[q]] = msm_finish_g1(pend_h[q]); });
   });
+  // the pool's futures do not wait when destroyed: wait for the lane tasks
+  // (they use this frame) before leaving it, also when an error unwinds it
+  struct WaitAll {
+    std::future<void>* f[3];
+    ~WaitAll() {
+      for (auto* x : f)
+        if (x->valid()) x->wait();
+    }
+  } wait_all{{&f_g1, &f_g2, &f_h}};
   ZK_HIP(hipEventSynchronize(G.ev[2]));  // quotients and the tail flag
   if (*R.flag_host) throw Error(ZKVC_EDEVICE, "internal error: a witness does not satisfy its circuit");
   for (int lane = 0; lane < ProveCtx::LANES; lane++) ZK_HIP(hipEventSynchronize(G.done_ev[lane]));

@@ -2,9 +2,14 @@
 // setup / prove drivers.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <condition_variable>
 #include <cstdint>
+#include <deque>
+#include <functional>
+#include <future>
 #include <memory>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "host_field.hpp"
@@ -89,6 +94,25 @@ struct ProveGen {
   std::vector<int> graph_prof;       // profiling slots recorded by the graph
 };
 
+// A few persistent host threads for a context's concurrent host work (the
+// lane enqueues of a batch's begin, the per-lane combination of its finish),
+// so that no thread is created per proof.  Tasks must not wait for each other.
+class TaskPool {
+ public:
+  explicit TaskPool(int nthreads);
+  ~TaskPool();
+  TaskPool(const TaskPool&) = delete;
+  TaskPool& operator=(const TaskPool&) = delete;
+  std::future<void> run(std::function<void()> fn);
+
+ private:
+  std::vector<std::thread> threads_;
+  std::deque<std::packaged_task<void()>> queue_;
+  std::mutex mu_;
+  std::condition_variable cv_;
+  bool stop_ = false;
+};
+
 // Device and host state for proving: the three MSM lanes (streams) and two
 // generations of per-batch resources, so that a batch can be enqueued while
 // the previous one is still on the device (continuous batching).  A proving
@@ -107,6 +131,7 @@ struct ProveCtx {
   bool graphs = true;  // capture and replay repeated compositions
   hipStream_t lanes[LANES] = {};
   hipStream_t graph_stream = nullptr;  // captures and replays run here, ordered after the calling stream
+  std::unique_ptr<TaskPool> pool;      // helper threads (at most three tasks at a time)
   ProveGen gen[GENS];
   zkvc_prove_stats last{};
 };
