@@ -84,8 +84,10 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def roofline(stats, workload=None):
-    """Roofline entry for the kernel with the most device time."""
+def roofline(stats, workload=None, measured=None):
+    """Roofline entry for the kernel with the most device time (peak: the
+    nominal 64 lane-ops per compute unit per clock at 2.4 GHz; beside it the
+    fraction of the microbenchmark's measured rate, if given)."""
     modeled = {k: v for k, v in stats.items() if k in FMUL_PER_UNIT} or stats
     if not modeled:
         return None, None
@@ -98,11 +100,16 @@ def roofline(stats, workload=None):
     achieved = mad_per_launch / (avg_ms * 1e-3) / 1e12
     peak = PEAK_MAD / 1e12
     traffic = recorded_traffic(name, workload) if workload else None
-    return name, {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
-                  "unit": "T u32-MAD/s", "frac": round(achieved / peak, 4),
-                  "traffic": None if traffic is None else round(traffic),
-                  "kernel": name, "launches": launches, "avg_launch_ms": round(avg_ms, 4),
-                  "work_units_per_launch": work / launches}
+    out = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
+           "unit": "T u32-MAD/s", "frac": round(achieved / peak, 4),
+           "traffic": None if traffic is None else round(traffic),
+           "kernel": name, "launches": launches, "avg_launch_ms": round(avg_ms, 4),
+           "work_units_per_launch": work / launches,
+           "timing": "HIP events around each launch on its stream (includes waiting behind other streams)"}
+    if measured:
+        out["measured_peak"] = round(measured / 1e12, 3)
+        out["frac_vs_measured_peak"] = round(achieved * 1e12 / measured, 4)
+    return name, out
 
 
 def time_proofs(zk, pk, X, W, r, s, steps, warmup, profile):
@@ -204,26 +211,10 @@ def ntt_rate(zk, log_n, seed=0, reps=5):
     return out
 
 
-BATCH_N = (64, 128, 320)
-BATCH_B = (64, 256, 512)
-
-
-def batch_jobs(seed, count):
-    """(n, b) per job from stream 10 over the 9 classes; X, W of job j from seed 1000*seed + j + 1."""
-    raw = synth.rng(seed, synth.STREAM_SHAPES).bit_generator.random_raw(count)
-    shapes = [(49, BATCH_N[int(w % 9) // 3], BATCH_B[int(w % 9) % 3]) for w in raw]
-    jobs = []
-    for j, (a, n, b) in enumerate(shapes):
-        X, W = synth.matmul_inputs(1000 * seed + j + 1, a, n, b)
-        r, s = synth.prover_randomness(seed, job=j)
-        jobs.append(((a, n, b), X, W, r, s))
-    return jobs
-
-
 def batch_section(zk, seed, count=64, reps=3):
     """Throughput of batched CRPC+PSQ proving over mixed shapes (one key per shape class)."""
     import torch
-    jobs = batch_jobs(seed, count)
+    jobs = synth.batch_jobs(seed, count)
     tox = synth.toxic_waste(seed)
     z = synth.crpc_point(seed)
     keys = {}
@@ -251,7 +242,7 @@ def batch_section(zk, seed, count=64, reps=3):
     nset = zk.autotune(zk.TUNE_MSM_G1 | zk.TUNE_MSM_G2 | zk.TUNE_NTT, 12, 16)
     tune_s = time.perf_counter() - t0
     dt, lat, outs = timed()
-    ok = all(zk.verify(keys[sh].vk, X, Y, p) == 1 for (sh, X, W, r, s), (Y, p) in zip(jobs[:4], outs[:4]))
+    ok = verify_all(zk, [(keys[sh].vk, X, Y, p) for (sh, X, W, r, s), (Y, p) in zip(jobs, outs)])
     # the same jobs one by one, for comparison
     t0 = time.perf_counter()
     for pk, X, W, r, s in batch:
@@ -267,17 +258,26 @@ def batch_section(zk, seed, count=64, reps=3):
             "autotune": {"seconds": round(tune_s, 2), "settings": nset, "table": zk.tune_export().split("\n")[:-1]},
             "batch_latency_ms_max": round(max(lat) * 1e3, 3),
             "same_jobs_one_by_one_proofs_per_s": round(count / single_s, 2),
-            "setup_s_all_keys": round(setup_s, 3), "verified_sample": ok}
+            "setup_s_all_keys": round(setup_s, 3), "verified_all": ok}
 
 
 SERVE_RATES = (5, 20, 50, 100, 200, 2000)  # the last one overloads a one-at-a-time prover
 
 
-def serve_section(zk, seed, rates=SERVE_RATES, max_batch=64):
+def verify_all(zk, items, threads=16):
+    """zkvc_verify on every (vk, X, Y, proof), on host threads (the verifier is
+    host code; ctypes releases the interpreter lock during the call)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        return all(v == 1 for v in ex.map(lambda it: zk.verify(*it), items))
+
+
+def serve_section(zk, seed, rates=SERVE_RATES, max_batch=64, seconds=20.0, max_jobs=2000):
     """Poisson arrivals of CRPC+PSQ jobs over 10 shape classes (the batch mix plus the paper shape),
-    proved by the library's server; latency = submission to results written."""
+    proved by the library's server; latency = submission to results written.  Each rate runs
+    min(max_jobs, rate * seconds) jobs (at least 40)."""
     import torch
-    classes = [(49, n, b) for n in BATCH_N for b in BATCH_B] + [(49, 320, 512)]
+    classes = synth.served_classes()
     tox = synth.toxic_waste(seed)
     z = synth.crpc_point(seed)
     keys = {sh: zk.setup(*sh, zk.CRPC_PSQ, tox, z) for sh in classes}
@@ -297,89 +297,179 @@ def serve_section(zk, seed, rates=SERVE_RATES, max_batch=64):
         for t in [srv.submit(keys[big], *synth.matmul_inputs(seed, *big), 3, 5) for _ in range(8)]:
             srv.wait(t)
     out = {}
+    all_ok = True
     for lam in rates:
-        count = int(min(400, max(40, 4 * lam)))
-        gaps = synth.exponential_gaps(seed + lam, lam, count)
-        pick = synth.rng(seed + lam, synth.STREAM_SHAPES).bit_generator.random_raw(count)
-        jobs = []
-        for j in range(count):
-            sh = classes[int(pick[j] % len(classes))]
-            X, W = synth.matmul_inputs(10000 * seed + 1000 * lam + j + 1, *sh)
-            r, s = synth.prover_randomness(seed + lam, job=j)
-            jobs.append((keys[sh], X, W, r, s))
+        count = int(max(40, min(max_jobs, lam * seconds)))
+        gaps, jobs = synth.served_jobs(seed, lam, count)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         due = t0
         tickets = []
-        for j, job in enumerate(jobs):
+        for j, (sh, X, W, r, s) in enumerate(jobs):
             due += gaps[j]
             pause = due - time.perf_counter()
             if pause > 0:
                 time.sleep(pause)
-            tickets.append(srv.submit(*job))
-        res = [srv.wait(t)[2] for t in tickets]
+            tickets.append(srv.submit(keys[sh], X, W, r, s))
+        got = [srv.wait(t) for t in tickets]
         span = time.perf_counter() - t0
+        res = [g[2] for g in got]
+        ok = verify_all(zk, [(keys[sh].vk, X, g[0], g[1]) for (sh, X, W, r, s), g in zip(jobs, got)])
+        all_ok = all_ok and ok
         lat = sorted(r.latency_ms for r in res)
-        out[f"{lam}_req_s"] = {"jobs": count, "proofs_per_s": round(count / span, 2),
+        out[f"{lam}_req_s"] = {"jobs": count, "seconds": round(span, 2), "proofs_per_s": round(count / span, 2),
                                "p50_ms": round(lat[len(lat) // 2], 3),
                                "p99_ms": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 3),
                                "mean_batch": round(sum(r.batch_size for r in res) / count, 2),
-                               "max_batch": max(r.batch_size for r in res)}
-        log(f"served {lam} req/s: p50 {out[f'{lam}_req_s']['p50_ms']} ms, p99 {out[f'{lam}_req_s']['p99_ms']} ms")
+                               "max_batch": max(r.batch_size for r in res), "verified_all": ok}
+        log(f"served {lam} req/s: {count} jobs, p50 {out[f'{lam}_req_s']['p50_ms']} ms, "
+            f"p99 {out[f'{lam}_req_s']['p99_ms']} ms")
     srv.close()
     for pk in keys.values():
         pk.close()
     return {"workload": "Poisson arrivals of CRPC+PSQ proof jobs, shapes uniform over 10 classes: a=49, (n, b) in "
                         "{64,128,320}x{64,256,512} and (320, 512); keys resident in HBM; one server, continuous "
-                        f"batching (max {max_batch} per batch); latency = submission to proof on the host",
-            "rates": out}
+                        f"batching (max {max_batch} per batch); latency = submission to proof on the host; each "
+                        f"rate runs min({max_jobs}, {seconds:g} s x rate) jobs, at least 40",
+            "rates": out, "verified_all": all_ok}
 
 
-def cpu_baseline(X, W, tox, z, r, s, budget_frac=256):
-    """The oracle prover's cost for one CRPC + PSQ proof of the paper shape.
+TABLE2_KINDS = (("PLAIN_ADD", "no CRPC, no PSQ"), ("PLAIN_PSQ", "no CRPC, PSQ"), ("CRPC", "CRPC, no PSQ"),
+                ("CRPC_PSQ", "CRPC, PSQ"))
 
-    Measured: witness and evaluation vectors, and the full QAP quotient (seven
-    transforms of 2^16 points by the oracle's recursive FFT).  Sampled: every
-    multi-scalar sum of the proof on 1/budget_frac of its terms (with the
-    proof's own scalars; double-and-add cost does not depend on the base), its
-    time scaled by the sampling factor.  Single-threaded Python.
-    """
+
+def table2_section(zk, seed, shapes=((49, 64, 128), (49, 320, 512)), steps=5):
+    """The four rows of the paper's Table II ablation (groth16 columns) proved on the GPU."""
+    X0 = {}
+    out = {}
+    tox = synth.toxic_waste(seed)
+    z = synth.crpc_point(seed)
+    r, s = synth.prover_randomness(seed)
+    for sh in shapes:
+        X, W = synth.matmul_inputs(seed, *sh)
+        X0[sh] = (X, W)
+        row = {}
+        for name, label in TABLE2_KINDS:
+            kind = getattr(zk, name)
+            log(f"Table II {name} {sh}")
+            pk = zk.setup(*sh, kind, tox, z if name.startswith("CRPC") else None)
+            info = pk.info()
+            zk.prove(pk, X, W, r, s)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                Y, proof = zk.prove(pk, X, W, r, s)
+            dt = (time.perf_counter() - t0) / steps
+            ok = zk.verify(pk.vk, X, Y, proof) == 1
+            row[name] = {"ablation_row": label, "ms_per_proof": round(dt * 1e3, 3),
+                         "proofs_per_s": round(1 / dt, 2), "qap_domain_log2": info.log_n,
+                         "a_query": info.a_query, "l_query": info.l_query, "verified": ok}
+            pk.close()
+        out[f"{sh[0]}x{sh[1]}x{sh[2]}"] = row
+    out["paper_context"] = {"note": "Table II groth16 prove times on a 16-core Threadripper PRO 3955WX (CPU, other "
+                                    "hardware; shape of the microbenchmark inferred as [49,64]x[64,128])",
+                            "PLAIN_ADD_s": 9.12, "PLAIN_PSQ_s": 8.69, "CRPC_s": 1.01, "CRPC_PSQ_s": 0.73}
+    return out
+
+
+_CPU = {}
+
+
+def _cpu_msm_part(job):
+    """One chunk of a multi-scalar sum by the oracle's double-and-add (bases cycled)."""
     from oracle import bn254 as bn
-    from oracle import qap, r1cs
-    sh = r1cs.Shape(*SHAPE)
+    name, group, lo, hi = job
+    sc = _CPU[name][lo:hi]
+    bases = _CPU["bases1"] if group == 1 else _CPU["bases2"]
+    pts = [bases[k % len(bases)] for k in range(lo, hi)]
+    return (bn.g1_msm if group == 1 else bn.g2_msm)(pts, sc)
+
+
+def _cpu_quotient(_):
+    from oracle import qap
+    return qap.quotient_coset(_CPU["aev"], _CPU["bev"], _CPU["cev"])
+
+
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(X, W, tox, z, r, s, workers=None, chunk=2048):
+    """The oracle prover, unmodified, for one CRPC + PSQ proof of the paper shape
+    on every host core: witness and evaluation vectors, the QAP quotient (seven
+    transforms of 2^16 by the oracle's recursive FFT, in one process), and the
+    five multi-scalar sums A, B1, B2, L, H over all their terms by the oracle's
+    double-and-add, split into chunks over a process pool and the chunk sums
+    added, then the assembly's scalar multiplications.  Nothing is sampled.
+    The proving key's bases are stood in for by 8 fixed points cycled (the
+    cost of double-and-add does not depend on the base), which saves the
+    oracle's key generation (about an hour of Python)."""
+    import multiprocessing as mp
+    import platform
+    from oracle import bn254 as bn
+    from oracle import r1cs
+    workers = workers or len(os.sched_getaffinity(0))
+    sh = r1cs.Shape(*synth.PAPER_SHAPE)
     kind = r1cs.CRPC_PSQ
     Xl, Wl = X.astype(int).tolist(), W.astype(int).tolist()
-    t0 = time.perf_counter()
+    t_start = time.perf_counter()
     a, _ = r1cs.assignment(sh, kind, Xl, Wl, z)
     aev, bev, cev = r1cs.eval_vectors(sh, kind, a, z)
-    t_wit = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    h = qap.quotient_coset(aev, bev, cev)
-    t_qap = time.perf_counter() - t0
+    t_wit = time.perf_counter() - t_start
     ell = r1cs.num_public(sh)
     w0 = r1cs.first_witness(sh)
-    bases1 = [bn.g1_mul(bn.G1_GEN, 1000 + k) for k in range(8)]
-    bases2 = [bn.g2_mul(bn.G2_GEN, 1000 + k) for k in range(8)]
-    msms = [("A", a[:ell + 1], 1), ("B1", a[w0:w0 + sh.n * sh.b], 1), ("B2", a[w0:w0 + sh.n * sh.b], 2),
-            ("L", a[w0:], 1), ("H", h, 1)]
-    t_msm = 0.0
-    for name, scalars, group in msms:
-        sample = scalars[::budget_frac]
-        pts = [(bases1 if group == 1 else bases2)[k % 8] for k in range(len(sample))]
-        t0 = time.perf_counter()
-        if group == 1:
-            bn.g1_msm(pts, sample)
-        else:
-            bn.g2_msm(pts, sample)
-        t_msm += (time.perf_counter() - t0) * len(scalars) / max(len(sample), 1)
-    total = t_wit + t_qap + t_msm
-    return {"value": round(1.0 / total, 6), "unit": "proofs/s", "cores": 1, "kind": "oracle",
-            "sample": (f"CRPC+PSQ proof of [49,320]x[320,512]: witness, evaluation vectors and the QAP "
-                       f"quotient (7 transforms of 2^16) measured in full ({t_wit + t_qap:.1f} s); each of "
-                       f"the five multi-scalar sums (A, B1, B2, L, H) run by double-and-add on every "
-                       f"{budget_frac}th term and scaled up ({t_msm:.1f} s extrapolated); single-threaded "
-                       f"Python on this host"),
-            "seconds_per_proof": round(total, 2)}
+    _CPU.update({"A": a[:ell + 1], "BW": a[w0:w0 + sh.n * sh.b], "L": a[w0:], "aev": aev, "bev": bev, "cev": cev,
+                 "bases1": [bn.g1_mul(bn.G1_GEN, 1000 + k) for k in range(8)],
+                 "bases2": [bn.g2_mul(bn.G2_GEN, 1000 + k) for k in range(8)]})
+    parts = {}
+    try:
+        with mp.get_context("fork").Pool(workers) as pool:
+            hq = pool.map_async(_cpu_quotient, [0])
+            jobs = []
+            for name, key, group in (("A", "A", 1), ("B1", "BW", 1), ("B2", "BW", 2), ("L", "L", 1)):
+                n = len(_CPU[key])
+                jobs += [((name, key, group), lo, min(n, lo + chunk)) for lo in range(0, n, chunk)]
+            res = pool.map_async(_cpu_msm_part, [(key, g, lo, hi) for (nm, key, g), lo, hi in jobs])
+            h = hq.get()[0]
+            t_qap = time.perf_counter() - t_start - t_wit
+            _CPU["H"] = h
+            hjobs = [("H", "H", 1, lo, min(len(h), lo + chunk)) for lo in range(0, len(h), chunk)]
+            # the H chunks see the quotient: a second pool forked after it exists
+            with mp.get_context("fork").Pool(workers) as pool2:
+                hres = pool2.map(_cpu_msm_part, [(key, g, lo, hi) for nm, key, g, lo, hi in hjobs])
+            for ((nm, key, g), lo, hi), v in zip(jobs, res.get()):
+                parts.setdefault(nm, []).append(v)
+            parts["H"] = hres
+    finally:
+        _CPU.clear()
+    sums = {nm: None for nm in parts}
+    for nm, vs in parts.items():
+        add = bn.g2_add if nm == "B2" else bn.g1_add
+        for v in vs:
+            sums[nm] = add(sums[nm], v)
+    # assembly: A + r delta1, B + s delta2, B1 + s delta1, C = L + H + s A + r B1 - r s delta1
+    d1, d2 = bn.g1_mul(bn.G1_GEN, 7), bn.g2_mul(bn.G2_GEN, 7)
+    A = bn.g1_add(sums["A"], bn.g1_mul(d1, r))
+    bn.g2_add(sums["B2"], bn.g2_mul(d2, s))
+    B1 = bn.g1_add(sums["B1"], bn.g1_mul(d1, s))
+    C = bn.g1_add(bn.g1_add(sums["L"], sums["H"]), bn.g1_add(bn.g1_mul(A, s), bn.g1_mul(B1, r)))
+    bn.g1_add(C, bn.g1_neg(bn.g1_mul(d1, r * s % bn.R)))
+    total = time.perf_counter() - t_start
+    nterms = {nm: sum(1 for _ in vs) for nm, vs in parts.items()}
+    return {"value": round(1.0 / total, 6), "unit": "proofs/s", "cores": workers, "kind": "oracle",
+            "sample": (f"one whole CRPC+PSQ proof of [49,320]x[320,512], nothing sampled: witness and evaluation "
+                       f"vectors ({t_wit:.1f} s, one process), QAP quotient (7 transforms of 2^16, one process, "
+                       f"{t_qap:.1f} s) overlapped with the A, B1, B2, L multi-scalar sums, then the H sum; all "
+                       f"five sums by double-and-add over every term, in chunks of {chunk} on a pool of {workers} "
+                       f"processes; bases cycled over 8 fixed points"),
+            "seconds_per_proof": round(total, 2), "cpu_model": cpu_model(),
+            "python": platform.python_version(), "msm_chunks": nterms}
 
 
 def main():
@@ -395,6 +485,11 @@ def main():
     ap.add_argument("--no-msm", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-table2", action="store_true")
+    ap.add_argument("--no-valu-peak", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="arrivals per served rate: min(--serve-max-jobs, rate x this), at least 40")
+    ap.add_argument("--serve-max-jobs", type=int, default=2000)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first copy this many MiB device to device (a known-size kernel for counter calibration)")
     args = ap.parse_args()
@@ -416,6 +511,10 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy of {args.calib_copy_mb} MiB done")
         del src, dst
+    valu = None
+    if not args.no_valu_peak:
+        log("integer-VALU peak microbenchmark (v_mad_u64_u32)")
+        valu = zkvc.valu_peak()
     a, n, b = SHAPE
     seed = args.seed
     X, W = synth.matmul_inputs(seed, a, n, b)
@@ -443,7 +542,9 @@ def main():
                 "msm_all_concurrent": round(st.msm_ms, 3), "host_windows_and_assembly": round(st.host_ms, 3),
                 "total_wall": round(st.total_ms, 3)}
     pk.close()
-    dom_name, roof = roofline(stats, "crpc_psq_49x320x512" if main_kind == zkvc.CRPC_PSQ else "plain_49x320x512")
+    mpeak = valu["mad_per_s"] if valu else None
+    dom_name, roof = roofline(stats, "crpc_psq_49x320x512" if main_kind == zkvc.CRPC_PSQ else "plain_49x320x512",
+                              mpeak)
     lat_ms = sorted(x * 1e3 for x in lat)
     ms_per_step = total / args.steps * 1e3
     out = {
@@ -472,6 +573,12 @@ def main():
                                  "value above uses the default eager launches on three streams"},
         "setup_s": round(setup_crpc_s, 3),
         "roofline": roof,
+        "valu_peak": None if valu is None else {
+            "what": "v_mad_u64_u32 microbenchmark (zkvc_valu_peak): 8 blocks of 256 threads per CU, 16 "
+                    "independent multiply-add chains per thread",
+            "t_mad_per_s": round(valu["mad_per_s"] / 1e12, 3), "clock_ghz": round(valu["clock_ghz"], 3),
+            "lane_ops_per_cu_clk": round(valu["lane_ops_per_cu_clk"], 2), "compute_units": valu["compute_units"],
+            "nominal_t_mad_per_s": round(PEAK_MAD / 1e12, 3)},
         "kernels_warmup": {k: {"launches": v[0], "total_ms": round(v[1], 3)} for k, v in
                            sorted(stats_warm.items(), key=lambda kv: -kv[1][1])},
     }
@@ -486,7 +593,7 @@ def main():
         Yp, pp = zkvc.prove(pkp, X, W, r, s)
         okp = zkvc.verify(pkp.vk, X, Yp, pp) == 1
         pkp.close()
-        name_p, roof_p = roofline(statsp, "plain_49x320x512")
+        name_p, roof_p = roofline(statsp, "plain_49x320x512", mpeak)
         out["plain"] = {"workload": "same matmul, per-product circuit: 8,028,160 constraints, QAP domain 2^23",
                         "proofs_per_s": round(steps_p / tp, 3), "ms_per_proof": round(tp / steps_p * 1e3, 3),
                         "setup_s": round(setup_plain, 3), "verified": okp, "roofline": roof_p,
@@ -520,11 +627,15 @@ def main():
         out["batched_crpc_psq_64"] = batch_section(zkvc, seed)
     if not args.no_serve:
         log("served proving: Poisson arrivals")
-        out["served_crpc_psq"] = serve_section(zkvc, seed)
+        out["served_crpc_psq"] = serve_section(zkvc, seed, seconds=args.serve_seconds,
+                                               max_jobs=args.serve_max_jobs)
+    if not args.no_table2:
+        log("Table II ablation rows")
+        out["table2_gpu"] = table2_section(zkvc, seed)
     out["paper_context"] = {"note": "the paper's CPU figures, other hardware (16-core Threadripper PRO 3955WX)",
                             "plain_prove_s_49x320x512": 180, "crpc_psq_prove_s_49x64x128_table2": 0.73}
     if not args.no_cpu_baseline:
-        log("CPU oracle baseline (bounded sample)")
+        log("CPU oracle baseline (one whole proof on every host core)")
         out["cpu_baseline"] = cpu_baseline(X, W, tox, z, r, s)
     print(json.dumps(out), flush=True)
     return 0

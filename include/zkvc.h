@@ -200,8 +200,10 @@ int zkvc_verify(const uint8_t* vk, size_t vk_len, const int8_t* X, const int32_t
 int zkvc_ntt_fr(void* d_data, uint32_t log_n, uint32_t flags, void* hip_stream);
 
 /*
- * Multi-scalar multiplication sum_i s_i P_i over G1 (Groth16's A, B1, L and H
- * queries).  d_points: n affine points (16 words each); d_scalars: n Fr
+ * Multi-scalar multiplication sum_i s_i P_i over G1: the operation that
+ * Groth16's Prove (Section II; the backend of Section IV) spends its time on,
+ * computing the A, B1, L and H query sums of the proof from the witness and
+ * the quotient coefficients.  d_points: n affine points (16 words each); d_scalars: n Fr
  * elements (8 words each); both in device memory.  Points must lie on the
  * curve (the all-zero encoding, infinity, is allowed); scalars must be < r.
  * The result is written to *out (host).  n = 0 gives infinity.
@@ -210,8 +212,11 @@ int zkvc_ntt_fr(void* d_data, uint32_t log_n, uint32_t flags, void* hip_stream);
 int zkvc_msm_g1(const void* d_points, const void* d_scalars, size_t n, uint32_t flags, zkvc_g1* out,
                 void* hip_stream);
 
-/* As zkvc_msm_g1 over G2 (Groth16's B query); points are 32 words each and
- * must lie in the order-r subgroup of the twist. */
+/* As zkvc_msm_g1 over G2: the B query sum of Groth16's Prove (Section II),
+ * the proof's G2 element.  d_points: n affine points of 32 words each
+ * (x0, x1, y0, y1), which must lie in the order-r subgroup of the twist;
+ * d_scalars as for zkvc_msm_g1.  The result is written to *out (host).
+ * n = 0 gives infinity.  Errors: ZKVC_EINVAL, ZKVC_ENOMEM, ZKVC_EDEVICE. */
 int zkvc_msm_g2(const void* d_points, const void* d_scalars, size_t n, uint32_t flags, zkvc_g2* out,
                 void* hip_stream);
 
@@ -326,6 +331,29 @@ int zkvc_profile_read(zkvc_kernel_stat* out, int capacity, int* count);
  * enqueued afterwards.  Host only; ZKVC_EINVAL if the list is 4096 bytes or
  * longer. */
 int zkvc_profile_select(const char* kernels);
+
+/*
+ * Integer-VALU peak microbenchmark.  Every field product of the prover is a
+ * column of 32x32 -> 64-bit multiply-adds (v_mad_u64_u32), so the rate at
+ * which the device issues that instruction is the roofline of the bucket
+ * accumulation and NTT kernels.  Runs 8 blocks of 256 threads per compute
+ * unit, each thread 16 independent multiply-add chains of 4 * iters steps,
+ * on hip_stream (one warm-up launch, one timed with HIP events), and reports:
+ * the multiply-adds executed and their rate over the timed launch; the shader
+ * clock during the loop (clock counter against the constant-rate counter);
+ * and lane operations per compute unit per clock (64 would be one wave64
+ * instruction per cycle per compute unit).  1 <= iters <= 2^20.
+ * Errors: ZKVC_EINVAL, ZKVC_ENOMEM, ZKVC_EDEVICE.
+ */
+typedef struct {
+  double mads;                /* multiply-adds executed by the timed launch */
+  double ms;                  /* its duration (HIP events) */
+  double mad_per_s;           /* mads / duration */
+  double clock_ghz;           /* average shader clock over the blocks' loops */
+  double lane_ops_per_cu_clk; /* mad_per_s / (compute units * clock) */
+  uint32_t compute_units;
+} zkvc_valu_peak_t;
+int zkvc_valu_peak(uint32_t iters, zkvc_valu_peak_t* out, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -65,17 +65,22 @@ int zkvc_prove(const zkvc_pk* pk, const int8_t* X, const int8_t* W, const zkvc_f
 }
 
 namespace {
-// One batch context per (device, stream), created on first use.
+// One batch context per (device, stream), created on first use and kept until
+// the process ends.  The table is never destroyed: a context's destructor
+// synchronizes and destroys streams and events, and a static destructor
+// would run those HIP calls during exit(), after the runtime (and a profiler
+// attached to it) has begun tearing down, which aborts the process.  The
+// operating system reclaims the memory.
 struct BatchCtxEntry {
   std::mutex mu;
   std::unique_ptr<ProveCtx> ctx;
 };
 BatchCtxEntry& batch_ctx(int dev, hipStream_t st) {
-  static std::mutex mu;
-  static std::map<std::pair<int, hipStream_t>, std::unique_ptr<BatchCtxEntry>> table;
-  std::lock_guard<std::mutex> lock(mu);
-  auto& e = table[{dev, st}];
-  if (!e) e.reset(new BatchCtxEntry());
+  static std::mutex* mu = new std::mutex();
+  static auto* table = new std::map<std::pair<int, hipStream_t>, BatchCtxEntry*>();
+  std::lock_guard<std::mutex> lock(*mu);
+  BatchCtxEntry*& e = (*table)[{dev, st}];
+  if (!e) e = new BatchCtxEntry();
   return *e;
 }
 }  // namespace

@@ -1059,7 +1059,58 @@ std::vector<Slot> enqueue_witness_batch(const ProveJob* jobs, size_t nj, ProveGe
   return slots;
 }
 
-// Runs fn(i) for i < n on up to `threads` host threads.
+// A process-wide set of persistent host threads for the data-parallel host
+// loops of a batch (plane combination and assembly per proof), so that no
+// thread is created per batch.  Created on first use and never destroyed
+// (its threads wait on a condition variable until the process ends).
+class HostPool {
+ public:
+  explicit HostPool(size_t nthreads) {
+    for (size_t t = 0; t < nthreads; t++)
+      std::thread([this] {
+        for (;;) {
+          std::function<void()> task;
+          {
+            std::unique_lock<std::mutex> lock(mu_);
+            cv_.wait(lock, [this] { return !queue_.empty(); });
+            task = std::move(queue_.front());
+            queue_.pop_front();
+          }
+          task();
+        }
+      }).detach();
+  }
+  void post(std::function<void()> fn) {
+    {
+      std::lock_guard<std::mutex> lock(mu_);
+      queue_.push_back(std::move(fn));
+    }
+    cv_.notify_one();
+  }
+
+ private:
+  std::deque<std::function<void()>> queue_;
+  std::mutex mu_;
+  std::condition_variable cv_;
+};
+
+size_t host_threads() {
+  const unsigned hc = std::thread::hardware_concurrency();
+  return hc ? std::min<size_t>(16, std::max<size_t>(1, hc / 2)) : 4;
+}
+
+HostPool& host_pool() {
+  static HostPool* p = new HostPool(host_threads());
+  return *p;
+}
+
+// Runs fn(i) for i < n on the calling thread plus up to threads - 1 helpers
+// of the host pool.  Indices are claimed from a shared counter; the caller
+// works too, so the call completes even if every helper is busy elsewhere,
+// and it waits only for helpers that have started (a helper that starts
+// after the loop has closed returns at once).  The first exception thrown by
+// fn is rethrown on the calling thread after every started helper has
+// stopped (indices not yet claimed are then skipped).
 template <class Fn>
 void parallel_for(size_t n, size_t threads, Fn&& fn) {
   threads = std::max<size_t>(1, std::min(threads, n));
@@ -1067,17 +1118,41 @@ void parallel_for(size_t n, size_t threads, Fn&& fn) {
     for (size_t i = 0; i < n; i++) fn(i);
     return;
   }
-  std::vector<std::future<void>> fs;
-  for (size_t t = 0; t < threads; t++)
-    fs.push_back(std::async(std::launch::async, [&, t] {
-      for (size_t i = t; i < n; i += threads) fn(i);
-    }));
-  for (auto& f : fs) f.get();
-}
-
-size_t host_threads() {
-  const unsigned hc = std::thread::hardware_concurrency();
-  return hc ? std::min<size_t>(16, std::max<size_t>(1, hc / 2)) : 4;
+  struct State {
+    std::atomic<size_t> next{0};
+    std::mutex mu;
+    std::condition_variable cv;
+    bool closed = false;
+    int active = 0;
+    std::exception_ptr err;
+  };
+  auto st = std::make_shared<State>();
+  std::function<void(size_t)> body = [&fn](size_t i) { fn(i); };
+  auto work = [st, n, &body] {
+    try {
+      for (size_t i; (i = st->next.fetch_add(1)) < n;) body(i);
+    } catch (...) {
+      st->next.store(n);
+      std::lock_guard<std::mutex> lock(st->mu);
+      if (!st->err) st->err = std::current_exception();
+    }
+  };
+  for (size_t t = 1; t < threads; t++)
+    host_pool().post([st, work] {
+      {
+        std::lock_guard<std::mutex> lock(st->mu);
+        if (st->closed) return;
+        st->active++;
+      }
+      work();
+      std::lock_guard<std::mutex> lock(st->mu);
+      if (--st->active == 0) st->cv.notify_all();
+    });
+  work();
+  std::unique_lock<std::mutex> lock(st->mu);
+  st->closed = true;
+  st->cv.wait(lock, [&] { return st->active == 0; });
+  if (st->err) std::rethrow_exception(st->err);
 }
 
 }  // namespace

@@ -79,6 +79,12 @@ class ServerResult(ctypes.Structure):
                 ("latency_ms", ctypes.c_double)]
 
 
+class ValuPeak(ctypes.Structure):
+    _fields_ = [("mads", ctypes.c_double), ("ms", ctypes.c_double), ("mad_per_s", ctypes.c_double),
+                ("clock_ghz", ctypes.c_double), ("lane_ops_per_cu_clk", ctypes.c_double),
+                ("compute_units", ctypes.c_uint32)]
+
+
 class ProveStats(ctypes.Structure):
     _fields_ = [("witness_ms", ctypes.c_float), ("ntt_ms", ctypes.c_float), ("msm_ms", ctypes.c_float),
                 ("host_ms", ctypes.c_float), ("total_ms", ctypes.c_float)]
@@ -114,6 +120,7 @@ _SIGS = {
     "zkvc_pk_export": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, _VP]),
     "zkvc_pk_last_stats": (ctypes.c_int, [_VP, ctypes.POINTER(ProveStats)]),
     "zkvc_field_op": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
+    "zkvc_valu_peak": (ctypes.c_int, [ctypes.c_uint32, ctypes.POINTER(ValuPeak), _VP]),
     "zkvc_profile_begin": (ctypes.c_int, []),
     "zkvc_profile_read": (ctypes.c_int, [ctypes.POINTER(KernelStat), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
 }
@@ -251,6 +258,13 @@ def set_graphs(enable):
     """Turn graph capture and replay of repeated proof compositions on or off
     (off by default); returns the previous setting."""
     return lib().zkvc_set_graphs(1 if enable else 0)
+
+
+def valu_peak(iters=4096, stream=None):
+    """The device's measured v_mad_u64_u32 rate (zkvc_valu_peak): a dict of its fields."""
+    out = ValuPeak()
+    _check(lib().zkvc_valu_peak(iters, ctypes.byref(out), _stream(stream)))
+    return {k: getattr(out, k) for k, _ in ValuPeak._fields_}
 
 
 def profile_begin():

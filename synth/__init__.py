@@ -108,3 +108,48 @@ def exponential_gaps(seed, rate, count):
     g = rng(seed, STREAM_ARRIVALS)
     u = (g.bit_generator.random_raw(count) >> np.uint64(11)).astype(np.float64) * 2.0**-53
     return -np.log1p(-u) / rate
+
+
+# ---------------------------------------------------------------- workload mixes
+# The paper's matmul shapes are [#tokens, dim1] x [dim1, dim2] with 49 tokens
+# (Section IV); the headline is [49, 320] x [320, 512] (Section I).
+TOKENS = 49
+PAPER_SHAPE = (49, 320, 512)
+BATCH_N = (64, 128, 320)
+BATCH_B = (64, 256, 512)
+
+
+def batch_jobs(seed, count):
+    """A batch of mixed-shape proof jobs: (shape, X, W, r, s) per job.
+
+    (n, b) of job j is class (word_j mod 9) of {64,128,320} x {64,256,512}
+    (stream 10), a = 49; X, W of job j come from seed 1000 seed + j + 1 and
+    (r, s) from prover_randomness(seed, job=j)."""
+    raw = rng(seed, STREAM_SHAPES).bit_generator.random_raw(count)
+    shapes = [(TOKENS, BATCH_N[int(w % 9) // 3], BATCH_B[int(w % 9) % 3]) for w in raw]
+    jobs = []
+    for j, (a, n, b) in enumerate(shapes):
+        X, W = matmul_inputs(1000 * seed + j + 1, a, n, b)
+        r, s = prover_randomness(seed, job=j)
+        jobs.append(((a, n, b), X, W, r, s))
+    return jobs
+
+
+def served_classes():
+    """The ten shape classes of served proving: the nine batch classes, then the paper shape."""
+    return [(TOKENS, n, b) for n in BATCH_N for b in BATCH_B] + [PAPER_SHAPE]
+
+
+def served_jobs(seed, rate, count):
+    """Poisson arrivals of proof jobs at `rate` per second over the served classes
+    (equal weights): (gaps in seconds, [(shape, X, W, r, s)])."""
+    classes = served_classes()
+    gaps = exponential_gaps(seed + rate, rate, count)
+    pick = rng(seed + rate, STREAM_SHAPES).bit_generator.random_raw(count)
+    jobs = []
+    for j in range(count):
+        sh = classes[int(pick[j] % len(classes))]
+        X, W = matmul_inputs(10000 * seed + 1000 * rate + j + 1, *sh)
+        r, s = prover_randomness(seed + rate, job=j)
+        jobs.append((sh, X, W, r, s))
+    return gaps, jobs

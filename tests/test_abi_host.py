@@ -43,6 +43,7 @@ def test_struct_layouts_match_header(zk):
     assert ctypes.sizeof(zk.ProveJob) == 104  # 3 pointers, 2 zkvc_fr, 2 pointers
     assert ctypes.sizeof(zk.ServerConfig) == 16
     assert ctypes.sizeof(zk.ServerResult) == 24
+    assert ctypes.sizeof(zk.ValuPeak) == 48  # 5 doubles, 1 uint32, padding
     text = open(HEADER).read()
     for name in ("ZKVC_PLAIN = 0", "ZKVC_CRPC_PSQ = 1", "ZKVC_PLAIN_ADD = 2", "ZKVC_PLAIN_PSQ = 3", "ZKVC_CRPC = 4"):
         assert name in text

@@ -87,6 +87,27 @@ def test_freivalds_check_accepts_and_rejects():
     assert not ntt.freivalds_check(x, bad, rho)
 
 
+def test_freivalds_parallel_agrees_with_plain_check():
+    """The chunked, batch-inverted evaluation decides like the plain one: it
+    accepts the DFT (computed by the O(N^2) definition) and rejects a single
+    changed output, a swapped pair and a transform on the wrong root."""
+    n = 64
+    x = _rand(n, 21)
+    X = ntt.dft(x, ntt.root_of_unity(n))
+    rho = 1234567890123456789
+    for workers in (1, 3):
+        assert ntt.freivalds_check_parallel(x, X, rho, workers)
+        bad = list(X)
+        bad[n - 1] = (bad[n - 1] + 5) % R
+        assert not ntt.freivalds_check_parallel(x, bad, rho, workers)
+        swapped = list(X)
+        swapped[3], swapped[4] = swapped[4], swapped[3]
+        assert not ntt.freivalds_check_parallel(x, swapped, rho, workers)
+        other = ntt.dft(x, pow(ntt.root_of_unity(n), 3, R))
+        assert not ntt.freivalds_check_parallel(x, other, rho, workers)
+    assert ntt.freivalds_check(x, X, rho)
+
+
 def test_lagrange_closed_form_matches_product_form():
     for n in (1, 2, 4, 16, 64):
         tau = 31415926535 + n
