@@ -334,6 +334,52 @@ def serve_section(zk, seed, rates=SERVE_RATES, max_batch=64, seconds=20.0, max_j
             "rates": out, "verified_all": all_ok}
 
 
+def spartan_section(zk, seed, steps=10, warmup=2):
+    """The Spartan backend (zkVC-S) on the GPU: CRPC+PSQ and CRPC at the paper shape and the
+    Table II shape.  The commitment generators are [k_j]G for seeded k_j (their discrete logarithms
+    are known, which serves measurement only: the cost does not depend on the generators)."""
+    import torch
+    out = {}
+    z = synth.crpc_point(seed)
+    for sh in ((49, 320, 512), (49, 64, 128)):
+        for name in ("CRPC_PSQ", "CRPC"):
+            kind = getattr(zk, name)
+            info = zk.spartan_info(*sh, kind)
+            ks = synth.fr_limbs(seed + 17, synth.STREAM_MSM_BASES, info.cols)
+            dk = torch.from_numpy(ks.view(np.int32).copy()).cuda()
+            pts = torch.zeros((info.cols * 16,), dtype=torch.int32, device="cuda")
+            zk.fixed_base_g1(dk, info.cols, pts)
+            words = pts.cpu().numpy().view(np.uint32).reshape(-1, 16)
+            ints = synth.limbs_to_ints(words.reshape(-1, 8))
+            gens = [(ints[2 * i], ints[2 * i + 1]) for i in range(info.cols)]
+            log(f"Spartan {name} {sh}")
+            key = zk.SpartanKey(*sh, kind, z, gens)
+            X, W = synth.matmul_inputs(seed, *sh)
+            for _ in range(warmup):
+                key.prove(X, W)
+            lat = []
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                t = time.perf_counter()
+                Y, proof = key.prove(X, W)
+                lat.append(time.perf_counter() - t)
+            dt = (time.perf_counter() - t0) / steps
+            tv = time.perf_counter()
+            ok = key.verify(X, Y, proof) == 1
+            verify_ms = (time.perf_counter() - tv) * 1e3
+            key.close()
+            lat.sort()
+            out[f"{name}_{sh[0]}x{sh[1]}x{sh[2]}"] = {
+                "ms_per_proof": round(dt * 1e3, 3), "proofs_per_s": round(1 / dt, 2),
+                "p50_ms": round(lat[len(lat) // 2] * 1e3, 3), "verify_ms_host": round(verify_ms, 2),
+                "proof_bytes": int(info.proof_bytes), "sumcheck_vars": [int(info.sx), int(info.sy)],
+                "commitment_rows_x_cols": [int(info.rows), int(info.cols)], "verified": ok}
+    out["paper_context"] = {"note": "Table II Spartan prove / verify on a 16-core Threadripper PRO 3955WX (CPU, "
+                                    "other hardware; shape inferred as [49,64]x[64,128])",
+                            "CRPC_PSQ_s": [1.75, 0.05], "CRPC_s": [1.79, 0.08]}
+    return out
+
+
 TABLE2_KINDS = (("PLAIN_ADD", "no CRPC, no PSQ"), ("PLAIN_PSQ", "no CRPC, PSQ"), ("CRPC", "CRPC, no PSQ"),
                 ("CRPC_PSQ", "CRPC, PSQ"))
 
@@ -486,6 +532,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-table2", action="store_true")
+    ap.add_argument("--no-spartan", action="store_true")
     ap.add_argument("--no-valu-peak", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="arrivals per served rate: min(--serve-max-jobs, rate x this), at least 40")
@@ -632,6 +679,9 @@ def main():
     if not args.no_table2:
         log("Table II ablation rows")
         out["table2_gpu"] = table2_section(zkvc, seed)
+    if not args.no_spartan:
+        log("Spartan backend (zkVC-S)")
+        out["spartan_zkvc_s"] = spartan_section(zkvc, seed)
     out["paper_context"] = {"note": "the paper's CPU figures, other hardware (16-core Threadripper PRO 3955WX)",
                             "plain_prove_s_49x320x512": 180, "crpc_psq_prove_s_49x64x128_table2": 0.73}
     if not args.no_cpu_baseline:

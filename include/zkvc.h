@@ -144,17 +144,21 @@ int zkvc_set_graphs(int enable);
 
 /*
  * Proving server (continuous batching).  One worker thread proves submitted
- * jobs in batches: each batch takes every queued job that fits max_batch and
- * memory_budget (bytes of estimated device workspace admitted at once; 0 = no
- * limit; a single job is always admitted), and is enqueued while the
- * previous batch is still on the device, so jobs that arrive during a batch
- * overlap it.  Every result equals zkvc_prove's for the same job, bit for bit.
- * The server is created on the current device and owns its own streams.
+ * jobs in batches: each batch takes the queued jobs in order while they fit
+ * max_batch and memory_budget, and is enqueued while the previous batch is
+ * still on the device, so jobs that arrive during a batch overlap it.
+ * memory_budget (bytes; 0 = no limit) bounds the estimated device workspace
+ * of the jobs in flight, the batch being admitted plus the one still on the
+ * device; a job's estimate is zkvc_pk_info().prove_bytes, and a job whose
+ * estimate alone exceeds the budget is rejected at submission.  Workspace
+ * buffers replaced by growth are freed when nothing is in flight.  Every
+ * result equals zkvc_prove's for the same job, bit for bit.  The server is
+ * created on the current device and owns its own streams.
  */
 typedef struct zkvc_server zkvc_server;
 typedef struct {
   uint32_t max_batch;      /* most proofs per batch, >= 1 */
-  uint64_t memory_budget;  /* bytes of estimated workspace per batch, 0 = unlimited */
+  uint64_t memory_budget;  /* bytes of estimated workspace in flight, 0 = unlimited */
 } zkvc_server_config;
 typedef struct {
   int32_t status;          /* ZKVC_OK, or the error code of the job's batch */
@@ -167,7 +171,8 @@ int zkvc_server_create(const zkvc_server_config* config, zkvc_server** server_ou
 /* Queues one job and returns its ticket.  X and W are copied before return;
  * Y_out and proof_out must stay valid until zkvc_server_wait returns for the
  * ticket.  Errors: ZKVC_EINVAL (null pointer, r or s >= r, key on another
- * device, server stopping). */
+ * device, server stopping), ZKVC_ENOMEM (the job's estimate exceeds the
+ * memory budget). */
 int zkvc_server_submit(zkvc_server* server, const zkvc_prove_job* job, uint64_t* ticket);
 /* Blocks until the job is done (results written), then reports it; each
  * ticket is reported once.  Errors: ZKVC_EINVAL (unknown ticket),
@@ -242,6 +247,7 @@ typedef struct {
   uint64_t num_public;  /* l: public inputs excluding the constant */
   uint64_t a_query, b_query, l_query, h_query;
   uint64_t device_bytes; /* proving key plus its proving workspace */
+  uint64_t prove_bytes;  /* estimated device workspace of one proof in a batch (server admission) */
 } zkvc_pk_info_t;
 int zkvc_pk_info(const zkvc_pk* pk, zkvc_pk_info_t* info);
 
@@ -331,6 +337,52 @@ int zkvc_profile_read(zkvc_kernel_stat* out, int capacity, int* count);
  * enqueued afterwards.  Host only; ZKVC_EINVAL if the list is 4096 bytes or
  * longer. */
 int zkvc_profile_select(const char* kernels);
+
+/* ---------------------------------------------------------------- Spartan (zkVC-S) */
+
+/*
+ * The paper's second backend, Spartan (Section II names it among the
+ * transparent SNARKs; Section IV uses it for zkVC-S; Table II times it beside
+ * Groth16), for the CRPC kinds (ZKVC_CRPC_PSQ, ZKVC_CRPC).  The paper fixes
+ * neither its commitment nor its curve; this implementation takes Spartan's
+ * NIZK with a verifier that evaluates the constraint matrices itself, over
+ * the BN254 scalar field, with the witness committed row by row by Pedersen
+ * commitments in G1 (square-root layout), without zero-knowledge blinding,
+ * and Fiat-Shamir by SHA-256.  The witness half of z (W entries, then the
+ * auxiliary values, zero-padded to 2^(sy-1)) is a rows x cols matrix; a proof
+ * is, all little-endian and canonical:
+ *   rows commitments (64 bytes each, affine x then y, all-zero = infinity),
+ *   sx rounds x 4 values of sum-check 1 (32 bytes each),
+ *   vA, vB, vC, sy rounds x 3 values of sum-check 2, and cols opening values.
+ * The caller supplies the commitment generators (cols points of G1, none at
+ * infinity); their discrete logarithms must be unknown to provers (e.g. a
+ * hash-to-curve), which the library cannot check.
+ */
+typedef struct zkvc_spartan_key zkvc_spartan_key; /* opaque, device-resident */
+typedef struct {
+  uint64_t constraints;   /* m: rows of the R1CS */
+  uint32_t sx, sy;        /* variables of the two sum-checks: 2^sx >= m rows, 2^sy entries of z */
+  uint32_t rows, cols;    /* the witness matrix; cols generators are needed */
+  uint64_t proof_bytes;
+} zkvc_spartan_info_t;
+/* Sizes of the Spartan instance of a shape (host only).  Errors: ZKVC_EINVAL
+ * (bad shape, or a kind other than the CRPC ones). */
+int zkvc_spartan_info(const zkvc_shape* shape, zkvc_spartan_info_t* out);
+/* Key for a shape: z (the public CRPC point, nonzero) and the cols
+ * generators (host, canonical affine).  Errors: ZKVC_EINVAL, ZKVC_ENOMEM,
+ * ZKVC_EDEVICE. */
+int zkvc_spartan_setup(const zkvc_shape* shape, const zkvc_fr* z, const zkvc_g1* gens, size_t ngens,
+                       zkvc_spartan_key** key_out, void* hip_stream);
+int zkvc_spartan_key_free(zkvc_spartan_key* key);
+/* Proves Y = X W (X, W host int8 row-major); writes Y (host int32) and the
+ * proof (proof_len must equal the info's proof_bytes).  Synchronous.  Calls
+ * with one key serialize.  Errors: ZKVC_EINVAL, ZKVC_ENOMEM, ZKVC_EDEVICE. */
+int zkvc_spartan_prove(zkvc_spartan_key* key, const int8_t* X, const int8_t* W, int32_t* Y_out, uint8_t* proof,
+                       size_t proof_len, void* hip_stream);
+/* Host verifier: 1 valid, 0 invalid (including a proof of the wrong length,
+ * values out of range or points off the curve), <0 for bad arguments. */
+int zkvc_spartan_verify(const zkvc_shape* shape, const zkvc_fr* z, const zkvc_g1* gens, size_t ngens,
+                        const int8_t* X, const int32_t* Y, const uint8_t* proof, size_t proof_len);
 
 /*
  * Integer-VALU peak microbenchmark.  Every field product of the prover is a

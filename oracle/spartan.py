@@ -335,3 +335,35 @@ def _eq_points(r, x):
         acc = acc * (rk * xk + (1 - rk) * (1 - xk)) % R
     return acc
 
+
+
+def proof_bytes(proof):
+    """The proof's byte encoding: commitments (64 bytes each), sum-check 1
+    values, vA vB vC, sum-check 2 values, opening values (32 bytes each)."""
+    out = b"".join(g1_bytes(c) for c in proof["comms"])
+    out += b"".join(fr_bytes(v) for g in proof["sc1"] for v in g)
+    out += b"".join(fr_bytes(v) for v in proof["vabc"])
+    out += b"".join(fr_bytes(v) for g in proof["sc2"] for v in g)
+    out += b"".join(fr_bytes(v) for v in proof["t"])
+    return out
+
+
+def proof_from_bytes(inst, data):
+    """Inverse of proof_bytes for the instance's sizes (None if the length is wrong)."""
+    need = inst.rows * 64 + (4 * inst.sx + 3 + 3 * inst.sy + inst.cols) * 32
+    if len(data) != need:
+        return None
+    pts = []
+    for i in range(inst.rows):
+        x = int.from_bytes(data[64 * i:64 * i + 32], "little")
+        y = int.from_bytes(data[64 * i + 32:64 * i + 64], "little")
+        pts.append(None if x == 0 and y == 0 else (x, y))
+    off = inst.rows * 64
+    vals = [int.from_bytes(data[off + 32 * k:off + 32 * k + 32], "little") for k in range((len(data) - off) // 32)]
+    sc1 = [vals[4 * j:4 * j + 4] for j in range(inst.sx)]
+    p = 4 * inst.sx
+    vabc = tuple(vals[p:p + 3])
+    p += 3
+    sc2 = [vals[p + 3 * j:p + 3 * j + 3] for j in range(inst.sy)]
+    p += 3 * inst.sy
+    return {"comms": pts, "sc1": sc1, "vabc": vabc, "sc2": sc2, "t": vals[p:p + inst.cols]}

@@ -136,14 +136,9 @@ int zkvc_pk_info(const zkvc_pk* pk, zkvc_pk_info_t* info) {
     info->b_query = total(L.segB);
     info->l_query = total(L.segL);
     info->h_query = L.N - 1;
-    size_t ctx_bytes = 0;
-    if (pk->ctx)
-      for (const ProveGen& g : pk->ctx->gen) {
-        for (const Workspace& w : g.lane_ws) ctx_bytes += w.bytes();
-        for (const auto& w : g.slot_ws) ctx_bytes += w->bytes();
-        ctx_bytes += g.shared.bytes();
-      }
+    const size_t ctx_bytes = pk->ctx ? pk->ctx->device_bytes() : 0;
     info->device_bytes = pk->key_bytes + pk->ws.bytes() + ctx_bytes;
+    info->prove_bytes = prove_footprint(L);
   });
 }
 

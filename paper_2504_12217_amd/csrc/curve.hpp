@@ -117,6 +117,91 @@ struct Xyzz {
   }
 };
 
+// ---------------------------------------------------------------- quad teams
+// Latency-bound steps (reduction trees, buckets with few entries) leave most
+// lanes idle while one addition's chain of dependent field products runs.
+// There, four consecutive lanes (a quad) hold the same operands and compute
+// one group operation together: per round each lane performs one of the
+// formula's independent field products, and a DPP quad broadcast
+// (quad_perm [k,k,k,k]) gives every lane all four results.  add-2008-s and
+// madd-2008-s then take 4 rounds of one product instead of 12 + 2 and 8 + 2
+// products in a chain.  Every branch inside is uniform over the quad (the
+// operands are the same in all four lanes), so the four lanes stay active
+// together, which the broadcast needs; the results are the same field
+// elements as the serial formulas' (a square is the product x x).
+// The broadcast stays a plain v_mov_b32_dpp: the empty asm statement takes
+// its result as an operand, so the compiler cannot fold the DPP read into the
+// instruction that consumes it (folded forms of the subtractions gave wrong
+// results on gfx950).
+template <int K>
+ZK_DEV uint32_t quad_bcast_u32(uint32_t v) {
+  uint32_t r = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, K * 0x55, 0xf, 0xf, false);
+  asm volatile("" : "+v"(r));
+  return r;
+}
+template <int K>
+ZK_DEV Fq quad_bcast(const Fq& x) {
+  Fq r;
+#pragma unroll
+  for (int q = 0; q < NL; q++) r.v[q] = quad_bcast_u32<K>(x.v[q]);
+  return r;
+}
+template <int K>
+ZK_DEV Fq2 quad_bcast(const Fq2& x) {
+  return {quad_bcast<K>(x.c0), quad_bcast<K>(x.c1)};
+}
+template <class F>
+ZK_DEV F sel4(uint32_t t, const F& a, const F& b, const F& c, const F& d) {
+  const F ab = F::select(t & 1u, b, a), cd = F::select(t & 1u, d, c);
+  return F::select(t & 2u, cd, ab);
+}
+
+template <class F>
+struct QuadOps {
+  using P = Xyzz<F>;
+  // p + q; t = lane index in the quad (0..3); p and q equal in the four lanes
+  static ZK_DEV P add(const P& p, const P& q, uint32_t t) {
+    if (P::is_inf(p)) return q;
+    if (P::is_inf(q)) return p;
+    F r = F::cmul(sel4(t, p.X, q.X, p.Y, q.Y), sel4(t, q.ZZ, p.ZZ, q.ZZZ, p.ZZZ));
+    const F U1 = quad_bcast<0>(r), U2 = quad_bcast<1>(r), S1 = quad_bcast<2>(r), S2 = quad_bcast<3>(r);
+    const F Pd = F::csub(U2, U1), R = F::csub(S2, S1);
+    if (F::cis_zero(Pd)) {
+      if (F::cis_zero(R)) return P::dbl(p);
+      return P::inf();
+    }
+    r = F::cmul(sel4(t, Pd, R, p.ZZ, p.ZZZ), sel4(t, Pd, R, q.ZZ, q.ZZZ));
+    const F PP = quad_bcast<0>(r), RR = quad_bcast<1>(r), ZZ12 = quad_bcast<2>(r), ZZZ12 = quad_bcast<3>(r);
+    r = F::cmul(sel4(t, Pd, U1, ZZ12, ZZ12), PP);
+    const F PPP = quad_bcast<0>(r), Q = quad_bcast<1>(r), ZZ3 = quad_bcast<2>(r);
+    const F X3 = F::csub(F::csub(RR, PPP), F::cdbl(Q));
+    r = F::cmul(sel4(t, R, S1, ZZZ12, ZZZ12), F::select(t == 0u, F::csub(Q, X3), PPP));
+    const F T1 = quad_bcast<0>(r), T2 = quad_bcast<1>(r), ZZZ3 = quad_bcast<2>(r);
+    return {X3, F::csub(T1, T2), ZZ3, ZZZ3};
+  }
+  // p + q with q affine, not infinity
+  static ZK_DEV P madd(const P& p, const Affine<F>& q, uint32_t t) {
+    if (P::is_inf(p)) return P::from_affine(q);
+    const bool odd = t & 1u;
+    F r = F::cmul(F::select(odd, q.y, q.x), F::select(odd, p.ZZZ, p.ZZ));
+    const F U2 = quad_bcast<0>(r), S2 = quad_bcast<1>(r);
+    const F Pd = F::csub(U2, p.X), R = F::csub(S2, p.Y);
+    if (F::cis_zero(Pd)) {
+      if (F::cis_zero(R)) return P::dbl_affine(q);
+      return P::inf();
+    }
+    const F PR = F::select(odd, R, Pd);
+    r = F::cmul(PR, PR);
+    const F PP = quad_bcast<0>(r), RR = quad_bcast<1>(r);
+    r = F::cmul(sel4(t, Pd, p.X, p.ZZ, p.ZZ), PP);
+    const F PPP = quad_bcast<0>(r), Q = quad_bcast<1>(r), ZZ3 = quad_bcast<2>(r);
+    const F X3 = F::csub(F::csub(RR, PPP), F::cdbl(Q));
+    r = F::cmul(sel4(t, R, p.Y, p.ZZZ, p.ZZZ), F::select(t == 0u, F::csub(Q, X3), PPP));
+    const F T1 = quad_bcast<0>(r), T2 = quad_bcast<1>(r), ZZZ3 = quad_bcast<2>(r);
+    return {X3, F::csub(T1, T2), ZZ3, ZZZ3};
+  }
+};
+
 // Memory helpers: a G1 affine point is 16 words, a G2 affine point 32 words,
 // an XYZZ accumulator 4 coordinates of the same widths.
 template <class F>

@@ -40,6 +40,7 @@ namespace zkvc {
 
 constexpr uint32_t EMPTY = 0xffffffffu;
 constexpr uint32_t WG_TASK_ENTRIES = 256;  // entries per large-bucket (wavefront) task
+constexpr uint32_t WG_TASK_ENTRIES_QUAD = 64;  // the same when the wavefront works in quads (latency-bound batches)
 constexpr uint32_t SIGN = 0x80000000u;
 enum MsmSlot {
   S_DIGITS = 100, S_COUNTS, S_OFFSETS, S_HEAVY, S_SORTED, S_TASKS, S_CNT_A, S_CNT_B, S_OFF_A, S_OFF_B,
@@ -62,8 +63,9 @@ struct JobDev {
   int pre;                  // precomputed windows: window w's digits index the points of copy w
   uint32_t nb;              // buckets per window: 2^(c-1)
   uint32_t nwb;             // bucket sets: nw, or 1 with precomputed windows
-  uint32_t chunk, nch;      // scalars per histogram chunk, number of chunks
-  uint32_t nchw;            // histogram columns per bucket: nch, or nw * nch with precomputed windows
+  uint32_t chunk, nch;      // digits per histogram chunk and number of chunks: per window, or (with
+                            // precomputed windows) over the job's whole digit stream of nw * n digits
+  uint32_t nchw;            // histogram columns per bucket (= nch)
   uint32_t digit_base;      // first digit word (nw * n words, window-major)
   uint32_t bucket_base;     // first bucket (nwb * nb buckets, window-major)
   uint32_t hist_base;       // first histogram word (nwb * nb * nchw words)
@@ -71,7 +73,7 @@ struct JobDev {
   uint32_t bpb;             // blocks per bit plane (a power of two)
   uint32_t blk_bp;          // first block of the bit-plane grid (nwb * c * bpb blocks)
   uint32_t blk_digits;      // first block of the digit grid
-  uint32_t blk_hs;          // first block of the histogram / scatter grid (nw * nch blocks)
+  uint32_t blk_hs;          // first block of the histogram / scatter grid (nw * nch blocks, or nch)
 };
 // The jobs of a batch live in a device table (uploaded with the batch), so a
 // batch may hold any number of MSMs: every proof of a proving batch at once.
@@ -100,6 +102,10 @@ constexpr int HS_THREADS = 512;   // histogram / scatter blocks
 constexpr int WG_THREADS = 64;    // one wavefront per large-bucket task (at most 4 entries per lane)
 constexpr int BP_THREADS = 256;   // bit-plane reduction block
 constexpr uint64_t FEW_BUCKETS = 4096;  // a wavefront per bucket leaves most of the device free
+// Above this many bucket entries, thread tasks of a few entries each already
+// fill the device, and their additions cost about half the VALU work of the
+// cooperative forms (no idle product slots, no trees inside a task).
+constexpr uint64_t FEW_ENTRIES = 1ull << 19;
 
 // ---------------------------------------------------------------- 1. digits
 // One thread per scalar: fold, recode into signed digits, write one word per
@@ -172,53 +178,74 @@ __global__ void __launch_bounds__(256) k_msm_digits(BatchDev B, uint32_t* digits
 
 // ---------------------------------------------------------------- 2. counting sort
 // Block (window w, chunk ch) counts its digits per bucket in LDS and writes
-// the counts to hist[(w nb + b) nch + ch] (with precomputed windows, all
-// windows share one bucket set: hist[b (nw nch) + w nch + ch]).  An exclusive
-// scan of hist then gives every (bucket, column) pair its first slot in
-// bucket order, with no global atomics however skewed the digits are.
-__device__ __forceinline__ size_t hist_column(const JobDev& J, uint32_t w, uint32_t ch) {
-  return J.pre ? (size_t)J.hist_base + (size_t)w * J.nch + ch
-               : (size_t)J.hist_base + (size_t)w * J.nb * J.nchw + ch;
+// the counts to hist[(w nb + b) nch + ch].  With precomputed windows all
+// windows share one bucket set and a block takes chunk ch of the job's whole
+// digit stream (window-major, nw n digits): hist[b nch + ch], so the
+// histogram holds nb columns per chunk of the stream rather than per window.
+// An exclusive scan of hist then gives every (bucket, column) pair its first
+// slot in bucket order, with no global atomics however skewed the digits are.
+struct HsRange {
+  const uint32_t* d;  // the block's digits: d[lo .. hi)
+  uint32_t lo, hi;
+  size_t col;         // its histogram column (bucket b at col + b nchw)
+};
+__device__ __forceinline__ HsRange hs_range(const JobDev& J, const uint32_t* digits, uint32_t local) {
+  HsRange r;
+  if (J.pre) {
+    const uint32_t total = (uint32_t)J.nw * J.n;
+    r.d = digits + J.digit_base;
+    r.lo = local * J.chunk;
+    r.hi = min(total, r.lo + J.chunk);
+    r.col = (size_t)J.hist_base + local;
+  } else {
+    const uint32_t w = local / J.nch, ch = local % J.nch;
+    r.d = digits + J.digit_base + (size_t)w * J.n;
+    r.lo = ch * J.chunk;
+    r.hi = min(J.n, r.lo + J.chunk);
+    r.col = (size_t)J.hist_base + (size_t)w * J.nb * J.nchw + ch;
+  }
+  return r;
 }
 __global__ void __launch_bounds__(HS_THREADS) k_msm_hist(BatchDev B, const uint32_t* digits, uint32_t* hist) {
   extern __shared__ uint32_t cnt[];
   const int k = job_of<&JobDev::blk_hs>(B, blockIdx.x);
   const JobDev& J = B.jobs[k];
-  const uint32_t local = blockIdx.x - J.blk_hs;
-  const uint32_t w = local / J.nch, ch = local % J.nch;
+  const HsRange R = hs_range(J, digits, blockIdx.x - J.blk_hs);
   for (uint32_t b = threadIdx.x; b < J.nb; b += HS_THREADS) cnt[b] = 0u;
   __syncthreads();
-  const uint32_t* d = digits + J.digit_base + (size_t)w * J.n;
-  const uint32_t lo = ch * J.chunk, hi = min(J.n, lo + J.chunk);
-  for (uint32_t i = lo + threadIdx.x; i < hi; i += HS_THREADS) {
-    const uint32_t v = d[i];
+  for (uint32_t i = R.lo + threadIdx.x; i < R.hi; i += HS_THREADS) {
+    const uint32_t v = R.d[i];
     if (v != EMPTY) atomicAdd(&cnt[v & ~SIGN], 1u);
   }
   __syncthreads();
-  uint32_t* h = hist + hist_column(J, w, ch);
+  uint32_t* h = hist + R.col;
   for (uint32_t b = threadIdx.x; b < J.nb; b += HS_THREADS) h[(size_t)b * J.nchw] = cnt[b];
 }
 
 // Same blocks as k_msm_hist: LDS cursors start at the scanned offsets and
 // every digit takes the next slot of its bucket (order inside a bucket does
-// not matter to the sum).  Entries are (point index | sign).
+// not matter to the sum).  Entries are (point index | sign); with
+// precomputed windows stream position p holds window p / n of scalar p % n,
+// whose point is copy p / n of the scalar's base.
 __global__ void __launch_bounds__(HS_THREADS) k_msm_scatter(BatchDev B, const uint32_t* digits, const uint32_t* offs,
                                                             uint32_t* sorted) {
   extern __shared__ uint32_t cur[];
   const int k = job_of<&JobDev::blk_hs>(B, blockIdx.x);
   const JobDev& J = B.jobs[k];
-  const uint32_t local = blockIdx.x - J.blk_hs;
-  const uint32_t w = local / J.nch, ch = local % J.nch;
-  const uint32_t* o = offs + hist_column(J, w, ch);
+  const HsRange R = hs_range(J, digits, blockIdx.x - J.blk_hs);
+  const uint32_t* o = offs + R.col;
   for (uint32_t b = threadIdx.x; b < J.nb; b += HS_THREADS) cur[b] = o[(size_t)b * J.nchw];
-  const uint32_t pbase = J.pre ? w * J.npoints : 0u;
   __syncthreads();
-  const uint32_t* d = digits + J.digit_base + (size_t)w * J.n;
-  const uint32_t lo = ch * J.chunk, hi = min(J.n, lo + J.chunk);
-  for (uint32_t i = lo + threadIdx.x; i < hi; i += HS_THREADS) {
-    const uint32_t v = d[i];
+  for (uint32_t p = R.lo + threadIdx.x; p < R.hi; p += HS_THREADS) {
+    const uint32_t v = R.d[p];
     if (v == EMPTY) continue;
     const uint32_t pos = atomicAdd(&cur[v & ~SIGN], 1u);
+    uint32_t i = p, pbase = 0u;
+    if (J.pre) {
+      const uint32_t w = p / J.n;
+      i = p - w * J.n;
+      pbase = w * J.npoints;
+    }
     const uint32_t idx = J.bitrev_bits ? bitrev_n(i, J.bitrev_bits) : i;
     sorted[pos] = (pbase + idx) | (v & SIGN);
   }
@@ -231,7 +258,8 @@ __global__ void __launch_bounds__(HS_THREADS) k_msm_scatter(BatchDev B, const ui
 // entries reduced by an LDS tree.  nt[f] is the number of partial sums of
 // bucket f; a bucket's partial sums are contiguous.
 __global__ void k_msm_task_counts(BatchDev B, const uint32_t* offs, uint32_t nbt, uint32_t K, uint32_t large,
-                                  uint32_t* cnt, uint32_t* off, uint32_t* nt, uint32_t* counters) {
+                                  uint32_t wg_entries, uint32_t* cnt, uint32_t* off, uint32_t* nt,
+                                  uint32_t* counters) {
   const uint32_t f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f == 0) {
     counters[0] = 0u;
@@ -248,7 +276,7 @@ __global__ void k_msm_task_counts(BatchDev B, const uint32_t* offs, uint32_t nbt
   const uint32_t c = e - s;
   cnt[f] = c;
   off[f] = s;
-  const uint32_t sz = c >= large ? WG_TASK_ENTRIES : K;
+  const uint32_t sz = c >= large ? wg_entries : K;
   nt[f] = (c + sz - 1) / sz;
 }
 
@@ -269,13 +297,14 @@ __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v, uint32_t lane
 
 __global__ void __launch_bounds__(256) k_msm_make_tasks(BatchDev B, const uint32_t* cnt, const uint32_t* off,
                                                         const uint32_t* part_off, uint32_t nbt, uint32_t K,
-                                                        uint32_t large, uint32_t fin_max, uint32_t* counters,
-                                                        uint4* th_tasks, uint4* wg_tasks, uint32_t* heavy) {
+                                                        uint32_t large, uint32_t wg_entries, uint32_t fin_max,
+                                                        uint32_t* counters, uint4* th_tasks, uint4* wg_tasks,
+                                                        uint32_t* heavy) {
   const uint32_t f = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t c = f < nbt ? cnt[f] : 0u;
   const bool big = c >= large;
-  const uint32_t sz = big ? WG_TASK_ENTRIES : K;
+  const uint32_t sz = big ? wg_entries : K;
   const uint32_t nt = (c + sz - 1) / sz;
   const uint32_t hv = nt > fin_max ? 1u : 0u;
   // inclusive wavefront scans of the three claims
@@ -303,6 +332,22 @@ __global__ void __launch_bounds__(256) k_msm_make_tasks(BatchDev B, const uint32
   }
 }
 
+// The sum over nteams quads of their values (each quad's four lanes hold the
+// same point): an LDS tree of cooperative additions.  Every thread of the
+// block must call; the result is valid in quad 0.
+template <class F>
+__device__ __forceinline__ Xyzz<F> quad_tree_sum(Xyzz<F> acc, uint32_t* sh, uint32_t nteams) {
+  constexpr int XW = PointIO<F>::XYZZ_WORDS;
+  const uint32_t team = threadIdx.x >> 2, tq = threadIdx.x & 3u;
+  for (uint32_t o = nteams / 2; o >= 1; o >>= 1) {
+    if (team >= o && team < 2 * o && tq == 0) PointIO<F>::store_xyzz(sh + (team - o) * XW, acc);
+    __syncthreads();
+    if (team < o) acc = QuadOps<F>::add(acc, PointIO<F>::load_xyzz(sh + team * XW), tq);
+    __syncthreads();
+  }
+  return acc;
+}
+
 // Bucket accumulation, one launch for both task lists: blocks below
 // th_blocks run thread tasks (each thread sums its entries serially), the
 // others run wavefront tasks (each lane sums a strided share of the task's
@@ -311,7 +356,7 @@ __global__ void __launch_bounds__(256) k_msm_make_tasks(BatchDev B, const uint32
 template <class F>
 __global__ void __launch_bounds__(64) k_msm_acc(BatchDev B, const uint4* th_tasks, const uint4* wg_tasks,
                                                 const uint32_t* counters, uint32_t th_blocks, const uint32_t* sorted,
-                                                uint32_t* partials) {
+                                                uint32_t* partials, int quad) {
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
   constexpr int AW = PointIO<F>::AFF_WORDS;
   __shared__ uint32_t sh[WG_THREADS / 2 * XW];
@@ -341,41 +386,54 @@ __global__ void __launch_bounds__(64) k_msm_acc(BatchDev B, const uint4* th_task
   }
   const uint32_t ntasks = counters[1];  // uniform: every lane of the block runs the same loop count
   const uint32_t wg_blocks = gridDim.x - th_blocks;
+  const uint32_t team = threadIdx.x >> 2, tq = threadIdx.x & 3u;
   for (uint32_t t = blockIdx.x - th_blocks; t < ntasks; t += wg_blocks) {
     const uint4 task = wg_tasks[t];
     const uint32_t* points = B.jobs[task.w].points;
     Xyzz<F> acc = Xyzz<F>::inf();
-    for (uint32_t e = threadIdx.x; e < task.y; e += WG_THREADS) {
-      const uint32_t ref = sorted[task.x + e];
-      Affine<F> pt = PointIO<F>::load_affine(points + (size_t)(ref & ~SIGN) * AW);
-      if (ref & SIGN) pt.y = F::neg(pt.y);
-      acc = Xyzz<F>::madd(acc, pt);
-    }
-    for (int o = WG_THREADS / 2; o >= 1; o >>= 1) {
-      if ((int)threadIdx.x >= o && (int)threadIdx.x < 2 * o) PointIO<F>::store_xyzz(sh + (threadIdx.x - o) * XW, acc);
-      __syncthreads();
-      if ((int)threadIdx.x < o) acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(sh + threadIdx.x * XW));
-      __syncthreads();
+    if (quad) {
+      // 16 quads, each summing a strided share with cooperative additions
+      for (uint32_t e = team; e < task.y; e += WG_THREADS / 4) {
+        const uint32_t ref = sorted[task.x + e];
+        Affine<F> pt = PointIO<F>::load_affine(points + (size_t)(ref & ~SIGN) * AW);
+        if (ref & SIGN) pt.y = F::neg(pt.y);
+        acc = QuadOps<F>::madd(acc, pt, tq);
+      }
+      acc = quad_tree_sum<F>(acc, sh, WG_THREADS / 4);
+    } else {
+      for (uint32_t e = threadIdx.x; e < task.y; e += WG_THREADS) {
+        const uint32_t ref = sorted[task.x + e];
+        Affine<F> pt = PointIO<F>::load_affine(points + (size_t)(ref & ~SIGN) * AW);
+        if (ref & SIGN) pt.y = F::neg(pt.y);
+        acc = Xyzz<F>::madd(acc, pt);
+      }
+      for (int o = WG_THREADS / 2; o >= 1; o >>= 1) {
+        if ((int)threadIdx.x >= o && (int)threadIdx.x < 2 * o) PointIO<F>::store_xyzz(sh + (threadIdx.x - o) * XW, acc);
+        __syncthreads();
+        if ((int)threadIdx.x < o) acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(sh + threadIdx.x * XW));
+        __syncthreads();
+      }
     }
     if (threadIdx.x == 0) PointIO<F>::store_xyzz(partials + (size_t)task.z * XW, acc);
   }
 }
 
 // Bucket sums from the partial sums, one launch: blocks below light_blocks
-// give each bucket with at most fin_max partials a thread (serial
-// sum); the others give each listed heavy bucket a wavefront (strided sums,
-// then an LDS tree), so one crowded bucket (e.g. the top window's few digit
-// values under uniform scalars) does not serialize the step.
+// give each bucket with at most fin_max partials a group of `group` lanes
+// (a power of two <= 64; each lane, or each quad with quad set, sums a
+// strided share, then a tree over the group); the others give each listed
+// heavy bucket a wavefront (strided sums, then a tree), so one crowded bucket
+// (e.g. the top window's few digit values under uniform scalars) does not
+// serialize the step.  quad: latency-bound batches add in cooperative quads.
 template <class F>
 __global__ void __launch_bounds__(64) k_msm_finalize(const uint32_t* nt, const uint32_t* part_off,
                                                      const uint32_t* partials, uint32_t nbt, const uint32_t* counters,
                                                      const uint32_t* heavy, uint32_t light_blocks, uint32_t fin_max,
-                                                     uint32_t group, uint32_t* buckets) {
+                                                     uint32_t group, int quad, uint32_t* buckets) {
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
   __shared__ uint32_t sh[WG_THREADS * XW];
+  const uint32_t tq = threadIdx.x & 3u;
   if (blockIdx.x < light_blocks) {
-    // `group` lanes per bucket (a power of two <= 64): each sums a strided
-    // share of the bucket's partials, then a tree over the group
     const uint32_t f = blockIdx.x * (WG_THREADS / group) + threadIdx.x / group;
     const uint32_t lane = threadIdx.x & (group - 1u);
     uint32_t c = 0, o = 0;
@@ -385,14 +443,27 @@ __global__ void __launch_bounds__(64) k_msm_finalize(const uint32_t* nt, const u
     }
     const bool mine = f < nbt && c <= fin_max;
     Xyzz<F> acc = Xyzz<F>::inf();
-    if (mine)
-      for (uint32_t e = lane; e < c; e += group)
-        acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(partials + (size_t)(o + e) * XW));
-    for (uint32_t q = group / 2; q >= 1; q >>= 1) {  // every thread of the block takes part
-      if (lane >= q && lane < 2 * q) PointIO<F>::store_xyzz(sh + (threadIdx.x - q) * XW, acc);
-      __syncthreads();
-      if (lane < q) acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(sh + threadIdx.x * XW));
-      __syncthreads();
+    if (quad) {  // group >= 4: group / 4 quads per bucket
+      const uint32_t qi = lane >> 2, nq = group >> 2;
+      if (mine)
+        for (uint32_t e = qi; e < c; e += nq)
+          acc = QuadOps<F>::add(acc, PointIO<F>::load_xyzz(partials + (size_t)(o + e) * XW), tq);
+      for (uint32_t q = nq / 2; q >= 1; q >>= 1) {  // every thread of the block takes part
+        if (qi >= q && qi < 2 * q && tq == 0) PointIO<F>::store_xyzz(sh + (threadIdx.x / 4 - q) * XW, acc);
+        __syncthreads();
+        if (qi < q) acc = QuadOps<F>::add(acc, PointIO<F>::load_xyzz(sh + (threadIdx.x / 4) * XW), tq);
+        __syncthreads();
+      }
+    } else {
+      if (mine)
+        for (uint32_t e = lane; e < c; e += group)
+          acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(partials + (size_t)(o + e) * XW));
+      for (uint32_t q = group / 2; q >= 1; q >>= 1) {  // every thread of the block takes part
+        if (lane >= q && lane < 2 * q) PointIO<F>::store_xyzz(sh + (threadIdx.x - q) * XW, acc);
+        __syncthreads();
+        if (lane < q) acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(sh + threadIdx.x * XW));
+        __syncthreads();
+      }
     }
     if (mine && lane == 0) PointIO<F>::store_xyzz(buckets + (size_t)f * XW, acc);
     return;
@@ -403,13 +474,19 @@ __global__ void __launch_bounds__(64) k_msm_finalize(const uint32_t* nt, const u
     const uint32_t f = heavy[h];
     const uint32_t c = nt[f], o = part_off[f];
     Xyzz<F> acc = Xyzz<F>::inf();
-    for (uint32_t e = threadIdx.x; e < c; e += WG_THREADS)
-      acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(partials + (size_t)(o + e) * XW));
-    for (int q = WG_THREADS / 2; q >= 1; q >>= 1) {
-      if ((int)threadIdx.x >= q && (int)threadIdx.x < 2 * q) PointIO<F>::store_xyzz(sh + (threadIdx.x - q) * XW, acc);
-      __syncthreads();
-      if ((int)threadIdx.x < q) acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(sh + threadIdx.x * XW));
-      __syncthreads();
+    if (quad) {
+      for (uint32_t e = threadIdx.x >> 2; e < c; e += WG_THREADS / 4)
+        acc = QuadOps<F>::add(acc, PointIO<F>::load_xyzz(partials + (size_t)(o + e) * XW), tq);
+      acc = quad_tree_sum<F>(acc, sh, WG_THREADS / 4);
+    } else {
+      for (uint32_t e = threadIdx.x; e < c; e += WG_THREADS)
+        acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(partials + (size_t)(o + e) * XW));
+      for (int q = WG_THREADS / 2; q >= 1; q >>= 1) {
+        if ((int)threadIdx.x >= q && (int)threadIdx.x < 2 * q) PointIO<F>::store_xyzz(sh + (threadIdx.x - q) * XW, acc);
+        __syncthreads();
+        if ((int)threadIdx.x < q) acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(sh + threadIdx.x * XW));
+        __syncthreads();
+      }
     }
     if (threadIdx.x == 0) PointIO<F>::store_xyzz(buckets + (size_t)f * XW, acc);
   }
@@ -419,26 +496,14 @@ __global__ void __launch_bounds__(64) k_msm_finalize(const uint32_t* nt, const u
 // For window w and bit j,
 //   S[w c + j] = sum of B_b over the buckets whose digit value b + 1 has bit j set,
 // so that window w contributes sum_j 2^j S[w c + j] = sum_b (b + 1) B_b.
-// A plane is split over bpb blocks; each thread sums a strided share of its
-// block's slice, an LDS tree sums the block, and k_msm_plane_sums adds the
-// bpb block sums of each plane.
-template <class F>
-__device__ __forceinline__ Xyzz<F> block_tree_sum(Xyzz<F> acc, uint32_t* sh, int nthreads) {
-  constexpr int XW = PointIO<F>::XYZZ_WORDS;
-  for (int o = nthreads / 2; o >= 1; o >>= 1) {
-    if ((int)threadIdx.x >= o && (int)threadIdx.x < 2 * o) PointIO<F>::store_xyzz(sh + (threadIdx.x - o) * XW, acc);
-    __syncthreads();
-    if ((int)threadIdx.x < o) acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(sh + threadIdx.x * XW));
-    __syncthreads();
-  }
-  return acc;
-}
-
+// A plane is split over bpb blocks; each quad of a block sums a strided
+// share of its block's slice with cooperative additions, a tree of quads
+// sums the block, and k_msm_plane_sums adds the bpb block sums of each plane.
 template <class F>
 __global__ void __launch_bounds__(BP_THREADS) k_msm_bitplanes(BatchDev B, const uint32_t* buckets, uint32_t* part,
                                                                uint32_t* S) {
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
-  __shared__ uint32_t sh[BP_THREADS / 2 * XW];
+  __shared__ uint32_t sh[BP_THREADS / 8 * XW];
   const int k = job_of<&JobDev::blk_bp>(B, blockIdx.x);
   const JobDev& J = B.jobs[k];
   const uint32_t local = blockIdx.x - J.blk_bp;
@@ -451,13 +516,14 @@ __global__ void __launch_bounds__(BP_THREADS) k_msm_bitplanes(BatchDev B, const 
   const uint32_t count = (j + 1 < c) ? nb / 2 : 1u;  // bit c-1 is set only in v = nb
   const uint32_t per = (count + J.bpb - 1) / J.bpb;
   const uint32_t t0 = slice * per, t1 = min(count, t0 + per);
+  const uint32_t team = threadIdx.x >> 2, tq = threadIdx.x & 3u, nteams = blockDim.x >> 2;
   Xyzz<F> acc = Xyzz<F>::inf();
-  for (uint32_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
+  for (uint32_t t = t0 + team; t < t1; t += nteams) {
     const uint32_t v = ((t >> j) << (j + 1)) | (1u << j) | (t & jmask);
     if (v > nb) continue;
-    acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(bw + (size_t)(v - 1) * XW));
+    acc = QuadOps<F>::add(acc, PointIO<F>::load_xyzz(bw + (size_t)(v - 1) * XW), tq);
   }
-  acc = block_tree_sum<F>(acc, sh, (int)blockDim.x);
+  acc = quad_tree_sum<F>(acc, sh, nteams);
   if (threadIdx.x != 0) return;
   if (J.bpb == 1)  // the block's sum is the plane
     PointIO<F>::store_xyzz(S + ((size_t)J.plane_base + q) * XW, Xyzz<F>::canon(acc));
@@ -465,19 +531,21 @@ __global__ void __launch_bounds__(BP_THREADS) k_msm_bitplanes(BatchDev B, const 
     PointIO<F>::store_xyzz(part + (size_t)blockIdx.x * XW, acc);
 }
 
-// One wavefront per plane: the sum of the plane's bpb block sums.
+// One wavefront (16 quads) per plane: the sum of the plane's bpb block sums.
 template <class F>
 __global__ void __launch_bounds__(64) k_msm_plane_sums(BatchDev B, const uint32_t* part, uint32_t* S) {
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
-  __shared__ uint32_t sh[32 * XW];
+  __shared__ uint32_t sh[8 * XW];
   const int k = job_of<&JobDev::plane_base>(B, blockIdx.x);
   const JobDev& J = B.jobs[k];
   if (J.bpb == 1) return;  // written by k_msm_bitplanes
   const uint32_t q = blockIdx.x - J.plane_base;
   const uint32_t* pp = part + ((size_t)J.blk_bp + (size_t)q * J.bpb) * XW;
+  const uint32_t tq = threadIdx.x & 3u;
   Xyzz<F> acc = Xyzz<F>::inf();
-  for (uint32_t t = threadIdx.x; t < J.bpb; t += 64) acc = Xyzz<F>::add(acc, PointIO<F>::load_xyzz(pp + (size_t)t * XW));
-  acc = block_tree_sum<F>(acc, sh, 64);
+  for (uint32_t t = threadIdx.x >> 2; t < J.bpb; t += 16)
+    acc = QuadOps<F>::add(acc, PointIO<F>::load_xyzz(pp + (size_t)t * XW), tq);
+  acc = quad_tree_sum<F>(acc, sh, 16);
   if (threadIdx.x == 0) PointIO<F>::store_xyzz(S + (size_t)blockIdx.x * XW, Xyzz<F>::canon(acc));
 }
 
@@ -559,7 +627,9 @@ struct BatchPlan {
   uint32_t large = 0;  // buckets with at least this many entries get wavefront tasks
   uint64_t max_th_tasks = 0, max_wg_tasks = 0, max_partials = 0;
   uint32_t fin_max = 0;  // partial sums above which a bucket gets a wavefront in the finalize step
-  uint32_t fin_group = 1;  // lanes per bucket below that (about four partial sums per lane)
+  uint32_t fin_group = 1;  // lanes per bucket below that (about four partial sums per lane, or two per quad)
+  bool quad = false;       // latency-bound batch: wavefront tasks and finalize add in cooperative quads
+  uint32_t wg_entries = WG_TASK_ENTRIES;
 };
 
 static BatchPlan batch_plan(const MsmInput* in, int njobs, int group) {
@@ -586,7 +656,8 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs, int group) {
     } else {
       msm_choose_window(J.n, in[q].max_bits, &J.c, &J.nw);
       // a tuned width for wide scalars of this size, if the autotuner picked one
-      const int tc = in[q].max_bits > 64 ? tuning().msm_c[group][std::min(32, ceil_log2(J.n))].load() : 0;
+      const int tc = in[q].max_bits > 64 && in[q].use_tuning
+                         ? tuning().msm_c[group][std::min(32, ceil_log2(J.n))].load() : 0;
       if (tc >= 2 && tc <= MAX_C) {
         J.c = tc;
         J.nw = (in[q].max_bits + 1 + tc - 1) / tc;
@@ -595,29 +666,40 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs, int group) {
     }
     J.nb = 1u << (J.c - 1);
     J.nwb = J.pre ? 1u : (uint32_t)J.nw;
-    // chunks of >= 4096 scalars, at most 2^22 histogram words per job
     const uint64_t wb = (uint64_t)J.nw * J.nb;
-    uint64_t nch = std::max<uint64_t>(1, std::min<uint64_t>((J.n + 4095) / 4096, (1ull << 22) / wb));
-    const uint64_t chunk = ((J.n + nch - 1) / nch + 255) / 256 * 256;
-    J.chunk = (uint32_t)chunk;
-    J.nch = (uint32_t)((J.n + chunk - 1) / chunk);
-    J.nchw = J.pre ? J.nch * (uint32_t)J.nw : J.nch;
+    if (J.pre) {
+      // one bucket set: chunks of >= 16384 digits over the whole stream, at
+      // most 2^22 histogram words
+      const uint64_t total = (uint64_t)J.nw * J.n;
+      const uint64_t nch = std::max<uint64_t>(1, std::min<uint64_t>((total + 16383) / 16384, (1ull << 22) / J.nb));
+      const uint64_t chunk = ((total + nch - 1) / nch + 255) / 256 * 256;
+      J.chunk = (uint32_t)chunk;
+      J.nch = (uint32_t)((total + chunk - 1) / chunk);
+    } else {
+      // chunks of >= 4096 scalars per window, at most 2^22 histogram words
+      const uint64_t nch = std::max<uint64_t>(1, std::min<uint64_t>((J.n + 4095) / 4096, (1ull << 22) / wb));
+      const uint64_t chunk = ((J.n + nch - 1) / nch + 255) / 256 * 256;
+      J.chunk = (uint32_t)chunk;
+      J.nch = (uint32_t)((J.n + chunk - 1) / chunk);
+    }
+    J.nchw = J.nch;
     J.digit_base = (uint32_t)p.ndigits;
     J.bucket_base = (uint32_t)p.nbt;
     J.hist_base = (uint32_t)p.nh;
     J.plane_base = (uint32_t)p.nplanes;
     // about two bucket additions per thread before each block's tree
-    J.bpb = std::max<uint32_t>(1, J.nb / 2 / (2 * BP_THREADS));
+    // about two bucket additions per quad (four lanes) before each block's tree
+    J.bpb = std::max<uint32_t>(1, J.nb / 2 / (BP_THREADS / 2));
     J.blk_bp = (uint32_t)p.bp_blocks;
     J.blk_digits = (uint32_t)p.digit_blocks;
     J.blk_hs = (uint32_t)p.hs_blocks;
     p.ndigits += (uint64_t)J.nw * J.n;
     p.nbt += (uint64_t)J.nwb * J.nb;
-    p.nh += wb * J.nch;
+    p.nh += (uint64_t)J.nwb * J.nb * J.nch;
     p.nplanes += (uint64_t)J.nwb * J.c;
     p.bp_blocks += (uint64_t)J.nwb * J.c * J.bpb;
     p.digit_blocks += cdiv(J.n, 256);
-    p.hs_blocks += (uint64_t)J.nw * J.nch;
+    p.hs_blocks += J.pre ? (uint64_t)J.nch : (uint64_t)J.nw * J.nch;
     p.max_nb = std::max(p.max_nb, J.nb);
     p.map.push_back(q);
     ZK_REQUIRE(p.ndigits < (1ull << 32) && p.nh < (1ull << 32) - 1 && p.nbt < (1ull << 31),
@@ -625,21 +707,29 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs, int group) {
   }
   const uint64_t E = p.ndigits;  // bound on the bucket entries
   // thread tasks: enough of them to fill the device, long enough to amortize
-  const int kd = E ? tuning().msm_kdiv_log[std::min(33, floor_log2(E))].load() : 0;
+  bool tuned = true;
+  for (int q = 0; q < njobs; q++) tuned = tuned && in[q].use_tuning;
+  const int kd = E && tuned ? tuning().msm_kdiv_log[std::min(33, floor_log2(E))].load() : 0;
   p.K = (uint32_t)std::max<uint64_t>(4, std::min<uint64_t>(E >> (kd > 0 ? kd : 17), 64));
-  // With few buckets in all (a small MSM, or full-width row terms over
-  // precomputed windows) the device has room for a wavefront per bucket, and
+  // With few buckets and few entries in all (a small MSM, or full-width row
+  // terms over precomputed windows) the device has room for a wavefront per bucket, and
   // a tree's depth beats a thread's chain of dependent additions: buckets of
   // 32 entries or more become wavefront tasks, and buckets with more than
   // FIN_THREAD_MIN partial sums are finished by a wavefront tree.
-  const bool few_buckets = p.nbt <= FEW_BUCKETS;
+  const bool few_buckets = p.nbt <= FEW_BUCKETS && E <= FEW_ENTRIES;
   // otherwise wavefront tasks only for buckets far above the typical size (a
   // window's few possible top digits, or small-integer scalars piling into few buckets)
   p.large = few_buckets ? 32u : std::max<uint32_t>(128, 32 * p.K);
+  // With few buckets and entries in all the batch is bound by chains of dependent
+  // additions, not by throughput: additions in the wavefront tasks and the
+  // finalize step are done by quads of lanes (shorter chains per point
+  // operation), and wavefront tasks are shorter.
+  p.quad = p.nbt <= 4 * FEW_BUCKETS && E <= FEW_ENTRIES;
+  p.wg_entries = p.quad ? WG_TASK_ENTRIES_QUAD : WG_TASK_ENTRIES;
   p.max_th_tasks = E / p.K + p.nbt;
   // a large bucket of c entries makes ceil(c / WG_TASK_ENTRIES) tasks, and at
   // most E / large buckets are large
-  p.max_wg_tasks = E / WG_TASK_ENTRIES + E / p.large + 1;
+  p.max_wg_tasks = E / p.wg_entries + E / p.large + 1;
   p.max_partials = p.max_th_tasks + p.max_wg_tasks;
   // a thread per bucket unless a bucket holds several times the average
   // number of partial sums (a tree over a wavefront costs ~7 dependent
@@ -649,8 +739,61 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs, int group) {
   // short thread tasks leave many partial sums per bucket: a small tree per
   // bucket keeps the finalize chain short
   p.fin_group = 1;
-  while (p.fin_group < 64 && 4 * p.fin_group < avg) p.fin_group *= 2;
+  if (p.quad) {  // quads of about two partial sums each
+    uint32_t quads = 1;
+    while (quads < 16 && 2 * quads < avg) quads *= 2;
+    p.fin_group = 4 * quads;
+  } else {
+    while (p.fin_group < 64 && 4 * p.fin_group < avg) p.fin_group *= 2;
+  }
   return p;
+}
+
+// The buffers of one batch, in a fixed order of workspace requests (every
+// request is made before the first launch, so a workspace in arena mode can
+// be sized by replaying the requests without launching anything).
+struct MsmBufs {
+  uint32_t *digits, *hist, *offs, *cnt, *off, *nt, *part_off, *sorted, *part, *buckets, *win, *bp_part, *heavy,
+      *meta, *win_host;
+  uint4 *th_tasks, *wg_tasks;
+  JobDev *jt_host, *jt_dev;
+};
+
+static MsmBufs msm_buffers(const BatchPlan& p, Workspace& ws, int XW) {
+  const size_t nj = p.jobs.size();
+  MsmBufs b;
+  b.digits = ws.get(S_DIGITS, p.ndigits * 4);
+  b.hist = ws.get(S_COUNTS, p.nh * 4);
+  b.offs = ws.get(S_OFFSETS, (p.nh + 1) * 4);
+  b.cnt = ws.get(S_CNT_A, p.nbt * 4);
+  b.off = ws.get(S_OFF_A, p.nbt * 4);
+  b.nt = ws.get(S_CNT_B, p.nbt * 4);
+  b.part_off = ws.get(S_OFF_B, p.nbt * 4);
+  b.sorted = ws.get(S_SORTED, p.ndigits * 4);
+  b.th_tasks = ws.get<uint4>(S_TASKS, p.max_th_tasks * 16);
+  b.wg_tasks = ws.get<uint4>(S_PART1, p.max_wg_tasks * 16);
+  b.part = ws.get(S_PART0, p.max_partials * XW * 4);
+  b.buckets = ws.get(S_SEG, p.nbt * XW * 4);
+  b.win = ws.get(S_WIN, p.nplanes * XW * 4);
+  b.bp_part = ws.get(S_BP_PART, p.bp_blocks * XW * 4);
+  b.heavy = ws.get(S_HEAVY, p.nbt * 4);
+  b.meta = ws.get(S_META, 64 * 4);  // [2] partials [8..10] thread tasks, wavefront tasks, heavy buckets
+  b.win_host = ws.host<uint32_t>(S_WIN, p.nplanes * XW * 4);
+  ws.get(S_SCRATCH, (size_t)cdiv(std::max(p.nh, p.nbt), 2048) * 4 + 64);
+  // the job table, through pinned memory (the workspace is not reused before
+  // this stream has completed)
+  b.jt_host = ws.host<JobDev>(S_JOBS, nj * sizeof(JobDev));
+  b.jt_dev = ws.get<JobDev>(S_JOBS, nj * sizeof(JobDev));
+  return b;
+}
+
+void msm_arena_need(const MsmInput* in, int njobs, int group, size_t* dev_bytes, size_t* host_bytes) {
+  const BatchPlan p = batch_plan(in, njobs, group == 1 ? 0 : 1);
+  Workspace count;
+  count.set_arena(nullptr, SIZE_MAX, nullptr, SIZE_MAX);
+  if (!p.jobs.empty()) msm_buffers(p, count, group == 1 ? PointIO<Fq>::XYZZ_WORDS : PointIO<Fq2>::XYZZ_WORDS);
+  *dev_bytes = count.arena_dev_used();
+  *host_bytes = count.arena_host_used();
 }
 
 template <class F>
@@ -668,28 +811,12 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
   const bool g1 = PointIO<F>::AFF_WORDS == 16;
 
   // all buffers first (a buffer that grows is replaced by a new one)
-  uint32_t* digits = ws.get(S_DIGITS, p.ndigits * 4);
-  uint32_t* hist = ws.get(S_COUNTS, p.nh * 4);
-  uint32_t* offs = ws.get(S_OFFSETS, (p.nh + 1) * 4);
-  uint32_t* cnt = ws.get(S_CNT_A, p.nbt * 4);
-  uint32_t* off = ws.get(S_OFF_A, p.nbt * 4);
-  uint32_t* nt = ws.get(S_CNT_B, p.nbt * 4);
-  uint32_t* part_off = ws.get(S_OFF_B, p.nbt * 4);
-  uint32_t* sorted = ws.get(S_SORTED, p.ndigits * 4);
-  uint4* th_tasks = ws.get<uint4>(S_TASKS, p.max_th_tasks * 16);
-  uint4* wg_tasks = ws.get<uint4>(S_PART1, p.max_wg_tasks * 16);
-  uint32_t* part = ws.get(S_PART0, p.max_partials * XW * 4);
-  uint32_t* buckets = ws.get(S_SEG, p.nbt * XW * 4);
-  uint32_t* win = ws.get(S_WIN, p.nplanes * XW * 4);
-  uint32_t* bp_part = ws.get(S_BP_PART, p.bp_blocks * XW * 4);
-  uint32_t* heavy = ws.get(S_HEAVY, p.nbt * 4);
-  uint32_t* meta = ws.get(S_META, 64 * 4);  // [2] partials [8..10] thread tasks, wavefront tasks, heavy buckets
-  uint32_t* win_host = ws.host<uint32_t>(S_WIN, p.nplanes * XW * 4);
-  ws.get(S_SCRATCH, (size_t)cdiv(std::max(p.nh, p.nbt), 2048) * 4 + 64);
-  // the job table, through pinned memory (the workspace is not reused before
-  // this stream has completed)
-  JobDev* jt_host = ws.host<JobDev>(S_JOBS, nj * sizeof(JobDev));
-  JobDev* jt_dev = ws.get<JobDev>(S_JOBS, nj * sizeof(JobDev));
+  const MsmBufs bf = msm_buffers(p, ws, XW);
+  uint32_t *digits = bf.digits, *hist = bf.hist, *offs = bf.offs, *cnt = bf.cnt, *off = bf.off, *nt = bf.nt,
+           *part_off = bf.part_off, *sorted = bf.sorted, *part = bf.part, *buckets = bf.buckets, *win = bf.win,
+           *bp_part = bf.bp_part, *heavy = bf.heavy, *meta = bf.meta, *win_host = bf.win_host;
+  uint4 *th_tasks = bf.th_tasks, *wg_tasks = bf.wg_tasks;
+  JobDev *jt_host = bf.jt_host, *jt_dev = bf.jt_dev;
   std::memcpy(jt_host, p.jobs.data(), nj * sizeof(JobDev));
   ZK_HIP(hipMemcpyAsync(jt_dev, jt_host, nj * sizeof(JobDev), hipMemcpyHostToDevice, st));
   const BatchDev dev{nj, jt_dev};
@@ -717,12 +844,13 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
     ZK_HIP(hipGetLastError());
   }
   // tasks by actual bucket size
-  hipLaunchKernelGGL(k_msm_task_counts, dim3(cdiv(nbt, 256)), dim3(256), 0, st, dev, offs, nbt, p.K, p.large, cnt,
+  hipLaunchKernelGGL(k_msm_task_counts, dim3(cdiv(nbt, 256)), dim3(256), 0, st, dev, offs, nbt, p.K, p.large,
+                     p.wg_entries, cnt,
                      off, nt, meta + 8);
   ZK_HIP(hipGetLastError());
   scan_exclusive(nt, part_off, nbt, 0, meta + 2, nullptr, ws, S_SCRATCH, st);
   hipLaunchKernelGGL(k_msm_make_tasks, dim3(cdiv(nbt, 256)), dim3(256), 0, st, dev, cnt, off, part_off, nbt, p.K,
-                     p.large, p.fin_max, meta + 8, th_tasks, wg_tasks, heavy);
+                     p.large, p.wg_entries, p.fin_max, meta + 8, th_tasks, wg_tasks, heavy);
   ZK_HIP(hipGetLastError());
   {
     ProfScope ps(g1 ? "msm_acc_points_g1" : "msm_acc_points_g2", st, -1.0);
@@ -730,7 +858,7 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
     const unsigned th_blocks = (unsigned)std::min<uint64_t>(cdiv(p.max_th_tasks, 64), 65536);
     const unsigned wg_blocks = (unsigned)std::min<uint64_t>(p.max_wg_tasks, 4096);
     hipLaunchKernelGGL(k_msm_acc<F>, dim3(th_blocks + wg_blocks), dim3(64), 0, st, dev, th_tasks, wg_tasks,
-                       meta + 8, th_blocks, sorted, part);
+                       meta + 8, th_blocks, sorted, part, p.quad ? 1 : 0);
     ZK_HIP(hipGetLastError());
     ps.set_work_from_device(offs + p.nh);
   }
@@ -739,19 +867,19 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
     const unsigned light_blocks = cdiv(nbt, 64 / p.fin_group);
     const unsigned heavy_blocks = (unsigned)std::min<uint64_t>(nbt, 1024);
     hipLaunchKernelGGL(k_msm_finalize<F>, dim3(light_blocks + heavy_blocks), dim3(64), 0, st, nt, part_off, part, nbt,
-                       meta + 8, heavy, light_blocks, p.fin_max, p.fin_group, buckets);
+                       meta + 8, heavy, light_blocks, p.fin_max, p.fin_group, p.quad ? 1 : 0, buckets);
     ZK_HIP(hipGetLastError());
   }
   {
     double adds = 0;
     for (int k = 0; k < nj; k++) adds += (double)p.jobs[k].nwb * p.jobs[k].c * p.jobs[k].nb / 2;
     ProfScope ps(g1 ? "msm_bitplanes_g1" : "msm_bitplanes_g2", st, adds);
-    // block size: about two bucket additions per thread (64 to BP_THREADS threads)
     uint32_t per_block = 1;
     for (int k = 0; k < nj; k++)
       per_block = std::max(per_block, (p.jobs[k].nb / 2 + p.jobs[k].bpb - 1) / p.jobs[k].bpb);
+    // quads of about two bucket additions each: 2 per_block lanes (64 to BP_THREADS)
     unsigned bp_threads = 64;
-    while (bp_threads < (unsigned)BP_THREADS && bp_threads * 2 < per_block) bp_threads *= 2;
+    while (bp_threads < (unsigned)BP_THREADS && bp_threads < 2 * per_block) bp_threads *= 2;
     hipLaunchKernelGGL(k_msm_bitplanes<F>, dim3((unsigned)p.bp_blocks), dim3(bp_threads), 0, st, dev, buckets,
                        bp_part, win);
     ZK_HIP(hipGetLastError());

@@ -21,6 +21,9 @@ struct MsmInput {
   // uses that window width and one set of buckets for all windows.
   int pre_c = 0;
   int pre_nw = 0;
+  // Use the autotuner's window width and task size where it set one (else
+  // the built-in rules, whose workspace size depends on n alone).
+  bool use_tuning = true;
 };
 
 // An MSM enqueued on a stream; its bit-plane sums land in pinned host memory.
@@ -37,6 +40,9 @@ struct MsmPending {
 // pending result.
 void msm_enqueue_batch_g1(const MsmInput* in, int njobs, Workspace& ws, hipStream_t st, MsmPending* pend);
 void msm_enqueue_batch_g2(const MsmInput* in, int njobs, Workspace& ws, hipStream_t st, MsmPending* pend);
+// Device and host workspace bytes that msm_enqueue_batch_g1/g2 takes for
+// these jobs from a workspace in arena mode (each slot once, 256-byte aligned).
+void msm_arena_need(const MsmInput* in, int njobs, int group, size_t* dev_bytes, size_t* host_bytes);
 // After the stream has completed: combine one job's bit planes (host).
 host::G1J msm_finish_g1(const MsmPending& pend);
 host::G2J msm_finish_g2(const MsmPending& pend);

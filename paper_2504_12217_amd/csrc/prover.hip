@@ -599,6 +599,68 @@ __global__ void __launch_bounds__(RED_THREADS) k_crpc_rows(WitTable T) {
   }
 }
 
+// The witness kernels for one proof outside a proving batch: Y, the
+// assignment and the first `rows` rows of the evaluation vectors (rows <= m
+// leaves out the input-consistency rows).  The CRPC kinds' per-k sums use
+// workspace slots 230..233.
+void enqueue_witness_one(const Layout& L, const uint32_t* zpow, uint64_t rows, const int8_t* X, const int8_t* W,
+                         int32_t* Y, uint32_t* assign, uint32_t* aev, uint32_t* bev, uint32_t* cev, Workspace& ws,
+                         hipStream_t st) {
+  WitTable T{};
+  WitJob& J = T.one;
+  J.kind = L.kind;
+  J.a = L.a;
+  J.n = L.n;
+  J.b = L.b;
+  J.m = L.m;
+  J.ell = L.ell;
+  J.aux_start = L.aux_start;
+  J.N = rows;
+  J.X = X;
+  J.W = W;
+  J.Y = Y;
+  J.zpow = zpow;
+  J.assign = assign;
+  J.aev = aev;
+  J.bev = bev;
+  J.cev = cev;
+  const bool crpc = kind_uses_z(L.kind);
+  J.xk = crpc ? ws.get(230, (size_t)L.n * 32) : nullptr;
+  J.wk = crpc ? ws.get(231, (size_t)L.n * 32) : nullptr;
+  J.pkk = crpc ? ws.get(232, (size_t)L.n * 32) : nullptr;
+  J.yz = crpc ? ws.get(233, 32 * YZ_BLOCKS) : nullptr;
+  hipLaunchKernelGGL(k_matmul, dim3(cdiv(L.b, 256), L.a, 1), dim3(256), 0, st, T);
+  ZK_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_assign_public, dim3(cdiv(L.aux_start, 256), 1), dim3(256), 0, st, T);
+  ZK_HIP(hipGetLastError());
+  if (crpc) {
+    hipLaunchKernelGGL(k_crpc_xw, dim3(L.n, 1), dim3(RED_THREADS), 0, st, T);
+    ZK_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_crpc_yz, dim3(YZ_BLOCKS, 1), dim3(RED_THREADS), 0, st, T);
+    ZK_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_crpc_rows, dim3(1), dim3(RED_THREADS), 0, st, T);
+    ZK_HIP(hipGetLastError());
+  } else {
+    hipLaunchKernelGGL(k_rows_plain, dim3(cdiv(L.m, 256), 1), dim3(256), 0, st, T);
+    ZK_HIP(hipGetLastError());
+  }
+  if (rows > L.m) {
+    hipLaunchKernelGGL(k_rows_tail, dim3(cdiv(rows - L.m, 256), 1), dim3(256), 0, st, T);
+    ZK_HIP(hipGetLastError());
+  }
+}
+
+size_t prove_footprint(const Layout& L) {
+  const uint64_t scalars = L.ell + 1 + 2 * (uint64_t)L.n * L.b + L.naux + L.N;
+  return (size_t)(32 * (L.nv + 3 * L.N) + 48 * scalars);
+}
+
+void enqueue_zpow(const uint32_t* z_dev, uint32_t count, uint32_t* out, hipStream_t st) {
+  if (!count) return;
+  hipLaunchKernelGGL(k_zpow, dim3(cdiv(count, 128)), dim3(128), 0, st, z_dev, count, out);
+  ZK_HIP(hipGetLastError());
+}
+
 // ------------------------------------------------------------------ host: setup
 namespace {
 
@@ -1037,13 +1099,21 @@ std::vector<Slot> enqueue_witness_batch(const ProveJob* jobs, size_t nj, ProveGe
     T.jobs = td;
   }
   const unsigned J = (unsigned)nj;
+  // the CRPC row values first: when every proof is CRPC+PSQ they are all the
+  // G2 lane needs (W_k(z) for the row terms; the CRPC kind's B query also
+  // holds the constant, written with the public assignment), so it starts here
+  bool rows_only = true;
+  for (size_t j = 0; j < nj; j++) rows_only = rows_only && jobs[j].pk->L.kind == ZKVC_CRPC_PSQ;
+  if (any_crpc) {
+    hipLaunchKernelGGL(k_crpc_xw, dim3(max_n_crpc, J), dim3(RED_THREADS), 0, st, T);
+    ZK_HIP(hipGetLastError());
+  }
+  if (rows_only) ZK_HIP(hipEventRecord(G.wrow_ev, st));
   hipLaunchKernelGGL(k_matmul, dim3(cdiv(max_b, 256), max_a, J), dim3(256), 0, st, T);
   ZK_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_assign_public, dim3(cdiv(max_pub, 256), J), dim3(256), 0, st, T);
   ZK_HIP(hipGetLastError());
   if (any_crpc) {
-    hipLaunchKernelGGL(k_crpc_xw, dim3(max_n_crpc, J), dim3(RED_THREADS), 0, st, T);
-    ZK_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_crpc_yz, dim3(YZ_BLOCKS, J), dim3(RED_THREADS), 0, st, T);
     ZK_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_crpc_rows, dim3(J), dim3(RED_THREADS), 0, st, T);
@@ -1055,6 +1125,7 @@ std::vector<Slot> enqueue_witness_batch(const ProveJob* jobs, size_t nj, ProveGe
   }
   hipLaunchKernelGGL(k_rows_tail, dim3(cdiv(max_tail, 256), J), dim3(256), 0, st, T);
   ZK_HIP(hipGetLastError());
+  if (!rows_only) ZK_HIP(hipEventRecord(G.wrow_ev, st));
   ZK_HIP(hipMemcpyAsync(y_host, y_dev, y_bytes, hipMemcpyDeviceToHost, st));
   return slots;
 }
@@ -1201,6 +1272,7 @@ ProveCtx::ProveCtx() {
   ZK_HIP(hipStreamCreateWithFlags(&graph_stream, hipStreamNonBlocking));
   for (ProveGen& g : gen) {
     ZK_HIP(hipEventCreateWithFlags(&g.witness_ev, hipEventDisableTiming));
+    ZK_HIP(hipEventCreateWithFlags(&g.wrow_ev, hipEventDisableTiming));
     ZK_HIP(hipEventCreateWithFlags(&g.quotient_ev, hipEventDisableTiming));
     ZK_HIP(hipEventCreateWithFlags(&g.fork_ev, hipEventDisableTiming));
     ZK_HIP(hipEventCreateWithFlags(&g.graph_ev, hipEventDisableTiming));
@@ -1231,6 +1303,7 @@ ProveCtx::~ProveCtx() {
     if (g.fork_ev) (void)hipEventDestroy(g.fork_ev);
     if (g.graph_ev) (void)hipEventDestroy(g.graph_ev);
     if (g.witness_ev) (void)hipEventSynchronize(g.witness_ev), (void)hipEventDestroy(g.witness_ev);
+    if (g.wrow_ev) (void)hipEventSynchronize(g.wrow_ev), (void)hipEventDestroy(g.wrow_ev);
     if (g.quotient_ev) (void)hipEventSynchronize(g.quotient_ev), (void)hipEventDestroy(g.quotient_ev);
     for (int lane = 0; lane < LANES; lane++) {
       if (g.done_ev[lane]) (void)hipEventDestroy(g.done_ev[lane]);
@@ -1240,6 +1313,34 @@ ProveCtx::~ProveCtx() {
     for (auto& e : g.ev)
       if (e) (void)hipEventDestroy(e);
   }
+}
+
+void ProveCtx::release_retired() {
+  for (ProveGen& g : gen) {
+    for (Workspace& w : g.lane_ws) w.release_retired();
+    for (auto& w : g.slot_ws) w->release_retired();
+    g.shared.release_retired();
+  }
+}
+
+size_t ProveCtx::device_bytes() const {
+  size_t s = 0;
+  for (const ProveGen& g : gen) {
+    for (const Workspace& w : g.lane_ws) s += w.bytes();
+    for (const auto& w : g.slot_ws) s += w->bytes();
+    s += g.shared.bytes();
+  }
+  return s;
+}
+
+size_t ProveCtx::host_bytes() const {
+  size_t s = 0;
+  for (const ProveGen& g : gen) {
+    for (const Workspace& w : g.lane_ws) s += w.host_bytes();
+    for (const auto& w : g.slot_ws) s += w->host_bytes();
+    s += g.shared.host_bytes();
+  }
+  return s;
 }
 
 // Everything a begun batch needs to be finished.
@@ -1424,7 +1525,7 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
   hipStream_t lane_h = ctx.lanes[ProveCtx::LANE_H], lane_g1 = ctx.lanes[ProveCtx::LANE_G1],
               lane_g2 = ctx.lanes[ProveCtx::LANE_G2];
   auto g2_lane = [&] {
-    ZK_HIP(hipStreamWaitEvent(lane_g2, G.witness_ev, 0));
+    ZK_HIP(hipStreamWaitEvent(lane_g2, G.wrow_ev, 0));
     msm_enqueue_batch_g2(in_g2.data(), (int)in_g2.size(), G.lane_ws[ProveCtx::LANE_G2], lane_g2, R.pend_g2.data());
     record_ext(G.done_ev[ProveCtx::LANE_G2], lane_g2, capture);
     record_ext(G.lane_t[ProveCtx::LANE_G2], lane_g2, capture);
@@ -1649,6 +1750,10 @@ void groth16_prove_batch(ProveCtx& ctx, const ProveJob* jobs, size_t nj, hipStre
     prove_batch_abandon(run);
     throw;
   }
+  // the context is idle: buffers replaced while this batch grew its
+  // workspaces can go (the graph, if one was captured, uses the current ones)
+  run.reset();
+  ctx.release_retired();
 }
 
 

@@ -56,6 +56,21 @@ struct Layout {
 Layout r1cs_layout(uint32_t a, uint32_t n, uint32_t b, uint32_t kind);
 bool kind_uses_z(uint32_t kind);
 
+// Witness generation for one proof (the kernels of the Groth16 prover):
+// Y = X W (device int32), the assignment (canonical words, L.nv elements) and
+// rows 0 .. rows-1 of the evaluation vectors <A_c,a>, <B_c,a>, <C_c,a>
+// (canonical words).  zpow: z^e for e < a b (device Montgomery form) for the
+// CRPC kinds.  X and W are device copies.
+void enqueue_witness_one(const Layout& L, const uint32_t* zpow, uint64_t rows, const int8_t* X, const int8_t* W,
+                         int32_t* Y, uint32_t* assign, uint32_t* aev, uint32_t* bev, uint32_t* cev, Workspace& ws,
+                         hipStream_t st);
+// Estimated device workspace of one proof of this circuit in a batch: the
+// assignment and three evaluation vectors, and its share of the MSM
+// pipelines (about 48 bytes per scalar: digits, sorted entries, partial sums).
+size_t prove_footprint(const Layout& L);
+// out[e] = z^e for e < count (device Montgomery form), z_dev one element in that form.
+void enqueue_zpow(const uint32_t* z_dev, uint32_t count, uint32_t* out, hipStream_t st);
+
 }  // namespace zkvc
 
 namespace zkvc {
@@ -72,6 +87,7 @@ using BatchRunPtr = std::unique_ptr<BatchRun, BatchRunDeleter>;
 // vectors, quotient, pinned staging).
 struct ProveGen {
   hipEvent_t witness_ev = nullptr;   // assignments complete
+  hipEvent_t wrow_ev = nullptr;      // the G2 lane's scalars ready (CRPC row values, or the whole witness)
   hipEvent_t quotient_ev = nullptr;  // every h complete (and the tail flag copied)
   hipEvent_t done_ev[3] = {};        // each lane's batch complete
   hipEvent_t lane_t[3] = {};         // the same, with timing
@@ -134,6 +150,11 @@ struct ProveCtx {
   std::unique_ptr<TaskPool> pool;      // helper threads (at most three tasks at a time)
   ProveGen gen[GENS];
   zkvc_prove_stats last{};
+  // Frees the workspaces' retired buffers; no batch of this context may be in flight.
+  void release_retired();
+  // Device and pinned host bytes held by the context's workspaces.
+  size_t device_bytes() const;
+  size_t host_bytes() const;
 };
 
 }  // namespace zkvc

@@ -39,14 +39,7 @@ struct Request {
   Clock::time_point t_submit, t_start;
 };
 
-// Estimated device memory of one proof in flight: the proof's workspace
-// (assignment, three evaluation vectors) and its share of the MSM pipelines
-// (about 48 bytes per scalar: digits, sorted entries, partial sums).
-size_t footprint(const zkvc_pk* pk) {
-  const Layout& L = pk->L;
-  const uint64_t scalars = L.ell + 1 + 2 * (uint64_t)L.n * L.b + L.naux + L.N;
-  return (size_t)(32 * (L.nv + 3 * L.N) + 48 * scalars);
-}
+size_t footprint(const zkvc_pk* pk) { return prove_footprint(pk->L); }
 
 double ms_between(Clock::time_point a, Clock::time_point b) {
   return std::chrono::duration<double, std::milli>(b - a).count();
@@ -104,23 +97,35 @@ void zkvc_server::run() {
   }
   BatchRunPtr prev;
   std::vector<std::unique_ptr<Request>> prev_reqs;
+  size_t prev_bytes = 0;  // estimated footprint of the batch in flight
   int gen = 0;
   for (;;) {
     std::vector<std::unique_ptr<Request>> take;
     {
       std::unique_lock<std::mutex> lock(mu);
-      // with nothing in flight, sleep until work arrives
+      // with nothing in flight: free the buffers that growth replaced, then
+      // sleep until work arrives
+      if (!prev && queue.empty() && !stop) {
+        lock.unlock();
+        ctx->release_retired();
+        lock.lock();
+      }
       if (!prev) cv_work.wait(lock, [&] { return stop || !queue.empty(); });
       if (!prev && queue.empty() && stop) break;
-      size_t bytes = 0;
+      // admission by footprint: the new batch and the one still in flight
+      // share the budget (submit rejects a job that exceeds it alone, so a
+      // job always fits once nothing is in flight)
+      size_t bytes = prev ? prev_bytes : 0;
       while (!queue.empty() && take.size() < max_batch) {
         const size_t b = queue.front()->bytes;
-        if (!take.empty() && budget && bytes + b > budget) break;  // admission by footprint
+        if (budget && bytes + b > budget) break;
         bytes += b;
         take.push_back(std::move(queue.front()));
         queue.pop_front();
       }
     }
+    size_t take_bytes = 0;
+    for (auto& r : take) take_bytes += r->bytes;
     BatchRunPtr cur;
     if (!take.empty()) {
       const Clock::time_point t = Clock::now();
@@ -156,6 +161,7 @@ void zkvc_server::run() {
     }
     prev = std::move(cur);
     prev_reqs = std::move(take);
+    prev_bytes = prev ? take_bytes : 0;
   }
   ctx.reset();
   if (st) (void)hipStreamDestroy(st);
@@ -192,6 +198,9 @@ int zkvc_server_submit(zkvc_server* srv, const zkvc_prove_job* job, uint64_t* ti
     r->job.Y = job->Y_out;
     r->job.out = job->proof_out;
     r->bytes = footprint(job->pk);
+    if (srv->budget && r->bytes > srv->budget)
+      throw Error(ZKVC_ENOMEM, "the job's estimated device footprint (" + std::to_string(r->bytes) +
+                                   " bytes) exceeds the server's memory budget");
     r->t_submit = Clock::now();
     std::lock_guard<std::mutex> lock(srv->mu);
     ZK_REQUIRE(!srv->stop, srv->fatal.empty() ? "the server is stopping" : srv->fatal);

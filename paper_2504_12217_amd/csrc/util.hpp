@@ -1,6 +1,7 @@
 // Error plumbing, device buffers and scratch workspaces for the library.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <cstdint>
 #include <cstdio>
 #include <map>
@@ -82,36 +83,63 @@ class HostBuf {
 // (a proving key's MSM lane, or one stream of the standalone calls) has its own.
 class Workspace {
  public:
-  // A buffer that has to grow is replaced, and the old one is retired (kept
-  // until the workspace goes) rather than freed: work still in flight may
-  // read it, and freeing device memory would wait for the whole device,
-  // stalling every other stream (a latency spike for a server).
+  // A buffer that has to grow is replaced, and the old one is retired rather
+  // than freed at once: work still in flight may read it, and freeing device
+  // memory waits for the whole device, stalling every other stream (a
+  // latency spike for a server).  Retired buffers are freed by
+  // release_retired(), which owners call when none of their work is in
+  // flight.  A replacement is at least 1.5 times the old size, so a slot
+  // retires O(log) buffers and holds at most 1.5 times its largest request.
   template <class T = uint32_t>
   T* get(int slot, size_t bytes) {
+    if (arena_) return reinterpret_cast<T*>(carve(dev_slots_, slot, bytes, arena_dev_, arena_dev_cap_, arena_dev_used_));
     auto& b = bufs_[slot];
     const size_t need = bytes < 256 ? 256 : bytes;
     if (need > b.size()) {
+      const size_t grow = b.size() ? std::max(need, b.size() + b.size() / 2) : need;
       if (b.size()) retired_.push_back(std::move(b));
-      b.alloc(need);
+      try {
+        b.alloc((grow + 255) & ~(size_t)255);
+      } catch (const Error& e) {
+        if (e.code != ZKVC_ENOMEM || grow == need) throw;
+        b.alloc(need);  // the headroom does not fit: the exact size
+      }
     }
     return b.get<T>();
   }
   template <class T = uint32_t>
   T* host(int slot, size_t bytes) {
+    if (arena_)
+      return reinterpret_cast<T*>(carve(host_slots_, slot, bytes, arena_host_, arena_host_cap_, arena_host_used_));
     auto& b = host_[slot];
     const size_t need = bytes < 256 ? 256 : bytes;
     if (need > b.size()) {
+      const size_t grow = b.size() ? std::max(need, b.size() + b.size() / 2) : need;
       if (b.size()) retired_host_.push_back(std::move(b));
-      b.ensure(need);
+      b.ensure((grow + 255) & ~(size_t)255);
     }
     return b.get<T>();
   }
+  // device bytes held, retired buffers included
   size_t bytes() const {
     size_t s = 0;
     for (auto& kv : bufs_) s += kv.second.size();
     for (auto& b : retired_) s += b.size();
     return s;
   }
+  // pinned host bytes held, retired buffers included
+  size_t host_bytes() const {
+    size_t s = 0;
+    for (auto& kv : host_) s += kv.second.size();
+    for (auto& b : retired_host_) s += b.size();
+    return s;
+  }
+  // Frees the retired buffers; the caller guarantees no work in flight uses them.
+  void release_retired() {
+    retired_.clear();
+    retired_host_.clear();
+  }
+  bool has_retired() const { return !retired_.empty() || !retired_host_.empty(); }
   void clear() {
     bufs_.clear();
     host_.clear();
@@ -119,7 +147,46 @@ class Workspace {
     retired_host_.clear();
   }
 
+  // Arena mode: get() and host() carve their buffers from caller-owned
+  // ranges (device and host memory) instead of allocating, each slot once
+  // per arena, 256-byte aligned; a request beyond a range throws ZKVC_EINVAL.
+  // With null bases nothing is dereferenced by the workspace itself: the
+  // returned pointers are offsets, and the used sizes tell what a sequence
+  // of requests needs.  set_arena clears earlier carvings.
+  void set_arena(void* dev, size_t dev_bytes, void* host, size_t host_bytes) {
+    arena_ = true;
+    arena_dev_ = static_cast<char*>(dev);
+    arena_host_ = static_cast<char*>(host);
+    arena_dev_cap_ = dev_bytes;
+    arena_host_cap_ = host_bytes;
+    arena_dev_used_ = arena_host_used_ = 0;
+    dev_slots_.clear();
+    host_slots_.clear();
+  }
+  size_t arena_dev_used() const { return arena_dev_used_; }
+  size_t arena_host_used() const { return arena_host_used_; }
+
  private:
+  struct Carved {
+    size_t off, size;
+  };
+  static char* carve(std::map<int, Carved>& slots, int slot, size_t bytes, char* base, size_t cap, size_t& used) {
+    const size_t need = bytes < 256 ? 256 : bytes;
+    auto it = slots.find(slot);
+    if (it != slots.end() && it->second.size >= need) return base ? base + it->second.off : nullptr;
+    const size_t off = (used + 255) & ~(size_t)255;
+    if (off > cap || need > cap - off)
+      throw Error(ZKVC_EINVAL, "request exceeds the fixed scratch buffer (" + std::to_string(cap) + " bytes)");
+    slots[slot] = Carved{off, need};
+    used = off + need;
+    return base ? base + off : nullptr;
+  }
+  bool arena_ = false;
+  char* arena_dev_ = nullptr;
+  char* arena_host_ = nullptr;
+  size_t arena_dev_cap_ = 0, arena_host_cap_ = 0, arena_dev_used_ = 0, arena_host_used_ = 0;
+  std::map<int, Carved> dev_slots_, host_slots_;
+
   std::map<int, DevBuf> bufs_;
   std::map<int, HostBuf> host_;
   std::vector<DevBuf> retired_;

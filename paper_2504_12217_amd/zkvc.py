@@ -57,7 +57,7 @@ class PkInfo(ctypes.Structure):
                 ("num_vars", ctypes.c_uint64), ("num_public", ctypes.c_uint64),
                 ("a_query", ctypes.c_uint64), ("b_query", ctypes.c_uint64),
                 ("l_query", ctypes.c_uint64), ("h_query", ctypes.c_uint64),
-                ("device_bytes", ctypes.c_uint64)]
+                ("device_bytes", ctypes.c_uint64), ("prove_bytes", ctypes.c_uint64)]
 
 
 class KernelStat(ctypes.Structure):
@@ -83,6 +83,11 @@ class ValuPeak(ctypes.Structure):
     _fields_ = [("mads", ctypes.c_double), ("ms", ctypes.c_double), ("mad_per_s", ctypes.c_double),
                 ("clock_ghz", ctypes.c_double), ("lane_ops_per_cu_clk", ctypes.c_double),
                 ("compute_units", ctypes.c_uint32)]
+
+
+class SpartanInfo(ctypes.Structure):
+    _fields_ = [("constraints", ctypes.c_uint64), ("sx", ctypes.c_uint32), ("sy", ctypes.c_uint32),
+                ("rows", ctypes.c_uint32), ("cols", ctypes.c_uint32), ("proof_bytes", ctypes.c_uint64)]
 
 
 class ProveStats(ctypes.Structure):
@@ -121,6 +126,13 @@ _SIGS = {
     "zkvc_pk_last_stats": (ctypes.c_int, [_VP, ctypes.POINTER(ProveStats)]),
     "zkvc_field_op": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
     "zkvc_valu_peak": (ctypes.c_int, [ctypes.c_uint32, ctypes.POINTER(ValuPeak), _VP]),
+    "zkvc_spartan_info": (ctypes.c_int, [ctypes.POINTER(Shape), ctypes.POINTER(SpartanInfo)]),
+    "zkvc_spartan_setup": (ctypes.c_int, [ctypes.POINTER(Shape), ctypes.POINTER(Fr), _VP, ctypes.c_size_t,
+                                          ctypes.POINTER(_VP), _VP]),
+    "zkvc_spartan_key_free": (ctypes.c_int, [_VP]),
+    "zkvc_spartan_prove": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]),
+    "zkvc_spartan_verify": (ctypes.c_int, [ctypes.POINTER(Shape), ctypes.POINTER(Fr), _VP, ctypes.c_size_t, _VP, _VP,
+                                           _VP, ctypes.c_size_t]),
     "zkvc_profile_begin": (ctypes.c_int, []),
     "zkvc_profile_read": (ctypes.c_int, [ctypes.POINTER(KernelStat), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
 }
@@ -455,3 +467,68 @@ def vk_header(vk):
     """(a, n, b, kind, log_n) from a verification-key blob."""
     _, a, n, b, kind, log_n = struct.unpack("<6I", vk[8:32])
     return a, n, b, kind, log_n
+
+
+# -------------------------------------------------------------------- Spartan (zkVC-S)
+def spartan_info(a, n, b, kind):
+    out = SpartanInfo()
+    _check(lib().zkvc_spartan_info(ctypes.byref(Shape(a, n, b, kind)), ctypes.byref(out)))
+    return out
+
+
+def _g1_array(points):
+    arr = (G1 * len(points))()
+    for k, (x, y) in enumerate(points):
+        for q in range(8):
+            arr[k].x[q] = (int(x) >> (32 * q)) & 0xFFFFFFFF
+            arr[k].y[q] = (int(y) >> (32 * q)) & 0xFFFFFFFF
+    return arr
+
+
+class SpartanKey:
+    """A device-resident Spartan key: shape, z and the commitment generators."""
+
+    def __init__(self, a, n, b, kind, z, gens, stream=None):
+        self.shape = (a, n, b, kind)
+        self.z = z
+        self.gens = _g1_array(gens)
+        self.info = spartan_info(a, n, b, kind)
+        h = _VP()
+        zz = fr(z)
+        _check(lib().zkvc_spartan_setup(ctypes.byref(Shape(a, n, b, kind)), ctypes.byref(zz),
+                                        ctypes.cast(self.gens, _VP), len(gens), ctypes.byref(h), _stream(stream)))
+        self.handle = h.value
+
+    def prove(self, X, W, stream=None):
+        """(Y int32 [a, b], proof bytes)."""
+        a, n, b, _ = self.shape
+        X = np.ascontiguousarray(X, dtype=np.int8)
+        W = np.ascontiguousarray(W, dtype=np.int8)
+        if X.shape != (a, n) or W.shape != (n, b):
+            raise ValueError("X or W does not match the key's shape")
+        Y = np.zeros((a, b), dtype=np.int32)
+        buf = (ctypes.c_uint8 * self.info.proof_bytes)()
+        _check(lib().zkvc_spartan_prove(self.handle, X.ctypes.data, W.ctypes.data, Y.ctypes.data,
+                                        ctypes.cast(buf, _VP), self.info.proof_bytes, _stream(stream)))
+        return Y, bytes(buf)
+
+    def verify(self, X, Y, proof):
+        a, n, b, kind = self.shape
+        X = np.ascontiguousarray(X, dtype=np.int8)
+        Y = np.ascontiguousarray(Y, dtype=np.int32)
+        pb = (ctypes.c_uint8 * len(proof)).from_buffer_copy(proof)
+        zz = fr(self.z)
+        return _check(lib().zkvc_spartan_verify(ctypes.byref(Shape(a, n, b, kind)), ctypes.byref(zz),
+                                                ctypes.cast(self.gens, _VP), len(self.gens), X.ctypes.data,
+                                                Y.ctypes.data, ctypes.cast(pb, _VP), len(proof)))
+
+    def close(self):
+        if self.handle:
+            lib().zkvc_spartan_key_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -77,9 +77,26 @@ def test_served_results_equal_single_proofs(zk, keys):
 
 
 def test_memory_budget_admits_one_job_at_a_time(zk, keys):
-    # a budget below any job's footprint still admits a single job per batch
-    sizes = _serve_and_check(zk, keys, _jobs(keys, 6, 2), max_batch=8, memory_budget=1)
+    # jobs of the two smallest keys and a budget that holds either job but no
+    # two of them: one job in flight at a time
+    small = sorted(keys, key=lambda k: k[4].info().prove_bytes)[:2]
+    est = [k[4].info().prove_bytes for k in small]
+    budget = max(est)
+    assert budget < est[0] + est[1] and 2 * min(est) > budget
+    sizes = _serve_and_check(zk, small, _jobs(small, 6, 2), max_batch=8, memory_budget=budget)
     assert max(sizes) == 1
+
+
+def test_job_larger_than_budget_is_rejected(zk, keys):
+    pk = keys[0][4]
+    X, W = synth.matmul_inputs(5, 4, 8, 4)
+    srv = zk.Server(max_batch=4, memory_budget=pk.info().prove_bytes - 1)
+    try:
+        with pytest.raises(zk.ZkvcError) as e:
+            srv.submit(pk, X, W, 5, 7)
+        assert e.value.code == zk.ENOMEM
+    finally:
+        srv.close()
 
 
 def test_server_argument_errors(zk, keys):

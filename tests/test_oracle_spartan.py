@@ -145,3 +145,17 @@ def test_layout_sizes_at_paper_shape():
     assert inst.m == 320 and inst.sx == 9
     assert inst.nw == 320 * 512 + 319 and inst.ell + 1 == 40769
     assert inst.sw == 18 and inst.sy == 19 and inst.rows == 512 and inst.cols == 512
+
+
+def test_proof_encoding_round_trip():
+    s, kind = r1cs.Shape(2, 3, 2), r1cs.CRPC
+    inst = sp.Instance(s, kind, 19)
+    gens = _gens(inst)
+    X, W = _inputs(s, 9)
+    proof, _ = sp.prove(inst, X, W, gens)
+    data = sp.proof_bytes(proof)
+    assert len(data) == inst.rows * 64 + (4 * inst.sx + 3 + 3 * inst.sy + inst.cols) * 32
+    back = sp.proof_from_bytes(inst, data)
+    assert back["comms"] == proof["comms"] and back["t"] == proof["t"]
+    assert back["sc1"] == proof["sc1"] and back["sc2"] == proof["sc2"] and back["vabc"] == tuple(proof["vabc"])
+    assert sp.proof_from_bytes(inst, data[:-1]) is None
