@@ -225,6 +225,25 @@ int zkvc_msm_g1(const void* d_points, const void* d_scalars, size_t n, uint32_t 
 int zkvc_msm_g2(const void* d_points, const void* d_scalars, size_t n, uint32_t flags, zkvc_g2* out,
                 void* hip_stream);
 
+/*
+ * zkvc_msm_g1 without allocating, for callers that cannot allocate memory:
+ * code under HIP graph capture, tight serving loops, and hosts that forbid
+ * device allocation.  Same arguments, layout, flags and result as
+ * zkvc_msm_g1 (the same kernels; the window width and task size always
+ * follow the built-in rules, never the autotuner's).  Its workspace is a
+ * fixed 56 MiB device array that each GPU holds from the library's load
+ * until the process ends, plus a fixed host array; no hipMalloc, hipFree or
+ * pinned allocation happens in the call.  n <= 65536; a larger n is rejected
+ * with ZKVC_EINVAL before anything is launched.  Calls in one process are
+ * serialized by a lock, since every call on a GPU shares that GPU's array
+ * (overlapping calls would race on it); the array keeps the last call's
+ * contents, and nothing in the pipeline reads a location it has not written
+ * in the same call.  Synchronous like zkvc_msm_g1.  Errors: ZKVC_EINVAL,
+ * ZKVC_EDEVICE.
+ */
+int zkvc_msm_g1_noalloc(const void* d_points, const void* d_scalars, size_t n, uint32_t flags, zkvc_g1* out,
+                        void* hip_stream);
+
 /* Message for the last error on the calling thread (or for the code if none). */
 const char* zkvc_strerror(int err);
 

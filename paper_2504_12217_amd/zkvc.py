@@ -118,6 +118,7 @@ _SIGS = {
     "zkvc_ntt_fr": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint32, _VP]),
     "zkvc_msm_g1": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, ctypes.c_uint32, ctypes.POINTER(G1), _VP]),
     "zkvc_msm_g2": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, ctypes.c_uint32, ctypes.POINTER(G2), _VP]),
+    "zkvc_msm_g1_noalloc": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, ctypes.c_uint32, ctypes.POINTER(G1), _VP]),
     "zkvc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "zkvc_fixed_base_g1": (ctypes.c_int, [_VP, ctypes.c_size_t, _VP, ctypes.c_uint32, _VP]),
     "zkvc_fixed_base_g2": (ctypes.c_int, [_VP, ctypes.c_size_t, _VP, ctypes.c_uint32, _VP]),
@@ -228,6 +229,13 @@ def ntt_fr(data, log_n, flags=0, stream=None):
 def msm_g1(points, scalars, n, flags=0, stream=None):
     out = G1()
     _check(lib().zkvc_msm_g1(_ptr(points), _ptr(scalars), n, flags, ctypes.byref(out), _stream(stream)))
+    return g1_to_tuple(out)
+
+
+def msm_g1_noalloc(points, scalars, n, flags=0, stream=None):
+    """zkvc_msm_g1 on the library's fixed scratch (no allocation); n <= 65536."""
+    out = G1()
+    _check(lib().zkvc_msm_g1_noalloc(_ptr(points), _ptr(scalars), n, flags, ctypes.byref(out), _stream(stream)))
     return g1_to_tuple(out)
 
 
