@@ -112,12 +112,12 @@ def roofline(stats, workload=None, measured=None):
     return name, out
 
 
-def time_proofs(zk, pk, X, W, r, s, steps, warmup, profile):
-    """Times `steps` proofs after `warmup` ones.  With profile set, the warm-up
+def time_proofs(zk, one, steps, warmup, profile):
+    """Times `steps` calls of one() (a proof) after `warmup` ones.  With profile set, the warm-up
     proofs time every instrumented launch (the per-kernel table), and the
-    timed proofs record only the launches of the kernels with an algorithmic
-    work model (two HIP events per such launch), among which the roofline
-    takes the one with the most device time over the timed region.
+    timed proofs record only the launches of the kernel with an algorithmic
+    work model that took the most device time in the warm-up (two HIP events
+    per launch), which the roofline reports.
     Returns (seconds, per-proof latencies, timed-region stats, warm-up stats)."""
     import torch
     stats_all = None
@@ -125,19 +125,23 @@ def time_proofs(zk, pk, X, W, r, s, steps, warmup, profile):
         zk.profile_select(None)
         zk.profile_begin()
     for _ in range(warmup):
-        zk.prove(pk, X, W, r, s)
+        one()
     torch.cuda.synchronize()
     if profile:
         stats_all = zk.profile_read()
-        # single-kernel scopes with an algorithmic work model (msm_sort, say,
-        # spans several kernels)
-        zk.profile_select(sorted(FMUL_PER_UNIT))
+        # the timed proofs record only the kernel with the most device time
+        # among the single-kernel scopes with an algorithmic work model
+        # (msm_sort, say, spans several kernels), so that the timed region
+        # carries two event records per launch of that kernel and no more
+        modeled = {k: v for k, v in stats_all.items() if k in FMUL_PER_UNIT}
+        dom = max(modeled, key=lambda k: modeled[k][1]) if modeled else None
+        zk.profile_select([dom] if dom else sorted(FMUL_PER_UNIT))
         zk.profile_begin()
     lat = []
     t0 = time.perf_counter()
     for _ in range(steps):
         t = time.perf_counter()
-        zk.prove(pk, X, W, r, s)
+        one()
         lat.append(time.perf_counter() - t)
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
@@ -574,16 +578,26 @@ def main():
     t0 = time.perf_counter()
     pk = zkvc.setup(a, n, b, main_kind, tox, z if main_kind == zkvc.CRPC_PSQ else None)
     setup_crpc_s = time.perf_counter() - t0
-    log(f"timing {args.steps} {args.circuit} proofs")
-    total, lat, stats, stats_warm = time_proofs(zkvc, pk, X, W, r, s, args.steps, args.warmup, profile=True)
-    Y, proof = zkvc.prove(pk, X, W, r, s)
-    ok = zkvc.verify(pk.vk, X, Y, proof) == 1
+    # X and W resident in HBM, Y written there: nothing but the proof crosses PCIe
+    Xd = torch.from_numpy(X).to("cuda")
+    Wd = torch.from_numpy(W).to("cuda")
+    Yd = torch.empty((a, b), dtype=torch.int32, device="cuda")
+    prove_dev = lambda: zkvc.prove_device(pk, Xd, Wd, r, s, Yd)  # noqa: E731
+    log(f"timing {args.steps} {args.circuit} proofs (operands in HBM)")
+    total, lat, stats, stats_warm = time_proofs(zkvc, prove_dev, args.steps, args.warmup, profile=True)
     st = pk.last_stats()
-    # the same proofs replaying a captured HIP graph instead of eager launches
+    proof = prove_dev()
+    Y = Yd.cpu().numpy()
+    Yh, proof_h = zkvc.prove(pk, X, W, r, s)
+    ok = zkvc.verify(pk.vk, X, Y, proof) == 1 and bytes(proof_h) == bytes(proof) and np.array_equal(Yh, Y)
+    # the host-buffer interface: X, W cross PCIe in the call and Y comes back
     steps_e = max(5, args.steps // 3)
+    log(f"timing {steps_e} {args.circuit} proofs from host buffers")
+    th, _, _, _ = time_proofs(zkvc, lambda: zkvc.prove(pk, X, W, r, s), steps_e, 2, profile=False)
+    # the same proofs replaying a captured HIP graph instead of eager launches
     log(f"timing {steps_e} {args.circuit} proofs with graph replay")
     prev_graphs = zkvc.set_graphs(1)
-    te, late, _, _ = time_proofs(zkvc, pk, X, W, r, s, steps_e, 2, profile=False)
+    te, late, _, _ = time_proofs(zkvc, prove_dev, steps_e, 2, profile=False)
     zkvc.set_graphs(prev_graphs)
     stage_ms = {"witness": round(st.witness_ms, 3), "qap_ntt": round(st.ntt_ms, 3),
                 "msm_all_concurrent": round(st.msm_ms, 3), "host_windows_and_assembly": round(st.host_ms, 3),
@@ -615,6 +629,9 @@ def main():
         "latency_ms": {"p50": round(lat_ms[len(lat_ms) // 2], 3),
                        "p99": round(lat_ms[min(len(lat_ms) - 1, int(0.99 * len(lat_ms)))], 3)},
         "stage_ms_last_proof": stage_ms,
+        "host_buffers": {"proofs_per_s": round(steps_e / th, 3), "ms_per_proof": round(th / steps_e * 1e3, 3),
+                         "note": "zkvc_prove with X, W and Y in host memory (PCIe-inclusive: ~276 KB cross "
+                                 "per proof); value above uses zkvc_prove_device with operands in HBM"},
         "graph_replay": {"proofs_per_s": round(steps_e / te, 3), "ms_per_proof": round(te / steps_e * 1e3, 3),
                          "note": "the same proofs replaying a captured HIP graph (zkvc_set_graphs(1)); "
                                  "value above uses the default eager launches on three streams"},
@@ -636,9 +653,10 @@ def main():
         setup_plain = time.perf_counter() - t0
         steps_p = max(3, args.steps // 3)
         log(f"timing {steps_p} plain proofs")
-        tp, latp, statsp, _ = time_proofs(zkvc, pkp, X, W, r, s, steps_p, 2, profile=True)
-        Yp, pp = zkvc.prove(pkp, X, W, r, s)
-        okp = zkvc.verify(pkp.vk, X, Yp, pp) == 1
+        tp, latp, statsp, _ = time_proofs(zkvc, lambda: zkvc.prove_device(pkp, Xd, Wd, r, s, Yd), steps_p, 2,
+                                          profile=True)
+        pp = zkvc.prove_device(pkp, Xd, Wd, r, s, Yd)
+        okp = zkvc.verify(pkp.vk, X, Yd.cpu().numpy(), pp) == 1
         pkp.close()
         name_p, roof_p = roofline(statsp, "plain_49x320x512", mpeak)
         out["plain"] = {"workload": "same matmul, per-product circuit: 8,028,160 constraints, QAP domain 2^23",

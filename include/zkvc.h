@@ -102,6 +102,18 @@ int zkvc_pk_free(zkvc_pk* pk);
 int zkvc_prove(const zkvc_pk* pk, const int8_t* X, const int8_t* W, const zkvc_fr* r, const zkvc_fr* s,
                int32_t* Y_out, zkvc_proof* proof_out, void* hip_stream);
 
+/*
+ * Prove with device-resident operands (Section II; the same proof as
+ * zkvc_prove): d_X (int8 a x n row-major), d_W (int8 n x b row-major) and
+ * d_Y (int32 a x b row-major, written) are device buffers on the proving
+ * key's device, owned by the caller; nothing crosses PCIe but the 256-byte
+ * proof (host).  The call is synchronous: d_Y and *proof_out are complete
+ * when it returns.  Errors: ZKVC_EINVAL (null pointer, a buffer that is not
+ * device memory of the key's device, r or s >= r), ZKVC_ENOMEM, ZKVC_EDEVICE.
+ */
+int zkvc_prove_device(const zkvc_pk* pk, const int8_t* d_X, const int8_t* d_W, const zkvc_fr* r, const zkvc_fr* s,
+                      int32_t* d_Y, zkvc_proof* proof_out, void* hip_stream);
+
 /* One proof of a batch (zkvc_prove_batch): the arguments of zkvc_prove. */
 typedef struct {
   const zkvc_pk* pk;      /* proving key of this proof's shape and circuit kind */

@@ -65,6 +65,37 @@ int zkvc_prove(const zkvc_pk* pk, const int8_t* X, const int8_t* W, const zkvc_f
 }
 
 namespace {
+// A caller's device buffer: memory of the given device (device or managed).
+void require_device_buffer(const void* p, int dev, const char* what) {
+  hipPointerAttribute_t at{};
+  const hipError_t e = hipPointerGetAttributes(&at, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(ZKVC_EINVAL, std::string(what) + " is not a device buffer");
+  }
+  ZK_REQUIRE(at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged,
+             std::string(what) + " is not a device buffer");
+  ZK_REQUIRE(at.device == dev, std::string(what) + " lives on another device");
+}
+}  // namespace
+
+int zkvc_prove_device(const zkvc_pk* pk, const int8_t* d_X, const int8_t* d_W, const zkvc_fr* r, const zkvc_fr* s,
+                      int32_t* d_Y, zkvc_proof* proof_out, void* hip_stream) {
+  return guarded([&] {
+    ZK_REQUIRE(pk && d_X && d_W && r && s && d_Y && proof_out, "null argument");
+    zkvc_pk* k = const_cast<zkvc_pk*>(pk);
+    std::lock_guard<std::mutex> lock(k->mu);
+    const host::HFr rr = fr_in(*r, "r"), ss = fr_in(*s, "s");
+    int dev = current_device();
+    ZK_REQUIRE(dev == k->device, "the proving key lives on another device");
+    require_device_buffer(d_X, dev, "X");
+    require_device_buffer(d_W, dev, "W");
+    require_device_buffer(d_Y, dev, "Y");
+    groth16_prove(k, d_X, d_W, rr, ss, d_Y, proof_out, (hipStream_t)hip_stream, true);
+  });
+}
+
+namespace {
 // One batch context per (device, stream), created on first use and kept until
 // the process ends.  The table is never destroyed: a context's destructor
 // synchronizes and destroys streams and events, and a static destructor

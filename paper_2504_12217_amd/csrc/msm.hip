@@ -75,11 +75,16 @@ struct JobDev {
   uint32_t blk_digits;      // first block of the digit grid
   uint32_t blk_hs;          // first block of the histogram / scatter grid (nw * nch blocks, or nch)
 };
-// The jobs of a batch live in a device table (uploaded with the batch), so a
-// batch may hold any number of MSMs: every proof of a proving batch at once.
+// A batch of up to INLINE_JOBS jobs (a single proof's lanes, a single MSM)
+// carries its job records in the kernel arguments; a larger batch (every
+// proof of a proving batch at once) keeps them in a device table uploaded
+// with the batch.  No upload means no copy on the lane's critical path.
+constexpr int INLINE_JOBS = 8;
 struct BatchDev {
   int njobs;
   const JobDev* jobs;
+  JobDev inl[INLINE_JOBS];
+  __device__ __forceinline__ const JobDev& job(int k) const { return njobs <= INLINE_JOBS ? inl[k] : jobs[k]; }
 };
 
 // The job owning index v of a per-job range whose first index is the field F
@@ -89,7 +94,7 @@ __device__ __forceinline__ int job_of(const BatchDev& B, uint32_t v) {
   int lo = 0, hi = B.njobs - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (B.jobs[mid].*F <= v)
+    if (B.job(mid).*F <= v)
       lo = mid;
     else
       hi = mid - 1;
@@ -113,7 +118,7 @@ constexpr uint64_t FEW_ENTRIES = 1ull << 19;
 template <class F>
 __global__ void __launch_bounds__(256) k_msm_digits(BatchDev B, uint32_t* digits) {
   const int k = job_of<&JobDev::blk_digits>(B, blockIdx.x);
-  const JobDev& J = B.jobs[k];
+  const JobDev& J = B.job(k);
   const uint32_t j = (blockIdx.x - J.blk_digits) * 256 + threadIdx.x;
   if (j >= J.n) return;
   const uint32_t idx = J.bitrev_bits ? bitrev_n(j, J.bitrev_bits) : j;
@@ -209,7 +214,7 @@ __device__ __forceinline__ HsRange hs_range(const JobDev& J, const uint32_t* dig
 __global__ void __launch_bounds__(HS_THREADS) k_msm_hist(BatchDev B, const uint32_t* digits, uint32_t* hist) {
   extern __shared__ uint32_t cnt[];
   const int k = job_of<&JobDev::blk_hs>(B, blockIdx.x);
-  const JobDev& J = B.jobs[k];
+  const JobDev& J = B.job(k);
   const HsRange R = hs_range(J, digits, blockIdx.x - J.blk_hs);
   for (uint32_t b = threadIdx.x; b < J.nb; b += HS_THREADS) cnt[b] = 0u;
   __syncthreads();
@@ -231,7 +236,7 @@ __global__ void __launch_bounds__(HS_THREADS) k_msm_scatter(BatchDev B, const ui
                                                             uint32_t* sorted) {
   extern __shared__ uint32_t cur[];
   const int k = job_of<&JobDev::blk_hs>(B, blockIdx.x);
-  const JobDev& J = B.jobs[k];
+  const JobDev& J = B.job(k);
   const HsRange R = hs_range(J, digits, blockIdx.x - J.blk_hs);
   const uint32_t* o = offs + R.col;
   for (uint32_t b = threadIdx.x; b < J.nb; b += HS_THREADS) cur[b] = o[(size_t)b * J.nchw];
@@ -268,7 +273,7 @@ __global__ void k_msm_task_counts(BatchDev B, const uint32_t* offs, uint32_t nbt
   }
   if (f >= nbt) return;
   const int k = job_of<&JobDev::bucket_base>(B, f);
-  const JobDev& J = B.jobs[k];
+  const JobDev& J = B.job(k);
   const size_t lf = f - J.bucket_base;
   // the bucket after the job's last one starts the next job's range (or the total)
   const uint32_t s = offs[J.hist_base + lf * J.nchw];
@@ -356,15 +361,20 @@ __device__ __forceinline__ Xyzz<F> quad_tree_sum(Xyzz<F> acc, uint32_t* sh, uint
 template <class F>
 __global__ void __launch_bounds__(64) k_msm_acc(BatchDev B, const uint4* th_tasks, const uint4* wg_tasks,
                                                 const uint32_t* counters, uint32_t th_blocks, const uint32_t* sorted,
-                                                uint32_t* partials, int quad) {
+                                                uint32_t* partials, int quad, const uint32_t* total,
+                                                uint32_t* work_out) {
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
   constexpr int AW = PointIO<F>::AFF_WORDS;
   __shared__ uint32_t sh[WG_THREADS / 2 * XW];
+  if (work_out && blockIdx.x == 0 && threadIdx.x == 0) {  // the work count for a profile (host memory)
+    *work_out = *total;
+    __threadfence_system();
+  }
   if (blockIdx.x < th_blocks) {
     const uint32_t ntasks = counters[0];
     for (uint32_t t = blockIdx.x * 64 + threadIdx.x; t < ntasks; t += th_blocks * 64) {
       const uint4 task = th_tasks[t];
-      const uint32_t* points = B.jobs[task.w].points;
+      const uint32_t* points = B.job(task.w).points;
       Xyzz<F> acc = Xyzz<F>::inf();
       // the next entry's point is loaded while the current one is added
       const uint32_t end = task.x + task.y;
@@ -389,7 +399,7 @@ __global__ void __launch_bounds__(64) k_msm_acc(BatchDev B, const uint4* th_task
   const uint32_t team = threadIdx.x >> 2, tq = threadIdx.x & 3u;
   for (uint32_t t = blockIdx.x - th_blocks; t < ntasks; t += wg_blocks) {
     const uint4 task = wg_tasks[t];
-    const uint32_t* points = B.jobs[task.w].points;
+    const uint32_t* points = B.job(task.w).points;
     Xyzz<F> acc = Xyzz<F>::inf();
     if (quad) {
       // 16 quads, each summing a strided share with cooperative additions
@@ -505,7 +515,7 @@ __global__ void __launch_bounds__(BP_THREADS) k_msm_bitplanes(BatchDev B, const 
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
   __shared__ uint32_t sh[BP_THREADS / 8 * XW];
   const int k = job_of<&JobDev::blk_bp>(B, blockIdx.x);
-  const JobDev& J = B.jobs[k];
+  const JobDev& J = B.job(k);
   const uint32_t local = blockIdx.x - J.blk_bp;
   const uint32_t q = local / J.bpb, slice = local % J.bpb;
   const uint32_t c = (uint32_t)J.c, nb = J.nb;
@@ -525,10 +535,12 @@ __global__ void __launch_bounds__(BP_THREADS) k_msm_bitplanes(BatchDev B, const 
   }
   acc = quad_tree_sum<F>(acc, sh, nteams);
   if (threadIdx.x != 0) return;
-  if (J.bpb == 1)  // the block's sum is the plane
+  if (J.bpb == 1) {  // the block's sum is the plane
     PointIO<F>::store_xyzz(S + ((size_t)J.plane_base + q) * XW, Xyzz<F>::canon(acc));
-  else
+    __threadfence_system();  // S may be host memory
+  } else {
     PointIO<F>::store_xyzz(part + (size_t)blockIdx.x * XW, acc);
+  }
 }
 
 // One wavefront (16 quads) per plane: the sum of the plane's bpb block sums.
@@ -537,7 +549,7 @@ __global__ void __launch_bounds__(64) k_msm_plane_sums(BatchDev B, const uint32_
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
   __shared__ uint32_t sh[8 * XW];
   const int k = job_of<&JobDev::plane_base>(B, blockIdx.x);
-  const JobDev& J = B.jobs[k];
+  const JobDev& J = B.job(k);
   if (J.bpb == 1) return;  // written by k_msm_bitplanes
   const uint32_t q = blockIdx.x - J.plane_base;
   const uint32_t* pp = part + ((size_t)J.blk_bp + (size_t)q * J.bpb) * XW;
@@ -546,7 +558,10 @@ __global__ void __launch_bounds__(64) k_msm_plane_sums(BatchDev B, const uint32_
   for (uint32_t t = threadIdx.x >> 2; t < J.bpb; t += 16)
     acc = QuadOps<F>::add(acc, PointIO<F>::load_xyzz(pp + (size_t)t * XW), tq);
   acc = quad_tree_sum<F>(acc, sh, 16);
-  if (threadIdx.x == 0) PointIO<F>::store_xyzz(S + (size_t)blockIdx.x * XW, Xyzz<F>::canon(acc));
+  if (threadIdx.x == 0) {
+    PointIO<F>::store_xyzz(S + (size_t)blockIdx.x * XW, Xyzz<F>::canon(acc));
+    __threadfence_system();  // S may be host memory
+  }
 }
 
 // ---------------------------------------------------------------- host driver
@@ -774,16 +789,21 @@ static MsmBufs msm_buffers(const BatchPlan& p, Workspace& ws, int XW) {
   b.wg_tasks = ws.get<uint4>(S_PART1, p.max_wg_tasks * 16);
   b.part = ws.get(S_PART0, p.max_partials * XW * 4);
   b.buckets = ws.get(S_SEG, p.nbt * XW * 4);
-  b.win = ws.get(S_WIN, p.nplanes * XW * 4);
+  // plane sums: written by the kernels straight into pinned host memory when
+  // the workspace's host buffers are device-visible, else copied back
+  b.win = ws.host_mapped() ? nullptr : ws.get(S_WIN, p.nplanes * XW * 4);
   b.bp_part = ws.get(S_BP_PART, p.bp_blocks * XW * 4);
   b.heavy = ws.get(S_HEAVY, p.nbt * 4);
   b.meta = ws.get(S_META, 64 * 4);  // [2] partials [8..10] thread tasks, wavefront tasks, heavy buckets
   b.win_host = ws.host<uint32_t>(S_WIN, p.nplanes * XW * 4);
   ws.get(S_SCRATCH, (size_t)cdiv(std::max(p.nh, p.nbt), 2048) * 4 + 64);
-  // the job table, through pinned memory (the workspace is not reused before
-  // this stream has completed)
-  b.jt_host = ws.host<JobDev>(S_JOBS, nj * sizeof(JobDev));
-  b.jt_dev = ws.get<JobDev>(S_JOBS, nj * sizeof(JobDev));
+  // a job table beyond the kernel arguments, through pinned memory (the
+  // workspace is not reused before this stream has completed)
+  b.jt_host = b.jt_dev = nullptr;
+  if (nj > (size_t)INLINE_JOBS) {
+    b.jt_host = ws.host<JobDev>(S_JOBS, nj * sizeof(JobDev));
+    b.jt_dev = ws.get<JobDev>(S_JOBS, nj * sizeof(JobDev));
+  }
   return b;
 }
 
@@ -816,10 +836,15 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
            *part_off = bf.part_off, *sorted = bf.sorted, *part = bf.part, *buckets = bf.buckets, *win = bf.win,
            *bp_part = bf.bp_part, *heavy = bf.heavy, *meta = bf.meta, *win_host = bf.win_host;
   uint4 *th_tasks = bf.th_tasks, *wg_tasks = bf.wg_tasks;
-  JobDev *jt_host = bf.jt_host, *jt_dev = bf.jt_dev;
-  std::memcpy(jt_host, p.jobs.data(), nj * sizeof(JobDev));
-  ZK_HIP(hipMemcpyAsync(jt_dev, jt_host, nj * sizeof(JobDev), hipMemcpyHostToDevice, st));
-  const BatchDev dev{nj, jt_dev};
+  BatchDev dev{};
+  dev.njobs = nj;
+  if (nj <= INLINE_JOBS) {
+    for (int k = 0; k < nj; k++) dev.inl[k] = p.jobs[k];
+  } else {
+    std::memcpy(bf.jt_host, p.jobs.data(), nj * sizeof(JobDev));
+    ZK_HIP(hipMemcpyAsync(bf.jt_dev, bf.jt_host, nj * sizeof(JobDev), hipMemcpyHostToDevice, st));
+    dev.jobs = bf.jt_dev;
+  }
   for (int k = 0; k < nj; k++) {
     MsmPending& pd = pend[p.map[k]];
     pd.empty = false;
@@ -827,6 +852,7 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
     pd.nw = (int)p.jobs[k].nwb;
     pd.win_host = win_host + (size_t)p.jobs[k].plane_base * XW;
   }
+  uint32_t* const win_out = win ? win : win_host;
   const size_t lds = (size_t)p.max_nb * 4;
   {
     ProfScope ps(g1 ? "msm_digits_g1" : "msm_digits_g2", st, (double)p.ndigits);
@@ -858,9 +884,8 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
     const unsigned th_blocks = (unsigned)std::min<uint64_t>(cdiv(p.max_th_tasks, 64), 65536);
     const unsigned wg_blocks = (unsigned)std::min<uint64_t>(p.max_wg_tasks, 4096);
     hipLaunchKernelGGL(k_msm_acc<F>, dim3(th_blocks + wg_blocks), dim3(64), 0, st, dev, th_tasks, wg_tasks,
-                       meta + 8, th_blocks, sorted, part, p.quad ? 1 : 0);
+                       meta + 8, th_blocks, sorted, part, p.quad ? 1 : 0, offs + p.nh, ps.work_word());
     ZK_HIP(hipGetLastError());
-    ps.set_work_from_device(offs + p.nh);
   }
   {
     ProfScope ps(g1 ? "msm_finalize_g1" : "msm_finalize_g2", st, (double)nbt);
@@ -881,17 +906,17 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
     unsigned bp_threads = 64;
     while (bp_threads < (unsigned)BP_THREADS && bp_threads < 2 * per_block) bp_threads *= 2;
     hipLaunchKernelGGL(k_msm_bitplanes<F>, dim3((unsigned)p.bp_blocks), dim3(bp_threads), 0, st, dev, buckets,
-                       bp_part, win);
+                       bp_part, win_out);
     ZK_HIP(hipGetLastError());
     // planes of one block each are final already
     bool split = false;
     for (int k = 0; k < nj; k++) split = split || p.jobs[k].bpb > 1;
     if (split) {
-      hipLaunchKernelGGL(k_msm_plane_sums<F>, dim3((unsigned)p.nplanes), dim3(64), 0, st, dev, bp_part, win);
+      hipLaunchKernelGGL(k_msm_plane_sums<F>, dim3((unsigned)p.nplanes), dim3(64), 0, st, dev, bp_part, win_out);
       ZK_HIP(hipGetLastError());
     }
   }
-  ZK_HIP(hipMemcpyAsync(win_host, win, p.nplanes * XW * 4, hipMemcpyDeviceToHost, st));
+  if (win) ZK_HIP(hipMemcpyAsync(win_host, win, p.nplanes * XW * 4, hipMemcpyDeviceToHost, st));
 }
 
 // Horner over the bit planes on the host; call after the MSM's stream has completed.

@@ -16,8 +16,8 @@ namespace zkvc {
 namespace {
 
 // Records come from fixed pools (events created once, one pinned word each
-// for device-side work counts), so recording costs two event records and at
-// most one 4-byte copy per launch.
+// for device-side work counts, written by the kernel itself), so recording
+// costs two event records per launch.
 constexpr int POOL = 8192;
 
 struct Rec {
@@ -145,13 +145,14 @@ ProfScope::ProfScope(const char* name, hipStream_t st, double work) : st_(st) {
   slot_ = k;
 }
 
-void ProfScope::set_work_from_device(const uint32_t* p) {
-  if (slot_ < 0) return;
+uint32_t* ProfScope::work_word() {
+  if (slot_ < 0) return nullptr;
   if (graph_) {
-    if (hipMemcpyAsync(g_gwords + slot_, p, 4, hipMemcpyDeviceToHost, st_) == hipSuccess) g_grecs[slot_].work_dev = true;
-    return;
+    g_grecs[slot_].work_dev = true;
+    return g_gwords + slot_;
   }
-  if (hipMemcpyAsync(g_words + slot_, p, 4, hipMemcpyDeviceToHost, st_) == hipSuccess) g_recs[slot_].work_dev = true;
+  g_recs[slot_].work_dev = true;
+  return g_words + slot_;
 }
 
 void ProfScope::stop() {

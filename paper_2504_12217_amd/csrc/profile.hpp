@@ -26,8 +26,9 @@ class ProfScope {
   ProfScope(const char* name, hipStream_t st, double work);
   ~ProfScope();
   void stop();
-  // work units = the device word at p when the profile is read (copied on the stream now)
-  void set_work_from_device(const uint32_t* p);
+  // A pinned, device-visible host word that a kernel of this scope writes
+  // with the work count (no copy launched); null when this scope records nothing.
+  uint32_t* work_word();
 
  private:
   int slot_ = -1;

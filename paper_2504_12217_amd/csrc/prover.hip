@@ -1010,16 +1010,25 @@ struct Slot {
   int8_t *xh, *wh;  // pinned staging of X and W
 };
 
+// The copy of Y (all host-buffer jobs of a batch) back to pinned memory.
+struct YCopy {
+  void* dst = nullptr;
+  const void* src = nullptr;
+  size_t bytes = 0;
+};
+
 // Witness and evaluation vectors of every proof of a batch, one launch per
-// kernel for all proofs.  X and W of all proofs cross PCIe in one copy from
-// pinned staging, Y of all proofs comes back in one copy to pinned memory:
-// no host wait inside the enqueue.
-std::vector<Slot> enqueue_witness_batch(const ProveJob* jobs, size_t nj, ProveGen& G, hipStream_t st) {
+// kernel for all proofs.  X and W of all host-buffer proofs cross PCIe in one
+// copy from pinned staging, and their Y comes back in one copy to pinned
+// memory (described in *ycopy, enqueued by the caller); device-buffer proofs
+// read and write the caller's buffers.  No host wait inside the enqueue.
+std::vector<Slot> enqueue_witness_batch(const ProveJob* jobs, size_t nj, ProveGen& G, hipStream_t st, YCopy* ycopy) {
   ZK_REQUIRE(nj <= 65535, "at most 65535 proofs per batch");
   auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
   std::vector<size_t> xo(nj), wo(nj), yo(nj);
   size_t xw_bytes = 0, y_bytes = 0;
   for (size_t j = 0; j < nj; j++) {
+    if (jobs[j].device_io) continue;
     const Layout& L = jobs[j].pk->L;
     xo[j] = xw_bytes;
     xw_bytes += align((size_t)L.a * L.n);
@@ -1028,10 +1037,10 @@ std::vector<Slot> enqueue_witness_batch(const ProveJob* jobs, size_t nj, ProveGe
     yo[j] = y_bytes;
     y_bytes += align((size_t)L.a * L.b * 4);
   }
-  int8_t* xw_host = G.shared.host<int8_t>(C_XW, xw_bytes);
-  int8_t* xw_dev = G.shared.get<int8_t>(C_XW, xw_bytes);
-  int8_t* y_host = G.shared.host<int8_t>(C_Y, y_bytes);
-  int8_t* y_dev = G.shared.get<int8_t>(C_Y, y_bytes);
+  int8_t* xw_host = xw_bytes ? G.shared.host<int8_t>(C_XW, xw_bytes) : nullptr;
+  int8_t* xw_dev = xw_bytes ? G.shared.get<int8_t>(C_XW, xw_bytes) : nullptr;
+  int8_t* y_host = y_bytes ? G.shared.host<int8_t>(C_Y, y_bytes) : nullptr;
+  int8_t* y_dev = y_bytes ? G.shared.get<int8_t>(C_Y, y_bytes) : nullptr;
   std::vector<Slot> slots(nj);
   std::vector<WitJob> wj(nj);
   uint32_t max_a = 0, max_b = 0, max_n_crpc = 0;
@@ -1046,11 +1055,14 @@ std::vector<Slot> enqueue_witness_batch(const ProveJob* jobs, size_t nj, ProveGe
     S.aev = ws.get(P_AEV, L.N * 32);
     S.bev = ws.get(P_BEV, L.N * 32);
     S.cev = ws.get(P_CEV, L.N * 32);
-    S.yh = reinterpret_cast<int32_t*>(y_host + yo[j]);
-    S.xh = xw_host + xo[j];
-    S.wh = xw_host + wo[j];
-    std::memcpy(S.xh, jobs[j].X, (size_t)L.a * L.n);
-    std::memcpy(S.wh, jobs[j].W, (size_t)L.n * L.b);
+    const bool dio = jobs[j].device_io;
+    S.yh = dio ? nullptr : reinterpret_cast<int32_t*>(y_host + yo[j]);
+    S.xh = dio ? nullptr : xw_host + xo[j];
+    S.wh = dio ? nullptr : xw_host + wo[j];
+    if (!dio) {
+      std::memcpy(S.xh, jobs[j].X, (size_t)L.a * L.n);
+      std::memcpy(S.wh, jobs[j].W, (size_t)L.n * L.b);
+    }
     WitJob& J = wj[j];
     J.kind = L.kind;
     J.a = L.a;
@@ -1060,9 +1072,9 @@ std::vector<Slot> enqueue_witness_batch(const ProveJob* jobs, size_t nj, ProveGe
     J.ell = L.ell;
     J.aux_start = L.aux_start;
     J.N = L.N;
-    J.X = xw_dev + xo[j];
-    J.W = xw_dev + wo[j];
-    J.Y = reinterpret_cast<int32_t*>(y_dev + yo[j]);
+    J.X = dio ? jobs[j].X : xw_dev + xo[j];
+    J.W = dio ? jobs[j].W : xw_dev + wo[j];
+    J.Y = dio ? jobs[j].Y : reinterpret_cast<int32_t*>(y_dev + yo[j]);
     J.zpow = pk->zpow.get();
     J.assign = S.assign;
     J.aev = S.aev;
@@ -1087,7 +1099,7 @@ std::vector<Slot> enqueue_witness_batch(const ProveJob* jobs, size_t nj, ProveGe
     max_pub = std::max<uint64_t>(max_pub, L.aux_start);
     max_tail = std::max<uint64_t>(max_tail, L.N - L.m);
   }
-  ZK_HIP(hipMemcpyAsync(xw_dev, xw_host, xw_bytes, hipMemcpyHostToDevice, st));
+  if (xw_bytes) ZK_HIP(hipMemcpyAsync(xw_dev, xw_host, xw_bytes, hipMemcpyHostToDevice, st));
   WitTable T{};
   if (nj == 1) {
     T.one = wj[0];
@@ -1126,7 +1138,10 @@ std::vector<Slot> enqueue_witness_batch(const ProveJob* jobs, size_t nj, ProveGe
   hipLaunchKernelGGL(k_rows_tail, dim3(cdiv(max_tail, 256), J), dim3(256), 0, st, T);
   ZK_HIP(hipGetLastError());
   if (!rows_only) ZK_HIP(hipEventRecord(G.wrow_ev, st));
-  ZK_HIP(hipMemcpyAsync(y_host, y_dev, y_bytes, hipMemcpyDeviceToHost, st));
+  // Y of host-buffer jobs goes back after the quotients (off the path to the H lane)
+  ycopy->dst = y_host;
+  ycopy->src = y_dev;
+  ycopy->bytes = y_bytes;
   return slots;
 }
 
@@ -1395,7 +1410,13 @@ BatchRunPtr prove_batch_begin(ProveCtx& ctx, int g, const ProveJob* jobs_in, siz
   key.push_back((uint64_t)(uintptr_t)st);
   key.push_back(tuning_fingerprint());
   key.push_back(profiling_enabled() ? 1 : 0);
-  for (size_t j = 0; j < nj; j++) key.push_back(jobs_in[j].pk->id);
+  for (size_t j = 0; j < nj; j++) {
+    key.push_back(jobs_in[j].pk->id);
+    // device buffers are baked into a captured graph
+    key.push_back(jobs_in[j].device_io ? (uint64_t)(uintptr_t)jobs_in[j].X : 0);
+    key.push_back(jobs_in[j].device_io ? (uint64_t)(uintptr_t)jobs_in[j].W : 0);
+    key.push_back(jobs_in[j].device_io ? (uint64_t)(uintptr_t)jobs_in[j].Y : 0);
+  }
   const bool graphs = ctx.graphs && g_graphs.load();
   // graphs run on the context's own stream, after everything queued on the
   // calling stream (which may be the null stream, which cannot be captured)
@@ -1416,6 +1437,7 @@ BatchRunPtr prove_batch_begin(ProveCtx& ctx, int g, const ProveJob* jobs_in, siz
     R.host_t0 = std::chrono::steady_clock::now();
     R.graphed = true;
     for (size_t j = 0; j < nj; j++) {
+      if (jobs_in[j].device_io) continue;  // the buffers are part of the key
       const Layout& L = jobs_in[j].pk->L;
       std::memcpy(R.slots[j].xh, jobs_in[j].X, (size_t)L.a * L.n);
       std::memcpy(R.slots[j].wh, jobs_in[j].W, (size_t)L.n * L.b);
@@ -1494,7 +1516,8 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
   record_ext(G.ev[0], st, capture);
 
   // ---- witnesses and evaluation vectors
-  R.slots = enqueue_witness_batch(jobs, nj, G, st);
+  YCopy ycopy;
+  R.slots = enqueue_witness_batch(jobs, nj, G, st, &ycopy);
   std::vector<Slot>& slots = R.slots;
   record_ext(G.ev[1], st, capture);
   ZK_HIP(hipEventRecord(G.witness_ev, st));
@@ -1533,6 +1556,8 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
   auto g1_lane = [&] {
     ZK_HIP(hipStreamWaitEvent(lane_g1, G.witness_ev, 0));
     msm_enqueue_batch_g1(in_g1.data(), (int)in_g1.size(), G.lane_ws[ProveCtx::LANE_G1], lane_g1, R.pend_g1.data());
+    // Y of host-buffer jobs (final since the witness event) at the end of this lane
+    if (ycopy.bytes) ZK_HIP(hipMemcpyAsync(ycopy.dst, ycopy.src, ycopy.bytes, hipMemcpyDeviceToHost, lane_g1));
     record_ext(G.done_ev[ProveCtx::LANE_G1], lane_g1, capture);
     record_ext(G.lane_t[ProveCtx::LANE_G1], lane_g1, capture);
   };
@@ -1714,7 +1739,7 @@ void prove_batch_finish(ProveCtx& ctx, BatchRun& R) {
     g1_to_abi(g1p[j].A, &jobs[j].out->A);
     g2_to_abi(Bp[j], &jobs[j].out->B);
     g1_to_abi(C, &jobs[j].out->C);
-    std::memcpy(jobs[j].Y, slots[j].yh, (size_t)L.a * L.b * 4);
+    if (!jobs[j].device_io) std::memcpy(jobs[j].Y, slots[j].yh, (size_t)L.a * L.b * 4);
   }
   const auto host_t1 = std::chrono::steady_clock::now();
   auto ms = [&](hipEvent_t a, hipEvent_t b) {
@@ -1759,7 +1784,7 @@ void groth16_prove_batch(ProveCtx& ctx, const ProveJob* jobs, size_t nj, hipStre
 
 
 void groth16_prove(zkvc_pk* pk, const int8_t* X, const int8_t* W, const host::HFr& r, const host::HFr& s, int32_t* Y,
-                   zkvc_proof* out, hipStream_t st) {
+                   zkvc_proof* out, hipStream_t st, bool device_io) {
   if (!pk->ctx) pk->ctx.reset(new ProveCtx());
   ProveJob j;
   j.pk = pk;
@@ -1769,6 +1794,7 @@ void groth16_prove(zkvc_pk* pk, const int8_t* X, const int8_t* W, const host::HF
   j.s = s;
   j.Y = Y;
   j.out = out;
+  j.device_io = device_io;
   groth16_prove_batch(*pk->ctx, &j, 1, st);
   pk->last = pk->ctx->last;
 }

@@ -196,6 +196,7 @@ struct ProveJob {
   host::HFr r, s;
   int32_t* Y = nullptr;
   zkvc_proof* out = nullptr;
+  bool device_io = false;  // X, W and Y are device buffers (no staging, no copies)
 };
 
 // Proves every job (keys of any shapes and kinds, repeats allowed) with one
@@ -217,9 +218,10 @@ void prove_batch_abandon(BatchRunPtr& run);
 // the previous setting.
 int set_graphs(int enable);
 
-// Proves Y = X W (a batch of one on the key's own context).
+// Proves Y = X W (a batch of one on the key's own context).  With device_io,
+// X, W and Y are device buffers on the key's device.
 void groth16_prove(zkvc_pk* pk, const int8_t* X, const int8_t* W, const host::HFr& r, const host::HFr& s,
-                   int32_t* Y, zkvc_proof* out, hipStream_t st);
+                   int32_t* Y, zkvc_proof* out, hipStream_t st, bool device_io = false);
 
 // Host verifier (pairing product) over a parsed key.
 int groth16_verify(const uint8_t* vk, size_t vk_len, const int8_t* X, const int32_t* Y, const zkvc_proof* proof);

@@ -1,5 +1,6 @@
-// Three-phase exclusive scan: per-tile scans with tile totals, a scan of the
-// totals, then a uniform add.  Used for bucket offsets in the MSM's counting sort.
+// Exclusive scan: one block for small arrays; otherwise three phases (per-tile
+// scans with tile totals, a scan of the totals, then a uniform add).  Used for
+// bucket offsets in the MSM's counting sort.
 #include "scan.hpp"
 
 namespace zkvc {
@@ -89,11 +90,83 @@ __global__ void k_scan_add(uint32_t* out, uint32_t n, const uint32_t* tile_prefi
   if (i < n) out[i] += tile_prefix[i / SCAN_TILE];
 }
 
+// Small arrays in one launch: one block walks the array in tiles of
+// SMALL_THREADS * SCAN_ITEMS values, carrying the running total.
+constexpr int SMALL_THREADS = 1024;
+constexpr uint32_t SMALL_SCAN_MAX = 1u << 15;
+
+__global__ void __launch_bounds__(SMALL_THREADS) k_scan_small(const uint32_t* in, uint32_t* out, uint32_t n,
+                                                              uint32_t div, uint32_t* d_total, uint32_t* d_max) {
+  __shared__ uint32_t sh[SMALL_THREADS / 64 + 1];
+  __shared__ uint32_t shmax[SMALL_THREADS / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t carry = 0, mx = 0;
+  for (uint32_t start = 0; start < n; start += SMALL_THREADS * SCAN_ITEMS) {
+    const uint32_t base = start + threadIdx.x * SCAN_ITEMS;
+    uint32_t vals[SCAN_ITEMS];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < SCAN_ITEMS; q++) {
+      const uint32_t i = base + q;
+      const uint32_t v = i < n ? scan_f(in[i], div) : 0u;
+      vals[q] = sum;
+      sum += v;
+      mx = v > mx ? v : mx;
+    }
+    // block-wide exclusive scan of the per-thread sums
+    uint32_t x = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) sh[wid] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t acc = 0;
+      for (int w = 0; w < SMALL_THREADS / 64; w++) {
+        const uint32_t t = sh[w];
+        sh[w] = acc;
+        acc += t;
+      }
+      sh[SMALL_THREADS / 64] = acc;
+    }
+    __syncthreads();
+    const uint32_t excl = carry + x - sum + sh[wid];
+#pragma unroll
+    for (int q = 0; q < SCAN_ITEMS; q++) {
+      const uint32_t i = base + q;
+      if (i < n) out[i] = vals[q] + excl;
+    }
+    carry += sh[SMALL_THREADS / 64];
+    __syncthreads();
+  }
+  if (d_max) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const uint32_t y = __shfl_xor(mx, o, 64);
+      mx = y > mx ? y : mx;
+    }
+    if (lane == 0) shmax[wid] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < SMALL_THREADS / 64; w++) mx = shmax[w] > mx ? shmax[w] : mx;
+      *d_max = mx;
+    }
+  }
+  if (threadIdx.x == 0 && d_total) *d_total = carry;
+}
+
 void scan_exclusive(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t div, uint32_t* d_total,
                     uint32_t* d_max, Workspace& ws, int slot, hipStream_t st) {
   if (n == 0) {
     if (d_total) fill_u32(d_total, 0u, 1, st);
     if (d_max) fill_u32(d_max, 0u, 1, st);
+    return;
+  }
+  if (n <= SMALL_SCAN_MAX) {
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(SMALL_THREADS), 0, st, in, out, n, div, d_total, d_max);
+    ZK_HIP(hipGetLastError());
     return;
   }
   const uint32_t ntiles = cdiv(n, SCAN_TILE);

@@ -107,6 +107,9 @@ class Workspace {
     }
     return b.get<T>();
   }
+  // Host buffers are pinned allocations that kernels may write directly
+  // (false in arena mode, whose host arena is ordinary memory).
+  bool host_mapped() const { return !arena_; }
   template <class T = uint32_t>
   T* host(int slot, size_t bytes) {
     if (arena_)

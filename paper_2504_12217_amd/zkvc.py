@@ -104,6 +104,8 @@ _SIGS = {
     "zkvc_pk_free": (ctypes.c_int, [_VP]),
     "zkvc_prove": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(Fr), ctypes.POINTER(Fr), _VP,
                                   ctypes.POINTER(Proof), _VP]),
+    "zkvc_prove_device": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(Fr), ctypes.POINTER(Fr), _VP,
+                                         ctypes.POINTER(Proof), _VP]),
     "zkvc_prove_batch": (ctypes.c_int, [ctypes.POINTER(ProveJob), ctypes.c_size_t, _VP]),
     "zkvc_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(_VP)]),
     "zkvc_server_submit": (ctypes.c_int, [_VP, ctypes.POINTER(ProveJob), ctypes.POINTER(ctypes.c_uint64)]),
@@ -383,6 +385,22 @@ def prove(pk, X, W, r, s, stream=None):
     _check(lib().zkvc_prove(pk.handle, X.ctypes.data, W.ctypes.data, ctypes.byref(rr), ctypes.byref(ss),
                             Y.ctypes.data, ctypes.byref(out), _stream(stream)))
     return Y, out
+
+
+def prove_device(pk, X, W, r, s, Y, stream=None):
+    """X int8 [a, n], W int8 [n, b] and Y int32 [a, b] contiguous device tensors
+    on the key's device; writes Y and returns the Proof."""
+    info = pk.info()
+    if tuple(X.shape) != (info.a, info.n) or tuple(W.shape) != (info.n, info.b) or tuple(Y.shape) != (info.a, info.b):
+        raise ValueError("X, W or Y does not match the proving key's shape")
+    for t, dt in ((X, "int8"), (W, "int8"), (Y, "int32")):
+        if str(t.dtype) != "torch." + dt or not t.is_contiguous():
+            raise ValueError(f"expected a contiguous {dt} tensor")
+    out = Proof()
+    rr, ss = fr(r), fr(s)
+    _check(lib().zkvc_prove_device(pk.handle, _ptr(X), _ptr(W), ctypes.byref(rr), ctypes.byref(ss), _ptr(Y),
+                                   ctypes.byref(out), _stream(stream)))
+    return out
 
 
 def prove_batch(jobs, stream=None):

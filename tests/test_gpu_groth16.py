@@ -185,3 +185,93 @@ def test_prove_is_deterministic_and_reusable(zk):
     st = pk.last_stats()
     assert st.total_ms > 0
     pk.close()
+
+
+def _dev(t, dtype):
+    return torch.from_numpy(np.ascontiguousarray(t)).to(dtype=dtype, device="cuda")
+
+
+@pytest.mark.parametrize("kind", [r1cs.PLAIN, r1cs.CRPC_PSQ, r1cs.CRPC])
+def test_prove_device_equals_oracle(zk, kind):
+    """zkvc_prove_device (X, W, Y in device memory) gives the oracle's proof and Y,
+    interleaved with host-buffer proofs on the same key."""
+    a, n, b = (5, 24, 9) if kind not in r1cs.CRPC_KINDS else (23, 40, 31)
+    s = r1cs.Shape(a, n, b)
+    X, W, tox, z, r, sr = _job(300 + kind, a, n, b, kind)
+    pk = zk.setup(a, n, b, kind, tuple(tox), z)
+    Xl, Wl = X.astype(int).tolist(), W.astype(int).tolist()
+    want, Yo = groth16.expected_proof_trapdoor(s, kind, tox, Xl, Wl, r, sr, z)
+    Xd, Wd = _dev(X, torch.int8), _dev(W, torch.int8)
+    for _ in range(2):
+        Yd = torch.full((a, b), -7, dtype=torch.int32, device="cuda")
+        proof = zk.prove_device(pk, Xd, Wd, r, sr, Yd)
+        assert Yd.cpu().numpy().tolist() == Yo
+        assert zk.proof_to_tuple(proof) == tuple(want)
+        Yh, ph = zk.prove(pk, X, W, r, sr)
+        assert Yh.tolist() == Yo and bytes(ph) == bytes(proof)
+    assert zk.verify(pk.vk, X, np.array(Yo, dtype=np.int32), proof) == 1
+    pk.close()
+
+
+def test_prove_device_graph_replay_follows_buffers(zk):
+    """With graph replay on, device buffers are part of the captured launches:
+    new buffers (or new contents of the same buffers) still give the right proofs."""
+    a, n, b = 4, 8, 4
+    kind = r1cs.CRPC_PSQ
+    s = r1cs.Shape(a, n, b)
+    _, _, tox, z, r, sr = _job(41, a, n, b, kind)
+    pk = zk.setup(a, n, b, kind, tuple(tox), z)
+    prev = zk.set_graphs(1)
+    try:
+        inputs = [synth.matmul_inputs(seed, a, n, b) for seed in (42, 43)]
+        bufs = [(_dev(X, torch.int8), _dev(W, torch.int8), torch.zeros((a, b), dtype=torch.int32, device="cuda"))
+                for X, W in inputs]
+        for rep in range(3):
+            for (X, W), (Xd, Wd, Yd) in zip(inputs, bufs):
+                want, Yo = groth16.expected_proof_trapdoor(s, kind, tox, X.astype(int).tolist(),
+                                                           W.astype(int).tolist(), r, sr, z)
+                Yd.zero_()
+                proof = zk.prove_device(pk, Xd, Wd, r, sr, Yd)
+                assert zk.proof_to_tuple(proof) == tuple(want), (rep,)
+                assert Yd.cpu().numpy().tolist() == Yo
+        # the same buffers with new contents
+        X2, W2 = synth.matmul_inputs(44, a, n, b)
+        Xd, Wd, Yd = bufs[0]
+        Xd.copy_(_dev(X2, torch.int8))
+        Wd.copy_(_dev(W2, torch.int8))
+        want, Yo = groth16.expected_proof_trapdoor(s, kind, tox, X2.astype(int).tolist(), W2.astype(int).tolist(),
+                                                   r, sr, z)
+        for _ in range(2):
+            proof = zk.prove_device(pk, Xd, Wd, r, sr, Yd)
+            assert zk.proof_to_tuple(proof) == tuple(want)
+            assert Yd.cpu().numpy().tolist() == Yo
+    finally:
+        zk.set_graphs(prev)
+    pk.close()
+
+
+def test_prove_device_argument_errors(zk):
+    import ctypes
+    a, n, b = 2, 3, 2
+    X, W, tox, z, r, sr = _job(8, a, n, b, r1cs.PLAIN)
+    pk = zk.setup(a, n, b, r1cs.PLAIN, tuple(tox), z)
+    Xd, Wd = _dev(X, torch.int8), _dev(W, torch.int8)
+    Yd = torch.zeros((a, b), dtype=torch.int32, device="cuda")
+    with pytest.raises(ValueError):
+        zk.prove_device(pk, Xd, Wd.t().contiguous(), r, sr, Yd)  # W transposed: wrong shape
+    with pytest.raises(ValueError):
+        zk.prove_device(pk, Xd.to(torch.int32), Wd, r, sr, Yd)
+    # a host buffer where device memory is required
+    Xh = np.ascontiguousarray(X)
+    out = zk.Proof()
+    rr, ss = zk.fr(r), zk.fr(sr)
+    rc = zk.lib().zkvc_prove_device(pk.handle, Xh.ctypes.data, Wd.data_ptr(), ctypes.byref(rr), ctypes.byref(ss),
+                                    Yd.data_ptr(), ctypes.byref(out), zk._stream(None))
+    assert rc == zk.EINVAL
+    rc = zk.lib().zkvc_prove_device(pk.handle, None, Wd.data_ptr(), ctypes.byref(rr), ctypes.byref(ss),
+                                    Yd.data_ptr(), ctypes.byref(out), zk._stream(None))
+    assert rc == zk.EINVAL
+    # the key still proves afterwards
+    proof = zk.prove_device(pk, Xd, Wd, r, sr, Yd)
+    assert zk.verify(pk.vk, X, Yd.cpu().numpy(), proof) == 1
+    pk.close()
