@@ -65,10 +65,9 @@ struct JobDev {
   uint32_t nwb;             // bucket sets: nw, or 1 with precomputed windows
   uint32_t chunk, nch;      // digits per histogram chunk and number of chunks: per window, or (with
                             // precomputed windows) over the job's whole digit stream of nw * n digits
-  uint32_t nchw;            // histogram columns per bucket (= nch)
   uint32_t digit_base;      // first digit word (nw * n words, window-major)
   uint32_t bucket_base;     // first bucket (nwb * nb buckets, window-major)
-  uint32_t hist_base;       // first histogram word (nwb * nb * nchw words)
+  uint32_t hist_base;       // first histogram word (nwb * nch * nb words)
   uint32_t plane_base;      // first bit plane (nwb * c planes)
   uint32_t bpb;             // blocks per bit plane (a power of two)
   uint32_t blk_bp;          // first block of the bit-plane grid (nwb * c * bpb blocks)
@@ -82,10 +81,17 @@ struct JobDev {
 constexpr int INLINE_JOBS = 8;
 struct BatchDev {
   int njobs;
+  int prio;  // 1: the batch is on the critical path (its waves win instruction issue)
   const JobDev* jobs;
   JobDev inl[INLINE_JOBS];
   __device__ __forceinline__ const JobDev& job(int k) const { return njobs <= INLINE_JOBS ? inl[k] : jobs[k]; }
 };
+
+// A critical-path batch raises its waves' issue priority over waves of
+// concurrent kernels on the same SIMD (the other lanes' MSMs).
+__device__ __forceinline__ void wave_priority(int prio) {
+  if (prio) __builtin_amdgcn_s_setprio(2);
+}
 
 // The job owning index v of a per-job range whose first index is the field F
 // (ascending over the jobs): a binary search of the table.
@@ -117,6 +123,7 @@ constexpr uint64_t FEW_ENTRIES = 1ull << 19;
 // window (bucket | sign, or EMPTY for a zero digit or a point at infinity).
 template <class F>
 __global__ void __launch_bounds__(256) k_msm_digits(BatchDev B, uint32_t* digits) {
+  wave_priority(B.prio);
   const int k = job_of<&JobDev::blk_digits>(B, blockIdx.x);
   const JobDev& J = B.job(k);
   const uint32_t j = (blockIdx.x - J.blk_digits) * 256 + threadIdx.x;
@@ -183,16 +190,19 @@ __global__ void __launch_bounds__(256) k_msm_digits(BatchDev B, uint32_t* digits
 
 // ---------------------------------------------------------------- 2. counting sort
 // Block (window w, chunk ch) counts its digits per bucket in LDS and writes
-// the counts to hist[(w nb + b) nch + ch].  With precomputed windows all
-// windows share one bucket set and a block takes chunk ch of the job's whole
-// digit stream (window-major, nw n digits): hist[b nch + ch], so the
-// histogram holds nb columns per chunk of the stream rather than per window.
-// An exclusive scan of hist then gives every (bucket, column) pair its first
-// slot in bucket order, with no global atomics however skewed the digits are.
+// the counts as one contiguous row, hist[(w nch + ch) nb + b].  With
+// precomputed windows all windows share one bucket set and a block takes
+// chunk ch of the job's whole digit stream (window-major, nw n digits):
+// hist[ch nb + b].  A thread per bucket then walks its column of rows
+// (k_msm_colscan), turning the counts into the bucket's running offsets per
+// chunk and its total; a scan of the totals gives each bucket its first slot.
+// Every access is coalesced and no global atomics are used, however skewed
+// the digits are.
 struct HsRange {
   const uint32_t* d;  // the block's digits: d[lo .. hi)
   uint32_t lo, hi;
-  size_t col;         // its histogram column (bucket b at col + b nchw)
+  size_t row;         // its histogram row (bucket b at row + b)
+  uint32_t w;         // its window's bucket set (0 with precomputed windows)
 };
 __device__ __forceinline__ HsRange hs_range(const JobDev& J, const uint32_t* digits, uint32_t local) {
   HsRange r;
@@ -201,17 +211,20 @@ __device__ __forceinline__ HsRange hs_range(const JobDev& J, const uint32_t* dig
     r.d = digits + J.digit_base;
     r.lo = local * J.chunk;
     r.hi = min(total, r.lo + J.chunk);
-    r.col = (size_t)J.hist_base + local;
+    r.row = (size_t)J.hist_base + (size_t)local * J.nb;
+    r.w = 0;
   } else {
     const uint32_t w = local / J.nch, ch = local % J.nch;
     r.d = digits + J.digit_base + (size_t)w * J.n;
     r.lo = ch * J.chunk;
     r.hi = min(J.n, r.lo + J.chunk);
-    r.col = (size_t)J.hist_base + (size_t)w * J.nb * J.nchw + ch;
+    r.row = (size_t)J.hist_base + ((size_t)w * J.nch + ch) * J.nb;
+    r.w = w;
   }
   return r;
 }
 __global__ void __launch_bounds__(HS_THREADS) k_msm_hist(BatchDev B, const uint32_t* digits, uint32_t* hist) {
+  wave_priority(B.prio);
   extern __shared__ uint32_t cnt[];
   const int k = job_of<&JobDev::blk_hs>(B, blockIdx.x);
   const JobDev& J = B.job(k);
@@ -223,23 +236,57 @@ __global__ void __launch_bounds__(HS_THREADS) k_msm_hist(BatchDev B, const uint3
     if (v != EMPTY) atomicAdd(&cnt[v & ~SIGN], 1u);
   }
   __syncthreads();
-  uint32_t* h = hist + R.col;
-  for (uint32_t b = threadIdx.x; b < J.nb; b += HS_THREADS) h[(size_t)b * J.nchw] = cnt[b];
+  uint32_t* h = hist + R.row;
+  for (uint32_t b = threadIdx.x; b < J.nb; b += HS_THREADS) h[b] = cnt[b];
 }
 
-// Same blocks as k_msm_hist: LDS cursors start at the scanned offsets and
-// every digit takes the next slot of its bucket (order inside a bucket does
-// not matter to the sum).  Entries are (point index | sign); with
+// A thread per bucket f (window w, digit value b): the bucket's counts down
+// its column of histogram rows become running offsets inside the bucket, in
+// place; cnt[f] receives the bucket's size and nt[f] its number of tasks
+// (see k_msm_make_tasks).  Also clears the task-list counters.
+__global__ void k_msm_colscan(BatchDev B, uint32_t* hist, uint32_t nbt, uint32_t K, uint32_t large,
+                              uint32_t wg_entries, uint32_t* cnt, uint32_t* nt, uint32_t* counters) {
+  wave_priority(B.prio);
+  const uint32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f == 0) {
+    counters[0] = 0u;
+    counters[1] = 0u;
+    counters[2] = 0u;
+  }
+  if (f >= nbt) return;
+  const int k = job_of<&JobDev::bucket_base>(B, f);
+  const JobDev& J = B.job(k);
+  const uint32_t lf = f - J.bucket_base;
+  const uint32_t w = lf / J.nb, b = lf - w * J.nb;
+  uint32_t* col = hist + J.hist_base + (size_t)w * J.nch * J.nb + b;
+  uint32_t run = 0;
+  const uint32_t nch = J.nch, nb = J.nb;
+#pragma unroll 4
+  for (uint32_t ch = 0; ch < nch; ch++) {
+    const uint32_t v = col[(size_t)ch * nb];
+    col[(size_t)ch * nb] = run;
+    run += v;
+  }
+  cnt[f] = run;
+  const uint32_t sz = run >= large ? wg_entries : K;
+  nt[f] = (run + sz - 1) / sz;
+}
+
+// Same blocks as k_msm_hist: LDS cursors start at the bucket's first slot
+// plus the chunk's running offset inside the bucket, and every digit takes the
+// next slot of its bucket (order inside a bucket does not matter to the sum).  Entries are (point index | sign); with
 // precomputed windows stream position p holds window p / n of scalar p % n,
 // whose point is copy p / n of the scalar's base.
-__global__ void __launch_bounds__(HS_THREADS) k_msm_scatter(BatchDev B, const uint32_t* digits, const uint32_t* offs,
-                                                            uint32_t* sorted) {
+__global__ void __launch_bounds__(HS_THREADS) k_msm_scatter(BatchDev B, const uint32_t* digits, const uint32_t* hist,
+                                                            const uint32_t* off, uint32_t* sorted) {
+  wave_priority(B.prio);
   extern __shared__ uint32_t cur[];
   const int k = job_of<&JobDev::blk_hs>(B, blockIdx.x);
   const JobDev& J = B.job(k);
   const HsRange R = hs_range(J, digits, blockIdx.x - J.blk_hs);
-  const uint32_t* o = offs + R.col;
-  for (uint32_t b = threadIdx.x; b < J.nb; b += HS_THREADS) cur[b] = o[(size_t)b * J.nchw];
+  const uint32_t* h = hist + R.row;
+  const uint32_t* o = off + J.bucket_base + (size_t)R.w * J.nb;
+  for (uint32_t b = threadIdx.x; b < J.nb; b += HS_THREADS) cur[b] = o[b] + h[b];
   __syncthreads();
   for (uint32_t p = R.lo + threadIdx.x; p < R.hi; p += HS_THREADS) {
     const uint32_t v = R.d[p];
@@ -260,30 +307,8 @@ __global__ void __launch_bounds__(HS_THREADS) k_msm_scatter(BatchDev B, const ui
 // Buckets are split into tasks by their actual size: a bucket with fewer than
 // `large` entries becomes thread tasks of at most K entries (one thread sums a
 // task serially); a larger one becomes wavefront tasks of WG_TASK_ENTRIES
-// entries reduced by an LDS tree.  nt[f] is the number of partial sums of
-// bucket f; a bucket's partial sums are contiguous.
-__global__ void k_msm_task_counts(BatchDev B, const uint32_t* offs, uint32_t nbt, uint32_t K, uint32_t large,
-                                  uint32_t wg_entries, uint32_t* cnt, uint32_t* off, uint32_t* nt,
-                                  uint32_t* counters) {
-  const uint32_t f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f == 0) {
-    counters[0] = 0u;
-    counters[1] = 0u;
-    counters[2] = 0u;
-  }
-  if (f >= nbt) return;
-  const int k = job_of<&JobDev::bucket_base>(B, f);
-  const JobDev& J = B.job(k);
-  const size_t lf = f - J.bucket_base;
-  // the bucket after the job's last one starts the next job's range (or the total)
-  const uint32_t s = offs[J.hist_base + lf * J.nchw];
-  const uint32_t e = offs[J.hist_base + (lf + 1) * J.nchw];
-  const uint32_t c = e - s;
-  cnt[f] = c;
-  off[f] = s;
-  const uint32_t sz = c >= large ? wg_entries : K;
-  nt[f] = (c + sz - 1) / sz;
-}
+// entries reduced by an LDS tree.  nt[f] (from k_msm_colscan) is the number
+// of partial sums of bucket f; a bucket's partial sums are contiguous.
 
 // Task records (first entry, length, output partial slot, job).  Slots in
 // the two task lists are claimed with one atomic per wavefront and list.
@@ -305,6 +330,7 @@ __global__ void __launch_bounds__(256) k_msm_make_tasks(BatchDev B, const uint32
                                                         uint32_t large, uint32_t wg_entries, uint32_t fin_max,
                                                         uint32_t* counters, uint4* th_tasks, uint4* wg_tasks,
                                                         uint32_t* heavy) {
+  wave_priority(B.prio);
   const uint32_t f = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t c = f < nbt ? cnt[f] : 0u;
@@ -363,6 +389,7 @@ __global__ void __launch_bounds__(64) k_msm_acc(BatchDev B, const uint4* th_task
                                                 const uint32_t* counters, uint32_t th_blocks, const uint32_t* sorted,
                                                 uint32_t* partials, int quad, const uint32_t* total,
                                                 uint32_t* work_out) {
+  wave_priority(B.prio);
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
   constexpr int AW = PointIO<F>::AFF_WORDS;
   __shared__ uint32_t sh[WG_THREADS / 2 * XW];
@@ -439,7 +466,8 @@ template <class F>
 __global__ void __launch_bounds__(64) k_msm_finalize(const uint32_t* nt, const uint32_t* part_off,
                                                      const uint32_t* partials, uint32_t nbt, const uint32_t* counters,
                                                      const uint32_t* heavy, uint32_t light_blocks, uint32_t fin_max,
-                                                     uint32_t group, int quad, uint32_t* buckets) {
+                                                     uint32_t group, int quad, uint32_t* buckets, int prio) {
+  wave_priority(prio);
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
   __shared__ uint32_t sh[WG_THREADS * XW];
   const uint32_t tq = threadIdx.x & 3u;
@@ -512,6 +540,7 @@ __global__ void __launch_bounds__(64) k_msm_finalize(const uint32_t* nt, const u
 template <class F>
 __global__ void __launch_bounds__(BP_THREADS) k_msm_bitplanes(BatchDev B, const uint32_t* buckets, uint32_t* part,
                                                                uint32_t* S) {
+  wave_priority(B.prio);
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
   __shared__ uint32_t sh[BP_THREADS / 8 * XW];
   const int k = job_of<&JobDev::blk_bp>(B, blockIdx.x);
@@ -546,6 +575,7 @@ __global__ void __launch_bounds__(BP_THREADS) k_msm_bitplanes(BatchDev B, const 
 // One wavefront (16 quads) per plane: the sum of the plane's bpb block sums.
 template <class F>
 __global__ void __launch_bounds__(64) k_msm_plane_sums(BatchDev B, const uint32_t* part, uint32_t* S) {
+  wave_priority(B.prio);
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
   __shared__ uint32_t sh[8 * XW];
   const int k = job_of<&JobDev::plane_base>(B, blockIdx.x);
@@ -697,7 +727,6 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs, int group) {
       J.chunk = (uint32_t)chunk;
       J.nch = (uint32_t)((J.n + chunk - 1) / chunk);
     }
-    J.nchw = J.nch;
     J.digit_base = (uint32_t)p.ndigits;
     J.bucket_base = (uint32_t)p.nbt;
     J.hist_base = (uint32_t)p.nh;
@@ -733,8 +762,12 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs, int group) {
   // FIN_THREAD_MIN partial sums are finished by a wavefront tree.
   const bool few_buckets = p.nbt <= FEW_BUCKETS && E <= FEW_ENTRIES;
   // otherwise wavefront tasks only for buckets far above the typical size (a
-  // window's few possible top digits, or small-integer scalars piling into few buckets)
-  p.large = few_buckets ? 32u : std::max<uint32_t>(128, 32 * p.K);
+  // window's few possible top digits, or small-integer scalars piling into few
+  // buckets): at least 32 tasks' worth and four times the average bucket
+  const uint64_t avg_bucket = p.nbt ? E / p.nbt : 0;
+  p.large = few_buckets ? 32u
+                        : (uint32_t)std::min<uint64_t>(
+                              1u << 30, std::max<uint64_t>({128, 32 * (uint64_t)p.K, 4 * avg_bucket}));
   // With few buckets and entries in all the batch is bound by chains of dependent
   // additions, not by throughput: additions in the wavefront tasks and the
   // finalize step are done by quads of lanes (shorter chains per point
@@ -768,8 +801,8 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs, int group) {
 // request is made before the first launch, so a workspace in arena mode can
 // be sized by replaying the requests without launching anything).
 struct MsmBufs {
-  uint32_t *digits, *hist, *offs, *cnt, *off, *nt, *part_off, *sorted, *part, *buckets, *win, *bp_part, *heavy,
-      *meta, *win_host;
+  uint32_t *digits, *hist, *cnt, *off, *nt, *part_off, *sorted, *part, *buckets, *win, *bp_part, *heavy, *meta,
+      *win_host;
   uint4 *th_tasks, *wg_tasks;
   JobDev *jt_host, *jt_dev;
 };
@@ -779,7 +812,6 @@ static MsmBufs msm_buffers(const BatchPlan& p, Workspace& ws, int XW) {
   MsmBufs b;
   b.digits = ws.get(S_DIGITS, p.ndigits * 4);
   b.hist = ws.get(S_COUNTS, p.nh * 4);
-  b.offs = ws.get(S_OFFSETS, (p.nh + 1) * 4);
   b.cnt = ws.get(S_CNT_A, p.nbt * 4);
   b.off = ws.get(S_OFF_A, p.nbt * 4);
   b.nt = ws.get(S_CNT_B, p.nbt * 4);
@@ -794,9 +826,9 @@ static MsmBufs msm_buffers(const BatchPlan& p, Workspace& ws, int XW) {
   b.win = ws.host_mapped() ? nullptr : ws.get(S_WIN, p.nplanes * XW * 4);
   b.bp_part = ws.get(S_BP_PART, p.bp_blocks * XW * 4);
   b.heavy = ws.get(S_HEAVY, p.nbt * 4);
-  b.meta = ws.get(S_META, 64 * 4);  // [2] partials [8..10] thread tasks, wavefront tasks, heavy buckets
+  b.meta = ws.get(S_META, 64 * 4);  // [2] partials [3] entries [8..10] thread tasks, wavefront tasks, heavy buckets
   b.win_host = ws.host<uint32_t>(S_WIN, p.nplanes * XW * 4);
-  ws.get(S_SCRATCH, (size_t)cdiv(std::max(p.nh, p.nbt), 2048) * 4 + 64);
+  ws.get(S_SCRATCH, (size_t)cdiv(p.nbt, 2048) * 4 + 64);
   // a job table beyond the kernel arguments, through pinned memory (the
   // workspace is not reused before this stream has completed)
   b.jt_host = b.jt_dev = nullptr;
@@ -817,7 +849,7 @@ void msm_arena_need(const MsmInput* in, int njobs, int group, size_t* dev_bytes,
 }
 
 template <class F>
-void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t st, MsmPending* pend) {
+void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t st, MsmPending* pend, int prio) {
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
   ZK_REQUIRE(njobs >= 0, "negative MSM count");
   for (int q = 0; q < njobs; q++) {
@@ -832,12 +864,13 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
 
   // all buffers first (a buffer that grows is replaced by a new one)
   const MsmBufs bf = msm_buffers(p, ws, XW);
-  uint32_t *digits = bf.digits, *hist = bf.hist, *offs = bf.offs, *cnt = bf.cnt, *off = bf.off, *nt = bf.nt,
+  uint32_t *digits = bf.digits, *hist = bf.hist, *cnt = bf.cnt, *off = bf.off, *nt = bf.nt,
            *part_off = bf.part_off, *sorted = bf.sorted, *part = bf.part, *buckets = bf.buckets, *win = bf.win,
            *bp_part = bf.bp_part, *heavy = bf.heavy, *meta = bf.meta, *win_host = bf.win_host;
   uint4 *th_tasks = bf.th_tasks, *wg_tasks = bf.wg_tasks;
   BatchDev dev{};
   dev.njobs = nj;
+  dev.prio = prio;
   if (nj <= INLINE_JOBS) {
     for (int k = 0; k < nj; k++) dev.inl[k] = p.jobs[k];
   } else {
@@ -863,18 +896,15 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
     ProfScope ps("msm_sort", st, (double)p.ndigits);
     hipLaunchKernelGGL(k_msm_hist, dim3((unsigned)p.hs_blocks), dim3(HS_THREADS), lds, st, dev, digits, hist);
     ZK_HIP(hipGetLastError());
-    // offs[nh] receives the total number of entries
-    scan_exclusive(hist, offs, (uint32_t)p.nh, 0, offs + p.nh, nullptr, ws, S_SCRATCH, st);
-    hipLaunchKernelGGL(k_msm_scatter, dim3((unsigned)p.hs_blocks), dim3(HS_THREADS), lds, st, dev, digits, offs,
+    // bucket sizes and task counts, then the buckets' first slots and first partial sums
+    hipLaunchKernelGGL(k_msm_colscan, dim3(cdiv(nbt, 256)), dim3(256), 0, st, dev, hist, nbt, p.K, p.large,
+                       p.wg_entries, cnt, nt, meta + 8);
+    ZK_HIP(hipGetLastError());
+    scan_exclusive2(cnt, off, meta + 3, nt, part_off, meta + 2, nbt, ws, S_SCRATCH, st);
+    hipLaunchKernelGGL(k_msm_scatter, dim3((unsigned)p.hs_blocks), dim3(HS_THREADS), lds, st, dev, digits, hist, off,
                        sorted);
     ZK_HIP(hipGetLastError());
   }
-  // tasks by actual bucket size
-  hipLaunchKernelGGL(k_msm_task_counts, dim3(cdiv(nbt, 256)), dim3(256), 0, st, dev, offs, nbt, p.K, p.large,
-                     p.wg_entries, cnt,
-                     off, nt, meta + 8);
-  ZK_HIP(hipGetLastError());
-  scan_exclusive(nt, part_off, nbt, 0, meta + 2, nullptr, ws, S_SCRATCH, st);
   hipLaunchKernelGGL(k_msm_make_tasks, dim3(cdiv(nbt, 256)), dim3(256), 0, st, dev, cnt, off, part_off, nbt, p.K,
                      p.large, p.wg_entries, p.fin_max, meta + 8, th_tasks, wg_tasks, heavy);
   ZK_HIP(hipGetLastError());
@@ -884,7 +914,7 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
     const unsigned th_blocks = (unsigned)std::min<uint64_t>(cdiv(p.max_th_tasks, 64), 65536);
     const unsigned wg_blocks = (unsigned)std::min<uint64_t>(p.max_wg_tasks, 4096);
     hipLaunchKernelGGL(k_msm_acc<F>, dim3(th_blocks + wg_blocks), dim3(64), 0, st, dev, th_tasks, wg_tasks,
-                       meta + 8, th_blocks, sorted, part, p.quad ? 1 : 0, offs + p.nh, ps.work_word());
+                       meta + 8, th_blocks, sorted, part, p.quad ? 1 : 0, meta + 3, ps.work_word());
     ZK_HIP(hipGetLastError());
   }
   {
@@ -892,7 +922,7 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
     const unsigned light_blocks = cdiv(nbt, 64 / p.fin_group);
     const unsigned heavy_blocks = (unsigned)std::min<uint64_t>(nbt, 1024);
     hipLaunchKernelGGL(k_msm_finalize<F>, dim3(light_blocks + heavy_blocks), dim3(64), 0, st, nt, part_off, part, nbt,
-                       meta + 8, heavy, light_blocks, p.fin_max, p.fin_group, p.quad ? 1 : 0, buckets);
+                       meta + 8, heavy, light_blocks, p.fin_max, p.fin_group, p.quad ? 1 : 0, buckets, prio);
     ZK_HIP(hipGetLastError());
   }
   {
@@ -947,16 +977,16 @@ typename HostOf<F>::Pt msm_finish(const MsmPending& pend) {
 template <class F>
 typename HostOf<F>::Pt msm_run(const MsmInput& in, Workspace& ws, hipStream_t st) {
   MsmPending pend;
-  msm_enqueue_batch<F>(&in, 1, ws, st, &pend);
+  msm_enqueue_batch<F>(&in, 1, ws, st, &pend, 0);
   ZK_HIP(hipStreamSynchronize(st));
   return msm_finish<F>(pend);
 }
 
-void msm_enqueue_batch_g1(const MsmInput* in, int njobs, Workspace& ws, hipStream_t st, MsmPending* pend) {
-  msm_enqueue_batch<Fq>(in, njobs, ws, st, pend);
+void msm_enqueue_batch_g1(const MsmInput* in, int njobs, Workspace& ws, hipStream_t st, MsmPending* pend, int prio) {
+  msm_enqueue_batch<Fq>(in, njobs, ws, st, pend, prio);
 }
-void msm_enqueue_batch_g2(const MsmInput* in, int njobs, Workspace& ws, hipStream_t st, MsmPending* pend) {
-  msm_enqueue_batch<Fq2>(in, njobs, ws, st, pend);
+void msm_enqueue_batch_g2(const MsmInput* in, int njobs, Workspace& ws, hipStream_t st, MsmPending* pend, int prio) {
+  msm_enqueue_batch<Fq2>(in, njobs, ws, st, pend, prio);
 }
 host::G1J msm_finish_g1(const MsmPending& pend) { return msm_finish<Fq>(pend); }
 host::G2J msm_finish_g2(const MsmPending& pend) { return msm_finish<Fq2>(pend); }

@@ -38,8 +38,12 @@ struct MsmPending {
 // group, with no host synchronization; the workspace must not be used by
 // anything else until the stream completes.  pend[q] receives job q's
 // pending result.
-void msm_enqueue_batch_g1(const MsmInput* in, int njobs, Workspace& ws, hipStream_t st, MsmPending* pend);
-void msm_enqueue_batch_g2(const MsmInput* in, int njobs, Workspace& ws, hipStream_t st, MsmPending* pend);
+// prio = 1 marks a batch on the critical path: its waves take instruction
+// issue ahead of concurrent kernels' waves (s_setprio); results are unchanged.
+void msm_enqueue_batch_g1(const MsmInput* in, int njobs, Workspace& ws, hipStream_t st, MsmPending* pend,
+                          int prio = 0);
+void msm_enqueue_batch_g2(const MsmInput* in, int njobs, Workspace& ws, hipStream_t st, MsmPending* pend,
+                          int prio = 0);
 // Device and host workspace bytes that msm_enqueue_batch_g1/g2 takes for
 // these jobs from a workspace in arena mode (each slot once, 256-byte aligned).
 void msm_arena_need(const MsmInput* in, int njobs, int group, size_t* dev_bytes, size_t* host_bytes);

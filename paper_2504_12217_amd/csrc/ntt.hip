@@ -123,8 +123,17 @@ __device__ __forceinline__ uint32_t pass_addr(uint32_t e, int k, int log_g, int 
   return ((gamma >> B) << log_m) | (t << B) | g;
 }
 
+// The transforms of a proof's quotient lie on its critical path (the H MSM
+// waits for them) while the G1 and G2 MSMs run beside them: their waves take
+// instruction issue first on a shared SIMD.
+constexpr bool NTT_PRIO = true;
+__device__ __forceinline__ void ntt_wave_priority() {
+  if (NTT_PRIO) __builtin_amdgcn_s_setprio(2);
+}
+
 __global__ void __launch_bounds__(NTT_THREADS) k_ntt_pass(PassParams p, NttTables T) {
   extern __shared__ uint32_t lds[];
+  ntt_wave_priority();
   const int k = p.k;
   const uint32_t K = 1u << k;
   const uint32_t G = 1u << p.log_g;
@@ -220,6 +229,7 @@ struct FusedParams {
 // Bottom fusion, one vector per blockIdx.y (A, B, C of each proof in turn).
 __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fused_bottom(FusedParams p, NttTables T) {
   extern __shared__ uint32_t lds[];
+  ntt_wave_priority();
   const int k = p.k;
   const uint32_t E = 1u << (k + p.log_g);
   const uint32_t gamma0 = blockIdx.x << p.log_g;
@@ -251,6 +261,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fused_bottom(FusedParams p,
 // Top fusion, one proof per blockIdx.y; the quotient overwrites A.
 __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fused_top(FusedParams p, NttTables T) {
   extern __shared__ uint32_t lds[];
+  ntt_wave_priority();
   const int k = p.k, L = p.log_n, B = L - k;
   const uint32_t K = 1u << k;
   const uint32_t E = 1u << (k + p.log_g);

@@ -925,12 +925,18 @@ __global__ void k_check_top(uint32_t* const* tab, const uint32_t* one, uint32_t 
   uint32_t t = 0;
 #pragma unroll
   for (int q = 0; q < 8; q++) t |= h[q];
-  if (t) atomicOr(flag, 1u);
+  if (t) {  // every writer stores the same value; flag is pinned host memory
+    *flag = 1u;
+    __threadfence_system();
+  }
 }
 
 namespace {
 enum ProveSlot { P_ASSIGN = 20, P_AEV, P_BEV, P_CEV, P_XK, P_WK, P_PK, P_YZ };
 enum SharedSlot { C_TABLE = 60, C_FLAG, C_XW, C_Y, C_WTAB };
+// The H lane follows the quotient and ends the proof: its waves take
+// instruction issue ahead of the G1 and G2 lanes' (results are unchanged).
+constexpr int H_LANE_PRIO = 1;
 
 // One MSM of a proof: a query segment (or the H query) and its scalars.
 struct MsmJob {
@@ -1369,7 +1375,7 @@ struct BatchRun {
   std::vector<MsmInput> in_g1, in_g2, in_h;
   std::vector<int> own_g1, query_g1, own_g2, own_h;
   std::vector<MsmPending> pend_g1, pend_g2, pend_h;
-  const uint32_t* flag_host = nullptr;
+  volatile uint32_t* flag_host = nullptr;  // pinned, written by the tail check
   std::chrono::steady_clock::time_point host_t0;
 };
 
@@ -1442,6 +1448,7 @@ BatchRunPtr prove_batch_begin(ProveCtx& ctx, int g, const ProveJob* jobs_in, siz
       std::memcpy(R.slots[j].xh, jobs_in[j].X, (size_t)L.a * L.n);
       std::memcpy(R.slots[j].wh, jobs_in[j].W, (size_t)L.n * L.b);
     }
+    *R.flag_host = 0u;
     fork();
     ZK_HIP(hipGraphLaunch(G.graph, gs));
     join();
@@ -1583,9 +1590,10 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
     // Proofs of one domain size share every launch.
     std::map<int, std::vector<size_t>> by_size;
     for (size_t j = 0; j < nj; j++) by_size[jobs[j].pk->L.log_n].push_back(j);
-    uint32_t* flag = G.shared.get(C_FLAG, 4);
+    // the tail check writes straight into pinned host memory (cleared here; a
+    // graph replay clears it before each launch)
     uint32_t* flag_host = G.shared.host<uint32_t>(C_FLAG, 4);
-    fill_u32(flag, 0u, 1, st);
+    *flag_host = 0u;
     // device tables for groups of several proofs: (A, B, C) triples, then the A's
     std::vector<uint32_t*> tab_v;
     std::vector<size_t> tab_off;
@@ -1616,25 +1624,26 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
         const Slot& S = slots[kv.second[0]];
         uint32_t* const vecs[3] = {S.aev, S.bev, S.cev};
         qap_quotient_launch(vecs, nullptr, 1, Lg, st);
-        hipLaunchKernelGGL(k_check_top, dim3(1), dim3(64), 0, st, (uint32_t* const*)nullptr, S.aev, 1u, N, flag);
+        hipLaunchKernelGGL(k_check_top, dim3(1), dim3(64), 0, st, (uint32_t* const*)nullptr, S.aev, 1u, N,
+                           flag_host);
         ZK_HIP(hipGetLastError());
       } else {
         uint32_t** tg = tab_dev + tab_off[gi];
         qap_quotient_launch(nullptr, tg, (int)k, Lg, st);
         hipLaunchKernelGGL(k_check_top, dim3(cdiv(k, 64)), dim3(64), 0, st, tg + 3 * k, (const uint32_t*)nullptr,
-                           (uint32_t)k, N, flag);
+                           (uint32_t)k, N, flag_host);
         ZK_HIP(hipGetLastError());
       }
       gi++;
     }
-    ZK_HIP(hipMemcpyAsync(flag_host, flag, 4, hipMemcpyDeviceToHost, st));
     R.flag_host = flag_host;
     record_ext(G.ev[2], st, capture);
     ZK_HIP(hipEventRecord(G.quotient_ev, st));
 
     // ---- the H lane after the quotients
     ZK_HIP(hipStreamWaitEvent(lane_h, G.quotient_ev, 0));
-    msm_enqueue_batch_g1(in_h.data(), (int)in_h.size(), G.lane_ws[ProveCtx::LANE_H], lane_h, R.pend_h.data());
+    msm_enqueue_batch_g1(in_h.data(), (int)in_h.size(), G.lane_ws[ProveCtx::LANE_H], lane_h, R.pend_h.data(),
+                         H_LANE_PRIO);
     record_ext(G.done_ev[ProveCtx::LANE_H], lane_h, capture);
     record_ext(G.lane_t[ProveCtx::LANE_H], lane_h, capture);
   } catch (...) {

@@ -95,8 +95,21 @@ __global__ void k_scan_add(uint32_t* out, uint32_t n, const uint32_t* tile_prefi
 constexpr int SMALL_THREADS = 1024;
 constexpr uint32_t SMALL_SCAN_MAX = 1u << 15;
 
-__global__ void __launch_bounds__(SMALL_THREADS) k_scan_small(const uint32_t* in, uint32_t* out, uint32_t n,
-                                                              uint32_t div, uint32_t* d_total, uint32_t* d_max) {
+// Up to two independent scans per launch: block 0 takes the first array,
+// block 1 (if launched) the second.
+struct SmallScan {
+  const uint32_t* in;
+  uint32_t* out;
+  uint32_t* d_total;
+  uint32_t* d_max;
+};
+
+__global__ void __launch_bounds__(SMALL_THREADS) k_scan_small(SmallScan s0, SmallScan s1, uint32_t n, uint32_t div) {
+  const SmallScan& S = blockIdx.x == 0 ? s0 : s1;
+  const uint32_t* in = S.in;
+  uint32_t* out = S.out;
+  uint32_t* d_total = S.d_total;
+  uint32_t* d_max = S.d_max;
   __shared__ uint32_t sh[SMALL_THREADS / 64 + 1];
   __shared__ uint32_t shmax[SMALL_THREADS / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -165,7 +178,8 @@ void scan_exclusive(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t div,
     return;
   }
   if (n <= SMALL_SCAN_MAX) {
-    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(SMALL_THREADS), 0, st, in, out, n, div, d_total, d_max);
+    const SmallScan s0{in, out, d_total, d_max};
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(SMALL_THREADS), 0, st, s0, s0, n, div);
     ZK_HIP(hipGetLastError());
     return;
   }
@@ -180,6 +194,18 @@ void scan_exclusive(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t div,
     hipLaunchKernelGGL(k_scan_add, dim3(cdiv(n, 256)), dim3(256), 0, st, out, n, totals);
     ZK_HIP(hipGetLastError());
   }
+}
+
+void scan_exclusive2(const uint32_t* in0, uint32_t* out0, uint32_t* d_total0, const uint32_t* in1, uint32_t* out1,
+                     uint32_t* d_total1, uint32_t n, Workspace& ws, int slot, hipStream_t st) {
+  if (n == 0 || n > SMALL_SCAN_MAX) {
+    scan_exclusive(in0, out0, n, 0, d_total0, nullptr, ws, slot, st);
+    scan_exclusive(in1, out1, n, 0, d_total1, nullptr, ws, slot, st);
+    return;
+  }
+  const SmallScan s0{in0, out0, d_total0, nullptr}, s1{in1, out1, d_total1, nullptr};
+  hipLaunchKernelGGL(k_scan_small, dim3(2), dim3(SMALL_THREADS), 0, st, s0, s1, n, 0u);
+  ZK_HIP(hipGetLastError());
 }
 
 }  // namespace zkvc
