@@ -117,6 +117,8 @@ constexpr uint64_t FEW_BUCKETS = 4096;  // a wavefront per bucket leaves most of
 // fill the device, and their additions cost about half the VALU work of the
 // cooperative forms (no idle product slots, no trees inside a task).
 constexpr uint64_t FEW_ENTRIES = 1ull << 19;
+constexpr uint64_t FIN_QUAD_BUCKETS = 16384;     // see batch_plan (finalize in quads)
+constexpr uint64_t FIN_QUAD_LANES = 1ull << 17;  // about two wavefronts per SIMD
 
 // ---------------------------------------------------------------- 1. digits
 // One thread per scalar: fold, recode into signed digits, write one word per
@@ -240,36 +242,53 @@ __global__ void __launch_bounds__(HS_THREADS) k_msm_hist(BatchDev B, const uint3
   for (uint32_t b = threadIdx.x; b < J.nb; b += HS_THREADS) h[b] = cnt[b];
 }
 
-// A thread per bucket f (window w, digit value b): the bucket's counts down
-// its column of histogram rows become running offsets inside the bucket, in
-// place; cnt[f] receives the bucket's size and nt[f] its number of tasks
-// (see k_msm_make_tasks).  Also clears the task-list counters.
-__global__ void k_msm_colscan(BatchDev B, uint32_t* hist, uint32_t nbt, uint32_t K, uint32_t large,
-                              uint32_t wg_entries, uint32_t* cnt, uint32_t* nt, uint32_t* counters) {
+// A quad of lanes per bucket f (window w, digit value b): lane q of the quad
+// takes the q-th quarter of the bucket's column of histogram rows.  A first
+// pass sums each quarter, a scan across the quad gives each quarter its
+// start, and a second pass turns the counts into running offsets inside the
+// bucket, in place; cnt[f] receives the bucket's size and nt[f] its number
+// of tasks (see k_msm_make_tasks).  Also clears the task-list counters.
+__global__ void __launch_bounds__(256) k_msm_colscan(BatchDev B, uint32_t* hist, uint32_t nbt, uint32_t K,
+                                                     uint32_t large, uint32_t wg_entries, uint32_t* cnt, uint32_t* nt,
+                                                     uint32_t* counters) {
   wave_priority(B.prio);
-  const uint32_t f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f == 0) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t f = t >> 2, q = t & 3u;
+  if (t == 0) {
     counters[0] = 0u;
     counters[1] = 0u;
     counters[2] = 0u;
   }
+  // a quad's four lanes share f: the whole quad is in or out
   if (f >= nbt) return;
   const int k = job_of<&JobDev::bucket_base>(B, f);
   const JobDev& J = B.job(k);
   const uint32_t lf = f - J.bucket_base;
   const uint32_t w = lf / J.nb, b = lf - w * J.nb;
-  uint32_t* col = hist + J.hist_base + (size_t)w * J.nch * J.nb + b;
-  uint32_t run = 0;
   const uint32_t nch = J.nch, nb = J.nb;
-#pragma unroll 4
-  for (uint32_t ch = 0; ch < nch; ch++) {
+  const uint32_t per = (nch + 3) >> 2;
+  const uint32_t c0 = min(nch, q * per), c1 = min(nch, c0 + per);
+  uint32_t* col = hist + J.hist_base + (size_t)w * nch * nb + b;
+  uint32_t part = 0;
+#pragma unroll 16
+  for (uint32_t ch = c0; ch < c1; ch++) part += col[(size_t)ch * nb];
+  // exclusive scan of the four quarter sums inside the quad
+  const uint32_t lane = threadIdx.x & 63u, qbase = lane & ~3u;
+  const uint32_t p0 = __shfl(part, qbase, 64), p1 = __shfl(part, qbase + 1, 64), p2 = __shfl(part, qbase + 2, 64),
+                 p3 = __shfl(part, qbase + 3, 64);
+  uint32_t run = (q > 0 ? p0 : 0u) + (q > 1 ? p1 : 0u) + (q > 2 ? p2 : 0u);
+#pragma unroll 16
+  for (uint32_t ch = c0; ch < c1; ch++) {
     const uint32_t v = col[(size_t)ch * nb];
     col[(size_t)ch * nb] = run;
     run += v;
   }
-  cnt[f] = run;
-  const uint32_t sz = run >= large ? wg_entries : K;
-  nt[f] = (run + sz - 1) / sz;
+  if (q == 0) {
+    const uint32_t total = p0 + p1 + p2 + p3;
+    cnt[f] = total;
+    const uint32_t sz = total >= large ? wg_entries : K;
+    nt[f] = (total + sz - 1) / sz;
+  }
 }
 
 // Same blocks as k_msm_hist: LDS cursors start at the bucket's first slot
@@ -673,7 +692,8 @@ struct BatchPlan {
   uint64_t max_th_tasks = 0, max_wg_tasks = 0, max_partials = 0;
   uint32_t fin_max = 0;  // partial sums above which a bucket gets a wavefront in the finalize step
   uint32_t fin_group = 1;  // lanes per bucket below that (about four partial sums per lane, or two per quad)
-  bool quad = false;       // latency-bound batch: wavefront tasks and finalize add in cooperative quads
+  bool quad = false;       // latency-bound batch: wavefront tasks add in cooperative quads
+  bool fin_quad = false;   // the finalize step adds in cooperative quads
   uint32_t wg_entries = WG_TASK_ENTRIES;
 };
 
@@ -713,10 +733,11 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs, int group) {
     J.nwb = J.pre ? 1u : (uint32_t)J.nw;
     const uint64_t wb = (uint64_t)J.nw * J.nb;
     if (J.pre) {
-      // one bucket set: chunks of >= 16384 digits over the whole stream, at
-      // most 2^22 histogram words
+      // one bucket set: chunks of >= 4096 digits over the whole stream (a
+      // block per chunk: enough blocks to spread the sort over the device),
+      // at most 2^22 histogram words
       const uint64_t total = (uint64_t)J.nw * J.n;
-      const uint64_t nch = std::max<uint64_t>(1, std::min<uint64_t>((total + 16383) / 16384, (1ull << 22) / J.nb));
+      const uint64_t nch = std::max<uint64_t>(1, std::min<uint64_t>((total + 4095) / 4096, (1ull << 22) / J.nb));
       const uint64_t chunk = ((total + nch - 1) / nch + 255) / 256 * 256;
       J.chunk = (uint32_t)chunk;
       J.nch = (uint32_t)((total + chunk - 1) / chunk);
@@ -787,9 +808,13 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs, int group) {
   // short thread tasks leave many partial sums per bucket: a small tree per
   // bucket keeps the finalize chain short
   p.fin_group = 1;
-  if (p.quad) {  // quads of about two partial sums each
+  // The finalize step is a chain of dependent additions per bucket; with few
+  // enough buckets that quads of lanes (up to about two wavefronts per SIMD)
+  // can share them, cooperative additions shorten the chains ~3x.
+  p.fin_quad = p.quad || p.nbt <= FIN_QUAD_BUCKETS;
+  if (p.fin_quad) {  // quads of about two partial sums each
     uint32_t quads = 1;
-    while (quads < 16 && 2 * quads < avg) quads *= 2;
+    while (quads < 16 && 2 * quads < avg && 8 * quads * p.nbt <= FIN_QUAD_LANES) quads *= 2;
     p.fin_group = 4 * quads;
   } else {
     while (p.fin_group < 64 && 4 * p.fin_group < avg) p.fin_group *= 2;
@@ -897,7 +922,7 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
     hipLaunchKernelGGL(k_msm_hist, dim3((unsigned)p.hs_blocks), dim3(HS_THREADS), lds, st, dev, digits, hist);
     ZK_HIP(hipGetLastError());
     // bucket sizes and task counts, then the buckets' first slots and first partial sums
-    hipLaunchKernelGGL(k_msm_colscan, dim3(cdiv(nbt, 256)), dim3(256), 0, st, dev, hist, nbt, p.K, p.large,
+    hipLaunchKernelGGL(k_msm_colscan, dim3(cdiv(nbt, 64)), dim3(256), 0, st, dev, hist, nbt, p.K, p.large,
                        p.wg_entries, cnt, nt, meta + 8);
     ZK_HIP(hipGetLastError());
     scan_exclusive2(cnt, off, meta + 3, nt, part_off, meta + 2, nbt, ws, S_SCRATCH, st);
@@ -922,7 +947,7 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
     const unsigned light_blocks = cdiv(nbt, 64 / p.fin_group);
     const unsigned heavy_blocks = (unsigned)std::min<uint64_t>(nbt, 1024);
     hipLaunchKernelGGL(k_msm_finalize<F>, dim3(light_blocks + heavy_blocks), dim3(64), 0, st, nt, part_off, part, nbt,
-                       meta + 8, heavy, light_blocks, p.fin_max, p.fin_group, p.quad ? 1 : 0, buckets, prio);
+                       meta + 8, heavy, light_blocks, p.fin_max, p.fin_group, p.fin_quad ? 1 : 0, buckets, prio);
     ZK_HIP(hipGetLastError());
   }
   {

@@ -1534,24 +1534,26 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
   // follow the quotient on the third lane.
   std::vector<MsmInput> &in_g1 = R.in_g1, &in_g2 = R.in_g2, &in_h = R.in_h;
   std::vector<int> &own_g1 = R.own_g1, &query_g1 = R.query_g1, &own_g2 = R.own_g2, &own_h = R.own_h;
-  for (size_t j = 0; j < nj; j++) {
-    for (const MsmJob& m : msm_jobs(jobs[j].pk, slots[j].assign, slots[j].aev, slots[j].wk)) {
-      if (m.query == ZKVC_Q_H) {
-        in_h.push_back(m.in);
-        own_h.push_back((int)j);
-      } else if (m.group == 2) {
-        in_g2.push_back(m.in);
-        own_g2.push_back((int)j);
-      } else {
-        in_g1.push_back(m.in);
-        own_g1.push_back((int)j);
-        query_g1.push_back(m.query);
+  auto build_lists = [&] {
+    for (size_t j = 0; j < nj; j++) {
+      for (const MsmJob& m : msm_jobs(jobs[j].pk, slots[j].assign, slots[j].aev, slots[j].wk)) {
+        if (m.query == ZKVC_Q_H) {
+          in_h.push_back(m.in);
+          own_h.push_back((int)j);
+        } else if (m.group == 2) {
+          in_g2.push_back(m.in);
+          own_g2.push_back((int)j);
+        } else {
+          in_g1.push_back(m.in);
+          own_g1.push_back((int)j);
+          query_g1.push_back(m.query);
+        }
       }
     }
-  }
-  R.pend_g1.resize(in_g1.size());
-  R.pend_g2.resize(in_g2.size());
-  R.pend_h.resize(in_h.size());
+    R.pend_g1.resize(in_g1.size());
+    R.pend_g2.resize(in_g2.size());
+    R.pend_h.resize(in_h.size());
+  };
   hipStream_t lane_h = ctx.lanes[ProveCtx::LANE_H], lane_g1 = ctx.lanes[ProveCtx::LANE_G1],
               lane_g2 = ctx.lanes[ProveCtx::LANE_G2];
   auto g2_lane = [&] {
@@ -1569,15 +1571,31 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
     record_ext(G.lane_t[ProveCtx::LANE_G1], lane_g1, capture);
   };
   // Every launch costs host time, so one thread enqueueing the lanes one
-  // after the other delays the later ones: the G2 and G1 lanes are enqueued
-  // by helper threads while this thread enqueues the quotient and the H lane
-  // (the critical path).  Under capture everything is enqueued from here.
+  // after the other delays the later ones: a helper builds the job lists and
+  // enqueues the G2 lane, another the G1 lane once the lists exist, while
+  // this thread goes straight on to the quotient and then the H lane (the
+  // critical path).  Under capture everything is enqueued from here.
   std::future<void> f_g2, f_g1;
+  std::promise<void> lists_ready;
+  std::shared_future<void> lists = lists_ready.get_future().share();
   if (capture) {
+    build_lists();
     g2_lane();
   } else {
-    f_g2 = ctx.pool->run(g2_lane);
-    f_g1 = ctx.pool->run(g1_lane);
+    f_g2 = ctx.pool->run([&] {
+      try {
+        build_lists();
+      } catch (...) {
+        lists_ready.set_exception(std::current_exception());
+        throw;
+      }
+      lists_ready.set_value();
+      g2_lane();
+    });
+    f_g1 = ctx.pool->run([&] {
+      lists.get();
+      g1_lane();
+    });
   }
   auto join_helpers = [&] {
     if (f_g2.valid()) f_g2.wait();
@@ -1641,6 +1659,7 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
     ZK_HIP(hipEventRecord(G.quotient_ev, st));
 
     // ---- the H lane after the quotients
+    if (!capture) lists.get();  // rethrows a failure to build the lists
     ZK_HIP(hipStreamWaitEvent(lane_h, G.quotient_ev, 0));
     msm_enqueue_batch_g1(in_h.data(), (int)in_h.size(), G.lane_ws[ProveCtx::LANE_H], lane_h, R.pend_h.data(),
                          H_LANE_PRIO);

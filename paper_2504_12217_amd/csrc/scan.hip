@@ -91,12 +91,14 @@ __global__ void k_scan_add(uint32_t* out, uint32_t n, const uint32_t* tile_prefi
 }
 
 // Small arrays in one launch: one block walks the array in tiles of
-// SMALL_THREADS * SCAN_ITEMS values, carrying the running total.
-constexpr int SMALL_THREADS = 1024;
+// SMALL_THREADS * SMALL_ITEMS values (16-byte loads), carrying the running
+// total.
+constexpr int SMALL_THREADS = 256;  // a small block finds room on a device busy with other kernels
+constexpr int SMALL_ITEMS = 32;
 constexpr uint32_t SMALL_SCAN_MAX = 1u << 15;
 
 // Up to two independent scans per launch: block 0 takes the first array,
-// block 1 (if launched) the second.
+// block 1 (if launched) the second.  Arrays are 16-byte aligned.
 struct SmallScan {
   const uint32_t* in;
   uint32_t* out;
@@ -114,14 +116,27 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_scan_small(SmallScan s0, Smal
   __shared__ uint32_t shmax[SMALL_THREADS / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   uint32_t carry = 0, mx = 0;
-  for (uint32_t start = 0; start < n; start += SMALL_THREADS * SCAN_ITEMS) {
-    const uint32_t base = start + threadIdx.x * SCAN_ITEMS;
-    uint32_t vals[SCAN_ITEMS];
+  for (uint32_t start = 0; start < n; start += SMALL_THREADS * SMALL_ITEMS) {
+    const uint32_t base = start + threadIdx.x * SMALL_ITEMS;
+    uint32_t vals[SMALL_ITEMS];
+    if (base + SMALL_ITEMS <= n) {
+      const uint4* v4 = reinterpret_cast<const uint4*>(in + base);
+#pragma unroll
+      for (int q = 0; q < SMALL_ITEMS / 4; q++) {
+        const uint4 v = v4[q];
+        vals[4 * q] = v.x;
+        vals[4 * q + 1] = v.y;
+        vals[4 * q + 2] = v.z;
+        vals[4 * q + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < SMALL_ITEMS; q++) vals[q] = base + q < n ? in[base + q] : 0u;
+    }
     uint32_t sum = 0;
 #pragma unroll
-    for (int q = 0; q < SCAN_ITEMS; q++) {
-      const uint32_t i = base + q;
-      const uint32_t v = i < n ? scan_f(in[i], div) : 0u;
+    for (int q = 0; q < SMALL_ITEMS; q++) {
+      const uint32_t v = scan_f(vals[q], div);
       vals[q] = sum;
       sum += v;
       mx = v > mx ? v : mx;
@@ -146,10 +161,15 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_scan_small(SmallScan s0, Smal
     }
     __syncthreads();
     const uint32_t excl = carry + x - sum + sh[wid];
+    if (base + SMALL_ITEMS <= n) {
+      uint4* o4 = reinterpret_cast<uint4*>(out + base);
 #pragma unroll
-    for (int q = 0; q < SCAN_ITEMS; q++) {
-      const uint32_t i = base + q;
-      if (i < n) out[i] = vals[q] + excl;
+      for (int q = 0; q < SMALL_ITEMS / 4; q++)
+        o4[q] = make_uint4(vals[4 * q] + excl, vals[4 * q + 1] + excl, vals[4 * q + 2] + excl, vals[4 * q + 3] + excl);
+    } else {
+#pragma unroll
+      for (int q = 0; q < SMALL_ITEMS; q++)
+        if (base + q < n) out[base + q] = vals[q] + excl;
     }
     carry += sh[SMALL_THREADS / 64];
     __syncthreads();
