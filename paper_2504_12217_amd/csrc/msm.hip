@@ -556,8 +556,15 @@ __global__ void __launch_bounds__(64) k_msm_finalize(const uint32_t* nt, const u
 // A plane is split over bpb blocks; each quad of a block sums a strided
 // share of its block's slice with cooperative additions, a tree of quads
 // sums the block, and k_msm_plane_sums adds the bpb block sums of each plane.
+// G1 bit planes run at four wavefronts per SIMD (at most 128 VGPRs, a few
+// spilled): the reduction of a large bucket set then fits the device in one
+// round of blocks.  G2's working set is too large for that.
 template <class F>
-__global__ void __launch_bounds__(BP_THREADS) k_msm_bitplanes(BatchDev B, const uint32_t* buckets, uint32_t* part,
+struct BpWaves {
+  static constexpr int value = sizeof(F) <= 64 ? 4 : 1;
+};
+template <class F>
+__global__ void __launch_bounds__(BP_THREADS, BpWaves<F>::value) k_msm_bitplanes(BatchDev B, const uint32_t* buckets, uint32_t* part,
                                                                uint32_t* S) {
   wave_priority(B.prio);
   constexpr int XW = PointIO<F>::XYZZ_WORDS;
