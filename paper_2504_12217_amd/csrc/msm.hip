@@ -44,7 +44,7 @@ constexpr uint32_t WG_TASK_ENTRIES_QUAD = 64;  // the same when the wavefront wo
 constexpr uint32_t SIGN = 0x80000000u;
 enum MsmSlot {
   S_DIGITS = 100, S_COUNTS, S_OFFSETS, S_HEAVY, S_SORTED, S_TASKS, S_CNT_A, S_CNT_B, S_OFF_A, S_OFF_B,
-  S_PART0, S_PART1, S_SCRATCH, S_SCRATCH2, S_SEG, S_WIN, S_META, S_FB_XYZZ, S_FB_PREFIX, S_BP_PART, S_JOBS
+  S_PART0, S_PART1, S_SCRATCH, S_SCRATCH2, S_SEG, S_WIN, S_META, S_FB_XYZZ, S_FB_PREFIX, S_BP_PART, S_JOBS, S_RED
 };
 
 __device__ __forceinline__ uint32_t bitrev_n(uint32_t a, int bits) {
@@ -71,6 +71,13 @@ struct JobDev {
   uint32_t plane_base;      // first bit plane (nwb * c planes)
   uint32_t bpb;             // blocks per bit plane (a power of two)
   uint32_t blk_bp;          // first block of the bit-plane grid (nwb * c * bpb blocks)
+  // the grid reduction of large bucket sets (see k_msm_gridsums): log2 of the
+  // grid's row length L (0: plain bit planes), its first sum, first block
+  uint32_t grid_lg, grid_base, blk_gs;
+  // bit-plane entries (the reduction table, see batch_plan): points per set
+  // read from set_stride apart, log2(nb), and where set w's plane j goes:
+  // plane_base + w * pstride + poff + j
+  uint32_t set_stride, lg, pstride, poff;
   uint32_t blk_digits;      // first block of the digit grid
   uint32_t blk_hs;          // first block of the histogram / scatter grid (nw * nch blocks, or nch)
 };
@@ -549,10 +556,63 @@ __global__ void __launch_bounds__(64) k_msm_finalize(const uint32_t* nt, const u
   }
 }
 
-// ---------------------------------------------------------------- 4. bucket reduction by bit planes
+// ---------------------------------------------------------------- 4. bucket reduction
 // For window w and bit j,
-//   S[w c + j] = sum of B_b over the buckets whose digit value b + 1 has bit j set,
-// so that window w contributes sum_j 2^j S[w c + j] = sum_b (b + 1) B_b.
+//   S[w c + j] = sum of B_{v-1} over the digit values v in [1, nb] with bit j set,
+// so that window w contributes sum_j 2^j S[w c + j] = sum_v v B_{v-1}; the
+// host adds the planes by Horner's rule.
+//
+// Grid reduction (bucket sets of nb >= GRID_MIN_NB).  With v = r L + l
+// (L = 2^grid_lg, R = nb / L; r in [0, R], l in [0, L)),
+//   sum_v v B_{v-1} = L sum_{r=1..R} r T_r + sum_{l=1..L-1} l C_l,
+// where the row sum T_r adds the buckets with v in [r L, r L + L) and the
+// column sum C_l those with v = l, L + l, ..., (R-1) L + l.  k_msm_gridsums
+// forms the R + L - 1 sums (about 2 nb additions in trees of depth
+// log2 L + 1, instead of the c nb / 2 of the bit planes over all buckets),
+// and the planes are then taken over the sums: planes 0 .. grid_lg - 1 of
+// the set from the column sums (digit value l), planes grid_lg .. c - 1 from
+// the row sums (digit value r), which is the same plane S[w c + j] as above.
+constexpr uint32_t GRID_MIN_NB = 1024;
+
+// One block per sum: (set w, index i); i < L - 1 is column l = i + 1 (into
+// slot i of the set's L + R sums), i >= L - 1 row r = i - L + 2 (into slot
+// L + r - 1).  Quads add a strided share, then a tree of quads.
+template <class F>
+__global__ void __launch_bounds__(BP_THREADS) k_msm_gridsums(BatchDev B, uint32_t* buckets) {
+  wave_priority(B.prio);
+  constexpr int XW = PointIO<F>::XYZZ_WORDS;
+  __shared__ uint32_t sh[BP_THREADS / 8 * XW];
+  const int k = job_of<&JobDev::blk_gs>(B, blockIdx.x);
+  const JobDev& J = B.job(k);
+  const uint32_t L = 1u << J.grid_lg, R = J.nb >> J.grid_lg;
+  const uint32_t local = blockIdx.x - J.blk_gs;
+  const uint32_t w = local / (L - 1 + R), i = local % (L - 1 + R);
+  const uint32_t* bw = buckets + ((size_t)J.bucket_base + (size_t)w * J.nb) * XW;
+  // entry e of the sum is bucket first + e * step (digit value first + 1 + e * step)
+  uint32_t first, step, count, slot;
+  if (i < L - 1) {
+    first = i;  // value l = i + 1
+    step = L;
+    count = R;
+    slot = i;
+  } else {
+    const uint32_t r = i - (L - 1) + 1;
+    first = r * L - 1;  // value r L
+    step = 1;
+    count = r < R ? L : 1u;  // row R holds only v = nb
+    slot = L + r - 1;
+  }
+  const uint32_t team = threadIdx.x >> 2, tq = threadIdx.x & 3u, nteams = blockDim.x >> 2;
+  Xyzz<F> acc = Xyzz<F>::inf();
+  for (uint32_t e = team; e < count; e += nteams)
+    acc = QuadOps<F>::add(acc, PointIO<F>::load_xyzz(bw + (size_t)(first + e * step) * XW), tq);
+  acc = quad_tree_sum<F>(acc, sh, nteams);
+  if (threadIdx.x == 0)
+    PointIO<F>::store_xyzz(buckets + ((size_t)J.grid_base + (size_t)w * (L + R) + slot) * XW, acc);
+}
+
+// Bit planes over the entries of the reduction table: plain jobs (their
+// buckets) and, for grid jobs, two entries over the column and row sums.
 // A plane is split over bpb blocks; each quad of a block sums a strided
 // share of its block's slice with cooperative additions, a tree of quads
 // sums the block, and k_msm_plane_sums adds the bpb block sums of each plane.
@@ -575,10 +635,10 @@ __global__ void __launch_bounds__(BP_THREADS, BpWaves<F>::value) k_msm_bitplanes
   const uint32_t q = local / J.bpb, slice = local % J.bpb;
   const uint32_t c = (uint32_t)J.c, nb = J.nb;
   const uint32_t w = q / c, j = q % c;
-  const uint32_t* bw = buckets + ((size_t)J.bucket_base + (size_t)w * nb) * XW;
+  const uint32_t* bw = buckets + ((size_t)J.bucket_base + (size_t)w * J.set_stride) * XW;
   // digit values v in [1, nb] with bit j set: v = ((t >> j) << (j + 1)) | 2^j | (t & (2^j - 1))
   const uint32_t jmask = (1u << j) - 1u;
-  const uint32_t count = (j + 1 < c) ? nb / 2 : 1u;  // bit c-1 is set only in v = nb
+  const uint32_t count = j < J.lg ? nb / 2 : 1u;  // bit lg = log2(nb) is set only in v = nb
   const uint32_t per = (count + J.bpb - 1) / J.bpb;
   const uint32_t t0 = slice * per, t1 = min(count, t0 + per);
   const uint32_t team = threadIdx.x >> 2, tq = threadIdx.x & 3u, nteams = blockDim.x >> 2;
@@ -591,7 +651,7 @@ __global__ void __launch_bounds__(BP_THREADS, BpWaves<F>::value) k_msm_bitplanes
   acc = quad_tree_sum<F>(acc, sh, nteams);
   if (threadIdx.x != 0) return;
   if (J.bpb == 1) {  // the block's sum is the plane
-    PointIO<F>::store_xyzz(S + ((size_t)J.plane_base + q) * XW, Xyzz<F>::canon(acc));
+    PointIO<F>::store_xyzz(S + ((size_t)J.plane_base + (size_t)w * J.pstride + J.poff + j) * XW, Xyzz<F>::canon(acc));
     __threadfence_system();  // S may be host memory
   } else {
     PointIO<F>::store_xyzz(part + (size_t)blockIdx.x * XW, acc);
@@ -691,7 +751,11 @@ void hfq2_to_dev(const host::HFq2& a, uint32_t* w) {
 // pipeline needs no host synchronization until the window sums come back.
 struct BatchPlan {
   std::vector<JobDev> jobs;   // the device table's contents
+  std::vector<JobDev> red;    // the reduction table: the bit-plane entries (see k_msm_bitplanes)
   std::vector<int> map;       // table entry -> caller's job
+  uint64_t ngrid = 0;         // grid sums after the nbt buckets in the bucket buffer
+  uint64_t gs_blocks = 0;     // blocks of k_msm_gridsums
+  uint32_t gs_threads = 64;
   uint64_t ndigits = 0, nbt = 0, nh = 0, nplanes = 0, digit_blocks = 0, hs_blocks = 0, bp_blocks = 0;
   uint32_t max_nb = 0;
   uint32_t K = 0;      // entries per thread task
@@ -759,23 +823,70 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs, int group) {
     J.bucket_base = (uint32_t)p.nbt;
     J.hist_base = (uint32_t)p.nh;
     J.plane_base = (uint32_t)p.nplanes;
-    // about two bucket additions per thread before each block's tree
     // about two bucket additions per quad (four lanes) before each block's tree
     J.bpb = std::max<uint32_t>(1, J.nb / 2 / (BP_THREADS / 2));
-    J.blk_bp = (uint32_t)p.bp_blocks;
     J.blk_digits = (uint32_t)p.digit_blocks;
     J.blk_hs = (uint32_t)p.hs_blocks;
     p.ndigits += (uint64_t)J.nw * J.n;
     p.nbt += (uint64_t)J.nwb * J.nb;
     p.nh += (uint64_t)J.nwb * J.nb * J.nch;
     p.nplanes += (uint64_t)J.nwb * J.c;
-    p.bp_blocks += (uint64_t)J.nwb * J.c * J.bpb;
     p.digit_blocks += cdiv(J.n, 256);
     p.hs_blocks += J.pre ? (uint64_t)J.nch : (uint64_t)J.nw * J.nch;
     p.max_nb = std::max(p.max_nb, J.nb);
     p.map.push_back(q);
     ZK_REQUIRE(p.ndigits < (1ull << 32) && p.nh < (1ull << 32) - 1 && p.nbt < (1ull << 31),
                "MSM batch too large for 32-bit offsets");
+  }
+  // the bucket reduction: grid sums of the large bucket sets after all the
+  // buckets, then the reduction table in job order
+  for (JobDev& J : p.jobs) {
+    J.grid_lg = J.grid_base = 0;
+    J.blk_gs = (uint32_t)p.gs_blocks;
+    if (J.nb >= GRID_MIN_NB) {
+      J.grid_lg = (uint32_t)(J.c - 1) / 2;
+      const uint32_t L = 1u << J.grid_lg, R = J.nb >> J.grid_lg;
+      J.grid_base = (uint32_t)(p.nbt + p.ngrid);
+      p.ngrid += (uint64_t)J.nwb * (L + R);
+      p.gs_blocks += (uint64_t)J.nwb * (L - 1 + R);
+      // quads of about two entries each (R >= L entries at most per sum)
+      while (p.gs_threads < (uint32_t)BP_THREADS && p.gs_threads < 2 * R) p.gs_threads *= 2;
+    }
+  }
+  ZK_REQUIRE(p.nbt + p.ngrid < (1ull << 31), "MSM batch too large for 32-bit offsets");
+  for (const JobDev& J : p.jobs) {
+    JobDev e = J;
+    e.pstride = (uint32_t)J.c;
+    if (!J.grid_lg) {
+      e.set_stride = J.nb;
+      e.lg = (uint32_t)J.c - 1;
+      e.poff = 0;
+      e.blk_bp = (uint32_t)p.bp_blocks;
+      p.bp_blocks += (uint64_t)J.nwb * J.c * J.bpb;
+      p.red.push_back(e);
+      continue;
+    }
+    const uint32_t L = 1u << J.grid_lg, R = J.nb >> J.grid_lg;
+    e.set_stride = L + R;
+    e.bpb = 1;  // L, R <= 128: one block per plane
+    // column sums: digit values l in [1, L), planes 0 .. grid_lg - 1
+    e.bucket_base = J.grid_base;
+    e.nb = L;
+    e.lg = J.grid_lg;
+    e.c = (int)J.grid_lg;
+    e.poff = 0;
+    e.blk_bp = (uint32_t)p.bp_blocks;
+    p.bp_blocks += (uint64_t)J.nwb * e.c;
+    p.red.push_back(e);
+    // row sums: digit values r in [1, R], planes grid_lg .. c - 1
+    e.bucket_base = J.grid_base + L;
+    e.nb = R;
+    e.lg = (uint32_t)J.c - 1 - J.grid_lg;
+    e.c = (int)e.lg + 1;
+    e.poff = J.grid_lg;
+    e.blk_bp = (uint32_t)p.bp_blocks;
+    p.bp_blocks += (uint64_t)J.nwb * e.c;
+    p.red.push_back(e);
   }
   const uint64_t E = p.ndigits;  // bound on the bucket entries
   // thread tasks: enough of them to fill the device, long enough to amortize
@@ -836,7 +947,7 @@ struct MsmBufs {
   uint32_t *digits, *hist, *cnt, *off, *nt, *part_off, *sorted, *part, *buckets, *win, *bp_part, *heavy, *meta,
       *win_host;
   uint4 *th_tasks, *wg_tasks;
-  JobDev *jt_host, *jt_dev;
+  JobDev *jt_host, *jt_dev, *rt_host, *rt_dev;
 };
 
 static MsmBufs msm_buffers(const BatchPlan& p, Workspace& ws, int XW) {
@@ -852,7 +963,7 @@ static MsmBufs msm_buffers(const BatchPlan& p, Workspace& ws, int XW) {
   b.th_tasks = ws.get<uint4>(S_TASKS, p.max_th_tasks * 16);
   b.wg_tasks = ws.get<uint4>(S_PART1, p.max_wg_tasks * 16);
   b.part = ws.get(S_PART0, p.max_partials * XW * 4);
-  b.buckets = ws.get(S_SEG, p.nbt * XW * 4);
+  b.buckets = ws.get(S_SEG, (p.nbt + p.ngrid) * XW * 4);
   // plane sums: written by the kernels straight into pinned host memory when
   // the workspace's host buffers are device-visible, else copied back
   b.win = ws.host_mapped() ? nullptr : ws.get(S_WIN, p.nplanes * XW * 4);
@@ -863,10 +974,15 @@ static MsmBufs msm_buffers(const BatchPlan& p, Workspace& ws, int XW) {
   ws.get(S_SCRATCH, (size_t)cdiv(p.nbt, 2048) * 4 + 64);
   // a job table beyond the kernel arguments, through pinned memory (the
   // workspace is not reused before this stream has completed)
-  b.jt_host = b.jt_dev = nullptr;
+  b.jt_host = b.jt_dev = b.rt_host = b.rt_dev = nullptr;
   if (nj > (size_t)INLINE_JOBS) {
     b.jt_host = ws.host<JobDev>(S_JOBS, nj * sizeof(JobDev));
     b.jt_dev = ws.get<JobDev>(S_JOBS, nj * sizeof(JobDev));
+  }
+  const size_t nr = p.red.size();
+  if (nr > (size_t)INLINE_JOBS) {
+    b.rt_host = ws.host<JobDev>(S_RED, nr * sizeof(JobDev));
+    b.rt_dev = ws.get<JobDev>(S_RED, nr * sizeof(JobDev));
   }
   return b;
 }
@@ -900,16 +1016,21 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
            *part_off = bf.part_off, *sorted = bf.sorted, *part = bf.part, *buckets = bf.buckets, *win = bf.win,
            *bp_part = bf.bp_part, *heavy = bf.heavy, *meta = bf.meta, *win_host = bf.win_host;
   uint4 *th_tasks = bf.th_tasks, *wg_tasks = bf.wg_tasks;
-  BatchDev dev{};
-  dev.njobs = nj;
-  dev.prio = prio;
-  if (nj <= INLINE_JOBS) {
-    for (int k = 0; k < nj; k++) dev.inl[k] = p.jobs[k];
-  } else {
-    std::memcpy(bf.jt_host, p.jobs.data(), nj * sizeof(JobDev));
-    ZK_HIP(hipMemcpyAsync(bf.jt_dev, bf.jt_host, nj * sizeof(JobDev), hipMemcpyHostToDevice, st));
-    dev.jobs = bf.jt_dev;
-  }
+  auto table = [&](const std::vector<JobDev>& v, JobDev* th, JobDev* td) {
+    BatchDev t{};
+    t.njobs = (int)v.size();
+    t.prio = prio;
+    if (v.size() <= (size_t)INLINE_JOBS) {
+      for (size_t k = 0; k < v.size(); k++) t.inl[k] = v[k];
+    } else {
+      std::memcpy(th, v.data(), v.size() * sizeof(JobDev));
+      ZK_HIP(hipMemcpyAsync(td, th, v.size() * sizeof(JobDev), hipMemcpyHostToDevice, st));
+      t.jobs = td;
+    }
+    return t;
+  };
+  const BatchDev dev = table(p.jobs, bf.jt_host, bf.jt_dev);
+  const BatchDev red = table(p.red, bf.rt_host, bf.rt_dev);
   for (int k = 0; k < nj; k++) {
     MsmPending& pd = pend[p.map[k]];
     pd.empty = false;
@@ -957,24 +1078,31 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
                        meta + 8, heavy, light_blocks, p.fin_max, p.fin_group, p.fin_quad ? 1 : 0, buckets, prio);
     ZK_HIP(hipGetLastError());
   }
+  if (p.gs_blocks) {
+    double adds = 0;  // about one addition per bucket for the rows and one for the columns
+    for (const JobDev& J : p.jobs)
+      if (J.grid_lg) adds += 2.0 * J.nwb * J.nb;
+    ProfScope ps(g1 ? "msm_gridsums_g1" : "msm_gridsums_g2", st, adds);
+    hipLaunchKernelGGL(k_msm_gridsums<F>, dim3((unsigned)p.gs_blocks), dim3(p.gs_threads), 0, st, dev, buckets);
+    ZK_HIP(hipGetLastError());
+  }
   {
     double adds = 0;
-    for (int k = 0; k < nj; k++) adds += (double)p.jobs[k].nwb * p.jobs[k].c * p.jobs[k].nb / 2;
+    for (const JobDev& e : p.red) adds += (double)e.nwb * e.c * e.nb / 2;
     ProfScope ps(g1 ? "msm_bitplanes_g1" : "msm_bitplanes_g2", st, adds);
     uint32_t per_block = 1;
-    for (int k = 0; k < nj; k++)
-      per_block = std::max(per_block, (p.jobs[k].nb / 2 + p.jobs[k].bpb - 1) / p.jobs[k].bpb);
+    for (const JobDev& e : p.red) per_block = std::max(per_block, (e.nb / 2 + e.bpb - 1) / e.bpb);
     // quads of about two bucket additions each: 2 per_block lanes (64 to BP_THREADS)
     unsigned bp_threads = 64;
     while (bp_threads < (unsigned)BP_THREADS && bp_threads < 2 * per_block) bp_threads *= 2;
-    hipLaunchKernelGGL(k_msm_bitplanes<F>, dim3((unsigned)p.bp_blocks), dim3(bp_threads), 0, st, dev, buckets,
+    hipLaunchKernelGGL(k_msm_bitplanes<F>, dim3((unsigned)p.bp_blocks), dim3(bp_threads), 0, st, red, buckets,
                        bp_part, win_out);
     ZK_HIP(hipGetLastError());
     // planes of one block each are final already
     bool split = false;
-    for (int k = 0; k < nj; k++) split = split || p.jobs[k].bpb > 1;
+    for (const JobDev& e : p.red) split = split || e.bpb > 1;
     if (split) {
-      hipLaunchKernelGGL(k_msm_plane_sums<F>, dim3((unsigned)p.nplanes), dim3(64), 0, st, dev, bp_part, win_out);
+      hipLaunchKernelGGL(k_msm_plane_sums<F>, dim3((unsigned)p.nplanes), dim3(64), 0, st, red, bp_part, win_out);
       ZK_HIP(hipGetLastError());
     }
   }
