@@ -1377,6 +1377,10 @@ struct BatchRun {
   std::vector<MsmPending> pend_g1, pend_g2, pend_h;
   volatile uint32_t* flag_host = nullptr;  // pinned, written by the tail check
   std::chrono::steady_clock::time_point host_t0;
+  // the H MSMs on the quotient's own stream (no cross-stream wait between
+  // them); a pipelined caller keeps them on the H lane so that its next
+  // batch's witness need not wait behind them
+  bool h_on_main = false;
 };
 
 void BatchRunDeleter::operator()(BatchRun* r) const { delete r; }
@@ -1404,7 +1408,8 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
 
 int set_graphs(int enable) { return g_graphs.exchange(enable ? 1 : 0); }
 
-BatchRunPtr prove_batch_begin(ProveCtx& ctx, int g, const ProveJob* jobs_in, size_t nj, hipStream_t st) {
+BatchRunPtr prove_batch_begin(ProveCtx& ctx, int g, const ProveJob* jobs_in, size_t nj, hipStream_t st,
+                              bool pipelined) {
   ZK_REQUIRE(nj >= 1, "empty proof batch");
   ZK_REQUIRE(g >= 0 && g < ProveCtx::GENS, "bad context generation");
   ZK_REQUIRE(current_device() == ctx.device, "proof context of another device");
@@ -1416,6 +1421,7 @@ BatchRunPtr prove_batch_begin(ProveCtx& ctx, int g, const ProveJob* jobs_in, siz
   key.push_back((uint64_t)(uintptr_t)st);
   key.push_back(tuning_fingerprint());
   key.push_back(profiling_enabled() ? 1 : 0);
+  key.push_back(pipelined ? 1 : 0);
   for (size_t j = 0; j < nj; j++) {
     key.push_back(jobs_in[j].pk->id);
     // device buffers are baked into a captured graph
@@ -1468,6 +1474,7 @@ BatchRunPtr prove_batch_begin(ProveCtx& ctx, int g, const ProveJob* jobs_in, siz
   BatchRun& R = *run;
   R.ctx = &ctx;
   R.g = g;
+  R.h_on_main = !pipelined;
   R.jobs.assign(jobs_in, jobs_in + nj);
   R.host_t0 = std::chrono::steady_clock::now();
   while (G.slot_ws.size() < nj) G.slot_ws.emplace_back(new Workspace());
@@ -1660,11 +1667,12 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
 
     // ---- the H lane after the quotients
     if (!capture) lists.get();  // rethrows a failure to build the lists
-    ZK_HIP(hipStreamWaitEvent(lane_h, G.quotient_ev, 0));
-    msm_enqueue_batch_g1(in_h.data(), (int)in_h.size(), G.lane_ws[ProveCtx::LANE_H], lane_h, R.pend_h.data(),
+    const hipStream_t h_st = R.h_on_main ? st : lane_h;
+    if (!R.h_on_main) ZK_HIP(hipStreamWaitEvent(lane_h, G.quotient_ev, 0));
+    msm_enqueue_batch_g1(in_h.data(), (int)in_h.size(), G.lane_ws[ProveCtx::LANE_H], h_st, R.pend_h.data(),
                          H_LANE_PRIO);
-    record_ext(G.done_ev[ProveCtx::LANE_H], lane_h, capture);
-    record_ext(G.lane_t[ProveCtx::LANE_H], lane_h, capture);
+    record_ext(G.done_ev[ProveCtx::LANE_H], h_st, capture);
+    record_ext(G.lane_t[ProveCtx::LANE_H], h_st, capture);
   } catch (...) {
     join_helpers();
     throw;
@@ -1796,7 +1804,7 @@ void prove_batch_abandon(BatchRunPtr& run) {
 }
 
 void groth16_prove_batch(ProveCtx& ctx, const ProveJob* jobs, size_t nj, hipStream_t st) {
-  BatchRunPtr run = prove_batch_begin(ctx, 0, jobs, nj, st);
+  BatchRunPtr run = prove_batch_begin(ctx, 0, jobs, nj, st, false);
   try {
     prove_batch_finish(ctx, *run);
   } catch (...) {

@@ -209,7 +209,8 @@ void groth16_prove_batch(ProveCtx& ctx, const ProveJob* jobs, size_t njobs, hipS
 // generation g of the context (no host wait); finish waits for it, combines
 // and assembles on the host, and writes the outputs.  A generation must be
 // finished before it is begun again; the other one may be in flight.
-BatchRunPtr prove_batch_begin(ProveCtx& ctx, int g, const ProveJob* jobs, size_t njobs, hipStream_t st);
+BatchRunPtr prove_batch_begin(ProveCtx& ctx, int g, const ProveJob* jobs, size_t njobs, hipStream_t st,
+                              bool pipelined = true);
 void prove_batch_finish(ProveCtx& ctx, BatchRun& run);
 // Releases a run; one begun but not finished first waits for its device work.
 void prove_batch_abandon(BatchRunPtr& run);
