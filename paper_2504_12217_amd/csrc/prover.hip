@@ -357,6 +357,7 @@ struct WitJob {
   const uint32_t* zpow;
   uint32_t *assign, *aev, *bev, *cev;
   uint32_t *xk, *wk, *pkk, *yz;  // CRPC kinds: per-k sums and Y(z) partial sums
+  uint32_t nyz;                  // number of Y(z) partial sums
 };
 struct WitTable {
   const WitJob* jobs;  // device table, or null: use `one`
@@ -364,40 +365,8 @@ struct WitTable {
   __device__ __forceinline__ const WitJob& get(uint32_t q) const { return jobs ? jobs[q] : one; }
 };
 
-__global__ void __launch_bounds__(256) k_matmul(WitTable T) {
-  const WitJob& J = T.get(blockIdx.z);
-  const uint32_t i = blockIdx.y;
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t n = J.n, b = J.b;
-  if (i >= J.a || j >= b) return;
-  const int8_t* x = J.X + (size_t)i * n;
-  const int8_t* W = J.W;
-  int32_t acc0 = 0, acc1 = 0;
-  uint32_t k = 0;
-  for (; k + 8 <= n; k += 8) {
-#pragma unroll
-    for (int q = 0; q < 8; q += 2) {
-      acc0 += (int32_t)x[k + q] * (int32_t)W[(size_t)(k + q) * b + j];
-      acc1 += (int32_t)x[k + q + 1] * (int32_t)W[(size_t)(k + q + 1) * b + j];
-    }
-  }
-  for (; k < n; k++) acc0 += (int32_t)x[k] * (int32_t)W[(size_t)k * b + j];
-  J.Y[(size_t)i * b + j] = acc0 + acc1;
-}
 
 // assignment (canonical words) of the constant, x, y and w variables
-__global__ void k_assign_public(WitTable T) {
-  const WitJob& J = T.get(blockIdx.y);
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t an = (uint64_t)J.a * J.n, ab = (uint64_t)J.a * J.b, nb = (uint64_t)J.n * J.b;
-  if (i >= 1 + an + ab + nb) return;
-  int64_t v;
-  if (i == 0) v = 1;
-  else if (i <= an) v = J.X[i - 1];
-  else if (i <= an + ab) v = J.Y[i - 1 - an];
-  else v = J.W[i - 1 - an - ab];
-  store_int(J.assign + 8ull * i, v);
-}
 
 // Multiplication rows of the plain family, and their auxiliary variables.
 __global__ void k_rows_plain(WitTable T) {
@@ -452,26 +421,6 @@ __global__ void k_rows_plain(WitTable T) {
   store_int(J.cev + 8ull * c, cval);
 }
 
-// Input-consistency rows m .. m + l (A = variable t) and the zero rows after them.
-__global__ void k_rows_tail(WitTable T) {
-  const WitJob& J = T.get(blockIdx.y);
-  const uint64_t c = J.m + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= J.N) return;
-  const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
-  if (c - J.m <= J.ell) {
-    const uint4* s = reinterpret_cast<const uint4*>(J.assign + 8ull * (c - J.m));
-    reinterpret_cast<uint4*>(J.aev + 8ull * c)[0] = s[0];
-    reinterpret_cast<uint4*>(J.aev + 8ull * c)[1] = s[1];
-  } else {
-    reinterpret_cast<uint4*>(J.aev + 8ull * c)[0] = z4;
-    reinterpret_cast<uint4*>(J.aev + 8ull * c)[1] = z4;
-  }
-  reinterpret_cast<uint4*>(J.bev + 8ull * c)[0] = z4;
-  reinterpret_cast<uint4*>(J.bev + 8ull * c)[1] = z4;
-  reinterpret_cast<uint4*>(J.cev + 8ull * c)[0] = z4;
-  reinterpret_cast<uint4*>(J.cev + 8ull * c)[1] = z4;
-}
-
 constexpr int RED_THREADS = 256;
 
 __device__ Fr block_sum(Fr x, uint32_t* sh) {
@@ -491,11 +440,7 @@ __device__ Fr block_sum(Fr x, uint32_t* sh) {
 }
 
 // Block k: X_k(z) = sum_i z^(i b) x_ik, W_k(z) = sum_j z^j w_kj and their product.
-__global__ void __launch_bounds__(RED_THREADS) k_crpc_xw(WitTable T) {
-  __shared__ uint32_t sh[RED_THREADS * NL];
-  const WitJob& J = T.get(blockIdx.y);
-  const uint32_t k = blockIdx.x;
-  if (!kind_uses_z_dev(J.kind) || k >= J.n) return;  // uniform per block
+__device__ void crpc_xw_body(const WitJob& J, uint32_t k, uint32_t* sh) {
   const uint32_t a = J.a, n = J.n, b = J.b;
   Fr sx = Fr::zero(), sw = Fr::zero();
   for (uint32_t i = threadIdx.x; i < a; i += RED_THREADS)
@@ -511,35 +456,17 @@ __global__ void __launch_bounds__(RED_THREADS) k_crpc_xw(WitTable T) {
   }
 }
 
-constexpr int YZ_BLOCKS = 64;
-
-// Partial sums of Y(z) = sum_ij z^(i b + j) y_ij, one per block (YZ_BLOCKS blocks per proof).
-__global__ void __launch_bounds__(RED_THREADS) k_crpc_yz(WitTable T) {
-  __shared__ uint32_t sh[RED_THREADS * NL];
-  const WitJob& J = T.get(blockIdx.y);
-  if (!kind_uses_z_dev(J.kind)) return;  // uniform per block
-  const uint32_t ab = J.a * J.b;
-  Fr s = Fr::zero();
-  for (uint32_t e = blockIdx.x * RED_THREADS + threadIdx.x; e < ab; e += gridDim.x * RED_THREADS)
-    s = Fr::add(s, Fr::mul(Fr::load(J.zpow + 8ull * e), fr_of_int(J.Y[e])));
-  s = block_sum(s, sh);
-  if (threadIdx.x == 0) s.store(J.yz + 8ull * blockIdx.x);
-}
-
 // Rows 0 .. m-1 and auxiliary variables of the CRPC kinds, one block per
 // proof: the prefix sums s_k = sum_{k' <= k} P_k' come from a block-wide
 // inclusive scan over chunks of RED_THREADS rows with a running carry.
-__global__ void __launch_bounds__(RED_THREADS) k_crpc_rows(WitTable T) {
-  __shared__ uint32_t sh[RED_THREADS * NL];
-  __shared__ uint32_t carry_sh[NL];
-  const WitJob& J = T.get(blockIdx.x);
-  if (!kind_uses_z_dev(J.kind)) return;  // uniform per block
+__device__ void crpc_rows_body(const WitJob& J, uint32_t* sh, uint32_t* carry_sh) {
   const uint32_t kind = J.kind, n = J.n;
   const uint64_t aux_start = J.aux_start;
   const uint32_t *xk = J.xk, *wk = J.wk, *pk = J.pkk;
   uint32_t *assign = J.assign, *aev = J.aev, *bev = J.bev, *cev = J.cev;
-  // Y(z) from the per-block partial sums
-  Fr yz = threadIdx.x < YZ_BLOCKS ? Fr::load(J.yz + 8ull * threadIdx.x) : Fr::zero();
+  // Y(z) from the partial sums
+  Fr yz = Fr::zero();
+  for (uint32_t q = threadIdx.x; q < J.nyz; q += RED_THREADS) yz = Fr::add(yz, Fr::load(J.yz + 8ull * q));
   yz = block_sum(yz, sh);
   if (threadIdx.x == 0) {
 #pragma unroll
@@ -599,6 +526,80 @@ __global__ void __launch_bounds__(RED_THREADS) k_crpc_rows(WitTable T) {
   }
 }
 
+// ---- the witness in two launches (a proving batch, or one proof)
+// First: blocks below xw_blocks sum a CRPC proof's row k (crpc_xw_body); the others
+// compute Y = X W, 256 entries of a row each, and (CRPC kinds) one partial
+// sum of Y(z) = sum_ij z^(i b + j) y_ij per block into yz.
+__global__ void __launch_bounds__(RED_THREADS) k_wit_first(WitTable T, uint32_t xw_blocks, uint32_t mm_bx) {
+  __shared__ uint32_t sh[RED_THREADS * NL];
+  const WitJob& J = T.get(blockIdx.y);
+  if (blockIdx.x < xw_blocks) {
+    if (!kind_uses_z_dev(J.kind) || blockIdx.x >= J.n) return;  // uniform per block
+    crpc_xw_body(J, blockIdx.x, sh);
+    return;
+  }
+  const uint32_t mm = blockIdx.x - xw_blocks;
+  const uint32_t i = mm / mm_bx, j = (mm % mm_bx) * RED_THREADS + threadIdx.x;
+  const uint32_t n = J.n, b = J.b;
+  const bool in = i < J.a && j < b;
+  int32_t y = 0;
+  if (in) {
+    const int8_t* x = J.X + (size_t)i * n;
+    const int8_t* W = J.W;
+    int32_t acc0 = 0, acc1 = 0;
+    uint32_t k = 0;
+    for (; k + 8 <= n; k += 8) {
+#pragma unroll
+      for (int q = 0; q < 8; q += 2) {
+        acc0 += (int32_t)x[k + q] * (int32_t)W[(size_t)(k + q) * b + j];
+        acc1 += (int32_t)x[k + q + 1] * (int32_t)W[(size_t)(k + q + 1) * b + j];
+      }
+    }
+    for (; k < n; k++) acc0 += (int32_t)x[k] * (int32_t)W[(size_t)k * b + j];
+    y = acc0 + acc1;
+    J.Y[(size_t)i * b + j] = y;
+  }
+  if (!kind_uses_z_dev(J.kind)) return;  // uniform per block
+  Fr s = in ? Fr::mul(Fr::load(J.zpow + 8ull * ((uint64_t)i * b + j)), fr_of_int(y)) : Fr::zero();
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) s.store(J.yz + 8ull * mm);
+}
+
+// Second: block 0 forms a CRPC proof's rows (crpc_rows_body); the others write the
+// public assignment (constant, x, y, w) and the rows from m on: rows m .. m
+// + l take the public variable t = row - m in A, every later row is zero,
+// and B, C are zero there (each value computed here, not read back).
+__global__ void __launch_bounds__(RED_THREADS) k_wit_second(WitTable T) {
+  __shared__ uint32_t sh[RED_THREADS * NL];
+  __shared__ uint32_t carry_sh[NL];
+  const WitJob& J = T.get(blockIdx.y);
+  if (blockIdx.x == 0) {
+    if (kind_uses_z_dev(J.kind)) crpc_rows_body(J, sh, carry_sh);  // uniform per block
+    return;
+  }
+  const uint64_t e = (uint64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x;
+  const uint64_t an = (uint64_t)J.a * J.n, ab = (uint64_t)J.a * J.b, nb = (uint64_t)J.n * J.b;
+  auto value = [&](uint64_t i) -> int64_t {
+    if (i == 0) return 1;
+    if (i <= an) return J.X[i - 1];
+    if (i <= an + ab) return J.Y[i - 1 - an];
+    return J.W[i - 1 - an - ab];
+  };
+  if (e < 1 + an + ab + nb) store_int(J.assign + 8ull * e, value(e));
+  const uint64_t c = J.m + e;
+  if (c < J.N) {
+    if (e <= J.ell)
+      store_int(J.aev + 8ull * c, value(e));
+    else
+      store_int(J.aev + 8ull * c, 0);
+    const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
+    reinterpret_cast<uint4*>(J.bev + 8ull * c)[0] = z4;
+    reinterpret_cast<uint4*>(J.bev + 8ull * c)[1] = z4;
+    reinterpret_cast<uint4*>(J.cev + 8ull * c)[0] = z4;
+    reinterpret_cast<uint4*>(J.cev + 8ull * c)[1] = z4;
+  }
+}
+
 // The witness kernels for one proof outside a proving batch: Y, the
 // assignment and the first `rows` rows of the evaluation vectors (rows <= m
 // leaves out the input-consistency rows).  The CRPC kinds' per-k sums use
@@ -628,24 +629,17 @@ void enqueue_witness_one(const Layout& L, const uint32_t* zpow, uint64_t rows, c
   J.xk = crpc ? ws.get(230, (size_t)L.n * 32) : nullptr;
   J.wk = crpc ? ws.get(231, (size_t)L.n * 32) : nullptr;
   J.pkk = crpc ? ws.get(232, (size_t)L.n * 32) : nullptr;
-  J.yz = crpc ? ws.get(233, 32 * YZ_BLOCKS) : nullptr;
-  hipLaunchKernelGGL(k_matmul, dim3(cdiv(L.b, 256), L.a, 1), dim3(256), 0, st, T);
+  const uint32_t mm_bx = cdiv(L.b, RED_THREADS), mm_blocks = mm_bx * L.a;
+  J.yz = crpc ? ws.get(233, 32ull * mm_blocks) : nullptr;
+  J.nyz = mm_blocks;
+  const uint32_t xw_blocks = crpc ? L.n : 0u;
+  hipLaunchKernelGGL(k_wit_first, dim3(xw_blocks + mm_blocks, 1), dim3(RED_THREADS), 0, st, T, xw_blocks, mm_bx);
   ZK_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_assign_public, dim3(cdiv(L.aux_start, 256), 1), dim3(256), 0, st, T);
+  const uint64_t wide = std::max<uint64_t>(L.aux_start, rows > L.m ? rows - L.m : 0);
+  hipLaunchKernelGGL(k_wit_second, dim3(1 + (unsigned)cdiv(wide, RED_THREADS), 1), dim3(RED_THREADS), 0, st, T);
   ZK_HIP(hipGetLastError());
-  if (crpc) {
-    hipLaunchKernelGGL(k_crpc_xw, dim3(L.n, 1), dim3(RED_THREADS), 0, st, T);
-    ZK_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_crpc_yz, dim3(YZ_BLOCKS, 1), dim3(RED_THREADS), 0, st, T);
-    ZK_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_crpc_rows, dim3(1), dim3(RED_THREADS), 0, st, T);
-    ZK_HIP(hipGetLastError());
-  } else {
+  if (!crpc) {
     hipLaunchKernelGGL(k_rows_plain, dim3(cdiv(L.m, 256), 1), dim3(256), 0, st, T);
-    ZK_HIP(hipGetLastError());
-  }
-  if (rows > L.m) {
-    hipLaunchKernelGGL(k_rows_tail, dim3(cdiv(rows - L.m, 256), 1), dim3(256), 0, st, T);
     ZK_HIP(hipGetLastError());
   }
 }
@@ -1091,7 +1085,7 @@ std::vector<Slot> enqueue_witness_batch(const ProveJob* jobs, size_t nj, ProveGe
       J.wk = ws.get(P_WK, (size_t)L.n * 32);
       S.wk = J.wk;
       J.pkk = ws.get(P_PK, (size_t)L.n * 32);
-      J.yz = ws.get(P_YZ, 32 * YZ_BLOCKS);
+      J.yz = nullptr;  // sized below, by the batch's tiling of Y
       any_crpc = true;
       max_n_crpc = std::max(max_n_crpc, L.n);
     } else {
@@ -1106,6 +1100,14 @@ std::vector<Slot> enqueue_witness_batch(const ProveJob* jobs, size_t nj, ProveGe
     max_tail = std::max<uint64_t>(max_tail, L.N - L.m);
   }
   if (xw_bytes) ZK_HIP(hipMemcpyAsync(xw_dev, xw_host, xw_bytes, hipMemcpyHostToDevice, st));
+  // Y is computed RED_THREADS entries of a row per block, and each block of a
+  // CRPC proof leaves one partial sum of Y(z)
+  const uint32_t mm_bx = cdiv(max_b, RED_THREADS), mm_blocks = mm_bx * max_a;
+  for (size_t j = 0; j < nj; j++) {
+    if (!kind_uses_z(jobs[j].pk->L.kind)) continue;
+    wj[j].yz = G.slot_ws[j]->get(P_YZ, 32ull * mm_blocks);
+    wj[j].nyz = mm_blocks;
+  }
   WitTable T{};
   if (nj == 1) {
     T.one = wj[0];
@@ -1122,27 +1124,19 @@ std::vector<Slot> enqueue_witness_batch(const ProveJob* jobs, size_t nj, ProveGe
   // holds the constant, written with the public assignment), so it starts here
   bool rows_only = true;
   for (size_t j = 0; j < nj; j++) rows_only = rows_only && jobs[j].pk->L.kind == ZKVC_CRPC_PSQ;
-  if (any_crpc) {
-    hipLaunchKernelGGL(k_crpc_xw, dim3(max_n_crpc, J), dim3(RED_THREADS), 0, st, T);
-    ZK_HIP(hipGetLastError());
-  }
+  // the CRPC per-row sums and Y in one launch, then the CRPC rows and the
+  // public assignment and tail rows in another
+  const uint32_t xw_blocks = any_crpc ? max_n_crpc : 0u;
+  hipLaunchKernelGGL(k_wit_first, dim3(xw_blocks + mm_blocks, J), dim3(RED_THREADS), 0, st, T, xw_blocks, mm_bx);
+  ZK_HIP(hipGetLastError());
   if (rows_only) ZK_HIP(hipEventRecord(G.wrow_ev, st));
-  hipLaunchKernelGGL(k_matmul, dim3(cdiv(max_b, 256), max_a, J), dim3(256), 0, st, T);
+  const uint64_t wide = std::max<uint64_t>(max_pub, max_tail);
+  hipLaunchKernelGGL(k_wit_second, dim3(1 + (unsigned)cdiv(wide, RED_THREADS), J), dim3(RED_THREADS), 0, st, T);
   ZK_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_assign_public, dim3(cdiv(max_pub, 256), J), dim3(256), 0, st, T);
-  ZK_HIP(hipGetLastError());
-  if (any_crpc) {
-    hipLaunchKernelGGL(k_crpc_yz, dim3(YZ_BLOCKS, J), dim3(RED_THREADS), 0, st, T);
-    ZK_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_crpc_rows, dim3(J), dim3(RED_THREADS), 0, st, T);
-    ZK_HIP(hipGetLastError());
-  }
   if (any_plain) {
     hipLaunchKernelGGL(k_rows_plain, dim3(cdiv(max_m_plain, 256), J), dim3(256), 0, st, T);
     ZK_HIP(hipGetLastError());
   }
-  hipLaunchKernelGGL(k_rows_tail, dim3(cdiv(max_tail, 256), J), dim3(256), 0, st, T);
-  ZK_HIP(hipGetLastError());
   if (!rows_only) ZK_HIP(hipEventRecord(G.wrow_ev, st));
   // Y of host-buffer jobs goes back after the quotients (off the path to the H lane)
   ycopy->dst = y_host;
