@@ -292,6 +292,20 @@ struct Fp {
     }
     return out;
   }
+  // a - b + 2m in (0, 4m) for a, b in [0, 2m), with no conditional step: an
+  // operand of mul_lz, whose result stays below 2m for one operand below 4m
+  // and the other below 2m (4m * 2m / 2^261 < m / 16).
+  static ZK_DEV Fp sub_nr(const Fp& a, const Fp& b) {
+    Fp out;
+    int32_t borrow = 0;
+#pragma unroll
+    for (int k = 0; k < NL; k++) {
+      const int32_t t = (int32_t)a.v[k] + (int32_t)M::P2[k] - (int32_t)b.v[k] + borrow;
+      out.v[k] = (uint32_t)t & LMASK;
+      borrow = t >> LB;
+    }
+    return out;  // the final borrow is 0: the value is positive
+  }
   static ZK_DEV Fp canon(const Fp& a) { return reduce_once(a.v); }
 
   // lazy products through the out-of-line functions

@@ -16,6 +16,12 @@
 // Memory: elements are 32 bytes (8 words).  A workgroup stages 1024 elements
 // (its groups, chosen so that global loads and stores come in runs of
 // consecutive addresses) in LDS as 29-bit limbs, 36 bytes each.
+//
+// Values inside a transform are lazy: any representative in [0, 2m) of the
+// residue (sums and differences fold back below 2m with one conditional
+// step, products skip their final subtraction, and a DIF difference that
+// meets a twiddle goes into the product as a - b + 2m unreduced).  The last
+// pass of a transform stores canonical values.
 #include "ntt.hpp"
 
 #include <algorithm>
@@ -81,18 +87,18 @@ __device__ __forceinline__ void lds_stages(uint32_t* lds, int k, uint32_t E, int
       const uint32_t t0 = ((j >> s) << (s + 1)) | (j & smask);
       const uint32_t t1 = t0 | (1u << s);
       const uint32_t widx = (j & smask) << (k - 1 - s);
+      // lazy values in [0, 2m) (see the header)
       Fr a = lds_get(lds, gl * K + t0);
       Fr b = lds_get(lds, gl * K + t1);
       if (dit) {
-        if (widx) b = Fr::mul(b, Fr::load(local + 8u * widx));
-        const Fr u = Fr::add(a, b);
-        const Fr v = Fr::sub(a, b);
+        if (widx) b = Fr::mul_lz(b, Fr::load(local + 8u * widx));
+        const Fr u = Fr::add_lz(a, b);
+        const Fr v = Fr::sub_lz(a, b);
         a = u;
         b = v;
       } else {
-        const Fr u = Fr::add(a, b);
-        Fr v = Fr::sub(a, b);
-        if (widx) v = Fr::mul(v, Fr::load(local + 8u * widx));
+        const Fr u = Fr::add_lz(a, b);
+        const Fr v = widx ? Fr::mul_lz(Fr::sub_nr(a, b), Fr::load(local + 8u * widx)) : Fr::sub_lz(a, b);
         a = u;
         b = v;
       }
@@ -168,7 +174,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_pass(PassParams p, NttTable
     }
     if (p.dit && p.twiddle) {
       const uint32_t ex = g * bitrev_bits(t, k);
-      if (ex) x = Fr::mul(x, p.tw ? Fr::load(p.tw + 8u * ((t << B) | g)) : pow_lookup(T.w[p.inverse], ex << tw_shift));
+      if (ex) x = Fr::mul_lz(x, p.tw ? Fr::load(p.tw + 8u * ((t << B) | g)) : pow_lookup(T.w[p.inverse], ex << tw_shift));
     }
     lds_put(lds, gl * K + t, x);
   }
@@ -193,7 +199,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_pass(PassParams p, NttTable
     Fr x = lds_get(lds, gl * K + t);
     if (!p.dit && p.twiddle) {
       const uint32_t ex = g * bitrev_bits(t, k);
-      if (ex) x = Fr::mul(x, p.tw ? Fr::load(p.tw + 8u * ((t << B) | g)) : pow_lookup(T.w[p.inverse], ex << tw_shift));
+      if (ex) x = Fr::mul_lz(x, p.tw ? Fr::load(p.tw + 8u * ((t << B) | g)) : pow_lookup(T.w[p.inverse], ex << tw_shift));
     }
     if (p.last && p.post_table) {
       x = Fr::mul(x, Fr::load(p.post_table + 8ull * addr));
@@ -206,6 +212,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_pass(PassParams p, NttTable
       if (p.post_const) x = Fr::mul(x, Fr::load(p.post_const));
       if (p.post_canon) x = Fr::from_mont(x);
     }
+    if (p.last) x = Fr::canon(x);  // a lazy value leaves the transform canonical
     x.store(data + 8ull * addr);
   }
 }
@@ -246,8 +253,8 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fused_bottom(FusedParams p,
     const uint32_t addr = pass_addr(e, k, p.log_g, 0, k, gamma0, &gl, &t, &g);
     const uint32_t slot = gl * (1u << k) + t;
     // coefficient bitrev(addr) of the inverse transform times g^i / N
-    const Fr x = p.coset ? Fr::mul(lds_get(lds, slot), Fr::load(p.coset + 8ull * addr))
-                         : Fr::mul(Fr::mul(lds_get(lds, slot), pow_lookup(T.g[0], bitrev_bits(addr, p.log_n))), ninv);
+    const Fr x = p.coset ? Fr::mul_lz(lds_get(lds, slot), Fr::load(p.coset + 8ull * addr))
+                         : Fr::mul_lz(Fr::mul_lz(lds_get(lds, slot), pow_lookup(T.g[0], bitrev_bits(addr, p.log_n))), ninv);
     lds_put(lds, slot, x);
   }
   __syncthreads();
@@ -277,7 +284,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fused_top(FusedParams p, Nt
     const uint32_t addr = pass_addr(el, k, p.log_g, B, L, gamma0, &gl, &t, &g);
     Fr x = Fr::load(vec[v] + 8ull * addr);
     const uint32_t ex = g * bitrev_bits(t, k);  // forward DIT twiddle first
-    if (ex) x = Fr::mul(x, p.tw[0] ? Fr::load(p.tw[0] + 8u * ((t << B) | g)) : pow_lookup(T.w[0], ex << tw_shift));
+    if (ex) x = Fr::mul_lz(x, p.tw[0] ? Fr::load(p.tw[0] + 8u * ((t << B) | g)) : pow_lookup(T.w[0], ex << tw_shift));
     lds_put(lds, v * E + gl * K + t, x);
   }
   __syncthreads();
@@ -285,7 +292,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fused_top(FusedParams p, Nt
   const Fr zinv = Fr::load(p.zinv);
   for (uint32_t e = threadIdx.x; e < E; e += blockDim.x) {
     const Fr a = lds_get(lds, e), b = lds_get(lds, E + e), c = lds_get(lds, 2 * E + e);
-    lds_put(lds, e, Fr::mul(Fr::sub(Fr::mul(a, b), c), zinv));
+    lds_put(lds, e, Fr::mul_lz(Fr::sub_nr(Fr::mul_lz(a, b), c), zinv));
   }
   __syncthreads();
   lds_stages(lds, k, E, 1, false, T.local[1]);  // inverse DIF, first pass
@@ -293,7 +300,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fused_top(FusedParams p, Nt
     const uint32_t addr = pass_addr(e, k, p.log_g, B, L, gamma0, &gl, &t, &g);
     Fr x = lds_get(lds, gl * K + t);
     const uint32_t ex = g * bitrev_bits(t, k);  // inverse DIF twiddle last
-    if (ex) x = Fr::mul(x, p.tw[1] ? Fr::load(p.tw[1] + 8u * ((t << B) | g)) : pow_lookup(T.w[1], ex << tw_shift));
+    if (ex) x = Fr::mul_lz(x, p.tw[1] ? Fr::load(p.tw[1] + 8u * ((t << B) | g)) : pow_lookup(T.w[1], ex << tw_shift));
     x.store(vec[0] + 8ull * addr);
   }
 }
