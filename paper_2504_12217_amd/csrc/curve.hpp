@@ -11,6 +11,16 @@
 // kernels inside the instruction cache).  Equality tests use the canonical
 // representative; coordinates leave for the host through canonical stores.
 //
+// Infinity is exactly ZZ = 0 (every limb zero): inf() and the canonical
+// stores write it that way, and no other value of ZZ is a multiple of m (ZZ
+// of a sum is a product of nonzero factors; the exceptional cases of the
+// formulas return inf() explicitly, and there are no points of order 2 to
+// double), so is_inf needs no canonical reduction.
+//
+// Over Fq, differences whose only uses are products and a zero test
+// (F::csub_p) skip the conditional step and lie in (0, 4m): the lazy product
+// of operands below 4m is below m + 16m^2/2^261 < 2m.
+//
 // Affine points in memory are stored x then y (each coordinate 8 x 32-bit
 // words in the device Montgomery form); the pair (0, 0) encodes infinity.
 #pragma once
@@ -28,11 +38,12 @@ struct Xyzz {
   F X, Y, ZZ, ZZZ;
 
   static ZK_DEV Xyzz inf() { return {F::one(), F::one(), F::zero(), F::zero()}; }
-  static ZK_DEV bool is_inf(const Xyzz& p) { return F::cis_zero(p.ZZ); }
+  static ZK_DEV bool is_inf(const Xyzz& p) { return F::is_zero(p.ZZ); }
   static ZK_DEV Xyzz from_affine(const Affine<F>& q) { return {q.x, q.y, F::one(), F::one()}; }
 
   // 2 * (x, y) for an affine input (mdbl-2008-s-1 with ZZ = ZZZ = 1)
   static ZK_DEV Xyzz dbl_affine(const Affine<F>& q) {
+    if (F::cis_zero(q.y)) return inf();
     const F U = F::cdbl(q.y);
     const F V = F::csqr(U);
     const F W = F::cmul(U, V);
@@ -46,6 +57,7 @@ struct Xyzz {
 
   // 2P (dbl-2008-s-1)
   static ZK_DEV Xyzz dbl(const Xyzz& p) {
+    if (is_inf(p) || F::cis_zero(p.Y)) return inf();
     const F U = F::cdbl(p.Y);
     const F V = F::csqr(U);
     const F W = F::cmul(U, V);
@@ -62,17 +74,17 @@ struct Xyzz {
     if (is_inf(p)) return from_affine(q);
     const F U2 = F::cmul(q.x, p.ZZ);
     const F S2 = F::cmul(q.y, p.ZZZ);
-    const F P = F::csub(U2, p.X);
-    const F R = F::csub(S2, p.Y);
-    if (F::cis_zero(P)) {
-      if (F::cis_zero(R)) return dbl_affine(q);
+    const F P = F::csub_p(U2, p.X);
+    const F R = F::csub_p(S2, p.Y);
+    if (F::cis_zero_p(P)) {
+      if (F::cis_zero_p(R)) return dbl_affine(q);
       return inf();
     }
     const F PP = F::csqr(P);
     const F PPP = F::cmul(P, PP);
     const F Q = F::cmul(p.X, PP);
     const F X3 = F::csub(F::csub(F::csqr(R), PPP), F::cdbl(Q));
-    const F Y3 = F::csub(F::cmul(R, F::csub(Q, X3)), F::cmul(p.Y, PPP));
+    const F Y3 = F::csub(F::cmul(R, F::csub_p(Q, X3)), F::cmul(p.Y, PPP));
     return {X3, Y3, F::cmul(p.ZZ, PP), F::cmul(p.ZZZ, PPP)};
   }
 
@@ -84,17 +96,17 @@ struct Xyzz {
     const F U2 = F::cmul(q.X, p.ZZ);
     const F S1 = F::cmul(p.Y, q.ZZZ);
     const F S2 = F::cmul(q.Y, p.ZZZ);
-    const F P = F::csub(U2, U1);
-    const F R = F::csub(S2, S1);
-    if (F::cis_zero(P)) {
-      if (F::cis_zero(R)) return dbl(p);
+    const F P = F::csub_p(U2, U1);
+    const F R = F::csub_p(S2, S1);
+    if (F::cis_zero_p(P)) {
+      if (F::cis_zero_p(R)) return dbl(p);
       return inf();
     }
     const F PP = F::csqr(P);
     const F PPP = F::cmul(P, PP);
     const F Q = F::cmul(U1, PP);
     const F X3 = F::csub(F::csub(F::csqr(R), PPP), F::cdbl(Q));
-    const F Y3 = F::csub(F::cmul(R, F::csub(Q, X3)), F::cmul(S1, PPP));
+    const F Y3 = F::csub(F::cmul(R, F::csub_p(Q, X3)), F::cmul(S1, PPP));
     return {X3, Y3, F::cmul(F::cmul(p.ZZ, q.ZZ), PP), F::cmul(F::cmul(p.ZZZ, q.ZZZ), PPP)};
   }
 
@@ -165,9 +177,9 @@ struct QuadOps {
     if (P::is_inf(q)) return p;
     F r = F::cmul(sel4(t, p.X, q.X, p.Y, q.Y), sel4(t, q.ZZ, p.ZZ, q.ZZZ, p.ZZZ));
     const F U1 = quad_bcast<0>(r), U2 = quad_bcast<1>(r), S1 = quad_bcast<2>(r), S2 = quad_bcast<3>(r);
-    const F Pd = F::csub(U2, U1), R = F::csub(S2, S1);
-    if (F::cis_zero(Pd)) {
-      if (F::cis_zero(R)) return P::dbl(p);
+    const F Pd = F::csub_p(U2, U1), R = F::csub_p(S2, S1);
+    if (F::cis_zero_p(Pd)) {
+      if (F::cis_zero_p(R)) return P::dbl(p);
       return P::inf();
     }
     r = F::cmul(sel4(t, Pd, R, p.ZZ, p.ZZZ), sel4(t, Pd, R, q.ZZ, q.ZZZ));
@@ -175,7 +187,7 @@ struct QuadOps {
     r = F::cmul(sel4(t, Pd, U1, ZZ12, ZZ12), PP);
     const F PPP = quad_bcast<0>(r), Q = quad_bcast<1>(r), ZZ3 = quad_bcast<2>(r);
     const F X3 = F::csub(F::csub(RR, PPP), F::cdbl(Q));
-    r = F::cmul(sel4(t, R, S1, ZZZ12, ZZZ12), F::select(t == 0u, F::csub(Q, X3), PPP));
+    r = F::cmul(sel4(t, R, S1, ZZZ12, ZZZ12), F::select(t == 0u, F::csub_p(Q, X3), PPP));
     const F T1 = quad_bcast<0>(r), T2 = quad_bcast<1>(r), ZZZ3 = quad_bcast<2>(r);
     return {X3, F::csub(T1, T2), ZZ3, ZZZ3};
   }
@@ -185,9 +197,9 @@ struct QuadOps {
     const bool odd = t & 1u;
     F r = F::cmul(F::select(odd, q.y, q.x), F::select(odd, p.ZZZ, p.ZZ));
     const F U2 = quad_bcast<0>(r), S2 = quad_bcast<1>(r);
-    const F Pd = F::csub(U2, p.X), R = F::csub(S2, p.Y);
-    if (F::cis_zero(Pd)) {
-      if (F::cis_zero(R)) return P::dbl_affine(q);
+    const F Pd = F::csub_p(U2, p.X), R = F::csub_p(S2, p.Y);
+    if (F::cis_zero_p(Pd)) {
+      if (F::cis_zero_p(R)) return P::dbl_affine(q);
       return P::inf();
     }
     const F PR = F::select(odd, R, Pd);
@@ -196,7 +208,7 @@ struct QuadOps {
     r = F::cmul(sel4(t, Pd, p.X, p.ZZ, p.ZZ), PP);
     const F PPP = quad_bcast<0>(r), Q = quad_bcast<1>(r), ZZ3 = quad_bcast<2>(r);
     const F X3 = F::csub(F::csub(RR, PPP), F::cdbl(Q));
-    r = F::cmul(sel4(t, R, p.Y, p.ZZZ, p.ZZZ), F::select(t == 0u, F::csub(Q, X3), PPP));
+    r = F::cmul(sel4(t, R, p.Y, p.ZZZ, p.ZZZ), F::select(t == 0u, F::csub_p(Q, X3), PPP));
     const F T1 = quad_bcast<0>(r), T2 = quad_bcast<1>(r), ZZZ3 = quad_bcast<2>(r);
     return {X3, F::csub(T1, T2), ZZ3, ZZZ3};
   }

@@ -307,6 +307,17 @@ struct Fp {
     return out;  // the final borrow is 0: the value is positive
   }
   static ZK_DEV Fp canon(const Fp& a) { return reduce_once(a.v); }
+  // x = 0 (mod m) for x in [0, 4m) as sub_nr returns it.  x is then k*m with
+  // k < 4, whose low limb takes one of four values: that screens out all but
+  // about 2^-27 of the nonzero inputs before the exact test, which sits in a
+  // branch of its own.
+  static ZK_DEV bool is_zero_4m(const Fp& x) {
+    const uint32_t l = x.v[0];
+    // branch-free (compares of one value against constants become a search tree)
+    const uint32_t t = min(min(l, l ^ M::P[0]), min(l ^ M::P2[0], l ^ ((M::P[0] + M::P2[0]) & LMASK)));
+    if (t != 0u) return false;
+    return is_zero(canon(reduce_2m(x.v)));
+  }
 
   // lazy products through the out-of-line functions
   static ZK_DEV Fp mul_oop(const Fp& a, const Fp& b) {
@@ -324,6 +335,10 @@ struct Fp {
   static ZK_DEV Fp cdbl(const Fp& a) { return add_lz(a, a); }
   static ZK_DEV Fp cneg(const Fp& a) { return sub_lz(zero(), a); }
   static ZK_DEV bool cis_zero(const Fp& a) { return is_zero(canon(a)); }
+  // a difference whose only uses are products (and the zero test below):
+  // a - b + 2m in (0, 4m), which the lazy product accepts (see sub_nr)
+  static ZK_DEV Fp csub_p(const Fp& a, const Fp& b) { return sub_nr(a, b); }
+  static ZK_DEV bool cis_zero_p(const Fp& a) { return is_zero_4m(a); }
 
   static ZK_DEV bool is_zero(const Fp& a) {
     uint32_t t = 0;
@@ -430,6 +445,10 @@ struct Fq2 {
   static ZK_DEV Fq2 cdbl(const Fq2& a) { return cadd(a, a); }
   static ZK_DEV Fq2 cneg(const Fq2& a) { return csub(zero(), a); }
   static ZK_DEV bool cis_zero(const Fq2& a) { return Fq::cis_zero(a.c0) && Fq::cis_zero(a.c1); }
+  // differences feeding products keep the [0, 2m) range here: cmul and csqr
+  // add and subtract their operands' components before multiplying
+  static ZK_DEV Fq2 csub_p(const Fq2& a, const Fq2& b) { return csub(a, b); }
+  static ZK_DEV bool cis_zero_p(const Fq2& a) { return cis_zero(a); }
   static ZK_DEV Fq2 canon(const Fq2& a) { return {Fq::canon(a.c0), Fq::canon(a.c1)}; }
   static ZK_DEV bool is_zero(const Fq2& a) { return Fq::is_zero(a.c0) && Fq::is_zero(a.c1); }
   static ZK_DEV bool eq(const Fq2& a, const Fq2& b) { return Fq::eq(a.c0, b.c0) && Fq::eq(a.c1, b.c1); }

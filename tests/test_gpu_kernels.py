@@ -261,6 +261,32 @@ def test_msm_g2_small_and_dlog(zk):
     assert got == bn.g2_mul(q, sum(a * b for a, b in zip(k_int, vals)) % bn.R)
 
 
+@pytest.mark.parametrize("small", [False, True])
+def test_msm_few_distinct_bases(zk, small):
+    """Bases cycling over three multiples of G: the buckets, their partial sums
+    and the reduction meet equal and opposite points (the doubling and
+    cancellation branches of every addition, and sums that pass through
+    infinity); checked by the discrete-log identity.  Small signed scalars
+    put everything in one window of few, crowded buckets (the quad paths)."""
+    rng = random.Random(77 + small)
+    n = (1 << 14) + 5
+    kk = [rng.randrange(1, bn.R) for _ in range(3)]
+    ks = [kk[i % 3] for i in range(n)]
+    if small:
+        sc = [rng.randrange(-300, 301) for _ in range(n)]
+    else:
+        sc = [rng.randrange(bn.R) for _ in range(n)]
+    dpts = torch.zeros((n * 16,), dtype=torch.int32, device="cuda")
+    zk.fixed_base_g1(ints_to_dev(ks), n, dpts)
+    got = zk.msm_g1(dpts, ints_to_dev([v % bn.R for v in sc]), n)
+    assert got == bn.g1_mul(bn.G1_GEN, sum(a * b for a, b in zip(ks, sc)) % bn.R)
+    m = 3000
+    dq = torch.zeros((m * 32,), dtype=torch.int32, device="cuda")
+    zk.fixed_base_g2(ints_to_dev(ks[:m]), m, dq)
+    got2 = zk.msm_g2(dq, ints_to_dev([v % bn.R for v in sc[:m]]), m)
+    assert got2 == bn.g2_mul(bn.G2_GEN, sum(a * b for a, b in zip(ks[:m], sc[:m])) % bn.R)
+
+
 def test_msm_rejects_bad_arguments(zk):
     """Rejections decided before any device memory is touched."""
     d = dev_words(np.zeros((4, 16), dtype=np.uint32))
