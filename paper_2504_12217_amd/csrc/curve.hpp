@@ -83,7 +83,7 @@ struct Xyzz {
     const F PP = F::csqr(P);
     const F PPP = F::cmul(P, PP);
     const F Q = F::cmul(p.X, PP);
-    const F X3 = F::csub(F::csub(F::csqr(R), PPP), F::cdbl(Q));
+    const F X3 = F::csub3(F::csqr(R), PPP, Q);
     const F Y3 = F::csub(F::cmul(R, F::csub_p(Q, X3)), F::cmul(p.Y, PPP));
     return {X3, Y3, F::cmul(p.ZZ, PP), F::cmul(p.ZZZ, PPP)};
   }
@@ -105,7 +105,7 @@ struct Xyzz {
     const F PP = F::csqr(P);
     const F PPP = F::cmul(P, PP);
     const F Q = F::cmul(U1, PP);
-    const F X3 = F::csub(F::csub(F::csqr(R), PPP), F::cdbl(Q));
+    const F X3 = F::csub3(F::csqr(R), PPP, Q);
     const F Y3 = F::csub(F::cmul(R, F::csub_p(Q, X3)), F::cmul(S1, PPP));
     return {X3, Y3, F::cmul(F::cmul(p.ZZ, q.ZZ), PP), F::cmul(F::cmul(p.ZZZ, q.ZZZ), PPP)};
   }
@@ -186,7 +186,7 @@ struct QuadOps {
     const F PP = quad_bcast<0>(r), RR = quad_bcast<1>(r), ZZ12 = quad_bcast<2>(r), ZZZ12 = quad_bcast<3>(r);
     r = F::cmul(sel4(t, Pd, U1, ZZ12, ZZ12), PP);
     const F PPP = quad_bcast<0>(r), Q = quad_bcast<1>(r), ZZ3 = quad_bcast<2>(r);
-    const F X3 = F::csub(F::csub(RR, PPP), F::cdbl(Q));
+    const F X3 = F::csub3(RR, PPP, Q);
     r = F::cmul(sel4(t, R, S1, ZZZ12, ZZZ12), F::select(t == 0u, F::csub_p(Q, X3), PPP));
     const F T1 = quad_bcast<0>(r), T2 = quad_bcast<1>(r), ZZZ3 = quad_bcast<2>(r);
     return {X3, F::csub(T1, T2), ZZ3, ZZZ3};
@@ -207,7 +207,7 @@ struct QuadOps {
     const F PP = quad_bcast<0>(r), RR = quad_bcast<1>(r);
     r = F::cmul(sel4(t, Pd, p.X, p.ZZ, p.ZZ), PP);
     const F PPP = quad_bcast<0>(r), Q = quad_bcast<1>(r), ZZ3 = quad_bcast<2>(r);
-    const F X3 = F::csub(F::csub(RR, PPP), F::cdbl(Q));
+    const F X3 = F::csub3(RR, PPP, Q);
     r = F::cmul(sel4(t, R, p.Y, p.ZZZ, p.ZZZ), F::select(t == 0u, F::csub_p(Q, X3), PPP));
     const F T1 = quad_bcast<0>(r), T2 = quad_bcast<1>(r), ZZZ3 = quad_bcast<2>(r);
     return {X3, F::csub(T1, T2), ZZ3, ZZZ3};

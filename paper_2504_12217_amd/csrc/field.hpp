@@ -307,6 +307,38 @@ struct Fp {
     return out;  // the final borrow is 0: the value is positive
   }
   static ZK_DEV Fp canon(const Fp& a) { return reduce_once(a.v); }
+  // a - b - 2c in [0, 2m) for a, b, c in [0, 2m): one pass forms
+  // a + 6m - b - 2c in (0, 8m), then 4m and 2m are subtracted where they fit
+  // (the x-coordinate of the addition formulas, in place of two lazy
+  // subtractions and a doubling, each with its own conditional step).
+  static ZK_DEV Fp sub3_lz(const Fp& a, const Fp& b, const Fp& c) {
+    uint32_t t[NL];
+    int32_t borrow = 0;
+#pragma unroll
+    for (int k = 0; k < NL; k++) {
+      const int32_t x = (int32_t)a.v[k] + (int32_t)M::P6[k] - (int32_t)b.v[k] - (int32_t)(c.v[k] << 1) + borrow;
+      t[k] = (uint32_t)x & LMASK;
+      borrow = x >> LB;
+    }
+    // the value is positive and below 8m < 2^257, so the top limb ends with no borrow
+    return cond_sub(cond_sub(t, M::P4).v, M::P2);
+  }
+  // r - s if that is not negative, else r
+  static ZK_DEV Fp cond_sub(const uint32_t r[NL], const uint32_t s[NL]) {
+    uint32_t d[NL];
+    int32_t borrow = 0;
+#pragma unroll
+    for (int k = 0; k < NL; k++) {
+      const int32_t x = (int32_t)r[k] - (int32_t)s[k] + borrow;
+      d[k] = (uint32_t)x & LMASK;
+      borrow = x >> LB;
+    }
+    Fp out;
+    const bool keep = borrow < 0;
+#pragma unroll
+    for (int k = 0; k < NL; k++) out.v[k] = keep ? r[k] : d[k];
+    return out;
+  }
   // x = 0 (mod m) for x in [0, 4m) as sub_nr returns it.  x is then k*m with
   // k < 4, whose low limb takes one of four values: that screens out all but
   // about 2^-27 of the nonzero inputs before the exact test, which sits in a
@@ -339,6 +371,7 @@ struct Fp {
   // a - b + 2m in (0, 4m), which the lazy product accepts (see sub_nr)
   static ZK_DEV Fp csub_p(const Fp& a, const Fp& b) { return sub_nr(a, b); }
   static ZK_DEV bool cis_zero_p(const Fp& a) { return is_zero_4m(a); }
+  static ZK_DEV Fp csub3(const Fp& a, const Fp& b, const Fp& c) { return sub3_lz(a, b, c); }
 
   static ZK_DEV bool is_zero(const Fp& a) {
     uint32_t t = 0;
@@ -448,6 +481,9 @@ struct Fq2 {
   // differences feeding products keep the [0, 2m) range here: cmul and csqr
   // add and subtract their operands' components before multiplying
   static ZK_DEV Fq2 csub_p(const Fq2& a, const Fq2& b) { return csub(a, b); }
+  static ZK_DEV Fq2 csub3(const Fq2& a, const Fq2& b, const Fq2& c) {
+    return {Fq::sub3_lz(a.c0, b.c0, c.c0), Fq::sub3_lz(a.c1, b.c1, c.c1)};
+  }
   static ZK_DEV bool cis_zero_p(const Fq2& a) { return cis_zero(a); }
   static ZK_DEV Fq2 canon(const Fq2& a) { return {Fq::canon(a.c0), Fq::canon(a.c1)}; }
   static ZK_DEV bool is_zero(const Fq2& a) { return Fq::is_zero(a.c0) && Fq::is_zero(a.c1); }
