@@ -158,6 +158,19 @@ struct Fp {
     return out;
   }
   static ZK_DEV Fp neg(const Fp& a) { return sub(zero(), a); }
+  // m - a for a in [0, m), e.g. a stored coordinate: a representative in
+  // (0, m] of -a with no conditional step (a lazy value for the group law)
+  static ZK_DEV Fp neg_canon_lz(const Fp& a) {
+    Fp out;
+    int32_t borrow = 0;
+#pragma unroll
+    for (int k = 0; k < NL; k++) {
+      const int32_t t = (int32_t)M::P[k] - (int32_t)a.v[k] + borrow;
+      out.v[k] = (uint32_t)t & LMASK;
+      borrow = t >> LB;
+    }
+    return out;
+  }
   static ZK_DEV Fp dbl(const Fp& a) { return add(a, a); }
 
   // Montgomery product a*b*2^-261 mod m (column-interleaved reduction).
@@ -450,6 +463,7 @@ struct Fq2 {
   static ZK_DEV Fq2 sub(const Fq2& a, const Fq2& b) { return {Fq::sub(a.c0, b.c0), Fq::sub(a.c1, b.c1)}; }
   static ZK_DEV Fq2 dbl(const Fq2& a) { return {Fq::dbl(a.c0), Fq::dbl(a.c1)}; }
   static ZK_DEV Fq2 neg(const Fq2& a) { return {Fq::neg(a.c0), Fq::neg(a.c1)}; }
+  static ZK_DEV Fq2 neg_canon_lz(const Fq2& a) { return {Fq::neg_canon_lz(a.c0), Fq::neg_canon_lz(a.c1)}; }
   // Karatsuba: 3 base multiplications
   static ZK_DEV Fq2 mul(const Fq2& a, const Fq2& b) {
     const Fq v0 = Fq::mul(a.c0, b.c0);

@@ -440,7 +440,7 @@ __global__ void __launch_bounds__(64) k_msm_acc(BatchDev B, const uint4* th_task
           ref = sorted[e + 1];
           pt = PointIO<F>::load_affine(points + (size_t)(ref & ~SIGN) * AW);
         }
-        if (cref & SIGN) cur.y = F::neg(cur.y);
+        if (cref & SIGN) cur.y = F::neg_canon_lz(cur.y);  // stored coordinates are canonical
         acc = Xyzz<F>::madd(acc, cur);
       }
       PointIO<F>::store_xyzz(partials + (size_t)task.z * XW, acc);
@@ -459,7 +459,7 @@ __global__ void __launch_bounds__(64) k_msm_acc(BatchDev B, const uint4* th_task
       for (uint32_t e = team; e < task.y; e += WG_THREADS / 4) {
         const uint32_t ref = sorted[task.x + e];
         Affine<F> pt = PointIO<F>::load_affine(points + (size_t)(ref & ~SIGN) * AW);
-        if (ref & SIGN) pt.y = F::neg(pt.y);
+        if (ref & SIGN) pt.y = F::neg_canon_lz(pt.y);
         acc = QuadOps<F>::madd(acc, pt, tq);
       }
       acc = quad_tree_sum<F>(acc, sh, WG_THREADS / 4);
@@ -467,7 +467,7 @@ __global__ void __launch_bounds__(64) k_msm_acc(BatchDev B, const uint4* th_task
       for (uint32_t e = threadIdx.x; e < task.y; e += WG_THREADS) {
         const uint32_t ref = sorted[task.x + e];
         Affine<F> pt = PointIO<F>::load_affine(points + (size_t)(ref & ~SIGN) * AW);
-        if (ref & SIGN) pt.y = F::neg(pt.y);
+        if (ref & SIGN) pt.y = F::neg_canon_lz(pt.y);
         acc = Xyzz<F>::madd(acc, pt);
       }
       for (int o = WG_THREADS / 2; o >= 1; o >>= 1) {

@@ -71,12 +71,22 @@ __device__ __forceinline__ Fr lds_get(const uint32_t* lds, uint32_t slot) {
   return x;
 }
 
+// Stage twiddles are stored as the nine 29-bit limbs the arithmetic uses
+// (12 words, 48 bytes: three 16-byte loads), so no unpacking per butterfly.
+constexpr uint32_t LOCAL_WORDS = 12;
+__device__ __forceinline__ Fr load_limbs(const uint32_t* p) {
+  const uint4 a = reinterpret_cast<const uint4*>(p)[0];
+  const uint4 b = reinterpret_cast<const uint4*>(p)[1];
+  const uint32_t c = p[8];
+  return Fr{{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c}};
+}
+
 // The k radix-2 stages of a pass on `nreg` consecutive LDS regions of E
 // elements (E / 2^k groups of 2^k each); every thread of the block must call.
 __device__ __forceinline__ void lds_stages(uint32_t* lds, int k, uint32_t E, int nreg, bool dit, const uint32_t* local_tab) {
   const uint32_t K = 1u << k;
   const uint32_t half = K >> 1;
-  const uint32_t* local = k > 0 ? local_tab + 8u * (half - 1u) : local_tab;
+  const uint32_t* local = k > 0 ? local_tab + LOCAL_WORDS * (half - 1u) : local_tab;
   const uint32_t nb = (E / 2) * (uint32_t)nreg;
   for (int st = 0; st < k; st++) {
     const int s = dit ? st : (k - 1 - st);
@@ -91,14 +101,14 @@ __device__ __forceinline__ void lds_stages(uint32_t* lds, int k, uint32_t E, int
       Fr a = lds_get(lds, gl * K + t0);
       Fr b = lds_get(lds, gl * K + t1);
       if (dit) {
-        if (widx) b = Fr::mul_lz(b, Fr::load(local + 8u * widx));
+        if (widx) b = Fr::mul_lz(b, load_limbs(local + LOCAL_WORDS * widx));
         const Fr u = Fr::add_lz(a, b);
         const Fr v = Fr::sub_lz(a, b);
         a = u;
         b = v;
       } else {
         const Fr u = Fr::add_lz(a, b);
-        const Fr v = widx ? Fr::mul_lz(Fr::sub_nr(a, b), Fr::load(local + 8u * widx)) : Fr::sub_lz(a, b);
+        const Fr v = widx ? Fr::mul_lz(Fr::sub_nr(a, b), load_limbs(local + LOCAL_WORDS * widx)) : Fr::sub_lz(a, b);
         a = u;
         b = v;
       }
@@ -383,17 +393,25 @@ DeviceTables* build_tables() {
   pow_table_host(wi, tabs[2], tabs[3]);
   pow_table_host(five, tabs[4], tabs[5]);
   pow_table_host(gi, tabs[6], tabs[7]);
-  // local tables: omega_{2^k}^j for k = 1..10, j < 2^(k-1), at offset 2^(k-1) - 1
+  // local tables: omega_{2^k}^j for k = 1..10, j < 2^(k-1), at entry 2^(k-1) - 1 + j,
+  // each as nine 29-bit limbs in 12 words
   std::vector<uint32_t> loc[2];
   for (int dir = 0; dir < 2; dir++) {
-    loc[dir].assign(8 * ((1 << NTT_MAX_K) - 1), 0);
+    loc[dir].assign(LOCAL_WORDS * ((1 << NTT_MAX_K) - 1), 0);
     for (int k = 1; k <= NTT_MAX_K; k++) {
       HFr wk = dir == 0 ? w : wi;
       for (int q = k; q < MAX_LOG; q++) wk = HFr::sqr(wk);  // omega_{2^k}
       HFr x = HFr::one();
       const int off = (1 << (k - 1)) - 1;
       for (int j = 0; j < (1 << (k - 1)); j++) {
-        x.to_dev(&loc[dir][8 * (off + j)]);
+        uint32_t w8[8];
+        x.to_dev(w8);
+        uint32_t* e = &loc[dir][LOCAL_WORDS * (off + j)];
+        for (int q = 0; q < NL; q++) {  // the same limbs as Fr::unpack
+          const int o = LB * q, i = o >> 5, sh = o & 31;
+          const uint64_t pair = ((uint64_t)(i + 1 < 8 ? w8[i + 1] : 0u) << 32) | w8[i];
+          e[q] = (uint32_t)(pair >> sh) & LMASK;
+        }
         x = HFr::mul(x, wk);
       }
     }

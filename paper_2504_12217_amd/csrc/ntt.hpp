@@ -22,7 +22,7 @@ struct PowTable {
 struct NttTables {
   PowTable w[2];      // powers of omega_{2^28} (index 0) and of its inverse (index 1)
   PowTable g[2];      // powers of the coset shift g = 5 and of g^-1
-  const uint32_t* local[2];  // omega_{2^k}^j for k = 1..10, j < 2^(k-1), at offset 2^(k-1) - 1
+  const uint32_t* local[2];  // omega_{2^k}^j for k = 1..10, j < 2^(k-1), at entry 2^(k-1) - 1 + j (12 words: 9 limbs)
   const uint32_t* ninv;      // 2^-L for L = 0..28 (8 words each)
   const uint32_t* coset_zinv; // (g^(2^L) - 1)^-1 for L = 0..28: 1/t on the coset g H
 };
