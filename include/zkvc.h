@@ -293,7 +293,13 @@ enum { ZKVC_Q_A = 0, ZKVC_Q_B1 = 1, ZKVC_Q_B2 = 2, ZKVC_Q_L = 3, ZKVC_Q_H = 4, Z
  *   A:      [u_i(tau)]1 for i = 0 .. l, then (PLAIN_ADD, CRPC) the auxiliary variables
  *   B1, B2: [v_i(tau)]1,2 for the w variables, then (PLAIN_ADD, CRPC) the constant
  *   L:      [(beta u_i + alpha v_i + w_i)(tau)/delta]1 for the w, then auxiliary variables
- *   H:      [tau^j (tau^N - 1)/delta]1 for j = 0 .. N-2
+ *   H:      [(tau^N - 1)/delta * L'_a(tau)]1 for a = 0 .. N-1, where L'_a is the
+ *           Lagrange basis polynomial of the coset g H = {5 omega_N^a} at the
+ *           point 5 omega_N^a (omega_N = w^(2^(28-log_n)), w = 5^((r-1)/2^28)):
+ *           L'_a(X) = (X^N - 5^N) x_a / (N 5^N (X - x_a)).  The prover takes h
+ *           = (A B - C) / Z as its values on that coset, so sum_a h(x_a) H_a
+ *           equals the textbook sum_j h_j [tau^j (tau^N - 1)/delta]1
+ *           (Section II, Groth16 Prove): the proof is the same.
  * Used to spot-check keys.  Errors: ZKVC_EINVAL (unknown query or range).
  */
 int zkvc_pk_export(const zkvc_pk* pk, uint32_t query, uint64_t start, uint64_t count, void* host_out);

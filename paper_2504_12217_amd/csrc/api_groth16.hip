@@ -166,7 +166,7 @@ int zkvc_pk_info(const zkvc_pk* pk, zkvc_pk_info_t* info) {
     info->a_query = total(L.segA);
     info->b_query = total(L.segB);
     info->l_query = total(L.segL);
-    info->h_query = L.N - 1;
+    info->h_query = L.N;
     const size_t ctx_bytes = pk->ctx ? pk->ctx->device_bytes() : 0;
     info->device_bytes = pk->key_bytes + pk->ws.bytes() + ctx_bytes;
     info->prove_bytes = prove_footprint(L);

@@ -230,16 +230,17 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_pass(PassParams p, NttTable
 // ---- fused passes of the QAP quotient chain.  The inverse transform's last
 // pass and the coset transform's first pass cover the same (bottom) bit
 // range, so one block does both with the coset scaling between them; the
-// coset transform's last pass, the pointwise quotient and the inverse coset
-// transform's first pass cover the same (top) bit range, so one block does
-// all three for a proof's A, B and C.
+// coset transform's last pass (the top bit range) and the pointwise quotient
+// are done by one block for a proof's A, B and C.  The chain ends there: the
+// quotient h stays as its values on the coset, the scalars of an H query
+// held in that coset's Lagrange basis.
 struct FusedParams {
   uint32_t* data[3];          // one proof's A, B, C ...
   uint32_t* const* table;     // ... or a device table, 3 entries per proof
   int log_n, k, log_g;
   const uint32_t* ninv;       // N^-1 (bottom: with the coset scaling)
   const uint32_t* zinv;       // (g^N - 1)^-1 (top: the pointwise quotient)
-  const uint32_t* tw[2];      // top: the pass's forward / inverse twiddle tables, or null
+  const uint32_t* tw[1];      // top: the pass's forward twiddle table, or null
   const uint32_t* coset;      // bottom: g^bitrev(i) / N by address i, or null
 };
 
@@ -275,7 +276,9 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fused_bottom(FusedParams p,
   }
 }
 
-// Top fusion, one proof per blockIdx.y; the quotient overwrites A.
+// Top fusion, one proof per blockIdx.y: the coset transform's last pass on
+// A, B and C, then the pointwise quotient, which overwrites A: h(g omega^a) at
+// address a (natural order; lazy values in [0, 2r), device Montgomery form).
 __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fused_top(FusedParams p, NttTables T) {
   extern __shared__ uint32_t lds[];
   ntt_wave_priority();
@@ -301,17 +304,10 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fused_top(FusedParams p, Nt
   lds_stages(lds, k, E, 3, true, T.local[0]);  // forward DIT, last pass, on A, B and C
   const Fr zinv = Fr::load(p.zinv);
   for (uint32_t e = threadIdx.x; e < E; e += blockDim.x) {
-    const Fr a = lds_get(lds, e), b = lds_get(lds, E + e), c = lds_get(lds, 2 * E + e);
-    lds_put(lds, e, Fr::mul_lz(Fr::sub_nr(Fr::mul_lz(a, b), c), zinv));
-  }
-  __syncthreads();
-  lds_stages(lds, k, E, 1, false, T.local[1]);  // inverse DIF, first pass
-  for (uint32_t e = threadIdx.x; e < E; e += blockDim.x) {
     const uint32_t addr = pass_addr(e, k, p.log_g, B, L, gamma0, &gl, &t, &g);
-    Fr x = lds_get(lds, gl * K + t);
-    const uint32_t ex = g * bitrev_bits(t, k);  // inverse DIF twiddle last
-    if (ex) x = Fr::mul_lz(x, p.tw[1] ? Fr::load(p.tw[1] + 8u * ((t << B) | g)) : pow_lookup(T.w[1], ex << tw_shift));
-    x.store(vec[0] + 8ull * addr);
+    const uint32_t slot = gl * K + t;
+    const Fr a = lds_get(lds, slot), b = lds_get(lds, E + slot), c = lds_get(lds, 2 * E + slot);
+    Fr::mul_lz(Fr::sub_nr(Fr::mul_lz(a, b), c), zinv).store(vec[0] + 8ull * addr);
   }
 }
 
@@ -654,14 +650,8 @@ void qap_quotient_launch(uint32_t* const* abc, uint32_t* const* dev_table, int n
   const PassPlan pl = plan_quotient(L);
   const int P = pl.npass;
   const int nvec = 3 * nproofs;
-  uint32_t* const* a_tab = dev_table ? dev_table + nvec : nullptr;
   NttFuse f1;
   f1.in_canonical = true;
-  NttFuse f3;
-  f3.post_const = T.ninv + 8 * L;
-  f3.post_coset = -1;
-  f3.post_bitrev = true;
-  f3.post_table = coset_table(1, L, T, st);  // the same factors, one product
   const NttFuse none;
   // inverse transform (DIF), all passes but the bottom one
   for (int j = 0; j < P - 1; j++) launch_pass(abc, dev_table, nvec, pl, j, false, true, j == 0, false, f1, T, st);
@@ -688,10 +678,9 @@ void qap_quotient_launch(uint32_t* const* abc, uint32_t* const* dev_table, int n
   // forward DIT passes between the bottom and the top
   for (int j = P - 2; j >= 1; j--) launch_pass(abc, dev_table, nvec, pl, j, true, false, false, false, none, T, st);
   {
-    // top: forward DIT pass, pointwise quotient, inverse DIF pass
+    // top: forward DIT pass and the pointwise quotient
     fp.k = pl.k[0];
     fp.tw[0] = twiddle_table(0, L, fp.k, T, st);
-    fp.tw[1] = twiddle_table(1, L, fp.k, T, st);
     const int a = TOP_MAX_K - fp.k, b = pl.log_g(0);
     fp.log_g = a < b ? a : b;
     const uint32_t E = 1u << (fp.k + fp.log_g);
@@ -702,10 +691,6 @@ void qap_quotient_launch(uint32_t* const* abc, uint32_t* const* dev_table, int n
                        (size_t)3 * E * NL * 4, st, fp, T);
     ZK_HIP(hipGetLastError());
   }
-  // inverse coset transform (DIF) on A, the remaining passes
-  uint32_t* const a_only[1] = {abc ? abc[0] : nullptr};
-  for (int j = 1; j < P; j++)
-    launch_pass(dev_table ? nullptr : a_only, a_tab, nproofs, pl, j, false, true, false, j == P - 1, f3, T, st);
 }
 
 void bitrev_launch(uint32_t* data, int log_n, hipStream_t st) {

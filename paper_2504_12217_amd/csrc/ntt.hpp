@@ -66,13 +66,13 @@ void ntt_launch_batch(uint32_t* const* data, int nvec, int log_n, bool dit, bool
                       hipStream_t st);
 
 // The QAP quotient of nproofs proofs of one domain size N = 2^log_n (>= 4):
-// A, B, C hold canonical evaluations on the domain; afterwards A holds the
-// coefficients of h = (A B - C) / Z in bit-reversed order (device Montgomery
-// form); B and C are clobbered.  The vectors are abc[0..2] (one proof) or,
-// for any number of proofs, a device table of 4 nproofs entries: (A, B, C)
-// per proof, then every proof's A again.  Same arithmetic as the chain
-// iNTT / coset NTT / pointwise / coset iNTT with ntt_launch_*, with the
-// bottom and top passes of neighbouring transforms fused.
+// A, B, C hold canonical evaluations on the domain; afterwards A holds
+// h = (A B - C) / Z on the coset g H: entry a is h(g omega_N^a) (natural
+// order, device Montgomery form, a lazy value in [0, 2r)); B and C are
+// clobbered.  The vectors are abc[0..2] (one proof) or, for any number of
+// proofs, a device table of 3 nproofs entries: (A, B, C) per proof.  Same
+// arithmetic as the chain iNTT / coset NTT / pointwise with ntt_launch_*,
+// with the bottom and top passes of neighbouring transforms fused.
 void qap_quotient_launch(uint32_t* const* abc, uint32_t* const* dev_table, int nproofs, int log_n, hipStream_t st);
 
 // In-place bit-reversal permutation of 2^log_n elements.

@@ -112,7 +112,7 @@ Layout r1cs_layout(uint32_t a, uint32_t n, uint32_t b, uint32_t kind) {
   if (aux_in_a) push(L.segB, 0, 1, 1, false);
   push(L.segL, L.w_start, (uint64_t)n * b, 7, true);
   push(L.segL, L.aux_start, L.naux, L.aux_bits, true);
-  L.segH.count = L.N - 1;
+  L.segH.count = L.N;  // h on the coset g H, one scalar per point
   L.segH.bits = 253;
   if (L.segH.count) precompute(L.segH);
   if (kind_uses_z(kind)) {
@@ -326,21 +326,35 @@ __global__ void k_scale_fr(const uint32_t* in, uint32_t n, const uint32_t* f, ui
 
 constexpr int H_CHUNK = 32;
 
-// H_j scalars tau^j (tau^N - 1) / delta for j < count
-__global__ void k_h_scalars(uint32_t count, const uint32_t* consts, uint32_t* out) {
+// The H query in the Lagrange basis of the coset g H: the prover then needs
+// h only as its values on the coset (the QAP quotient's pointwise step), not
+// as coefficients, and the sum is the same group element
+// sum_a h(x_a) [L_a(tau) Z(tau) / delta] = [h(tau) Z(tau) / delta].
+// With x_a = g omega_N^a (the points of the coset transform, taken from the
+// same tables), L_a(tau) = (tau^N - g^N) x_a / (N g^N (tau - x_a)), so
+// scalar a = c x_a / (tau - x_a) for c = (tau^N - 1)(tau^N - g^N) / (delta N g^N).
+// One thread per chunk of H_CHUNK scalars: the prefix products of the
+// denominators go to `out` first, then one inversion gives every 1 / (tau - x_a)
+// of the chunk (Montgomery's trick), which overwrites them.
+__global__ void k_h_scalars(uint32_t count, int log_n, const uint32_t* consts, NttTables T, uint32_t* out) {
   const uint32_t j0 = (blockIdx.x * blockDim.x + threadIdx.x) * H_CHUNK;
   if (j0 >= count) return;
-  const Fr tau = Fr::load(consts), c = Fr::load(consts + 8);
-  Fr x = Fr::one();
-  for (int bit = 31; bit >= 0; bit--) {
-    x = Fr::sqr(x);
-    if ((j0 >> bit) & 1u) x = Fr::mul(x, tau);
-  }
-  x = Fr::mul(x, c);
   const uint32_t j1 = j0 + H_CHUNK < count ? j0 + H_CHUNK : count;
+  const Fr tau = Fr::load(consts), c = Fr::load(consts + 8), g = Fr::load(consts + 16);
+  const int sh = NTT_MAX_LOG - log_n;
+  auto point = [&](uint32_t j) { return Fr::mul(g, pow_lookup(T.w[0], j << sh)); };
+  Fr acc = Fr::one();
   for (uint32_t j = j0; j < j1; j++) {
-    x.store(out + 8ull * j);
-    x = Fr::mul(x, tau);
+    acc.store(out + 8ull * j);  // product of the denominators before j
+    acc = Fr::mul(acc, Fr::sub(tau, point(j)));
+  }
+  Fr inv = Fr::inv(acc);
+  for (uint32_t jj = j1; jj > j0; jj--) {
+    const uint32_t j = jj - 1;
+    const Fr x = point(j);
+    const Fr dinv = Fr::mul(inv, Fr::load(out + 8ull * j));
+    inv = Fr::mul(inv, Fr::sub(tau, x));
+    Fr::mul(Fr::mul(c, x), dinv).store(out + 8ull * j);
   }
 }
 
@@ -358,6 +372,7 @@ struct WitJob {
   uint32_t *assign, *aev, *bev, *cev;
   uint32_t *xk, *wk, *pkk, *yz;  // CRPC kinds: per-k sums and Y(z) partial sums
   uint32_t nyz;                  // number of Y(z) partial sums
+  uint32_t* flag;                // pinned host word set when a row is not satisfied, or null
 };
 struct WitTable {
   const WitJob* jobs;  // device table, or null: use `one`
@@ -365,6 +380,17 @@ struct WitTable {
   __device__ __forceinline__ const WitJob& get(uint32_t q) const { return jobs ? jobs[q] : one; }
 };
 
+
+// A constraint row that the witness does not satisfy (A B != C): the rows
+// whose three values are not a product by construction are checked, and the
+// host reports an internal error instead of returning a proof that cannot
+// verify.  Every writer stores the same value.
+__device__ __forceinline__ void flag_unsatisfied(const WitJob& J) {
+  if (J.flag) {
+    *J.flag = 1u;
+    __threadfence_system();
+  }
+}
 
 // assignment (canonical words) of the constant, x, y and w variables
 
@@ -382,6 +408,7 @@ __global__ void k_rows_plain(WitTable T) {
   if (J.kind == ZKVC_PLAIN_ADD && k == n) {  // (sum_k p_ijk) * 1 = y_ij
     int64_t sum = 0;
     for (uint64_t kk = 0; kk < n; kk++) sum += x(kk) * w(kk);
+    if (sum != (int64_t)J.Y[ij]) flag_unsatisfied(J);
     store_int(J.aev + 8ull * c, sum);
     store_int(J.bev + 8ull * c, 1);
     store_int(J.cev + 8ull * c, J.Y[ij]);
@@ -400,6 +427,7 @@ __global__ void k_rows_plain(WitTable T) {
         int64_t s = 0;
         for (uint64_t kk = 0; kk + 1 < n; kk++) s += x(kk) * w(kk);
         cval = (int64_t)J.Y[ij] - s;
+        if (cval != prod) flag_unsatisfied(J);
       }
       break;
     case ZKVC_PLAIN_ADD:
@@ -414,6 +442,7 @@ __global__ void k_rows_plain(WitTable T) {
         cval = (before + prod) - before;
       } else {
         cval = (int64_t)J.Y[ij] - before;
+        if (cval != prod) flag_unsatisfied(J);
       }
       break;
     }
@@ -508,6 +537,9 @@ __device__ void crpc_rows_body(const WitJob& J, uint32_t* sh, uint32_t* carry_sh
       } else {
         store_canonical(cev + 8ull * k, Fr::sub(yz, prev));
       }
+      // the last PSQ row (Y(z) - s_(n-2) = P_(n-1)) and the CRPC sum row
+      // (s_(n-1) * 1 = Y(z)) both hold exactly when s_(n-1) = Y(z)
+      if (k == n - 1 && !Fr::eq(s, yz)) flag_unsatisfied(J);
       if (kind == ZKVC_CRPC && k == n - 1) {  // (sum_k P_k) * 1 = Y(z)
         store_canonical(aev + 8ull * n, s);
         store_canonical(bev + 8ull * n, Fr::one());
@@ -632,6 +664,7 @@ void enqueue_witness_one(const Layout& L, const uint32_t* zpow, uint64_t rows, c
   const uint32_t mm_bx = cdiv(L.b, RED_THREADS), mm_blocks = mm_bx * L.a;
   J.yz = crpc ? ws.get(233, 32ull * mm_blocks) : nullptr;
   J.nyz = mm_blocks;
+  J.flag = nullptr;
   const uint32_t xw_blocks = crpc ? L.n : 0u;
   hipLaunchKernelGGL(k_wit_first, dim3(xw_blocks + mm_blocks, 1), dim3(RED_THREADS), 0, st, T, xw_blocks, mm_bx);
   ZK_HIP(hipGetLastError());
@@ -702,6 +735,7 @@ zkvc_pk* groth16_setup(const Layout& L, const host::HFr toxic[5], const host::HF
   const uint64_t Nexp[4] = {L.N, 0, 0, 0};
   const HFr tN = HFr::pow(tau, Nexp);
   ZK_REQUIRE(tN != HFr::one(), "tau lies in the evaluation domain");
+  ZK_REQUIRE(tN != HFr::pow(HFr::from_uint(5), Nexp), "tau lies in the quotient's coset");
   const bool use_z = kind_uses_z(L.kind);
   if (use_z) ZK_REQUIRE(z != nullptr && !z->is_zero(), "this circuit kind needs a nonzero z");
 
@@ -844,15 +878,20 @@ zkvc_pk* groth16_setup(const Layout& L, const host::HFr toxic[5], const host::HF
       emit_g1(rsc, L.segR, pk->qRL.get());
     }
   }
-  // H query: tau^j (tau^N - 1) / delta, j < N - 1
+  // H query: (tau^N - 1) / delta times the Lagrange basis of the coset g H at tau
   if (N > 1) {
-    std::vector<uint32_t> hc(16);
+    const HFr g = HFr::from_uint(5);  // the coset shift of the quotient's transforms
+    const HFr gN = HFr::pow(g, Nexp);
+    std::vector<uint32_t> hc(24);
     tau.to_dev(&hc[0]);
-    HFr::mul(HFr::sub(tN, HFr::one()), HFr::inv(delta)).to_dev(&hc[8]);
+    HFr::mul(HFr::mul(HFr::sub(tN, HFr::one()), HFr::sub(tN, gN)), HFr::inv(HFr::mul(HFr::mul(delta, gN), HFr::from_uint(L.N))))
+        .to_dev(&hc[8]);
+    g.to_dev(&hc[16]);
     uint32_t* dhc = ws.get(10, hc.size() * 4);
     upload_words(dhc, hc, st);
-    const uint32_t cnt = (uint32_t)(N - 1);
-    hipLaunchKernelGGL(k_h_scalars, dim3(cdiv(cdiv(cnt, H_CHUNK), 128)), dim3(128), 0, st, cnt, dhc, sc);
+    const uint32_t cnt = (uint32_t)N;
+    hipLaunchKernelGGL(k_h_scalars, dim3(cdiv(cdiv(cnt, H_CHUNK), 128)), dim3(128), 0, st, cnt, (int)L.log_n, dhc, T,
+                       sc);
     ZK_HIP(hipGetLastError());
     emit_g1(sc, L.segH, pk->qH.get());
   }
@@ -908,23 +947,6 @@ zkvc_pk* groth16_setup(const Layout& L, const host::HFr toxic[5], const host::HF
 }
 
 // ------------------------------------------------------------------ host: prove
-// flag |= 1 if some proof's h_{N-1} (the last element of its quotient, which
-// bit reversal leaves in place) is nonzero: the quotient of a satisfied
-// system has degree < N - 1.  The vectors come from a table (count of them)
-// or, without a table, `one` alone.
-__global__ void k_check_top(uint32_t* const* tab, const uint32_t* one, uint32_t count, uint64_t N, uint32_t* flag) {
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= count) return;
-  const uint32_t* h = (tab ? tab[j] : one) + 8ull * (N - 1);
-  uint32_t t = 0;
-#pragma unroll
-  for (int q = 0; q < 8; q++) t |= h[q];
-  if (t) {  // every writer stores the same value; flag is pinned host memory
-    *flag = 1u;
-    __threadfence_system();
-  }
-}
-
 namespace {
 enum ProveSlot { P_ASSIGN = 20, P_AEV, P_BEV, P_CEV, P_XK, P_WK, P_PK, P_YZ };
 enum SharedSlot { C_TABLE = 60, C_FLAG, C_XW, C_Y, C_WTAB };
@@ -940,7 +962,7 @@ struct MsmJob {
 };
 
 // wk: for the CRPC kinds, W_k(z) = sum_j z^j w_kj for k < n (device Montgomery form).
-std::vector<MsmJob> msm_jobs(const zkvc_pk* pk, const uint32_t* assign, const uint32_t* h_bitrev,
+std::vector<MsmJob> msm_jobs(const zkvc_pk* pk, const uint32_t* assign, const uint32_t* h_coset,
                              const uint32_t* wk) {
   const Layout& L = pk->L;
   std::vector<MsmJob> jobs;
@@ -983,11 +1005,11 @@ std::vector<MsmJob> msm_jobs(const zkvc_pk* pk, const uint32_t* assign, const ui
     j.group = 1;
     j.query = ZKVC_Q_H;
     j.in.points = pk->qH.get();
-    j.in.npoints = L.N - 1;
-    j.in.scalars = h_bitrev;
+    j.in.npoints = L.N;
+    j.in.scalars = h_coset;
     j.in.nscalars = L.N;
     j.in.scalars_mont = true;
-    j.in.point_index_bitrev = L.log_n;
+    j.in.point_index_bitrev = 0;
     j.in.max_bits = L.segH.bits;
     if (L.segH.pre_nw > 1) {
       j.in.pre_c = L.segH.pre_c;
@@ -1022,8 +1044,14 @@ struct YCopy {
 // copy from pinned staging, and their Y comes back in one copy to pinned
 // memory (described in *ycopy, enqueued by the caller); device-buffer proofs
 // read and write the caller's buffers.  No host wait inside the enqueue.
-std::vector<Slot> enqueue_witness_batch(const ProveJob* jobs, size_t nj, ProveGen& G, hipStream_t st, YCopy* ycopy) {
+std::vector<Slot> enqueue_witness_batch(const ProveJob* jobs, size_t nj, ProveGen& G, hipStream_t st, YCopy* ycopy,
+                                        volatile uint32_t** flag_out) {
   ZK_REQUIRE(nj <= 65535, "at most 65535 proofs per batch");
+  // the row check writes straight into pinned host memory (cleared here; a
+  // graph replay clears it before each launch)
+  uint32_t* flag = G.shared.host<uint32_t>(C_FLAG, 4);
+  *flag = 0u;
+  *flag_out = flag;
   auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
   std::vector<size_t> xo(nj), wo(nj), yo(nj);
   size_t xw_bytes = 0, y_bytes = 0;
@@ -1080,6 +1108,7 @@ std::vector<Slot> enqueue_witness_batch(const ProveJob* jobs, size_t nj, ProveGe
     J.aev = S.aev;
     J.bev = S.bev;
     J.cev = S.cev;
+    J.flag = flag;
     if (kind_uses_z(L.kind)) {
       J.xk = ws.get(P_XK, (size_t)L.n * 32);
       J.wk = ws.get(P_WK, (size_t)L.n * 32);
@@ -1369,7 +1398,7 @@ struct BatchRun {
   std::vector<MsmInput> in_g1, in_g2, in_h;
   std::vector<int> own_g1, query_g1, own_g2, own_h;
   std::vector<MsmPending> pend_g1, pend_g2, pend_h;
-  volatile uint32_t* flag_host = nullptr;  // pinned, written by the tail check
+  volatile uint32_t* flag_host = nullptr;  // pinned, written by the witness row check
   std::chrono::steady_clock::time_point host_t0;
   // the H MSMs on the quotient's own stream (no cross-stream wait between
   // them); a pipelined caller keeps them on the H lane so that its next
@@ -1525,7 +1554,7 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
 
   // ---- witnesses and evaluation vectors
   YCopy ycopy;
-  R.slots = enqueue_witness_batch(jobs, nj, G, st, &ycopy);
+  R.slots = enqueue_witness_batch(jobs, nj, G, st, &ycopy, &R.flag_host);
   std::vector<Slot>& slots = R.slots;
   record_ext(G.ev[1], st, capture);
   ZK_HIP(hipEventRecord(G.witness_ev, st));
@@ -1605,15 +1634,11 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
   try {
     // ---- QAP quotients: iNTT (DIF, natural -> bit-reversed coefficients),
     // coset NTT (DIT, bit-reversed -> natural evaluations on g H), pointwise
-    // (A B - C)/(g^N - 1), inverse coset NTT (DIF: h in bit-reversed order).
-    // Proofs of one domain size share every launch.
+    // (A B - C)/(g^N - 1): h on the coset, the H query's scalars.  Proofs of
+    // one domain size share every launch.
     std::map<int, std::vector<size_t>> by_size;
     for (size_t j = 0; j < nj; j++) by_size[jobs[j].pk->L.log_n].push_back(j);
-    // the tail check writes straight into pinned host memory (cleared here; a
-    // graph replay clears it before each launch)
-    uint32_t* flag_host = G.shared.host<uint32_t>(C_FLAG, 4);
-    *flag_host = 0u;
-    // device tables for groups of several proofs: (A, B, C) triples, then the A's
+    // device tables for groups of several proofs: (A, B, C) triples
     std::vector<uint32_t*> tab_v;
     std::vector<size_t> tab_off;
     for (auto& kv : by_size) {
@@ -1624,7 +1649,6 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
         tab_v.push_back(slots[j].bev);
         tab_v.push_back(slots[j].cev);
       }
-      for (size_t j : kv.second) tab_v.push_back(slots[j].aev);
     }
     uint32_t** tab_dev = nullptr;
     if (!tab_v.empty()) {
@@ -1637,25 +1661,16 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
     size_t gi = 0;
     for (auto& kv : by_size) {
       const int Lg = kv.first;
-      const uint64_t N = 1ull << Lg;
       const size_t k = kv.second.size();
       if (k == 1) {
         const Slot& S = slots[kv.second[0]];
         uint32_t* const vecs[3] = {S.aev, S.bev, S.cev};
         qap_quotient_launch(vecs, nullptr, 1, Lg, st);
-        hipLaunchKernelGGL(k_check_top, dim3(1), dim3(64), 0, st, (uint32_t* const*)nullptr, S.aev, 1u, N,
-                           flag_host);
-        ZK_HIP(hipGetLastError());
       } else {
-        uint32_t** tg = tab_dev + tab_off[gi];
-        qap_quotient_launch(nullptr, tg, (int)k, Lg, st);
-        hipLaunchKernelGGL(k_check_top, dim3(cdiv(k, 64)), dim3(64), 0, st, tg + 3 * k, (const uint32_t*)nullptr,
-                           (uint32_t)k, N, flag_host);
-        ZK_HIP(hipGetLastError());
+        qap_quotient_launch(nullptr, tab_dev + tab_off[gi], (int)k, Lg, st);
       }
       gi++;
     }
-    R.flag_host = flag_host;
     record_ext(G.ev[2], st, capture);
     ZK_HIP(hipEventRecord(G.quotient_ev, st));
 
@@ -1755,7 +1770,7 @@ void prove_batch_finish(ProveCtx& ctx, BatchRun& R) {
         if (x->valid()) x->wait();
     }
   } wait_all{{&f_g1, &f_g2, &f_h}};
-  ZK_HIP(hipEventSynchronize(G.ev[2]));  // quotients and the tail flag
+  ZK_HIP(hipEventSynchronize(G.ev[2]));  // witnesses (the row flag) and quotients
   if (*R.flag_host) throw Error(ZKVC_EDEVICE, "internal error: a witness does not satisfy its circuit");
   for (int lane = 0; lane < ProveCtx::LANES; lane++) ZK_HIP(hipEventSynchronize(G.done_ev[lane]));
   const auto asm_t0 = std::chrono::steady_clock::now();

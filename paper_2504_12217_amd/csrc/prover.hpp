@@ -46,7 +46,7 @@ struct Layout {
   uint64_t aux_start = 0; // first auxiliary variable
   int y_bits = 0, aux_bits = 253;
   std::vector<Seg> segA, segB, segL;  // query coverage
-  Seg segH;                            // the H query (j < N - 1)
+  Seg segH;                            // the H query (the Lagrange basis of the coset g H: N points)
   // CRPC kinds: one base per constraint row k < n (the B1, B2 and L entries
   // of w_k0), stored with precomputed windows; the prover sums the n b
   // W terms of those queries as n row terms (see msm_jobs)

@@ -11,6 +11,7 @@ import pytest
 import synth
 from oracle import bn254 as bn
 from oracle import encoding, groth16, qap, r1cs
+from oracle import ntt as ontt
 
 pytestmark = pytest.mark.gpu
 
@@ -49,6 +50,21 @@ def _oracle_query_layout(s, kind):
     return A, B, L
 
 
+def _coset_points(N):
+    """x_a = g omega_N^a, a < N: the coset g H of the quotient (g = 5)."""
+    w = ontt.root_of_unity(N)
+    return [ontt.COSET_SHIFT * pow(w, a, bn.R) % bn.R for a in range(N)]
+
+
+def _coset_lagrange_h(tox, N):
+    """[(tau^N - 1)/delta * L'_a(tau)]_1 with L'_a the Lagrange basis of the
+    coset at x_a: L'_a(X) = (X^N - g^N) x_a / (N g^N (X - x_a))."""
+    R, g = bn.R, ontt.COSET_SHIFT
+    tN, gN = pow(tox.tau, N, R), pow(g, N, R)
+    c = (tN - 1) * (tN - gN) * pow(tox.delta * N * gN, R - 2, R) % R
+    return [bn.g1_mul(bn.G1_GEN, c * x * pow(tox.tau - x, R - 2, R) % R) for x in _coset_points(N)]
+
+
 def _check_honest(zk, seed, a, n, b, kind):
     s = r1cs.Shape(a, n, b)
     X, W, tox, z, r, sr = _job(seed, a, n, b, kind)
@@ -62,13 +78,21 @@ def _check_honest(zk, seed, a, n, b, kind):
     # every proving-key entry identical
     info = pk.info()
     A, B, L = _oracle_query_layout(s, kind)
-    assert (info.a_query, info.b_query, info.l_query, info.h_query) == (len(A), len(B), len(L), len(opk["H"]))
+    N = opk["N"]
+    assert (info.a_query, info.b_query, info.l_query, info.h_query) == (len(A), len(B), len(L), N)
     assert pk.export(zk.Q_A, 0, len(A)) == [opk["A"][i] for i in A]
     assert pk.export(zk.Q_B1, 0, len(B)) == [opk["B1"][i] for i in B]
     assert pk.export(zk.Q_B2, 0, len(B)) == [opk["B2"][i] for i in B]
     w0 = r1cs.first_witness(s)
     assert pk.export(zk.Q_L, 0, len(L)) == [opk["L"][i - w0] for i in L]
-    assert pk.export(zk.Q_H, 0, len(opk["H"])) == opk["H"]
+    # H in the Lagrange basis of the coset g H (the form zkvc.h documents),
+    # pinned to the oracle's tau-power query: X^j interpolated on the coset is
+    # X^j itself (j < N), so sum_a x_a^j H_a = [tau^j Z(tau) / delta] = H_j
+    got_h = pk.export(zk.Q_H, 0, N)
+    assert got_h == _coset_lagrange_h(tox, N)
+    xs = _coset_points(N)
+    for j in sorted({0, 1, N // 2, N - 2}):
+        assert bn.g1_msm(got_h, [pow(x, j, bn.R) for x in xs]) == opk["H"][j]
     assert pk.export(zk.Q_CONST, 0, 0) == [opk["alpha1"], opk["beta1"], opk["delta1"], opk["beta2"],
                                            opk["delta2"]]
     # the proof equals the oracle's honest proof

@@ -18,6 +18,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle import ntt as ontt
 from oracle import bn254 as bn
 from oracle import encoding, groth16, qap, r1cs
 from oracle.bn254 import R
@@ -87,11 +88,15 @@ def _spot_check_pk(zk, pk, s, kind, tox, z, count=24, seed=0):
         u, v, w = polys[i]
         lin = (tox.beta * u + tox.alpha * v + w) * d_inv % R
         assert zk_point(pk, zk.Q_L, i - w0) == bn.g1_mul(bn.G1_GEN, lin)
+    # H: (tau^N - 1)/delta times the Lagrange basis of the coset g H at x_a = g omega_N^a
     n_dom = 1 << info.log_n
-    t_tau = (pow(tox.tau, n_dom, R) - 1) % R
-    for j in sorted(set(rng.randrange(n_dom - 1) for _ in range(count)) | {0, n_dom - 2}):
-        want = bn.g1_mul(bn.G1_GEN, pow(tox.tau, j, R) * t_tau % R * d_inv)
-        assert zk_point(pk, zk.Q_H, j) == want
+    g, w = ontt.COSET_SHIFT, ontt.root_of_unity(n_dom)
+    tN, gN = pow(tox.tau, n_dom, R), pow(g, n_dom, R)
+    c = (tN - 1) * (tN - gN) * pow(tox.delta * n_dom * gN, -1, R) % R
+    for a in sorted(set(rng.randrange(n_dom) for _ in range(count)) | {0, n_dom - 1}):
+        x = g * pow(w, a, R) % R
+        want = bn.g1_mul(bn.G1_GEN, c * x * pow(tox.tau - x, -1, R) % R)
+        assert zk_point(pk, zk.Q_H, a) == want
 
 
 def zk_point(pk, q, idx):
@@ -124,6 +129,6 @@ def test_plain_paper_shape(zk):
     """The per-product circuit for [49,320] x [320,512]: 8,028,160 constraints, N = 2^23."""
     s, tox, z, pk, X, Y, proof = _run(zk, 0, 49, 320, 512, r1cs.PLAIN)
     info = pk.info()
-    assert info.log_n == 23 and info.h_query == (1 << 23) - 1
+    assert info.log_n == 23 and info.h_query == 1 << 23
     _spot_check_pk(zk, pk, s, r1cs.PLAIN, tox, z, count=6)
     pk.close()
