@@ -410,8 +410,17 @@ __device__ __forceinline__ Xyzz<F> quad_tree_sum(Xyzz<F> acc, uint32_t* sh, uint
 // others run wavefront tasks (each lane sums a strided share of the task's
 // entries, then an LDS tree).  Task counts are read on the device; every
 // loop is bounded by them.
+// Waves per SIMD the accumulation and finalize kernels are built for.  The G2
+// kernels would otherwise take ~370 registers, one wave per SIMD: a wave then
+// holds a whole SIMD, next to the critical path's kernels, for its lifetime.
+// Two waves (256 registers, a few hundred bytes of spill) measured faster
+// for the proofs and for the G2 MSMs themselves; three spill too much.
 template <class F>
-__global__ void __launch_bounds__(64) k_msm_acc(BatchDev B, const uint4* th_tasks, const uint4* wg_tasks,
+struct AccWaves {
+  static constexpr int value = sizeof(F) <= 64 ? 1 : 2;
+};
+template <class F>
+__global__ void __launch_bounds__(64, AccWaves<F>::value) k_msm_acc(BatchDev B, const uint4* th_tasks, const uint4* wg_tasks,
                                                 const uint32_t* counters, uint32_t th_blocks, const uint32_t* sorted,
                                                 uint32_t* partials, int quad, const uint32_t* total,
                                                 uint32_t* work_out) {
@@ -489,7 +498,7 @@ __global__ void __launch_bounds__(64) k_msm_acc(BatchDev B, const uint4* th_task
 // (e.g. the top window's few digit values under uniform scalars) does not
 // serialize the step.  quad: latency-bound batches add in cooperative quads.
 template <class F>
-__global__ void __launch_bounds__(64) k_msm_finalize(const uint32_t* nt, const uint32_t* part_off,
+__global__ void __launch_bounds__(64, AccWaves<F>::value) k_msm_finalize(const uint32_t* nt, const uint32_t* part_off,
                                                      const uint32_t* partials, uint32_t nbt, const uint32_t* counters,
                                                      const uint32_t* heavy, uint32_t light_blocks, uint32_t fin_max,
                                                      uint32_t group, int quad, uint32_t* buckets, int prio) {
@@ -618,10 +627,11 @@ __global__ void __launch_bounds__(BP_THREADS) k_msm_gridsums(BatchDev B, uint32_
 // sums the block, and k_msm_plane_sums adds the bpb block sums of each plane.
 // G1 bit planes run at four wavefronts per SIMD (at most 128 VGPRs, a few
 // spilled): the reduction of a large bucket set then fits the device in one
-// round of blocks.  G2's working set is too large for that.
+// round of blocks.  G2's working set is too large for that: two waves (as
+// for its accumulation, see AccWaves).
 template <class F>
 struct BpWaves {
-  static constexpr int value = sizeof(F) <= 64 ? 4 : 1;
+  static constexpr int value = sizeof(F) <= 64 ? 4 : 2;
 };
 template <class F>
 __global__ void __launch_bounds__(BP_THREADS, BpWaves<F>::value) k_msm_bitplanes(BatchDev B, const uint32_t* buckets, uint32_t* part,
