@@ -80,6 +80,11 @@ struct JobDev {
   uint32_t set_stride, lg, pstride, poff;
   uint32_t blk_digits;      // first block of the digit grid
   uint32_t blk_hs;          // first block of the histogram / scatter grid (nw * nch blocks, or nch)
+  // signed-digit recoding: K = sum_{w < nw} (2^(c-1) - 1) 2^(c w) (9 words:
+  // c nw reaches 268 bits); digits_pw: one digit thread per (window, scalar)
+  // instead of per scalar
+  uint32_t kadd[9];
+  uint32_t digits_pw;
 };
 // A batch of up to INLINE_JOBS jobs (a single proof's lanes, a single MSM)
 // carries its job records in the kernel arguments; a larger batch (every
@@ -128,30 +133,47 @@ constexpr uint64_t FIN_QUAD_BUCKETS = 16384;     // see batch_plan (finalize in 
 constexpr uint64_t FIN_QUAD_LANES = 1ull << 17;  // about two wavefronts per SIMD
 
 // ---------------------------------------------------------------- 1. digits
-// One thread per scalar: fold, recode into signed digits, write one word per
-// window (bucket | sign, or EMPTY for a zero digit or a point at infinity).
+// Fold s > (r-1)/2 to r - s with the sign flipped, then recode into signed
+// digits d_w in (-2^(c-1), 2^(c-1)] with s = sum_w d_w 2^(c w).  With the
+// constant K = sum_w (2^(c-1) - 1) 2^(c w), window w of S = s + K holds
+// d_w + 2^(c-1) - 1 (a window's carry into the next is exactly the carry of
+// the binary addition), so every window's digit is read off S on its own.
+// Output: one word per window (bucket |d| - 1 | sign, or EMPTY for a zero
+// digit or a point at infinity).  Jobs with few scalars and many windows
+// take a thread per (window, scalar), the others a thread per scalar.
 template <class F>
 __global__ void __launch_bounds__(256) k_msm_digits(BatchDev B, uint32_t* digits) {
   wave_priority(B.prio);
   const int k = job_of<&JobDev::blk_digits>(B, blockIdx.x);
   const JobDev& J = B.job(k);
-  const uint32_t j = (blockIdx.x - J.blk_digits) * 256 + threadIdx.x;
-  if (j >= J.n) return;
+  const uint32_t t = (blockIdx.x - J.blk_digits) * 256 + threadIdx.x;
+  uint32_t j, w0, w1;
+  if (J.digits_pw) {
+    if (t >= J.n * (uint32_t)J.nw) return;
+    w0 = t / J.n;
+    j = t - w0 * J.n;
+    w1 = w0 + 1;
+  } else {
+    if (t >= J.n) return;
+    j = t;
+    w0 = 0;
+    w1 = (uint32_t)J.nw;
+  }
   const uint32_t idx = J.bitrev_bits ? bitrev_n(j, J.bitrev_bits) : j;
   bool skip = idx >= J.npoints;
   if (!skip) skip = PointIO<F>::affine_is_zero(J.points + (size_t)idx * PointIO<F>::AFF_WORDS);
-  uint32_t s[8];
+  uint32_t s[9];
   {
     const uint4 a = reinterpret_cast<const uint4*>(J.scalars + 8ull * j)[0];
     const uint4 b = reinterpret_cast<const uint4*>(J.scalars + 8ull * j)[1];
     s[0] = a.x; s[1] = a.y; s[2] = a.z; s[3] = a.w; s[4] = b.x; s[5] = b.y; s[6] = b.z; s[7] = b.w;
+    s[8] = 0u;
   }
   if (J.mont) {
     Fr x = Fr::unpack(s);
     x = Fr::from_mont(x);
     x.pack(s);
   }
-  // fold: s > (r-1)/2  ->  r - s with the sign flipped
   bool gt = false, decided = false;
 #pragma unroll
   for (int q = 7; q >= 0; q--) {
@@ -165,35 +187,38 @@ __global__ void __launch_bounds__(256) k_msm_digits(BatchDev B, uint32_t* digits
     uint64_t borrow = 0;
 #pragma unroll
     for (int q = 0; q < 8; q++) {
-      const uint64_t t = (uint64_t)FrParams::P32[q] - s[q] - borrow;
-      s[q] = (uint32_t)t;
-      borrow = (t >> 32) & 1u;
+      const uint64_t d = (uint64_t)FrParams::P32[q] - s[q] - borrow;
+      s[q] = (uint32_t)d;
+      borrow = (d >> 32) & 1u;
+    }
+  }
+  // S = s + K (below 2^(c nw): s < 2^(c nw - 1) and K < 2^(c nw - 1))
+  {
+    uint64_t carry = 0;
+#pragma unroll
+    for (int q = 0; q < 9; q++) {
+      const uint64_t a = (uint64_t)s[q] + J.kadd[q] + carry;
+      s[q] = (uint32_t)a;
+      carry = a >> 32;
     }
   }
   const int c = J.c;
-  const uint32_t half = 1u << (c - 1);
+  const int32_t bias = (int32_t)(1u << (c - 1)) - 1;
   const uint32_t cmask = (1u << c) - 1u;
-  uint32_t carry = 0;
   uint32_t* out = digits + J.digit_base + j;
-  for (int w = 0; w < J.nw; w++) {
-    const int pos = c * w;
+  for (uint32_t w = w0; w < w1; w++) {
+    const int pos = c * (int)w;
     const int q = pos >> 5, sh = pos & 31;
     uint32_t raw = 0;
-    if (q < 8) {
+    if (q < 9) {
       const uint32_t lo = s[q];
-      const uint32_t hi = q + 1 < 8 ? s[q + 1] : 0u;
+      const uint32_t hi = q + 1 < 9 ? s[q + 1] : 0u;
       raw = (uint32_t)((((uint64_t)hi << 32) | lo) >> sh) & cmask;
     }
-    uint32_t d = raw + carry;
-    uint32_t sgn = 0;
-    if (d > half) {
-      d = (1u << c) - d;
-      sgn = 1;
-      carry = 1;
-    } else {
-      carry = 0;
-    }
-    out[(size_t)w * J.n] = (!skip && d != 0u) ? ((d - 1u) | ((neg ^ sgn) << 31)) : EMPTY;
+    const int32_t d = (int32_t)raw - bias;
+    const uint32_t sgn = d < 0 ? 1u : 0u;
+    const uint32_t mag = (uint32_t)(d < 0 ? -d : d);
+    out[(size_t)w * J.n] = (!skip && mag != 0u) ? ((mag - 1u) | ((neg ^ sgn) << 31)) : EMPTY;
   }
 }
 
@@ -812,6 +837,28 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs, int group) {
     }
     J.nb = 1u << (J.c - 1);
     J.nwb = J.pre ? 1u : (uint32_t)J.nw;
+    {  // K = sum_w (2^(c-1) - 1) 2^(c w), c nw <= 256 bits
+      uint64_t kw[5] = {0, 0, 0, 0, 0};
+      for (int w = 0; w < J.nw; w++) {
+        const int pos = J.c * w, q = pos >> 6, sh = pos & 63;
+        const uint64_t v = (1ull << (J.c - 1)) - 1ull;
+        // add v << pos into the 256-bit value (no overflow: K < 2^(c nw - 1))
+        unsigned __int128 acc = (unsigned __int128)v << sh;
+        for (int i = q; i < 5 && acc; i++) {
+          acc += kw[i];
+          kw[i] = (uint64_t)acc;
+          acc >>= 64;
+        }
+      }
+      for (int i = 0; i < 4; i++) {
+        J.kadd[2 * i] = (uint32_t)kw[i];
+        J.kadd[2 * i + 1] = (uint32_t)(kw[i] >> 32);
+      }
+      J.kadd[8] = (uint32_t)kw[4];
+      ZK_REQUIRE((kw[4] >> 32) == 0, "MSM window layout beyond 288 bits");
+    }
+    // few scalars, many windows: spread the recoding over (window, scalar)
+    J.digits_pw = J.nw >= 4 && J.n < 16384 ? 1u : 0u;
     const uint64_t wb = (uint64_t)J.nw * J.nb;
     if (J.pre) {
       // one bucket set: chunks of >= 4096 digits over the whole stream (a
@@ -841,7 +888,7 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs, int group) {
     p.nbt += (uint64_t)J.nwb * J.nb;
     p.nh += (uint64_t)J.nwb * J.nb * J.nch;
     p.nplanes += (uint64_t)J.nwb * J.c;
-    p.digit_blocks += cdiv(J.n, 256);
+    p.digit_blocks += J.digits_pw ? cdiv((uint64_t)J.n * J.nw, 256) : cdiv(J.n, 256);
     p.hs_blocks += J.pre ? (uint64_t)J.nch : (uint64_t)J.nw * J.nch;
     p.max_nb = std::max(p.max_nb, J.nb);
     p.map.push_back(q);
