@@ -274,49 +274,54 @@ __global__ void __launch_bounds__(HS_THREADS) k_msm_hist(BatchDev B, const uint3
   for (uint32_t b = threadIdx.x; b < J.nb; b += HS_THREADS) h[b] = cnt[b];
 }
 
-// A quad of lanes per bucket f (window w, digit value b): lane q of the quad
-// takes the q-th quarter of the bucket's column of histogram rows.  A first
-// pass sums each quarter, a scan across the quad gives each quarter its
-// start, and a second pass turns the counts into running offsets inside the
-// bucket, in place; cnt[f] receives the bucket's size and nt[f] its number
-// of tasks (see k_msm_make_tasks).  Also clears the task-list counters.
+// A group of G lanes (G = 4, 8 or 16, a power of two dividing the wavefront)
+// per bucket f (window w, digit value b): lane q of the group takes the q-th
+// share of the bucket's column of histogram rows.  A first pass sums each
+// share, a scan across the group gives each share its start, and a second
+// pass turns the counts into running offsets inside the bucket, in place;
+// cnt[f] receives the bucket's size and nt[f] its number of tasks (see
+// k_msm_make_tasks).  Also clears the task-list counters.
 __global__ void __launch_bounds__(256) k_msm_colscan(BatchDev B, uint32_t* hist, uint32_t nbt, uint32_t K,
                                                      uint32_t large, uint32_t wg_entries, uint32_t* cnt, uint32_t* nt,
-                                                     uint32_t* counters) {
+                                                     uint32_t* counters, uint32_t lg_group) {
   wave_priority(B.prio);
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t f = t >> 2, q = t & 3u;
+  const uint32_t G = 1u << lg_group;
+  const uint32_t f = t >> lg_group, q = t & (G - 1u);
   if (t == 0) {
     counters[0] = 0u;
     counters[1] = 0u;
     counters[2] = 0u;
   }
-  // a quad's four lanes share f: the whole quad is in or out
+  // a group's lanes share f: the whole group is in or out
   if (f >= nbt) return;
   const int k = job_of<&JobDev::bucket_base>(B, f);
   const JobDev& J = B.job(k);
   const uint32_t lf = f - J.bucket_base;
   const uint32_t w = lf / J.nb, b = lf - w * J.nb;
   const uint32_t nch = J.nch, nb = J.nb;
-  const uint32_t per = (nch + 3) >> 2;
+  const uint32_t per = (nch + G - 1) >> lg_group;
   const uint32_t c0 = min(nch, q * per), c1 = min(nch, c0 + per);
   uint32_t* col = hist + J.hist_base + (size_t)w * nch * nb + b;
   uint32_t part = 0;
-#pragma unroll 16
+#pragma unroll 8
   for (uint32_t ch = c0; ch < c1; ch++) part += col[(size_t)ch * nb];
-  // exclusive scan of the four quarter sums inside the quad
-  const uint32_t lane = threadIdx.x & 63u, qbase = lane & ~3u;
-  const uint32_t p0 = __shfl(part, qbase, 64), p1 = __shfl(part, qbase + 1, 64), p2 = __shfl(part, qbase + 2, 64),
-                 p3 = __shfl(part, qbase + 3, 64);
-  uint32_t run = (q > 0 ? p0 : 0u) + (q > 1 ? p1 : 0u) + (q > 2 ? p2 : 0u);
-#pragma unroll 16
+  // inclusive scan of the share sums inside the group (lanes of a group are
+  // consecutive and aligned inside the wavefront)
+  uint32_t inc = part;
+  for (uint32_t o = 1; o < G; o <<= 1) {
+    const uint32_t v = __shfl_up(inc, o, 64);
+    if (q >= o) inc += v;
+  }
+  const uint32_t total = __shfl(inc, (threadIdx.x & 63u) | (G - 1u), 64);
+  uint32_t run = inc - part;
+#pragma unroll 8
   for (uint32_t ch = c0; ch < c1; ch++) {
     const uint32_t v = col[(size_t)ch * nb];
     col[(size_t)ch * nb] = run;
     run += v;
   }
   if (q == 0) {
-    const uint32_t total = p0 + p1 + p2 + p3;
     cnt[f] = total;
     const uint32_t sz = total >= large ? wg_entries : K;
     nt[f] = (total + sz - 1) / sz;
@@ -793,6 +798,7 @@ struct BatchPlan {
   uint32_t gs_threads = 64;
   uint64_t ndigits = 0, nbt = 0, nh = 0, nplanes = 0, digit_blocks = 0, hs_blocks = 0, bp_blocks = 0;
   uint32_t max_nb = 0;
+  uint32_t max_nch = 0;  // the largest number of histogram chunks of one bucket set
   uint32_t K = 0;      // entries per thread task
   uint32_t large = 0;  // buckets with at least this many entries get wavefront tasks
   uint64_t max_th_tasks = 0, max_wg_tasks = 0, max_partials = 0;
@@ -891,6 +897,7 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs, int group) {
     p.digit_blocks += J.digits_pw ? cdiv((uint64_t)J.n * J.nw, 256) : cdiv(J.n, 256);
     p.hs_blocks += J.pre ? (uint64_t)J.nch : (uint64_t)J.nw * J.nch;
     p.max_nb = std::max(p.max_nb, J.nb);
+    p.max_nch = std::max(p.max_nch, J.nch);
     p.map.push_back(q);
     ZK_REQUIRE(p.ndigits < (1ull << 32) && p.nh < (1ull << 32) - 1 && p.nbt < (1ull << 31),
                "MSM batch too large for 32-bit offsets");
@@ -1107,8 +1114,11 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
     hipLaunchKernelGGL(k_msm_hist, dim3((unsigned)p.hs_blocks), dim3(HS_THREADS), lds, st, dev, digits, hist);
     ZK_HIP(hipGetLastError());
     // bucket sizes and task counts, then the buckets' first slots and first partial sums
-    hipLaunchKernelGGL(k_msm_colscan, dim3(cdiv(nbt, 64)), dim3(256), 0, st, dev, hist, nbt, p.K, p.large,
-                       p.wg_entries, cnt, nt, meta + 8);
+    // lanes per bucket: about 16 histogram rows each
+    uint32_t lg_group = 2;
+    while (lg_group < 4 && p.max_nch > (16u << lg_group)) lg_group++;
+    hipLaunchKernelGGL(k_msm_colscan, dim3(cdiv((uint64_t)nbt << lg_group, 256)), dim3(256), 0, st, dev, hist, nbt,
+                       p.K, p.large, p.wg_entries, cnt, nt, meta + 8, lg_group);
     ZK_HIP(hipGetLastError());
     scan_exclusive2(cnt, off, meta + 3, nt, part_off, meta + 2, nbt, ws, S_SCRATCH, st);
     hipLaunchKernelGGL(k_msm_scatter, dim3((unsigned)p.hs_blocks), dim3(HS_THREADS), lds, st, dev, digits, hist, off,
