@@ -130,7 +130,7 @@ constexpr uint64_t FEW_BUCKETS = 4096;  // a wavefront per bucket leaves most of
 // cooperative forms (no idle product slots, no trees inside a task).
 constexpr uint64_t FEW_ENTRIES = 1ull << 19;
 constexpr uint64_t FIN_QUAD_BUCKETS = 16384;     // see batch_plan (finalize in quads)
-constexpr uint64_t FIN_QUAD_LANES = 1ull << 17;  // about two wavefronts per SIMD
+constexpr uint64_t FIN_QUAD_LANES = 1ull << 16;  // about one wavefront per SIMD (2^17 measured 2% slower)
 
 // ---------------------------------------------------------------- 1. digits
 // Fold s > (r-1)/2 to r - s with the sign flipped, then recode into signed
@@ -991,7 +991,7 @@ static BatchPlan batch_plan(const MsmInput* in, int njobs, int group) {
   // bucket keeps the finalize chain short
   p.fin_group = 1;
   // The finalize step is a chain of dependent additions per bucket; with few
-  // enough buckets that quads of lanes (up to about two wavefronts per SIMD)
+  // enough buckets that quads of lanes (up to about one wavefront per SIMD)
   // can share them, cooperative additions shorten the chains ~3x.
   p.fin_quad = p.quad || p.nbt <= FIN_QUAD_BUCKETS;
   if (p.fin_quad) {  // quads of about two partial sums each
