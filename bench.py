@@ -8,13 +8,17 @@ over BN254, with the proving key resident in device memory.
 
   step   = one complete proof with zkVC's circuit (CRPC + PSQ, QAP domain 2^16):
            witness and evaluation vectors, QAP quotient (3 iNTT, 3 coset NTT,
-           pointwise, coset iNTT), G1 MSMs (A, B1, L, H), G2 MSM (B), assembly.
-           Inputs X, W start in host memory (the prover's interface); the
-           proof and Y return to host memory.
+           pointwise: h on the coset), G1 MSMs (A, B1, L, H), G2 MSM (B),
+           assembly.  X and W are resident in device memory when the timed
+           region starts and Y is written there (zkvc_prove_device); the
+           256-byte proof comes back to the host.
   value  = CRPC + PSQ proofs per second.
-Timed beside it in the same run: the plain per-product circuit of the same
-matmul (8,028,160 constraints, domain 2^23), standalone G1 MSMs (points per
-second, uniform scalars), and the CPU oracle on a bounded sample.
+Timed beside it in the same run: the same proofs from host buffers (PCIe
+included) and by graph replay, the plain per-product circuit of the same
+matmul (8,028,160 constraints, domain 2^23), standalone G1 and G2 MSMs and Fr
+NTTs, a batch of 64 mixed-shape proofs, served proving at several arrival
+rates, Table II's four rows, the Spartan backend, the integer-VALU peak, and
+the CPU oracle on one whole proof.
 
 Prints one JSON line.  Only one GPU is supported (--gpus 1).
 """

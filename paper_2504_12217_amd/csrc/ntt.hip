@@ -1,4 +1,4 @@
-// Fr number-theoretic transforms for the QAP quotient (iNTT, coset NTT, coset iNTT).
+// Fr number-theoretic transforms for the QAP quotient (iNTT, coset NTT, pointwise).
 //
 // A transform of N = 2^L points runs as a sequence of in-place passes (the
 // four-step decomposition of Bailey applied recursively).  Pass j owns a
