@@ -1309,10 +1309,40 @@ std::future<void> TaskPool::run(std::function<void()> fn) {
   return f;
 }
 
+// The lane streams every proving context of a device shares.  A process has
+// few hardware queues (four by default) and a new stream takes the next one
+// in turn: with lane streams per context, the lanes of every key created
+// after the first landed on queues that the calling stream or other lanes
+// already used, and those keys proved ~40% slower (0.92 against 0.67 ms per
+// proof of [49,320]x[320,512]), their lanes serialized behind other work.
+// Created on first use and kept for the process (released by the operating
+// system at exit, never from a static destructor).  Contexts that prove
+// concurrently from several host threads order their lane work on these
+// streams; every wait is on an event recorded before it, so no cycle forms.
+namespace {
+struct SharedLanes {
+  hipStream_t lanes[ProveCtx::LANES];
+};
+const SharedLanes& shared_lanes(int device) {
+  static std::mutex mu;
+  static std::map<int, SharedLanes*>* by_dev = new std::map<int, SharedLanes*>();
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = by_dev->find(device);
+  if (it != by_dev->end()) return *it->second;
+  std::unique_ptr<SharedLanes> s(new SharedLanes());
+  for (int lane = 0; lane < ProveCtx::LANES; lane++)
+    ZK_HIP(hipStreamCreateWithFlags(&s->lanes[lane], hipStreamNonBlocking));
+  SharedLanes* p = s.release();
+  (*by_dev)[device] = p;
+  return *p;
+}
+}  // namespace
+
 ProveCtx::ProveCtx() {
   device = current_device();
   pool.reset(new TaskPool(4));
-  for (int lane = 0; lane < LANES; lane++) ZK_HIP(hipStreamCreateWithFlags(&lanes[lane], hipStreamNonBlocking));
+  const SharedLanes& sl = shared_lanes(device);
+  for (int lane = 0; lane < LANES; lane++) lanes[lane] = sl.lanes[lane];
   ZK_HIP(hipStreamCreateWithFlags(&graph_stream, hipStreamNonBlocking));
   for (ProveGen& g : gen) {
     ZK_HIP(hipEventCreateWithFlags(&g.witness_ev, hipEventDisableTiming));
@@ -1330,11 +1360,13 @@ ProveCtx::ProveCtx() {
 }
 
 ProveCtx::~ProveCtx() {
-  // wait for anything still queued on the lanes, then release them
+  // wait for anything still queued on the lanes (the shared ones stay), then
+  // release the context's own capture lanes
   for (int lane = 0; lane < LANES; lane++) {
-    if (lanes[lane]) {
-      (void)hipStreamSynchronize(lanes[lane]);
-      (void)hipStreamDestroy(lanes[lane]);
+    if (lanes[lane]) (void)hipStreamSynchronize(lanes[lane]);
+    if (cap_lanes[lane]) {
+      (void)hipStreamSynchronize(cap_lanes[lane]);
+      (void)hipStreamDestroy(cap_lanes[lane]);
     }
   }
   if (graph_stream) {
@@ -1506,7 +1538,11 @@ BatchRunPtr prove_batch_begin(ProveCtx& ctx, int g, const ProveJob* jobs_in, siz
     return run;
   }
   // the composition ran just before on this generation, so every buffer
-  // already has its size: the capture allocates nothing
+  // already has its size: the capture allocates nothing.  The lanes join the
+  // capture, so it uses the context's own lane streams (another context's
+  // eager work on the shared lanes must not end up in this graph).
+  for (int lane = 0; lane < ProveCtx::LANES; lane++)
+    if (!ctx.cap_lanes[lane]) ZK_HIP(hipStreamCreateWithFlags(&ctx.cap_lanes[lane], hipStreamNonBlocking));
   fork();
   ZK_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeRelaxed));
   hipGraph_t graph = nullptr;
@@ -1515,7 +1551,7 @@ BatchRunPtr prove_batch_begin(ProveCtx& ctx, int g, const ProveJob* jobs_in, siz
   try {
     enqueue_batch(ctx, G, R, gs, true);
     for (int lane = 0; lane < ProveCtx::LANES; lane++) {
-      ZK_HIP(hipEventRecord(G.join_ev[lane], ctx.lanes[lane]));
+      ZK_HIP(hipEventRecord(G.join_ev[lane], ctx.cap_lanes[lane]));
       ZK_HIP(hipStreamWaitEvent(gs, G.join_ev[lane], 0));
     }
   } catch (...) {
@@ -1584,8 +1620,8 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
     R.pend_g2.resize(in_g2.size());
     R.pend_h.resize(in_h.size());
   };
-  hipStream_t lane_h = ctx.lanes[ProveCtx::LANE_H], lane_g1 = ctx.lanes[ProveCtx::LANE_G1],
-              lane_g2 = ctx.lanes[ProveCtx::LANE_G2];
+  const hipStream_t* lanes = capture ? ctx.cap_lanes : ctx.lanes;
+  hipStream_t lane_h = lanes[ProveCtx::LANE_H], lane_g1 = lanes[ProveCtx::LANE_G1], lane_g2 = lanes[ProveCtx::LANE_G2];
   auto g2_lane = [&] {
     ZK_HIP(hipStreamWaitEvent(lane_g2, G.wrow_ev, 0));
     msm_enqueue_batch_g2(in_g2.data(), (int)in_g2.size(), G.lane_ws[ProveCtx::LANE_G2], lane_g2, R.pend_g2.data());

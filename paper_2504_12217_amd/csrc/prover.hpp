@@ -145,7 +145,10 @@ struct ProveCtx {
   ProveCtx& operator=(const ProveCtx&) = delete;
   int device = 0;
   bool graphs = true;  // capture and replay repeated compositions
+  // Eager lanes: the device's shared lane streams (see shared_lanes in
+  // prover.hip); a capture uses the context's own capture lanes instead.
   hipStream_t lanes[LANES] = {};
+  hipStream_t cap_lanes[LANES] = {};   // created on the first capture
   hipStream_t graph_stream = nullptr;  // captures and replays run here, ordered after the calling stream
   std::unique_ptr<TaskPool> pool;      // helper threads (at most three tasks at a time)
   ProveGen gen[GENS];
