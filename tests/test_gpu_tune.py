@@ -48,6 +48,37 @@ def test_autotune_then_results_unchanged(zk):
         assert dev_to_ints(d) == ontt.transform(synth.limbs_to_ints(x))
 
 
+def test_every_window_width_equals_dlog(zk):
+    """Each window width c = 2..15 forced through the tuning table: the signed
+    digits (read off s + K window by window, K = sum_w (2^(c-1) - 1) 2^(c w))
+    must sum the same point.  c nw exceeds 256 bits for c = 6, 7 and 9..14, so
+    the recoding's ninth word is exercised.  G2 at a few widths as well."""
+    n = (1 << 12) - 7
+    ks = synth.fr_limbs(31, synth.STREAM_MSM_BASES, n)
+    sc = synth.fr_limbs(31, synth.STREAM_MSM_SCALARS, n)
+    k_int, s_int = synth.limbs_to_ints(ks), synth.limbs_to_ints(sc)
+    dk, ds = dev_words(ks), dev_words(sc)
+    dpts = torch.zeros((n * 16,), dtype=torch.int32, device="cuda")
+    zk.fixed_base_g1(dk, n, dpts)
+    want = bn.g1_mul(bn.G1_GEN, sum(a * b for a, b in zip(k_int, s_int)) % bn.R)
+    try:
+        for c in range(2, 16):
+            zk.tune_import(f"msm_g1 12 {c}\n")
+            assert zk.msm_g1(dpts, ds, n) == want, c
+    finally:
+        zk.tune_import("msm_g1 12 0\n")
+    m = 600
+    dq = torch.zeros((m * 32,), dtype=torch.int32, device="cuda")
+    zk.fixed_base_g2(dev_words(ks[:m]), m, dq)
+    want2 = bn.g2_mul(bn.G2_GEN, sum(a * b for a, b in zip(k_int[:m], s_int[:m])) % bn.R)
+    try:
+        for c in (4, 7, 11, 14):
+            zk.tune_import(f"msm_g2 10 {c}\n")
+            assert zk.msm_g2(dq, dev_words(sc[:m]), m) == want2, c
+    finally:
+        zk.tune_import("msm_g2 10 0\n")
+
+
 def test_autotune_argument_errors(zk):
     for what, lo, hi in ((8, 8, 10), (1, 3, 10), (1, 12, 10), (1, 10, 23)):
         with pytest.raises(zk.ZkvcError) as e:
