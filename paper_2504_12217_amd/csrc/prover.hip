@@ -452,19 +452,59 @@ __global__ void k_rows_plain(WitTable T) {
 
 constexpr int RED_THREADS = 256;
 
+constexpr int RED_WAVES = RED_THREADS / 64;
+
+// Sum over a block of RED_THREADS lanes, valid in every lane: a butterfly
+// over each wavefront's lanes (cross-lane reads, no barrier; every lane ends
+// with the same canonical sum), then the wavefront sums through LDS.
 __device__ Fr block_sum(Fr x, uint32_t* sh) {
-  for (int o = RED_THREADS / 2; o >= 1; o >>= 1) {
+  for (int o = 32; o >= 1; o >>= 1) {
+    Fr y;
 #pragma unroll
-    for (int q = 0; q < NL; q++) sh[threadIdx.x * NL + q] = x.v[q];
-    __syncthreads();
-    if ((int)threadIdx.x < o) {
-      Fr y;
-#pragma unroll
-      for (int q = 0; q < NL; q++) y.v[q] = sh[(threadIdx.x + o) * NL + q];
-      x = Fr::add(x, y);
-    }
-    __syncthreads();
+    for (int q = 0; q < NL; q++) y.v[q] = (uint32_t)__shfl_xor((int)x.v[q], o, 64);
+    x = Fr::add(x, y);
   }
+  const int wid = (int)(threadIdx.x >> 6);
+  if ((threadIdx.x & 63u) == 0u) {
+#pragma unroll
+    for (int q = 0; q < NL; q++) sh[wid * NL + q] = x.v[q];
+  }
+  __syncthreads();
+  Fr t = Fr::zero();
+  for (int w = 0; w < RED_WAVES; w++) {
+    Fr y;
+#pragma unroll
+    for (int q = 0; q < NL; q++) y.v[q] = sh[w * NL + q];
+    t = Fr::add(t, y);
+  }
+  __syncthreads();  // sh is free again
+  return t;
+}
+
+// Inclusive prefix sum over a block of RED_THREADS lanes (lane order): a
+// shift-and-add scan inside each wavefront, then the sums of the wavefronts
+// before this one through LDS.
+__device__ Fr block_inclusive_scan(Fr x, uint32_t* sh) {
+  const uint32_t lane = threadIdx.x & 63u;
+  for (uint32_t o = 1; o < 64; o <<= 1) {
+    Fr y;
+#pragma unroll
+    for (int q = 0; q < NL; q++) y.v[q] = (uint32_t)__shfl_up((int)x.v[q], o, 64);
+    if (lane >= o) x = Fr::add(x, y);
+  }
+  const int wid = (int)(threadIdx.x >> 6);
+  if (lane == 63u) {
+#pragma unroll
+    for (int q = 0; q < NL; q++) sh[wid * NL + q] = x.v[q];
+  }
+  __syncthreads();
+  for (int w = 0; w < wid; w++) {
+    Fr y;
+#pragma unroll
+    for (int q = 0; q < NL; q++) y.v[q] = sh[w * NL + q];
+    x = Fr::add(x, y);
+  }
+  __syncthreads();  // sh is free again
   return x;
 }
 
@@ -509,20 +549,7 @@ __device__ void crpc_rows_body(const WitJob& J, uint32_t* sh, uint32_t* carry_sh
   for (uint32_t k0 = 0; k0 < n; k0 += RED_THREADS) {
     const uint32_t k = k0 + threadIdx.x;
     const Fr P = k < n ? Fr::load(pk + 8ull * k) : Fr::zero();
-    // Hillis-Steele inclusive scan of P over the chunk
-    Fr x = P;
-    for (int o = 1; o < RED_THREADS; o <<= 1) {
-#pragma unroll
-      for (int q = 0; q < NL; q++) sh[threadIdx.x * NL + q] = x.v[q];
-      __syncthreads();
-      if ((int)threadIdx.x >= o) {
-        Fr y;
-#pragma unroll
-        for (int q = 0; q < NL; q++) y.v[q] = sh[(threadIdx.x - o) * NL + q];
-        x = Fr::add(x, y);
-      }
-      __syncthreads();
-    }
+    const Fr x = block_inclusive_scan(P, sh);  // over the chunk
     const Fr s = Fr::add(x, carry);  // s_k
     const Fr prev = Fr::sub(s, P);   // s_(k-1)
     if (k < n) {
