@@ -148,7 +148,87 @@ struct HF {
       }
     return r;
   }
-  static HF inv(const HF& a) {  // a^(m-2)
+  // 1/a (0 for a = 0) by the binary extended Euclidean algorithm on the
+  // stored integer A = a R (R = 2^256): it yields A^-1 = a^-1 R^-1, and two
+  // products by R^2 give a^-1 R.  Runs of t zero bits are removed at once
+  // (x / 2^t mod m as (x + k m) / 2^t with k = x (-m^-1) mod 2^t).
+  static HF inv(const HF& a) {
+    if (a.is_zero()) return zero();
+    uint64_t u[4], v[4], x1[4] = {1, 0, 0, 0}, x2[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 4; k++) {
+      u[k] = a.l[k];
+      v[k] = M::P64[k];
+    }
+    auto is_one = [](const uint64_t* w) { return w[0] == 1 && (w[1] | w[2] | w[3]) == 0; };
+    auto shr = [](uint64_t* w, int t) {  // 0 < t < 64
+      for (int k = 0; k < 3; k++) w[k] = (w[k] >> t) | (w[k + 1] << (64 - t));
+      w[3] >>= t;
+    };
+    // x / 2^t mod m for x in [0, m), 0 < t < 64: x + k m < 2^(256 + t) is exact in five words
+    auto div_pow2 = [](uint64_t* x, int t) {
+      const uint64_t k = (x[0] * M::PINV64) & ((1ull << t) - 1ull);
+      u128 c = 0;
+      for (int i = 0; i < 4; i++) {
+        c += (u128)k * M::P64[i] + x[i];
+        x[i] = (uint64_t)c;
+        c >>= 64;
+      }
+      const uint64_t hi = (uint64_t)c;
+      for (int i = 0; i < 3; i++) x[i] = (x[i] >> t) | (x[i + 1] << (64 - t));
+      x[3] = (x[3] >> t) | (hi << (64 - t));
+    };
+    // strip the factors of two of w (nonzero), dividing x by the same power mod m
+    auto strip = [&](uint64_t* w, uint64_t* x) {
+      while ((w[0] & 1) == 0) {
+        const int t = w[0] ? __builtin_ctzll(w[0]) : 63;
+        shr(w, t);
+        div_pow2(x, t);
+      }
+    };
+    auto geq = [](const uint64_t* p, const uint64_t* q) {
+      for (int k = 3; k >= 0; k--)
+        if (p[k] != q[k]) return p[k] > q[k];
+      return true;
+    };
+    auto sub_in = [](uint64_t* p, const uint64_t* q) {  // p -= q, p >= q
+      u128 borrow = 0;
+      for (int k = 0; k < 4; k++) {
+        const u128 t = (u128)p[k] - q[k] - borrow;
+        p[k] = (uint64_t)t;
+        borrow = (t >> 64) & 1;
+      }
+    };
+    auto sub_mod_in = [&](uint64_t* p, const uint64_t* q) {  // p = p - q mod m, both in [0, m)
+      if (!geq(p, q)) {
+        u128 c = 0;
+        for (int k = 0; k < 4; k++) {  // p + m (below 2^255)
+          c += (u128)p[k] + M::P64[k];
+          p[k] = (uint64_t)c;
+          c >>= 64;
+        }
+      }
+      sub_in(p, q);
+    };
+    // invariants: x1 A = u, x2 A = v (mod m); u, v > 0 with gcd(u, v) = 1
+    while (!is_one(u) && !is_one(v)) {
+      strip(u, x1);
+      strip(v, x2);
+      if (is_one(u) || is_one(v)) break;
+      if (geq(u, v)) {
+        sub_in(u, v);
+        sub_mod_in(x1, x2);
+      } else {
+        sub_in(v, u);
+        sub_mod_in(x2, x1);
+      }
+    }
+    HF r;
+    for (int k = 0; k < 4; k++) r.l[k] = is_one(u) ? x1[k] : x2[k];
+    const HF r2{{M::R2_64[0], M::R2_64[1], M::R2_64[2], M::R2_64[3]}};
+    return mul(mul(r, r2), r2);
+  }
+  // a^(m-2), the inverse by Fermat's little theorem
+  static HF inv_fermat(const HF& a) {
     uint64_t e[4] = {M::P64[0] - 2, M::P64[1], M::P64[2], M::P64[3]};
     return pow(a, e);
   }

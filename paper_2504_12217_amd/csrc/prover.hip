@@ -1808,6 +1808,7 @@ void prove_batch_finish(ProveCtx& ctx, BatchRun& R) {
       const host::G1J B1 = host::G1J::add(host::G1J::add(pk->beta1, msmB1), pk->delta1_table.mul(sw));
       o.sA_rB1 = host::G1J::add(host::G1J::mul2(o.A, sw, B1, rw), host::G1J::neg(pk->delta1_table.mul(rsw)));
       o.L = msmL;
+      g1_to_abi(o.A, &J.out->A);  // A is final here (its inversion stays off the H lane's tail)
     });
   });
   auto f_g2 = ctx.pool->run([&] {
@@ -1818,6 +1819,7 @@ void prove_batch_finish(ProveCtx& ctx, BatchRun& R) {
       host::G2J msmB2 = host::G2J::inf();
       for (size_t q : g2_of[j]) msmB2 = host::G2J::add(msmB2, msm_finish_g2(pend_g2[q]));
       Bp[j] = host::G2J::add(host::G2J::add(jobs[j].pk->beta2, msmB2), jobs[j].pk->delta2_table.mul(sw));
+      g2_to_abi(Bp[j], &jobs[j].out->B);
     });
   });
   auto f_h = ctx.pool->run([&] {
@@ -1844,9 +1846,7 @@ void prove_batch_finish(ProveCtx& ctx, BatchRun& R) {
     const Layout& L = jobs[j].pk->L;
     // C = sum_aux a_i L_i + h(tau) t(tau)/delta + s A + r B1 - r s delta
     const host::G1J C = host::G1J::add(host::G1J::add(g1p[j].L, Hp[j]), g1p[j].sA_rB1);
-    g1_to_abi(g1p[j].A, &jobs[j].out->A);
-    g2_to_abi(Bp[j], &jobs[j].out->B);
-    g1_to_abi(C, &jobs[j].out->C);
+    g1_to_abi(C, &jobs[j].out->C);  // A and B were written by their lanes' tasks
     if (!jobs[j].device_io) std::memcpy(jobs[j].Y, slots[j].yh, (size_t)L.a * L.b * 4);
   }
   const auto host_t1 = std::chrono::steady_clock::now();
