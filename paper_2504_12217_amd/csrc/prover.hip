@@ -1785,15 +1785,30 @@ void prove_batch_finish(ProveCtx& ctx, BatchRun& R) {
   std::vector<std::vector<size_t>> g1_of(nj), g2_of(nj);
   for (size_t q = 0; q < own_g1.size(); q++) g1_of[own_g1[q]].push_back(q);
   for (size_t q = 0; q < own_g2.size(); q++) g2_of[own_g2[q]].push_back(q);
+  // What needs only r and s (the fixed-base multiples of delta) is done while
+  // the lanes run; a single proof also splits s A + r B1 over two threads.
+  struct Fixed {
+    host::G1J rd1, sd1, rsd1;
+    host::G2J sd2;
+  };
+  std::vector<Fixed> fx(nj);
   auto f_g1 = ctx.pool->run([&] {
+    parallel_for(nj, nthr, [&](size_t j) {
+      uint64_t rw[4], sw[4], rsw[4];
+      jobs[j].r.to_u64(rw);
+      jobs[j].s.to_u64(sw);
+      host::HFr::mul(jobs[j].r, jobs[j].s).to_u64(rsw);
+      fx[j].rd1 = jobs[j].pk->delta1_table.mul(rw);
+      fx[j].sd1 = jobs[j].pk->delta1_table.mul(sw);
+      fx[j].rsd1 = jobs[j].pk->delta1_table.mul(rsw);
+    });
     ZK_HIP(hipEventSynchronize(G.done_ev[ProveCtx::LANE_G1]));
     parallel_for(nj, nthr, [&](size_t j) {
       const ProveJob& J = jobs[j];
       const zkvc_pk* pk = J.pk;
-      uint64_t rw[4], sw[4], rsw[4];
+      uint64_t rw[4], sw[4];
       J.r.to_u64(rw);
       J.s.to_u64(sw);
-      host::HFr::mul(J.r, J.s).to_u64(rsw);
       host::G1J msmA = host::G1J::inf(), msmB1 = host::G1J::inf(), msmL = host::G1J::inf();
       for (size_t q : g1_of[j]) {
         const host::G1J v = msm_finish_g1(pend_g1[q]);
@@ -1804,44 +1819,59 @@ void prove_batch_finish(ProveCtx& ctx, BatchRun& R) {
         }
       }
       G1Part& o = g1p[j];
-      o.A = host::G1J::add(host::G1J::add(pk->alpha1, msmA), pk->delta1_table.mul(rw));
-      const host::G1J B1 = host::G1J::add(host::G1J::add(pk->beta1, msmB1), pk->delta1_table.mul(sw));
-      o.sA_rB1 = host::G1J::add(host::G1J::mul2(o.A, sw, B1, rw), host::G1J::neg(pk->delta1_table.mul(rsw)));
+      o.A = host::G1J::add(host::G1J::add(pk->alpha1, msmA), fx[j].rd1);
+      const host::G1J B1 = host::G1J::add(host::G1J::add(pk->beta1, msmB1), fx[j].sd1);
+      host::G1J sArB1;
+      if (nj == 1) {  // s A on a second thread, r B1 here
+        host::G1J sA;
+        std::future<void> fa = ctx.pool->run([&] { sA = host::G1J::mul(o.A, sw); });
+        const host::G1J rB1 = host::G1J::mul(B1, rw);
+        fa.get();
+        sArB1 = host::G1J::add(sA, rB1);
+      } else {
+        sArB1 = host::G1J::mul2(o.A, sw, B1, rw);
+      }
+      o.sA_rB1 = host::G1J::add(sArB1, host::G1J::neg(fx[j].rsd1));
       o.L = msmL;
       g1_to_abi(o.A, &J.out->A);  // A is final here (its inversion stays off the H lane's tail)
     });
   });
   auto f_g2 = ctx.pool->run([&] {
-    ZK_HIP(hipEventSynchronize(G.done_ev[ProveCtx::LANE_G2]));
     parallel_for(nj, nthr / 2 + 1, [&](size_t j) {
       uint64_t sw[4];
       jobs[j].s.to_u64(sw);
+      fx[j].sd2 = jobs[j].pk->delta2_table.mul(sw);
+    });
+    ZK_HIP(hipEventSynchronize(G.done_ev[ProveCtx::LANE_G2]));
+    parallel_for(nj, nthr / 2 + 1, [&](size_t j) {
       host::G2J msmB2 = host::G2J::inf();
       for (size_t q : g2_of[j]) msmB2 = host::G2J::add(msmB2, msm_finish_g2(pend_g2[q]));
-      Bp[j] = host::G2J::add(host::G2J::add(jobs[j].pk->beta2, msmB2), jobs[j].pk->delta2_table.mul(sw));
+      Bp[j] = host::G2J::add(host::G2J::add(jobs[j].pk->beta2, msmB2), fx[j].sd2);
       g2_to_abi(Bp[j], &jobs[j].out->B);
     });
-  });
-  auto f_h = ctx.pool->run([&] {
-    ZK_HIP(hipEventSynchronize(G.done_ev[ProveCtx::LANE_H]));
-    parallel_for(own_h.size(), nthr / 2 + 1, [&](size_t q) { Hp[own_h[q]] = msm_finish_g1(pend_h[q]); });
   });
   // the pool's futures do not wait when destroyed: wait for the lane tasks
   // (they use this frame) before leaving it, also when an error unwinds it
   struct WaitAll {
-    std::future<void>* f[3];
+    std::future<void>* f[2];
     ~WaitAll() {
       for (auto* x : f)
         if (x->valid()) x->wait();
     }
-  } wait_all{{&f_g1, &f_g2, &f_h}};
+  } wait_all{{&f_g1, &f_g2}};
   ZK_HIP(hipEventSynchronize(G.ev[2]));  // witnesses (the row flag) and quotients
   if (*R.flag_host) throw Error(ZKVC_EDEVICE, "internal error: a witness does not satisfy its circuit");
-  for (int lane = 0; lane < ProveCtx::LANES; lane++) ZK_HIP(hipEventSynchronize(G.done_ev[lane]));
+  // The H lane ends the proof: this thread polls for it (no sleeping thread
+  // to wake at the end of the device work) and combines its planes.
+  for (;;) {
+    const hipError_t e = hipEventQuery(G.done_ev[ProveCtx::LANE_H]);
+    if (e == hipSuccess) break;
+    if (e != hipErrorNotReady) ZK_HIP(e);
+  }
   const auto asm_t0 = std::chrono::steady_clock::now();
+  parallel_for(own_h.size(), nthr / 2 + 1, [&](size_t q) { Hp[own_h[q]] = msm_finish_g1(pend_h[q]); });
   f_g1.get();
   f_g2.get();
-  f_h.get();
   for (size_t j = 0; j < nj; j++) {
     const Layout& L = jobs[j].pk->L;
     // C = sum_aux a_i L_i + h(tau) t(tau)/delta + s A + r B1 - r s delta
