@@ -71,33 +71,28 @@ struct HF {
   }
   static HF neg(const HF& a) { return sub(zero(), a); }
   static HF dbl(const HF& a) { return add(a, a); }
-  // CIOS Montgomery multiplication (Koc, Acar, Kaliski 1996)
+  // CIOS Montgomery multiplication (Koc, Acar, Kaliski 1996).  The modulus's
+  // top word is below 2^63 - 1, so each row's two carry chains end within
+  // four words (no fifth or sixth accumulator word) and the result is < 2m.
+  static_assert(M::P64[3] < 0x7fffffffffffffffull, "modulus too wide for the short carry chain");
   static HF mul(const HF& a, const HF& b) {
-    uint64_t t[6] = {0, 0, 0, 0, 0, 0};
+    uint64_t t[4] = {0, 0, 0, 0};
     for (int i = 0; i < 4; i++) {
-      u128 c = 0;
-      for (int j = 0; j < 4; j++) {
-        c += (u128)a.l[j] * b.l[i] + t[j];
-        t[j] = (uint64_t)c;
-        c >>= 64;
-      }
-      c += t[4];
-      t[4] = (uint64_t)c;
-      t[5] = (uint64_t)(c >> 64);
-      const uint64_t m = t[0] * M::PINV64;
-      c = (u128)m * M::P64[0] + t[0];
-      c >>= 64;
+      u128 A = (u128)a.l[0] * b.l[i] + t[0];
+      const uint64_t m = (uint64_t)A * M::PINV64;
+      u128 C = ((u128)m * M::P64[0] + (uint64_t)A) >> 64;
+      A >>= 64;
       for (int j = 1; j < 4; j++) {
-        c += (u128)m * M::P64[j] + t[j];
-        t[j - 1] = (uint64_t)c;
-        c >>= 64;
+        A += (u128)a.l[j] * b.l[i] + t[j];
+        C += (u128)m * M::P64[j] + (uint64_t)A;
+        A >>= 64;
+        t[j - 1] = (uint64_t)C;
+        C >>= 64;
       }
-      c += t[4];
-      t[3] = (uint64_t)c;
-      t[4] = t[5] + (uint64_t)(c >> 64);
+      t[3] = (uint64_t)(A + C);
     }
     HF r{{t[0], t[1], t[2], t[3]}};
-    if (t[4] || geq_mod(r.l)) sub_mod_inplace(r.l);
+    if (geq_mod(r.l)) sub_mod_inplace(r.l);
     return r;
   }
   static HF sqr(const HF& a) { return mul(a, a); }
@@ -289,6 +284,41 @@ struct HFq2 {
   }
 };
 
+// Width-5 non-adjacent form of a 256-bit k (little-endian words): digits
+// d[i] in {0, +-1, +-3, ..., +-15}, k = sum_i d[i] 2^i, every nonzero digit
+// followed by at least four zeros.  Returns the digit count (at most 257).
+inline int wnaf5(const uint64_t k_in[4], int8_t d[260]) {
+  uint64_t k[5] = {k_in[0], k_in[1], k_in[2], k_in[3], 0};
+  int n = 0;
+  while (k[0] | k[1] | k[2] | k[3] | k[4]) {
+    int v = 0;
+    if (k[0] & 1) {
+      v = (int)(k[0] & 31);
+      if (v >= 16) v -= 32;
+      // k -= v, leaving k divisible by 32
+      if (v > 0) {
+        u128 t = (u128)k[0] - (uint64_t)v;
+        k[0] = (uint64_t)t;
+        for (int w = 1; w < 5 && (t >> 64); w++) {
+          t = (u128)k[w] - 1;
+          k[w] = (uint64_t)t;
+        }
+      } else {
+        u128 t = (u128)k[0] + (uint64_t)(-v);
+        k[0] = (uint64_t)t;
+        for (int w = 1; w < 5 && (t >> 64); w++) {
+          t = (u128)k[w] + 1;
+          k[w] = (uint64_t)t;
+        }
+      }
+    }
+    d[n++] = (int8_t)v;
+    for (int w = 0; w < 4; w++) k[w] = (k[w] >> 1) | (k[w + 1] << 63);
+    k[4] >>= 1;
+  }
+  return n;
+}
+
 // ---------------------------------------------------------------- Jacobian points
 // Generic over the coordinate field (HFq for G1, HFq2 for G2); a = 0.
 template <class F>
@@ -346,23 +376,6 @@ struct Jac {
     F Y3 = F::sub(F::mul(Rr, F::sub(V, X3)), F::mul(p.Y, HHH));
     return {X3, Y3, F::mul(p.Z, H)};
   }
-  // a P + b Q sharing one doubling chain (Straus), 4-bit windows
-  static Jac mul2(const Jac& p, const uint64_t a[4], const Jac& q, const uint64_t b[4]) {
-    Jac tp[16], tq[16];
-    tp[0] = tq[0] = inf();
-    for (int i = 1; i < 16; i++) {
-      tp[i] = add(tp[i - 1], p);
-      tq[i] = add(tq[i - 1], q);
-    }
-    Jac acc = inf();
-    for (int w = 63; w >= 0; w--) {
-      for (int d = 0; d < 4; d++) acc = dbl(acc);
-      const int na = (int)((a[w / 16] >> (4 * (w % 16))) & 15), nb = (int)((b[w / 16] >> (4 * (w % 16))) & 15);
-      if (na) acc = add(acc, tp[na]);
-      if (nb) acc = add(acc, tq[nb]);
-    }
-    return acc;
-  }
   // scalar given as little-endian 64-bit words (4-bit fixed window)
   static Jac mul(const Jac& p, const uint64_t k[4]) {
     Jac table[16];
@@ -373,6 +386,32 @@ struct Jac {
       for (int d = 0; d < 4; d++) acc = dbl(acc);
       const int nib = (int)((k[w / 16] >> (4 * (w % 16))) & 15);
       if (nib) acc = add(acc, table[nib]);
+    }
+    return acc;
+  }
+  // t[i] = (2i + 1) P for i < 8
+  static void odd_multiples(const Jac& p, Jac t[8]) {
+    const Jac p2 = dbl(p);
+    t[0] = p;
+    for (int i = 1; i < 8; i++) t[i] = add(t[i - 1], p2);
+  }
+  // sum_j (+-k_j) P_j for n terms sharing one doubling chain (Straus), each
+  // scalar in width-5 NAF over its odd multiples tab[j]; neg[j] negates term j
+  static Jac naf_multi(int n, const Jac (*tab)[8], const uint64_t (*k)[4], const bool* neg) {
+    int8_t d[4][260];
+    int len[4], top = 0;
+    for (int j = 0; j < n; j++) {
+      len[j] = wnaf5(k[j], d[j]);
+      top = len[j] > top ? len[j] : top;
+    }
+    Jac acc = inf();
+    for (int i = top - 1; i >= 0; i--) {
+      acc = dbl(acc);
+      for (int j = 0; j < n; j++) {
+        const int v = i < len[j] ? (neg[j] ? -d[j][i] : d[j][i]) : 0;
+        if (v > 0) acc = add(acc, tab[j][v >> 1]);
+        if (v < 0) acc = add(acc, Jac::neg(tab[j][(-v) >> 1]));
+      }
     }
     return acc;
   }
@@ -392,6 +431,112 @@ struct Jac {
 
 using G1J = Jac<HFq>;
 using G2J = Jac<HFq2>;
+
+// ---------------------------------------------------------------- GLV on G1
+// G1 has the endomorphism phi(x, y) = (beta x, y) with beta a primitive cube
+// root of unity in Fq; on the order-r group phi is multiplication by a cube
+// root of unity lambda in Fr (Gallant, Lambert and Vanstone, CRYPTO 2001).
+// A scalar splits as k = k1 + k2 lambda (mod r) with |k1|, |k2| < 2^128, so
+// k P = k1 P + k2 phi(P) takes half the doublings, and the two halves can run
+// on two threads.
+struct GlvSplit {
+  uint64_t mag[2][4];  // |k1|, |k2|
+  bool neg[2];         // k1 < 0, k2 < 0
+};
+
+namespace glv_detail {
+// low 4 and high 4 words of the 512-bit product a b
+inline void mul_256(const uint64_t a[4], const uint64_t b[4], uint64_t lo[4], uint64_t hi[4]) {
+  uint64_t t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int i = 0; i < 4; i++) {
+    u128 c = 0;
+    for (int j = 0; j < 4; j++) {
+      c += (u128)a[i] * b[j] + t[i + j];
+      t[i + j] = (uint64_t)c;
+      c >>= 64;
+    }
+    t[i + 4] = (uint64_t)c;
+  }
+  for (int w = 0; w < 4; w++) {
+    lo[w] = t[w];
+    hi[w] = t[w + 4];
+  }
+}
+inline void sub_256(uint64_t a[4], const uint64_t b[4]) {  // a -= b mod 2^256
+  u128 borrow = 0;
+  for (int w = 0; w < 4; w++) {
+    const u128 t = (u128)a[w] - b[w] - borrow;
+    a[w] = (uint64_t)t;
+    borrow = (t >> 64) & 1;
+  }
+}
+// two's complement value of a (mod 2^256) -> sign and magnitude
+inline bool to_sign_mag(uint64_t a[4]) {
+  if (!(a[3] >> 63)) return false;
+  uint64_t m[4] = {0, 0, 0, 0};
+  sub_256(m, a);
+  for (int w = 0; w < 4; w++) a[w] = m[w];
+  return true;
+}
+}  // namespace glv_detail
+
+// k < r (little-endian words).  With the lattice basis v1 = (a1, -b1'),
+// v2 = (a2, b2) of {(a, b): a + b lambda = 0 mod r}: c1 = floor(k g1 / 2^256),
+// c2 = floor(k g2 / 2^256) approximate k b2 / r and k b1' / r, and
+// (k1, k2) = (k, 0) - c1 v1 - c2 v2 lies in the lattice's coset of (k, 0),
+// hence k1 + k2 lambda = k (mod r), with |k1| <= a1 + a2 and |k2| <= b1' + b2
+// since both floors are off by less than one.
+inline GlvSplit glv_split(const uint64_t k[4]) {
+  using namespace glv_detail;
+  uint64_t lo[4], c1[4], c2[4];
+  mul_256(k, G1Glv::G1C, lo, c1);
+  mul_256(k, G1Glv::G2C, lo, c2);
+  GlvSplit s;
+  uint64_t* k1 = s.mag[0];
+  uint64_t* k2 = s.mag[1];
+  for (int w = 0; w < 4; w++) k1[w] = k[w];
+  uint64_t t[4], hi[4];
+  mul_256(c1, G1Glv::A1, t, hi);
+  sub_256(k1, t);
+  mul_256(c2, G1Glv::A2, t, hi);
+  sub_256(k1, t);
+  mul_256(c1, G1Glv::B1ABS, k2, hi);
+  mul_256(c2, G1Glv::B2, t, hi);
+  sub_256(k2, t);
+  s.neg[0] = to_sign_mag(k1);
+  s.neg[1] = to_sign_mag(k2);
+  return s;
+}
+
+inline G1J glv_phi(const G1J& p) {
+  static const HFq beta = HFq::from_u64(G1Glv::BETA);
+  return {HFq::mul(p.X, beta), p.Y, p.Z};
+}
+
+// One half of k P: half 0 is k1 P, half 1 is k2 phi(P).
+inline G1J glv_half(const G1J& p, const GlvSplit& s, int half) {
+  G1J tab[1][8];
+  G1J::odd_multiples(half ? glv_phi(p) : p, tab[0]);
+  return G1J::naf_multi(1, tab, &s.mag[half], &s.neg[half]);
+}
+
+// a P + b Q over one doubling chain of ~128 steps (four half-scalars)
+inline G1J glv_mul2(const G1J& p, const uint64_t a[4], const G1J& q, const uint64_t b[4]) {
+  const GlvSplit sa = glv_split(a), sb = glv_split(b);
+  G1J tab[4][8];
+  G1J::odd_multiples(p, tab[0]);
+  G1J::odd_multiples(q, tab[2]);
+  for (int i = 0; i < 8; i++) {
+    tab[1][i] = glv_phi(tab[0][i]);
+    tab[3][i] = glv_phi(tab[2][i]);
+  }
+  const uint64_t k[4][4] = {{sa.mag[0][0], sa.mag[0][1], sa.mag[0][2], sa.mag[0][3]},
+                            {sa.mag[1][0], sa.mag[1][1], sa.mag[1][2], sa.mag[1][3]},
+                            {sb.mag[0][0], sb.mag[0][1], sb.mag[0][2], sb.mag[0][3]},
+                            {sb.mag[1][0], sb.mag[1][1], sb.mag[1][2], sb.mag[1][3]}};
+  const bool neg[4] = {sa.neg[0], sa.neg[1], sb.neg[0], sb.neg[1]};
+  return G1J::naf_multi(4, tab, k, neg);
+}
 
 // XYZZ (x = X/ZZ, y = Y/ZZZ, ZZ^3 = ZZZ^2) -> Jacobian without an inversion.
 // Fixed-base table: entry [w][d] = d 2^(8w) P in affine form, for w < 32, d < 256;

@@ -1772,8 +1772,9 @@ void prove_batch_finish(ProveCtx& ctx, BatchRun& R) {
   const std::vector<MsmPending> &pend_g1 = R.pend_g1, &pend_g2 = R.pend_g2, &pend_h = R.pend_h;
   // ---- host side, per lane as each lane completes: the plane sums by
   // Horner's rule, then everything that lane's results allow.  The G1 lane
-  // yields A, B1 and s A + r B1 - r s delta (one shared doubling chain, off the
-  // critical path); the G2 lane yields B; the H lane only its sums.
+  // yields A, B1 and s A + r B1 - r s delta (by the G1 endomorphism: half-length
+  // scalars, one shared doubling chain per proof of a batch, four threads for a
+  // single proof); the G2 lane yields B; the H lane only its sums.
   const size_t nthr = host_threads();
   struct G1Part {
     host::G1J A, L, sA_rB1;
@@ -1822,14 +1823,15 @@ void prove_batch_finish(ProveCtx& ctx, BatchRun& R) {
       o.A = host::G1J::add(host::G1J::add(pk->alpha1, msmA), fx[j].rd1);
       const host::G1J B1 = host::G1J::add(host::G1J::add(pk->beta1, msmB1), fx[j].sd1);
       host::G1J sArB1;
-      if (nj == 1) {  // s A on a second thread, r B1 here
-        host::G1J sA;
-        std::future<void> fa = ctx.pool->run([&] { sA = host::G1J::mul(o.A, sw); });
-        const host::G1J rB1 = host::G1J::mul(B1, rw);
-        fa.get();
-        sArB1 = host::G1J::add(sA, rB1);
+      if (nj == 1) {  // the four GLV halves of s A and r B1 on four threads
+        const host::GlvSplit ss = host::glv_split(sw), rs = host::glv_split(rw);
+        host::G1J part[4];
+        parallel_for(4, 4, [&](size_t h) {
+          part[h] = h < 2 ? host::glv_half(o.A, ss, (int)h) : host::glv_half(B1, rs, (int)h - 2);
+        });
+        sArB1 = host::G1J::add(host::G1J::add(part[0], part[1]), host::G1J::add(part[2], part[3]));
       } else {
-        sArB1 = host::G1J::mul2(o.A, sw, B1, rw);
+        sArB1 = host::glv_mul2(o.A, sw, B1, rw);
       }
       o.sA_rB1 = host::G1J::add(sArB1, host::G1J::neg(fx[j].rsd1));
       o.L = msmL;
