@@ -1620,7 +1620,12 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
   R.slots = enqueue_witness_batch(jobs, nj, G, st, &ycopy, &R.flag_host);
   std::vector<Slot>& slots = R.slots;
   record_ext(G.ev[1], st, capture);
-  ZK_HIP(hipEventRecord(G.witness_ev, st));
+  // Each event record on the stream holds its next kernel back by a few
+  // microseconds, so eager lanes wait on the stage-timing event itself; under
+  // capture the timing events are graph nodes and a plain record carries the
+  // dependency.
+  if (capture) ZK_HIP(hipEventRecord(G.witness_ev, st));
+  const hipEvent_t wit_ev = capture ? G.witness_ev : G.ev[1];
   // ---- MSM jobs of every proof, by lane.  Those that need only the
   // assignment run from the end of the witness on, overlapping the quotient:
   // one pipeline for all G1 queries A, B1, L and one for B2 in G2; the H MSMs
@@ -1656,7 +1661,7 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
     record_ext(G.lane_t[ProveCtx::LANE_G2], lane_g2, capture);
   };
   auto g1_lane = [&] {
-    ZK_HIP(hipStreamWaitEvent(lane_g1, G.witness_ev, 0));
+    ZK_HIP(hipStreamWaitEvent(lane_g1, wit_ev, 0));
     msm_enqueue_batch_g1(in_g1.data(), (int)in_g1.size(), G.lane_ws[ProveCtx::LANE_G1], lane_g1, R.pend_g1.data());
     // Y of host-buffer jobs (final since the witness event) at the end of this lane
     if (ycopy.bytes) ZK_HIP(hipMemcpyAsync(ycopy.dst, ycopy.src, ycopy.bytes, hipMemcpyDeviceToHost, lane_g1));
@@ -1735,12 +1740,12 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
       gi++;
     }
     record_ext(G.ev[2], st, capture);
-    ZK_HIP(hipEventRecord(G.quotient_ev, st));
+    if (capture) ZK_HIP(hipEventRecord(G.quotient_ev, st));
 
     // ---- the H lane after the quotients
     if (!capture) lists.get();  // rethrows a failure to build the lists
     const hipStream_t h_st = R.h_on_main ? st : lane_h;
-    if (!R.h_on_main) ZK_HIP(hipStreamWaitEvent(lane_h, G.quotient_ev, 0));
+    if (!R.h_on_main) ZK_HIP(hipStreamWaitEvent(lane_h, capture ? G.quotient_ev : G.ev[2], 0));
     msm_enqueue_batch_g1(in_h.data(), (int)in_h.size(), G.lane_ws[ProveCtx::LANE_H], h_st, R.pend_h.data(),
                          H_LANE_PRIO);
     record_ext(G.done_ev[ProveCtx::LANE_H], h_st, capture);
