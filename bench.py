@@ -111,7 +111,7 @@ def roofline(stats, workload=None, measured=None):
            "traffic": None if traffic is None else round(traffic),
            "kernel": name, "launches": launches, "avg_launch_ms": round(avg_ms, 4),
            "work_units_per_launch": work / launches,
-           "timing": "HIP events around each launch on its stream (includes waiting behind other streams)"}
+           "timing": "HIP events bound to each launch on its stream (hipExtLaunchKernel: the kernel's own start and end)"}
     if measured:
         out["measured_peak"] = round(measured / 1e12, 3)
         out["frac_vs_measured_peak"] = round(achieved * 1e12 / measured, 4)

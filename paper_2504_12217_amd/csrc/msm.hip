@@ -1131,12 +1131,14 @@ void msm_enqueue_batch(const MsmInput* in, int njobs, Workspace& ws, hipStream_t
                      p.large, p.wg_entries, p.fin_max, meta + 8, th_tasks, wg_tasks, heavy);
   ZK_HIP(hipGetLastError());
   {
-    ProfScope ps(g1 ? "msm_acc_points_g1" : "msm_acc_points_g2", st, -1.0);
+    ProfScope ps(g1 ? "msm_acc_points_g1" : "msm_acc_points_g2", st, -1.0, true);
+    hipEvent_t e0, e1;
+    ps.bind_events(&e0, &e1);
     // capped grids with stride loops: the task counts are only known on the device
     const unsigned th_blocks = (unsigned)std::min<uint64_t>(cdiv(p.max_th_tasks, 64), 65536);
     const unsigned wg_blocks = (unsigned)std::min<uint64_t>(p.max_wg_tasks, 4096);
-    hipLaunchKernelGGL(k_msm_acc<F>, dim3(th_blocks + wg_blocks), dim3(64), 0, st, dev, th_tasks, wg_tasks,
-                       meta + 8, th_blocks, sorted, part, p.quad ? 1 : 0, meta + 3, ps.work_word());
+    launch_ev(e0, e1, k_msm_acc<F>, dim3(th_blocks + wg_blocks), dim3(64), 0, st, dev, th_tasks, wg_tasks,
+              meta + 8, th_blocks, sorted, part, p.quad ? 1 : 0, meta + 3, ps.work_word());
     ZK_HIP(hipGetLastError());
   }
   {

@@ -640,7 +640,8 @@ void ntt_launch(uint32_t* data, int log_n, bool dit, bool inverse, const NttFuse
   ntt_launch_batch(&data, 1, log_n, dit, inverse, fuse, st);
 }
 
-void qap_quotient_launch(uint32_t* const* abc, uint32_t* const* dev_table, int nproofs, int log_n, hipStream_t st) {
+void qap_quotient_launch(uint32_t* const* abc, uint32_t* const* dev_table, int nproofs, int log_n, hipStream_t st,
+                         hipEvent_t done_ev) {
   ZK_REQUIRE(log_n >= 2 && log_n <= MAX_LOG, "quotient domain out of range");
   ZK_REQUIRE(nproofs >= 1 && 3 * nproofs <= 65535 && (dev_table || nproofs == 1), "quotient batch out of range");
   const NttTables& T = ntt_tables(current_device());
@@ -684,12 +685,15 @@ void qap_quotient_launch(uint32_t* const* abc, uint32_t* const* dev_table, int n
     const int a = TOP_MAX_K - fp.k, b = pl.log_g(0);
     fp.log_g = a < b ? a : b;
     const uint32_t E = 1u << (fp.k + fp.log_g);
-    ProfScope ps("ntt_fused_top", st, (double)nproofs * (double)(1ull << L) * (1.5 * fp.k + 1.0));
+    ProfScope ps("ntt_fused_top", st, (double)nproofs * (double)(1ull << L) * (1.5 * fp.k + 1.0), true);
+    hipEvent_t e0, e1;
+    const bool timed = ps.bind_events(&e0, &e1);
     // one butterfly of each of the three regions per thread and stage
     const uint32_t threads = 3 * E / 2 < 64 ? 64 : (3 * E / 2 > NTT_THREADS ? NTT_THREADS : 3 * E / 2);
-    hipLaunchKernelGGL(k_ntt_fused_top, dim3(1u << (L - fp.k - fp.log_g), nproofs), dim3(threads),
-                       (size_t)3 * E * NL * 4, st, fp, T);
+    launch_ev(e0, timed ? e1 : done_ev, k_ntt_fused_top, dim3(1u << (L - fp.k - fp.log_g), nproofs), dim3(threads),
+              (uint32_t)(3 * E * NL * 4), st, fp, T);
     ZK_HIP(hipGetLastError());
+    if (timed && done_ev) ZK_HIP(hipEventRecord(done_ev, st));
   }
 }
 

@@ -73,7 +73,10 @@ void ntt_launch_batch(uint32_t* const* data, int nvec, int log_n, bool dit, bool
 // proofs, a device table of 3 nproofs entries: (A, B, C) per proof.  Same
 // arithmetic as the chain iNTT / coset NTT / pointwise with ntt_launch_*,
 // with the bottom and top passes of neighbouring transforms fused.
-void qap_quotient_launch(uint32_t* const* abc, uint32_t* const* dev_table, int nproofs, int log_n, hipStream_t st);
+// done_ev, when not null, is bound to the last kernel's dispatch (it completes
+// with it; eager streams only).
+void qap_quotient_launch(uint32_t* const* abc, uint32_t* const* dev_table, int nproofs, int log_n, hipStream_t st,
+                         hipEvent_t done_ev = nullptr);
 
 // In-place bit-reversal permutation of 2^log_n elements.
 void bitrev_launch(uint32_t* data, int log_n, hipStream_t st);

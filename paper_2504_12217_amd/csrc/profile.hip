@@ -111,7 +111,7 @@ void release_graph_slots(std::vector<int>& slots) {
 
 bool profiling_enabled() { return g_on.load(std::memory_order_relaxed); }
 
-ProfScope::ProfScope(const char* name, hipStream_t st, double work) : st_(st) {
+ProfScope::ProfScope(const char* name, hipStream_t st, double work, bool bind) : st_(st) {
   if (!profiling_enabled()) return;
   const char* sel = g_select.load(std::memory_order_acquire);
   if (sel && !selected(sel, name)) return;
@@ -141,8 +141,21 @@ ProfScope::ProfScope(const char* name, hipStream_t st, double work) : st_(st) {
   g_recs[k].work_dev = false;
   g_recs[k].fixed = false;
   g_st[k] = st;
-  if (hipEventRecord(g_ev[2 * k], st) != hipSuccess) return;
+  if (bind) {
+    defer_ = true;
+  } else if (hipEventRecord(g_ev[2 * k], st) != hipSuccess) {
+    return;
+  }
   slot_ = k;
+}
+
+bool ProfScope::bind_events(hipEvent_t* start, hipEvent_t* stop) {
+  *start = *stop = nullptr;
+  if (slot_ < 0 || graph_ || !defer_) return false;
+  *start = g_ev[2 * slot_];
+  *stop = g_ev[2 * slot_ + 1];
+  bound_ = true;
+  return true;
 }
 
 uint32_t* ProfScope::work_word() {
@@ -160,6 +173,8 @@ void ProfScope::stop() {
   if (graph_) {
     if (record_event_nothrow(g_gev[2 * slot_ + 1], st_) == hipSuccess)
       g_grecs[slot_].stopped = true;
+  } else if (defer_) {
+    g_recs[slot_].stopped = bound_;  // recorded by the launch it was bound to
   } else if (hipEventRecord(g_ev[2 * slot_ + 1], st_) == hipSuccess) {
     g_recs[slot_].stopped = true;
   }

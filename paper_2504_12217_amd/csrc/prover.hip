@@ -1071,8 +1071,11 @@ struct YCopy {
 // copy from pinned staging, and their Y comes back in one copy to pinned
 // memory (described in *ycopy, enqueued by the caller); device-buffer proofs
 // read and write the caller's buffers.  No host wait inside the enqueue.
+// With bind (eager streams), the row event and end_ev are bound to the
+// dispatch of the kernels they follow instead of recorded after them;
+// otherwise the row event is recorded and end_ev is left to the caller.
 std::vector<Slot> enqueue_witness_batch(const ProveJob* jobs, size_t nj, ProveGen& G, hipStream_t st, YCopy* ycopy,
-                                        volatile uint32_t** flag_out) {
+                                        volatile uint32_t** flag_out, bool bind, hipEvent_t end_ev) {
   ZK_REQUIRE(nj <= 65535, "at most 65535 proofs per batch");
   // the row check writes straight into pinned host memory (cleared here; a
   // graph replay clears it before each launch)
@@ -1183,14 +1186,18 @@ std::vector<Slot> enqueue_witness_batch(const ProveJob* jobs, size_t nj, ProveGe
   // the CRPC per-row sums and Y in one launch, then the CRPC rows and the
   // public assignment and tail rows in another
   const uint32_t xw_blocks = any_crpc ? max_n_crpc : 0u;
-  hipLaunchKernelGGL(k_wit_first, dim3(xw_blocks + mm_blocks, J), dim3(RED_THREADS), 0, st, T, xw_blocks, mm_bx);
+  const hipEvent_t row_bound = bind && rows_only ? G.wrow_ev : nullptr;
+  launch_ev(nullptr, row_bound, k_wit_first, dim3(xw_blocks + mm_blocks, J), dim3(RED_THREADS), 0u, st, T, xw_blocks,
+            mm_bx);
   ZK_HIP(hipGetLastError());
-  if (rows_only) ZK_HIP(hipEventRecord(G.wrow_ev, st));
+  if (rows_only && !bind) ZK_HIP(hipEventRecord(G.wrow_ev, st));
   const uint64_t wide = std::max<uint64_t>(max_pub, max_tail);
-  hipLaunchKernelGGL(k_wit_second, dim3(1 + (unsigned)cdiv(wide, RED_THREADS), J), dim3(RED_THREADS), 0, st, T);
+  const hipEvent_t end_bound = bind ? end_ev : nullptr;
+  launch_ev(nullptr, any_plain ? nullptr : end_bound, k_wit_second, dim3(1 + (unsigned)cdiv(wide, RED_THREADS), J),
+            dim3(RED_THREADS), 0u, st, T);
   ZK_HIP(hipGetLastError());
   if (any_plain) {
-    hipLaunchKernelGGL(k_rows_plain, dim3(cdiv(max_m_plain, 256), J), dim3(256), 0, st, T);
+    launch_ev(nullptr, end_bound, k_rows_plain, dim3(cdiv(max_m_plain, 256), J), dim3(256), 0u, st, T);
     ZK_HIP(hipGetLastError());
   }
   if (!rows_only) ZK_HIP(hipEventRecord(G.wrow_ev, st));
@@ -1373,7 +1380,7 @@ ProveCtx::ProveCtx() {
   ZK_HIP(hipStreamCreateWithFlags(&graph_stream, hipStreamNonBlocking));
   for (ProveGen& g : gen) {
     ZK_HIP(hipEventCreateWithFlags(&g.witness_ev, hipEventDisableTiming));
-    ZK_HIP(hipEventCreateWithFlags(&g.wrow_ev, hipEventDisableTiming));
+    ZK_HIP(hipEventCreate(&g.wrow_ev));  // may be bound to a kernel's dispatch
     ZK_HIP(hipEventCreateWithFlags(&g.quotient_ev, hipEventDisableTiming));
     ZK_HIP(hipEventCreateWithFlags(&g.fork_ev, hipEventDisableTiming));
     ZK_HIP(hipEventCreateWithFlags(&g.graph_ev, hipEventDisableTiming));
@@ -1615,11 +1622,12 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
   const size_t nj = R.jobs.size();
   record_ext(G.ev[0], st, capture);
 
-  // ---- witnesses and evaluation vectors
+  // ---- witnesses and evaluation vectors (eager: the stage events are bound
+  // to the dispatch of the kernels they follow, no marker packets between)
   YCopy ycopy;
-  R.slots = enqueue_witness_batch(jobs, nj, G, st, &ycopy, &R.flag_host);
+  R.slots = enqueue_witness_batch(jobs, nj, G, st, &ycopy, &R.flag_host, !capture, G.ev[1]);
   std::vector<Slot>& slots = R.slots;
-  record_ext(G.ev[1], st, capture);
+  if (capture) record_ext(G.ev[1], st, capture);
   // Each event record on the stream holds its next kernel back by a few
   // microseconds, so eager lanes wait on the stage-timing event itself; under
   // capture the timing events are graph nodes and a plain record carries the
@@ -1730,16 +1738,17 @@ void enqueue_batch(ProveCtx& ctx, ProveGen& G, BatchRun& R, hipStream_t st, bool
     for (auto& kv : by_size) {
       const int Lg = kv.first;
       const size_t k = kv.second.size();
+      const hipEvent_t end_bound = !capture && gi + 1 == by_size.size() ? G.ev[2] : nullptr;
       if (k == 1) {
         const Slot& S = slots[kv.second[0]];
         uint32_t* const vecs[3] = {S.aev, S.bev, S.cev};
-        qap_quotient_launch(vecs, nullptr, 1, Lg, st);
+        qap_quotient_launch(vecs, nullptr, 1, Lg, st, end_bound);
       } else {
-        qap_quotient_launch(nullptr, tab_dev + tab_off[gi], (int)k, Lg, st);
+        qap_quotient_launch(nullptr, tab_dev + tab_off[gi], (int)k, Lg, st, end_bound);
       }
       gi++;
     }
-    record_ext(G.ev[2], st, capture);
+    if (capture) record_ext(G.ev[2], st, capture);
     if (capture) ZK_HIP(hipEventRecord(G.quotient_ev, st));
 
     // ---- the H lane after the quotients
