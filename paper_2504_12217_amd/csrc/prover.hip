@@ -598,26 +598,48 @@ __global__ void __launch_bounds__(RED_THREADS) k_wit_first(WitTable T, uint32_t 
     return;
   }
   const uint32_t mm = blockIdx.x - xw_blocks;
-  const uint32_t i = mm / mm_bx, j = (mm % mm_bx) * RED_THREADS + threadIdx.x;
+  const uint32_t i = mm / mm_bx, bx = mm % mm_bx, j = bx * RED_THREADS + threadIdx.x;
   const uint32_t n = J.n, b = J.b;
   const bool in = i < J.a && j < b;
+  // Y[i, the block's RED_THREADS columns]: each wavefront sums a quarter of
+  // the k range and each lane four adjacent columns (one 32-bit load of W per
+  // k when the rows are 4-byte aligned); the quarters meet in LDS.
+  static_assert(RED_THREADS == 256, "four wavefronts of 64 lanes, four columns per lane");
+  int32_t* part = reinterpret_cast<int32_t*>(sh);  // [4][RED_THREADS], before block_sum uses sh
+  if (i < J.a) {  // uniform per block
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t k0 = (uint32_t)((uint64_t)n * wave / 4), k1 = (uint32_t)((uint64_t)n * (wave + 1) / 4);
+    const uint32_t j0 = bx * RED_THREADS + 4u * lane;
+    const int8_t* x = J.X + (size_t)i * n;
+    int32_t acc[4] = {0, 0, 0, 0};
+    if ((b & 3u) == 0 && (reinterpret_cast<uintptr_t>(J.W) & 3u) == 0) {
+      if (j0 < b) {
+        const int8_t* wp = J.W + j0;
+#pragma unroll 8
+        for (uint32_t k = k0; k < k1; k++) {
+          const int32_t xv = x[k];
+          const uint32_t w4 = *reinterpret_cast<const uint32_t*>(wp + (size_t)k * b);
+#pragma unroll
+          for (int q = 0; q < 4; q++) acc[q] += xv * (int32_t)(int8_t)(w4 >> (8 * q));
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        if (j0 + q < b)
+          for (uint32_t k = k0; k < k1; k++) acc[q] += (int32_t)x[k] * (int32_t)J.W[(size_t)k * b + j0 + q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) part[wave * RED_THREADS + 4u * lane + q] = acc[q];
+  }
+  __syncthreads();
   int32_t y = 0;
   if (in) {
-    const int8_t* x = J.X + (size_t)i * n;
-    const int8_t* W = J.W;
-    int32_t acc0 = 0, acc1 = 0;
-    uint32_t k = 0;
-    for (; k + 8 <= n; k += 8) {
-#pragma unroll
-      for (int q = 0; q < 8; q += 2) {
-        acc0 += (int32_t)x[k + q] * (int32_t)W[(size_t)(k + q) * b + j];
-        acc1 += (int32_t)x[k + q + 1] * (int32_t)W[(size_t)(k + q + 1) * b + j];
-      }
-    }
-    for (; k < n; k++) acc0 += (int32_t)x[k] * (int32_t)W[(size_t)k * b + j];
-    y = acc0 + acc1;
+    y = part[threadIdx.x] + part[RED_THREADS + threadIdx.x] + part[2 * RED_THREADS + threadIdx.x] +
+        part[3 * RED_THREADS + threadIdx.x];
     J.Y[(size_t)i * b + j] = y;
   }
+  __syncthreads();  // part is read before block_sum reuses sh
   if (!kind_uses_z_dev(J.kind)) return;  // uniform per block
   Fr s = in ? Fr::mul(Fr::load(J.zpow + 8ull * ((uint64_t)i * b + j)), fr_of_int(y)) : Fr::zero();
   s = block_sum(s, sh);
