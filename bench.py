@@ -570,8 +570,8 @@ def main():
                     help="first copy this many MiB device to device (a known-size kernel for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build proves on a single MI355X "
-              "(multi-GPU sharding is a design note, not implemented); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the prover runs on a single MI355X "
+              "(multi-GPU sharding is described, not implemented); run with --gpus 1", file=sys.stderr)
         return 2
     import torch
     from paper_2504_12217_amd import zkvc
