@@ -357,7 +357,11 @@ int zkvc_field_op(uint32_t field, uint32_t op, const void* d_a, const void* d_b,
  * additions for MSM accumulation, butterflies for NTT passes, elements for
  * the others).  zkvc_profile_read turns recording off, waits for the events
  * and writes one aggregate per kernel name (up to `capacity`; *count receives
- * the number of kernels seen).  Recording adds two event records per launch.
+ * the number of kernels seen).  Recording adds two event records per launch;
+ * for the single-kernel scopes (the MSM bucket accumulation, the quotient's
+ * last NTT kernel) the two events are bound to the kernel's own dispatch on
+ * eager streams (hipExtLaunchKernel), so they time the kernel itself and add
+ * no marker packet between it and the next launch.
  */
 typedef struct {
   char name[48];
